@@ -1,0 +1,219 @@
+/*
+ * Direct Wick-contraction oracle for baryon-baryon four-point correlators.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the CPU
+ * baseline of the benchmark; never by the product path.
+ *
+ * Computes, for the requested relative coordinates r, the plain definition
+ *
+ *   C(r)_{a b a' b'} = sum_X sum_{terms} w1 w2 w3 w4
+ *       sum_{xi, xi'} T1(xi_1 xi_2 xi_3; a) T2(xi_4 xi_5 xi_6; b)
+ *                     T3(xi'_1 xi'_2 xi'_3; a') T4(xi'_4 xi'_5 xi'_6; b')
+ *       < q_1 .. q_6  qbar'_6 .. qbar'_1 >
+ *
+ * with q_1..q_3 the fields of B1 at X+r (periodic), q_4..q_6 those of B2 at X
+ * (Sec. 3, Eq. (LN.pLLp.ududsu) and its coordinate assignment), and the source
+ * antiquarks in the mirrored order written there.  For that order Wick's theorem
+ * gives the determinant of the 6x6 propagator matrix
+ *     P_ij = [f_i == f'_j] S_{f_i}(x_i)[xi_i][xi'_j]
+ * (Sec. 3, Eq. (Qexchdiag)), i.e. a signed sum over flavour-preserving
+ * bijections sigma of sink fields onto source fields.
+ *
+ * T(xi_a xi_b xi_c; g) = eps(c_a c_b c_c) M(mu_a, mu_b) delta(g, mu_c), M = C gamma_5,
+ * from the interpolating fields of Sec. 2; xi = 3*mu + c.  The source tensor is
+ * the sink tensor with primed indices, exactly as printed in Sec. 3.
+ *
+ * Evaluation order (plain, no FFT): the sum over the sink indices xi of one
+ * baryon is done first at each site, giving
+ *     G(x; g; e_a, e_b, e_c) = sum_xi T(xi; g) S_fa(x)[xi_a][e_a] S_fb(x)[xi_b][e_b] S_fc(x)[xi_c][e_c]
+ * and then, for each sigma and each nonzero source-tensor entry, the product
+ * G1(X+r; a; e'_{sigma(1..3)}) G2(X; b; e'_{sigma(4..6)}) is summed over X.
+ * The cost is O(V^2) per channel and time slice.
+ */
+#include <complex.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double _Complex cplx;
+
+#define NE 1728 /* 12^3 */
+
+static int perm_sign(const int *p, int n) {
+    int q[8], s = 1;
+    for (int i = 0; i < n; ++i) q[i] = p[i];
+    for (int i = 0; i < n; ++i)
+        while (q[i] != i) { int j = q[i]; int t = q[j]; q[j] = j; q[i] = t; s = -s; }
+    return s;
+}
+
+static double eps3(int a, int b, int c) {
+    if (a == b || b == c || a == c) return 0.0;
+    if ((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) return 1.0;
+    return -1.0;
+}
+
+/* Nonzero entries of one baryon tensor T(e_a e_b e_c; g). */
+typedef struct { int e[3]; double v; } nzent;
+
+static int tensor_nz(const cplx *M, int g, nzent *out) {
+    int n = 0;
+    for (int ca = 0; ca < 3; ++ca) for (int cb = 0; cb < 3; ++cb) for (int cc = 0; cc < 3; ++cc) {
+        double e = eps3(ca, cb, cc);
+        if (e == 0.0) continue;
+        for (int ma = 0; ma < 4; ++ma) for (int mb = 0; mb < 4; ++mb) {
+            cplx m = M[4 * ma + mb];
+            if (m == 0) continue;
+            /* C gamma_5 is real in the Dirac representation; keep the real part
+               and refuse anything else so that a wrong matrix cannot pass silently. */
+            if (cimag(m) != 0.0) return -1;
+            out[n].e[0] = 3 * ma + ca; out[n].e[1] = 3 * mb + cb; out[n].e[2] = 3 * g + cc;
+            out[n].v = e * creal(m);
+            ++n;
+        }
+    }
+    return n;
+}
+
+static const cplx *prop(const cplx *Sl, const cplx *Ss, int f, long x) {
+    return (f == 2 ? Ss : Sl) + x * 144;
+}
+
+/* G(x; g; .) for one sink term, for g in {g_lo, g_lo+1}, all sites. */
+static void build_G(long V, const cplx *Sl, const cplx *Ss, const nzent *nz, const int *nnz,
+                    const int *f, cplx *G) {
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < V; ++x) {
+        const cplx *Sa = prop(Sl, Ss, f[0], x), *Sb = prop(Sl, Ss, f[1], x), *Sc = prop(Sl, Ss, f[2], x);
+        for (int g = 0; g < 2; ++g) {
+            cplx *Gx = G + (x * 2 + g) * NE;
+            memset(Gx, 0, sizeof(cplx) * NE);
+            for (int k = 0; k < nnz[g]; ++k) {
+                const nzent *t = &nz[g * 24 + k];
+                const cplx *ra = Sa + 12 * t->e[0], *rb = Sb + 12 * t->e[1], *rc = Sc + 12 * t->e[2];
+                for (int ea = 0; ea < 12; ++ea) {
+                    cplx va = t->v * ra[ea];
+                    for (int eb = 0; eb < 12; ++eb) {
+                        cplx vab = va * rb[eb];
+                        cplx *dst = Gx + 144 * ea + 12 * eb;
+                        for (int ec = 0; ec < 12; ++ec) dst[ec] += vab * rc[ec];
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* One entry of the flattened work list: a (sigma, source-tensor entry pair) with
+   its sign and weight, the G-index of each sink baryon, and the source spins. */
+typedef struct { int t1, t2; int A, B; int sp; double coef; } work;
+
+/*
+ * Arguments
+ *   Lx,Ly,Lz     lattice extent; sites ordered x fastest, then y, then z.
+ *   Sl, Ss       light / strange propagator of one time slice, [V][12][12] complex (re,im).
+ *   M            4x4 complex spin matrix of the diquark (C gamma_5), row-major.
+ *   nterm[4]     number of terms of B1, B2, B3, B4 (at most 3 each).
+ *   w[4][3]      term weights.
+ *   flav[4][3][3] flavour of each field of each term (0 = u, 1 = d, 2 = s), field order a,b,c.
+ *   glo          first spin component computed for every baryon (0: upper two, 2: lower two).
+ *   nr, r[nr][3] relative coordinates.
+ *   out[nr][16]  complex result, spin index a + 2*(b + 2*(a' + 2*b')), spins relative to glo.
+ * Returns 0, or a negative value on bad input or allocation failure.
+ */
+int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, const double *M_,
+                const int *nterm, const double *w, const int *flav, int glo,
+                int nr, const int *r, double *out_) {
+    const cplx *Sl = (const cplx *)Sl_, *Ss = (const cplx *)Ss_, *M = (const cplx *)M_;
+    cplx *out = (cplx *)out_;
+    long V = (long)Lx * Ly * Lz;
+    for (int b = 0; b < 4; ++b) if (nterm[b] < 1 || nterm[b] > 3) return -1;
+
+    /* tensor nonzeros for the two spin components g = glo, glo+1 */
+    nzent nz[2 * 24];
+    int nnz[2];
+    for (int g = 0; g < 2; ++g) {
+        nnz[g] = tensor_nz(M, glo + g, nz + 24 * g);
+        if (nnz[g] < 0 || nnz[g] > 24) return -2;
+    }
+
+    /* G tensors of every sink term of B1 and B2 */
+    int n1 = nterm[0], n2 = nterm[1];
+    cplx *G1 = malloc(sizeof(cplx) * (size_t)n1 * V * 2 * NE);
+    cplx *G2 = malloc(sizeof(cplx) * (size_t)n2 * V * 2 * NE);
+    if (!G1 || !G2) { free(G1); free(G2); return -3; }
+    for (int t = 0; t < n1; ++t) build_G(V, Sl, Ss, nz, nnz, flav + (0 * 3 + t) * 3, G1 + (size_t)t * V * 2 * NE);
+    for (int t = 0; t < n2; ++t) build_G(V, Sl, Ss, nz, nnz, flav + (1 * 3 + t) * 3, G2 + (size_t)t * V * 2 * NE);
+
+    /* flattened work list over term tuples, sigma and source nonzeros */
+    size_t cap = 1024, nw = 0;
+    work *wl = malloc(sizeof(work) * cap);
+    if (!wl) { free(G1); free(G2); return -3; }
+    for (int t1 = 0; t1 < nterm[0]; ++t1) for (int t2 = 0; t2 < nterm[1]; ++t2)
+    for (int t3 = 0; t3 < nterm[2]; ++t3) for (int t4 = 0; t4 < nterm[3]; ++t4) {
+        int fs[6], fsrc[6];
+        for (int i = 0; i < 3; ++i) {
+            fs[i] = flav[(0 * 3 + t1) * 3 + i]; fs[3 + i] = flav[(1 * 3 + t2) * 3 + i];
+            fsrc[i] = flav[(2 * 3 + t3) * 3 + i]; fsrc[3 + i] = flav[(3 * 3 + t4) * 3 + i];
+        }
+        double wt = w[0 * 3 + t1] * w[1 * 3 + t2] * w[2 * 3 + t3] * w[3 * 3 + t4];
+        /* all permutations of 6 (Heap-free: lexicographic enumeration) */
+        int p[6] = {0, 1, 2, 3, 4, 5};
+        for (;;) {
+            int ok = 1;
+            for (int i = 0; i < 6; ++i) if (fs[i] != fsrc[p[i]]) { ok = 0; break; }
+            if (ok) {
+                int sg = perm_sign(p, 6);
+                for (int a3 = 0; a3 < 2; ++a3) for (int a4 = 0; a4 < 2; ++a4)
+                for (int k3 = 0; k3 < nnz[a3]; ++k3) for (int k4 = 0; k4 < nnz[a4]; ++k4) {
+                    int e[6];
+                    for (int i = 0; i < 3; ++i) { e[i] = nz[24 * a3 + k3].e[i]; e[3 + i] = nz[24 * a4 + k4].e[i]; }
+                    if (nw == cap) {
+                        cap *= 2;
+                        work *nwl = realloc(wl, sizeof(work) * cap);
+                        if (!nwl) { free(wl); free(G1); free(G2); return -3; }
+                        wl = nwl;
+                    }
+                    work *q = &wl[nw++];
+                    q->t1 = t1; q->t2 = t2;
+                    q->A = 144 * e[p[0]] + 12 * e[p[1]] + e[p[2]];
+                    q->B = 144 * e[p[3]] + 12 * e[p[4]] + e[p[5]];
+                    q->sp = a3 + 2 * a4;
+                    q->coef = wt * sg * nz[24 * a3 + k3].v * nz[24 * a4 + k4].v;
+                }
+            }
+            /* next permutation */
+            int i = 4;
+            while (i >= 0 && p[i] > p[i + 1]) --i;
+            if (i < 0) break;
+            int j = 5;
+            while (p[j] < p[i]) --j;
+            int t = p[i]; p[i] = p[j]; p[j] = t;
+            for (int a = i + 1, b = 5; a < b; ++a, --b) { t = p[a]; p[a] = p[b]; p[b] = t; }
+        }
+    }
+
+    /* direct O(V^2) sum */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ir = 0; ir < nr; ++ir) {
+        cplx acc[16];
+        for (int s = 0; s < 16; ++s) acc[s] = 0;
+        int rx = r[3 * ir], ry = r[3 * ir + 1], rz = r[3 * ir + 2];
+        for (long X = 0; X < V; ++X) {
+            int x = (int)(X % Lx), y = (int)((X / Lx) % Ly), z = (int)(X / ((long)Lx * Ly));
+            long x1 = (long)(((x + rx) % Lx + Lx) % Lx) + (long)Lx * ((((y + ry) % Ly + Ly) % Ly)
+                      + (long)Ly * (((z + rz) % Lz + Lz) % Lz));
+            for (size_t k = 0; k < nw; ++k) {
+                const work *q = &wl[k];
+                const cplx *g1 = G1 + ((size_t)q->t1 * V + x1) * 2 * NE + q->A;
+                const cplx *g2 = G2 + ((size_t)q->t2 * V + X) * 2 * NE + q->B;
+                cplx u0 = q->coef * g1[0], u1 = q->coef * g1[NE];
+                cplx v0 = g2[0], v1 = g2[NE];
+                cplx *o = acc + 4 * q->sp;
+                o[0] += u0 * v0; o[1] += u1 * v0; o[2] += u0 * v1; o[3] += u1 * v1;
+            }
+        }
+        for (int s = 0; s < 16; ++s) out[(size_t)ir * 16 + s] = acc[s];
+    }
+    free(wl); free(G1); free(G2);
+    return 0;
+}
