@@ -192,28 +192,54 @@ int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, co
         }
     }
 
-    /* direct O(V^2) sum */
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int ir = 0; ir < nr; ++ir) {
-        cplx acc[16];
-        for (int s = 0; s < 16; ++s) acc[s] = 0;
-        int rx = r[3 * ir], ry = r[3 * ir + 1], rz = r[3 * ir + 2];
-        for (long X = 0; X < V; ++X) {
-            int x = (int)(X % Lx), y = (int)((X / Lx) % Ly), z = (int)(X / ((long)Lx * Ly));
-            long x1 = (long)(((x + rx) % Lx + Lx) % Lx) + (long)Lx * ((((y + ry) % Ly + Ly) % Ly)
-                      + (long)Ly * (((z + rz) % Lz + Lz) % Lz));
-            for (size_t k = 0; k < nw; ++k) {
-                const work *q = &wl[k];
-                const cplx *g1 = G1 + ((size_t)q->t1 * V + x1) * 2 * NE + q->A;
-                const cplx *g2 = G2 + ((size_t)q->t2 * V + X) * 2 * NE + q->B;
-                cplx u0 = q->coef * g1[0], u1 = q->coef * g1[NE];
-                cplx v0 = g2[0], v1 = g2[NE];
-                cplx *o = acc + 4 * q->sp;
-                o[0] += u0 * v0; o[1] += u1 * v0; o[2] += u0 * v1; o[3] += u1 * v1;
+    /* direct O(V^2) sum over X.  Summation: double partial sums over chunks of
+       the work list, flushed into long double accumulators per (r, X block).  The
+       sum has ~V * |work| terms of random sign; plain recursive double summation
+       loses ~sqrt(N) eps (about 1e-12 relative at 16^3), this keeps the oracle's
+       own rounding near 1e-15.  Work is shared over (r, X block) pairs. */
+    const long XB = 64;
+    const long nxb = (V + XB - 1) / XB;
+    long double _Complex *tot = calloc((size_t)nr * 16, sizeof(long double _Complex));
+    if (!tot) { free(wl); free(G1); free(G2); return -3; }
+#pragma omp parallel
+    {
+        long double _Complex *acc = calloc((size_t)nr * 16, sizeof(long double _Complex));
+#pragma omp for schedule(dynamic, 1)
+        for (long job = 0; job < (long)nr * nxb; ++job) {
+            if (!acc) continue;
+            int ir = (int)(job / nxb);
+            long X0 = (job % nxb) * XB, X1 = X0 + XB < V ? X0 + XB : V;
+            int rx = r[3 * ir], ry = r[3 * ir + 1], rz = r[3 * ir + 2];
+            for (long X = X0; X < X1; ++X) {
+                int x = (int)(X % Lx), y = (int)((X / Lx) % Ly), z = (int)(X / ((long)Lx * Ly));
+                long x1 = (long)(((x + rx) % Lx + Lx) % Lx) + (long)Lx * ((((y + ry) % Ly + Ly) % Ly)
+                          + (long)Ly * (((z + rz) % Lz + Lz) % Lz));
+                for (size_t k0 = 0; k0 < nw; k0 += 1024) {
+                    size_t k1 = k0 + 1024 < nw ? k0 + 1024 : nw;
+                    cplx part[16];
+                    for (int s = 0; s < 16; ++s) part[s] = 0;
+                    for (size_t k = k0; k < k1; ++k) {
+                        const work *q = &wl[k];
+                        const cplx *g1 = G1 + ((size_t)q->t1 * V + x1) * 2 * NE + q->A;
+                        const cplx *g2 = G2 + ((size_t)q->t2 * V + X) * 2 * NE + q->B;
+                        cplx u0 = q->coef * g1[0], u1 = q->coef * g1[NE];
+                        cplx v0 = g2[0], v1 = g2[NE];
+                        cplx *o = part + 4 * q->sp;
+                        o[0] += u0 * v0; o[1] += u1 * v0; o[2] += u0 * v1; o[3] += u1 * v1;
+                    }
+                    for (int s = 0; s < 16; ++s) acc[(size_t)ir * 16 + s] += part[s];
+                }
             }
         }
-        for (int s = 0; s < 16; ++s) out[(size_t)ir * 16 + s] = acc[s];
+#pragma omp critical
+        {
+            if (acc)
+                for (size_t i = 0; i < (size_t)nr * 16; ++i) tot[i] += acc[i];
+        }
+        free(acc);
     }
+    for (size_t i = 0; i < (size_t)nr * 16; ++i) out[i] = (cplx)tot[i];
+    free(tot);
     free(wl); free(G1); free(G2);
     return 0;
 }
