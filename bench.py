@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the effective-block correlator on one MI355X.
+
+One step = the whole hot path over one job: all 52 channels, all 32 time slices
+of a 16^3 x 32 lattice in the FP64 form (block construction, forward FFT,
+transpose, open-index contraction, inverse FFT, normalisation) -- the workload
+of the paper's timing table (Sec. 5, Table 5: 16^3 x 32, 52 channels), with
+seeded synthetic propagators in place of the CP-PACS/JLQCD configuration.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line: throughput in site-channels/s (one output point
+C_ch(r, t) with its 16 spin components), per-stage device times from HIP
+events recorded on the library's stream, the roofline figures of the
+dominant kernel, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6        # vector and matrix
+PEAK_FP32_TFLOPS = 157.3
+
+PAPER_SITE_CH_PER_S = 6815744 / 19.0   # best BG/Q layout of Table 5 (32 nodes), context only
+
+
+def stage_model(stage, L, nc, n_ch, csize):
+    """Algorithmic work of one launch of each stage.
+
+    Returns (bound, bytes, flops).  nc = intermediate components per sink spin.
+    """
+    V = L ** 3
+    field = 2 * nc * V * csize                      # all block intermediates, both sink spins
+    out_field = n_ch * 16 * V * csize
+    if stage == "blocks":
+        return "hbm", V * 2 * 144 * csize + field, None
+    if stage == "fft_forward":                       # one axis pass: read + write the field
+        return "hbm", 2 * field, None
+    if stage == "transpose":
+        return "hbm", 2 * field, None
+    if stage == "contract":
+        return "alu", field + out_field, None        # flops filled in by caller (needs K totals)
+    if stage == "fft_inverse":
+        return "hbm", 2 * out_field, None
+    if stage == "finalize":
+        return "hbm", 2 * out_field, None
+    raise ValueError(stage)
+
+
+def traffic_for(kernel, csize_tag):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, csize_tag))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_1510_00903_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernels_sha256") != sha:
+        return None
+    return rec.get("bytes_per_dispatch")
+
+
+def cpu_baseline(Sl, Ss, t_idx, budget_s=20.0):
+    """The FP64 oracle (direct Wick, O(V^2)) on a bounded sample of the same job:
+    one r point of the time slice t_idx for channels 0, 4, 8, ... until budget_s."""
+    import numpy as np
+    from oracle import operators as ops
+    from oracle import wick
+    wick.build(force=False)
+    r = np.array([[3, 11, 6]], dtype=np.int32)
+    done = []
+    t0 = time.perf_counter()
+    for c in range(0, 52, 4):
+        wick.correlate(Sl[t_idx], Ss[t_idx], ops.CHANNELS[c], r)
+        done.append(c)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": len(done) / el, "unit": "site-channels/s", "cores": threads, "kind": "oracle",
+            "sample": "direct-Wick O(V^2) oracle, 16^3 slice t=%d, r=(3,11,6), channels %s: %d site-channels "
+                      "in %.1f s" % (t_idx, done, len(done), el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 1 GiB (for scaling rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; the correlator of each time slice is "
+              "independent, so more GPUs would shard time slices (see DESIGN.md). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1510_00903_amd as bbc
+    import synth
+
+    L, T = 16, 32
+    channels = list(range(52))
+    n_ch = len(channels)
+    dev = torch.device("cuda:0")
+    print("bench: generating %d^3 x %d propagators" % (L, T), file=sys.stderr, flush=True)
+    Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 1)
+    d_l = torch.from_numpy(Sl).to(dev)
+    d_s = torch.from_numpy(Ss).to(dev)
+    out = torch.empty((T, n_ch, L, L, L, 16), dtype=torch.complex128, device=dev)
+    ctx = bbc.Context(0)
+    t_list = list(range(T))
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.correlate(d_l, d_s, t_list, channels, out=out)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.correlate(d_l, d_s, t_list, channels, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    print("bench: timed %d steps in %.3f s" % (args.steps, el), file=sys.stderr, flush=True)
+
+    ms_per_step = 1000.0 * el / args.steps
+    site_ch = L ** 3 * T * n_ch
+    value = site_ch / (ms_per_step / 1000.0)
+
+    st = bbc.plan_stats(channels)
+    nc = st["components"] // 2
+    csize = 16
+    stages = {}
+    for name, (ms, launches) in prof.items():
+        # fft stages launch one kernel per axis
+        per_stage_launch = 3 if name.startswith("fft") else 1
+        n_launch = launches * per_stage_launch
+        stages[name] = {"ms_total": round(ms, 4), "launches": int(n_launch),
+                        "us_per_launch": round(1000.0 * ms / max(1, n_launch), 2)}
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, launches = prof[dom]
+    n_launch = launches * (3 if dom.startswith("fft") else 1)
+    avg_s = ms / 1000.0 / max(1, n_launch)
+    bound, nbytes, _ = stage_model(dom, L, nc, n_ch, csize)
+    if dom == "contract":
+        flops = 8.0 * 16 * st["iterations"] * L ** 3        # complex MAC = 8 flops, 16 spin outputs
+        achieved = flops / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
+    else:
+        achieved = nbytes / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roof["kernel"] = dom
+    roof["traffic"] = traffic_for(dom, "f64")
+    for name in stages:
+        b2, nb, _ = stage_model(name, L, nc, n_ch, csize)
+        stages[name]["hbm_GBs"] = round(nb / (stages[name]["us_per_launch"] * 1e-6) / 1e9, 1)
+
+    res = {
+        "metric": "correlator site-channels/sec (C_ch(r,t))",
+        "value": round(value, 1),
+        "unit": "site-channels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_SITE_CH_PER_S, 2),
+        "baseline_context": "paper Table 5, 16^3x32, 52 channels, 32 BlueGene/Q nodes, best layout 19 s",
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian propagators, exp(-m t) decay)",
+        "config": {"workload": "16^3x32 lattice, all 52 BB channels, FP64 plain form, upper spins",
+                   "lattice": [L, L, L], "T": T, "channels": n_ch, "site_channels_per_step": site_ch,
+                   "block_components_per_site": st["components"], "iterations": st["iterations"]},
+        "roofline": roof,
+        "stages": stages,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(Sl, Ss, 7)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * bbcorr.h -- C ABI of the MI355X (gfx950) effective-block baryon-baryon correlator.
+ *
+ * The library computes the four-point correlators of Sec. 2, Eq. (2) of
+ * H. Nemura, "Instructive discussion of an effective block algorithm for
+ * baryon-baryon correlators" (arXiv:1510.00903):
+ *
+ *   C_ch(r, t)_{a b a' b'} = exp(E_ch (t - t0)) *
+ *        sum_X < B1_a(X + r, t) B2_b(X, t)  Bbar4_b'  Bbar3_a' >
+ *
+ * for the 52 isospin-symmetric octet-octet channels of Sec. 4, Eqs.
+ * (GeneralBB_NN)-(GeneralBB_XX), from light (u = d) and strange wall-source
+ * propagators, with the effective block algorithm of Sec. 3: site-local block
+ * construction, 3-D FFT of every block component, contraction of the open
+ * source indices in momentum space (Eq. (LN.pLLp.FFT)) and inverse FFT.
+ *
+ * Conventions (all fixed by the paper unless marked "reading"):
+ *  - Propagator of flavour f on one time slice: S_f(x)[i][j], i = 3*mu + c the
+ *    sink spin-colour, j = 3*mu' + c' the source spin-colour (reading: the
+ *    paper does not fix the flattening), complex interleaved (re, im).
+ *    Sites are ordered x fastest, then y, then z (Sec. 6, index xi).
+ *  - Baryon fields of Sec. 2 with C = gamma_4 gamma_2 in the Dirac
+ *    representation; the source operator is the sink operator with primed
+ *    indices and the quark fields in mirrored order (Sec. 3, Eq. (LN.pLLp.ududsu)).
+ *  - Spatial boundary periodic; B1 sits at X + r (Sec. 3).
+ *  - Spin components: BBC_SPIN_UPPER computes alpha, beta, alpha', beta' in
+ *    {0, 1} (Dirac upper components, positive parity forward in time, Sec. 6).
+ *  - Output element (t-index n, channel-index m, site r, spin s) with
+ *    s = a + 2*(b + 2*(a' + 2*b')) is at
+ *        C_out[((n * n_ch + m) * V + r) * 16 + s]
+ *    i.e. the paper's linear index xi of Sec. 6 with the channel and time
+ *    running over the requested lists.
+ *
+ * Errors: every call returns a bbc_status; on failure a message is kept per
+ * thread (bbc_last_error).  Arguments are validated before any device work.
+ * On failure the contents of output buffers are unspecified.  No C++
+ * exception crosses this interface.
+ *
+ * Ownership: the caller owns every input and output buffer; the library never
+ * frees them.  A context owns its device workspace, which it allocates on the
+ * first call that needs it and keeps within the budget given to bbc_create.
+ */
+#ifndef BBCORR_H
+#define BBCORR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BBC_OK = 0,
+    BBC_EINVAL = -1,       /* bad argument (null pointer, size, channel, lattice) */
+    BBC_ENOMEM = -2,       /* workspace would exceed the budget, or allocation failed */
+    BBC_EDEVICE = -3,      /* HIP runtime error */
+    BBC_EUNSUPPORTED = -4  /* valid request this build does not handle (e.g. lattice extent) */
+} bbc_status;
+
+typedef enum { BBC_F64 = 0, BBC_F32 = 1 } bbc_precision;
+typedef enum { BBC_SPIN_UPPER = 0, BBC_SPIN_LOWER = 1 } bbc_spin;
+
+typedef struct bbc_context bbc_context;
+
+/* Number of channels: the 52 channels of Sec. 4 in printed order (indices 0..51),
+   followed by the four off-diagonal channels the paper omits because they vanish
+   in the isospin limit (indices 52..55; computed for verification only). */
+int bbc_num_channels(void);          /* 52 */
+int bbc_num_channels_all(void);      /* 56 */
+
+/* Channel name "B1 B2 > B3 B4" with baryon names p n L S+ S0 S- X0 X-
+   (L = Lambda, S = Sigma, X = Xi).  Returns NULL for an invalid index. */
+const char *bbc_channel_name(int channel);
+
+/* Number of light and strange quark propagators in every term of a channel
+   (n_light + n_strange = 6).  Sec. 2 field content. */
+bbc_status bbc_channel_content(int channel, int *n_light, int *n_strange);
+
+/* Source terms of a channel: the number of terms of source baryons B3 and B4
+   (3 for Lambda = X_u, X_d, X_s; 2 for Sigma0 = X_u, X_d; 1 otherwise), Sec. 2. */
+bbc_status bbc_source_terms(int channel, int *n_terms3, int *n_terms4);
+
+/* Diagram classification of Sec. 3 and Tables 1-4 for one channel and one
+   combination of source terms (term3 of B3, term4 of B4): the number of
+   diagrams and, for each, the number of iterations of its open-index sum (K)
+   and the parity of its permutation (+1 / -1).  K and sign must hold room for
+   max_diagrams entries. */
+bbc_status bbc_diagram_table(int channel, int term3, int term4, int max_diagrams,
+                             int *n_diagrams, int32_t *K, int32_t *sign);
+
+/* Plan statistics for a channel set: number of distinct block intermediates,
+   complex components per site (both sink spins), contraction terms, and the
+   total open-index iterations (sum of K over diagrams and source terms). */
+bbc_status bbc_plan_stats(int n_ch, const int32_t *ch_list, int64_t *n_intermediates,
+                          int64_t *n_components, int64_t *n_terms, int64_t *n_iterations);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+   workspace (0: no bound beyond free memory). */
+bbc_status bbc_create(int device, uint64_t hbm_budget_bytes, bbc_context **out);
+void bbc_destroy(bbc_context *ctx);
+
+/* Thread-local message of the last failure in this thread ("" if none). */
+const char *bbc_last_error(void);
+
+/* Device workspace needed by bbc_correlate for the given request, in bytes. */
+bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
+                         const int32_t *ch_list, uint64_t *bytes);
+
+/*
+ * Correlators for n_t time slices and n_ch channels (Sec. 2 Eq. (2), Sec. 3).
+ *
+ *   lattice[3]    Lx, Ly, Lz; each in {1,2,3,4,6,8,12,16,24,32,48,64,96}.
+ *   prec          BBC_F64: propagators and output are complex double.
+ *                 BBC_F32: complex float (blocks, FFT and contraction in FP32).
+ *   S_light, S_strange  device pointers, [n_t][Lz][Ly][Lx][12][12] complex of
+ *                 the precision's type: the slices for the times in t_list.
+ *   t_list[n_t]   time of each slice (used for exp(E (t - t0)) only).
+ *   t0            source time.
+ *   ch_list[n_ch] channel indices (0..55), any order, repeats allowed.
+ *   spin          BBC_SPIN_UPPER or BBC_SPIN_LOWER (components 2,3 mapped to 0,1).
+ *   energy[n_ch]  E_ch of the normalisation factor exp(E_ch (t - t0)) of Sec. 2
+ *                 Eq. (2); NULL means 0 for every channel (unnormalised).
+ *   C_out         device pointer, n_t * n_ch * V * 16 complex of the
+ *                 precision's type, layout given above.
+ *   C_scale       BBC_F32 only (NULL for BBC_F64): device pointer to n_t * n_ch
+ *                 doubles.  The correlator is C_scale[n * n_ch + m] times the
+ *                 FP32 field of (n, m); the FP64 factor carries the power-of-two
+ *                 rescaling of the propagators and exp(E (t - t0)), so that
+ *                 six-propagator products do not leave the FP32 range.
+ *   stream        hipStream_t (as void*) on which all work is ordered; NULL = default.
+ * Stream-ordered: returns after enqueueing; synchronise the stream before reading C_out.
+ */
+bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec,
+                         const void *S_light, const void *S_strange,
+                         int n_t, const int32_t *t_list, int t0,
+                         int n_ch, const int32_t *ch_list, bbc_spin spin,
+                         const double *energy, void *C_out, double *C_scale, void *stream);
+
+/*
+ * Measurement.  With profiling on, bbc_correlate records a HIP event pair on
+ * its stream around every kernel stage of every time slice:
+ *   0 block construction (step 1a)      1 forward FFT, three axis passes (step 1b)
+ *   2 transpose to momentum-major       3 open-index contraction (step 2a)
+ *   4 inverse FFT (step 2b)             5 normalisation / output layout
+ * bbc_profile_read waits for the recorded events, adds their elapsed times to
+ * ms[stage] (milliseconds) and the number of timed launches to launches[stage]
+ * (both arrays of n_stages <= BBC_NUM_STAGES entries, overwritten), then clears
+ * the record.  Timing adds two events per stage and slice; it does not change
+ * results.
+ */
+#define BBC_NUM_STAGES 6
+bbc_status bbc_profile_enable(bbc_context *ctx, int enable);
+bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBCORR_H */

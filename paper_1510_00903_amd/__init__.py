@@ -1,0 +1,217 @@
+"""MI355X effective-block baryon-baryon correlator: Python binding of libbbcorr.
+
+The binding only marshals arguments for the C ABI declared in
+``include/bbcorr.h``; every step of the computation runs in the HIP kernels of
+``libbbcorr.so``.  PyTorch provides device memory and the current HIP stream.
+There is no fallback: if the library is missing, every call raises.
+
+Paper: H. Nemura, "Instructive discussion of an effective block algorithm for
+baryon-baryon correlators", arXiv:1510.00903.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["BBCError", "F64", "F32", "UPPER", "LOWER", "STAGES", "Context", "library_path", "load",
+           "num_channels", "num_channels_all", "channel_name", "channel_content", "source_terms",
+           "diagram_table", "plan_stats", "footprint", "EXPORTED_SYMBOLS"]
+
+F64, F32 = 0, 1
+UPPER, LOWER = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbbcorr.so")
+_lib = None
+
+EXPORTED_SYMBOLS = [
+    "bbc_num_channels", "bbc_num_channels_all", "bbc_channel_name", "bbc_channel_content",
+    "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create", "bbc_destroy",
+    "bbc_last_error", "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
+]
+STAGES = ["blocks", "fft_forward", "transpose", "contract", "fft_inverse", "finalize"]
+
+
+class BBCError(RuntimeError):
+    """A negative bbc_status from the library, with its message."""
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libbbcorr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise BBCError("libbbcorr.so is not built; run `python -m paper_1510_00903_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    I, P, I64, U64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    lib.bbc_num_channels.restype = I
+    lib.bbc_num_channels_all.restype = I
+    lib.bbc_channel_name.argtypes = [I]
+    lib.bbc_channel_name.restype = ctypes.c_char_p
+    lib.bbc_channel_content.argtypes = [I, P, P]
+    lib.bbc_source_terms.argtypes = [I, P, P]
+    lib.bbc_diagram_table.argtypes = [I, I, I, I, P, P, P]
+    lib.bbc_plan_stats.argtypes = [I, P, P, P, P, P]
+    lib.bbc_create.argtypes = [I, U64, P]
+    lib.bbc_destroy.argtypes = [P]
+    lib.bbc_destroy.restype = None
+    lib.bbc_last_error.restype = ctypes.c_char_p
+    lib.bbc_footprint.argtypes = [P, I, I, P, P]
+    lib.bbc_correlate.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
+    lib.bbc_profile_enable.argtypes = [P, I]
+    lib.bbc_profile_read.argtypes = [P, I, P, P]
+    for f in ("bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
+              "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read"):
+        getattr(lib, f).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        raise BBCError("bbcorr error %d: %s" % (status, load().bbc_last_error().decode()))
+
+
+def _i32(values):
+    vals = [int(v) for v in values]
+    return (ctypes.c_int32 * max(1, len(vals)))(*vals), len(vals)
+
+
+def num_channels() -> int:
+    return load().bbc_num_channels()
+
+
+def num_channels_all() -> int:
+    return load().bbc_num_channels_all()
+
+
+def channel_name(c: int) -> str:
+    s = load().bbc_channel_name(c)
+    if s is None:
+        raise BBCError("invalid channel %d" % c)
+    return s.decode()
+
+
+def channel_content(c: int):
+    nl, ns = ctypes.c_int(), ctypes.c_int()
+    _check(load().bbc_channel_content(c, ctypes.byref(nl), ctypes.byref(ns)))
+    return nl.value, ns.value
+
+
+def source_terms(c: int):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(load().bbc_source_terms(c, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def diagram_table(c: int, term3: int, term4: int):
+    """[(K, sign)] of every diagram of channel c for the given source terms."""
+    K = (ctypes.c_int32 * 64)()
+    sg = (ctypes.c_int32 * 64)()
+    n = ctypes.c_int()
+    _check(load().bbc_diagram_table(c, term3, term4, 64, ctypes.byref(n), K, sg))
+    return [(K[i], sg[i]) for i in range(n.value)]
+
+
+def plan_stats(channels):
+    arr, n = _i32(channels)
+    vals = [ctypes.c_int64() for _ in range(4)]
+    _check(load().bbc_plan_stats(n, arr, *[ctypes.byref(v) for v in vals]))
+    keys = ("intermediates", "components", "diagrams", "iterations")
+    return dict(zip(keys, (v.value for v in vals)))
+
+
+def footprint(lattice, channels, precision=F64) -> int:
+    lat, _ = _i32(lattice)
+    arr, n = _i32(channels)
+    b = ctypes.c_uint64()
+    _check(load().bbc_footprint(lat, precision, n, arr, ctypes.byref(b)))
+    return b.value
+
+
+class Context:
+    """A device context: plan cache and workspace on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._lib = load()
+        self._ptr = ctypes.c_void_p()
+        _check(self._lib.bbc_create(device, hbm_budget_bytes, ctypes.byref(self._ptr)))
+        self.device = device
+
+    def close(self):
+        if self._ptr:
+            self._lib.bbc_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every kernel stage of later correlate calls."""
+        _check(self._lib.bbc_profile_enable(self._ptr, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (milliseconds, launches)} accumulated since the last read."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(self._lib.bbc_profile_read(self._ptr, n, ms, cnt))
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def correlate(self, S_light, S_strange, t_list, channels, t0=0, spin=UPPER, energy=None, out=None,
+                  scale=None, stream=None):
+        """C_ch(r, t) for the slices in S_light/S_strange (torch tensors on the context's GPU).
+
+        S_*:   [n_t, Lz, Ly, Lx, 12, 12], complex128 (FP64 form) or complex64 (FP32 form).
+        Returns ``out`` [n_t, n_ch, Lz, Ly, Lx, 16] (same dtype); in the FP32 form also
+        ``scale`` [n_t, n_ch] float64, the FP64 factor of each (t, channel) field.
+        Stream-ordered on ``stream`` (default: torch's current stream).
+        """
+        import torch
+
+        if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
+            raise BBCError("S_light and S_strange must have the same shape and dtype")
+        if S_light.dim() != 6 or tuple(S_light.shape[-2:]) != (12, 12):
+            raise BBCError("propagators must be [n_t, Lz, Ly, Lx, 12, 12]")
+        if S_light.dtype == torch.complex128:
+            prec = F64
+        elif S_light.dtype == torch.complex64:
+            prec = F32
+        else:
+            raise BBCError("propagators must be complex128 or complex64")
+        if not (S_light.is_cuda and S_strange.is_cuda):
+            raise BBCError("propagators must be device tensors")
+        S_light = S_light.contiguous()
+        S_strange = S_strange.contiguous()
+        n_t, Lz, Ly, Lx = S_light.shape[:4]
+        t_arr, nt2 = _i32(t_list)
+        if nt2 != n_t:
+            raise BBCError("t_list must have one entry per slice")
+        ch_arr, n_ch = _i32(channels)
+        lat, _ = _i32([Lx, Ly, Lz])
+        if out is None:
+            out = torch.empty((n_t, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, device=S_light.device)
+        if prec == F32 and scale is None:
+            scale = torch.empty((n_t, n_ch), dtype=torch.float64, device=S_light.device)
+        e_arr = None
+        if energy is not None:
+            e_vals = [float(e) for e in energy]
+            if len(e_vals) != n_ch:
+                raise BBCError("energy must have one entry per channel")
+            e_arr = (ctypes.c_double * n_ch)(*e_vals)
+        if stream is None:
+            stream = torch.cuda.current_stream(S_light.device)
+        _check(self._lib.bbc_correlate(
+            self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()), ctypes.c_void_p(S_strange.data_ptr()),
+            n_t, t_arr, int(t0), n_ch, ch_arr, int(spin), e_arr, ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(scale.data_ptr()) if (prec == F32) else None,
+            ctypes.c_void_p(stream.cuda_stream)))
+        return (out, scale) if prec == F32 else out

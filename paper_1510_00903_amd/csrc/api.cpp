@@ -1,0 +1,459 @@
+// C ABI of the MI355X effective-block correlator (include/bbcorr.h).
+//
+// The driver owns a plan cache (per channel list and spin selection), the
+// device copies of the planner tables and a workspace that grows on demand
+// within the context's HBM budget.  Each time slice runs the kernel sequence
+// of kernels.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bbcorr.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+bbc_status fail(bbc_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                       \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess) return fail(BBC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevPlan {
+    bbc::Plan plan;
+    int pat_begin[5];
+    uint32_t *d_terms = nullptr;
+    int32_t *d_term_begin = nullptr;
+    int32_t *d_item_begin = nullptr;
+    uint32_t *d_items = nullptr;
+    bbc::DDiag *d_diags = nullptr;
+    bbc::DRef *d_refs = nullptr;
+    size_t table_bytes = 0;
+    ~DevPlan() {
+        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_item_begin);
+        (void)hipFree(d_items); (void)hipFree(d_diags); (void)hipFree(d_refs);
+    }
+};
+
+// Contraction tables of a plan: per requested channel a flat list of
+// (diagram, k3, k4) items, diagram descriptors and block references with the
+// index strides of every intermediate.
+void contraction_tables(const bbc::Plan &P, std::vector<int32_t> &item_begin, std::vector<uint32_t> &items,
+                        std::vector<bbc::DDiag> &diags, std::vector<bbc::DRef> &refs) {
+    const int n = (int)P.channels.size();
+    item_begin.assign(n + 1, 0);
+    for (int m = 0; m < n; ++m) {
+        item_begin[m] = (int)items.size();
+        for (int d = P.ch_begin[m]; d < P.ch_begin[m + 1]; ++d) {
+            const bbc::Diagram &D = P.diags[d];
+            bbc::DDiag dd{};
+            dd.coef = D.coef;
+            for (int s = 0; s < 2; ++s) {
+                int b = (int)refs.size();
+                for (const bbc::BlockRef &br : D.blk[s]) {
+                    const bbc::Intermediate &I = P.inters[br.inter];
+                    bbc::DRef r{};
+                    r.coef = br.coef;
+                    r.base = I.offset;
+                    int so[2] = {0, 0}, sk[2] = {0, 0};
+                    for (int X = 0; X < 2; ++X) {
+                        int y = br.ymap[X];
+                        if (y < 0) continue;
+                        if (I.no[y] == 2) so[X] = I.stride_o[y];
+                        if (I.nk[y] > 1) sk[X] = I.stride_k[y];
+                    }
+                    r.so3 = so[0]; r.so4 = so[1]; r.sk3 = sk[0]; r.sk4 = sk[1];
+                    refs.push_back(r);
+                }
+                if (s == 0) { dd.ref0 = b; dd.ref0_end = (int)refs.size(); }
+                else { dd.ref1 = b; dd.ref1_end = (int)refs.size(); }
+            }
+            const int di = (int)diags.size();
+            diags.push_back(dd);
+            for (int k3 = 0; k3 < D.kdim[0]; ++k3)
+                for (int k4 = 0; k4 < D.kdim[1]; ++k4)
+                    items.push_back(((uint32_t)di << 8) | ((uint32_t)k3 << 4) | (uint32_t)k4);
+        }
+    }
+    item_begin[n] = (int)items.size();
+}
+
+template <typename E>
+hipError_t upload_vec(E **dst, const std::vector<E> &src) {
+    size_t bytes = std::max<size_t>(sizeof(E), src.size() * sizeof(E));
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(E), hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace
+
+struct bbc_context {
+    int device = 0;
+    uint64_t budget = 0;
+    std::mutex mu;
+    std::map<std::pair<std::vector<int>, int>, std::unique_ptr<DevPlan>> plans;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    double *d_energy = nullptr;
+    int energy_cap = 0;
+    // profiling: event pairs recorded around kernel stages
+    bool prof = false;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t event() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) { e = pool.back(); pool.pop_back(); return e; }
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~bbc_context() {
+        if (ws) (void)hipFree(ws);
+        if (d_energy) (void)hipFree(d_energy);
+        for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+// Records an event pair around one kernel stage when profiling is on.
+struct StageTimer {
+    bbc_context *ctx; hipStream_t st; int stage; hipEvent_t a = nullptr;
+    StageTimer(bbc_context *c, hipStream_t s, int g) : ctx(c), st(s), stage(g) {
+        if (ctx->prof && (a = ctx->event())) (void)hipEventRecord(a, st);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = ctx->event();
+        if (!b) { ctx->pool.push_back(a); return; }
+        (void)hipEventRecord(b, st);
+        ctx->recs.push_back({stage, a, b});
+    }
+};
+}  // namespace
+
+namespace {
+
+bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, DevPlan **out) {
+    auto key = std::make_pair(chans, spin_offset);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) { *out = it->second.get(); return BBC_OK; }
+    std::unique_ptr<DevPlan> dp(new DevPlan);
+    try {
+        dp->plan = bbc::build_plan(chans, spin_offset);
+    } catch (const std::exception &e) {
+        return fail(BBC_EINVAL, std::string("planner: ") + e.what());
+    }
+    const bbc::Plan &P = dp->plan;
+    // pattern ranges of the component layout
+    for (int p = 0; p <= 4; ++p) dp->pat_begin[p] = P.ncomp;
+    for (int c = P.ncomp - 1; c >= 0; --c) dp->pat_begin[P.comp_pat[c]] = c;
+    for (int p = 3; p >= 0; --p)
+        if (dp->pat_begin[p] > dp->pat_begin[p + 1]) dp->pat_begin[p] = dp->pat_begin[p + 1];
+    std::vector<int32_t> item_begin;
+    std::vector<uint32_t> items;
+    std::vector<bbc::DDiag> diags;
+    std::vector<bbc::DRef> refs;
+    contraction_tables(P, item_begin, items, diags, refs);
+    if (diags.size() >= (1u << 24)) return fail(BBC_EUNSUPPORTED, "too many diagrams in one request");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(upload_vec(&dp->d_terms, P.terms));
+    HIP_TRY(upload_vec(&dp->d_term_begin, P.term_begin));
+    HIP_TRY(upload_vec(&dp->d_item_begin, item_begin));
+    HIP_TRY(upload_vec(&dp->d_items, items));
+    HIP_TRY(upload_vec(&dp->d_diags, diags));
+    HIP_TRY(upload_vec(&dp->d_refs, refs));
+    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + item_begin.size() * 4 + items.size() * 4 +
+                      diags.size() * sizeof(bbc::DDiag) + refs.size() * sizeof(bbc::DRef);
+    *out = dp.get();
+    ctx->plans.emplace(key, std::move(dp));
+    return BBC_OK;
+}
+
+size_t workspace_bytes(long V, int nc, int n_ch, size_t csize) {
+    // I and Iq: 2 spins x nc components x V; Ct: n_ch x 16 x V
+    return (size_t)2 * 2 * nc * V * csize + (size_t)n_ch * 16 * V * csize + 256 * 3;
+}
+
+bbc_status check_lattice(const int32_t *lattice, long *V) {
+    if (!lattice) return fail(BBC_EINVAL, "lattice is NULL");
+    long v = 1;
+    for (int i = 0; i < 3; ++i) {
+        if (lattice[i] < 1) return fail(BBC_EINVAL, "lattice extent must be positive");
+        if (!bbc::fft_size_supported(lattice[i]))
+            return fail(BBC_EUNSUPPORTED, "lattice extent " + std::to_string(lattice[i]) +
+                                              " not in {1,2,3,4,6,8,12,16,24,32,48,64,96}");
+        v *= lattice[i];
+    }
+    if (v > (1L << 30)) return fail(BBC_EUNSUPPORTED, "lattice volume too large");
+    *V = v;
+    return BBC_OK;
+}
+
+template <typename T>
+bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const void *S_light,
+                         const void *S_strange, int n_t, const int32_t *t_list, int t0, int n_ch,
+                         const double *energy, void *C_out, double *C_scale, hipStream_t st) {
+    using T2 = typename bbc::cplx_t<T>::type;
+    const bbc::Plan &P = dp->plan;
+    const int nc = P.ncomp;
+    const size_t need = workspace_bytes(V, nc, n_ch, sizeof(T2));
+    if (ctx->budget && need + dp->table_bytes > ctx->budget)
+        return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
+    if (ctx->ws_bytes < need) {
+        HIP_TRY(hipStreamSynchronize(st));
+        if (ctx->ws) { HIP_TRY(hipFree(ctx->ws)); ctx->ws = nullptr; ctx->ws_bytes = 0; }
+        hipError_t e = hipMalloc(&ctx->ws, need);
+        if (e != hipSuccess) { ctx->ws = nullptr; return fail(BBC_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e)); }
+        ctx->ws_bytes = need;
+    }
+    if (energy) {
+        if (ctx->energy_cap < n_ch) {
+            if (ctx->d_energy) HIP_TRY(hipFree(ctx->d_energy));
+            ctx->d_energy = nullptr;
+            HIP_TRY(hipMalloc((void **)&ctx->d_energy, sizeof(double) * n_ch));
+            ctx->energy_cap = n_ch;
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->d_energy, energy, sizeof(double) * n_ch, hipMemcpyHostToDevice, st));
+    }
+    char *w = (char *)ctx->ws;
+    T2 *I = (T2 *)w;
+    T2 *Iq = I + (size_t)2 * nc * V;
+    T2 *Ct = Iq + (size_t)2 * nc * V;
+    const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
+    T2 *out = (T2 *)C_out;
+    for (int n = 0; n < n_t; ++n) {
+        const T2 *sl = Sl + (size_t)n * V * 144, *ss = Ss + (size_t)n * V * 144;
+        {
+            StageTimer tm(ctx, st, 0);
+            bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin,
+                                  dp->pat_begin, st);
+        }
+        {
+            StageTimer tm(ctx, st, 1);
+            if (bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+        }
+        {
+            StageTimer tm(ctx, st, 2);
+            bbc::launch_transpose<T>(I, Iq, 2L * nc, V, st);
+        }
+        {
+            StageTimer tm(ctx, st, 3);
+            bbc::launch_contract<T>(Iq, Ct, nc, L, n_ch, dp->d_item_begin, dp->d_items, dp->d_diags, dp->d_refs,
+                                    st);
+        }
+        {
+            StageTimer tm(ctx, st, 4);
+            if (bbc::launch_fft3d<T>(Ct, 16L * n_ch, L, +1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+        }
+        {
+            StageTimer tm(ctx, st, 5);
+            bbc::launch_finalize<T>(Ct, out + (size_t)n * n_ch * V * 16, n_ch, (int)V,
+                                    energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0), 1.0 / (double)V,
+                                    C_scale ? C_scale + (size_t)n * n_ch : nullptr, st);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    return BBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbc_num_channels(void) { return bbc::kNumChannels; }
+int bbc_num_channels_all(void) { return bbc::kNumChannelsAll; }
+
+const char *bbc_channel_name(int channel) {
+    static std::vector<std::string> names = [] {
+        std::vector<std::string> v;
+        for (int c = 0; c < bbc::kNumChannelsAll; ++c) v.push_back(bbc::channel_name(c));
+        return v;
+    }();
+    if (channel < 0 || channel >= bbc::kNumChannelsAll) return nullptr;
+    return names[channel].c_str();
+}
+
+bbc_status bbc_channel_content(int channel, int *n_light, int *n_strange) {
+    if (channel < 0 || channel >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    if (!n_light || !n_strange) return fail(BBC_EINVAL, "NULL output");
+    const int *b = bbc::channel_baryons(channel);
+    int ns = 0;
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < 3; ++i) ns += bbc::baryon(b[s]).flav[i] == bbc::FS;
+    *n_strange = ns;
+    *n_light = 6 - ns;
+    return BBC_OK;
+}
+
+bbc_status bbc_source_terms(int channel, int *n3, int *n4) {
+    if (channel < 0 || channel >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    if (!n3 || !n4) return fail(BBC_EINVAL, "NULL output");
+    const int *b = bbc::channel_baryons(channel);
+    *n3 = bbc::baryon(b[2]).nterm;
+    *n4 = bbc::baryon(b[3]).nterm;
+    return BBC_OK;
+}
+
+bbc_status bbc_diagram_table(int channel, int term3, int term4, int max_diagrams, int *n_diagrams, int32_t *K,
+                             int32_t *sign) {
+    if (channel < 0 || channel >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    const int *b = bbc::channel_baryons(channel);
+    if (term3 < 0 || term3 >= bbc::baryon(b[2]).nterm || term4 < 0 || term4 >= bbc::baryon(b[3]).nterm)
+        return fail(BBC_EINVAL, "source term index out of range");
+    if (!n_diagrams) return fail(BBC_EINVAL, "NULL output");
+    try {
+        auto ds = bbc::classify(channel, term3, term4, nullptr, nullptr);
+        *n_diagrams = (int)ds.size();
+        if ((int)ds.size() > max_diagrams || !K || !sign) return fail(BBC_EINVAL, "output arrays too small");
+        for (size_t i = 0; i < ds.size(); ++i) { K[i] = ds[i].K; sign[i] = ds[i].sign; }
+    } catch (const std::exception &e) {
+        return fail(BBC_EINVAL, e.what());
+    }
+    return BBC_OK;
+}
+
+bbc_status bbc_plan_stats(int n_ch, const int32_t *ch_list, int64_t *n_inter, int64_t *n_comp, int64_t *n_terms,
+                          int64_t *n_iter) {
+    if (n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list");
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    try {
+        bbc::Plan P = bbc::build_plan(chans, 0);
+        if (n_inter) *n_inter = (int64_t)P.inters.size();
+        if (n_comp) *n_comp = 2 * (int64_t)P.ncomp;
+        if (n_terms) *n_terms = (int64_t)P.diags.size();
+        if (n_iter) *n_iter = P.iterations;
+    } catch (const std::exception &e) {
+        return fail(BBC_EINVAL, e.what());
+    }
+    return BBC_OK;
+}
+
+const char *bbc_last_error(void) { return g_err.c_str(); }
+
+bbc_status bbc_create(int device, uint64_t budget, bbc_context **out) {
+    if (!out) return fail(BBC_EINVAL, "NULL output");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(BBC_EINVAL, "no HIP device " + std::to_string(device));
+    HIP_TRY(hipSetDevice(device));
+    bbc_context *c = new (std::nothrow) bbc_context;
+    if (!c) return fail(BBC_ENOMEM, "context allocation");
+    c->device = device;
+    c->budget = budget;
+    *out = c;
+    return BBC_OK;
+}
+
+void bbc_destroy(bbc_context *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->plans.clear();
+    delete ctx;
+}
+
+bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch, const int32_t *ch_list,
+                         uint64_t *bytes) {
+    long V;
+    bbc_status s = check_lattice(lattice, &V);
+    if (s) return s;
+    if (n_ch <= 0 || !ch_list || !bytes) return fail(BBC_EINVAL, "bad channel list or output");
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    try {
+        bbc::Plan P = bbc::build_plan(chans, 0);
+        *bytes = workspace_bytes(V, P.ncomp, n_ch, prec == BBC_F64 ? 16 : 8);
+    } catch (const std::exception &e) {
+        return fail(BBC_EINVAL, e.what());
+    }
+    return BBC_OK;
+}
+
+bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, const void *S_light,
+                         const void *S_strange, int n_t, const int32_t *t_list, int t0, int n_ch,
+                         const int32_t *ch_list, bbc_spin spin, const double *energy, void *C_out, double *C_scale,
+                         void *stream) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_lattice(lattice, &V);
+    if (s) return s;
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
+    if (n_t < 0 || n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list or negative n_t");
+    if (n_t > 0 && (!S_light || !S_strange || !t_list || !C_out)) return fail(BBC_EINVAL, "NULL buffer");
+    if (prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
+    if (prec == BBC_F32) return fail(BBC_EUNSUPPORTED, "FP32 form not available in this build");
+    for (int i = 0; i < n_ch; ++i)
+        if (ch_list[i] < 0 || ch_list[i] >= bbc::kNumChannelsAll)
+            return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
+    if (n_t == 0) return BBC_OK;
+    for (const void *p : {S_light, S_strange, (const void *)C_out}) {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(BBC_EINVAL, "S_light, S_strange and C_out must be device pointers");
+        }
+    }
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    DevPlan *dp = nullptr;
+    s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, &dp);
+    if (s) return s;
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == BBC_F64)
+        return run_correlate<double>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out,
+                                     nullptr, st);
+    return run_correlate<float>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, C_scale,
+                                st);
+}
+
+bbc_status bbc_profile_enable(bbc_context *ctx, int enable) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->prof = enable != 0;
+    return BBC_OK;
+}
+
+bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t *launches) {
+    if (!ctx || !ms || !launches || n_stages < 1 || n_stages > BBC_NUM_STAGES)
+        return fail(BBC_EINVAL, "bad profile_read arguments");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    for (int i = 0; i < n_stages; ++i) { ms[i] = 0; launches[i] = 0; }
+    HIP_TRY(hipSetDevice(ctx->device));
+    bbc_status st = BBC_OK;
+    for (auto &r : ctx->recs) {
+        float t = 0;
+        if (st == BBC_OK) {
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+            if (e != hipSuccess) st = fail(BBC_EDEVICE, std::string("profile: ") + hipGetErrorString(e));
+        }
+        if (r.stage < n_stages) { ms[r.stage] += t; launches[r.stage] += 1; }
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return st;
+}
+
+}  // extern "C"

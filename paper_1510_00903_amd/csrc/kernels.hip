@@ -1,0 +1,451 @@
+// gfx950 kernels of the effective block algorithm for baryon-baryon correlators.
+// Paper: H. Nemura, arXiv:1510.00903, Sec. 3 (effective blocks and the FFT
+// correlation of Eq. (LN.pLLp.FFT)).
+//
+// Per time slice the host driver launches, on one stream:
+//   k_blocks     step 1a: every block intermediate at every site        (site-local)
+//   k_fft (x3)   step 1b: forward 3-D FFT of every component            (one pass per axis)
+//   k_transpose  component-major [comp][q] -> momentum-major [q][comp]
+//   k_contract   step 2a: open-index sums per momentum, all channels    (one workgroup per q)
+//   k_fft (x3)   step 2b: inverse 3-D FFT of the 16 spin components per channel
+//   k_finalize   normalisation and transpose to the output layout [r][spin]
+#include "kernels.hpp"
+
+namespace bbc {
+
+template <typename T2> __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+    return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T2> __device__ __forceinline__ void cfma(T2 &acc, T2 a, T2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
+// ----------------------------------------------------------------------------
+// Step 1a: block intermediates.
+//
+// For a sink baryon term with tensor eps(c_a c_b c_c) (C g5)(mu_a mu_b) delta(g, mu_c)
+// (Sec. 2) and propagators S_a, S_b, S_c, the diquark tensor
+//   Q(c_c; e_a, e_b) = sum_{c_a c_b} eps(c_a c_b c_c) sum_mu (C g5)(mu, mu^1)
+//                      S_a[3mu + c_a][e_a] S_b[3(mu^1) + c_b][e_b]
+// gives G(g; e_a, e_b, e_c) = sum_{c_c} Q(c_c; e_a, e_b) S_c[3g + c_c][e_c].
+// Every intermediate component is a signed sum of G values over the source
+// indices closed at this site; the host planner lists those terms (packed
+// e_a | e_b << 4 | e_c << 8 | negative << 12) per component.
+// Components are grouped by pattern: 0 = (light diquark, light third quark),
+// 1 = (light, strange), 2 = (light-strange diquark, light), 3 = (ls, strange).
+// One workgroup handles TS consecutive sites; both sink spins are produced.
+// Output layout: I[(g * nc + comp) * V + x].
+// ----------------------------------------------------------------------------
+template <typename T, int TS>
+__global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *__restrict__ Sl,
+                                                const typename cplx_t<T>::type *__restrict__ Ss,
+                                                typename cplx_t<T>::type *__restrict__ I, int V, int nc, int g0,
+                                                const uint32_t *__restrict__ terms,
+                                                const int32_t *__restrict__ term_begin, int p0, int p1, int p2,
+                                                int p3, int p4) {
+    using T2 = typename cplx_t<T>::type;
+    __shared__ T2 sS[2][TS][144];
+    __shared__ T2 sQ[TS][432];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TS;
+    for (int i = tid; i < TS * 144; i += 256) {
+        int s = i / 144, e = i - s * 144, x = x0 + s;
+        T2 zl = T2{0, 0}, zs = T2{0, 0};
+        if (x < V) { zl = Sl[(size_t)x * 144 + e]; zs = Ss[(size_t)x * 144 + e]; }
+        sS[0][s][e] = zl;
+        sS[1][s][e] = zs;
+    }
+    const int pb[5] = {p0, p1, p2, p3, p4};
+    const int site = tid % TS;
+    const int slot = tid / TS;
+    constexpr int NSLOT = 256 / TS;
+    for (int qsel = 0; qsel < 2; ++qsel) {
+        __syncthreads();
+        // diquark tensor: a-quark light, b-quark light (qsel 0) or strange (qsel 1)
+        for (int i = tid; i < TS * 432; i += 256) {
+            int s = i / 432, r = i - s * 432;
+            int cc = r / 144, ea = (r / 12) % 12, eb = r % 12;
+            int c1 = (cc + 1) % 3, c2 = (cc + 2) % 3;
+            T2 acc = T2{0, 0};
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                const T m = (mu & 1) ? T(-1) : T(1);           // (C g5)(mu, mu^1)
+                const int nu = mu ^ 1;
+                T2 a1 = sS[0][s][(3 * mu + c1) * 12 + ea], b2 = sS[qsel][s][(3 * nu + c2) * 12 + eb];
+                T2 a2 = sS[0][s][(3 * mu + c2) * 12 + ea], b1 = sS[qsel][s][(3 * nu + c1) * 12 + eb];
+                T2 d = cmul(a1, b2);
+                T2 e = cmul(a2, b1);
+                acc.x += m * (d.x - e.x);
+                acc.y += m * (d.y - e.y);
+            }
+            sQ[s][r] = acc;
+        }
+        __syncthreads();
+        for (int pc = 0; pc < 2; ++pc) {
+            const int p = qsel * 2 + pc;
+            for (int comp = pb[p] + slot; comp < pb[p + 1]; comp += NSLOT) {
+                T2 acc0 = T2{0, 0}, acc1 = T2{0, 0};
+                const int tb = term_begin[comp], te = term_begin[comp + 1];
+                for (int t = tb; t < te; ++t) {
+                    const uint32_t code = terms[t];
+                    const int ea = code & 15, eb = (code >> 4) & 15, ec = (code >> 8) & 15;
+                    const T sg = (code >> 12) & 1 ? T(-1) : T(1);
+                    T2 g0v = T2{0, 0}, g1v = T2{0, 0};
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const T2 q = sQ[site][cc * 144 + ea * 12 + eb];
+                        cfma(g0v, q, sS[pc][site][(3 * (g0 + 0) + cc) * 12 + ec]);
+                        cfma(g1v, q, sS[pc][site][(3 * (g0 + 1) + cc) * 12 + ec]);
+                    }
+                    acc0.x += sg * g0v.x; acc0.y += sg * g0v.y;
+                    acc1.x += sg * g1v.x; acc1.y += sg * g1v.y;
+                }
+                const int x = x0 + site;
+                if (x < V) {
+                    I[((size_t)comp) * V + x] = acc0;
+                    I[((size_t)nc + comp) * V + x] = acc1;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
+                   typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
+                   const int32_t *term_begin, const int pb[5], hipStream_t st) {
+    constexpr int TS = 8;
+    int nblk = (V + TS - 1) / TS;
+    hipLaunchKernelGGL((k_blocks<T, TS>), dim3(nblk), dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms, term_begin,
+                       pb[0], pb[1], pb[2], pb[3], pb[4]);
+}
+
+// ----------------------------------------------------------------------------
+// FFT: batched 1-D transforms along one axis, one line per thread, held in
+// registers; Stockham autosort with radix 4/2/3 stages (compile-time length).
+// X(k) = sum_j x(j) exp(sign * 2 pi i j k / N).
+// ----------------------------------------------------------------------------
+template <typename T2, int R> struct Dft;
+template <typename T2> struct Dft<T2, 2> {
+    __device__ static void run(T2 *v, int) {
+        T2 a = v[0], b = v[1];
+        v[0] = T2{a.x + b.x, a.y + b.y};
+        v[1] = T2{a.x - b.x, a.y - b.y};
+    }
+};
+template <typename T2> struct Dft<T2, 3> {
+    __device__ static void run(T2 *v, int sgn) {
+        using T = decltype(v[0].x);
+        const T h = T(0.86602540378443864676);    // sqrt(3)/2
+        T2 t{v[1].x + v[2].x, v[1].y + v[2].y};
+        T2 u{v[1].x - v[2].x, v[1].y - v[2].y};
+        T2 m{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+        T2 iu{-sgn * h * u.y, sgn * h * u.x};      // sign * i * sqrt(3)/2 * u
+        v[0] = T2{v[0].x + t.x, v[0].y + t.y};
+        v[1] = T2{m.x + iu.x, m.y + iu.y};
+        v[2] = T2{m.x - iu.x, m.y - iu.y};
+    }
+};
+template <typename T2> struct Dft<T2, 4> {
+    __device__ static void run(T2 *v, int sgn) {
+        T2 a{v[0].x + v[2].x, v[0].y + v[2].y}, b{v[0].x - v[2].x, v[0].y - v[2].y};
+        T2 c{v[1].x + v[3].x, v[1].y + v[3].y}, e{v[1].x - v[3].x, v[1].y - v[3].y};
+        T2 d{-sgn * e.y, sgn * e.x};               // sign * i * (v1 - v3)
+        v[0] = T2{a.x + c.x, a.y + c.y};
+        v[2] = T2{a.x - c.x, a.y - c.y};
+        v[1] = T2{b.x + d.x, b.y + d.y};
+        v[3] = T2{b.x - d.x, b.y - d.y};
+    }
+};
+
+template <int Rem> struct NextRadix {
+    static constexpr int value = (Rem % 4 == 0) ? 4 : ((Rem % 2 == 0) ? 2 : 3);
+};
+
+template <typename T2, int N, int Ns, int R>
+__device__ __forceinline__ void stockham_stage(const T2 *in, T2 *out, const T2 *tw, int sgn) {
+#pragma unroll
+    for (int j = 0; j < N / R; ++j) {
+        T2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[j + r * (N / R)];
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            if (k != 0) v[r] = cmul(v[r], tw[(r * k * (N / (Ns * R))) % N]);
+        Dft<T2, R>::run(v, sgn);
+        const int idx = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[idx + r * Ns] = v[r];
+    }
+}
+
+template <typename T2, int N, int Ns> struct Stages {
+    __device__ static void run(T2 *a, T2 *b, const T2 *tw, int sgn) {
+        if constexpr (N / Ns > 1) {
+            constexpr int R = NextRadix<N / Ns>::value;
+            stockham_stage<T2, N, Ns, R>(a, b, tw, sgn);
+            Stages<T2, N, Ns * R>::run(b, a, tw, sgn);
+#pragma unroll
+            for (int i = 0; i < N; ++i) a[i] = b[i];
+        }
+    }
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fft(typename cplx_t<T>::type *__restrict__ data, long nlines, int Lx,
+                                             int Ly, int Lz, int axis, int sgn) {
+    using T2 = typename cplx_t<T>::type;
+    __shared__ T2 tw[N];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double s, c;
+        sincospi(2.0 * i / N, &s, &c);
+        tw[i] = T2{T(c), T(sgn * s)};
+    }
+    __syncthreads();
+    const long line = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= nlines) return;
+    const long V = (long)Lx * Ly * Lz;
+    const long lpc = V / N;                    // lines per component
+    const long comp = line / lpc;
+    const long l = line - comp * lpc;
+    long base, stride;
+    if (axis == 0) { base = l * Lx; stride = 1; }
+    else if (axis == 1) { long x = l % Lx, z = l / Lx; base = z * Lx * Ly + x; stride = Lx; }
+    else { base = l; stride = (long)Lx * Ly; }
+    T2 *p = data + comp * V + base;
+    T2 a[N], b[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] = p[j * stride];
+    Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[j * stride] = a[j];
+}
+
+bool fft_size_supported(int n) {
+    switch (n) {
+    case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
+        return true;
+    default:
+        return false;
+    }
+}
+
+template <typename T, int N>
+static void fft_axis(typename cplx_t<T>::type *data, long ncomp, const int L[3], int axis, int sgn, hipStream_t st) {
+    const long V = (long)L[0] * L[1] * L[2];
+    const long nlines = ncomp * (V / N);
+    const long nblk = (nlines + 255) / 256;
+    hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)nblk), dim3(256), 0, st, data, nlines, L[0], L[1], L[2],
+                       axis, sgn);
+}
+
+template <typename T>
+int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sgn, hipStream_t st) {
+    for (int axis = 0; axis < 3; ++axis) {
+        switch (L[axis]) {
+        case 1: break;
+        case 2: fft_axis<T, 2>(data, ncomp, L, axis, sgn, st); break;
+        case 3: fft_axis<T, 3>(data, ncomp, L, axis, sgn, st); break;
+        case 4: fft_axis<T, 4>(data, ncomp, L, axis, sgn, st); break;
+        case 6: fft_axis<T, 6>(data, ncomp, L, axis, sgn, st); break;
+        case 8: fft_axis<T, 8>(data, ncomp, L, axis, sgn, st); break;
+        case 12: fft_axis<T, 12>(data, ncomp, L, axis, sgn, st); break;
+        case 16: fft_axis<T, 16>(data, ncomp, L, axis, sgn, st); break;
+        case 24: fft_axis<T, 24>(data, ncomp, L, axis, sgn, st); break;
+        case 32: fft_axis<T, 32>(data, ncomp, L, axis, sgn, st); break;
+        case 48: fft_axis<T, 48>(data, ncomp, L, axis, sgn, st); break;
+        case 64: fft_axis<T, 64>(data, ncomp, L, axis, sgn, st); break;
+        case 96: fft_axis<T, 96>(data, ncomp, L, axis, sgn, st); break;
+        default: return -1;
+        }
+    }
+    return 0;
+}
+
+// ----------------------------------------------------------------------------
+// Transpose [R][C] -> [C][R] through a padded LDS tile.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const typename cplx_t<T>::type *__restrict__ in,
+                                                   typename cplx_t<T>::type *__restrict__ out, long R, long C) {
+    using T2 = typename cplx_t<T>::type;
+    __shared__ T2 tile[32][33];
+    const long bc = (long)blockIdx.x * 32, br = (long)blockIdx.y * 32;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    for (int j = ty; j < 32; j += 8) {
+        long r = br + j, c = bc + tx;
+        if (r < R && c < C) tile[j][tx] = in[r * C + c];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        long c = bc + j, r = br + tx;
+        if (c < C && r < R) out[c * R + r] = tile[tx][j];
+    }
+}
+
+template <typename T>
+void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long R, long C,
+                      hipStream_t st) {
+    dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
+    hipLaunchKernelGGL((k_transpose<T>), grid, dim3(32, 8), 0, st, in, out, R, C);
+}
+
+// ----------------------------------------------------------------------------
+// Step 2a: contraction in momentum space (Sec. 3, Eq. (LN.pLLp.FFT)):
+//   C~_ch(q)_{a b a' b'} = sum_diagrams coef * sum_{k3,k4} E1(q; a, a', b', k) E2(-q; b, a', b', k)
+// with each block value E a weighted sum of intermediate components.  One
+// workgroup per momentum q; each wave takes whole channels and its lanes split
+// the (diagram, k3, k4) items of the channel, then reduce.
+// Iq layout: [q][g][nc]; output Ct[(m * 16 + spin) * V + q].
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type *__restrict__ Iq,
+                                                  typename cplx_t<T>::type *__restrict__ Ct, int nc, int Lx,
+                                                  int Ly, int Lz, int n_ch, const int32_t *__restrict__ item_begin,
+                                                  const uint32_t *__restrict__ items,
+                                                  const DDiag *__restrict__ diags, const DRef *__restrict__ refs) {
+    using T2 = typename cplx_t<T>::type;
+    const int q = blockIdx.x;
+    const int V = Lx * Ly * Lz;
+    const int qx = q % Lx, qy = (q / Lx) % Ly, qz = q / (Lx * Ly);
+    const int qm = ((Lx - qx) % Lx) + Lx * (((Ly - qy) % Ly) + Ly * ((Lz - qz) % Lz));
+    const T2 *Ia = Iq + (size_t)q * 2 * nc;
+    const T2 *Ib = Iq + (size_t)qm * 2 * nc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int m = wave; m < n_ch; m += 4) {
+        T2 acc[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc[s] = T2{0, 0};
+        const int ib = item_begin[m], ie = item_begin[m + 1];
+        for (int it = ib + lane; it < ie; it += 64) {
+            const uint32_t code = items[it];
+            const int d = code >> 8, k3 = (code >> 4) & 15, k4 = code & 15;
+            const DDiag D = diags[d];
+            T2 e1[8], e2[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) { e1[i] = T2{0, 0}; e2[i] = T2{0, 0}; }
+            for (int r = D.ref0; r < D.ref0_end; ++r) {
+                const DRef R = refs[r];
+                const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
+                const T c = T(R.coef);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const int off = b + (o & 1) * R.so3 + (o >> 1) * R.so4;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        T2 v = Ia[g * nc + off];
+                        e1[g + 2 * o].x += c * v.x;
+                        e1[g + 2 * o].y += c * v.y;
+                    }
+                }
+            }
+            for (int r = D.ref1; r < D.ref1_end; ++r) {
+                const DRef R = refs[r];
+                const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
+                const T c = T(R.coef);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const int off = b + (o & 1) * R.so3 + (o >> 1) * R.so4;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        T2 v = Ib[g * nc + off];
+                        e2[g + 2 * o].x += c * v.x;
+                        e2[g + 2 * o].y += c * v.y;
+                    }
+                }
+            }
+            const T dc = T(D.coef);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int a = s & 1, bb = (s >> 1) & 1, o = s >> 2;
+                T2 p = cmul(e1[a + 2 * o], e2[bb + 2 * o]);
+                acc[s].x += dc * p.x;
+                acc[s].y += dc * p.y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                acc[s].x += __shfl_xor(acc[s].x, off, 64);
+                acc[s].y += __shfl_xor(acc[s].y, off, 64);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) Ct[((size_t)m * 16 + s) * V + q] = acc[s];
+        }
+    }
+}
+
+template <typename T>
+void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *Ct, int nc, const int L[3],
+                     int n_ch, const int32_t *item_begin, const uint32_t *items, const DDiag *diags,
+                     const DRef *refs, hipStream_t st) {
+    const int V = L[0] * L[1] * L[2];
+    hipLaunchKernelGGL((k_contract<T>), dim3(V), dim3(256), 0, st, Iq, Ct, nc, L[0], L[1], L[2], n_ch, item_begin,
+                       items, diags, refs);
+}
+
+// ----------------------------------------------------------------------------
+// Finalisation: C(r) = (1/V) sum_q ... is already summed by the inverse FFT;
+// multiply by exp(E_ch (t - t0)) / V (Sec. 2 Eq. (2)) and write [r][spin].
+// With scale_out (FP32 form) the FP64 factor is written there instead and the
+// field keeps only 1/V.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type *__restrict__ Ct,
+                                                  typename cplx_t<T>::type *__restrict__ out, int n_ch, int V,
+                                                  const double *__restrict__ energy, double dt, double inv_v,
+                                                  double *__restrict__ scale_out) {
+    using T2 = typename cplx_t<T>::type;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)n_ch * V) return;
+    const int m = (int)(i / V), x = (int)(i - (long)m * V);
+    const double e = energy ? exp(energy[m] * dt) : 1.0;
+    T f;
+    if (scale_out) {
+        f = T(inv_v);
+        if (x == 0) scale_out[m] = e;
+    } else {
+        f = T(e * inv_v);
+    }
+    T2 *o = out + ((size_t)m * V + x) * 16;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        T2 v = Ct[((size_t)m * 16 + s) * V + x];
+        o[s] = T2{v.x * f, v.y * f};
+    }
+}
+
+template <typename T>
+void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
+                     const double *energy, double dt, double inv_v, double *scale_out, hipStream_t st) {
+    const long n = (long)n_ch * V;
+    hipLaunchKernelGGL((k_finalize<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Ct, out, n_ch, V,
+                       energy, dt, inv_v, scale_out);
+}
+
+// explicit instantiations
+template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
+                                    const int32_t *, const int[5], hipStream_t);
+template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
+                                   const int32_t *, const int[5], hipStream_t);
+template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
+template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
+template void launch_transpose<double>(const double2 *, double2 *, long, long, hipStream_t);
+template void launch_transpose<float>(const float2 *, float2 *, long, long, hipStream_t);
+template void launch_contract<double>(const double2 *, double2 *, int, const int[3], int, const int32_t *,
+                                      const uint32_t *, const DDiag *, const DRef *, hipStream_t);
+template void launch_contract<float>(const float2 *, float2 *, int, const int[3], int, const int32_t *,
+                                     const uint32_t *, const DDiag *, const DRef *, hipStream_t);
+template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
+                                      double *, hipStream_t);
+template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,
+                                     hipStream_t);
+
+}  // namespace bbc

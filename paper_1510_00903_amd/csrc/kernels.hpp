@@ -1,0 +1,52 @@
+// gfx950 kernels of the effective block algorithm (declarations shared by the
+// host driver).  Paper: arXiv:1510.00903, Sec. 3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bbc {
+
+// Contraction tables (device layout).
+struct DDiag {           // one diagram of one requested channel
+    double coef;         // parity of the representative permutation times source weights
+    int ref0, ref0_end;  // block refs of site 0 (B1 at X+r)
+    int ref1, ref1_end;  // block refs of site 1 (B2 at X)
+    int pad[2];
+};
+struct DRef {            // one intermediate entering a block
+    double coef;         // sink-term weight times exchange sign
+    int base;            // component offset (per sink spin)
+    int so3, so4;        // stride of alpha' / beta' (0 if not carried by this intermediate)
+    int sk3, sk4;        // stride of the open index of B3 / B4 (0 if absent)
+    int pad;
+};
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+
+template <typename T>
+void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
+                   typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
+                   const int32_t *term_begin, const int pat_begin[5], hipStream_t st);
+
+template <typename T>
+int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sign, hipStream_t st);
+
+template <typename T>
+void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long R, long C,
+                      hipStream_t st);
+
+template <typename T>
+void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *Ct, int nc, const int L[3],
+                     int n_ch, const int32_t *item_begin, const uint32_t *items, const DDiag *diags,
+                     const DRef *refs, hipStream_t st);
+
+template <typename T>
+void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
+                     const double *energy, double dt, double inv_v, double *scale_out, hipStream_t st);
+
+bool fft_size_supported(int n);
+
+}  // namespace bbc

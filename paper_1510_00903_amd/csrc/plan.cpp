@@ -1,0 +1,400 @@
+// Host planner of the effective block algorithm (see plan.hpp).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+namespace bbc {
+
+namespace {
+
+const double kR6 = 1.0 / std::sqrt(6.0), kR2 = 1.0 / std::sqrt(2.0);
+
+// Baryon fields of Sec. 2, Eqs. (FieldOperator_N), (FieldOperator_SLXi),
+// (FieldOperator_xxx).  Lambda and Sigma0 keep the fixed field order
+// (d, s, u) used in Sec. 3, Eq. (LN.pLLp.ududsu): X_d = eps (s C g5 u) d and
+// X_s = eps (u C g5 d) s are cyclic rotations of that order (an even
+// permutation of three Grassmann fields), so only their tensor roles move.
+enum { B_P, B_N, B_SP, B_SM, B_X0, B_XM, B_L, B_S0, B_COUNT };
+
+const Baryon kBaryons[B_COUNT] = {
+    {"p",  {FU, FD, FU}, 1, {{+1.0, {0, 1, 2}, "-"}}},
+    {"n",  {FU, FD, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}},
+    {"S+", {FU, FS, FU}, 1, {{-1.0, {0, 1, 2}, "-"}}},
+    {"S-", {FD, FS, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}},
+    {"X0", {FU, FS, FS}, 1, {{+1.0, {0, 1, 2}, "-"}}},
+    {"X-", {FD, FS, FS}, 1, {{-1.0, {0, 1, 2}, "-"}}},
+    {"L",  {FD, FS, FU}, 3, {{kR6, {0, 1, 2}, "Xu"}, {kR6, {1, 2, 0}, "Xd"}, {-2.0 * kR6, {2, 0, 1}, "Xs"}}},
+    {"S0", {FD, FS, FU}, 2, {{kR2, {0, 1, 2}, "Xu"}, {-kR2, {1, 2, 0}, "Xd"}}},
+};
+
+// Channel list of Sec. 4 (printed order), then the four omitted isospin-zero ones.
+const int kChannels[kNumChannelsAll][4] = {
+    {B_P, B_N, B_P, B_N},
+    {B_P, B_L, B_P, B_L}, {B_P, B_L, B_SP, B_N}, {B_P, B_L, B_S0, B_P},
+    {B_SP, B_N, B_P, B_L}, {B_SP, B_N, B_SP, B_N}, {B_SP, B_N, B_S0, B_P},
+    {B_S0, B_P, B_P, B_L}, {B_S0, B_P, B_SP, B_N}, {B_S0, B_P, B_S0, B_P},
+    {B_L, B_L, B_L, B_L}, {B_L, B_L, B_P, B_XM}, {B_L, B_L, B_N, B_X0}, {B_L, B_L, B_SP, B_SM},
+    {B_L, B_L, B_S0, B_S0},
+    {B_P, B_XM, B_L, B_L}, {B_P, B_XM, B_P, B_XM}, {B_P, B_XM, B_N, B_X0}, {B_P, B_XM, B_SP, B_SM},
+    {B_P, B_XM, B_S0, B_S0}, {B_P, B_XM, B_S0, B_L},
+    {B_N, B_X0, B_L, B_L}, {B_N, B_X0, B_P, B_XM}, {B_N, B_X0, B_N, B_X0}, {B_N, B_X0, B_SP, B_SM},
+    {B_N, B_X0, B_S0, B_S0}, {B_N, B_X0, B_S0, B_L},
+    {B_SP, B_SM, B_L, B_L}, {B_SP, B_SM, B_P, B_XM}, {B_SP, B_SM, B_N, B_X0},
+    {B_SP, B_SM, B_SP, B_SM}, {B_SP, B_SM, B_S0, B_S0}, {B_SP, B_SM, B_S0, B_L},
+    {B_S0, B_S0, B_L, B_L}, {B_S0, B_S0, B_P, B_XM}, {B_S0, B_S0, B_N, B_X0},
+    {B_S0, B_S0, B_SP, B_SM}, {B_S0, B_S0, B_S0, B_S0},
+    {B_S0, B_L, B_P, B_XM}, {B_S0, B_L, B_N, B_X0}, {B_S0, B_L, B_SP, B_SM}, {B_S0, B_L, B_S0, B_L},
+    {B_XM, B_L, B_XM, B_L}, {B_XM, B_L, B_SM, B_X0}, {B_XM, B_L, B_S0, B_XM},
+    {B_SM, B_X0, B_XM, B_L}, {B_SM, B_X0, B_SM, B_X0}, {B_SM, B_X0, B_S0, B_XM},
+    {B_S0, B_XM, B_XM, B_L}, {B_S0, B_XM, B_SM, B_X0}, {B_S0, B_XM, B_S0, B_XM},
+    {B_XM, B_X0, B_XM, B_X0},
+    // omitted in Sec. 4: identically zero in the isospin limit
+    {B_L, B_L, B_S0, B_L}, {B_S0, B_S0, B_S0, B_L}, {B_S0, B_L, B_L, B_L}, {B_S0, B_L, B_S0, B_S0},
+};
+
+int perm_sign(const int *p, int n) {
+    int q[8];
+    for (int i = 0; i < n; ++i) q[i] = p[i];
+    int s = 1;
+    for (int i = 0; i < n; ++i)
+        while (q[i] != i) { std::swap(q[i], q[q[i]]); s = -s; }
+    return s;
+}
+
+// Canonical key of an intermediate from per-role (light/strange, source baryon
+// X, type).  The sink tensor is symmetric under exchanging roles a and b
+// together with their propagators (eps and C gamma_5 are both antisymmetric),
+// and which source baryon is "first" is a label; the canonical form relabels
+// source baryons by first appearance and takes the smaller of the two role
+// orders.  ymap receives X -> canonical Y for the chosen form.
+uint32_t canonical(const int pf[3], const int X[3], const int T[3], int ymap[2], int cpf[3], int cy[3],
+                   int ct[3]) {
+    uint32_t best = 0xffffffffu;
+    const int orders[2][3] = {{0, 1, 2}, {1, 0, 2}};
+    for (const auto &ord : orders) {
+        int m[2] = {-1, -1}, nx = 0;
+        int lpf[3], ly[3], lt[3];
+        for (int i = 0; i < 3; ++i) {
+            int r = ord[i];
+            if (m[X[r]] < 0) m[X[r]] = nx++;
+            lpf[i] = pf[r]; ly[i] = m[X[r]]; lt[i] = T[r];
+        }
+        uint32_t key = 0;
+        for (int i = 0; i < 3; ++i) key = key * 8 + (uint32_t)(lpf[i] * 4 + ly[i] * 2 + lt[i]);
+        if (key < best) {
+            best = key;
+            ymap[0] = m[0]; ymap[1] = m[1];
+            for (int i = 0; i < 3; ++i) { cpf[i] = lpf[i]; cy[i] = ly[i]; ct[i] = lt[i]; }
+        }
+    }
+    return best;
+}
+
+Intermediate make_intermediate(uint32_t key, const int pf[3], const int y[3], const int t[3]) {
+    Intermediate I{};
+    I.key = key;
+    for (int i = 0; i < 3; ++i) { I.pflav[i] = pf[i]; I.role_y[i] = y[i]; I.role_t[i] = t[i]; }
+    I.ny = (y[0] == 1 || y[1] == 1 || y[2] == 1) ? 2 : 1;
+    for (int Y = 0; Y < 2; ++Y) {
+        int nD = 0, nd = 0;
+        for (int i = 0; i < 3; ++i)
+            if (y[i] == Y) (t[i] ? nd : nD)++;
+        int kind = -1;
+        if (nD == 2 && nd == 1) kind = Y_FULL;
+        else if (nD == 2 && nd == 0) kind = Y_DD;
+        else if (nD == 1 && nd == 1) kind = Y_DDELTA;
+        else if (nD == 1 && nd == 0) kind = Y_DIN;
+        else if (nD == 0 && nd == 1) kind = Y_DELTAIN;
+        else if (nD == 0 && nd == 0) kind = -1;
+        else throw std::logic_error("impossible source-baryon arrangement");
+        I.kind[Y] = kind;
+        static const int NO[5] = {2, 1, 2, 1, 2}, NK[5] = {1, 3, 12, 12, 3};
+        I.no[Y] = kind < 0 ? 1 : NO[kind];
+        I.nk[Y] = kind < 0 ? 1 : NK[kind];
+    }
+    int d1 = I.no[1] * I.nk[1];
+    I.stride_o[0] = I.nk[0] * d1; I.stride_k[0] = d1;
+    I.stride_o[1] = I.nk[1];      I.stride_k[1] = 1;
+    I.ncomp = I.no[0] * I.nk[0] * d1;
+    return I;
+}
+
+}  // namespace
+
+const Baryon &baryon(int id) { return kBaryons[id]; }
+const int *channel_baryons(int ch) { return kChannels[ch]; }
+
+std::string channel_name(int ch) {
+    const int *b = kChannels[ch];
+    return std::string(kBaryons[b[0]].name) + " " + kBaryons[b[1]].name + " > " + kBaryons[b[2]].name + " " +
+           kBaryons[b[3]].name;
+}
+
+std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *index,
+                              std::vector<Intermediate> *inters) {
+    const int *bb = kChannels[ch];
+    const Baryon &B1 = kBaryons[bb[0]], &B2 = kBaryons[bb[1]], &B3 = kBaryons[bb[2]], &B4 = kBaryons[bb[3]];
+    int fs[6], fsrc[6], rsrc[6];
+    for (int i = 0; i < 3; ++i) {
+        fs[i] = B1.flav[i]; fs[3 + i] = B2.flav[i];
+        fsrc[i] = B3.flav[i]; fsrc[3 + i] = B4.flav[i];
+    }
+    // role of each source field in the chosen source terms
+    for (int r = 0; r < 3; ++r) {
+        rsrc[B3.term[t3].role[r]] = r;
+        rsrc[3 + B4.term[t4].role[r]] = r;
+    }
+    const double w34 = B3.term[t3].w * B4.term[t4].w;
+    std::vector<Diagram> out;
+    // A diagram is the set of source fields contracted with the quarks of B1
+    // (site X+r); Wick maps differing only by exchanges of identical quarks
+    // inside one sink baryon belong to the same diagram (Sec. 3).
+    for (int a0 = 0; a0 < 6; ++a0)
+        for (int a1 = a0 + 1; a1 < 6; ++a1)
+            for (int a2 = a1 + 1; a2 < 6; ++a2) {
+                int inA[6] = {0, 0, 0, 0, 0, 0};
+                inA[a0] = inA[a1] = inA[a2] = 1;
+                int cnt[3] = {0, 0, 0};
+                for (int i = 0; i < 3; ++i) cnt[fs[i]]++;
+                for (int q = 0; q < 6; ++q)
+                    if (inA[q]) cnt[fsrc[q]]--;
+                if (cnt[0] || cnt[1] || cnt[2]) continue;
+                // representative: each flavour's quarks of a site go to that
+                // site's source fields of the flavour in increasing order
+                int sig[6];
+                for (int s = 0; s < 2; ++s)
+                    for (int f = 0; f < 3; ++f) {
+                        int qs[6], nq = 0;
+                        for (int q = 0; q < 6; ++q)
+                            if (inA[q] == (s == 0) && fsrc[q] == f) qs[nq++] = q;
+                        int k = 0;
+                        for (int i = 3 * s; i < 3 * s + 3; ++i)
+                            if (fs[i] == f) sig[i] = qs[k++];
+                    }
+                Diagram d;
+                d.sign = perm_sign(sig, 6);
+                d.coef = d.sign * w34;
+                d.K = 1;
+                for (int X = 0; X < 2; ++X) {
+                    int n1 = inA[3 * X] + inA[3 * X + 1] + inA[3 * X + 2];
+                    const Baryon &BX = X ? B4 : B3;
+                    int cfield = 3 * X + BX.term[X ? t4 : t3].role[2];
+                    d.carry[X] = inA[cfield] ? 0 : 1;
+                    d.kdim[X] = 1;
+                    if (n1 == 1 || n1 == 2) {
+                        int lone = -1;
+                        for (int q = 3 * X; q < 3 * X + 3; ++q)
+                            if (inA[q] == (n1 == 1)) lone = q;
+                        d.kdim[X] = rsrc[lone] == 2 ? 3 : 12;
+                    }
+                    d.K *= d.kdim[X];
+                }
+                if (index) {
+                    for (int s = 0; s < 2; ++s) {
+                        const Baryon &Bs = s ? B2 : B1;
+                        // flavour-preserving permutations of the site's three fields
+                        static const int P3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+                        for (int t = 0; t < Bs.nterm; ++t)
+                            for (const auto &pi : P3) {
+                                if (Bs.flav[pi[0]] != Bs.flav[0] || Bs.flav[pi[1]] != Bs.flav[1] ||
+                                    Bs.flav[pi[2]] != Bs.flav[2])
+                                    continue;
+                                int pf[3], X[3], T[3];
+                                for (int r = 0; r < 3; ++r) {
+                                    int p = Bs.term[t].role[r];
+                                    int q = sig[3 * s + pi[p]];
+                                    pf[r] = Bs.flav[p] == FS ? 1 : 0;
+                                    X[r] = q / 3;
+                                    T[r] = rsrc[q] == 2 ? 1 : 0;
+                                }
+                                BlockRef br;
+                                int cpf[3], cy[3], ct[3];
+                                uint32_t key = canonical(pf, X, T, br.ymap, cpf, cy, ct);
+                                auto it = index->find(key);
+                                if (it == index->end()) {
+                                    int id = (int)inters->size();
+                                    inters->push_back(make_intermediate(key, cpf, cy, ct));
+                                    it = index->emplace(key, id).first;
+                                }
+                                br.inter = it->second;
+                                br.coef = Bs.term[t].w * perm_sign(pi, 3);
+                                d.blk[s].push_back(br);
+                            }
+                    }
+                    // consistency of the open indices between the two sites: a split
+                    // source baryon leaves the same open index at both sites, a full one
+                    // sits at one site only, and its outer spin is carried by one site
+                    for (int X = 0; X < 2; ++X)
+                        for (int s = 0; s < 2; ++s)
+                            for (const BlockRef &r : d.blk[s]) {
+                                const Intermediate &I = (*inters)[r.inter];
+                                int y = r.ymap[X];
+                                int nk = y >= 0 ? I.nk[y] : 0, no = y >= 0 ? I.no[y] : 1;
+                                bool ok = d.kdim[X] > 1 ? (nk == d.kdim[X]) : (nk == 0 || nk == 1);
+                                ok = ok && (no == (d.carry[X] == s ? 2 : 1));
+                                if (!ok) throw std::logic_error("inconsistent open indices in " + channel_name(ch));
+                            }
+                }
+                out.push_back(std::move(d));
+            }
+    return out;
+}
+
+namespace {
+
+// eps(c0, c1, c2)
+int eps3(int a, int b, int c) {
+    if (a == b || b == c || a == c) return 0;
+    return ((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) ? 1 : -1;
+}
+
+// C gamma_5 in the Dirac representation: nonzero (mu, nu) -> +-1.
+int cg5(int mu, int nu) {
+    if (mu == 0 && nu == 1) return 1;
+    if (mu == 1 && nu == 0) return -1;
+    if (mu == 2 && nu == 3) return 1;
+    if (mu == 3 && nu == 2) return -1;
+    return 0;
+}
+int cg5_partner(int mu) { return mu ^ 1; }
+
+struct Part { int e[3]; int set[3]; int sign; };   // partial assignment of source indices to roles
+
+// Source-tensor pieces of one canonical source baryon Y at the site, for fixed (o, k).
+// Source tensor (Sec. 3): eps(c'_a c'_b c'_c) (C g5)(mu'_a, mu'_b) delta(o, mu'_c).
+std::vector<Part> y_parts(const Intermediate &I, int Y, int o, int k, int so) {
+    int rD[3], nD = 0, rd = -1;
+    for (int r = 0; r < 3; ++r)
+        if (I.role_y[r] == Y) { if (I.role_t[r]) rd = r; else rD[nD++] = r; }
+    std::vector<Part> out;
+    auto base = []() { Part p{}; p.sign = 1; for (int i = 0; i < 3; ++i) { p.e[i] = 0; p.set[i] = 0; } return p; };
+    switch (I.kind[Y]) {
+    case Y_FULL:
+        for (int c1 = 0; c1 < 3; ++c1) for (int c2 = 0; c2 < 3; ++c2) for (int c3 = 0; c3 < 3; ++c3) {
+            int e = eps3(c1, c2, c3);
+            if (!e) continue;
+            for (int m1 = 0; m1 < 4; ++m1) {
+                int m2 = cg5_partner(m1);
+                Part p = base();
+                p.sign = e * cg5(m1, m2);
+                p.e[rD[0]] = 3 * m1 + c1; p.set[rD[0]] = 1;
+                p.e[rD[1]] = 3 * m2 + c2; p.set[rD[1]] = 1;
+                p.e[rd] = 3 * (so + o) + c3; p.set[rd] = 1;
+                out.push_back(p);
+            }
+        }
+        break;
+    case Y_DD:   // k = colour of the delta quark, which sits at the other site
+        for (int c1 = 0; c1 < 3; ++c1) for (int c2 = 0; c2 < 3; ++c2) {
+            int e = eps3(c1, c2, k);
+            if (!e) continue;
+            for (int m1 = 0; m1 < 4; ++m1) {
+                int m2 = cg5_partner(m1);
+                Part p = base();
+                p.sign = e * cg5(m1, m2);
+                p.e[rD[0]] = 3 * m1 + c1; p.set[rD[0]] = 1;
+                p.e[rD[1]] = 3 * m2 + c2; p.set[rD[1]] = 1;
+                out.push_back(p);
+            }
+        }
+        break;
+    case Y_DDELTA: {  // k = (mu_L, c_L) of the diquark partner at the other site
+        int muL = k / 3, cL = k % 3;
+        int mD = cg5_partner(muL);
+        for (int cD = 0; cD < 3; ++cD) for (int cd = 0; cd < 3; ++cd) {
+            int e = eps3(cD, cL, cd);
+            if (!e) continue;
+            Part p = base();
+            p.sign = e * cg5(mD, muL);
+            p.e[rD[0]] = 3 * mD + cD; p.set[rD[0]] = 1;
+            p.e[rd] = 3 * (so + o) + cd; p.set[rd] = 1;
+            out.push_back(p);
+        }
+        break;
+    }
+    case Y_DIN: {
+        Part p = base();
+        p.e[rD[0]] = k; p.set[rD[0]] = 1;
+        out.push_back(p);
+        break;
+    }
+    case Y_DELTAIN: {
+        Part p = base();
+        p.e[rd] = 3 * (so + o) + k; p.set[rd] = 1;
+        out.push_back(p);
+        break;
+    }
+    default:
+        out.push_back(base());
+    }
+    return out;
+}
+
+}  // namespace
+
+Plan build_plan(const std::vector<int> &channels, int spin_offset) {
+    Plan P;
+    P.channels = channels;
+    P.spin_offset = spin_offset;
+    std::map<uint32_t, int> index;
+    for (int ch : channels) {
+        if (ch < 0 || ch >= kNumChannelsAll) throw std::invalid_argument("channel index out of range");
+        P.ch_begin.push_back((int)P.diags.size());
+        const int *bb = kChannels[ch];
+        for (int t3 = 0; t3 < kBaryons[bb[2]].nterm; ++t3)
+            for (int t4 = 0; t4 < kBaryons[bb[3]].nterm; ++t4)
+                for (auto &d : classify(ch, t3, t4, &index, &P.inters)) {
+                    P.iterations += d.K;
+                    P.diags.push_back(std::move(d));
+                }
+    }
+    P.ch_begin.push_back((int)P.diags.size());
+    // component layout: intermediates grouped by pattern (so the block kernel
+    // builds each diquark tensor once), then in registration order
+    std::vector<int> order(P.inters.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return pattern_id(P.inters[a]) < pattern_id(P.inters[b]);
+    });
+    int off = 0;
+    for (int id : order) {
+        P.inters[id].offset = off;
+        off += P.inters[id].ncomp;
+    }
+    P.ncomp = off;
+    // block-kernel term lists, per component (sink spin is applied by the kernel)
+    P.term_begin.assign(P.ncomp + 1, 0);
+    P.comp_pat.assign(P.ncomp, 0);
+    std::vector<std::vector<uint32_t>> per(P.ncomp);
+    for (const auto &I : P.inters) {
+        if (I.pflav[0] != 0) throw std::logic_error("canonical pattern with strange first role");
+        for (int o0 = 0; o0 < I.no[0]; ++o0) for (int k0 = 0; k0 < I.nk[0]; ++k0)
+        for (int o1 = 0; o1 < I.no[1]; ++o1) for (int k1 = 0; k1 < I.nk[1]; ++k1) {
+            int c = I.offset + o0 * I.stride_o[0] + k0 * I.stride_k[0] + o1 * I.stride_o[1] + k1 * I.stride_k[1];
+            P.comp_pat[c] = pattern_id(I);
+            auto p0 = y_parts(I, 0, o0, k0, spin_offset);
+            auto p1 = y_parts(I, 1, o1, k1, spin_offset);
+            for (const auto &a : p0) for (const auto &b : p1) {
+                int e[3];
+                for (int r = 0; r < 3; ++r) {
+                    if (a.set[r] + b.set[r] != 1) throw std::logic_error("role not covered exactly once");
+                    e[r] = a.set[r] ? a.e[r] : b.e[r];
+                }
+                int sg = a.sign * b.sign;
+                if (sg == 0) continue;
+                per[c].push_back((uint32_t)e[0] | ((uint32_t)e[1] << 4) | ((uint32_t)e[2] << 8) |
+                                 ((sg < 0 ? 1u : 0u) << 12));
+            }
+        }
+    }
+    for (int c = 0; c < P.ncomp; ++c) {
+        P.term_begin[c] = (int)P.terms.size();
+        P.terms.insert(P.terms.end(), per[c].begin(), per[c].end());
+    }
+    P.term_begin[P.ncomp] = (int)P.terms.size();
+    return P;
+}
+
+}  // namespace bbc

@@ -1,0 +1,99 @@
+// Host planner of the effective block algorithm: baryon operators, diagram
+// classification, block intermediates and the tables the GPU kernels read.
+//
+// Paper: H. Nemura, arXiv:1510.00903.  Sec. 2 (interpolating fields),
+// Sec. 3 (Wick contraction, effective blocks, FFT correlation), Sec. 4 (the 52
+// channels, Tables 1-4), Appendix A (reusable blocks).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace bbc {
+
+enum : int { FU = 0, FD = 1, FS = 2 };
+
+// One term of a baryon field: weight and, for each tensor role r in {a, b, c}
+// (eps(c_a c_b c_c) (C gamma_5)(mu_a, mu_b) delta(gamma, mu_c)), the position of
+// the quark field that plays it in the baryon's fixed field order.
+struct BaryonTerm {
+    double w;
+    int role[3];
+    const char *name;
+};
+
+struct Baryon {
+    const char *name;
+    int flav[3];      // flavour of the quark fields in Grassmann order
+    int nterm;
+    BaryonTerm term[3];
+};
+
+constexpr int kNumChannels = 52;
+constexpr int kNumChannelsAll = 56;
+
+const Baryon &baryon(int id);
+const int *channel_baryons(int ch);          // 4 baryon ids: sink B1, B2, source B3, B4
+std::string channel_name(int ch);
+
+// Kinds of what one source baryon leaves at one sink site.
+enum YKind : int { Y_FULL = 0, Y_DD = 1, Y_DDELTA = 2, Y_DIN = 3, Y_DELTAIN = 4 };
+
+// A block intermediate: the sink tensor of one baryon term contracted with three
+// propagators and with the parts of the source tensors that close on that site.
+// Indices: sink spin g (2), then per source baryon Y present (canonical order):
+// outer spin o_Y (no = 1 or 2) and open index k_Y (nk = 1, 3 or 12).
+struct Intermediate {
+    uint32_t key;
+    int pflav[3];     // per role a, b, c: 0 light, 1 strange
+    int role_y[3];    // per role: canonical source baryon 0/1
+    int role_t[3];    // per role: 0 = diquark quark (a' or b'), 1 = delta quark (c')
+    int ny;
+    int kind[2], no[2], nk[2];
+    int ncomp;        // components per sink spin
+    int offset;       // offset of component 0 in the per-spin component space
+    int stride_o[2], stride_k[2];
+};
+
+struct BlockRef {
+    int inter;
+    double coef;      // sink-term weight times sign of the in-site exchange
+    int ymap[2];      // canonical Y of source baryon B3 / B4 at this site, -1 if absent
+};
+
+struct Diagram {
+    int K;            // open-index iterations (kdim3 * kdim4)
+    int sign;         // parity of the representative permutation
+    int kdim[2];      // open-index dimension contributed by B3 / B4 (1, 3, 12)
+    int carry[2];     // site (0: B1 at X+r, 1: B2 at X) holding the outer spin of B3 / B4
+    double coef;      // sign * w3 * w4
+    std::vector<BlockRef> blk[2];
+};
+
+struct Plan {
+    std::vector<int> channels;               // requested channel list
+    int spin_offset = 0;                     // 0 upper, 2 lower components
+    std::vector<Intermediate> inters;
+    int ncomp = 0;                           // components per sink spin, all intermediates
+    std::vector<Diagram> diags;
+    std::vector<int> ch_begin;               // per requested channel: first diagram (size n+1)
+    // block-kernel tables
+    std::vector<uint32_t> terms;             // packed (e_a, e_b, e_c, sign)
+    std::vector<int32_t> term_begin;         // per component (size ncomp+1)
+    std::vector<int32_t> comp_pat;           // per component: pattern id 0..3
+    int64_t iterations = 0;                  // sum of K over diagrams
+};
+
+// Diagrams of one channel and source-term pair; intermediates are registered in
+// `index`/`inters` (pass nullptrs to only classify).
+std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *index,
+                              std::vector<Intermediate> *inters);
+
+Plan build_plan(const std::vector<int> &channels, int spin_offset);
+
+// Pattern id of an intermediate: diquark flavour pair (ll = 0, ls = 1) * 2 + delta flavour.
+inline int pattern_id(const Intermediate &I) { return (I.pflav[1] ? 2 : 0) + (I.pflav[2] ? 1 : 0); }
+
+}  // namespace bbc

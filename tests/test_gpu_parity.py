@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerance (FP64 form): normwise per (channel, time slice),
+    max_{r,spin} |C_gpu - C_oracle| <= 1e-12 * max_{r,spin} |C_oracle|,
+the reading of the paper's "accuracy of almost the double precision" (Sec. 6)
+adopted for this build; relative errors near zeros are not meaningful.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators as ops
+from oracle import unified, wick
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+ALL = list(range(56))
+
+
+def _name_to_tuple(name):
+    a, b = name.split(">")
+    return tuple(a.split() + b.split())
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    import paper_1510_00903_amd as mod
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mod.load()
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(bbc):
+    c = bbc.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_correlate(ctx, Sl, Ss, t_list, channels, **kw):
+    dev = torch.device("cuda:0")
+    tl = torch.from_numpy(np.ascontiguousarray(Sl)).to(dev)
+    ts = torch.from_numpy(np.ascontiguousarray(Ss)).to(dev)
+    out = ctx.correlate(tl, ts, t_list, channels, **kw)
+    torch.cuda.synchronize()
+    if isinstance(out, tuple):
+        return out[0].cpu().numpy(), out[1].cpu().numpy()
+    return out.cpu().numpy()
+
+
+def normwise(a, ref):
+    return np.abs(a - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("lat", [(3, 3, 3), (4, 4, 4), (4, 2, 3)])
+def test_all_channels_full_field_small(bbc, ctx, lat):
+    """Every channel (52 + the 4 isospin-zero ones), every r, two time slices, ragged tiles."""
+    Lx, Ly, Lz = lat
+    Sl, Ss = synth.propagators(lat, 2, seed=101)
+    print("case: lattice", lat, flush=True)
+    out = gpu_correlate(ctx, Sl, Ss, [0, 1], ALL)
+    r = wick.all_r(Lx, Ly, Lz)
+    for t in range(2):
+        scale = None
+        for c in ALL:
+            ch = _name_to_tuple(bbc.channel_name(c))
+            ref = wick.correlate(Sl[t], Ss[t], ch, r)
+            got = out[t, c].reshape(-1, 16)
+            if c < 52:
+                assert normwise(got, ref) < TOL64, (lat, t, c)
+                scale = max(scale or 0, np.abs(ref).max())
+            else:
+                assert np.abs(got).max() < TOL64 * scale, (lat, t, c)
+                assert np.abs(ref).max() < TOL64 * scale
+
+
+def test_p_lambda_8cubed_all_t(bbc, ctx):
+    """The 8^3 x 8 p-Lambda workload: every r at two slices (O-U), sampled r at every slice (O-W)."""
+    L, T = 8, 8
+    Sl, Ss = synth.propagators(L, T, seed=102)
+    out = gpu_correlate(ctx, Sl, Ss, list(range(T)), [1])
+    ch = ops.CHANNELS[1]
+    for t in (0, 5):
+        ref = unified.correlate(Sl[t], Ss[t], ch).reshape(-1, 16)
+        assert normwise(out[t, 0].reshape(-1, 16), ref) < TOL64, t
+    rs = np.array([[0, 0, 0], [4, 4, 4], [1, 2, 3], [7, 0, 5], [3, 6, 1]])
+    idx = rs[:, 0] + L * (rs[:, 1] + L * rs[:, 2])
+    for t in range(T):
+        ref = wick.correlate(Sl[t], Ss[t], ch, rs)
+        assert normwise(out[t, 0].reshape(-1, 16)[idx], ref) < TOL64, t
+
+
+def test_energy_normalisation_and_time_labels(bbc, ctx):
+    """exp(E (t - t0)) of Sec. 2 Eq. (2): output scales per channel and per slice."""
+    Sl, Ss = synth.propagators(2, 2, seed=103)
+    a = gpu_correlate(ctx, Sl, Ss, [3, 4], [1, 5])
+    b = gpu_correlate(ctx, Sl, Ss, [3, 4], [1, 5], t0=1, energy=[1.2, -0.3])
+    for n, t in enumerate([3, 4]):
+        assert normwise(b[n, 0], a[n, 0] * np.exp(1.2 * (t - 1))) < 1e-14
+        assert normwise(b[n, 1], a[n, 1] * np.exp(-0.3 * (t - 1))) < 1e-14
+
+
+def test_lower_components(bbc, ctx):
+    """Spin selection LOWER (components 2, 3, Sec. 6) against the oracle."""
+    Sl, Ss = synth.propagators(3, 1, seed=104)
+    out = gpu_correlate(ctx, Sl, Ss, [0], [1, 10, 46], spin=1)
+    r = wick.all_r(3, 3, 3)
+    for m, c in enumerate([1, 10, 46]):
+        ref = wick.correlate(Sl[0], Ss[0], ops.CHANNELS[c], r, lower=True)
+        assert normwise(out[0, m].reshape(-1, 16), ref) < TOL64
+
+
+def test_repeated_and_reordered_channels(bbc, ctx):
+    """Channel lists are taken in the caller's order, repeats allowed."""
+    Sl, Ss = synth.propagators(2, 1, seed=105)
+    a = gpu_correlate(ctx, Sl, Ss, [0], [51, 3, 3, 0])
+    b = gpu_correlate(ctx, Sl, Ss, [0], [0, 3, 51])
+    assert np.array_equal(a[0, 0], b[0, 2])
+    assert np.array_equal(a[0, 1], a[0, 2])
+    assert np.array_equal(a[0, 3], b[0, 0])
+
+
+def test_errors_are_reported(bbc, ctx):
+    Sl, Ss = synth.propagators(2, 1, seed=106)
+    dev = torch.device("cuda:0")
+    tl, ts = torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
+    with pytest.raises(bbc.BBCError):
+        ctx.correlate(tl, ts, [0], [56])
+    with pytest.raises(bbc.BBCError):
+        ctx.correlate(tl.cpu(), ts.cpu(), [0], [0])
+    bad = torch.zeros((1, 5, 5, 5, 12, 12), dtype=torch.complex128, device=dev)
+    with pytest.raises(bbc.BBCError):
+        ctx.correlate(bad, bad, [0], [0])
+
+
+# ---------------------------------------------------------------- full size (16^3)
+@pytest.fixture(scope="module")
+def big(bbc, ctx):
+    """All 52 channels on a 16^3 lattice, slices t = 0 and 7 (SU(3)-broken inputs)."""
+    L = 16
+    Sl, Ss = synth.propagators(L, 8, seed=107, t_list=[0, 7])
+    out = gpu_correlate(ctx, Sl, Ss, [0, 7], list(range(56)))
+    return L, Sl, Ss, out
+
+
+SAMPLED = [1, 5, 10, 16, 30, 41, 46, 51]
+
+
+@pytest.mark.parametrize("c", SAMPLED)
+def test_16cubed_sampled_points(big, c):
+    """Sampled r (including 0 and L/2 points) of representative channels at full size."""
+    L, Sl, Ss, out = big
+    rs = np.array([[0, 0, 0], [8, 8, 8], [3, 11, 6]])
+    idx = rs[:, 0] + L * (rs[:, 1] + L * rs[:, 2])
+    t = 1
+    print("case: 16^3 channel", c, flush=True)
+    ref = wick.correlate(Sl[t], Ss[t], ops.CHANNELS[c], rs)
+    assert normwise(out[t, c].reshape(-1, 16)[idx], ref) < TOL64
+
+
+def test_16cubed_invariants(big, bbc):
+    """Properties that hold at any size, over all channels: the isospin-zero channels
+    vanish, identical sink baryons are antisymmetric, and the isospin relations hold."""
+    L, Sl, Ss, out = big
+    for t in range(2):
+        scale = np.abs(out[t, :52]).max()
+        assert np.abs(out[t, 52:]).max() < TOL64 * scale
+        C = out[t].reshape(56, -1, 16)
+        r = wick.all_r(L, L, L)
+        m = (-r) % L
+        mi = m[:, 0] + L * (m[:, 1] + L * m[:, 2])
+        sink_swap = [((s >> 1) & 1) + 2 * (s & 1) + 4 * ((s >> 2) & 3) for s in range(16)]
+        names = {bbc.channel_name(c): c for c in range(56)}
+        for c in range(52):
+            ch = _name_to_tuple(bbc.channel_name(c))
+            if ch[0] == ch[1]:
+                assert normwise(C[c], -C[c][mi][:, sink_swap]) < TOL64, c
+        iso = [("p X- > p X-", "n X0 > n X0", 1), ("p X- > n X0", "n X0 > p X-", 1),
+               ("L L > p X-", "L L > n X0", -1), ("p X- > L L", "n X0 > L L", -1),
+               ("S0 S0 > p X-", "S0 S0 > n X0", -1), ("S0 L > p X-", "S0 L > n X0", 1)]
+        for a, b, s in iso:
+            assert normwise(C[names[a]], s * C[names[b]]) < TOL64, (a, b)
