@@ -6,6 +6,7 @@
 // of kernels.hip on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -40,30 +41,47 @@ struct DevPlan {
     int pat_begin[5];
     uint32_t *d_terms = nullptr;
     int32_t *d_term_begin = nullptr;
-    int32_t *d_item_begin = nullptr;
     uint32_t *d_items = nullptr;
     bbc::DDiag *d_diags = nullptr;
     bbc::DRef *d_refs = nullptr;
+    int4 *d_segs = nullptr;
+    int32_t *d_ch_slot_begin = nullptr;
+    int ntask = 0, nslot = 0;
     size_t table_bytes = 0;
     ~DevPlan() {
-        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_item_begin);
-        (void)hipFree(d_items); (void)hipFree(d_diags); (void)hipFree(d_refs);
+        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_items); (void)hipFree(d_diags);
+        (void)hipFree(d_refs); (void)hipFree(d_segs); (void)hipFree(d_ch_slot_begin);
     }
 };
 
-// Contraction tables of a plan: per requested channel a flat list of
-// (diagram, k3, k4) items, diagram descriptors and block references with the
-// index strides of every intermediate.
-void contraction_tables(const bbc::Plan &P, std::vector<int32_t> &item_begin, std::vector<uint32_t> &items,
-                        std::vector<bbc::DDiag> &diags, std::vector<bbc::DRef> &refs) {
+// Contraction tables of a plan.  Per requested channel: its diagrams (sorted by
+// the sites carrying a' and b', so that neighbouring items take the same code
+// path) and the flat list of (diagram, k3, k4) items, cut into segments of at
+// most kSegItems items.  Every segment owns one partial-result slot; the slots
+// of a channel are contiguous.  Segments, largest first, are dealt four to a
+// task (one per wave of a workgroup).
+constexpr int kSegItems = 512;
+
+void contraction_tables(const bbc::Plan &P, std::vector<uint32_t> &items, std::vector<bbc::DDiag> &diags,
+                        std::vector<bbc::DRef> &refs, std::vector<int4> &segs, std::vector<int32_t> &ch_slot_begin,
+                        int *ntask) {
     const int n = (int)P.channels.size();
-    item_begin.assign(n + 1, 0);
+    ch_slot_begin.assign(n + 1, 0);
+    std::vector<int4> all;   // (begin, end, slot, 0)
+    int slot = 0;
     for (int m = 0; m < n; ++m) {
-        item_begin[m] = (int)items.size();
-        for (int d = P.ch_begin[m]; d < P.ch_begin[m + 1]; ++d) {
+        std::vector<int> order;
+        for (int d = P.ch_begin[m]; d < P.ch_begin[m + 1]; ++d) order.push_back(d);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const auto &A = P.diags[a], &B = P.diags[b];
+            return A.carry[0] + 2 * A.carry[1] < B.carry[0] + 2 * B.carry[1];
+        });
+        const int ib = (int)items.size();
+        for (int d : order) {
             const bbc::Diagram &D = P.diags[d];
             bbc::DDiag dd{};
             dd.coef = D.coef;
+            dd.pad[0] = D.carry[0] + 2 * D.carry[1];
             for (int s = 0; s < 2; ++s) {
                 int b = (int)refs.size();
                 for (const bbc::BlockRef &br : D.blk[s]) {
@@ -90,8 +108,36 @@ void contraction_tables(const bbc::Plan &P, std::vector<int32_t> &item_begin, st
                 for (int k4 = 0; k4 < D.kdim[1]; ++k4)
                     items.push_back(((uint32_t)di << 8) | ((uint32_t)k3 << 4) | (uint32_t)k4);
         }
+        const int ie = (int)items.size();
+        const int nseg = std::max(1, (ie - ib + kSegItems - 1) / kSegItems);
+        ch_slot_begin[m] = slot;
+        for (int g = 0; g < nseg; ++g) {
+            int b = ib + (int)((long)(ie - ib) * g / nseg), e = ib + (int)((long)(ie - ib) * (g + 1) / nseg);
+            all.push_back(make_int4(b, e, slot++, 0));
+        }
     }
-    item_begin[n] = (int)items.size();
+    ch_slot_begin[n] = slot;
+    std::stable_sort(all.begin(), all.end(), [](const int4 &a, const int4 &b) { return a.y - a.x > b.y - b.x; });
+    *ntask = (int)((all.size() + 3) / 4);
+    segs.assign((size_t)*ntask * 4, make_int4(0, 0, 0, 0));
+    for (size_t i = 0; i < all.size(); ++i) segs[i] = all[i];
+}
+
+// Momenta ordered so that every q is followed by -q (L-periodic), letting the
+// contraction tasks of a pair run back to back on one XCD.
+std::vector<int32_t> pair_order(const int L[3]) {
+    const int V = L[0] * L[1] * L[2];
+    std::vector<int32_t> out;
+    std::vector<char> seen(V, 0);
+    for (int q = 0; q < V; ++q) {
+        if (seen[q]) continue;
+        int qx = q % L[0], qy = (q / L[0]) % L[1], qz = q / (L[0] * L[1]);
+        int qm = ((L[0] - qx) % L[0]) + L[0] * (((L[1] - qy) % L[1]) + L[1] * ((L[2] - qz) % L[2]));
+        out.push_back(q);
+        seen[q] = 1;
+        if (!seen[qm]) { out.push_back(qm); seen[qm] = 1; }
+    }
+    return out;
 }
 
 template <typename E>
@@ -114,6 +160,7 @@ struct bbc_context {
     size_t ws_bytes = 0;
     double *d_energy = nullptr;
     int energy_cap = 0;
+    std::map<std::vector<int>, int32_t *> qorders;   // per lattice: momentum order
     // profiling: event pairs recorded around kernel stages
     bool prof = false;
     struct Rec { int stage; hipEvent_t a, b; };
@@ -128,6 +175,7 @@ struct bbc_context {
     ~bbc_context() {
         if (ws) (void)hipFree(ws);
         if (d_energy) (void)hipFree(d_energy);
+        for (auto &kv : qorders) (void)hipFree(kv.second);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
     }
@@ -168,29 +216,33 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
     for (int c = P.ncomp - 1; c >= 0; --c) dp->pat_begin[P.comp_pat[c]] = c;
     for (int p = 3; p >= 0; --p)
         if (dp->pat_begin[p] > dp->pat_begin[p + 1]) dp->pat_begin[p] = dp->pat_begin[p + 1];
-    std::vector<int32_t> item_begin;
     std::vector<uint32_t> items;
     std::vector<bbc::DDiag> diags;
     std::vector<bbc::DRef> refs;
-    contraction_tables(P, item_begin, items, diags, refs);
+    std::vector<int4> segs;
+    std::vector<int32_t> ch_slot_begin;
+    contraction_tables(P, items, diags, refs, segs, ch_slot_begin, &dp->ntask);
+    dp->nslot = ch_slot_begin.back();
     if (diags.size() >= (1u << 24)) return fail(BBC_EUNSUPPORTED, "too many diagrams in one request");
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(upload_vec(&dp->d_terms, P.terms));
     HIP_TRY(upload_vec(&dp->d_term_begin, P.term_begin));
-    HIP_TRY(upload_vec(&dp->d_item_begin, item_begin));
     HIP_TRY(upload_vec(&dp->d_items, items));
     HIP_TRY(upload_vec(&dp->d_diags, diags));
     HIP_TRY(upload_vec(&dp->d_refs, refs));
-    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + item_begin.size() * 4 + items.size() * 4 +
-                      diags.size() * sizeof(bbc::DDiag) + refs.size() * sizeof(bbc::DRef);
+    HIP_TRY(upload_vec(&dp->d_segs, segs));
+    HIP_TRY(upload_vec(&dp->d_ch_slot_begin, ch_slot_begin));
+    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + items.size() * 4 +
+                      diags.size() * sizeof(bbc::DDiag) + refs.size() * sizeof(bbc::DRef) +
+                      segs.size() * sizeof(int4) + ch_slot_begin.size() * 4;
     *out = dp.get();
     ctx->plans.emplace(key, std::move(dp));
     return BBC_OK;
 }
 
-size_t workspace_bytes(long V, int nc, int n_ch, size_t csize) {
-    // I and Iq: 2 spins x nc components x V; Ct: n_ch x 16 x V
-    return (size_t)2 * 2 * nc * V * csize + (size_t)n_ch * 16 * V * csize + 256 * 3;
+size_t workspace_bytes(long V, int nc, int n_ch, int nslot, size_t csize) {
+    // I and Iq: 2 spins x nc components x V; Ct: n_ch x 16 x V; partial slots: nslot x 16 x V
+    return (size_t)2 * 2 * nc * V * csize + (size_t)(n_ch + nslot) * 16 * V * csize + 256 * 4;
 }
 
 bbc_status check_lattice(const int32_t *lattice, long *V) {
@@ -215,7 +267,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     using T2 = typename bbc::cplx_t<T>::type;
     const bbc::Plan &P = dp->plan;
     const int nc = P.ncomp;
-    const size_t need = workspace_bytes(V, nc, n_ch, sizeof(T2));
+    const size_t need = workspace_bytes(V, nc, n_ch, dp->nslot, sizeof(T2));
     if (ctx->budget && need + dp->table_bytes > ctx->budget)
         return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
     if (ctx->ws_bytes < need) {
@@ -238,6 +290,21 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     T2 *I = (T2 *)w;
     T2 *Iq = I + (size_t)2 * nc * V;
     T2 *Ct = Iq + (size_t)2 * nc * V;
+    T2 *slots = Ct + (size_t)n_ch * 16 * V;
+    const int32_t *qorder = nullptr;
+    {
+        auto key = std::vector<int>{L[0], L[1], L[2]};
+        auto it = ctx->qorders.find(key);
+        if (it == ctx->qorders.end()) {
+            std::vector<int32_t> qo = pair_order(L);
+            int32_t *d = nullptr;
+            HIP_TRY(upload_vec(&d, qo));
+            it = ctx->qorders.emplace(key, d).first;
+        }
+        qorder = it->second;
+    }
+    bbc::ContractTables tb{qorder, dp->ntask, dp->d_segs, dp->d_items, dp->d_diags, dp->d_refs,
+                           dp->d_ch_slot_begin, dp->nslot};
     const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
     T2 *out = (T2 *)C_out;
     for (int n = 0; n < n_t; ++n) {
@@ -257,8 +324,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         }
         {
             StageTimer tm(ctx, st, 3);
-            bbc::launch_contract<T>(Iq, Ct, nc, L, n_ch, dp->d_item_begin, dp->d_items, dp->d_diags, dp->d_refs,
-                                    st);
+            bbc::launch_contract<T>(Iq, slots, Ct, nc, L, n_ch, tb, st);
         }
         {
             StageTimer tm(ctx, st, 4);
@@ -380,7 +446,14 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
     std::vector<int> chans(ch_list, ch_list + n_ch);
     try {
         bbc::Plan P = bbc::build_plan(chans, 0);
-        *bytes = workspace_bytes(V, P.ncomp, n_ch, prec == BBC_F64 ? 16 : 8);
+        std::vector<uint32_t> items;
+        std::vector<bbc::DDiag> diags;
+        std::vector<bbc::DRef> refs;
+        std::vector<int4> segs;
+        std::vector<int32_t> csb;
+        int ntask = 0;
+        contraction_tables(P, items, diags, refs, segs, csb, &ntask);
+        *bytes = workspace_bytes(V, P.ncomp, n_ch, csb.back(), prec == BBC_F64 ? 16 : 8);
     } catch (const std::exception &e) {
         return fail(BBC_EINVAL, e.what());
     }

@@ -296,99 +296,165 @@ void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::ty
 
 // ----------------------------------------------------------------------------
 // Step 2a: contraction in momentum space (Sec. 3, Eq. (LN.pLLp.FFT)):
-//   C~_ch(q)_{a b a' b'} = sum_diagrams coef * sum_{k3,k4} E1(q; a, a', b', k) E2(-q; b, a', b', k)
-// with each block value E a weighted sum of intermediate components.  One
-// workgroup per momentum q; each wave takes whole channels and its lanes split
-// the (diagram, k3, k4) items of the channel, then reduce.
-// Iq layout: [q][g][nc]; output Ct[(m * 16 + spin) * V + q].
+//   C~_ch(q)_{a b a' b'} = sum_diagrams coef * sum_{k3,k4} E1(q; a, ., k) E2(-q; b, ., k)
+// with each block value E a weighted sum of intermediate components, and the
+// outer source spins a', b' carried by one of the two blocks each (the site
+// holding that source baryon's delta quark).
+//
+// Work decomposition: the items (diagram, k3, k4) of each channel are cut into
+// segments; four segments form a task (one per wave).  Workgroup = (momentum q,
+// task).  Workgroup ids are mapped so that all tasks of q and of -q run
+// back to back on the same XCD: the q-pair's intermediate slices (the only
+// data the tasks read) then stay in that XCD's L2.  Each wave reduces its
+// segment and writes one partial result slot; k_combine adds the slots of a
+// channel in a fixed order (no atomics: results are bit-reproducible).
+// Iq layout: [q][g][nc]; slot layout: [slot][16][V].
 // ----------------------------------------------------------------------------
+template <typename T, int C3, int C4>
+__device__ __forceinline__ void contract_item(const typename cplx_t<T>::type *__restrict__ Ia,
+                                              const typename cplx_t<T>::type *__restrict__ Ib, int nc,
+                                              const DDiag &D, const DRef *__restrict__ refs, int k3, int k4,
+                                              typename cplx_t<T>::type (&acc)[16]) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int N1 = 1 << ((C3 == 0) + (C4 == 0));   // outer-spin combinations held by site 0
+    constexpr int N2 = 4 / N1;
+    T2 e1[2 * N1], e2[2 * N2];
+#pragma unroll
+    for (int i = 0; i < 2 * N1; ++i) e1[i] = T2{0, 0};
+#pragma unroll
+    for (int i = 0; i < 2 * N2; ++i) e2[i] = T2{0, 0};
+    for (int r = D.ref0; r < D.ref0_end; ++r) {
+        const DRef R = refs[r];
+        const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
+        const T c = T(R.coef);
+#pragma unroll
+        for (int o = 0; o < N1; ++o) {
+            const int a3 = (C3 == 0) ? (o & 1) : 0;
+            const int a4 = (C4 == 0) ? ((C3 == 0) ? (o >> 1) : o) : 0;
+            const int off = b + a3 * R.so3 + a4 * R.so4;
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const T2 v = Ia[g * nc + off];
+                e1[g + 2 * o].x += c * v.x;
+                e1[g + 2 * o].y += c * v.y;
+            }
+        }
+    }
+    for (int r = D.ref1; r < D.ref1_end; ++r) {
+        const DRef R = refs[r];
+        const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
+        const T c = T(R.coef);
+#pragma unroll
+        for (int o = 0; o < N2; ++o) {
+            const int a3 = (C3 == 1) ? (o & 1) : 0;
+            const int a4 = (C4 == 1) ? ((C3 == 1) ? (o >> 1) : o) : 0;
+            const int off = b + a3 * R.so3 + a4 * R.so4;
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const T2 v = Ib[g * nc + off];
+                e2[g + 2 * o].x += c * v.x;
+                e2[g + 2 * o].y += c * v.y;
+            }
+        }
+    }
+    const T dc = T(D.coef);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int a = s & 1, bb = (s >> 1) & 1, a3 = (s >> 2) & 1, a4 = s >> 3;
+        const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
+        const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
+        const T2 p = cmul(e1[a + 2 * o1], e2[bb + 2 * o2]);
+        acc[s].x = fma(dc, p.x, acc[s].x);
+        acc[s].y = fma(dc, p.y, acc[s].y);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type *__restrict__ Iq,
-                                                  typename cplx_t<T>::type *__restrict__ Ct, int nc, int Lx,
-                                                  int Ly, int Lz, int n_ch, const int32_t *__restrict__ item_begin,
-                                                  const uint32_t *__restrict__ items,
+                                                  typename cplx_t<T>::type *__restrict__ slots, int nc, int Lx,
+                                                  int Ly, int Lz, const int32_t *__restrict__ qorder, int ntask,
+                                                  const int4 *__restrict__ segs, const uint32_t *__restrict__ items,
                                                   const DDiag *__restrict__ diags, const DRef *__restrict__ refs) {
     using T2 = typename cplx_t<T>::type;
-    const int q = blockIdx.x;
     const int V = Lx * Ly * Lz;
+    // XCD-aware placement: consecutive workgroup ids cycle over the 8 XCDs;
+    // XCD x owns the contiguous range of q positions [x*P8, (x+1)*P8).
+    const int xcd = blockIdx.x & 7;
+    const int j = blockIdx.x >> 3;
+    const int P8 = (V + 7) >> 3;
+    const int pos = xcd * P8 + j / ntask;
+    const int task = j - (j / ntask) * ntask;
+    if (pos >= V) return;
+    const int q = qorder[pos];
     const int qx = q % Lx, qy = (q / Lx) % Ly, qz = q / (Lx * Ly);
     const int qm = ((Lx - qx) % Lx) + Lx * (((Ly - qy) % Ly) + Ly * ((Lz - qz) % Lz));
     const T2 *Ia = Iq + (size_t)q * 2 * nc;
     const T2 *Ib = Iq + (size_t)qm * 2 * nc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int m = wave; m < n_ch; m += 4) {
-        T2 acc[16];
+    const int4 sg = segs[task * 4 + wave];
+    if (sg.x >= sg.y) return;
+    T2 acc[16];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) acc[s] = T2{0, 0};
-        const int ib = item_begin[m], ie = item_begin[m + 1];
-        for (int it = ib + lane; it < ie; it += 64) {
-            const uint32_t code = items[it];
-            const int d = code >> 8, k3 = (code >> 4) & 15, k4 = code & 15;
-            const DDiag D = diags[d];
-            T2 e1[8], e2[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) { e1[i] = T2{0, 0}; e2[i] = T2{0, 0}; }
-            for (int r = D.ref0; r < D.ref0_end; ++r) {
-                const DRef R = refs[r];
-                const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
-                const T c = T(R.coef);
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const int off = b + (o & 1) * R.so3 + (o >> 1) * R.so4;
-#pragma unroll
-                    for (int g = 0; g < 2; ++g) {
-                        T2 v = Ia[g * nc + off];
-                        e1[g + 2 * o].x += c * v.x;
-                        e1[g + 2 * o].y += c * v.y;
-                    }
-                }
-            }
-            for (int r = D.ref1; r < D.ref1_end; ++r) {
-                const DRef R = refs[r];
-                const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
-                const T c = T(R.coef);
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const int off = b + (o & 1) * R.so3 + (o >> 1) * R.so4;
-#pragma unroll
-                    for (int g = 0; g < 2; ++g) {
-                        T2 v = Ib[g * nc + off];
-                        e2[g + 2 * o].x += c * v.x;
-                        e2[g + 2 * o].y += c * v.y;
-                    }
-                }
-            }
-            const T dc = T(D.coef);
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int a = s & 1, bb = (s >> 1) & 1, o = s >> 2;
-                T2 p = cmul(e1[a + 2 * o], e2[bb + 2 * o]);
-                acc[s].x += dc * p.x;
-                acc[s].y += dc * p.y;
-            }
+    for (int s = 0; s < 16; ++s) acc[s] = T2{0, 0};
+    for (int it = sg.x + lane; it < sg.y; it += 64) {
+        const uint32_t code = items[it];
+        const int d = code >> 8, k3 = (code >> 4) & 15, k4 = code & 15;
+        const DDiag D = diags[d];
+        switch (D.pad[0]) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
+        case 0: contract_item<T, 0, 0>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
+        case 1: contract_item<T, 1, 0>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
+        case 2: contract_item<T, 0, 1>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
+        default: contract_item<T, 1, 1>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
         }
+    }
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+    for (int s = 0; s < 16; ++s) {
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                acc[s].x += __shfl_xor(acc[s].x, off, 64);
-                acc[s].y += __shfl_xor(acc[s].y, off, 64);
-            }
+        for (int off = 32; off > 0; off >>= 1) {
+            acc[s].x += __shfl_xor(acc[s].x, off, 64);
+            acc[s].y += __shfl_xor(acc[s].y, off, 64);
         }
-        if (lane == 0) {
+    }
+    if (lane < 16) {
+        T2 v = acc[0];
 #pragma unroll
-            for (int s = 0; s < 16; ++s) Ct[((size_t)m * 16 + s) * V + q] = acc[s];
-        }
+        for (int s = 1; s < 16; ++s)
+            if (lane == s) v = acc[s];
+        slots[((size_t)sg.z * 16 + lane) * V + q] = v;
     }
 }
 
+// Sum of the partial slots of each channel, in slot order.
 template <typename T>
-void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *Ct, int nc, const int L[3],
-                     int n_ch, const int32_t *item_begin, const uint32_t *items, const DDiag *diags,
-                     const DRef *refs, hipStream_t st) {
+__global__ __launch_bounds__(256) void k_combine(const typename cplx_t<T>::type *__restrict__ slots,
+                                                 typename cplx_t<T>::type *__restrict__ Ct, int n_ch, int V,
+                                                 const int32_t *__restrict__ ch_slot_begin) {
+    using T2 = typename cplx_t<T>::type;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)n_ch * 16 * V) return;
+    const int m = (int)(i / (16L * V));
+    const long rest = i - (long)m * 16 * V;
+    const int b = ch_slot_begin[m], e = ch_slot_begin[m + 1];
+    T2 v = slots[(size_t)b * 16 * V + rest];
+    for (int s = b + 1; s < e; ++s) {
+        const T2 w = slots[(size_t)s * 16 * V + rest];
+        v.x += w.x;
+        v.y += w.y;
+    }
+    Ct[i] = v;
+}
+
+template <typename T>
+void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots,
+                     typename cplx_t<T>::type *Ct, int nc, const int L[3], int n_ch, const ContractTables &tb,
+                     hipStream_t st) {
     const int V = L[0] * L[1] * L[2];
-    hipLaunchKernelGGL((k_contract<T>), dim3(V), dim3(256), 0, st, Iq, Ct, nc, L[0], L[1], L[2], n_ch, item_begin,
-                       items, diags, refs);
+    const long nwg = 8L * ((V + 7) / 8) * tb.ntask;
+    hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, L[0], L[1], L[2],
+                       tb.qorder, tb.ntask, tb.segs, tb.items, tb.diags, tb.refs);
+    const long n = (long)n_ch * 16 * V;
+    hipLaunchKernelGGL((k_combine<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slots, Ct, n_ch, V,
+                       tb.ch_slot_begin);
 }
 
 // ----------------------------------------------------------------------------
@@ -439,10 +505,10 @@ template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
 template void launch_transpose<double>(const double2 *, double2 *, long, long, hipStream_t);
 template void launch_transpose<float>(const float2 *, float2 *, long, long, hipStream_t);
-template void launch_contract<double>(const double2 *, double2 *, int, const int[3], int, const int32_t *,
-                                      const uint32_t *, const DDiag *, const DRef *, hipStream_t);
-template void launch_contract<float>(const float2 *, float2 *, int, const int[3], int, const int32_t *,
-                                     const uint32_t *, const DDiag *, const DRef *, hipStream_t);
+template void launch_contract<double>(const double2 *, double2 *, double2 *, int, const int[3], int,
+                                      const ContractTables &, hipStream_t);
+template void launch_contract<float>(const float2 *, float2 *, float2 *, int, const int[3], int,
+                                     const ContractTables &, hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
                                       double *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,

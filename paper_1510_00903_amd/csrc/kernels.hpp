@@ -12,7 +12,7 @@ struct DDiag {           // one diagram of one requested channel
     double coef;         // parity of the representative permutation times source weights
     int ref0, ref0_end;  // block refs of site 0 (B1 at X+r)
     int ref1, ref1_end;  // block refs of site 1 (B2 at X)
-    int pad[2];
+    int pad[2];          // pad[0]: carry pattern, bit 0 = site of a', bit 1 = site of b'
 };
 struct DRef {            // one intermediate entering a block
     double coef;         // sink-term weight times exchange sign
@@ -20,6 +20,18 @@ struct DRef {            // one intermediate entering a block
     int so3, so4;        // stride of alpha' / beta' (0 if not carried by this intermediate)
     int sk3, sk4;        // stride of the open index of B3 / B4 (0 if absent)
     int pad;
+};
+
+// Device pointers of the contraction tables of one plan.
+struct ContractTables {
+    const int32_t *qorder;        // V momenta, each q followed by -q
+    int ntask;                    // tasks per momentum
+    const int4 *segs;             // 4 per task: item begin, item end, slot, unused
+    const uint32_t *items;        // diagram << 8 | k3 << 4 | k4
+    const DDiag *diags;
+    const DRef *refs;
+    const int32_t *ch_slot_begin; // n_ch + 1
+    int nslot;
 };
 
 template <typename T> struct cplx_t;
@@ -39,9 +51,9 @@ void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::ty
                       hipStream_t st);
 
 template <typename T>
-void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *Ct, int nc, const int L[3],
-                     int n_ch, const int32_t *item_begin, const uint32_t *items, const DDiag *diags,
-                     const DRef *refs, hipStream_t st);
+void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots,
+                     typename cplx_t<T>::type *Ct, int nc, const int L[3], int n_ch, const ContractTables &tb,
+                     hipStream_t st);
 
 template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
