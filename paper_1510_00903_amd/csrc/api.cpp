@@ -47,10 +47,11 @@ struct DevPlan {
     int4 *d_segs = nullptr;
     int32_t *d_ch_slot_begin = nullptr;
     int ntask = 0, nslot = 0;
+    int2 *d_content = nullptr;      // per requested channel: (n_light, n_strange)
     size_t table_bytes = 0;
     ~DevPlan() {
         (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_items); (void)hipFree(d_diags);
-        (void)hipFree(d_refs); (void)hipFree(d_segs); (void)hipFree(d_ch_slot_begin);
+        (void)hipFree(d_refs); (void)hipFree(d_segs); (void)hipFree(d_ch_slot_begin); (void)hipFree(d_content);
     }
 };
 
@@ -232,6 +233,17 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
     HIP_TRY(upload_vec(&dp->d_refs, refs));
     HIP_TRY(upload_vec(&dp->d_segs, segs));
     HIP_TRY(upload_vec(&dp->d_ch_slot_begin, ch_slot_begin));
+    {
+        std::vector<int2> content;
+        for (int ch : P.channels) {
+            const int *b = bbc::channel_baryons(ch);
+            int ns = 0;
+            for (int s2 = 0; s2 < 2; ++s2)
+                for (int i = 0; i < 3; ++i) ns += bbc::baryon(b[s2]).flav[i] == bbc::FS;
+            content.push_back(make_int2(6 - ns, ns));
+        }
+        HIP_TRY(upload_vec(&dp->d_content, content));
+    }
     dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + items.size() * 4 +
                       diags.size() * sizeof(bbc::DDiag) + refs.size() * sizeof(bbc::DRef) +
                       segs.size() * sizeof(int4) + ch_slot_begin.size() * 4;
@@ -241,7 +253,8 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
 }
 
 size_t workspace_bytes(long V, int nc, int n_ch, int nslot, size_t csize) {
-    // I and Iq: 2 spins x nc components x V; Ct: n_ch x 16 x V; partial slots: nslot x 16 x V
+    // I and Iq: 2 spins x nc components x V; Ct: n_ch x 16 x V; partial slots: nslot x 16 x V;
+    // then the rescale maxima (FP32 form)
     return (size_t)2 * 2 * nc * V * csize + (size_t)(n_ch + nslot) * 16 * V * csize + 256 * 4;
 }
 
@@ -291,6 +304,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     T2 *Iq = I + (size_t)2 * nc * V;
     T2 *Ct = Iq + (size_t)2 * nc * V;
     T2 *slots = Ct + (size_t)n_ch * 16 * V;
+    uint32_t *kmax = (uint32_t *)(slots + (size_t)dp->nslot * 16 * V);
     const int32_t *qorder = nullptr;
     {
         auto key = std::vector<int>{L[0], L[1], L[2]};
@@ -309,10 +323,12 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     T2 *out = (T2 *)C_out;
     for (int n = 0; n < n_t; ++n) {
         const T2 *sl = Sl + (size_t)n * V * 144, *ss = Ss + (size_t)n * V * 144;
+        const bool fp32 = sizeof(T) == 4;
         {
             StageTimer tm(ctx, st, 0);
+            if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
             bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin,
-                                  dp->pat_begin, st);
+                                  dp->pat_begin, fp32 ? kmax : nullptr, st);
         }
         {
             StageTimer tm(ctx, st, 1);
@@ -334,7 +350,8 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
             StageTimer tm(ctx, st, 5);
             bbc::launch_finalize<T>(Ct, out + (size_t)n * n_ch * V * 16, n_ch, (int)V,
                                     energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0), 1.0 / (double)V,
-                                    C_scale ? C_scale + (size_t)n * n_ch : nullptr, st);
+                                    C_scale ? C_scale + (size_t)n * n_ch : nullptr, fp32 ? kmax : nullptr,
+                                    dp->d_content, st);
         }
         HIP_TRY(hipGetLastError());
     }
@@ -473,7 +490,6 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     if (n_t < 0 || n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list or negative n_t");
     if (n_t > 0 && (!S_light || !S_strange || !t_list || !C_out)) return fail(BBC_EINVAL, "NULL buffer");
     if (prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
-    if (prec == BBC_F32) return fail(BBC_EUNSUPPORTED, "FP32 form not available in this build");
     for (int i = 0; i < n_ch; ++i)
         if (ch_list[i] < 0 || ch_list[i] >= bbc::kNumChannelsAll)
             return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");

@@ -11,7 +11,17 @@
 //   k_finalize   normalisation and transpose to the output layout [r][spin]
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace bbc {
+
+// floor(log2(m)) for m > 0 (0 for m == 0): the rescale 2^-e brings max|S| into [1, 2).
+__device__ __forceinline__ int pow2_exponent(float m) {
+    if (!(m > 0.0f)) return 0;
+    int e;
+    (void)frexpf(m, &e);
+    return e - 1;
+}
 
 template <typename T2> __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
     return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -45,18 +55,24 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
                                                 typename cplx_t<T>::type *__restrict__ I, int V, int nc, int g0,
                                                 const uint32_t *__restrict__ terms,
                                                 const int32_t *__restrict__ term_begin, int p0, int p1, int p2,
-                                                int p3, int p4) {
+                                                int p3, int p4, const uint32_t *__restrict__ kmax) {
     using T2 = typename cplx_t<T>::type;
     __shared__ T2 sS[2][TS][144];
     __shared__ T2 sQ[TS][432];
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * TS;
+    // FP32 form: exact power-of-two rescale of each flavour's slice
+    T kl = T(1), ks = T(1);
+    if (kmax) {
+        kl = T(ldexp(1.0, -pow2_exponent(__uint_as_float(kmax[0]))));
+        ks = T(ldexp(1.0, -pow2_exponent(__uint_as_float(kmax[1]))));
+    }
     for (int i = tid; i < TS * 144; i += 256) {
         int s = i / 144, e = i - s * 144, x = x0 + s;
         T2 zl = T2{0, 0}, zs = T2{0, 0};
         if (x < V) { zl = Sl[(size_t)x * 144 + e]; zs = Ss[(size_t)x * 144 + e]; }
-        sS[0][s][e] = zl;
-        sS[1][s][e] = zs;
+        sS[0][s][e] = T2{zl.x * kl, zl.y * kl};
+        sS[1][s][e] = T2{zs.x * ks, zs.y * ks};
     }
     const int pb[5] = {p0, p1, p2, p3, p4};
     const int site = tid % TS;
@@ -116,11 +132,38 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const int pb[5], hipStream_t st) {
+                   const int32_t *term_begin, const int pb[5], const uint32_t *kmax, hipStream_t st) {
     constexpr int TS = 8;
     int nblk = (V + TS - 1) / TS;
     hipLaunchKernelGGL((k_blocks<T, TS>), dim3(nblk), dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms, term_begin,
-                       pb[0], pb[1], pb[2], pb[3], pb[4]);
+                       pb[0], pb[1], pb[2], pb[3], pb[4], kmax);
+}
+
+// ----------------------------------------------------------------------------
+// FP32 form, input staging: largest |Re|, |Im| of one flavour's slice, as the
+// bit pattern of a non-negative float (integer max is order independent, so
+// the result does not depend on scheduling).
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_absmax(const float2 *__restrict__ S, long n, uint32_t *__restrict__ out) {
+    float m = 0.0f;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float2 v = S[i];
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, kmax, 2);
+    const int nblk = (int)std::min<long>(2048, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Sl, n, kmax);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Ss, n, kmax + 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -310,11 +353,26 @@ void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::ty
 // channel in a fixed order (no atomics: results are bit-reproducible).
 // Iq layout: [q][g][nc]; slot layout: [slot][16][V].
 // ----------------------------------------------------------------------------
+// acc += v; in the FP32 form with a running compensation (TwoSum, Knuth), so
+// that the open-index and diagram sums keep FP32 rounding at every addition.
+template <typename T> struct Acc {
+    __device__ static void add(T &a, T &c, T v) { a += v; }
+};
+template <> struct Acc<float> {
+    __device__ static void add(float &a, float &c, float v) {
+        const float s = a + v;
+        const float bv = s - a;
+        c += (a - (s - bv)) + (v - bv);
+        a = s;
+    }
+};
+
 template <typename T, int C3, int C4>
 __device__ __forceinline__ void contract_item(const typename cplx_t<T>::type *__restrict__ Ia,
                                               const typename cplx_t<T>::type *__restrict__ Ib, int nc,
                                               const DDiag &D, const DRef *__restrict__ refs, int k3, int k4,
-                                              typename cplx_t<T>::type (&acc)[16]) {
+                                              typename cplx_t<T>::type (&acc)[16],
+                                              typename cplx_t<T>::type (&cmp)[16]) {
     using T2 = typename cplx_t<T>::type;
     constexpr int N1 = 1 << ((C3 == 0) + (C4 == 0));   // outer-spin combinations held by site 0
     constexpr int N2 = 4 / N1;
@@ -364,8 +422,8 @@ __device__ __forceinline__ void contract_item(const typename cplx_t<T>::type *__
         const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
         const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
         const T2 p = cmul(e1[a + 2 * o1], e2[bb + 2 * o2]);
-        acc[s].x = fma(dc, p.x, acc[s].x);
-        acc[s].y = fma(dc, p.y, acc[s].y);
+        Acc<T>::add(acc[s].x, cmp[s].x, dc * p.x);
+        Acc<T>::add(acc[s].y, cmp[s].y, dc * p.y);
     }
 }
 
@@ -393,22 +451,24 @@ __global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int4 sg = segs[task * 4 + wave];
     if (sg.x >= sg.y) return;
-    T2 acc[16];
+    T2 acc[16], cmp[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) acc[s] = T2{0, 0};
+    for (int s = 0; s < 16; ++s) { acc[s] = T2{0, 0}; cmp[s] = T2{0, 0}; }
     for (int it = sg.x + lane; it < sg.y; it += 64) {
         const uint32_t code = items[it];
         const int d = code >> 8, k3 = (code >> 4) & 15, k4 = code & 15;
         const DDiag D = diags[d];
         switch (D.pad[0]) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
-        case 0: contract_item<T, 0, 0>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
-        case 1: contract_item<T, 1, 0>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
-        case 2: contract_item<T, 0, 1>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
-        default: contract_item<T, 1, 1>(Ia, Ib, nc, D, refs, k3, k4, acc); break;
+        case 0: contract_item<T, 0, 0>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
+        case 1: contract_item<T, 1, 0>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
+        case 2: contract_item<T, 0, 1>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
+        default: contract_item<T, 1, 1>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
         }
     }
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
+        acc[s].x += cmp[s].x;
+        acc[s].y += cmp[s].y;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             acc[s].x += __shfl_xor(acc[s].x, off, 64);
@@ -467,7 +527,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type *__restrict__ Ct,
                                                   typename cplx_t<T>::type *__restrict__ out, int n_ch, int V,
                                                   const double *__restrict__ energy, double dt, double inv_v,
-                                                  double *__restrict__ scale_out) {
+                                                  double *__restrict__ scale_out, const uint32_t *__restrict__ kmax,
+                                                  const int2 *__restrict__ content) {
     using T2 = typename cplx_t<T>::type;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (long)n_ch * V) return;
@@ -475,8 +536,15 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
     const double e = energy ? exp(energy[m] * dt) : 1.0;
     T f;
     if (scale_out) {
+        // FP64 factor: exp(E (t - t0)) and the inverse of the propagator rescale,
+        // kappa_l^-n_l kappa_s^-n_s with kappa = 2^-e (exact powers of two)
         f = T(inv_v);
-        if (x == 0) scale_out[m] = e;
+        if (x == 0) {
+            const int el = kmax ? pow2_exponent(__uint_as_float(kmax[0])) : 0;
+            const int es = kmax ? pow2_exponent(__uint_as_float(kmax[1])) : 0;
+            const int2 nls = content[m];
+            scale_out[m] = ldexp(e, el * nls.x + es * nls.y);
+        }
     } else {
         f = T(e * inv_v);
     }
@@ -490,17 +558,18 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
 
 template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
-                     const double *energy, double dt, double inv_v, double *scale_out, hipStream_t st) {
+                     const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
+                     const int2 *content, hipStream_t st) {
     const long n = (long)n_ch * V;
     hipLaunchKernelGGL((k_finalize<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Ct, out, n_ch, V,
-                       energy, dt, inv_v, scale_out);
+                       energy, dt, inv_v, scale_out, kmax, content);
 }
 
 // explicit instantiations
 template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
-                                    const int32_t *, const int[5], hipStream_t);
+                                    const int32_t *, const int[5], const uint32_t *, hipStream_t);
 template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
-                                   const int32_t *, const int[5], hipStream_t);
+                                   const int32_t *, const int[5], const uint32_t *, hipStream_t);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
 template void launch_transpose<double>(const double2 *, double2 *, long, long, hipStream_t);
@@ -510,8 +579,8 @@ template void launch_contract<double>(const double2 *, double2 *, double2 *, int
 template void launch_contract<float>(const float2 *, float2 *, float2 *, int, const int[3], int,
                                      const ContractTables &, hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
-                                      double *, hipStream_t);
+                                      double *, const uint32_t *, const int2 *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,
-                                     hipStream_t);
+                                     const uint32_t *, const int2 *, hipStream_t);
 
 }  // namespace bbc

@@ -41,7 +41,10 @@ template <> struct cplx_t<float> { using type = float2; };
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const int pat_begin[5], hipStream_t st);
+                   const int32_t *term_begin, const int pat_begin[5], const uint32_t *kmax, hipStream_t st);
+
+// FP32 form: per-flavour max |Re|,|Im| of a slice into kmax[0] (light), kmax[1] (strange).
+void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st);
 
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sign, hipStream_t st);
@@ -57,7 +60,8 @@ void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::typ
 
 template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
-                     const double *energy, double dt, double inv_v, double *scale_out, hipStream_t st);
+                     const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
+                     const int2 *content, hipStream_t st);
 
 bool fft_size_supported(int n);
 

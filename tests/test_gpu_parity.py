@@ -185,3 +185,60 @@ def test_16cubed_invariants(big, bbc):
                ("S0 S0 > p X-", "S0 S0 > n X0", -1), ("S0 L > p X-", "S0 L > n X0", 1)]
         for a, b, s in iso:
             assert normwise(C[names[a]], s * C[names[b]]) < TOL64, (a, b)
+
+
+# ---------------------------------------------------------------- FP32 form
+TOL32 = 1e-5
+
+
+def _fp32_inputs(lat, t_list, seed):
+    """Correlated slices (t-independent field + 1e-3 noise, exp(-m t) decay), rounded to FP32."""
+    Sl = np.stack([synth.slice_correlated(lat, t, synth.LIGHT, seed=seed, dtype=np.complex64) for t in t_list])
+    Ss = np.stack([synth.slice_correlated(lat, t, synth.STRANGE, seed=seed, dtype=np.complex64) for t in t_list])
+    return Sl, Ss
+
+
+def test_fp32_all_channels_small_with_deep_slice(bbc, ctx):
+    """FP32 form against the FP64 oracle (on the same FP32-rounded inputs), every channel,
+    including t = 63 where unscaled six-propagator products would underflow FP32."""
+    lat = (3, 3, 3)
+    t_list = [0, 63]
+    Sl, Ss = _fp32_inputs(lat, t_list, seed=201)
+    out, scale = gpu_correlate(ctx, Sl, Ss, t_list, ALL)
+    assert out.dtype == np.complex64 and scale.dtype == np.float64
+    r = wick.all_r(*lat)
+    for n in range(2):
+        ref_scale = None
+        for c in ALL:
+            ch = _name_to_tuple(bbc.channel_name(c))
+            ref = wick.correlate(Sl[n].astype(np.complex128), Ss[n].astype(np.complex128), ch, r)
+            got = out[n, c].reshape(-1, 16).astype(np.complex128) * scale[n, c]
+            if c < 52:
+                assert np.isfinite(got).all()
+                assert normwise(got, ref) < TOL32, (t_list[n], c, normwise(got, ref))
+                ref_scale = max(ref_scale or 0, np.abs(ref).max())
+            else:
+                assert np.abs(got).max() < TOL32 * ref_scale
+
+
+def test_fp32_vs_fp64_16cubed_all_channels(bbc, ctx):
+    """FP32 form against the FP64 form on a 16^3 lattice, every r, all 52 channels;
+    the per-channel normwise error is written to gpurun_out/ when that folder exists."""
+    lat = (16, 16, 16)
+    t_list = [5, 40]
+    Sl, Ss = _fp32_inputs(lat, t_list, seed=202)
+    chans = list(range(52))
+    out32, scale = gpu_correlate(ctx, Sl, Ss, t_list, chans)
+    out64 = gpu_correlate(ctx, Sl.astype(np.complex128), Ss.astype(np.complex128), t_list, chans)
+    errs = np.zeros((len(t_list), 52))
+    for n in range(len(t_list)):
+        for c in chans:
+            got = out32[n, c].astype(np.complex128) * scale[n, c]
+            errs[n, c] = normwise(got, out64[n, c])
+    out_dir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out_dir):
+        with open(os.path.join(out_dir, "fp32_errors_16c.txt"), "w") as f:
+            f.write("# channel  normwise error of the FP32 form vs the FP64 form, 16^3, t=%s\n" % t_list)
+            for c in chans:
+                f.write("%2d %-16s %s\n" % (c, bbc.channel_name(c), " ".join("%.3e" % e for e in errs[:, c])))
+    assert errs.max() < TOL32, errs.max()
