@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="16c32-f64", choices=["16c32-f64", "32c64-f64", "32c64-f32"],
+                    help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
+                         "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -120,15 +123,21 @@ def main():
     import paper_1510_00903_amd as bbc
     import synth
 
-    L, T = 16, 32
+    fp32 = args.workload.endswith("f32")
+    L, T = (16, 32) if args.workload.startswith("16") else (32, 64)
     channels = list(range(52))
     n_ch = len(channels)
     dev = torch.device("cuda:0")
+    cdt = np.complex64 if fp32 else np.complex128
     print("bench: generating %d^3 x %d propagators" % (L, T), file=sys.stderr, flush=True)
-    Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 1)
+    if L == 16:
+        Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 1)
+    else:
+        Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 2, kind="correlated", dtype=cdt)
     d_l = torch.from_numpy(Sl).to(dev)
     d_s = torch.from_numpy(Ss).to(dev)
-    out = torch.empty((T, n_ch, L, L, L, 16), dtype=torch.complex128, device=dev)
+    out = torch.empty((T, n_ch, L, L, L, 16), dtype=torch.complex64 if fp32 else torch.complex128, device=dev)
+    scale = torch.empty((T, n_ch), dtype=torch.float64, device=dev) if fp32 else None
     ctx = bbc.Context(0)
     t_list = list(range(T))
 
@@ -143,14 +152,14 @@ def main():
 
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        ctx.correlate(d_l, d_s, t_list, channels, out=out)
+        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
     torch.cuda.synchronize()
     ctx.profile(True)
     ctx.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ctx.correlate(d_l, d_s, t_list, channels, out=out)
+        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = ctx.profile_read()
@@ -163,7 +172,8 @@ def main():
 
     st = bbc.plan_stats(channels)
     nc = st["components"] // 2
-    csize = 16
+    csize = 8 if fp32 else 16
+    peak_alu = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     stages = {}
     for name, (ms, launches) in prof.items():
         # fft stages launch one kernel per axis
@@ -179,14 +189,14 @@ def main():
     if dom == "contract":
         flops = 8.0 * 16 * st["iterations"] * L ** 3        # complex MAC = 8 flops, 16 spin outputs
         achieved = flops / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak_alu,
+                "unit": "TFLOP/s", "frac": round(achieved / peak_alu, 4)}
     else:
         achieved = nbytes / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4)}
     roof["kernel"] = dom
-    roof["traffic"] = traffic_for(dom, "f64")
+    roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64")
     for name in stages:
         b2, nb, _ = stage_model(name, L, nc, n_ch, csize)
         stages[name]["hbm_GBs"] = round(nb / (stages[name]["us_per_launch"] * 1e-6) / 1e9, 1)
@@ -201,17 +211,20 @@ def main():
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(value / PAPER_SITE_CH_PER_S, 2),
-        "baseline_context": "paper Table 5, 16^3x32, 52 channels, 32 BlueGene/Q nodes, best layout 19 s",
-        "dtype": "f64",
-        "data": "synthetic (seeded Gaussian propagators, exp(-m t) decay)",
-        "config": {"workload": "16^3x32 lattice, all 52 BB channels, FP64 plain form, upper spins",
+        "vs_baseline": round(value / PAPER_SITE_CH_PER_S, 2) if L == 16 else None,
+        "baseline_context": "paper Table 5, 16^3x32, 52 channels, 32 BlueGene/Q nodes, best layout 19 s"
+                            if L == 16 else None,
+        "dtype": "f32" if fp32 else "f64",
+        "data": "synthetic (seeded Gaussian propagators, exp(-m t) decay)" if L == 16 else
+                "synthetic (seeded t-independent Gaussian field + 1e-3 noise per slice, exp(-m t) decay)",
+        "config": {"workload": "%d^3x%d lattice, all 52 BB channels, %s, upper spins"
+                               % (L, T, "FP32 form (rescaled, compensated)" if fp32 else "FP64 plain form"),
                    "lattice": [L, L, L], "T": T, "channels": n_ch, "site_channels_per_step": site_ch,
                    "block_components_per_site": st["components"], "iterations": st["iterations"]},
         "roofline": roof,
         "stages": stages,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and L == 16:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(Sl, Ss, 7)
     ctx.close()

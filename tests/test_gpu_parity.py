@@ -242,3 +242,19 @@ def test_fp32_vs_fp64_16cubed_all_channels(bbc, ctx):
             for c in chans:
                 f.write("%2d %-16s %s\n" % (c, bbc.channel_name(c), " ".join("%.3e" % e for e in errs[:, c])))
     assert errs.max() < TOL32, errs.max()
+
+
+def test_16cubed_su3_limit_relations(bbc, ctx):
+    """SU(3)-limit run (S_s := S_l) at 16^3: u <-> s maps Sigma+ n onto Sigma- Xi0 and
+    p Xi- onto itself, with r -> -r and both baryon pairs swapped."""
+    L = 16
+    Sl, Ss = synth.propagators(L, 8, seed=108, t_list=[3], su3=True)
+    names = {bbc.channel_name(c): c for c in range(52)}
+    chans = [names["S+ n > S+ n"], names["S- X0 > S- X0"], names["p X- > p X-"]]
+    out = gpu_correlate(ctx, Sl, Ss, [3], chans)[0].reshape(3, -1, 16)
+    r = wick.all_r(L, L, L)
+    m = (-r) % L
+    mi = m[:, 0] + L * (m[:, 1] + L * m[:, 2])
+    swap = [((s >> 1) & 1) + 2 * (s & 1) + 4 * ((s >> 3) & 1) + 8 * ((s >> 2) & 1) for s in range(16)]
+    assert normwise(out[0], out[1][mi][:, swap]) < TOL64
+    assert normwise(out[2], out[2][mi][:, swap]) < TOL64
