@@ -54,7 +54,10 @@ typedef enum {
     BBC_EINVAL = -1,       /* bad argument (null pointer, size, channel, lattice) */
     BBC_ENOMEM = -2,       /* workspace would exceed the budget, or allocation failed */
     BBC_EDEVICE = -3,      /* HIP runtime error */
-    BBC_EUNSUPPORTED = -4  /* valid request this build does not handle (e.g. lattice extent) */
+    BBC_EUNSUPPORTED = -4, /* valid request this build does not handle (e.g. lattice extent) */
+    BBC_ETIMEOUT = -5,     /* bbc_wait: job not finished within the timeout */
+    BBC_ECANCELLED = -6,   /* bbc_wait: job was cancelled */
+    BBC_ESTATE = -7        /* call not valid in the current state (server not started, job running) */
 } bbc_status;
 
 typedef enum { BBC_F64 = 0, BBC_F32 = 1 } bbc_precision;
@@ -135,6 +138,47 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
                          int n_t, const int32_t *t_list, int t0,
                          int n_ch, const int32_t *ch_list, bbc_spin spin,
                          const double *energy, void *C_out, double *C_scale, void *stream);
+
+/*
+ * Serving: continuous batching of correlator jobs on one device.
+ *
+ * A job is (resident propagator set, list of its time slices, channel list).
+ * bbc_server_start starts n_slots slots, each with its own HIP stream and
+ * workspace.  Queued jobs are admitted in arrival order as soon as a slot is
+ * free and the job's workspace fits the context's HBM budget (together with
+ * the resident propagators and the other slots' workspaces); an admitted job
+ * advances one time slice at a time, so jobs that arrive while others run are
+ * started between slices and their work overlaps on the device.  A job's
+ * result does not depend on what runs beside it (same kernels, own workspace,
+ * fixed reduction order).  Output buffers are caller-owned device memory
+ * (layout as for bbc_correlate) and must stay valid until the job finishes.
+ *
+ * bbc_prop_upload copies n_t slices of both flavours (host or device memory,
+ * [n_t][Lz][Ly][Lx][12][12] complex of the precision's type) into memory owned
+ * by the context and returns a handle; bbc_prop_release frees it once no queued
+ * or running job uses it.  bbc_submit queues a job over slices slice_idx[] of a
+ * propagator set (t_list gives their times for exp(E (t - t0))).  Job states:
+ * 0 queued, 1 running, 2 done, 3 cancelled, 4 failed.  bbc_wait blocks until the
+ * job ends (timeout_ms < 0: no limit) and returns BBC_OK, BBC_ECANCELLED, the
+ * job's error, or BBC_ETIMEOUT.  bbc_cancel removes a queued job or stops a
+ * running one after its slices in flight (its output is then incomplete).
+ * bbc_job_times reports submit-to-start, start-to-end and total wall time in ms.
+ * bbc_job_forget drops a finished job's record.  bbc_server_stop cancels queued
+ * jobs, waits for running ones, and frees the slots.
+ */
+bbc_status bbc_server_start(bbc_context *ctx, int n_slots);
+bbc_status bbc_server_stop(bbc_context *ctx);
+bbc_status bbc_prop_upload(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, const void *S_light,
+                           const void *S_strange, int n_t, uint64_t *handle);
+bbc_status bbc_prop_release(bbc_context *ctx, uint64_t handle);
+bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *slice_idx, const int32_t *t_list,
+                      int t0, int n_ch, const int32_t *ch_list, bbc_spin spin, const double *energy, void *C_out,
+                      double *C_scale, uint64_t *job);
+bbc_status bbc_poll(bbc_context *ctx, uint64_t job, int *state);
+bbc_status bbc_wait(bbc_context *ctx, uint64_t job, int timeout_ms);
+bbc_status bbc_cancel(bbc_context *ctx, uint64_t job);
+bbc_status bbc_job_times(bbc_context *ctx, uint64_t job, double *queue_ms, double *run_ms, double *total_ms);
+bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job);
 
 /*
  * Measurement.  With profiling on, bbc_correlate records a HIP event pair on

@@ -28,12 +28,20 @@ EXPORTED_SYMBOLS = [
     "bbc_num_channels", "bbc_num_channels_all", "bbc_channel_name", "bbc_channel_content",
     "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create", "bbc_destroy",
     "bbc_last_error", "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
+    "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
+    "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
 ]
+JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
+ETIMEOUT, ECANCELLED, ESTATE, ENOMEM = -5, -6, -7, -2
 STAGES = ["blocks", "fft_forward", "transpose", "contract", "fft_inverse", "finalize"]
 
 
 class BBCError(RuntimeError):
     """A negative bbc_status from the library, with its message."""
+
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 def library_path() -> str:
@@ -65,8 +73,20 @@ def load():
     lib.bbc_correlate.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
     lib.bbc_profile_enable.argtypes = [P, I]
     lib.bbc_profile_read.argtypes = [P, I, P, P]
+    lib.bbc_server_start.argtypes = [P, I]
+    lib.bbc_server_stop.argtypes = [P]
+    lib.bbc_prop_upload.argtypes = [P, P, I, P, P, I, P]
+    lib.bbc_prop_release.argtypes = [P, U64]
+    lib.bbc_submit.argtypes = [P, U64, I, P, P, I, I, P, I, P, P, P, P]
+    lib.bbc_poll.argtypes = [P, U64, P]
+    lib.bbc_wait.argtypes = [P, U64, I]
+    lib.bbc_cancel.argtypes = [P, U64]
+    lib.bbc_job_times.argtypes = [P, U64, P, P, P]
+    lib.bbc_job_forget.argtypes = [P, U64]
     for f in ("bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
-              "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read"):
+              "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
+              "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit",
+              "bbc_poll", "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -74,7 +94,7 @@ def load():
 
 def _check(status):
     if status != 0:
-        raise BBCError("bbcorr error %d: %s" % (status, load().bbc_last_error().decode()))
+        raise BBCError("bbcorr error %d: %s" % (status, load().bbc_last_error().decode()), status)
 
 
 def _i32(values):
@@ -165,6 +185,70 @@ class Context:
         cnt = (ctypes.c_int64 * n)()
         _check(self._lib.bbc_profile_read(self._ptr, n, ms, cnt))
         return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    # ---------------------------------------------------------------- serving
+    def server_start(self, n_slots: int = 2):
+        """Start the continuous-batching scheduler with n_slots concurrent job slots."""
+        _check(self._lib.bbc_server_start(self._ptr, n_slots))
+
+    def server_stop(self):
+        _check(self._lib.bbc_server_stop(self._ptr))
+
+    def prop_upload(self, S_light, S_strange) -> int:
+        """Copy a propagator set ([n_t, Lz, Ly, Lx, 12, 12] complex, host or device tensors)
+        into memory owned by the context; returns its handle."""
+        import torch
+        if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
+            raise BBCError("S_light and S_strange must have the same shape and dtype")
+        prec = F64 if S_light.dtype == torch.complex128 else F32
+        S_light, S_strange = S_light.contiguous(), S_strange.contiguous()
+        n_t, Lz, Ly, Lx = S_light.shape[:4]
+        lat, _ = _i32([Lx, Ly, Lz])
+        h = ctypes.c_uint64()
+        _check(self._lib.bbc_prop_upload(self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()),
+                                         ctypes.c_void_p(S_strange.data_ptr()), n_t, ctypes.byref(h)))
+        return h.value
+
+    def prop_release(self, handle: int):
+        _check(self._lib.bbc_prop_release(self._ptr, handle))
+
+    def submit(self, prop: int, slices, t_list, channels, out, scale=None, t0=0, spin=UPPER, energy=None) -> int:
+        """Queue a job over slices of a resident propagator set; out (and scale in FP32)
+        are caller-owned device tensors shaped as for correlate()."""
+        s_arr, n_t = _i32(slices)
+        t_arr, n2 = _i32(t_list)
+        ch_arr, n_ch = _i32(channels)
+        if n2 != n_t:
+            raise BBCError("t_list must have one entry per slice")
+        e_arr = None
+        if energy is not None:
+            e_arr = (ctypes.c_double * n_ch)(*[float(e) for e in energy])
+        j = ctypes.c_uint64()
+        _check(self._lib.bbc_submit(self._ptr, prop, n_t, s_arr, t_arr, int(t0), n_ch, ch_arr, int(spin), e_arr,
+                                    ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(scale.data_ptr()) if scale is not None else None,
+                                    ctypes.byref(j)))
+        return j.value
+
+    def poll(self, job: int) -> str:
+        st = ctypes.c_int()
+        _check(self._lib.bbc_poll(self._ptr, job, ctypes.byref(st)))
+        return JOB_STATES[st.value]
+
+    def wait(self, job: int, timeout_ms: int = -1):
+        _check(self._lib.bbc_wait(self._ptr, job, timeout_ms))
+
+    def cancel(self, job: int):
+        _check(self._lib.bbc_cancel(self._ptr, job))
+
+    def job_times(self, job: int):
+        """(queue_ms, run_ms, total_ms) of a finished job."""
+        v = [ctypes.c_double() for _ in range(3)]
+        _check(self._lib.bbc_job_times(self._ptr, job, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def job_forget(self, job: int):
+        _check(self._lib.bbc_job_forget(self._ptr, job))
 
     def correlate(self, S_light, S_strange, t_list, channels, t0=0, spin=UPPER, energy=None, out=None,
                   scale=None, stream=None):

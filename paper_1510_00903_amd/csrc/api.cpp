@@ -7,8 +7,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
+#include <deque>
+#include <thread>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -152,8 +156,67 @@ hipError_t upload_vec(E **dst, const std::vector<E> &src) {
 
 }  // namespace
 
+namespace {
+enum JobState { JOB_QUEUED = 0, JOB_RUNNING = 1, JOB_DONE = 2, JOB_CANCELLED = 3, JOB_FAILED = 4 };
+using Clock = std::chrono::steady_clock;
+
+// A propagator set resident in HBM (serving): n_t slices of both flavours.
+struct PropSet {
+    int L[3];
+    int prec;
+    int n_t;
+    void *dl = nullptr, *ds = nullptr;
+    size_t bytes = 0;
+    int refs = 0;            // queued or running jobs using it
+    bool released = false;
+};
+
+struct Job {
+    uint64_t id = 0;
+    PropSet *ps = nullptr;
+    std::vector<int> slice, tl;
+    int t0 = 0;
+    std::vector<int> chans;
+    int spin = 0;
+    std::vector<double> energy;
+    void *out = nullptr;
+    double *scale = nullptr;
+    DevPlan *dp = nullptr;
+    size_t foot = 0;
+    int state = JOB_QUEUED;
+    bbc_status status = BBC_OK;
+    std::string err;
+    bool cancel = false;
+    int next = 0, inflight = 0;
+    Clock::time_point t_submit, t_start, t_done;
+};
+
+struct Slot {
+    hipStream_t st = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    Job *job = nullptr;
+    std::deque<hipEvent_t> evs;   // one completion event per enqueued slice
+};
+
+struct Server {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    bool running = false, stop = false;
+    std::deque<Job *> queue;
+    std::map<uint64_t, std::unique_ptr<Job>> jobs;
+    std::map<uint64_t, std::unique_ptr<PropSet>> props;
+    std::vector<Slot> slots;
+    std::vector<hipEvent_t> evpool;
+    uint64_t next_id = 1;
+    size_t committed = 0;         // resident propagators + slot workspaces
+};
+}  // namespace
+
 struct bbc_context {
     int device = 0;
+    Server srv;
     uint64_t budget = 0;
     std::mutex mu;
     std::map<std::pair<std::vector<int>, int>, std::unique_ptr<DevPlan>> plans;
@@ -162,6 +225,7 @@ struct bbc_context {
     double *d_energy = nullptr;
     int energy_cap = 0;
     std::map<std::vector<int>, int32_t *> qorders;   // per lattice: momentum order
+    std::mutex qmu;                                   // guards qorders and plans for the server thread
     // profiling: event pairs recorded around kernel stages
     bool prof = false;
     struct Rec { int stage; hipEvent_t a, b; };
@@ -183,11 +247,11 @@ struct bbc_context {
 };
 
 namespace {
-// Records an event pair around one kernel stage when profiling is on.
+// Records an event pair around one kernel stage when profiling is on (ctx may be null).
 struct StageTimer {
     bbc_context *ctx; hipStream_t st; int stage; hipEvent_t a = nullptr;
     StageTimer(bbc_context *c, hipStream_t s, int g) : ctx(c), st(s), stage(g) {
-        if (ctx->prof && (a = ctx->event())) (void)hipEventRecord(a, st);
+        if (ctx && ctx->prof && (a = ctx->event())) (void)hipEventRecord(a, st);
     }
     ~StageTimer() {
         if (!a) return;
@@ -202,6 +266,7 @@ struct StageTimer {
 namespace {
 
 bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, DevPlan **out) {
+    std::lock_guard<std::mutex> lock(ctx->qmu);
     auto key = std::make_pair(chans, spin_offset);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) { *out = it->second.get(); return BBC_OK; }
@@ -273,14 +338,82 @@ bbc_status check_lattice(const int32_t *lattice, long *V) {
     return BBC_OK;
 }
 
+const int32_t *get_qorder(bbc_context *ctx, const int L[3], bbc_status *st) {
+    std::lock_guard<std::mutex> lock(ctx->qmu);
+    auto key = std::vector<int>{L[0], L[1], L[2]};
+    auto it = ctx->qorders.find(key);
+    if (it == ctx->qorders.end()) {
+        std::vector<int32_t> qo = pair_order(L);
+        int32_t *d = nullptr;
+        hipError_t e = upload_vec(&d, qo);
+        if (e != hipSuccess) {
+            *st = fail(BBC_EDEVICE, std::string("momentum order upload: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        it = ctx->qorders.emplace(key, d).first;
+    }
+    *st = BBC_OK;
+    return it->second;
+}
+
+// Launches the kernel sequence of one time slice on stream st, using the
+// workspace ws (layout of workspace_bytes).  Stage events are recorded only
+// for the direct (profiled) path.
+template <typename T>
+bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, void *ws, const int32_t *qorder,
+                         const void *slp, const void *ssp, int n_ch, const double *d_energy, double dt, void *outp,
+                         double *scale, hipStream_t st, bool timed) {
+    using T2 = typename bbc::cplx_t<T>::type;
+    const bbc::Plan &P = dp->plan;
+    const int nc = P.ncomp;
+    T2 *I = (T2 *)ws;
+    T2 *Iq = I + (size_t)2 * nc * V;
+    T2 *Ct = Iq + (size_t)2 * nc * V;
+    T2 *slots = Ct + (size_t)n_ch * 16 * V;
+    uint32_t *kmax = (uint32_t *)(slots + (size_t)dp->nslot * 16 * V);
+    bbc::ContractTables tb{qorder, dp->ntask, dp->d_segs, dp->d_items, dp->d_diags, dp->d_refs,
+                           dp->d_ch_slot_begin, dp->nslot};
+    const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
+    T2 *out = (T2 *)outp;
+    const bool fp32 = sizeof(T) == 4;
+    bbc_context *pc = timed ? ctx : nullptr;
+    {
+        StageTimer tm(pc, st, 0);
+        if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
+        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin, dp->pat_begin,
+                              fp32 ? kmax : nullptr, st);
+    }
+    {
+        StageTimer tm(pc, st, 1);
+        if (bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+    }
+    {
+        StageTimer tm(pc, st, 2);
+        bbc::launch_transpose<T>(I, Iq, 2L * nc, V, st);
+    }
+    {
+        StageTimer tm(pc, st, 3);
+        bbc::launch_contract<T>(Iq, slots, Ct, nc, L, n_ch, tb, st);
+    }
+    {
+        StageTimer tm(pc, st, 4);
+        if (bbc::launch_fft3d<T>(Ct, 16L * n_ch, L, +1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+    }
+    {
+        StageTimer tm(pc, st, 5);
+        bbc::launch_finalize<T>(Ct, out, n_ch, (int)V, d_energy, dt, 1.0 / (double)V, scale, fp32 ? kmax : nullptr,
+                                dp->d_content, st);
+    }
+    HIP_TRY(hipGetLastError());
+    return BBC_OK;
+}
+
 template <typename T>
 bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const void *S_light,
                          const void *S_strange, int n_t, const int32_t *t_list, int t0, int n_ch,
                          const double *energy, void *C_out, double *C_scale, hipStream_t st) {
     using T2 = typename bbc::cplx_t<T>::type;
-    const bbc::Plan &P = dp->plan;
-    const int nc = P.ncomp;
-    const size_t need = workspace_bytes(V, nc, n_ch, dp->nslot, sizeof(T2));
+    const size_t need = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->nslot, sizeof(T2));
     if (ctx->budget && need + dp->table_bytes > ctx->budget)
         return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
     if (ctx->ws_bytes < need) {
@@ -299,63 +432,176 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         }
         HIP_TRY(hipMemcpyAsync(ctx->d_energy, energy, sizeof(double) * n_ch, hipMemcpyHostToDevice, st));
     }
-    char *w = (char *)ctx->ws;
-    T2 *I = (T2 *)w;
-    T2 *Iq = I + (size_t)2 * nc * V;
-    T2 *Ct = Iq + (size_t)2 * nc * V;
-    T2 *slots = Ct + (size_t)n_ch * 16 * V;
-    uint32_t *kmax = (uint32_t *)(slots + (size_t)dp->nslot * 16 * V);
-    const int32_t *qorder = nullptr;
-    {
-        auto key = std::vector<int>{L[0], L[1], L[2]};
-        auto it = ctx->qorders.find(key);
-        if (it == ctx->qorders.end()) {
-            std::vector<int32_t> qo = pair_order(L);
-            int32_t *d = nullptr;
-            HIP_TRY(upload_vec(&d, qo));
-            it = ctx->qorders.emplace(key, d).first;
-        }
-        qorder = it->second;
-    }
-    bbc::ContractTables tb{qorder, dp->ntask, dp->d_segs, dp->d_items, dp->d_diags, dp->d_refs,
-                           dp->d_ch_slot_begin, dp->nslot};
+    bbc_status s;
+    const int32_t *qorder = get_qorder(ctx, L, &s);
+    if (!qorder) return s;
     const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
     T2 *out = (T2 *)C_out;
     for (int n = 0; n < n_t; ++n) {
-        const T2 *sl = Sl + (size_t)n * V * 144, *ss = Ss + (size_t)n * V * 144;
-        const bool fp32 = sizeof(T) == 4;
-        {
-            StageTimer tm(ctx, st, 0);
-            if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
-            bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin,
-                                  dp->pat_begin, fp32 ? kmax : nullptr, st);
-        }
-        {
-            StageTimer tm(ctx, st, 1);
-            if (bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
-        }
-        {
-            StageTimer tm(ctx, st, 2);
-            bbc::launch_transpose<T>(I, Iq, 2L * nc, V, st);
-        }
-        {
-            StageTimer tm(ctx, st, 3);
-            bbc::launch_contract<T>(Iq, slots, Ct, nc, L, n_ch, tb, st);
-        }
-        {
-            StageTimer tm(ctx, st, 4);
-            if (bbc::launch_fft3d<T>(Ct, 16L * n_ch, L, +1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
-        }
-        {
-            StageTimer tm(ctx, st, 5);
-            bbc::launch_finalize<T>(Ct, out + (size_t)n * n_ch * V * 16, n_ch, (int)V,
-                                    energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0), 1.0 / (double)V,
-                                    C_scale ? C_scale + (size_t)n * n_ch : nullptr, fp32 ? kmax : nullptr,
-                                    dp->d_content, st);
-        }
-        HIP_TRY(hipGetLastError());
+        s = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, qorder, Sl + (size_t)n * V * 144, Ss + (size_t)n * V * 144,
+                             n_ch, energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0),
+                             out + (size_t)n * n_ch * V * 16, C_scale ? C_scale + (size_t)n * n_ch : nullptr, st,
+                             true);
+        if (s) return s;
     }
     return BBC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+size_t job_footprint(const Job &j) {
+    const long V = (long)j.ps->L[0] * j.ps->L[1] * j.ps->L[2];
+    const size_t cs = j.ps->prec == BBC_F64 ? 16 : 8;
+    return workspace_bytes(V, j.dp->plan.ncomp, (int)j.chans.size(), j.dp->nslot, cs) + 8 * j.chans.size() + 256;
+}
+
+// Enqueues slice j.next of a running job on its slot.
+bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
+    const PropSet &ps = *j.ps;
+    const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
+    const int n_ch = (int)j.chans.size();
+    bbc_status s;
+    const int32_t *qorder = get_qorder(ctx, ps.L, &s);
+    if (!qorder) return s;
+    const size_t wsz = workspace_bytes(V, j.dp->plan.ncomp, n_ch, j.dp->nslot, ps.prec == BBC_F64 ? 16 : 8);
+    const double *d_energy = j.energy.empty() ? nullptr : (const double *)((char *)sl.ws + ((wsz + 255) & ~(size_t)255));
+    const int n = j.next;
+    const int si = j.slice[n];
+    const size_t slice_elems = (size_t)V * 144;
+    const double dt = (double)(j.tl[n] - j.t0);
+    if (ps.prec == BBC_F64) {
+        const double2 *dl = (const double2 *)ps.dl + si * slice_elems, *ds = (const double2 *)ps.ds + si * slice_elems;
+        return enqueue_slice<double>(ctx, j.dp, ps.L, V, sl.ws, qorder, dl, ds, n_ch, d_energy, dt,
+                                     (double2 *)j.out + (size_t)n * n_ch * V * 16, nullptr, sl.st, false);
+    }
+    const float2 *dl = (const float2 *)ps.dl + si * slice_elems, *ds = (const float2 *)ps.ds + si * slice_elems;
+    return enqueue_slice<float>(ctx, j.dp, ps.L, V, sl.ws, qorder, dl, ds, n_ch, d_energy, dt,
+                                (float2 *)j.out + (size_t)n * n_ch * V * 16, j.scale + (size_t)n * n_ch, sl.st,
+                                false);
+}
+
+void release_prop_if_unused(Server &S, PropSet *ps) {
+    if (ps->released && ps->refs == 0) {
+        (void)hipFree(ps->dl);
+        (void)hipFree(ps->ds);
+        S.committed -= ps->bytes;
+        for (auto it = S.props.begin(); it != S.props.end(); ++it)
+            if (it->second.get() == ps) { S.props.erase(it); break; }
+    }
+}
+
+void finish_job(Server &S, Job &j, int state) {
+    j.state = state;
+    j.t_done = Clock::now();
+    j.ps->refs--;
+    release_prop_if_unused(S, j.ps);
+    S.done_cv.notify_all();
+}
+
+// Continuous batching: every slot advances its job one time slice at a time
+// (at most two slices in flight per slot); as soon as a slot is free, the
+// next queued job is admitted if its workspace fits the context budget.
+// Slots run on separate streams, so the slices of different jobs overlap on
+// the device.  Results do not depend on the mix: each slice uses its own
+// slot workspace and the same kernels and reduction order as when alone.
+void server_loop(bbc_context *ctx) {
+    Server &S = ctx->srv;
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(S.mu);
+    for (;;) {
+        bool progressed = false;
+        for (auto &sl : S.slots) {
+            Job *j = sl.job;
+            if (!j) continue;
+            while (!sl.evs.empty() && hipEventQuery(sl.evs.front()) == hipSuccess) {
+                S.evpool.push_back(sl.evs.front());
+                sl.evs.pop_front();
+                j->inflight--;
+                progressed = true;
+            }
+            while (!j->cancel && j->state == JOB_RUNNING && j->inflight < 2 && j->next < (int)j->slice.size()) {
+                bbc_status st = server_enqueue(ctx, sl, *j);
+                if (st != BBC_OK) {
+                    j->status = st;
+                    j->err = g_err;
+                    j->state = JOB_FAILED;
+                    break;
+                }
+                hipEvent_t ev = nullptr;
+                if (!S.evpool.empty()) { ev = S.evpool.back(); S.evpool.pop_back(); }
+                else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+                if (!ev || hipEventRecord(ev, sl.st) != hipSuccess) {
+                    j->status = BBC_EDEVICE;
+                    j->err = "event record failed";
+                    j->state = JOB_FAILED;
+                    if (ev) S.evpool.push_back(ev);
+                    break;
+                }
+                sl.evs.push_back(ev);
+                j->next++;
+                j->inflight++;
+                progressed = true;
+            }
+            if (j->inflight == 0 && (j->next == (int)j->slice.size() || j->cancel || j->state == JOB_FAILED)) {
+                int final_state = j->state == JOB_FAILED ? JOB_FAILED
+                                  : (j->cancel && j->next < (int)j->slice.size()) ? JOB_CANCELLED : JOB_DONE;
+                finish_job(S, *j, final_state);
+                sl.job = nullptr;
+                progressed = true;
+            }
+        }
+        for (auto &sl : S.slots) {
+            if (sl.job || S.queue.empty()) continue;
+            Job *j = S.queue.front();
+            if (j->foot > sl.ws_bytes) {
+                const size_t after = S.committed - sl.ws_bytes + j->foot;
+                if (ctx->budget && after > ctx->budget) {
+                    bool any_busy = false;
+                    for (auto &o : S.slots) any_busy = any_busy || o.job;
+                    if (!any_busy && sl.ws_bytes == 0) {
+                        // can never fit: refuse
+                        S.queue.pop_front();
+                        j->status = BBC_ENOMEM;
+                        j->err = "job workspace exceeds the HBM budget";
+                        finish_job(S, *j, JOB_FAILED);
+                        progressed = true;
+                    }
+                    break;   // wait for memory to free up (keeps arrival order)
+                }
+                if (sl.ws) { (void)hipFree(sl.ws); S.committed -= sl.ws_bytes; sl.ws = nullptr; sl.ws_bytes = 0; }
+                if (hipMalloc(&sl.ws, j->foot) != hipSuccess) {
+                    sl.ws = nullptr;
+                    S.queue.pop_front();
+                    j->status = BBC_ENOMEM;
+                    j->err = "hipMalloc of a job workspace failed";
+                    finish_job(S, *j, JOB_FAILED);
+                    progressed = true;
+                    continue;
+                }
+                sl.ws_bytes = j->foot;
+                S.committed += j->foot;
+            }
+            S.queue.pop_front();
+            j->state = JOB_RUNNING;
+            j->t_start = Clock::now();
+            if (!j->energy.empty()) {
+                const PropSet &ps = *j->ps;
+                const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
+                const size_t wsz = workspace_bytes(V, j->dp->plan.ncomp, (int)j->chans.size(), j->dp->nslot,
+                                                   ps.prec == BBC_F64 ? 16 : 8);
+                (void)hipMemcpyAsync((char *)sl.ws + ((wsz + 255) & ~(size_t)255), j->energy.data(),
+                                     8 * j->energy.size(), hipMemcpyHostToDevice, sl.st);
+            }
+            sl.job = j;
+            progressed = true;
+        }
+        bool idle = S.queue.empty();
+        for (auto &sl : S.slots) idle = idle && !sl.job;
+        if (S.stop && idle) break;
+        if (!progressed) S.cv.wait_for(lk, std::chrono::microseconds(50));
+    }
 }
 
 }  // namespace
@@ -448,7 +694,10 @@ bbc_status bbc_create(int device, uint64_t budget, bbc_context **out) {
 
 void bbc_destroy(bbc_context *ctx) {
     if (!ctx) return;
+    (void)bbc_server_stop(ctx);
     (void)hipSetDevice(ctx->device);
+    for (auto &kv : ctx->srv.props) { (void)hipFree(kv.second->dl); (void)hipFree(kv.second->ds); }
+    ctx->srv.props.clear();
     (void)hipDeviceSynchronize();
     ctx->plans.clear();
     delete ctx;
@@ -514,6 +763,208 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
                                      nullptr, st);
     return run_correlate<float>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, C_scale,
                                 st);
+}
+
+
+bbc_status bbc_server_start(bbc_context *ctx, int n_slots) {
+    if (!ctx || n_slots < 1 || n_slots > 16) return fail(BBC_EINVAL, "n_slots must be 1..16");
+    Server &S = ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.running) return fail(BBC_ESTATE, "server already running");
+    HIP_TRY(hipSetDevice(ctx->device));
+    S.slots.assign(n_slots, Slot());
+    for (auto &sl : S.slots) HIP_TRY(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+    S.stop = false;
+    S.running = true;
+    S.th = std::thread(server_loop, ctx);
+    return BBC_OK;
+}
+
+bbc_status bbc_server_stop(bbc_context *ctx) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    Server &S = ctx->srv;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (!S.running) return BBC_OK;
+        for (Job *j : S.queue) finish_job(S, *j, JOB_CANCELLED);
+        S.queue.clear();
+        S.stop = true;
+        S.cv.notify_all();
+    }
+    S.th.join();
+    std::lock_guard<std::mutex> lk(S.mu);
+    for (auto &sl : S.slots) {
+        (void)hipStreamSynchronize(sl.st);
+        for (auto e : sl.evs) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(sl.st);
+        if (sl.ws) { (void)hipFree(sl.ws); S.committed -= sl.ws_bytes; }
+    }
+    S.slots.clear();
+    for (auto e : S.evpool) (void)hipEventDestroy(e);
+    S.evpool.clear();
+    S.running = false;
+    return BBC_OK;
+}
+
+bbc_status bbc_prop_upload(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, const void *S_light,
+                           const void *S_strange, int n_t, uint64_t *handle) {
+    if (!ctx || !handle || !S_light || !S_strange || n_t < 1) return fail(BBC_EINVAL, "bad prop_upload arguments");
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    long V;
+    bbc_status s = check_lattice(lattice, &V);
+    if (s) return s;
+    Server &S = ctx->srv;
+    std::unique_ptr<PropSet> ps(new PropSet);
+    for (int i = 0; i < 3; ++i) ps->L[i] = lattice[i];
+    ps->prec = prec;
+    ps->n_t = n_t;
+    const size_t one = (size_t)n_t * V * 144 * (prec == BBC_F64 ? 16 : 8);
+    ps->bytes = 2 * one;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (ctx->budget && S.committed + ps->bytes > ctx->budget)
+            return fail(BBC_ENOMEM, "propagator set exceeds the HBM budget");
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (hipMalloc(&ps->dl, one) != hipSuccess || hipMalloc(&ps->ds, one) != hipSuccess) {
+        (void)hipFree(ps->dl);
+        (void)hipFree(ps->ds);
+        return fail(BBC_ENOMEM, "hipMalloc of a propagator set failed");
+    }
+    HIP_TRY(hipMemcpy(ps->dl, S_light, one, hipMemcpyDefault));
+    HIP_TRY(hipMemcpy(ps->ds, S_strange, one, hipMemcpyDefault));
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.committed += ps->bytes;
+    *handle = S.next_id++;
+    S.props.emplace(*handle, std::move(ps));
+    return BBC_OK;
+}
+
+bbc_status bbc_prop_release(bbc_context *ctx, uint64_t handle) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    Server &S = ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.props.find(handle);
+    if (it == S.props.end() || it->second->released) return fail(BBC_EINVAL, "unknown propagator handle");
+    it->second->released = true;
+    release_prop_if_unused(S, it->second.get());
+    return BBC_OK;
+}
+
+bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *slice_idx, const int32_t *t_list,
+                      int t0, int n_ch, const int32_t *ch_list, bbc_spin spin, const double *energy, void *C_out,
+                      double *C_scale, uint64_t *job) {
+    if (!ctx || !job || n_t < 1 || !slice_idx || !t_list || n_ch < 1 || !ch_list || !C_out)
+        return fail(BBC_EINVAL, "bad submit arguments");
+    if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
+    for (int i = 0; i < n_ch; ++i)
+        if (ch_list[i] < 0 || ch_list[i] >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    Server &S = ctx->srv;
+    std::unique_ptr<Job> j(new Job);
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (!S.running) return fail(BBC_ESTATE, "server not started");
+        auto it = S.props.find(prop);
+        if (it == S.props.end() || it->second->released) return fail(BBC_EINVAL, "unknown propagator handle");
+        j->ps = it->second.get();
+    }
+    if (j->ps->prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
+    for (int i = 0; i < n_t; ++i)
+        if (slice_idx[i] < 0 || slice_idx[i] >= j->ps->n_t) return fail(BBC_EINVAL, "slice index out of range");
+    j->slice.assign(slice_idx, slice_idx + n_t);
+    j->tl.assign(t_list, t_list + n_t);
+    j->t0 = t0;
+    j->chans.assign(ch_list, ch_list + n_ch);
+    j->spin = spin;
+    if (energy) j->energy.assign(energy, energy + n_ch);
+    j->out = C_out;
+    j->scale = j->ps->prec == BBC_F32 ? C_scale : nullptr;
+    bbc_status s = get_plan(ctx, j->chans, spin == BBC_SPIN_LOWER ? 2 : 0, &j->dp);
+    if (s) return s;
+    j->foot = job_footprint(*j);
+    if (ctx->budget && j->foot > ctx->budget) return fail(BBC_ENOMEM, "job workspace exceeds the HBM budget");
+    std::lock_guard<std::mutex> lk(S.mu);
+    j->id = S.next_id++;
+    j->t_submit = Clock::now();
+    j->ps->refs++;
+    *job = j->id;
+    S.queue.push_back(j.get());
+    S.jobs.emplace(j->id, std::move(j));
+    S.cv.notify_all();
+    return BBC_OK;
+}
+
+bbc_status bbc_poll(bbc_context *ctx, uint64_t job, int *state) {
+    if (!ctx || !state) return fail(BBC_EINVAL, "bad poll arguments");
+    Server &S = ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(job);
+    if (it == S.jobs.end()) return fail(BBC_EINVAL, "unknown job");
+    *state = it->second->state;
+    return BBC_OK;
+}
+
+bbc_status bbc_wait(bbc_context *ctx, uint64_t job, int timeout_ms) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    Server &S = ctx->srv;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(job);
+    if (it == S.jobs.end()) return fail(BBC_EINVAL, "unknown job");
+    Job *j = it->second.get();
+    auto pred = [j] { return j->state >= JOB_DONE; };
+    if (timeout_ms < 0) S.done_cv.wait(lk, pred);
+    else if (!S.done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred))
+        return fail(BBC_ETIMEOUT, "job not finished within the timeout");
+    if (j->state == JOB_CANCELLED) return fail(BBC_ECANCELLED, "job cancelled");
+    if (j->state == JOB_FAILED) return fail(j->status, j->err);
+    return BBC_OK;
+}
+
+bbc_status bbc_cancel(bbc_context *ctx, uint64_t job) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    Server &S = ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(job);
+    if (it == S.jobs.end()) return fail(BBC_EINVAL, "unknown job");
+    Job *j = it->second.get();
+    if (j->state == JOB_QUEUED) {
+        for (auto q = S.queue.begin(); q != S.queue.end(); ++q)
+            if (*q == j) { S.queue.erase(q); break; }
+        finish_job(S, *j, JOB_CANCELLED);
+    } else if (j->state == JOB_RUNNING) {
+        j->cancel = true;
+        S.cv.notify_all();
+    }
+    return BBC_OK;
+}
+
+bbc_status bbc_job_times(bbc_context *ctx, uint64_t job, double *queue_ms, double *run_ms, double *total_ms) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    Server &S = ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(job);
+    if (it == S.jobs.end()) return fail(BBC_EINVAL, "unknown job");
+    const Job &j = *it->second;
+    if (j.state < JOB_DONE) return fail(BBC_ESTATE, "job not finished");
+    auto ms = [](Clock::time_point a, Clock::time_point b) {
+        return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const bool started = j.t_start.time_since_epoch().count() != 0;
+    if (queue_ms) *queue_ms = ms(j.t_submit, started ? j.t_start : j.t_done);
+    if (run_ms) *run_ms = started ? ms(j.t_start, j.t_done) : 0.0;
+    if (total_ms) *total_ms = ms(j.t_submit, j.t_done);
+    return BBC_OK;
+}
+
+bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    Server &S = ctx->srv;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(job);
+    if (it == S.jobs.end()) return fail(BBC_EINVAL, "unknown job");
+    if (it->second->state < JOB_DONE) return fail(BBC_ESTATE, "job not finished");
+    S.jobs.erase(it);
+    return BBC_OK;
 }
 
 bbc_status bbc_profile_enable(bbc_context *ctx, int enable) {
