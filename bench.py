@@ -99,13 +99,122 @@ def cpu_baseline(Sl, Ss, t_idx, budget_s=20.0):
                       % (t_idx, len(done), [list(p) for p in r_points[:1 + (len(done) - 1) // 13]], el)}
 
 
+def serve_mix(bbc, torch, np, n_jobs=64, n_slots=4, load=0.8):
+    """Continuous-batching serving on a Poisson stream of mixed jobs (FP32 form).
+
+    Jobs: lattice uniform over {16^3x32, 24^3x48, 32^3x64}, channel subset of
+    size U[4,52] drawn without replacement, n_t U[4,16] distinct slices, one of
+    4 resident propagator sets per lattice (seeded PCG64, seed 1510009034).
+    The service rate is measured by running all jobs one after another on a
+    single slot (which also gives every job's result alone); the stream then
+    arrives at load x that rate on n_slots slots.  Reports p50/p99 latency
+    (submit to completion) and throughput, and checks that every job's result
+    in the mix is bit-identical to its result alone.
+    """
+    dev = torch.device("cuda:0")
+    lattices = [(16, 32), (24, 48), (32, 64)]
+    rng = np.random.Generator(np.random.PCG64(1510009034))
+    ctx = bbc.Context(0)
+    ctx.server_start(1)
+    # propagator sets: seeded Gaussian entries x exp(-m t), generated on the device (FP32)
+    props = {}
+    for li, (L, T) in enumerate(lattices):
+        decay_l = torch.exp(-0.5 * torch.arange(T, dtype=torch.float32, device=dev)).view(T, 1, 1, 1, 1, 1)
+        decay_s = torch.exp(-0.7 * torch.arange(T, dtype=torch.float32, device=dev)).view(T, 1, 1, 1, 1, 1)
+        for k in range(4):
+            g = torch.Generator(device=dev)
+            g.manual_seed(1510009034 + 16 * li + k)
+            shape = (T, L, L, L, 12, 12)
+            Sl = torch.randn(shape, dtype=torch.complex64, device=dev, generator=g) * decay_l
+            Ss = torch.randn(shape, dtype=torch.complex64, device=dev, generator=g) * decay_s
+            props[(li, k)] = ctx.prop_upload(Sl, Ss)
+            del Sl, Ss
+    torch.cuda.empty_cache()
+    jobs = []
+    for _ in range(n_jobs):
+        li = int(rng.integers(0, 3))
+        L, T = lattices[li]
+        n_ch = int(rng.integers(4, 53))
+        ch = sorted(rng.choice(52, size=n_ch, replace=False).tolist())
+        n_t = int(rng.integers(4, 17))
+        sl = sorted(rng.choice(T, size=n_t, replace=False).tolist())
+        jobs.append({"li": li, "L": L, "prop": props[(li, int(rng.integers(0, 4)))], "ch": ch, "sl": sl,
+                     "sites": L ** 3 * n_t * n_ch})
+
+    def run_job(j):
+        L = j["L"]
+        out = torch.empty((len(j["sl"]), len(j["ch"]), L, L, L, 16), dtype=torch.complex64, device=dev)
+        scale = torch.empty((len(j["sl"]), len(j["ch"])), dtype=torch.float64, device=dev)
+        jid = ctx.submit(j["prop"], j["sl"], j["sl"], j["ch"], out, scale)
+        return jid, out, scale
+
+    def fingerprint(out, scale):
+        return (int(out.view(torch.int32).to(torch.int64).sum().item()),
+                int(scale.view(torch.int64).sum().item()))
+
+    # single stream: service rate and results alone
+    alone, service = [], []
+    run_job(jobs[0])   # warm-up: plans and workspaces
+    torch.cuda.synchronize()
+    ctx.server_stop()
+    ctx.server_start(1)
+    t0 = time.perf_counter()
+    for j in jobs:
+        jid, out, scale = run_job(j)
+        ctx.wait(jid)
+        service.append(ctx.job_times(jid)[1])
+        alone.append(fingerprint(out, scale))
+        ctx.job_forget(jid)
+        del out, scale
+    single_s = time.perf_counter() - t0
+    mu = n_jobs / single_s
+    lam = load * mu
+    gaps = rng.exponential(1.0 / lam, size=n_jobs)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    ctx.server_stop()
+    ctx.server_start(n_slots)
+    print("serve: single stream %.2f s (%.1f jobs/s); mix at %.1f jobs/s on %d slots"
+          % (single_s, mu, lam, n_slots), file=sys.stderr, flush=True)
+    inflight = []
+    start = time.perf_counter()
+    for j, at in zip(jobs, arrivals):
+        now = time.perf_counter() - start
+        if at > now:
+            time.sleep(at - now)
+        inflight.append(run_job(j))
+    lat, same = [], 0
+    for (jid, out, scale), a in zip(inflight, alone):
+        ctx.wait(jid)
+        lat.append(ctx.job_times(jid)[2])
+        same += fingerprint(out, scale) == a
+    makespan = time.perf_counter() - start
+    ctx.server_stop()
+    ctx.close()
+    sites = sum(j["sites"] for j in jobs)
+    lat = np.array(lat)
+    return {
+        "metric": "serving: job latency p50/p99 and throughput (site-channels/s)",
+        "value": round(sites / makespan, 1), "unit": "site-channels/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic (seeded on the device)",
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                       "mean": round(float(lat.mean()), 2), "max": round(float(lat.max()), 2)},
+        "single_stream": {"jobs_per_s": round(mu, 3), "site_channels_per_s": round(sites / single_s, 1),
+                          "mean_service_ms": round(float(np.mean(service)), 2)},
+        "arrival_rate_jobs_per_s": round(lam, 3), "load": load, "slots": n_slots, "jobs": n_jobs,
+        "makespan_s": round(makespan, 3), "results_identical_alone_vs_mix": "%d/%d" % (same, n_jobs),
+        "config": {"workload": "64-job Poisson mix: lattices 16^3x32/24^3x48/32^3x64, 4-52 channels, "
+                               "4-16 slices, 4 resident propagator sets per lattice, FP32 form"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="16c32-f64", choices=["16c32-f64", "32c64-f64", "32c64-f32"],
+    ap.add_argument("--workload", default="16c32-f64",
+                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -122,6 +231,10 @@ def main():
 
     import paper_1510_00903_amd as bbc
     import synth
+
+    if args.workload == "serve-mix":
+        print(json.dumps(serve_mix(bbc, torch, np)), flush=True)
+        return
 
     fp32 = args.workload.endswith("f32")
     L, T = (16, 32) if args.workload.startswith("16") else (32, 64)
