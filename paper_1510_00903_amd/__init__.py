@@ -252,9 +252,12 @@ class Context:
 
     def correlate(self, S_light, S_strange, t_list, channels, t0=0, spin=UPPER, energy=None, out=None,
                   scale=None, stream=None):
-        """C_ch(r, t) for the slices in S_light/S_strange (torch tensors on the context's GPU).
+        """C_ch(r, t) for the slices in S_light/S_strange.
 
-        S_*:   [n_t, Lz, Ly, Lx, 12, 12], complex128 (FP64 form) or complex64 (FP32 form).
+        S_*:   [n_t, Lz, Ly, Lx, 12, 12], complex128 (FP64 form) or complex64 (FP32 form), on the
+               context's GPU or in host memory (pinned recommended: slices are then streamed
+               through device staging buffers, overlapping the transfers with the kernels).
+        out:   device or host tensor (default: device if the inputs are, else pinned host memory).
         Returns ``out`` [n_t, n_ch, Lz, Ly, Lx, 16] (same dtype); in the FP32 form also
         ``scale`` [n_t, n_ch] float64, the FP64 factor of each (t, channel) field.
         Stream-ordered on ``stream`` (default: torch's current stream).
@@ -271,8 +274,8 @@ class Context:
             prec = F32
         else:
             raise BBCError("propagators must be complex128 or complex64")
-        if not (S_light.is_cuda and S_strange.is_cuda):
-            raise BBCError("propagators must be device tensors")
+        if S_light.is_cuda != S_strange.is_cuda:
+            raise BBCError("S_light and S_strange must both be on the device or both on the host")
         S_light = S_light.contiguous()
         S_strange = S_strange.contiguous()
         n_t, Lz, Ly, Lx = S_light.shape[:4]
@@ -281,10 +284,14 @@ class Context:
             raise BBCError("t_list must have one entry per slice")
         ch_arr, n_ch = _i32(channels)
         lat, _ = _i32([Lx, Ly, Lz])
+        dev = S_light.device if S_light.is_cuda else torch.device("cuda", self.device)
         if out is None:
-            out = torch.empty((n_t, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, device=S_light.device)
+            if S_light.is_cuda:
+                out = torch.empty((n_t, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, device=dev)
+            else:
+                out = torch.empty((n_t, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, pin_memory=True)
         if prec == F32 and scale is None:
-            scale = torch.empty((n_t, n_ch), dtype=torch.float64, device=S_light.device)
+            scale = torch.empty((n_t, n_ch), dtype=torch.float64, device=dev)
         e_arr = None
         if energy is not None:
             e_vals = [float(e) for e in energy]
@@ -292,7 +299,7 @@ class Context:
                 raise BBCError("energy must have one entry per channel")
             e_arr = (ctypes.c_double * n_ch)(*e_vals)
         if stream is None:
-            stream = torch.cuda.current_stream(S_light.device)
+            stream = torch.cuda.current_stream(dev)
         _check(self._lib.bbc_correlate(
             self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()), ctypes.c_void_p(S_strange.data_ptr()),
             n_t, t_arr, int(t0), n_ch, ch_arr, int(spin), e_arr, ctypes.c_void_p(out.data_ptr()),

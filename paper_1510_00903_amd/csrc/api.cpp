@@ -226,6 +226,8 @@ struct bbc_context {
     int energy_cap = 0;
     std::map<std::vector<int>, int32_t *> qorders;   // per lattice: momentum order
     std::mutex qmu;                                   // guards qorders and plans for the server thread
+    hipStream_t cin = nullptr, cout = nullptr;        // copy streams of the host-streamed direct path
+    hipEvent_t sev[8] = {};
     // profiling: event pairs recorded around kernel stages
     bool prof = false;
     struct Rec { int stage; hipEvent_t a, b; };
@@ -241,6 +243,9 @@ struct bbc_context {
         if (ws) (void)hipFree(ws);
         if (d_energy) (void)hipFree(d_energy);
         for (auto &kv : qorders) (void)hipFree(kv.second);
+        if (cin) (void)hipStreamDestroy(cin);
+        if (cout) (void)hipStreamDestroy(cout);
+        for (auto e : sev) if (e) (void)hipEventDestroy(e);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
     }
@@ -317,10 +322,26 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
     return BBC_OK;
 }
 
+// Workspace of one slice:
+//   region A: the intermediates I in site space (2 spins x nc x V); once they
+//             are transposed it is dead, and the contracted fields Ct (n_ch x 16
+//             x V) and the partial slots (nslot x 16 x V) reuse it;
+//   region B: the momentum-major copy Iq (2 x nc x V);
+//   then the rescale maxima of the FP32 form.
+struct WsLayout {
+    size_t a, b, total;   // byte offsets of region B, of the small tail, and total size
+};
+WsLayout ws_layout(long V, int nc, int n_ch, int nslot, size_t csize) {
+    WsLayout L;
+    const size_t ra = std::max<size_t>((size_t)2 * nc, (size_t)(n_ch + nslot) * 16) * V * csize;
+    const size_t rb = (size_t)2 * nc * V * csize;
+    L.a = (ra + 255) & ~(size_t)255;
+    L.b = L.a + ((rb + 255) & ~(size_t)255);
+    L.total = L.b + 256;
+    return L;
+}
 size_t workspace_bytes(long V, int nc, int n_ch, int nslot, size_t csize) {
-    // I and Iq: 2 spins x nc components x V; Ct: n_ch x 16 x V; partial slots: nslot x 16 x V;
-    // then the rescale maxima (FP32 form)
-    return (size_t)2 * 2 * nc * V * csize + (size_t)(n_ch + nslot) * 16 * V * csize + 256 * 4;
+    return ws_layout(V, nc, n_ch, nslot, csize).total;
 }
 
 bbc_status check_lattice(const int32_t *lattice, long *V) {
@@ -366,11 +387,12 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     using T2 = typename bbc::cplx_t<T>::type;
     const bbc::Plan &P = dp->plan;
     const int nc = P.ncomp;
+    const WsLayout lay = ws_layout(V, nc, n_ch, dp->nslot, sizeof(T2));
     T2 *I = (T2 *)ws;
-    T2 *Iq = I + (size_t)2 * nc * V;
-    T2 *Ct = Iq + (size_t)2 * nc * V;
+    T2 *Iq = (T2 *)((char *)ws + lay.a);
+    T2 *Ct = I;                                   // reuses region A after the transpose
     T2 *slots = Ct + (size_t)n_ch * 16 * V;
-    uint32_t *kmax = (uint32_t *)(slots + (size_t)dp->nslot * 16 * V);
+    uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
     bbc::ContractTables tb{qorder, dp->ntask, dp->d_segs, dp->d_items, dp->d_diags, dp->d_refs,
                            dp->d_ch_slot_begin, dp->nslot};
     const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
@@ -408,16 +430,36 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     return BBC_OK;
 }
 
+// True unless the pointer is memory kernels may dereference directly: HIP device
+// allocations (or managed memory).  Pinned host memory, and pageable memory --
+// reported either as an error or as hipMemoryTypeUnregistered -- count as host
+// memory and are only ever touched by copies.
+bool is_host_pointer(const void *p) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) { (void)hipGetLastError(); return true; }
+    return !(attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
+}
+
+// Direct path.  Propagators and output may be device or host memory; host
+// buffers (pinned memory recommended) are streamed per slice through two
+// device staging buffers each, on separate copy streams, so that the transfer
+// of slice n+1 in, and of slice n-1 out, overlap the kernels of slice n.
 template <typename T>
 bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const void *S_light,
                          const void *S_strange, int n_t, const int32_t *t_list, int t0, int n_ch,
-                         const double *energy, void *C_out, double *C_scale, hipStream_t st) {
+                         const double *energy, void *C_out, double *C_scale, hipStream_t st, bool host_in,
+                         bool host_out) {
     using T2 = typename bbc::cplx_t<T>::type;
-    const size_t need = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->nslot, sizeof(T2));
+    const size_t cs = sizeof(T2);
+    const size_t core = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->nslot, cs);
+    const size_t in_slice = (size_t)V * 144 * cs, out_slice = (size_t)n_ch * V * 16 * cs;
+    const size_t in_stage = host_in ? 2 * 2 * in_slice : 0, out_stage = host_out ? 2 * out_slice : 0;
+    const size_t need = core + in_stage + out_stage;
     if (ctx->budget && need + dp->table_bytes > ctx->budget)
         return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
     if (ctx->ws_bytes < need) {
-        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipDeviceSynchronize());
         if (ctx->ws) { HIP_TRY(hipFree(ctx->ws)); ctx->ws = nullptr; ctx->ws_bytes = 0; }
         hipError_t e = hipMalloc(&ctx->ws, need);
         if (e != hipSuccess) { ctx->ws = nullptr; return fail(BBC_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e)); }
@@ -435,15 +477,64 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     bbc_status s;
     const int32_t *qorder = get_qorder(ctx, L, &s);
     if (!qorder) return s;
+    char *stage_in = (char *)ctx->ws + core, *stage_out = stage_in + in_stage;
+    if ((host_in || host_out) && !ctx->cin) {
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->cin, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->cout, hipStreamNonBlocking));
+        for (auto &e : ctx->sev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    // events: [0,1] input staged, [2,3] input consumed, [4,5] output ready, [6,7] output drained
+    hipEvent_t *ev = ctx->sev;
+    auto stage_input = [&](int n) -> bbc_status {
+        const int b = n & 1;
+        char *dl = stage_in + (size_t)b * 2 * in_slice, *ds = dl + in_slice;
+        if (n >= 2) HIP_TRY(hipStreamWaitEvent(ctx->cin, ev[2 + b], 0));
+        HIP_TRY(hipMemcpyAsync(dl, (const char *)S_light + (size_t)n * in_slice, in_slice, hipMemcpyHostToDevice,
+                               ctx->cin));
+        HIP_TRY(hipMemcpyAsync(ds, (const char *)S_strange + (size_t)n * in_slice, in_slice, hipMemcpyHostToDevice,
+                               ctx->cin));
+        HIP_TRY(hipEventRecord(ev[b], ctx->cin));
+        return BBC_OK;
+    };
+    if (host_in && n_t > 0) {
+        HIP_TRY(hipEventRecord(ev[7], st));           // stage after earlier work on st
+        HIP_TRY(hipStreamWaitEvent(ctx->cin, ev[7], 0));
+        if ((s = stage_input(0))) return s;
+    }
     const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
-    T2 *out = (T2 *)C_out;
     for (int n = 0; n < n_t; ++n) {
-        s = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, qorder, Sl + (size_t)n * V * 144, Ss + (size_t)n * V * 144,
-                             n_ch, energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0),
-                             out + (size_t)n * n_ch * V * 16, C_scale ? C_scale + (size_t)n * n_ch : nullptr, st,
+        const int b = n & 1;
+        const T2 *sl = Sl + (size_t)n * V * 144, *ss = Ss + (size_t)n * V * 144;
+        if (host_in) {
+            if (n + 1 < n_t && (s = stage_input(n + 1))) return s;
+            HIP_TRY(hipStreamWaitEvent(st, ev[b], 0));
+            sl = (const T2 *)(stage_in + (size_t)b * 2 * in_slice);
+            ss = (const T2 *)(stage_in + (size_t)b * 2 * in_slice + in_slice);
+        }
+        void *out = (char *)C_out + (size_t)n * out_slice;
+        if (host_out) {
+            if (n >= 2) HIP_TRY(hipStreamWaitEvent(st, ev[6 + b], 0));
+            out = stage_out + (size_t)b * out_slice;
+        }
+        s = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, qorder, sl, ss, n_ch, energy ? ctx->d_energy : nullptr,
+                             (double)(t_list[n] - t0), out, C_scale ? C_scale + (size_t)n * n_ch : nullptr, st,
                              true);
         if (s) return s;
+        if (host_in) HIP_TRY(hipEventRecord(ev[2 + b], st));    // staged input of slice n no longer needed
+        if (host_out) {
+            HIP_TRY(hipEventRecord(ev[4 + b], st));
+            HIP_TRY(hipStreamWaitEvent(ctx->cout, ev[4 + b], 0));
+            HIP_TRY(hipMemcpyAsync((char *)C_out + (size_t)n * out_slice, out, out_slice, hipMemcpyDeviceToHost,
+                                   ctx->cout));
+            HIP_TRY(hipEventRecord(ev[6 + b], ctx->cout));
+        }
     }
+    // the caller's stream completes only when the last outputs have left the device
+    if (host_out && n_t > 0) {
+        HIP_TRY(hipStreamWaitEvent(st, ev[6 + ((n_t - 1) & 1)], 0));
+        if (n_t > 1) HIP_TRY(hipStreamWaitEvent(st, ev[6 + ((n_t - 2) & 1)], 0));
+    }
+    if (host_in && n_t > 0) HIP_TRY(hipStreamWaitEvent(st, ev[(n_t - 1) & 1], 0));
     return BBC_OK;
 }
 
@@ -743,13 +834,10 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
         if (ch_list[i] < 0 || ch_list[i] >= bbc::kNumChannelsAll)
             return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
     if (n_t == 0) return BBC_OK;
-    for (const void *p : {S_light, S_strange, (const void *)C_out}) {
-        hipPointerAttribute_t attr;
-        if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-            (void)hipGetLastError();
-            return fail(BBC_EINVAL, "S_light, S_strange and C_out must be device pointers");
-        }
-    }
+    const bool host_in = is_host_pointer(S_light), host_out = is_host_pointer(C_out);
+    if (is_host_pointer(S_strange) != host_in)
+        return fail(BBC_EINVAL, "S_light and S_strange must both be host or both be device memory");
+    if (C_scale && is_host_pointer(C_scale)) return fail(BBC_EINVAL, "C_scale must be device memory");
     std::lock_guard<std::mutex> lock(ctx->mu);
     HIP_TRY(hipSetDevice(ctx->device));
     std::vector<int> chans(ch_list, ch_list + n_ch);
@@ -760,9 +848,9 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     hipStream_t st = (hipStream_t)stream;
     if (prec == BBC_F64)
         return run_correlate<double>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out,
-                                     nullptr, st);
+                                     nullptr, st, host_in, host_out);
     return run_correlate<float>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, C_scale,
-                                st);
+                                st, host_in, host_out);
 }
 
 
@@ -831,8 +919,10 @@ bbc_status bbc_prop_upload(bbc_context *ctx, const int32_t lattice[3], bbc_preci
         (void)hipFree(ps->ds);
         return fail(BBC_ENOMEM, "hipMalloc of a propagator set failed");
     }
-    HIP_TRY(hipMemcpy(ps->dl, S_light, one, hipMemcpyDefault));
-    HIP_TRY(hipMemcpy(ps->ds, S_strange, one, hipMemcpyDefault));
+    const hipMemcpyKind kl = is_host_pointer(S_light) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind ks = is_host_pointer(S_strange) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpy(ps->dl, S_light, one, kl));
+    HIP_TRY(hipMemcpy(ps->ds, S_strange, one, ks));
     std::lock_guard<std::mutex> lk(S.mu);
     S.committed += ps->bytes;
     *handle = S.next_id++;
@@ -869,6 +959,8 @@ bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *s
         j->ps = it->second.get();
     }
     if (j->ps->prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
+    if (is_host_pointer(C_out) || (C_scale && j->ps->prec == BBC_F32 && is_host_pointer(C_scale)))
+        return fail(BBC_EINVAL, "C_out and C_scale of a served job must be device memory");
     for (int i = 0; i < n_t; ++i)
         if (slice_idx[i] < 0 || slice_idx[i] >= j->ps->n_t) return fail(BBC_EINVAL, "slice index out of range");
     j->slice.assign(slice_idx, slice_idx + n_t);
