@@ -268,6 +268,8 @@ def main():
                     choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
+    ap.add_argument("--slices", type=int, default=0,
+                    help="time only the first N slices of the job (for profiling runs; 0 = all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 1 GiB (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -306,6 +308,11 @@ def main():
     out = torch.empty((T, n_ch, L, L, L, 16), dtype=torch.complex64 if fp32 else torch.complex128, device=dev)
     scale = torch.empty((T, n_ch), dtype=torch.float64, device=dev) if fp32 else None
     ctx = bbc.Context(0)
+    if args.slices:
+        T = min(T, args.slices)
+        Sl, Ss = Sl[:T], Ss[:T]
+        d_l, d_s, out = d_l[:T], d_s[:T], out[:T]
+        scale = scale[:T] if scale is not None else None
     t_list = list(range(T))
 
     if args.copy_calibration:
