@@ -45,7 +45,6 @@ struct DevPlan {
     int pat_begin[5];
     uint32_t *d_terms = nullptr;
     int32_t *d_term_begin = nullptr;
-    uint32_t *d_items = nullptr;
     bbc::DDiag *d_diags = nullptr;
     bbc::DRef *d_refs = nullptr;
     int4 *d_segs = nullptr;
@@ -54,39 +53,39 @@ struct DevPlan {
     int2 *d_content = nullptr;      // per requested channel: (n_light, n_strange)
     size_t table_bytes = 0;
     ~DevPlan() {
-        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_items); (void)hipFree(d_diags);
+        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_diags);
         (void)hipFree(d_refs); (void)hipFree(d_segs); (void)hipFree(d_ch_slot_begin); (void)hipFree(d_content);
     }
 };
 
-// Contraction tables of a plan.  Per requested channel: its diagrams (sorted by
-// the sites carrying a' and b', so that neighbouring items take the same code
-// path) and the flat list of (diagram, k3, k4) items, cut into segments of at
-// most kSegItems items.  Every segment owns one partial-result slot; the slots
-// of a channel are contiguous.  Segments, largest first, are dealt four to a
-// task (one per wave of a workgroup).
+// Contraction tables of a plan.  Per requested channel: its diagrams, cut into
+// segments of whole diagrams holding about kSegItems (diagram, k3, k4) items
+// each.  Every segment owns one partial-result slot; the slots of a channel are
+// contiguous.  Segments, largest first, are dealt four to a task (one per wave
+// of a workgroup).  A diagram records its carry pattern, K = kdim3 * kdim4 and
+// kdim4 with a 16-bit reciprocal, from which a lane rebuilds (k3, k4) = divmod(kk, kdim4).
 constexpr int kSegItems = 512;
 
-void contraction_tables(const bbc::Plan &P, std::vector<uint32_t> &items, std::vector<bbc::DDiag> &diags,
-                        std::vector<bbc::DRef> &refs, std::vector<int4> &segs, std::vector<int32_t> &ch_slot_begin,
-                        int *ntask) {
+void contraction_tables(const bbc::Plan &P, std::vector<bbc::DDiag> &diags, std::vector<bbc::DRef> &refs,
+                        std::vector<int4> &segs, std::vector<int32_t> &ch_slot_begin, int *ntask) {
     const int n = (int)P.channels.size();
     ch_slot_begin.assign(n + 1, 0);
-    std::vector<int4> all;   // (begin, end, slot, 0)
+    std::vector<int4> all;   // (first diagram, end diagram, slot, items)
     int slot = 0;
     for (int m = 0; m < n; ++m) {
-        std::vector<int> order;
-        for (int d = P.ch_begin[m]; d < P.ch_begin[m + 1]; ++d) order.push_back(d);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            const auto &A = P.diags[a], &B = P.diags[b];
-            return A.carry[0] + 2 * A.carry[1] < B.carry[0] + 2 * B.carry[1];
-        });
-        const int ib = (int)items.size();
-        for (int d : order) {
+        const int db = (int)diags.size();
+        long total = 0;
+        for (int d = P.ch_begin[m]; d < P.ch_begin[m + 1]; ++d) {
             const bbc::Diagram &D = P.diags[d];
             bbc::DDiag dd{};
             dd.coef = D.coef;
-            dd.pad[0] = D.carry[0] + 2 * D.carry[1];
+            const int kd4 = D.kdim[1];
+            const int inv = (65536 + kd4 - 1) / kd4;
+            for (int kk = 0; kk < D.K; ++kk)
+                if (((kk * inv) >> 16) != kk / kd4) throw std::logic_error("open-index reciprocal");
+            if (D.K > 255 || kd4 > 15) throw std::logic_error("open-index range");
+            dd.pad[0] = (D.carry[0] + 2 * D.carry[1]) | (D.K << 2) | (kd4 << 10);
+            dd.pad[1] = inv;
             for (int s = 0; s < 2; ++s) {
                 int b = (int)refs.size();
                 for (const bbc::BlockRef &br : D.blk[s]) {
@@ -107,42 +106,72 @@ void contraction_tables(const bbc::Plan &P, std::vector<uint32_t> &items, std::v
                 if (s == 0) { dd.ref0 = b; dd.ref0_end = (int)refs.size(); }
                 else { dd.ref1 = b; dd.ref1_end = (int)refs.size(); }
             }
-            const int di = (int)diags.size();
             diags.push_back(dd);
-            for (int k3 = 0; k3 < D.kdim[0]; ++k3)
-                for (int k4 = 0; k4 < D.kdim[1]; ++k4)
-                    items.push_back(((uint32_t)di << 8) | ((uint32_t)k3 << 4) | (uint32_t)k4);
+            total += D.K;
         }
-        const int ie = (int)items.size();
-        const int nseg = std::max(1, (ie - ib + kSegItems - 1) / kSegItems);
+        const int de = (int)diags.size();
+        const int nseg = (int)std::max<long>(1, (total + kSegItems - 1) / kSegItems);
         ch_slot_begin[m] = slot;
-        for (int g = 0; g < nseg; ++g) {
-            int b = ib + (int)((long)(ie - ib) * g / nseg), e = ib + (int)((long)(ie - ib) * (g + 1) / nseg);
-            all.push_back(make_int4(b, e, slot++, 0));
+        long acc = 0;
+        int sb = db;
+        for (int d = db; d < de; ++d) {
+            acc += P.diags[P.ch_begin[m] + (d - db)].K;
+            // close a segment when the running count reaches the next 1/nseg mark
+            const long mark = total * (long)(slot - ch_slot_begin[m] + 1) / nseg;
+            if (acc >= mark || d + 1 == de) {
+                long items = 0;
+                for (int e = sb; e <= d; ++e) items += P.diags[P.ch_begin[m] + (e - db)].K;
+                all.push_back(make_int4(sb, d + 1, slot++, (int)items));
+                sb = d + 1;
+            }
         }
     }
     ch_slot_begin[n] = slot;
-    std::stable_sort(all.begin(), all.end(), [](const int4 &a, const int4 &b) { return a.y - a.x > b.y - b.x; });
+    std::stable_sort(all.begin(), all.end(), [](const int4 &a, const int4 &b) { return a.w > b.w; });
     *ntask = (int)((all.size() + 3) / 4);
     segs.assign((size_t)*ntask * 4, make_int4(0, 0, 0, 0));
-    for (size_t i = 0; i < all.size(); ++i) segs[i] = all[i];
+    for (size_t i = 0; i < all.size(); ++i) segs[i] = make_int4(all[i].x, all[i].y, all[i].z, 0);
 }
 
-// Momenta ordered so that every q is followed by -q (L-periodic), letting the
-// contraction tasks of a pair run back to back on one XCD.
-std::vector<int32_t> pair_order(const int L[3]) {
+// Number of self-conjugate momenta (q = -q mod L): 0 and L/2 along each even axis.
+long self_conjugate(const int L[3]) {
+    long s = 1;
+    for (int d = 0; d < 3; ++d) s *= (L[d] % 2 == 0) ? 2 : 1;
+    return s;
+}
+
+// Positions of the momentum-grouped copy: V momenta, one padding slot when the
+// number of self-conjugate momenta is odd, rounded up to whole groups of G.
+long grouped_positions(long V, const int L[3], int G) {
+    const long n = V + (self_conjugate(L) & 1);
+    return (n + G - 1) / G * G;
+}
+
+// Momentum groups of G positions, each closed under q -> -q: the self-conjugate
+// momenta first, one padding slot if their number is odd, then the pairs
+// (q, -q) in increasing q (a pair starts at an even position, so never straddles
+// two groups), the last group padded.  Entry p: (momentum at position p, or -1
+// for padding; the lane within the group that holds -q).
+std::vector<int2> momentum_groups(const int L[3], int G) {
     const int V = L[0] * L[1] * L[2];
-    std::vector<int32_t> out;
-    std::vector<char> seen(V, 0);
+    auto neg = [&](int q) {
+        const int qx = q % L[0], qy = (q / L[0]) % L[1], qz = q / (L[0] * L[1]);
+        return ((L[0] - qx) % L[0]) + L[0] * (((L[1] - qy) % L[1]) + L[1] * ((L[2] - qz) % L[2]));
+    };
+    std::vector<int2> pos;
+    auto lane = [&]() { return (int)(pos.size() % G); };
+    for (int q = 0; q < V; ++q)
+        if (neg(q) == q) pos.push_back(make_int2(q, lane()));
+    if (pos.size() & 1) pos.push_back(make_int2(-1, lane()));
     for (int q = 0; q < V; ++q) {
-        if (seen[q]) continue;
-        int qx = q % L[0], qy = (q / L[0]) % L[1], qz = q / (L[0] * L[1]);
-        int qm = ((L[0] - qx) % L[0]) + L[0] * (((L[1] - qy) % L[1]) + L[1] * ((L[2] - qz) % L[2]));
-        out.push_back(q);
-        seen[q] = 1;
-        if (!seen[qm]) { out.push_back(qm); seen[qm] = 1; }
+        const int m = neg(q);
+        if (m <= q) continue;
+        const int l = lane();
+        pos.push_back(make_int2(q, l + 1));
+        pos.push_back(make_int2(m, l));
     }
-    return out;
+    while (pos.size() % G) pos.push_back(make_int2(-1, lane()));
+    return pos;
 }
 
 template <typename E>
@@ -224,8 +253,8 @@ struct bbc_context {
     size_t ws_bytes = 0;
     double *d_energy = nullptr;
     int energy_cap = 0;
-    std::map<std::vector<int>, int32_t *> qorders;   // per lattice: momentum order
-    std::mutex qmu;                                   // guards qorders and plans for the server thread
+    std::map<std::vector<int>, int2 *> groups;       // per (lattice, G): momentum groups
+    std::mutex qmu;                                   // guards groups and plans for the server thread
     hipStream_t cin = nullptr, cout = nullptr;        // copy streams of the host-streamed direct path
     hipEvent_t sev[8] = {};
     // profiling: event pairs recorded around kernel stages
@@ -242,7 +271,7 @@ struct bbc_context {
     ~bbc_context() {
         if (ws) (void)hipFree(ws);
         if (d_energy) (void)hipFree(d_energy);
-        for (auto &kv : qorders) (void)hipFree(kv.second);
+        for (auto &kv : groups) (void)hipFree(kv.second);
         if (cin) (void)hipStreamDestroy(cin);
         if (cout) (void)hipStreamDestroy(cout);
         for (auto e : sev) if (e) (void)hipEventDestroy(e);
@@ -287,18 +316,20 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
     for (int c = P.ncomp - 1; c >= 0; --c) dp->pat_begin[P.comp_pat[c]] = c;
     for (int p = 3; p >= 0; --p)
         if (dp->pat_begin[p] > dp->pat_begin[p + 1]) dp->pat_begin[p] = dp->pat_begin[p + 1];
-    std::vector<uint32_t> items;
     std::vector<bbc::DDiag> diags;
     std::vector<bbc::DRef> refs;
     std::vector<int4> segs;
     std::vector<int32_t> ch_slot_begin;
-    contraction_tables(P, items, diags, refs, segs, ch_slot_begin, &dp->ntask);
+    try {
+        contraction_tables(P, diags, refs, segs, ch_slot_begin, &dp->ntask);
+    } catch (const std::exception &e) {
+        return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
+    }
     dp->nslot = ch_slot_begin.back();
     if (diags.size() >= (1u << 24)) return fail(BBC_EUNSUPPORTED, "too many diagrams in one request");
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(upload_vec(&dp->d_terms, P.terms));
     HIP_TRY(upload_vec(&dp->d_term_begin, P.term_begin));
-    HIP_TRY(upload_vec(&dp->d_items, items));
     HIP_TRY(upload_vec(&dp->d_diags, diags));
     HIP_TRY(upload_vec(&dp->d_refs, refs));
     HIP_TRY(upload_vec(&dp->d_segs, segs));
@@ -314,7 +345,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         }
         HIP_TRY(upload_vec(&dp->d_content, content));
     }
-    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + items.size() * 4 +
+    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 +
                       diags.size() * sizeof(bbc::DDiag) + refs.size() * sizeof(bbc::DRef) +
                       segs.size() * sizeof(int4) + ch_slot_begin.size() * 4;
     *out = dp.get();
@@ -326,7 +357,8 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
 //   region A: the intermediates I in site space (2 spins x nc x V); once they
 //             are transposed it is dead, and the contracted fields Ct (n_ch x 16
 //             x V) and the partial slots (nslot x 16 x V) reuse it;
-//   region B: the momentum-major copy Iq (2 x nc x V);
+//   region B: the momentum-grouped copy Iq (groups x 2 x nc x G, at most V + 8
+//             positions);
 //   then the rescale maxima of the FP32 form.
 struct WsLayout {
     size_t a, b, total;   // byte offsets of region B, of the small tail, and total size
@@ -334,7 +366,7 @@ struct WsLayout {
 WsLayout ws_layout(long V, int nc, int n_ch, int nslot, size_t csize) {
     WsLayout L;
     const size_t ra = std::max<size_t>((size_t)2 * nc, (size_t)(n_ch + nslot) * 16) * V * csize;
-    const size_t rb = (size_t)2 * nc * V * csize;
+    const size_t rb = (size_t)2 * nc * (V + 8) * csize;
     L.a = (ra + 255) & ~(size_t)255;
     L.b = L.a + ((rb + 255) & ~(size_t)255);
     L.total = L.b + 256;
@@ -359,29 +391,37 @@ bbc_status check_lattice(const int32_t *lattice, long *V) {
     return BBC_OK;
 }
 
-const int32_t *get_qorder(bbc_context *ctx, const int L[3], bbc_status *st) {
+// Device table of the momentum groups for precision T.
+struct MomGroups {
+    const int2 *pos = nullptr;
+    int ngroup = 0;
+};
+template <typename T>
+MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
+    constexpr int G = sizeof(T) == 8 ? 4 : 8;   // momenta per group (a component's 2 G values: 128 bytes)
     std::lock_guard<std::mutex> lock(ctx->qmu);
-    auto key = std::vector<int>{L[0], L[1], L[2]};
-    auto it = ctx->qorders.find(key);
-    if (it == ctx->qorders.end()) {
-        std::vector<int32_t> qo = pair_order(L);
-        int32_t *d = nullptr;
-        hipError_t e = upload_vec(&d, qo);
+    auto key = std::vector<int>{L[0], L[1], L[2], G};
+    auto it = ctx->groups.find(key);
+    const long V = (long)L[0] * L[1] * L[2];
+    if (it == ctx->groups.end()) {
+        std::vector<int2> g = momentum_groups(L, G);
+        int2 *d = nullptr;
+        hipError_t e = upload_vec(&d, g);
         if (e != hipSuccess) {
-            *st = fail(BBC_EDEVICE, std::string("momentum order upload: ") + hipGetErrorString(e));
-            return nullptr;
+            *st = fail(BBC_EDEVICE, std::string("momentum group upload: ") + hipGetErrorString(e));
+            return MomGroups{};
         }
-        it = ctx->qorders.emplace(key, d).first;
+        it = ctx->groups.emplace(key, d).first;
     }
     *st = BBC_OK;
-    return it->second;
+    return MomGroups{it->second, (int)(grouped_positions(V, L, G) / G)};
 }
 
 // Launches the kernel sequence of one time slice on stream st, using the
 // workspace ws (layout of workspace_bytes).  Stage events are recorded only
 // for the direct (profiled) path.
 template <typename T>
-bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, void *ws, const int32_t *qorder,
+bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, void *ws, const MomGroups &mg,
                          const void *slp, const void *ssp, int n_ch, const double *d_energy, double dt, void *outp,
                          double *scale, hipStream_t st, bool timed) {
     using T2 = typename bbc::cplx_t<T>::type;
@@ -393,7 +433,7 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     T2 *Ct = I;                                   // reuses region A after the transpose
     T2 *slots = Ct + (size_t)n_ch * 16 * V;
     uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
-    bbc::ContractTables tb{qorder, dp->ntask, dp->d_segs, dp->d_items, dp->d_diags, dp->d_refs,
+    bbc::ContractTables tb{mg.pos, mg.ngroup, dp->ntask, dp->d_segs, dp->d_diags, dp->d_refs,
                            dp->d_ch_slot_begin, dp->nslot};
     const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
     T2 *out = (T2 *)outp;
@@ -411,11 +451,11 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     }
     {
         StageTimer tm(pc, st, 2);
-        bbc::launch_transpose<T>(I, Iq, 2L * nc, V, st);
+        bbc::launch_transpose_grouped<T>(I, Iq, nc, V, mg.ngroup, mg.pos, st);
     }
     {
         StageTimer tm(pc, st, 3);
-        bbc::launch_contract<T>(Iq, slots, Ct, nc, L, n_ch, tb, st);
+        bbc::launch_contract<T>(Iq, slots, Ct, nc, V, n_ch, tb, st);
     }
     {
         StageTimer tm(pc, st, 4);
@@ -475,8 +515,8 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         HIP_TRY(hipMemcpyAsync(ctx->d_energy, energy, sizeof(double) * n_ch, hipMemcpyHostToDevice, st));
     }
     bbc_status s;
-    const int32_t *qorder = get_qorder(ctx, L, &s);
-    if (!qorder) return s;
+    const MomGroups mg = get_groups<T>(ctx, L, &s);
+    if (!mg.pos) return s;
     char *stage_in = (char *)ctx->ws + core, *stage_out = stage_in + in_stage;
     if ((host_in || host_out) && !ctx->cin) {
         HIP_TRY(hipStreamCreateWithFlags(&ctx->cin, hipStreamNonBlocking));
@@ -516,7 +556,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
             if (n >= 2) HIP_TRY(hipStreamWaitEvent(st, ev[6 + b], 0));
             out = stage_out + (size_t)b * out_slice;
         }
-        s = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, qorder, sl, ss, n_ch, energy ? ctx->d_energy : nullptr,
+        s = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, mg, sl, ss, n_ch, energy ? ctx->d_energy : nullptr,
                              (double)(t_list[n] - t0), out, C_scale ? C_scale + (size_t)n * n_ch : nullptr, st,
                              true);
         if (s) return s;
@@ -554,8 +594,6 @@ bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
     const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
     const int n_ch = (int)j.chans.size();
     bbc_status s;
-    const int32_t *qorder = get_qorder(ctx, ps.L, &s);
-    if (!qorder) return s;
     const size_t wsz = workspace_bytes(V, j.dp->plan.ncomp, n_ch, j.dp->nslot, ps.prec == BBC_F64 ? 16 : 8);
     const double *d_energy = j.energy.empty() ? nullptr : (const double *)((char *)sl.ws + ((wsz + 255) & ~(size_t)255));
     const int n = j.next;
@@ -563,12 +601,16 @@ bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
     const size_t slice_elems = (size_t)V * 144;
     const double dt = (double)(j.tl[n] - j.t0);
     if (ps.prec == BBC_F64) {
+        const MomGroups mg = get_groups<double>(ctx, ps.L, &s);
+        if (!mg.pos) return s;
         const double2 *dl = (const double2 *)ps.dl + si * slice_elems, *ds = (const double2 *)ps.ds + si * slice_elems;
-        return enqueue_slice<double>(ctx, j.dp, ps.L, V, sl.ws, qorder, dl, ds, n_ch, d_energy, dt,
+        return enqueue_slice<double>(ctx, j.dp, ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
                                      (double2 *)j.out + (size_t)n * n_ch * V * 16, nullptr, sl.st, false);
     }
+    const MomGroups mg = get_groups<float>(ctx, ps.L, &s);
+    if (!mg.pos) return s;
     const float2 *dl = (const float2 *)ps.dl + si * slice_elems, *ds = (const float2 *)ps.ds + si * slice_elems;
-    return enqueue_slice<float>(ctx, j.dp, ps.L, V, sl.ws, qorder, dl, ds, n_ch, d_energy, dt,
+    return enqueue_slice<float>(ctx, j.dp, ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
                                 (float2 *)j.out + (size_t)n * n_ch * V * 16, j.scale + (size_t)n * n_ch, sl.st,
                                 false);
 }
@@ -803,13 +845,12 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
     std::vector<int> chans(ch_list, ch_list + n_ch);
     try {
         bbc::Plan P = bbc::build_plan(chans, 0);
-        std::vector<uint32_t> items;
         std::vector<bbc::DDiag> diags;
         std::vector<bbc::DRef> refs;
         std::vector<int4> segs;
         std::vector<int32_t> csb;
         int ntask = 0;
-        contraction_tables(P, items, diags, refs, segs, csb, &ntask);
+        contraction_tables(P, diags, refs, segs, csb, &ntask);
         *bytes = workspace_bytes(V, P.ncomp, n_ch, csb.back(), prec == BBC_F64 ? 16 : 8);
     } catch (const std::exception &e) {
         return fail(BBC_EINVAL, e.what());

@@ -5,8 +5,8 @@
 // Per time slice the host driver launches, on one stream:
 //   k_blocks     step 1a: every block intermediate at every site        (site-local)
 //   k_fft (x3)   step 1b: forward 3-D FFT of every component            (one pass per axis)
-//   k_transpose  component-major [comp][q] -> momentum-major [q][comp]
-//   k_contract   step 2a: open-index sums per momentum, all channels    (one workgroup per q)
+//   k_transpose_grouped  component-major [g][comp][q] -> momentum groups (GroupLayout)
+//   k_contract   step 2a: open-index sums per momentum, all channels    (workgroups per group)
 //   k_fft (x3)   step 2b: inverse 3-D FFT of the 16 spin components per channel
 //   k_finalize   normalisation and transpose to the output layout [r][spin]
 #include "kernels.hpp"
@@ -312,29 +312,89 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
 // ----------------------------------------------------------------------------
 // Transpose [R][C] -> [C][R] through a padded LDS tile.
 // ----------------------------------------------------------------------------
+// ----------------------------------------------------------------------------
+// Momentum groups.  The contraction pairs every momentum q with -q.  Momenta are
+// packed into groups of G (4 in FP64, 8 in FP32) that are closed under
+// q -> -q, and the momentum-space intermediates are stored group by group:
+// per group and component c, the two sink spins g and the G momenta,
+//   FP64: [group][c][g][G]      FP32: [group][c][G][g],
+// so that one component of a group fills one 128-byte line (2 x G complex
+// numbers), both sites of a pair (q and -q) read inside the same group, and in
+// FP32 one 16-byte load fetches both sink spins of a momentum.
+// gpos[p] = (momentum held by position p, or -1 for a padding slot; lane of -q
+// within the group).
+// ----------------------------------------------------------------------------
+// Element offset of (component c, sink spin g, lane j) within a group:
+// c * 2G + j * S + g * SG.
+template <typename T2> struct GroupLayout;
+template <> struct GroupLayout<double2> {
+    static constexpr int G = 4;
+    static constexpr int S = 1;      // stride of the momentum lane
+    static constexpr int SG = 4;     // stride of the sink spin
+};
+template <> struct GroupLayout<float2> {
+    static constexpr int G = 8;
+    static constexpr int S = 2;
+    static constexpr int SG = 1;
+};
+
+// Loads both sink spins of one component for one momentum lane.
+__device__ __forceinline__ void load_spins(const double2 *__restrict__ p, unsigned i, double2 &v0, double2 &v1) {
+    v0 = p[i];
+    v1 = p[i + GroupLayout<double2>::SG];
+}
+__device__ __forceinline__ void load_spins(const float2 *__restrict__ p, unsigned i, float2 &v0, float2 &v1) {
+    const float4 v = *reinterpret_cast<const float4 *>(p + i);
+    v0 = float2{v.x, v.y};
+    v1 = float2{v.z, v.w};
+}
+
+// Tile: 64 positions x TC components x both sink spins through LDS; read along
+// the (grouped) momenta, written as one contiguous run per group.
 template <typename T>
-__global__ __launch_bounds__(256) void k_transpose(const typename cplx_t<T>::type *__restrict__ in,
-                                                   typename cplx_t<T>::type *__restrict__ out, long R, long C) {
+__global__ __launch_bounds__(256) void k_transpose_grouped(const typename cplx_t<T>::type *__restrict__ in,
+                                                           typename cplx_t<T>::type *__restrict__ out, int nc,
+                                                           long V, long npos, const int2 *__restrict__ gpos) {
     using T2 = typename cplx_t<T>::type;
-    __shared__ T2 tile[32][33];
-    const long bc = (long)blockIdx.x * 32, br = (long)blockIdx.y * 32;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    for (int j = ty; j < 32; j += 8) {
-        long r = br + j, c = bc + tx;
-        if (r < R && c < C) tile[j][tx] = in[r * C + c];
+    using Ly = GroupLayout<T2>;
+    constexpr int G = Ly::G;
+    constexpr int TC = 16384 / (64 * sizeof(T2));   // 16 components (FP64) or 32 (FP32): 32 KB tile
+    __shared__ T2 tile[2 * TC][65];
+    const long p0 = (long)blockIdx.x * 64;
+    const int c0 = blockIdx.y * TC;
+    const int t = threadIdx.x;
+    {
+        const int pl = t & 63;
+        const long p = p0 + pl;
+        const int q = p < npos ? gpos[p].x : -1;
+        for (int r = t >> 6; r < 2 * TC; r += 4) {
+            const int g = r / TC, c = c0 + (r - g * TC);
+            T2 v = T2{0, 0};
+            if (q >= 0 && c < nc) v = in[((long)g * nc + c) * V + q];
+            tile[r][pl] = v;
+        }
     }
     __syncthreads();
-    for (int j = ty; j < 32; j += 8) {
-        long c = bc + j, r = br + tx;
-        if (c < C && r < R) out[c * R + r] = tile[tx][j];
+    const int ncl = min(TC, nc - c0);               // components in this tile
+    for (int e = t; e < 64 * 2 * TC; e += 256) {
+        const int gi = e / (2 * TC * G), rem = e - gi * (2 * TC * G);
+        const int cl = rem / (2 * G), w = rem - cl * (2 * G);
+        const int j = (w % (G * Ly::S)) / Ly::S, g = (w / Ly::SG) % 2;
+        const long p = p0 + gi * G + j;
+        if (p < npos && cl < ncl)
+            out[((p / G) * nc + c0) * 2 * G + rem] = tile[g * TC + cl][gi * G + j];
     }
 }
 
 template <typename T>
-void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long R, long C,
-                      hipStream_t st) {
-    dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
-    hipLaunchKernelGGL((k_transpose<T>), grid, dim3(32, 8), 0, st, in, out, R, C);
+void launch_transpose_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, long V,
+                              int ngroup, const int2 *gpos, hipStream_t st) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int G = GroupLayout<T2>::G;
+    constexpr int TC = 16384 / (64 * sizeof(T2));
+    const long npos = (long)ngroup * G;
+    dim3 grid((unsigned)((npos + 63) / 64), (unsigned)((nc + TC - 1) / TC));
+    hipLaunchKernelGGL((k_transpose_grouped<T>), grid, dim3(256), 0, st, in, out, nc, V, npos, gpos);
 }
 
 // ----------------------------------------------------------------------------
@@ -344,143 +404,150 @@ void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::ty
 // outer source spins a', b' carried by one of the two blocks each (the site
 // holding that source baryon's delta quark).
 //
-// Work decomposition: the items (diagram, k3, k4) of each channel are cut into
-// segments; four segments form a task (one per wave).  Workgroup = (momentum q,
-// task).  Workgroup ids are mapped so that all tasks of q and of -q run
-// back to back on the same XCD: the q-pair's intermediate slices (the only
-// data the tasks read) then stay in that XCD's L2.  Each wave reduces its
-// segment and writes one partial result slot; k_combine adds the slots of a
-// channel in a fixed order (no atomics: results are bit-reproducible).
-// Iq layout: [q][g][nc]; slot layout: [slot][16][V].
+// Work decomposition: the diagrams of each channel are cut into segments of
+// whole diagrams; four segments form a task (one per wave).  Workgroup =
+// (momentum group, task).  A wave walks its diagrams one at a time, so the
+// diagram and block tables are wave-uniform (scalar loads); its 64 lanes are
+// 64/G open-index lanes x G momentum lanes, each open-index lane taking one
+// (k3, k4) of the diagram per step.  The G momentum lanes of an open index read
+// one 64-byte sector per load.  Workgroup ids are mapped so that all tasks of
+// a group run back to back on the same XCD: the group's intermediates (the
+// only data the tasks read, about 1 MB) then stay in that XCD's L2.  Each wave
+// reduces its segment and writes one partial result slot per momentum;
+// k_combine adds the slots of a channel in a fixed order (no atomics: results
+// are bit-reproducible).
+// Iq layout: [group][g][nc][G]; slot layout: [slot][16][V].
 // ----------------------------------------------------------------------------
-// acc += v; in the FP32 form with a running compensation (TwoSum, Knuth), so
-// that the open-index and diagram sums keep FP32 rounding at every addition.
-template <typename T> struct Acc {
-    __device__ static void add(T &a, T &c, T v) { a += v; }
-};
-template <> struct Acc<float> {
-    __device__ static void add(float &a, float &c, float v) {
-        const float s = a + v;
-        const float bv = s - a;
-        c += (a - (s - bv)) + (v - bv);
-        a = s;
-    }
-};
-
+// One diagram for this lane's momentum: sum over the (k3, k4) taken by this
+// open-index lane of E1(q) (x) E2(-q), each block value E a weighted sum of
+// intermediate components.  `base` points at the group's data; la / lb are the
+// offsets of the lanes of q and -q.  Table data (D, refs) is wave-uniform.
+// Products are formed in T and summed in FP64 (in the FP32 form this keeps the
+// open-index and diagram sums free of FP32 rounding).
 template <typename T, int C3, int C4>
-__device__ __forceinline__ void contract_item(const typename cplx_t<T>::type *__restrict__ Ia,
-                                              const typename cplx_t<T>::type *__restrict__ Ib, int nc,
-                                              const DDiag &D, const DRef *__restrict__ refs, int k3, int k4,
-                                              typename cplx_t<T>::type (&acc)[16],
-                                              typename cplx_t<T>::type (&cmp)[16]) {
+__device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__restrict__ base, unsigned la,
+                                            unsigned lb, const DDiag &D, const DRef *__restrict__ refs, int il,
+                                            double2 (&acc)[16]) {
     using T2 = typename cplx_t<T>::type;
+    constexpr int G = GroupLayout<T2>::G;
+    constexpr int NI = 64 / G;
     constexpr int N1 = 1 << ((C3 == 0) + (C4 == 0));   // outer-spin combinations held by site 0
     constexpr int N2 = 4 / N1;
-    T2 e1[2 * N1], e2[2 * N2];
+    const int K = (D.pad[0] >> 2) & 255, kd4 = (D.pad[0] >> 10) & 15, inv = D.pad[1];
+    const double dc = D.coef;
+    for (int c = 0; c < K; c += NI) {
+        const int kk = c + il;
+        if (kk >= K) break;
+        const int k3 = (kk * inv) >> 16, k4 = kk - k3 * kd4;
+        T2 e1[2 * N1], e2[2 * N2];
 #pragma unroll
-    for (int i = 0; i < 2 * N1; ++i) e1[i] = T2{0, 0};
+        for (int i = 0; i < 2 * N1; ++i) e1[i] = T2{0, 0};
 #pragma unroll
-    for (int i = 0; i < 2 * N2; ++i) e2[i] = T2{0, 0};
-    for (int r = D.ref0; r < D.ref0_end; ++r) {
-        const DRef R = refs[r];
-        const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
-        const T c = T(R.coef);
+        for (int i = 0; i < 2 * N2; ++i) e2[i] = T2{0, 0};
+        for (int r = D.ref0; r < D.ref0_end; ++r) {
+            const DRef R = refs[r];
+            const unsigned vl = la + (unsigned)(2 * G * (k3 * R.sk3 + k4 * R.sk4));
+            const T c0 = T(R.coef);
 #pragma unroll
-        for (int o = 0; o < N1; ++o) {
-            const int a3 = (C3 == 0) ? (o & 1) : 0;
-            const int a4 = (C4 == 0) ? ((C3 == 0) ? (o >> 1) : o) : 0;
-            const int off = b + a3 * R.so3 + a4 * R.so4;
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                const T2 v = Ia[g * nc + off];
-                e1[g + 2 * o].x += c * v.x;
-                e1[g + 2 * o].y += c * v.y;
+            for (int o = 0; o < N1; ++o) {
+                const int a3 = (C3 == 0) ? (o & 1) : 0;
+                const int a4 = (C4 == 0) ? ((C3 == 0) ? (o >> 1) : o) : 0;
+                const T2 *p = base + (size_t)2 * G * (R.base + a3 * R.so3 + a4 * R.so4);
+                T2 v0, v1;
+                load_spins(p, vl, v0, v1);
+                e1[2 * o].x += c0 * v0.x;
+                e1[2 * o].y += c0 * v0.y;
+                e1[2 * o + 1].x += c0 * v1.x;
+                e1[2 * o + 1].y += c0 * v1.y;
             }
         }
-    }
-    for (int r = D.ref1; r < D.ref1_end; ++r) {
-        const DRef R = refs[r];
-        const int b = R.base + k3 * R.sk3 + k4 * R.sk4;
-        const T c = T(R.coef);
+        for (int r = D.ref1; r < D.ref1_end; ++r) {
+            const DRef R = refs[r];
+            const unsigned vl = lb + (unsigned)(2 * G * (k3 * R.sk3 + k4 * R.sk4));
+            const T c0 = T(R.coef);
 #pragma unroll
-        for (int o = 0; o < N2; ++o) {
-            const int a3 = (C3 == 1) ? (o & 1) : 0;
-            const int a4 = (C4 == 1) ? ((C3 == 1) ? (o >> 1) : o) : 0;
-            const int off = b + a3 * R.so3 + a4 * R.so4;
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                const T2 v = Ib[g * nc + off];
-                e2[g + 2 * o].x += c * v.x;
-                e2[g + 2 * o].y += c * v.y;
+            for (int o = 0; o < N2; ++o) {
+                const int a3 = (C3 == 1) ? (o & 1) : 0;
+                const int a4 = (C4 == 1) ? ((C3 == 1) ? (o >> 1) : o) : 0;
+                const T2 *p = base + (size_t)2 * G * (R.base + a3 * R.so3 + a4 * R.so4);
+                T2 v0, v1;
+                load_spins(p, vl, v0, v1);
+                e2[2 * o].x += c0 * v0.x;
+                e2[2 * o].y += c0 * v0.y;
+                e2[2 * o + 1].x += c0 * v1.x;
+                e2[2 * o + 1].y += c0 * v1.y;
             }
         }
-    }
-    const T dc = T(D.coef);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int a = s & 1, bb = (s >> 1) & 1, a3 = (s >> 2) & 1, a4 = s >> 3;
-        const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
-        const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
-        const T2 p = cmul(e1[a + 2 * o1], e2[bb + 2 * o2]);
-        Acc<T>::add(acc[s].x, cmp[s].x, dc * p.x);
-        Acc<T>::add(acc[s].y, cmp[s].y, dc * p.y);
+        for (int s = 0; s < 16; ++s) {
+            const int a = s & 1, bb = (s >> 1) & 1, a3 = (s >> 2) & 1, a4 = s >> 3;
+            const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
+            const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
+            const T2 p = cmul(e1[a + 2 * o1], e2[bb + 2 * o2]);
+            acc[s].x = fma(dc, (double)p.x, acc[s].x);
+            acc[s].y = fma(dc, (double)p.y, acc[s].y);
+        }
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type *__restrict__ Iq,
-                                                  typename cplx_t<T>::type *__restrict__ slots, int nc, int Lx,
-                                                  int Ly, int Lz, const int32_t *__restrict__ qorder, int ntask,
-                                                  const int4 *__restrict__ segs, const uint32_t *__restrict__ items,
-                                                  const DDiag *__restrict__ diags, const DRef *__restrict__ refs) {
+                                                  typename cplx_t<T>::type *__restrict__ slots, int nc, long V,
+                                                  int ngroup, const int2 *__restrict__ gpos, int ntask,
+                                                  const int4 *__restrict__ segs, const DDiag *__restrict__ diags,
+                                                  const DRef *__restrict__ refs) {
     using T2 = typename cplx_t<T>::type;
-    const int V = Lx * Ly * Lz;
+    using Ly = GroupLayout<T2>;
+    constexpr int G = Ly::G;             // momentum lanes per open index
+    constexpr int NI = 64 / G;           // open-index lanes per wave
     // XCD-aware placement: consecutive workgroup ids cycle over the 8 XCDs;
-    // XCD x owns the contiguous range of q positions [x*P8, (x+1)*P8).
+    // XCD x owns the contiguous range of groups [x*P8, (x+1)*P8).
     const int xcd = blockIdx.x & 7;
     const int j = blockIdx.x >> 3;
-    const int P8 = (V + 7) >> 3;
-    const int pos = xcd * P8 + j / ntask;
+    const int P8 = (ngroup + 7) >> 3;
+    const int grp = xcd * P8 + j / ntask;
     const int task = j - (j / ntask) * ntask;
-    if (pos >= V) return;
-    const int q = qorder[pos];
-    const int qx = q % Lx, qy = (q / Lx) % Ly, qz = q / (Lx * Ly);
-    const int qm = ((Lx - qx) % Lx) + Lx * (((Ly - qy) % Ly) + Ly * ((Lz - qz) % Lz));
-    const T2 *Ia = Iq + (size_t)q * 2 * nc;
-    const T2 *Ib = Iq + (size_t)qm * 2 * nc;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (grp >= ngroup) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gl = lane & (G - 1), il = lane / G;
+    const int2 pq = gpos[(size_t)grp * G + gl];
+    const T2 *base = Iq + (size_t)grp * nc * 2 * G;
     const int4 sg = segs[task * 4 + wave];
-    if (sg.x >= sg.y) return;
-    T2 acc[16], cmp[16];
+    const int d0 = __builtin_amdgcn_readfirstlane(sg.x), d1 = __builtin_amdgcn_readfirstlane(sg.y);
+    if (d0 >= d1) return;
+    const unsigned la = gl * Ly::S, lb = pq.y * Ly::S;
+    double2 acc[16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) { acc[s] = T2{0, 0}; cmp[s] = T2{0, 0}; }
-    for (int it = sg.x + lane; it < sg.y; it += 64) {
-        const uint32_t code = items[it];
-        const int d = code >> 8, k3 = (code >> 4) & 15, k4 = code & 15;
+    for (int s = 0; s < 16; ++s) acc[s] = double2{0, 0};
+    for (int d = d0; d < d1; ++d) {
         const DDiag D = diags[d];
-        switch (D.pad[0]) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
-        case 0: contract_item<T, 0, 0>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
-        case 1: contract_item<T, 1, 0>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
-        case 2: contract_item<T, 0, 1>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
-        default: contract_item<T, 1, 1>(Ia, Ib, nc, D, refs, k3, k4, acc, cmp); break;
+        switch (D.pad[0] & 3) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
+        case 0: diagram_sum<T, 0, 0>(base, la, lb, D, refs, il, acc); break;
+        case 1: diagram_sum<T, 1, 0>(base, la, lb, D, refs, il, acc); break;
+        case 2: diagram_sum<T, 0, 1>(base, la, lb, D, refs, il, acc); break;
+        default: diagram_sum<T, 1, 1>(base, la, lb, D, refs, il, acc); break;
         }
     }
+    // sum over the open-index lanes of each momentum lane
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        acc[s].x += cmp[s].x;
-        acc[s].y += cmp[s].y;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
+        for (int off = 32; off >= G; off >>= 1) {
             acc[s].x += __shfl_xor(acc[s].x, off, 64);
             acc[s].y += __shfl_xor(acc[s].y, off, 64);
         }
     }
-    if (lane < 16) {
-        T2 v = acc[0];
+    if (pq.x < 0) return;             // padding slot
+    const int slot = __builtin_amdgcn_readfirstlane(sg.z);
+#pragma unroll
+    for (int s0 = 0; s0 < 16; s0 += NI) {
+        const int want = s0 + il;
+        double2 v = acc[0];
 #pragma unroll
         for (int s = 1; s < 16; ++s)
-            if (lane == s) v = acc[s];
-        slots[((size_t)sg.z * 16 + lane) * V + q] = v;
+            if (want == s) v = acc[s];
+        slots[((size_t)slot * 16 + want) * V + pq.x] = T2{T(v.x), T(v.y)};
     }
 }
 
@@ -506,14 +573,13 @@ __global__ __launch_bounds__(256) void k_combine(const typename cplx_t<T>::type 
 
 template <typename T>
 void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots,
-                     typename cplx_t<T>::type *Ct, int nc, const int L[3], int n_ch, const ContractTables &tb,
+                     typename cplx_t<T>::type *Ct, int nc, long V, int n_ch, const ContractTables &tb,
                      hipStream_t st) {
-    const int V = L[0] * L[1] * L[2];
-    const long nwg = 8L * ((V + 7) / 8) * tb.ntask;
-    hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, L[0], L[1], L[2],
-                       tb.qorder, tb.ntask, tb.segs, tb.items, tb.diags, tb.refs);
+    const long nwg = 8L * ((tb.ngroup + 7) / 8) * tb.ntask;
+    hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, V, tb.ngroup,
+                       tb.gpos, tb.ntask, tb.segs, tb.diags, tb.refs);
     const long n = (long)n_ch * 16 * V;
-    hipLaunchKernelGGL((k_combine<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slots, Ct, n_ch, V,
+    hipLaunchKernelGGL((k_combine<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slots, Ct, n_ch, (int)V,
                        tb.ch_slot_begin);
 }
 
@@ -572,12 +638,13 @@ template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int
                                    const int32_t *, const int[5], const uint32_t *, hipStream_t);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
-template void launch_transpose<double>(const double2 *, double2 *, long, long, hipStream_t);
-template void launch_transpose<float>(const float2 *, float2 *, long, long, hipStream_t);
-template void launch_contract<double>(const double2 *, double2 *, double2 *, int, const int[3], int,
-                                      const ContractTables &, hipStream_t);
-template void launch_contract<float>(const float2 *, float2 *, float2 *, int, const int[3], int,
-                                     const ContractTables &, hipStream_t);
+template void launch_transpose_grouped<double>(const double2 *, double2 *, int, long, int, const int2 *,
+                                               hipStream_t);
+template void launch_transpose_grouped<float>(const float2 *, float2 *, int, long, int, const int2 *, hipStream_t);
+template void launch_contract<double>(const double2 *, double2 *, double2 *, int, long, int, const ContractTables &,
+                                      hipStream_t);
+template void launch_contract<float>(const float2 *, float2 *, float2 *, int, long, int, const ContractTables &,
+                                     hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
                                       double *, const uint32_t *, const int2 *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,

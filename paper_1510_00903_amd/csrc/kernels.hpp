@@ -12,7 +12,8 @@ struct DDiag {           // one diagram of one requested channel
     double coef;         // parity of the representative permutation times source weights
     int ref0, ref0_end;  // block refs of site 0 (B1 at X+r)
     int ref1, ref1_end;  // block refs of site 1 (B2 at X)
-    int pad[2];          // pad[0]: carry pattern, bit 0 = site of a', bit 1 = site of b'
+    int pad[2];          // pad[0]: carry pattern (bit 0 = site of a', bit 1 = site of b') | K << 2 | kdim4 << 10;
+                         // pad[1]: ceil(65536 / kdim4), so that k3 = (kk * pad[1]) >> 16 for kk < K
 };
 struct DRef {            // one intermediate entering a block
     double coef;         // sink-term weight times exchange sign
@@ -24,10 +25,10 @@ struct DRef {            // one intermediate entering a block
 
 // Device pointers of the contraction tables of one plan.
 struct ContractTables {
-    const int32_t *qorder;        // V momenta, each q followed by -q
-    int ntask;                    // tasks per momentum
-    const int4 *segs;             // 4 per task: item begin, item end, slot, unused
-    const uint32_t *items;        // diagram << 8 | k3 << 4 | k4
+    const int2 *gpos;             // per grouped position: (momentum or -1, lane of -q in the group)
+    int ngroup;                   // momentum groups (G positions each)
+    int ntask;                    // tasks per group
+    const int4 *segs;             // 4 per task: first diagram, end diagram, slot, unused
     const DDiag *diags;
     const DRef *refs;
     const int32_t *ch_slot_begin; // n_ch + 1
@@ -49,13 +50,16 @@ void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, h
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sign, hipStream_t st);
 
+// Momentum-grouped copy: in [g][nc][V] (component-major) -> out, per group of G
+// momenta (4 in FP64, 8 in FP32) and component, both sink spins and the G
+// momenta; gpos is the position table of the groups.
 template <typename T>
-void launch_transpose(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long R, long C,
-                      hipStream_t st);
+void launch_transpose_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, long V,
+                              int ngroup, const int2 *gpos, hipStream_t st);
 
 template <typename T>
 void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots,
-                     typename cplx_t<T>::type *Ct, int nc, const int L[3], int n_ch, const ContractTables &tb,
+                     typename cplx_t<T>::type *Ct, int nc, long V, int n_ch, const ContractTables &tb,
                      hipStream_t st);
 
 template <typename T>
