@@ -34,26 +34,19 @@ PAPER_SITE_CH_PER_S = 6815744 / 19.0   # best BG/Q layout of Table 5 (32 nodes),
 
 
 def stage_model(stage, L, nc, n_ch, csize):
-    """Algorithmic work of one launch of each stage.
-
-    Returns (bound, bytes, flops).  nc = intermediate components per sink spin.
-    """
+    """Algorithmic HBM bytes of one time slice of each stage: every
+    array read and written once.  nc = intermediate components per sink spin."""
     V = L ** 3
     field = 2 * nc * V * csize                      # all block intermediates, both sink spins
     out_field = n_ch * 16 * V * csize
-    if stage == "blocks":
-        return "hbm", V * 2 * 144 * csize + field, None
-    if stage == "fft_forward":                       # one axis pass: read + write the field
-        return "hbm", 2 * field, None
-    if stage == "transpose":
-        return "hbm", 2 * field, None
-    if stage == "contract":
-        return "alu", field + out_field, None        # flops filled in by caller (needs K totals)
-    if stage == "fft_inverse":
-        return "hbm", 2 * out_field, None
-    if stage == "finalize":
-        return "hbm", 2 * out_field, None
-    raise ValueError(stage)
+    return {
+        "blocks": V * 2 * 144 * csize + field,      # two propagator slices in, intermediates out
+        "fft_forward": 2 * field,
+        "transpose": 2 * field,
+        "contract": field,                          # intermediates in (partial slots are small)
+        "fft_inverse": 2 * out_field,
+        "finalize": 2 * out_field,
+    }.get(stage)
 
 
 def traffic_for(kernel, csize_tag):
@@ -349,31 +342,31 @@ def main():
     csize = 8 if fp32 else 16
     peak_alu = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     stages = {}
+    n_slices = T * args.steps
     for name, (ms, launches) in prof.items():
-        # fft stages launch one kernel per axis
-        per_stage_launch = 3 if name.startswith("fft") else 1
-        n_launch = launches * per_stage_launch
-        stages[name] = {"ms_total": round(ms, 4), "launches": int(n_launch),
-                        "us_per_launch": round(1000.0 * ms / max(1, n_launch), 2)}
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, launches = prof[dom]
-    n_launch = launches * (3 if dom.startswith("fft") else 1)
-    avg_s = ms / 1000.0 / max(1, n_launch)
-    bound, nbytes, _ = stage_model(dom, L, nc, n_ch, csize)
+        if launches == 0:
+            continue                                 # stage without kernels on this path (fused)
+        ms_slice = ms / n_slices
+        stages[name] = {"ms_total": round(ms, 4), "kernels": int(launches), "ms_per_slice": round(ms_slice, 4)}
+        nb = stage_model(name, L, nc, n_ch, csize)
+        if nb is not None:
+            stages[name]["alg_GBs"] = round(nb / (ms_slice * 1e-3) / 1e9, 1)
+    # dominant kernel: the contraction (one kernel per slice)
+    dom = max(stages, key=lambda k: stages[k]["ms_total"])
+    avg_s = stages[dom]["ms_total"] / 1000.0 / stages[dom]["kernels"]
     if dom == "contract":
         flops = 8.0 * 16 * st["iterations"] * L ** 3        # complex MAC = 8 flops, 16 spin outputs
         achieved = flops / avg_s / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak_alu,
                 "unit": "TFLOP/s", "frac": round(achieved / peak_alu, 4)}
     else:
+        nbytes = stage_model(dom, L, nc, n_ch, csize) * n_slices / stages[dom]["kernels"]
         achieved = nbytes / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4)}
     roof["kernel"] = dom
+    roof["avg_launch_us"] = round(avg_s * 1e6, 2)
     roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64")
-    for name in stages:
-        b2, nb, _ = stage_model(name, L, nc, n_ch, csize)
-        stages[name]["hbm_GBs"] = round(nb / (stages[name]["us_per_launch"] * 1e-6) / 1e9, 1)
 
     res = {
         "metric": "correlator site-channels/sec (C_ch(r,t))",

@@ -183,16 +183,21 @@ bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job);
 /*
  * Measurement.  With profiling on, bbc_correlate records a HIP event pair on
  * its stream around every kernel stage of every time slice:
- *   0 block construction (step 1a)      1 forward FFT, three axis passes (step 1b)
- *   2 transpose to momentum-major       3 open-index contraction (step 2a)
- *   4 inverse FFT (step 2b)             5 normalisation / output layout
+ *   0 block construction (step 1a)
+ *   1 forward FFT (step 1b): one pass per axis, or on small cubic lattices one
+ *     fused pass that also writes the momentum groups
+ *   2 copy into the momentum groups (no kernel when stage 1 was fused)
+ *   3 open-index contraction into partial slots (step 2a)
+ *   4 inverse FFT (step 2b), one pass per axis
+ *   5 normalisation / output layout
+ *   6 per-channel sum of the partial slots
  * bbc_profile_read waits for the recorded events, adds their elapsed times to
- * ms[stage] (milliseconds) and the number of timed launches to launches[stage]
- * (both arrays of n_stages <= BBC_NUM_STAGES entries, overwritten), then clears
- * the record.  Timing adds two events per stage and slice; it does not change
- * results.
+ * ms[stage] (milliseconds) and the number of kernels launched inside them to
+ * launches[stage] (both arrays of n_stages <= BBC_NUM_STAGES entries,
+ * overwritten), then clears the record.  Timing adds two events per stage and
+ * slice; it does not change results.
  */
-#define BBC_NUM_STAGES 6
+#define BBC_NUM_STAGES 7
 bbc_status bbc_profile_enable(bbc_context *ctx, int enable);
 bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t *launches);
 

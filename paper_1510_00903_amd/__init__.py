@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
 ]
 JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
 ETIMEOUT, ECANCELLED, ESTATE, ENOMEM = -5, -6, -7, -2
-STAGES = ["blocks", "fft_forward", "transpose", "contract", "fft_inverse", "finalize"]
+STAGES = ["blocks", "fft_forward", "transpose", "contract", "fft_inverse", "finalize", "combine"]
 
 
 class BBCError(RuntimeError):

@@ -259,7 +259,7 @@ struct bbc_context {
     hipEvent_t sev[8] = {};
     // profiling: event pairs recorded around kernel stages
     bool prof = false;
-    struct Rec { int stage; hipEvent_t a, b; };
+    struct Rec { int stage, nk; hipEvent_t a, b; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t event() {
@@ -284,6 +284,7 @@ namespace {
 // Records an event pair around one kernel stage when profiling is on (ctx may be null).
 struct StageTimer {
     bbc_context *ctx; hipStream_t st; int stage; hipEvent_t a = nullptr;
+    int nk = 1;                      // kernels launched inside the stage
     StageTimer(bbc_context *c, hipStream_t s, int g) : ctx(c), st(s), stage(g) {
         if (ctx && ctx->prof && (a = ctx->event())) (void)hipEventRecord(a, st);
     }
@@ -292,7 +293,7 @@ struct StageTimer {
         hipEvent_t b = ctx->event();
         if (!b) { ctx->pool.push_back(a); return; }
         (void)hipEventRecord(b, st);
-        ctx->recs.push_back({stage, a, b});
+        ctx->recs.push_back({stage, nk, a, b});
     }
 };
 }  // namespace
@@ -445,21 +446,32 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin, dp->pat_begin,
                               fp32 ? kmax : nullptr, st);
     }
+    // small cubic lattices: one fused pass (FFT in LDS, written straight into the groups)
+    const bool fused = bbc::fft3d_grouped_fits<T>(L);
     {
         StageTimer tm(pc, st, 1);
-        if (bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+        if (fused) {
+            if (bbc::launch_fft3d_grouped<T>(I, Iq, nc, L, mg.ngroup, mg.pos, st))
+                return fail(BBC_EUNSUPPORTED, "FFT size");
+        } else if ((tm.nk = bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) < 0) {
+            return fail(BBC_EUNSUPPORTED, "FFT size");
+        }
     }
-    {
+    if (!fused) {
         StageTimer tm(pc, st, 2);
         bbc::launch_transpose_grouped<T>(I, Iq, nc, V, mg.ngroup, mg.pos, st);
     }
     {
         StageTimer tm(pc, st, 3);
-        bbc::launch_contract<T>(Iq, slots, Ct, nc, V, n_ch, tb, st);
+        bbc::launch_contract<T>(Iq, slots, nc, V, tb, st);
+    }
+    {
+        StageTimer tm(pc, st, 6);
+        bbc::launch_combine<T>(slots, Ct, n_ch, V, dp->d_ch_slot_begin, st);
     }
     {
         StageTimer tm(pc, st, 4);
-        if (bbc::launch_fft3d<T>(Ct, 16L * n_ch, L, +1, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+        if ((tm.nk = bbc::launch_fft3d<T>(Ct, 16L * n_ch, L, +1, st)) < 0) return fail(BBC_EUNSUPPORTED, "FFT size");
     }
     {
         StageTimer tm(pc, st, 5);
@@ -1121,7 +1133,7 @@ bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t 
             if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
             if (e != hipSuccess) st = fail(BBC_EDEVICE, std::string("profile: ") + hipGetErrorString(e));
         }
-        if (r.stage < n_stages) { ms[r.stage] += t; launches[r.stage] += 1; }
+        if (r.stage < n_stages) { ms[r.stage] += t; launches[r.stage] += r.nk; }
         ctx->pool.push_back(r.a);
         ctx->pool.push_back(r.b);
     }

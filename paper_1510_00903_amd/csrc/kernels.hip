@@ -5,6 +5,7 @@
 // Per time slice the host driver launches, on one stream:
 //   k_blocks     step 1a: every block intermediate at every site        (site-local)
 //   k_fft (x3)   step 1b: forward 3-D FFT of every component            (one pass per axis)
+//   k_fft3d_grouped  step 1b fused with the grouped copy, one pass (small cubic lattices)
 //   k_transpose_grouped  component-major [g][comp][q] -> momentum groups (GroupLayout)
 //   k_contract   step 2a: open-index sums per momentum, all channels    (workgroups per group)
 //   k_fft (x3)   step 2b: inverse 3-D FFT of the 16 spin components per channel
@@ -288,7 +289,9 @@ static void fft_axis(typename cplx_t<T>::type *data, long ncomp, const int L[3],
 
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sgn, hipStream_t st) {
+    int n = 0;
     for (int axis = 0; axis < 3; ++axis) {
+        if (L[axis] > 1) ++n;
         switch (L[axis]) {
         case 1: break;
         case 2: fft_axis<T, 2>(data, ncomp, L, axis, sgn, st); break;
@@ -306,7 +309,7 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
         default: return -1;
         }
     }
-    return 0;
+    return n;
 }
 
 // ----------------------------------------------------------------------------
@@ -395,6 +398,110 @@ void launch_transpose_grouped(const typename cplx_t<T>::type *in, typename cplx_
     const long npos = (long)ngroup * G;
     dim3 grid((unsigned)((npos + 63) / 64), (unsigned)((nc + TC - 1) / TC));
     hipLaunchKernelGGL((k_transpose_grouped<T>), grid, dim3(256), 0, st, in, out, nc, V, npos, gpos);
+}
+
+// ----------------------------------------------------------------------------
+// Forward 3-D FFT of one component held whole in LDS (cubic lattices with
+// N^3 complex numbers <= 64 KB), fused with the scatter into the momentum
+// groups: one workgroup per (sink spin g, component c) reads the component's
+// N^3 values once, transforms x, y and z in LDS (one N-point line per thread
+// and axis, rows padded to N + 1 against bank conflicts), and writes every
+// momentum to its group position.  Replaces three axis passes and the
+// transpose for such lattices.
+// ----------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fft3d_grouped(const typename cplx_t<T>::type *__restrict__ in,
+                                                       typename cplx_t<T>::type *__restrict__ out, int nc,
+                                                       long npos, const int2 *__restrict__ gpos, int sgn) {
+    using T2 = typename cplx_t<T>::type;
+    using Ly = GroupLayout<T2>;
+    constexpr int G = Ly::G;
+    constexpr int V = N * N * N;
+    constexpr int NP = N + 1;                      // padded row
+    __shared__ T2 buf[N * N * NP];
+    __shared__ T2 tw[N];
+    const int t = threadIdx.x;
+    const int g = blockIdx.x / nc, c = blockIdx.x - g * nc;
+    for (int i = t; i < N; i += 256) {
+        double s, co;
+        sincospi(2.0 * i / N, &s, &co);
+        tw[i] = T2{T(co), T(sgn * s)};
+    }
+    const T2 *src = in + ((long)g * nc + c) * V;
+    for (int i = t; i < V; i += 256) {
+        const int x = i % N, r = i / N;             // r = z * N + y
+        buf[r * NP + x] = src[i];
+    }
+    __syncthreads();
+    T2 a[N], b[N];
+    // x lines: line l = z * N + y, elements stride 1
+    for (int l = t; l < N * N; l += 256) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = buf[l * NP + j];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+        for (int j = 0; j < N; ++j) buf[l * NP + j] = a[j];
+    }
+    __syncthreads();
+    // y lines: (x, z), elements stride NP
+    for (int l = t; l < N * N; l += 256) {
+        const int x = l % N, z = l / N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = buf[(z * N + j) * NP + x];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+        for (int j = 0; j < N; ++j) buf[(z * N + j) * NP + x] = a[j];
+    }
+    __syncthreads();
+    // z lines: (x, y), elements stride N * NP
+    for (int l = t; l < N * N; l += 256) {
+        const int x = l % N, y = l / N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = buf[(j * N + y) * NP + x];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+        for (int j = 0; j < N; ++j) buf[(j * N + y) * NP + x] = a[j];
+    }
+    __syncthreads();
+    T2 *dst = out + (long)c * 2 * G + g * Ly::SG;
+    for (long p = t; p < npos; p += 256) {
+        const int q = gpos[p].x;
+        T2 v = T2{0, 0};
+        if (q >= 0) {
+            const int x = q % N, r = q / N;
+            v = buf[r * NP + x];
+        }
+        dst[(p / G) * nc * 2 * G + (p % G) * Ly::S] = v;
+    }
+}
+
+// Whether the fused single-pass form applies: cubic lattice, N^3 complex <= 64 KB.
+template <typename T> bool fft3d_grouped_fits(const int L[3]) {
+    using T2 = typename cplx_t<T>::type;
+    if (L[0] != L[1] || L[1] != L[2]) return false;
+    switch (L[0]) {
+    case 4: case 6: case 8: case 12: case 16: break;
+    default: return false;
+    }
+    return (long)L[0] * L[0] * L[0] * sizeof(T2) <= 65536;
+}
+
+template <typename T>
+int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
+                         int ngroup, const int2 *gpos, hipStream_t st) {
+    using T2 = typename cplx_t<T>::type;
+    if (!fft3d_grouped_fits<T>(L)) return -1;
+    const long npos = (long)ngroup * GroupLayout<T2>::G;
+    const dim3 grid((unsigned)(2 * nc));
+    switch (L[0]) {
+    case 4: hipLaunchKernelGGL((k_fft3d_grouped<T, 4>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
+    case 6: hipLaunchKernelGGL((k_fft3d_grouped<T, 6>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
+    case 8: hipLaunchKernelGGL((k_fft3d_grouped<T, 8>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
+    case 12: hipLaunchKernelGGL((k_fft3d_grouped<T, 12>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
+    case 16: hipLaunchKernelGGL((k_fft3d_grouped<T, 16>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
+    default: return -1;
+    }
+    return 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -572,15 +679,19 @@ __global__ __launch_bounds__(256) void k_combine(const typename cplx_t<T>::type 
 }
 
 template <typename T>
-void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots,
-                     typename cplx_t<T>::type *Ct, int nc, long V, int n_ch, const ContractTables &tb,
-                     hipStream_t st) {
+void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots, int nc, long V,
+                     const ContractTables &tb, hipStream_t st) {
     const long nwg = 8L * ((tb.ngroup + 7) / 8) * tb.ntask;
     hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, V, tb.ngroup,
                        tb.gpos, tb.ntask, tb.segs, tb.diags, tb.refs);
+}
+
+template <typename T>
+void launch_combine(const typename cplx_t<T>::type *slots, typename cplx_t<T>::type *Ct, int n_ch, long V,
+                    const int32_t *ch_slot_begin, hipStream_t st) {
     const long n = (long)n_ch * 16 * V;
     hipLaunchKernelGGL((k_combine<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slots, Ct, n_ch, (int)V,
-                       tb.ch_slot_begin);
+                       ch_slot_begin);
 }
 
 // ----------------------------------------------------------------------------
@@ -641,10 +752,15 @@ template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t)
 template void launch_transpose_grouped<double>(const double2 *, double2 *, int, long, int, const int2 *,
                                                hipStream_t);
 template void launch_transpose_grouped<float>(const float2 *, float2 *, int, long, int, const int2 *, hipStream_t);
-template void launch_contract<double>(const double2 *, double2 *, double2 *, int, long, int, const ContractTables &,
-                                      hipStream_t);
-template void launch_contract<float>(const float2 *, float2 *, float2 *, int, long, int, const ContractTables &,
-                                     hipStream_t);
+template bool fft3d_grouped_fits<double>(const int[3]);
+template bool fft3d_grouped_fits<float>(const int[3]);
+template int launch_fft3d_grouped<double>(const double2 *, double2 *, int, const int[3], int, const int2 *,
+                                          hipStream_t);
+template int launch_fft3d_grouped<float>(const float2 *, float2 *, int, const int[3], int, const int2 *, hipStream_t);
+template void launch_contract<double>(const double2 *, double2 *, int, long, const ContractTables &, hipStream_t);
+template void launch_contract<float>(const float2 *, float2 *, int, long, const ContractTables &, hipStream_t);
+template void launch_combine<double>(const double2 *, double2 *, int, long, const int32_t *, hipStream_t);
+template void launch_combine<float>(const float2 *, float2 *, int, long, const int32_t *, hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
                                       double *, const uint32_t *, const int2 *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,

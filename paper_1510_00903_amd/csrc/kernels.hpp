@@ -57,10 +57,20 @@ template <typename T>
 void launch_transpose_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, long V,
                               int ngroup, const int2 *gpos, hipStream_t st);
 
+// Forward 3-D FFT fused with the grouped copy (one pass), for cubic lattices
+// whose N^3 complex values fit in 64 KB; returns -1 where it does not apply.
+template <typename T> bool fft3d_grouped_fits(const int L[3]);
 template <typename T>
-void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots,
-                     typename cplx_t<T>::type *Ct, int nc, long V, int n_ch, const ContractTables &tb,
-                     hipStream_t st);
+int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
+                         int ngroup, const int2 *gpos, hipStream_t st);
+
+// Open-index contraction into the partial slots, then their per-channel sum.
+template <typename T>
+void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots, int nc, long V,
+                     const ContractTables &tb, hipStream_t st);
+template <typename T>
+void launch_combine(const typename cplx_t<T>::type *slots, typename cplx_t<T>::type *Ct, int n_ch, long V,
+                    const int32_t *ch_slot_begin, hipStream_t st);
 
 template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
