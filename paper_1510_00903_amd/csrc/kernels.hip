@@ -47,10 +47,15 @@ template <typename T2> __device__ __forceinline__ void cfma(T2 &acc, T2 a, T2 b)
 // e_a | e_b << 4 | e_c << 8 | negative << 12) per component.
 // Components are grouped by pattern: 0 = (light diquark, light third quark),
 // 1 = (light, strange), 2 = (light-strange diquark, light), 3 = (ls, strange).
-// One workgroup handles TS consecutive sites; both sink spins are produced.
+// One workgroup handles TS consecutive sites and one of NSPLIT interleaved
+// shares of the components (the diquark tensor is rebuilt per share, which is
+// cheap next to the components); both sink spins are produced.  LDS rows are
+// padded by one element so that the TS sites of a wave fall in distinct banks.
+// Site blocks are placed XCD-aware (consecutive blocks on one XCD), so the
+// partial output lines of neighbouring blocks meet in the same L2.
 // Output layout: I[(g * nc + comp) * V + x].
 // ----------------------------------------------------------------------------
-template <typename T, int TS>
+template <typename T, int TS, int NSPLIT>
 __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *__restrict__ Sl,
                                                 const typename cplx_t<T>::type *__restrict__ Ss,
                                                 typename cplx_t<T>::type *__restrict__ I, int V, int nc, int g0,
@@ -58,10 +63,14 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
                                                 const int32_t *__restrict__ term_begin, int p0, int p1, int p2,
                                                 int p3, int p4, const uint32_t *__restrict__ kmax) {
     using T2 = typename cplx_t<T>::type;
-    __shared__ T2 sS[2][TS][144];
-    __shared__ T2 sQ[TS][432];
+    __shared__ T2 sS[2][TS][145];
+    __shared__ T2 sQ[TS][433];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TS;
+    const int nsb = (V + TS - 1) / TS;
+    const int sb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (sb >= nsb) return;
+    const int x0 = sb * TS;
+    const int share = blockIdx.y;
     // FP32 form: exact power-of-two rescale of each flavour's slice
     T kl = T(1), ks = T(1);
     if (kmax) {
@@ -103,7 +112,7 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
         __syncthreads();
         for (int pc = 0; pc < 2; ++pc) {
             const int p = qsel * 2 + pc;
-            for (int comp = pb[p] + slot; comp < pb[p + 1]; comp += NSLOT) {
+            for (int comp = pb[p] + share * NSLOT + slot; comp < pb[p + 1]; comp += NSLOT * NSPLIT) {
                 T2 acc0 = T2{0, 0}, acc1 = T2{0, 0};
                 const int tb = term_begin[comp], te = term_begin[comp + 1];
                 for (int t = tb; t < te; ++t) {
@@ -134,9 +143,10 @@ template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
                    const int32_t *term_begin, const int pb[5], const uint32_t *kmax, hipStream_t st) {
-    constexpr int TS = 8;
-    int nblk = (V + TS - 1) / TS;
-    hipLaunchKernelGGL((k_blocks<T, TS>), dim3(nblk), dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms, term_begin,
+    constexpr int TS = 4, NSPLIT = 2;
+    const long nsb = (V + TS - 1) / TS;
+    const dim3 grid((unsigned)(8 * ((nsb + 7) / 8)), NSPLIT);
+    hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms, term_begin,
                        pb[0], pb[1], pb[2], pb[3], pb[4], kmax);
 }
 
@@ -418,59 +428,64 @@ __global__ __launch_bounds__(256) void k_fft3d_grouped(const typename cplx_t<T>:
     constexpr int G = Ly::G;
     constexpr int V = N * N * N;
     constexpr int NP = N + 1;                      // padded row
+    constexpr int NQ = (V + 8 + 255) / 256;        // output positions per thread (npos <= V + 8)
+    static_assert(N * N <= 256, "one z line per thread");
     __shared__ T2 buf[N * N * NP];
     __shared__ T2 tw[N];
     const int t = threadIdx.x;
     const int g = blockIdx.x / nc, c = blockIdx.x - g * nc;
+    const bool line = t < N * N;
+    // issue every global load first: this thread's z line (x, y) = (t % N, t / N)
+    // and the momenta of its output positions
+    const T2 *src = in + ((long)g * nc + c) * V;
+    T2 a[N], b[N];
+    if (line) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = src[j * N * N + t];
+    }
+    int qv[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const long p = t + 256L * i;
+        qv[i] = p < npos ? gpos[p].x : -2;
+    }
     for (int i = t; i < N; i += 256) {
         double s, co;
         sincospi(2.0 * i / N, &s, &co);
         tw[i] = T2{T(co), T(sgn * s)};
     }
-    const T2 *src = in + ((long)g * nc + c) * V;
-    for (int i = t; i < V; i += 256) {
-        const int x = i % N, r = i / N;             // r = z * N + y
-        buf[r * NP + x] = src[i];
+    __syncthreads();
+    const int xt = t % N, yt = t / N;
+    if (line) {
+        Stages<T2, N, 1>::run(a, b, tw, sgn);          // z
+#pragma unroll
+        for (int j = 0; j < N; ++j) buf[(j * N + yt) * NP + xt] = a[j];
     }
     __syncthreads();
-    T2 a[N], b[N];
-    // x lines: line l = z * N + y, elements stride 1
-    for (int l = t; l < N * N; l += 256) {
+    if (line) {                                    // x line r = z * N + y, here r = t
 #pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = buf[l * NP + j];
+        for (int j = 0; j < N; ++j) a[j] = buf[t * NP + j];
         Stages<T2, N, 1>::run(a, b, tw, sgn);
 #pragma unroll
-        for (int j = 0; j < N; ++j) buf[l * NP + j] = a[j];
+        for (int j = 0; j < N; ++j) buf[t * NP + j] = a[j];
     }
     __syncthreads();
-    // y lines: (x, z), elements stride NP
-    for (int l = t; l < N * N; l += 256) {
-        const int x = l % N, z = l / N;
+    if (line) {                                    // y line (x, z) = (t % N, t / N)
 #pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = buf[(z * N + j) * NP + x];
+        for (int j = 0; j < N; ++j) a[j] = buf[(yt * N + j) * NP + xt];
         Stages<T2, N, 1>::run(a, b, tw, sgn);
 #pragma unroll
-        for (int j = 0; j < N; ++j) buf[(z * N + j) * NP + x] = a[j];
-    }
-    __syncthreads();
-    // z lines: (x, y), elements stride N * NP
-    for (int l = t; l < N * N; l += 256) {
-        const int x = l % N, y = l / N;
-#pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = buf[(j * N + y) * NP + x];
-        Stages<T2, N, 1>::run(a, b, tw, sgn);
-#pragma unroll
-        for (int j = 0; j < N; ++j) buf[(j * N + y) * NP + x] = a[j];
+        for (int j = 0; j < N; ++j) buf[(yt * N + j) * NP + xt] = a[j];
     }
     __syncthreads();
     T2 *dst = out + (long)c * 2 * G + g * Ly::SG;
-    for (long p = t; p < npos; p += 256) {
-        const int q = gpos[p].x;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = qv[i];
+        if (q == -2) break;                        // past the last position
+        const long p = t + 256L * i;
         T2 v = T2{0, 0};
-        if (q >= 0) {
-            const int x = q % N, r = q / N;
-            v = buf[r * NP + x];
-        }
+        if (q >= 0) v = buf[(q / N) * NP + q % N];
         dst[(p / G) * nc * 2 * G + (p % G) * Ly::S] = v;
     }
 }
