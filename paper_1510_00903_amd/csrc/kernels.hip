@@ -544,9 +544,11 @@ int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>:
 // open-index lane of E1(q) (x) E2(-q), each block value E a weighted sum of
 // intermediate components.  `base` points at the group's data; la / lb are the
 // offsets of the lanes of q and -q.  Table data (D, refs) is wave-uniform.
+// Each step a lane takes IPL open indices (kk, kk + NI, ...), sharing the
+// table reads; indices past K are replaced by a valid one with weight 0.
 // Products are formed in T and summed in FP64 (in the FP32 form this keeps the
 // open-index and diagram sums free of FP32 rounding).
-template <typename T, int C3, int C4>
+template <typename T, int C3, int C4, int IPL>
 __device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__restrict__ base, unsigned la,
                                             unsigned lb, const DDiag &D, const DRef *__restrict__ refs, int il,
                                             double2 (&acc)[16]) {
@@ -557,57 +559,82 @@ __device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__re
     constexpr int N2 = 4 / N1;
     const int K = (D.pad[0] >> 2) & 255, kd4 = (D.pad[0] >> 10) & 15, inv = D.pad[1];
     const double dc = D.coef;
-    for (int c = 0; c < K; c += NI) {
-        const int kk = c + il;
-        if (kk >= K) break;
-        const int k3 = (kk * inv) >> 16, k4 = kk - k3 * kd4;
-        T2 e1[2 * N1], e2[2 * N2];
+    for (int c = 0; c < K; c += NI * IPL) {
+        if (c + il >= K) break;
+        int k3[IPL], k4[IPL];
+        double wt[IPL];
 #pragma unroll
-        for (int i = 0; i < 2 * N1; ++i) e1[i] = T2{0, 0};
+        for (int u = 0; u < IPL; ++u) {
+            const int kk = c + il + u * NI;
+            const bool valid = kk < K;
+            const int kc = valid ? kk : c + il;          // an open index in range (weight 0 if padding)
+            k3[u] = (kc * inv) >> 16;
+            k4[u] = kc - k3[u] * kd4;
+            wt[u] = valid ? dc : 0.0;
+        }
+        T2 e1[IPL][2 * N1], e2[IPL][2 * N2];
 #pragma unroll
-        for (int i = 0; i < 2 * N2; ++i) e2[i] = T2{0, 0};
+        for (int u = 0; u < IPL; ++u) {
+#pragma unroll
+            for (int i = 0; i < 2 * N1; ++i) e1[u][i] = T2{0, 0};
+#pragma unroll
+            for (int i = 0; i < 2 * N2; ++i) e2[u][i] = T2{0, 0};
+        }
         for (int r = D.ref0; r < D.ref0_end; ++r) {
             const DRef R = refs[r];
-            const unsigned vl = la + (unsigned)(2 * G * (k3 * R.sk3 + k4 * R.sk4));
             const T c0 = T(R.coef);
+            unsigned vl[IPL];
+#pragma unroll
+            for (int u = 0; u < IPL; ++u) vl[u] = la + (unsigned)(2 * G * (k3[u] * R.sk3 + k4[u] * R.sk4));
 #pragma unroll
             for (int o = 0; o < N1; ++o) {
                 const int a3 = (C3 == 0) ? (o & 1) : 0;
                 const int a4 = (C4 == 0) ? ((C3 == 0) ? (o >> 1) : o) : 0;
                 const T2 *p = base + (size_t)2 * G * (R.base + a3 * R.so3 + a4 * R.so4);
-                T2 v0, v1;
-                load_spins(p, vl, v0, v1);
-                e1[2 * o].x += c0 * v0.x;
-                e1[2 * o].y += c0 * v0.y;
-                e1[2 * o + 1].x += c0 * v1.x;
-                e1[2 * o + 1].y += c0 * v1.y;
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    T2 v0, v1;
+                    load_spins(p, vl[u], v0, v1);
+                    e1[u][2 * o].x += c0 * v0.x;
+                    e1[u][2 * o].y += c0 * v0.y;
+                    e1[u][2 * o + 1].x += c0 * v1.x;
+                    e1[u][2 * o + 1].y += c0 * v1.y;
+                }
             }
         }
         for (int r = D.ref1; r < D.ref1_end; ++r) {
             const DRef R = refs[r];
-            const unsigned vl = lb + (unsigned)(2 * G * (k3 * R.sk3 + k4 * R.sk4));
             const T c0 = T(R.coef);
+            unsigned vl[IPL];
+#pragma unroll
+            for (int u = 0; u < IPL; ++u) vl[u] = lb + (unsigned)(2 * G * (k3[u] * R.sk3 + k4[u] * R.sk4));
 #pragma unroll
             for (int o = 0; o < N2; ++o) {
                 const int a3 = (C3 == 1) ? (o & 1) : 0;
                 const int a4 = (C4 == 1) ? ((C3 == 1) ? (o >> 1) : o) : 0;
                 const T2 *p = base + (size_t)2 * G * (R.base + a3 * R.so3 + a4 * R.so4);
-                T2 v0, v1;
-                load_spins(p, vl, v0, v1);
-                e2[2 * o].x += c0 * v0.x;
-                e2[2 * o].y += c0 * v0.y;
-                e2[2 * o + 1].x += c0 * v1.x;
-                e2[2 * o + 1].y += c0 * v1.y;
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    T2 v0, v1;
+                    load_spins(p, vl[u], v0, v1);
+                    e2[u][2 * o].x += c0 * v0.x;
+                    e2[u][2 * o].y += c0 * v0.y;
+                    e2[u][2 * o + 1].x += c0 * v1.x;
+                    e2[u][2 * o + 1].y += c0 * v1.y;
+                }
             }
         }
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int a = s & 1, bb = (s >> 1) & 1, a3 = (s >> 2) & 1, a4 = s >> 3;
-            const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
-            const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
-            const T2 p = cmul(e1[a + 2 * o1], e2[bb + 2 * o2]);
-            acc[s].x = fma(dc, (double)p.x, acc[s].x);
-            acc[s].y = fma(dc, (double)p.y, acc[s].y);
+        for (int u = 0; u < IPL; ++u) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int a = s & 1, bb = (s >> 1) & 1, a3 = (s >> 2) & 1, a4 = s >> 3;
+                const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
+                const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
+                const T2 p = cmul(e1[u][a + 2 * o1], e2[u][bb + 2 * o2]);
+                acc[s].x = fma(wt[u], (double)p.x, acc[s].x);
+                acc[s].y = fma(wt[u], (double)p.y, acc[s].y);
+            }
         }
     }
 }
@@ -639,16 +666,24 @@ __global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type
     const int d0 = __builtin_amdgcn_readfirstlane(sg.x), d1 = __builtin_amdgcn_readfirstlane(sg.y);
     if (d0 >= d1) return;
     const unsigned la = gl * Ly::S, lb = pq.y * Ly::S;
+    // diagrams with at least kWide open-index items take two per lane and step
+    // (more loads in flight per table read; register use sets the thresholds)
+    constexpr int kWide = sizeof(T) == 8 ? 128 : 32;
     double2 acc[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) acc[s] = double2{0, 0};
     for (int d = d0; d < d1; ++d) {
         const DDiag D = diags[d];
-        switch (D.pad[0] & 3) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
-        case 0: diagram_sum<T, 0, 0>(base, la, lb, D, refs, il, acc); break;
-        case 1: diagram_sum<T, 1, 0>(base, la, lb, D, refs, il, acc); break;
-        case 2: diagram_sum<T, 0, 1>(base, la, lb, D, refs, il, acc); break;
-        default: diagram_sum<T, 1, 1>(base, la, lb, D, refs, il, acc); break;
+        const bool wide = ((D.pad[0] >> 2) & 255) >= kWide;
+        switch ((D.pad[0] & 3) | (wide ? 4 : 0)) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
+        case 0: diagram_sum<T, 0, 0, 1>(base, la, lb, D, refs, il, acc); break;
+        case 1: diagram_sum<T, 1, 0, 1>(base, la, lb, D, refs, il, acc); break;
+        case 2: diagram_sum<T, 0, 1, 1>(base, la, lb, D, refs, il, acc); break;
+        case 3: diagram_sum<T, 1, 1, 1>(base, la, lb, D, refs, il, acc); break;
+        case 4: diagram_sum<T, 0, 0, 2>(base, la, lb, D, refs, il, acc); break;
+        case 5: diagram_sum<T, 1, 0, 2>(base, la, lb, D, refs, il, acc); break;
+        case 6: diagram_sum<T, 0, 1, 2>(base, la, lb, D, refs, il, acc); break;
+        default: diagram_sum<T, 1, 1, 2>(base, la, lb, D, refs, il, acc); break;
         }
     }
     // sum over the open-index lanes of each momentum lane
