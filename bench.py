@@ -49,10 +49,10 @@ def stage_model(stage, L, nc, n_ch, csize):
     }.get(stage)
 
 
-def traffic_for(kernel, csize_tag):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, csize_tag))
+def traffic_for(kernel, csize_tag, L):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary for this
+    kernel, form and lattice, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_%dc.json" % (kernel, csize_tag, L))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -366,7 +366,7 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4)}
     roof["kernel"] = dom
     roof["avg_launch_us"] = round(avg_s * 1e6, 2)
-    roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64")
+    roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64", L)
 
     res = {
         "metric": "correlator site-channels/sec (C_ch(r,t))",
