@@ -18,4 +18,6 @@ Contents
   unified.py    O-U: the same sum with the source-tensor and sigma sums folded
                 into weights first and the X-sum done by a library FFT (the idea
                 of the unified-contraction cross-check of Sec. 6).
+  postproc.py   post-processing of C(r, t) (Sec. 2): spin projection to (J, M),
+                A1+ projection over the cubic group, HAL QCD central potential.
 """
