@@ -251,6 +251,74 @@ def stream96(bbc, torch, np, n_slices):
             "stages": stages}
 
 
+def postproc(bbc, torch, np, steps):
+    """Post-processing of the 16^3 x 32, 52-channel FP64 output (Sec. 2): spin
+    projection (J = 0 at sink and source; source J = 1, M = 0 keeping the sink
+    pair), A1+ projection over the cubic group of the 4-component field, and the
+    central potential of every channel's J = 0 field.  Inputs: a seeded random field
+    of the correlator's shape (the kernels' cost does not depend on the values).
+    Each kernel is timed over `steps` calls with HIP events on the current stream;
+    rates are algorithmic bytes (every array read and written once) per second."""
+    L, T, n_ch = 16, 32, 52
+    V = L ** 3
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1510009036)
+    C = torch.randn((T, n_ch, L, L, L, 16), dtype=torch.complex128, device=dev, generator=g)
+    sq = np.sqrt(0.5)
+    P00 = np.array([[0, sq], [-sq, 0]])
+    P10 = np.array([[0, sq], [sq, 0]])
+    def sidx(a, b, ap, bp):
+        return a + 2 * (b + 2 * (ap + 2 * bp))
+    W0 = np.zeros((1, 16), dtype=complex)
+    W1 = np.zeros((4, 16), dtype=complex)
+    for a in range(2):
+        for b in range(2):
+            for ap in range(2):
+                for bp in range(2):
+                    W0[0, sidx(a, b, ap, bp)] = P00[a][b] * P00[ap][bp]
+                    W1[a + 2 * b, sidx(a, b, ap, bp)] = P10[ap][bp]
+    ctx = bbc.Context(0)
+    out0 = torch.empty((T, n_ch, L, L, L, 1), dtype=C.dtype, device=dev)
+    out1 = torch.empty((T, n_ch, L, L, L, 4), dtype=C.dtype, device=dev)
+    outc = torch.empty_like(out1)
+    ctx.spin_project(C, W0, out=out0)
+    R = out0[..., 0].permute(1, 0, 2, 3, 4).contiguous()          # [channel][t][z][y][x]
+    Vp = torch.empty((n_ch, T - 2, L, L, L), dtype=C.dtype, device=dev)
+    cs = 16
+    jobs = {
+        "spin_project_J0": (lambda: ctx.spin_project(C, W0, out=out0), T * n_ch * V * (16 + 1) * cs),
+        "spin_project_src_J1M0": (lambda: ctx.spin_project(C, W1, out=out1), T * n_ch * V * (16 + 4) * cs),
+        "cubic_project_A1": (lambda: ctx.cubic_project(out1, out=outc), 2 * T * n_ch * V * 4 * cs),
+        "central_potential": (lambda: [ctx.central_potential(R[m], 0.5, out=Vp[m]) for m in range(n_ch)],
+                              n_ch * (T + T - 2) * V * cs),
+    }
+    res = {}
+    for name, (fn, nbytes) in jobs.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "alg_GB": round(nbytes / 1e9, 3), "GB_s": round(gbs, 1),
+                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+    ok = bool(torch.isfinite(Vp).all().item())
+    ctx.close()
+    total_ms = sum(v["ms"] for v in res.values())
+    return {"metric": "post-processing of C(r,t): site-channels/sec", "value": round(T * n_ch * V / (total_ms * 1e-3), 1),
+            "unit": "site-channels/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic (seeded random field of the correlator's shape)", "outputs_finite": ok,
+            "config": {"workload": "16^3x32, 52 channels: spin projection J=0 and source J=1 M=0, A1+ cubic "
+                                   "projection, central potential per channel", "lattice": [L, L, L], "T": T,
+                       "channels": n_ch},
+            "kernels": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,7 +326,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="16c32-f64",
-                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream"],
+                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream", "post-16c32"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
     ap.add_argument("--slices", type=int, default=0,
@@ -283,6 +351,9 @@ def main():
         return
     if args.workload == "96c-f32-stream":
         print(json.dumps(stream96(bbc, torch, np, args.steps)), flush=True)
+        return
+    if args.workload == "post-16c32":
+        print(json.dumps(postproc(bbc, torch, np, args.steps)), flush=True)
         return
 
     fp32 = args.workload.endswith("f32")

@@ -201,6 +201,49 @@ bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job);
 bbc_status bbc_profile_enable(bbc_context *ctx, int enable);
 bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t *launches);
 
+/*
+ * Post-processing of C(r, t) (Sec. 2).  All buffers are device memory on the
+ * context's GPU, complex interleaved (re, im); calls are stream-ordered on
+ * `stream` and do not allocate.  `in` and `out` must not overlap.
+ *
+ * bbc_spin_project: projection of the 16 spin values of each site (the
+ *   bbc_correlate layout, spin index s = a + 2 (b + 2 (a' + 2 b')) for sink spins
+ *   a, b and source spins a', b' of the selected upper or lower components,
+ *   component 0 = spin up, 1 = down in the Dirac representation) onto n_out
+ *   combinations: out[f][site][m] = sum_s W[m][s] in[f][site][s] for n_fields
+ *   fields of V sites.  W: host array of n_out x 16 complex doubles; with
+ *   W[m][s] = P^(J,M)(a,b)* P^(J,M)(a',b') (Clebsch-Gordan coefficients) it forms
+ *   the source operator J^(J,M) of Sec. 2 and the same projection at the sink.
+ *   1 <= n_out <= 16; the FP32 form's per-(t, channel) scale factors pass through
+ *   unchanged (the projection is linear).
+ */
+bbc_status bbc_spin_project(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_fields,
+                            const void *in, int n_out, const double *W, void *out, void *stream);
+
+/*
+ * bbc_cubic_project: projection of the relative coordinate onto the A1+
+ *   representation of the cubic group, P f(r) = (1/24) sum_{R in O} f(R r) over the
+ *   24 proper rotations, r taken mod L (Sec. 2, separation of 3S1 from 3D1); with
+ *   mode BBC_CUBIC_A1_COMPLEMENT the output is Q f = f - P f.  Layout
+ *   [n_fields][z][y][x][n_comp]; the lattice must be cubic (else BBC_EUNSUPPORTED).
+ */
+#define BBC_CUBIC_A1 0
+#define BBC_CUBIC_A1_COMPLEMENT 1
+bbc_status bbc_cubic_project(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_fields, int n_comp,
+                             const void *in, int mode, void *out, void *stream);
+
+/*
+ * bbc_central_potential: leading-order central potential of the HAL QCD method
+ *   (Sec. 2), V(r, t) = (lap R(r, t) / (2 mu) - dR/dt) / R(r, t), with the six-point
+ *   periodic lattice Laplacian and the symmetric difference (R(t+1) - R(t-1)) / 2,
+ *   for the n_t - 2 inner slices of n_t consecutive slices R[t][z][y][x] (complex
+ *   FP64; e.g. a spin-projected C with the e^{(m1+m2)(t-t0)} normalisation).
+ *   inv_2mu = 1 / (2 mu), mu the reduced mass in lattice units.  V_out:
+ *   [n_t - 2][z][y][x] complex FP64.  Sites where R = 0 give non-finite values.
+ */
+bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int n_t, const void *R, double inv_2mu,
+                                 void *V_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

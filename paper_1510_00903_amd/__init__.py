@@ -13,7 +13,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["BBCError", "F64", "F32", "UPPER", "LOWER", "STAGES", "Context", "library_path", "load",
+__all__ = ["BBCError", "F64", "F32", "UPPER", "LOWER", "STAGES", "CUBIC_A1", "CUBIC_A1_COMPLEMENT",
+           "Context", "library_path", "load",
            "num_channels", "num_channels_all", "channel_name", "channel_content", "source_terms",
            "diagram_table", "plan_stats", "footprint", "EXPORTED_SYMBOLS"]
 
@@ -30,7 +31,9 @@ EXPORTED_SYMBOLS = [
     "bbc_last_error", "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
     "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
     "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
+    "bbc_spin_project", "bbc_cubic_project", "bbc_central_potential",
 ]
+CUBIC_A1, CUBIC_A1_COMPLEMENT = 0, 1
 JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
 ETIMEOUT, ECANCELLED, ESTATE, ENOMEM = -5, -6, -7, -2
 STAGES = ["blocks", "fft_forward", "transpose", "contract", "fft_inverse", "finalize", "combine"]
@@ -83,7 +86,10 @@ def load():
     lib.bbc_cancel.argtypes = [P, U64]
     lib.bbc_job_times.argtypes = [P, U64, P, P, P]
     lib.bbc_job_forget.argtypes = [P, U64]
-    for f in ("bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
+    lib.bbc_spin_project.argtypes = [P, P, I, I, P, I, P, P, P]
+    lib.bbc_cubic_project.argtypes = [P, P, I, I, I, P, I, P, P]
+    lib.bbc_central_potential.argtypes = [P, P, I, P, ctypes.c_double, P, P]
+    for f in ("bbc_spin_project", "bbc_cubic_project", "bbc_central_potential", "bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
               "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
               "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit",
               "bbc_poll", "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget"):
@@ -306,3 +312,75 @@ class Context:
             ctypes.c_void_p(scale.data_ptr()) if (prec == F32) else None,
             ctypes.c_void_p(stream.cuda_stream)))
         return (out, scale) if prec == F32 else out
+
+    # ------------------------------------------------------- post-processing
+    def _field_args(self, field, n_site_vals):
+        import torch
+        if not field.is_cuda:
+            raise BBCError("post-processing fields must be device tensors")
+        if field.dtype == torch.complex128:
+            prec = F64
+        elif field.dtype == torch.complex64:
+            prec = F32
+        else:
+            raise BBCError("fields must be complex128 or complex64")
+        if field.dim() < 4:
+            raise BBCError("field must be [..., Lz, Ly, Lx, n]")
+        Lz, Ly, Lx, n = field.shape[-4:]
+        if n != n_site_vals:
+            raise BBCError("last dimension must be %d" % n_site_vals)
+        n_fields = field.numel() // (Lx * Ly * Lz * n)
+        lat, _ = _i32([Lx, Ly, Lz])
+        return prec, lat, n_fields, (Lz, Ly, Lx)
+
+    def spin_project(self, C, W, out=None, stream=None):
+        """out[..., m] = sum_s W[m, s] C[..., s] for C [..., Lz, Ly, Lx, 16] on the device;
+        W: n_out x 16 complex (host, e.g. Clebsch-Gordan products)."""
+        import numpy as np
+        import torch
+        C = C.contiguous()
+        prec, lat, n_fields, sp = self._field_args(C, 16)
+        Wn = np.ascontiguousarray(np.asarray(W, dtype=np.complex128))
+        if Wn.ndim != 2 or Wn.shape[1] != 16:
+            raise BBCError("W must be n_out x 16")
+        n_out = Wn.shape[0]
+        if out is None:
+            out = torch.empty(C.shape[:-1] + (n_out,), dtype=C.dtype, device=C.device)
+        w_arr = Wn.view(np.float64).ctypes.data_as(ctypes.c_void_p)
+        if stream is None:
+            stream = torch.cuda.current_stream(C.device)
+        _check(self._lib.bbc_spin_project(self._ptr, lat, prec, n_fields, ctypes.c_void_p(C.data_ptr()), n_out,
+                                          w_arr, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def cubic_project(self, F, complement=False, out=None, stream=None):
+        """A1+ projection over the cubic group of F [..., L, L, L, n] (device); Q = 1 - P if complement."""
+        import torch
+        F = F.contiguous()
+        prec, lat, n_fields, _ = self._field_args(F, F.shape[-1])
+        if out is None:
+            out = torch.empty_like(F)
+        if stream is None:
+            stream = torch.cuda.current_stream(F.device)
+        _check(self._lib.bbc_cubic_project(self._ptr, lat, prec, n_fields, F.shape[-1],
+                                           ctypes.c_void_p(F.data_ptr()),
+                                           CUBIC_A1_COMPLEMENT if complement else CUBIC_A1,
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+        return out
+
+    def central_potential(self, R, inv_2mu, out=None, stream=None):
+        """V(r, t) for the inner slices of R [n_t, Lz, Ly, Lx] complex128 on the device."""
+        import torch
+        if not R.is_cuda or R.dtype != torch.complex128 or R.dim() != 4:
+            raise BBCError("R must be a [n_t, Lz, Ly, Lx] complex128 device tensor")
+        R = R.contiguous()
+        n_t, Lz, Ly, Lx = R.shape
+        lat, _ = _i32([Lx, Ly, Lz])
+        if out is None:
+            out = torch.empty((max(n_t - 2, 0), Lz, Ly, Lx), dtype=R.dtype, device=R.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(R.device)
+        _check(self._lib.bbc_central_potential(self._ptr, lat, n_t, ctypes.c_void_p(R.data_ptr()),
+                                               float(inv_2mu), ctypes.c_void_p(out.data_ptr()),
+                                               ctypes.c_void_p(stream.cuda_stream)))
+        return out

@@ -1142,3 +1142,125 @@ bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- post-processing
+namespace {
+bbc_status check_extents(const int32_t *lattice, long *V) {
+    if (!lattice) return fail(BBC_EINVAL, "lattice is NULL");
+    long v = 1;
+    for (int i = 0; i < 3; ++i) {
+        if (lattice[i] < 1) return fail(BBC_EINVAL, "lattice extent must be positive");
+        v *= lattice[i];
+    }
+    if (v > (1L << 30)) return fail(BBC_EUNSUPPORTED, "lattice volume too large");
+    *V = v;
+    return BBC_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+// The 24 proper rotations of the cube as signed permutations of (x, y, z).
+bbc::CubicRotations cubic_rotations() {
+    bbc::CubicRotations R{};
+    int k = 0;
+    int p[3] = {0, 1, 2};
+    do {
+        // parity of the permutation: number of inversions
+        int inv = (p[0] > p[1]) + (p[0] > p[2]) + (p[1] > p[2]);
+        for (int sgn = 0; sgn < 8; ++sgn) {
+            int s[3] = {(sgn & 1) ? -1 : 1, (sgn & 2) ? -1 : 1, (sgn & 4) ? -1 : 1};
+            int det = ((inv & 1) ? -1 : 1) * s[0] * s[1] * s[2];
+            if (det != 1) continue;
+            for (int d = 0; d < 3; ++d) {
+                R.perm[k][d] = (int8_t)p[d];
+                R.sign[k][d] = (int8_t)s[d];
+            }
+            ++k;
+        }
+    } while (std::next_permutation(p, p + 3));
+    return R;
+}
+}  // namespace
+
+extern "C" {
+
+bbc_status bbc_spin_project(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_fields,
+                            const void *in, int n_out, const double *W, void *out, void *stream) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_extents(lattice, &V);
+    if (s) return s;
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    if (n_fields < 0 || n_out < 1 || n_out > 16) return fail(BBC_EINVAL, "n_fields >= 0 and 1 <= n_out <= 16");
+    if (!W) return fail(BBC_EINVAL, "NULL weights");
+    if (n_fields == 0) return BBC_OK;
+    if (!in || !out) return fail(BBC_EINVAL, "NULL buffer");
+    if (is_host_pointer(in) || is_host_pointer(out)) return fail(BBC_EINVAL, "in and out must be device memory");
+    const size_t cs = prec == BBC_F64 ? 16 : 8;
+    const long nsite = (long)n_fields * V;
+    if (overlap(in, nsite * 16 * cs, out, nsite * n_out * cs)) return fail(BBC_EINVAL, "in and out overlap");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == BBC_F64)
+        bbc::launch_spin_project<double>((const double2 *)in, (double2 *)out, nsite, n_out, W, st);
+    else
+        bbc::launch_spin_project<float>((const float2 *)in, (float2 *)out, nsite, n_out, W, st);
+    HIP_TRY(hipGetLastError());
+    return BBC_OK;
+}
+
+bbc_status bbc_cubic_project(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_fields, int n_comp,
+                             const void *in, int mode, void *out, void *stream) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_extents(lattice, &V);
+    if (s) return s;
+    if (lattice[0] != lattice[1] || lattice[1] != lattice[2])
+        return fail(BBC_EUNSUPPORTED, "the cubic-group projection needs a cubic lattice");
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    if (mode != BBC_CUBIC_A1 && mode != BBC_CUBIC_A1_COMPLEMENT) return fail(BBC_EINVAL, "mode");
+    if (n_fields < 0 || n_comp < 1) return fail(BBC_EINVAL, "n_fields >= 0 and n_comp >= 1");
+    if (n_fields == 0) return BBC_OK;
+    if (!in || !out) return fail(BBC_EINVAL, "NULL buffer");
+    if (is_host_pointer(in) || is_host_pointer(out)) return fail(BBC_EINVAL, "in and out must be device memory");
+    const size_t cs = prec == BBC_F64 ? 16 : 8;
+    const size_t bytes = (size_t)n_fields * V * n_comp * cs;
+    if (overlap(in, bytes, out, bytes)) return fail(BBC_EINVAL, "in and out overlap");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const bbc::CubicRotations rot = cubic_rotations();
+    const int cmp = mode == BBC_CUBIC_A1_COMPLEMENT;
+    if (prec == BBC_F64)
+        bbc::launch_cubic_project<double>((const double2 *)in, (double2 *)out, n_fields, lattice[0], n_comp, cmp, rot,
+                                          st);
+    else
+        bbc::launch_cubic_project<float>((const float2 *)in, (float2 *)out, n_fields, lattice[0], n_comp, cmp, rot,
+                                         st);
+    HIP_TRY(hipGetLastError());
+    return BBC_OK;
+}
+
+bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int n_t, const void *R, double inv_2mu,
+                                 void *V_out, void *stream) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_extents(lattice, &V);
+    if (s) return s;
+    if (n_t < 3) return fail(BBC_EINVAL, "the potential needs n_t >= 3 consecutive slices");
+    if (!R || !V_out) return fail(BBC_EINVAL, "NULL buffer");
+    if (is_host_pointer(R) || is_host_pointer(V_out)) return fail(BBC_EINVAL, "R and V must be device memory");
+    if (overlap(R, (size_t)n_t * V * 16, V_out, (size_t)(n_t - 2) * V * 16)) return fail(BBC_EINVAL, "R and V overlap");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    bbc::launch_central_potential((const double2 *)R, (double2 *)V_out, L, n_t, inv_2mu, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return BBC_OK;
+}
+
+}  // extern "C"

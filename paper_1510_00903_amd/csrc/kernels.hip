@@ -10,6 +10,7 @@
 //   k_contract   step 2a: open-index sums per momentum, all channels    (workgroups per group)
 //   k_fft (x3)   step 2b: inverse 3-D FFT of the 16 spin components per channel
 //   k_finalize   normalisation and transpose to the output layout [r][spin]
+// Post-processing of C(r, t): k_spin_project, k_cubic_project, k_central_potential.
 #include "kernels.hpp"
 
 #include <algorithm>
@@ -792,6 +793,128 @@ void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::typ
                        energy, dt, inv_v, scale_out, kmax, content);
 }
 
+// ----------------------------------------------------------------------------
+// Post-processing of C(r, t) (Sec. 2): spin projection, projection of the
+// spatial argument onto the A1+ representation of the cubic group, and the
+// leading-order central potential.  All three are site-local or stencil work
+// on the output field, bound by HBM.
+// ----------------------------------------------------------------------------
+// Spin projection: out[f][r][m0 + m] = sum_s W.w[m][s] in[f][r][s], m < W.n (<= 4
+// outputs per launch; the weights travel in the kernel arguments).
+template <typename T>
+__global__ __launch_bounds__(256) void k_spin_project(const typename cplx_t<T>::type *__restrict__ in,
+                                                      typename cplx_t<T>::type *__restrict__ out, long nsite,
+                                                      int n_out, int m0, SpinWeights4 W) {
+    using T2 = typename cplx_t<T>::type;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsite) return;
+    const T2 *p = in + i * 16;
+    double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const T2 v = p[s];
+        const double vx = v.x, vy = v.y;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const double2 w = W.w[m][s];
+            acc[m].x += w.x * vx - w.y * vy;
+            acc[m].y += w.x * vy + w.y * vx;
+        }
+    }
+    T2 *q = out + i * n_out + m0;
+    for (int m = 0; m < W.n; ++m) q[m] = T2{T(acc[m].x), T(acc[m].y)};
+}
+
+// A1+ projection over the 24 proper rotations of the cube: thread = (field,
+// site, component); rotation R maps (x, y, z) to (s0 r_p0, s1 r_p1, s2 r_p2) mod L.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cubic_project(const typename cplx_t<T>::type *__restrict__ in,
+                                                       typename cplx_t<T>::type *__restrict__ out, long n_fields,
+                                                       int L, int n_comp, int complement, CubicRotations rot) {
+    using T2 = typename cplx_t<T>::type;
+    const long V = (long)L * L * L;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_fields * V * n_comp) return;
+    const int c = (int)(i % n_comp);
+    const long site = (i / n_comp) % V;
+    const long f = i / (n_comp * V);
+    const int r[3] = {(int)(site % L), (int)((site / L) % L), (int)(site / ((long)L * L))};
+    const T2 *src = in + f * V * n_comp + c;
+    double ax = 0, ay = 0;
+    for (int k = 0; k < 24; ++k) {
+        int rr[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int v = r[rot.perm[k][d]];
+            rr[d] = rot.sign[k][d] > 0 ? v : (v == 0 ? 0 : L - v);
+        }
+        const T2 v = src[(((long)rr[2] * L + rr[1]) * L + rr[0]) * n_comp];
+        ax += v.x;
+        ay += v.y;
+    }
+    ax *= 1.0 / 24.0;
+    ay *= 1.0 / 24.0;
+    if (complement) {
+        const T2 v = src[site * n_comp];
+        ax = v.x - ax;
+        ay = v.y - ay;
+    }
+    out[i] = T2{T(ax), T(ay)};
+}
+
+// Central potential at slice t of n_t consecutive slices (t = 1 .. n_t - 2):
+//   V = (lap R(t) * inv_2mu - (R(t+1) - R(t-1)) / 2) / R(t), six-point periodic Laplacian.
+__global__ __launch_bounds__(256) void k_central_potential(const double2 *__restrict__ R, double2 *__restrict__ Vout,
+                                                           int Lx, int Ly, int Lz, int n_t, double inv_2mu) {
+    const long V = (long)Lx * Ly * Lz;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)(n_t - 2) * V) return;
+    const long site = i % V;
+    const int t = (int)(i / V) + 1;
+    const int x = (int)(site % Lx), y = (int)((site / Lx) % Ly), z = (int)(site / ((long)Lx * Ly));
+    const double2 *Rt = R + (long)t * V;
+    auto at = [&](int xx, int yy, int zz) { return Rt[((long)zz * Ly + yy) * Lx + xx]; };
+    const double2 c = Rt[site];
+    const double2 n[6] = {at((x + 1) % Lx, y, z), at((x + Lx - 1) % Lx, y, z), at(x, (y + 1) % Ly, z),
+                          at(x, (y + Ly - 1) % Ly, z), at(x, y, (z + 1) % Lz), at(x, y, (z + Lz - 1) % Lz)};
+    double lx = -6.0 * c.x, ly = -6.0 * c.y;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { lx += n[k].x; ly += n[k].y; }
+    const double2 up = R[(long)(t + 1) * V + site], dn = R[(long)(t - 1) * V + site];
+    const double nx = lx * inv_2mu - 0.5 * (up.x - dn.x);
+    const double ny = ly * inv_2mu - 0.5 * (up.y - dn.y);
+    const double den = c.x * c.x + c.y * c.y;     // (nx + i ny) / (c.x + i c.y)
+    Vout[i] = double2{(nx * c.x + ny * c.y) / den, (ny * c.x - nx * c.y) / den};
+}
+
+template <typename T>
+void launch_spin_project(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long nsite, int n_out,
+                         const double *W, hipStream_t st) {
+    for (int m0 = 0; m0 < n_out; m0 += 4) {
+        SpinWeights4 w{};
+        w.n = n_out - m0 < 4 ? n_out - m0 : 4;
+        for (int m = 0; m < w.n; ++m)
+            for (int s = 0; s < 16; ++s) w.w[m][s] = double2{W[((m0 + m) * 16 + s) * 2], W[((m0 + m) * 16 + s) * 2 + 1]};
+        hipLaunchKernelGGL((k_spin_project<T>), dim3((unsigned)((nsite + 255) / 256)), dim3(256), 0, st, in, out,
+                           nsite, n_out, m0, w);
+    }
+}
+
+template <typename T>
+void launch_cubic_project(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long n_fields, int L,
+                          int n_comp, int complement, const CubicRotations &rot, hipStream_t st) {
+    const long n = n_fields * (long)L * L * L * n_comp;
+    hipLaunchKernelGGL((k_cubic_project<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n_fields,
+                       L, n_comp, complement, rot);
+}
+
+void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], int n_t, double inv_2mu,
+                              hipStream_t st) {
+    const long n = (long)(n_t - 2) * L[0] * L[1] * L[2];
+    hipLaunchKernelGGL(k_central_potential, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, Vout, L[0], L[1],
+                       L[2], n_t, inv_2mu);
+}
+
 // explicit instantiations
 template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
                                     const int32_t *, const int[5], const uint32_t *, hipStream_t);
@@ -815,5 +938,12 @@ template void launch_finalize<double>(const double2 *, double2 *, int, int, cons
                                       double *, const uint32_t *, const int2 *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,
                                      const uint32_t *, const int2 *, hipStream_t);
+
+template void launch_spin_project<double>(const double2 *, double2 *, long, int, const double *, hipStream_t);
+template void launch_spin_project<float>(const float2 *, float2 *, long, int, const double *, hipStream_t);
+template void launch_cubic_project<double>(const double2 *, double2 *, long, int, int, int, const CubicRotations &,
+                                           hipStream_t);
+template void launch_cubic_project<float>(const float2 *, float2 *, long, int, int, int, const CubicRotations &,
+                                          hipStream_t);
 
 }  // namespace bbc
