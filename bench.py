@@ -290,7 +290,7 @@ def postproc(bbc, torch, np, steps):
         "spin_project_J0": (lambda: ctx.spin_project(C, W0, out=out0), T * n_ch * V * (16 + 1) * cs),
         "spin_project_src_J1M0": (lambda: ctx.spin_project(C, W1, out=out1), T * n_ch * V * (16 + 4) * cs),
         "cubic_project_A1": (lambda: ctx.cubic_project(out1, out=outc), 2 * T * n_ch * V * 4 * cs),
-        "central_potential": (lambda: [ctx.central_potential(R[m], 0.5, out=Vp[m]) for m in range(n_ch)],
+        "central_potential": (lambda: ctx.central_potential(R, 0.5, out=Vp),
                               n_ch * (T + T - 2) * V * cs),
     }
     res = {}

@@ -236,13 +236,14 @@ bbc_status bbc_cubic_project(bbc_context *ctx, const int32_t lattice[3], bbc_pre
  * bbc_central_potential: leading-order central potential of the HAL QCD method
  *   (Sec. 2), V(r, t) = (lap R(r, t) / (2 mu) - dR/dt) / R(r, t), with the six-point
  *   periodic lattice Laplacian and the symmetric difference (R(t+1) - R(t-1)) / 2,
- *   for the n_t - 2 inner slices of n_t consecutive slices R[t][z][y][x] (complex
- *   FP64; e.g. a spin-projected C with the e^{(m1+m2)(t-t0)} normalisation).
- *   inv_2mu = 1 / (2 mu), mu the reduced mass in lattice units.  V_out:
- *   [n_t - 2][z][y][x] complex FP64.  Sites where R = 0 give non-finite values.
+ *   for the n_t - 2 inner slices of each of n_fields independent sequences of n_t
+ *   consecutive slices, R[f][t][z][y][x] (complex FP64; e.g. a spin-projected C
+ *   per channel with the e^{(m1+m2)(t-t0)} normalisation).  inv_2mu = 1 / (2 mu),
+ *   mu the reduced mass in lattice units.  V_out: [f][n_t - 2][z][y][x] complex
+ *   FP64.  Sites where R = 0 give non-finite values.
  */
-bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int n_t, const void *R, double inv_2mu,
-                                 void *V_out, void *stream);
+bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int n_fields, int n_t, const void *R,
+                                 double inv_2mu, void *V_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -88,7 +88,7 @@ def load():
     lib.bbc_job_forget.argtypes = [P, U64]
     lib.bbc_spin_project.argtypes = [P, P, I, I, P, I, P, P, P]
     lib.bbc_cubic_project.argtypes = [P, P, I, I, I, P, I, P, P]
-    lib.bbc_central_potential.argtypes = [P, P, I, P, ctypes.c_double, P, P]
+    lib.bbc_central_potential.argtypes = [P, P, I, I, P, ctypes.c_double, P, P]
     for f in ("bbc_spin_project", "bbc_cubic_project", "bbc_central_potential", "bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
               "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
               "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit",
@@ -369,18 +369,20 @@ class Context:
         return out
 
     def central_potential(self, R, inv_2mu, out=None, stream=None):
-        """V(r, t) for the inner slices of R [n_t, Lz, Ly, Lx] complex128 on the device."""
+        """V(r, t) for the inner slices of R [..., n_t, Lz, Ly, Lx] complex128 on the device
+        (leading dimensions: independent sequences, e.g. channels)."""
         import torch
-        if not R.is_cuda or R.dtype != torch.complex128 or R.dim() != 4:
-            raise BBCError("R must be a [n_t, Lz, Ly, Lx] complex128 device tensor")
+        if not R.is_cuda or R.dtype != torch.complex128 or R.dim() < 4:
+            raise BBCError("R must be a [..., n_t, Lz, Ly, Lx] complex128 device tensor")
         R = R.contiguous()
-        n_t, Lz, Ly, Lx = R.shape
+        n_t, Lz, Ly, Lx = R.shape[-4:]
+        n_fields = R.numel() // (n_t * Lz * Ly * Lx) if R.numel() else 0
         lat, _ = _i32([Lx, Ly, Lz])
         if out is None:
-            out = torch.empty((max(n_t - 2, 0), Lz, Ly, Lx), dtype=R.dtype, device=R.device)
+            out = torch.empty(R.shape[:-4] + (max(n_t - 2, 0), Lz, Ly, Lx), dtype=R.dtype, device=R.device)
         if stream is None:
             stream = torch.cuda.current_stream(R.device)
-        _check(self._lib.bbc_central_potential(self._ptr, lat, n_t, ctypes.c_void_p(R.data_ptr()),
+        _check(self._lib.bbc_central_potential(self._ptr, lat, n_fields, n_t, ctypes.c_void_p(R.data_ptr()),
                                                float(inv_2mu), ctypes.c_void_p(out.data_ptr()),
                                                ctypes.c_void_p(stream.cuda_stream)))
         return out

@@ -1162,27 +1162,6 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
-// The 24 proper rotations of the cube as signed permutations of (x, y, z).
-bbc::CubicRotations cubic_rotations() {
-    bbc::CubicRotations R{};
-    int k = 0;
-    int p[3] = {0, 1, 2};
-    do {
-        // parity of the permutation: number of inversions
-        int inv = (p[0] > p[1]) + (p[0] > p[2]) + (p[1] > p[2]);
-        for (int sgn = 0; sgn < 8; ++sgn) {
-            int s[3] = {(sgn & 1) ? -1 : 1, (sgn & 2) ? -1 : 1, (sgn & 4) ? -1 : 1};
-            int det = ((inv & 1) ? -1 : 1) * s[0] * s[1] * s[2];
-            if (det != 1) continue;
-            for (int d = 0; d < 3; ++d) {
-                R.perm[k][d] = (int8_t)p[d];
-                R.sign[k][d] = (int8_t)s[d];
-            }
-            ++k;
-        }
-    } while (std::next_permutation(p, p + 3));
-    return R;
-}
 }  // namespace
 
 extern "C" {
@@ -1233,32 +1212,33 @@ bbc_status bbc_cubic_project(bbc_context *ctx, const int32_t lattice[3], bbc_pre
     std::lock_guard<std::mutex> lock(ctx->mu);
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    const bbc::CubicRotations rot = cubic_rotations();
     const int cmp = mode == BBC_CUBIC_A1_COMPLEMENT;
     if (prec == BBC_F64)
-        bbc::launch_cubic_project<double>((const double2 *)in, (double2 *)out, n_fields, lattice[0], n_comp, cmp, rot,
-                                          st);
+        bbc::launch_cubic_project<double>((const double2 *)in, (double2 *)out, n_fields, lattice[0], n_comp, cmp, st);
     else
-        bbc::launch_cubic_project<float>((const float2 *)in, (float2 *)out, n_fields, lattice[0], n_comp, cmp, rot,
-                                         st);
+        bbc::launch_cubic_project<float>((const float2 *)in, (float2 *)out, n_fields, lattice[0], n_comp, cmp, st);
     HIP_TRY(hipGetLastError());
     return BBC_OK;
 }
 
-bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int n_t, const void *R, double inv_2mu,
-                                 void *V_out, void *stream) {
+bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int n_fields, int n_t, const void *R,
+                                 double inv_2mu, void *V_out, void *stream) {
     if (!ctx) return fail(BBC_EINVAL, "NULL context");
     long V;
     bbc_status s = check_extents(lattice, &V);
     if (s) return s;
+    if (n_fields < 0) return fail(BBC_EINVAL, "n_fields >= 0");
     if (n_t < 3) return fail(BBC_EINVAL, "the potential needs n_t >= 3 consecutive slices");
+    if (n_fields == 0) return BBC_OK;
     if (!R || !V_out) return fail(BBC_EINVAL, "NULL buffer");
     if (is_host_pointer(R) || is_host_pointer(V_out)) return fail(BBC_EINVAL, "R and V must be device memory");
-    if (overlap(R, (size_t)n_t * V * 16, V_out, (size_t)(n_t - 2) * V * 16)) return fail(BBC_EINVAL, "R and V overlap");
+    if (overlap(R, (size_t)n_fields * n_t * V * 16, V_out, (size_t)n_fields * (n_t - 2) * V * 16))
+        return fail(BBC_EINVAL, "R and V overlap");
     std::lock_guard<std::mutex> lock(ctx->mu);
     HIP_TRY(hipSetDevice(ctx->device));
     const int L[3] = {lattice[0], lattice[1], lattice[2]};
-    bbc::launch_central_potential((const double2 *)R, (double2 *)V_out, L, n_t, inv_2mu, (hipStream_t)stream);
+    bbc::launch_central_potential((const double2 *)R, (double2 *)V_out, L, n_fields, n_t, inv_2mu,
+                                  (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return BBC_OK;
 }

@@ -800,7 +800,7 @@ void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::typ
 // on the output field, bound by HBM.
 // ----------------------------------------------------------------------------
 // Spin projection: out[f][r][m0 + m] = sum_s W.w[m][s] in[f][r][s], m < W.n (<= 4
-// outputs per launch; the weights travel in the kernel arguments).
+// outputs per launch; the weights travel in the kernel arguments).  One thread per site.
 template <typename T>
 __global__ __launch_bounds__(256) void k_spin_project(const typename cplx_t<T>::type *__restrict__ in,
                                                       typename cplx_t<T>::type *__restrict__ out, long nsite,
@@ -825,12 +825,62 @@ __global__ __launch_bounds__(256) void k_spin_project(const typename cplx_t<T>::
     for (int m = 0; m < W.n; ++m) q[m] = T2{T(acc[m].x), T(acc[m].y)};
 }
 
+// The 24 proper rotations of the cube as signed permutations of (x, y, z):
+// r'_d = s[d] * r_{p[d]}, enumerated at compile time (permutation parity times
+// the product of the signs must be +1).
+struct CubeRot {
+    int p[3], s[3];
+};
+struct CubeRotTable {
+    CubeRot r[24];
+};
+constexpr CubeRotTable make_cube_rotations() {
+    CubeRotTable t{};
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int k = 0;
+    for (int i = 0; i < 6; ++i) {
+        const int inv = (perms[i][0] > perms[i][1]) + (perms[i][0] > perms[i][2]) + (perms[i][1] > perms[i][2]);
+        for (int sg = 0; sg < 8; ++sg) {
+            const int s0 = (sg & 1) ? -1 : 1, s1 = (sg & 2) ? -1 : 1, s2 = (sg & 4) ? -1 : 1;
+            if (((inv & 1) ? -1 : 1) * s0 * s1 * s2 != 1) continue;
+            t.r[k].p[0] = perms[i][0]; t.r[k].p[1] = perms[i][1]; t.r[k].p[2] = perms[i][2];
+            t.r[k].s[0] = s0; t.r[k].s[1] = s1; t.r[k].s[2] = s2;
+            ++k;
+        }
+    }
+    return t;
+}
+constexpr CubeRotTable kCubeRot = make_cube_rotations();
+
+// Sum over the 24 rotations of v(R r): r and -r (mod L) per axis are formed once.
+template <typename Load>
+__device__ __forceinline__ double2 cube_sum(const int r[3], int L, Load load) {
+    int pos[3], neg[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pos[d] = r[d];
+        neg[d] = r[d] == 0 ? 0 : L - r[d];
+    }
+    double ax = 0, ay = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        const CubeRot &R = kCubeRot.r[k];
+        const int x = R.s[0] > 0 ? pos[R.p[0]] : neg[R.p[0]];
+        const int y = R.s[1] > 0 ? pos[R.p[1]] : neg[R.p[1]];
+        const int z = R.s[2] > 0 ? pos[R.p[2]] : neg[R.p[2]];
+        const auto v = load((z * L + y) * L + x);
+        ax += v.x;
+        ay += v.y;
+    }
+    return double2{ax, ay};
+}
+
 // A1+ projection over the 24 proper rotations of the cube: thread = (field,
-// site, component); rotation R maps (x, y, z) to (s0 r_p0, s1 r_p1, s2 r_p2) mod L.
+// site, component), the rotated values gathered from global memory (L2).
 template <typename T>
 __global__ __launch_bounds__(256) void k_cubic_project(const typename cplx_t<T>::type *__restrict__ in,
                                                        typename cplx_t<T>::type *__restrict__ out, long n_fields,
-                                                       int L, int n_comp, int complement, CubicRotations rot) {
+                                                       int L, int n_comp, int complement) {
     using T2 = typename cplx_t<T>::type;
     const long V = (long)L * L * L;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -838,41 +888,72 @@ __global__ __launch_bounds__(256) void k_cubic_project(const typename cplx_t<T>:
     const int c = (int)(i % n_comp);
     const long site = (i / n_comp) % V;
     const long f = i / (n_comp * V);
-    const int r[3] = {(int)(site % L), (int)((site / L) % L), (int)(site / ((long)L * L))};
+    const int si = (int)site, r[3] = {si % L, (si / L) % L, si / (L * L)};
     const T2 *src = in + f * V * n_comp + c;
-    double ax = 0, ay = 0;
-    for (int k = 0; k < 24; ++k) {
-        int rr[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int v = r[rot.perm[k][d]];
-            rr[d] = rot.sign[k][d] > 0 ? v : (v == 0 ? 0 : L - v);
-        }
-        const T2 v = src[(((long)rr[2] * L + rr[1]) * L + rr[0]) * n_comp];
-        ax += v.x;
-        ay += v.y;
-    }
-    ax *= 1.0 / 24.0;
-    ay *= 1.0 / 24.0;
+    double2 a = cube_sum(r, L, [&](int s) { return src[(long)s * n_comp]; });
+    a.x *= 1.0 / 24.0;
+    a.y *= 1.0 / 24.0;
     if (complement) {
         const T2 v = src[site * n_comp];
-        ax = v.x - ax;
-        ay = v.y - ay;
+        a.x = v.x - a.x;
+        a.y = v.y - a.y;
     }
-    out[i] = T2{T(ax), T(ay)};
+    out[i] = T2{T(a.x), T(a.y)};
 }
 
-// Central potential at slice t of n_t consecutive slices (t = 1 .. n_t - 2):
+// The same projection with one component of one field staged whole in LDS
+// (lattices with L^3 complex values <= 64 KB): one workgroup per (field,
+// component), placed XCD-aware so that the components of a field share an L2;
+// the 24 rotated reads per output come from LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cubic_project_lds(const typename cplx_t<T>::type *__restrict__ in,
+                                                           typename cplx_t<T>::type *__restrict__ out, long n_fields,
+                                                           int L, int n_comp, int complement) {
+    using T2 = typename cplx_t<T>::type;
+    extern __shared__ unsigned char lds_raw[];
+    T2 *buf = reinterpret_cast<T2 *>(lds_raw);
+    const long V = (long)L * L * L;
+    const long nwg = n_fields * n_comp;
+    const long P8 = (nwg + 7) / 8;
+    const long id = (blockIdx.x & 7) * P8 + (blockIdx.x >> 3);
+    if (id >= nwg) return;
+    const long f = id / n_comp;
+    const int c = (int)(id - f * n_comp);
+    const T2 *src = in + f * V * n_comp + c;
+    const int Vi = (int)V;
+    for (int s = threadIdx.x; s < Vi; s += 256) buf[s] = src[(long)s * n_comp];
+    __syncthreads();
+    T2 *dst = out + f * V * n_comp + c;
+    for (int s = threadIdx.x; s < Vi; s += 256) {
+        const int r[3] = {s % L, (s / L) % L, s / (L * L)};
+        double2 a = cube_sum(r, L, [&](int q) { return buf[q]; });
+        a.x *= 1.0 / 24.0;
+        a.y *= 1.0 / 24.0;
+        if (complement) {
+            const T2 v = buf[s];
+            a.x = v.x - a.x;
+            a.y = v.y - a.y;
+        }
+        dst[(long)s * n_comp] = T2{T(a.x), T(a.y)};
+    }
+}
+
+// Central potential at slice t of n_t consecutive slices (t = 1 .. n_t - 2) of
+// each of n_fields independent sequences R[f][t][site]:
 //   V = (lap R(t) * inv_2mu - (R(t+1) - R(t-1)) / 2) / R(t), six-point periodic Laplacian.
 __global__ __launch_bounds__(256) void k_central_potential(const double2 *__restrict__ R, double2 *__restrict__ Vout,
-                                                           int Lx, int Ly, int Lz, int n_t, double inv_2mu) {
+                                                           int Lx, int Ly, int Lz, long n_fields, int n_t,
+                                                           double inv_2mu) {
     const long V = (long)Lx * Ly * Lz;
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)(n_t - 2) * V) return;
+    if (i >= n_fields * (n_t - 2) * V) return;
     const long site = i % V;
-    const int t = (int)(i / V) + 1;
+    const long ft = i / V;                         // f * (n_t - 2) + (t - 1)
+    const long f = ft / (n_t - 2);
+    const int t = (int)(ft - f * (n_t - 2)) + 1;
     const int x = (int)(site % Lx), y = (int)((site / Lx) % Ly), z = (int)(site / ((long)Lx * Ly));
-    const double2 *Rt = R + (long)t * V;
+    const double2 *Rf = R + f * n_t * V;
+    const double2 *Rt = Rf + (long)t * V;
     auto at = [&](int xx, int yy, int zz) { return Rt[((long)zz * Ly + yy) * Lx + xx]; };
     const double2 c = Rt[site];
     const double2 n[6] = {at((x + 1) % Lx, y, z), at((x + Lx - 1) % Lx, y, z), at(x, (y + 1) % Ly, z),
@@ -880,7 +961,7 @@ __global__ __launch_bounds__(256) void k_central_potential(const double2 *__rest
     double lx = -6.0 * c.x, ly = -6.0 * c.y;
 #pragma unroll
     for (int k = 0; k < 6; ++k) { lx += n[k].x; ly += n[k].y; }
-    const double2 up = R[(long)(t + 1) * V + site], dn = R[(long)(t - 1) * V + site];
+    const double2 up = Rf[(long)(t + 1) * V + site], dn = Rf[(long)(t - 1) * V + site];
     const double nx = lx * inv_2mu - 0.5 * (up.x - dn.x);
     const double ny = ly * inv_2mu - 0.5 * (up.y - dn.y);
     const double den = c.x * c.x + c.y * c.y;     // (nx + i ny) / (c.x + i c.y)
@@ -902,17 +983,25 @@ void launch_spin_project(const typename cplx_t<T>::type *in, typename cplx_t<T>:
 
 template <typename T>
 void launch_cubic_project(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long n_fields, int L,
-                          int n_comp, int complement, const CubicRotations &rot, hipStream_t st) {
-    const long n = n_fields * (long)L * L * L * n_comp;
+                          int n_comp, int complement, hipStream_t st) {
+    using T2 = typename cplx_t<T>::type;
+    const long V = (long)L * L * L;
+    if (V * (long)sizeof(T2) <= 65536) {
+        const long nwg = n_fields * n_comp;
+        hipLaunchKernelGGL((k_cubic_project_lds<T>), dim3((unsigned)(8 * ((nwg + 7) / 8))), dim3(256),
+                           V * sizeof(T2), st, in, out, n_fields, L, n_comp, complement);
+        return;
+    }
+    const long n = n_fields * V * n_comp;
     hipLaunchKernelGGL((k_cubic_project<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n_fields,
-                       L, n_comp, complement, rot);
+                       L, n_comp, complement);
 }
 
-void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], int n_t, double inv_2mu,
-                              hipStream_t st) {
-    const long n = (long)(n_t - 2) * L[0] * L[1] * L[2];
+void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], long n_fields, int n_t,
+                              double inv_2mu, hipStream_t st) {
+    const long n = n_fields * (n_t - 2) * L[0] * L[1] * L[2];
     hipLaunchKernelGGL(k_central_potential, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, Vout, L[0], L[1],
-                       L[2], n_t, inv_2mu);
+                       L[2], n_fields, n_t, inv_2mu);
 }
 
 // explicit instantiations
@@ -941,9 +1030,7 @@ template void launch_finalize<float>(const float2 *, float2 *, int, int, const d
 
 template void launch_spin_project<double>(const double2 *, double2 *, long, int, const double *, hipStream_t);
 template void launch_spin_project<float>(const float2 *, float2 *, long, int, const double *, hipStream_t);
-template void launch_cubic_project<double>(const double2 *, double2 *, long, int, int, int, const CubicRotations &,
-                                           hipStream_t);
-template void launch_cubic_project<float>(const float2 *, float2 *, long, int, int, int, const CubicRotations &,
-                                          hipStream_t);
+template void launch_cubic_project<double>(const double2 *, double2 *, long, int, int, int, hipStream_t);
+template void launch_cubic_project<float>(const float2 *, float2 *, long, int, int, int, hipStream_t);
 
 }  // namespace bbc

@@ -84,17 +84,13 @@ struct SpinWeights4 {            // up to 4 output combinations of the 16 spin v
     double2 w[4][16];
     int n;
 };
-struct CubicRotations {          // the 24 proper rotations: r'_d = sign[k][d] * r_{perm[k][d]} (mod L)
-    int8_t perm[24][3];
-    int8_t sign[24][3];
-};
 template <typename T>
 void launch_spin_project(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long nsite, int n_out,
                          const double *W, hipStream_t st);
 template <typename T>
 void launch_cubic_project(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long n_fields, int L,
-                          int n_comp, int complement, const CubicRotations &rot, hipStream_t st);
-void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], int n_t, double inv_2mu,
-                              hipStream_t st);
+                          int n_comp, int complement, hipStream_t st);
+void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], long n_fields, int n_t,
+                              double inv_2mu, hipStream_t st);
 
 }  // namespace bbc

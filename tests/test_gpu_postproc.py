@@ -63,8 +63,10 @@ def test_spin_project_matches_oracle(ctx, dtype, lat):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-@pytest.mark.parametrize("L,ncomp", [(4, 16), (5, 3), (6, 1), (8, 4)])
+@pytest.mark.parametrize("L,ncomp", [(4, 16), (5, 3), (6, 1), (8, 4), (17, 2), (21, 1)])
 def test_cubic_project_matches_oracle(ctx, dtype, L, ncomp):
+    # L^3 values of one component up to 64 KB go through LDS, larger ones are
+    # gathered from global memory (17^3 FP64, 21^3 both forms)
     F = rand_field((2, L, L, L, ncomp), 31 + L)
     dF = torch.from_numpy(F).to("cuda:0", dtype)
     Fin = dF.cpu().numpy().astype(np.complex128)
@@ -78,14 +80,15 @@ def test_cubic_project_matches_oracle(ctx, dtype, L, ncomp):
 @pytest.mark.parametrize("lat", [(4, 4, 4), (6, 5, 3)])
 def test_central_potential_matches_oracle(ctx, lat):
     Lx, Ly, Lz = lat
-    n_t = 6
-    R = rand_field((n_t, Lz, Ly, Lx), 41) + 3.0          # keep |R| away from 0
+    n_f, n_t = 3, 6
+    R = rand_field((n_f, n_t, Lz, Ly, Lx), 41) + 3.0      # keep |R| away from 0
     dR = torch.from_numpy(R).to("cuda:0")
     got = ctx.central_potential(dR, 0.73).cpu().numpy()
-    assert got.shape == (n_t - 2, Lz, Ly, Lx)
-    for t in range(1, n_t - 1):
-        ref = pp.central_potential(R[t - 1], R[t], R[t + 1], 0.73)
-        assert np.abs(got[t - 1] - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert got.shape == (n_f, n_t - 2, Lz, Ly, Lx)
+    for f in range(n_f):
+        for t in range(1, n_t - 1):
+            ref = pp.central_potential(R[f, t - 1], R[f, t], R[f, t + 1], 0.73)
+            assert np.abs(got[f, t - 1] - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
 def test_correlate_then_project_identical_source(ctx):
