@@ -71,6 +71,18 @@ typedef struct bbc_context bbc_context;
 int bbc_num_channels(void);          /* 52 */
 int bbc_num_channels_all(void);      /* 56 */
 
+/* Other charge states (Sec. 4 notes that the extension is direct): any
+   quadruple of the octet fields B1 B2 > B3 B4 whose sink and source hold the
+   same numbers of u, d and s quarks is a channel too.  Baryon indices 0..7 name
+   the fields p, n, S+, S-, X0, X-, L, S0 (bbc_baryon_name); bbc_channel_id
+   returns the index of a quadruple in the list above when it is listed, else
+   56 + ((b1 * 8 + b2) * 8 + b3) * 8 + b4, or BBC_EINVAL if an index is out of
+   range or the quark content differs.  Every call taking a channel index
+   accepts these ids. */
+int bbc_num_baryons(void);           /* 8 */
+const char *bbc_baryon_name(int b);  /* NULL for an invalid index */
+int bbc_channel_id(int b1, int b2, int b3, int b4);
+
 /* Channel name "B1 B2 > B3 B4" with baryon names p n L S+ S0 S- X0 X-
    (L = Lambda, S = Sigma, X = Xi).  Returns NULL for an invalid index. */
 const char *bbc_channel_name(int channel);

@@ -14,6 +14,7 @@ import ctypes
 import os
 
 __all__ = ["BBCError", "F64", "F32", "UPPER", "LOWER", "STAGES", "CUBIC_A1", "CUBIC_A1_COMPLEMENT",
+           "baryon_names", "channel_id",
            "Context", "library_path", "load",
            "num_channels", "num_channels_all", "channel_name", "channel_content", "source_terms",
            "diagram_table", "plan_stats", "footprint", "EXPORTED_SYMBOLS"]
@@ -32,6 +33,7 @@ EXPORTED_SYMBOLS = [
     "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
     "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
     "bbc_spin_project", "bbc_cubic_project", "bbc_central_potential",
+    "bbc_num_baryons", "bbc_baryon_name", "bbc_channel_id",
 ]
 CUBIC_A1, CUBIC_A1_COMPLEMENT = 0, 1
 JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
@@ -61,6 +63,11 @@ def load():
     lib = ctypes.CDLL(_LIB_PATH)
     I, P, I64, U64 = ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
     lib.bbc_num_channels.restype = I
+    lib.bbc_num_baryons.restype = I
+    lib.bbc_baryon_name.argtypes = [I]
+    lib.bbc_baryon_name.restype = ctypes.c_char_p
+    lib.bbc_channel_id.argtypes = [I, I, I, I]
+    lib.bbc_channel_id.restype = I
     lib.bbc_num_channels_all.restype = I
     lib.bbc_channel_name.argtypes = [I]
     lib.bbc_channel_name.restype = ctypes.c_char_p
@@ -142,6 +149,23 @@ def diagram_table(c: int, term3: int, term4: int):
     n = ctypes.c_int()
     _check(load().bbc_diagram_table(c, term3, term4, 64, ctypes.byref(n), K, sg))
     return [(K[i], sg[i]) for i in range(n.value)]
+
+
+def baryon_names():
+    """The octet fields that name channels, in index order (p n S+ S- X0 X- L S0)."""
+    lib = load()
+    return [lib.bbc_baryon_name(b).decode() for b in range(lib.bbc_num_baryons())]
+
+
+def channel_id(b1, b2, b3, b4):
+    """Channel index of the quadruple B1 B2 > B3 B4 (names or indices); other charge
+    states than the 52 listed channels get extended ids."""
+    names = baryon_names()
+    idx = [names.index(b) if isinstance(b, str) else int(b) for b in (b1, b2, b3, b4)]
+    c = load().bbc_channel_id(*idx)
+    if c < 0:
+        _check(c)
+    return c
 
 
 def plan_stats(channels):

@@ -759,15 +759,31 @@ int bbc_num_channels_all(void) { return bbc::kNumChannelsAll; }
 const char *bbc_channel_name(int channel) {
     static std::vector<std::string> names = [] {
         std::vector<std::string> v;
-        for (int c = 0; c < bbc::kNumChannelsAll; ++c) v.push_back(bbc::channel_name(c));
+        for (int c = 0; c < bbc::kNumChannelIds; ++c) v.push_back(bbc::channel_name(c));
         return v;
     }();
-    if (channel < 0 || channel >= bbc::kNumChannelsAll) return nullptr;
+    if (!bbc::channel_valid(channel)) return nullptr;
     return names[channel].c_str();
 }
 
+int bbc_num_baryons(void) { return bbc::kNumBaryons; }
+
+const char *bbc_baryon_name(int b) {
+    if (b < 0 || b >= bbc::kNumBaryons) return nullptr;
+    return bbc::baryon(b).name;
+}
+
+int bbc_channel_id(int b1, int b2, int b3, int b4) {
+    const int b[4] = {b1, b2, b3, b4};
+    for (int i = 0; i < 4; ++i)
+        if (b[i] < 0 || b[i] >= bbc::kNumBaryons) return fail(BBC_EINVAL, "baryon index out of range");
+    const int id = bbc::channel_id(b);
+    if (!bbc::channel_valid(id)) return fail(BBC_EINVAL, "the sink and source differ in quark content");
+    return id;
+}
+
 bbc_status bbc_channel_content(int channel, int *n_light, int *n_strange) {
-    if (channel < 0 || channel >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    if (!bbc::channel_valid(channel)) return fail(BBC_EINVAL, "channel index out of range or flavour not conserved");
     if (!n_light || !n_strange) return fail(BBC_EINVAL, "NULL output");
     const int *b = bbc::channel_baryons(channel);
     int ns = 0;
@@ -779,7 +795,7 @@ bbc_status bbc_channel_content(int channel, int *n_light, int *n_strange) {
 }
 
 bbc_status bbc_source_terms(int channel, int *n3, int *n4) {
-    if (channel < 0 || channel >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    if (!bbc::channel_valid(channel)) return fail(BBC_EINVAL, "channel index out of range or flavour not conserved");
     if (!n3 || !n4) return fail(BBC_EINVAL, "NULL output");
     const int *b = bbc::channel_baryons(channel);
     *n3 = bbc::baryon(b[2]).nterm;
@@ -789,7 +805,7 @@ bbc_status bbc_source_terms(int channel, int *n3, int *n4) {
 
 bbc_status bbc_diagram_table(int channel, int term3, int term4, int max_diagrams, int *n_diagrams, int32_t *K,
                              int32_t *sign) {
-    if (channel < 0 || channel >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+    if (!bbc::channel_valid(channel)) return fail(BBC_EINVAL, "channel index out of range or flavour not conserved");
     const int *b = bbc::channel_baryons(channel);
     if (term3 < 0 || term3 >= bbc::baryon(b[2]).nterm || term4 < 0 || term4 >= bbc::baryon(b[3]).nterm)
         return fail(BBC_EINVAL, "source term index out of range");
@@ -884,7 +900,7 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     if (n_t > 0 && (!S_light || !S_strange || !t_list || !C_out)) return fail(BBC_EINVAL, "NULL buffer");
     if (prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
     for (int i = 0; i < n_ch; ++i)
-        if (ch_list[i] < 0 || ch_list[i] >= bbc::kNumChannelsAll)
+        if (!bbc::channel_valid(ch_list[i]))
             return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
     if (n_t == 0) return BBC_OK;
     const bool host_in = is_host_pointer(S_light), host_out = is_host_pointer(C_out);
@@ -1001,7 +1017,7 @@ bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *s
         return fail(BBC_EINVAL, "bad submit arguments");
     if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
     for (int i = 0; i < n_ch; ++i)
-        if (ch_list[i] < 0 || ch_list[i] >= bbc::kNumChannelsAll) return fail(BBC_EINVAL, "channel index out of range");
+        if (!bbc::channel_valid(ch_list[i])) return fail(BBC_EINVAL, "channel index out of range");
     Server &S = ctx->srv;
     std::unique_ptr<Job> j(new Job);
     {

@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <stdexcept>
 
@@ -123,18 +124,49 @@ Intermediate make_intermediate(uint32_t key, const int pf[3], const int y[3], co
 
 }  // namespace
 
+// Baryon quadruples of every channel id: the listed channels, then all quadruples.
+static const std::vector<std::array<int, 4>> &channel_table() {
+    static const std::vector<std::array<int, 4>> t = [] {
+        std::vector<std::array<int, 4>> v;
+        for (int c = 0; c < kNumChannelsAll; ++c)
+            v.push_back({kChannels[c][0], kChannels[c][1], kChannels[c][2], kChannels[c][3]});
+        for (int e = 0; e < kNumChannelIds - kChannelExtBase; ++e)
+            v.push_back({e / 512, (e / 64) % 8, (e / 8) % 8, e % 8});
+        return v;
+    }();
+    return t;
+}
+
 const Baryon &baryon(int id) { return kBaryons[id]; }
-const int *channel_baryons(int ch) { return kChannels[ch]; }
+const int *channel_baryons(int ch) { return channel_table()[ch].data(); }
+
+bool channel_valid(int ch) {
+    if (ch < 0 || ch >= kNumChannelIds) return false;
+    const int *b = channel_baryons(ch);
+    int n[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) {
+        n[kBaryons[b[0]].flav[i]]++; n[kBaryons[b[1]].flav[i]]++;
+        n[kBaryons[b[2]].flav[i]]--; n[kBaryons[b[3]].flav[i]]--;
+    }
+    return n[0] == 0 && n[1] == 0 && n[2] == 0;
+}
+
+int channel_id(const int b[4]) {
+    for (int c = 0; c < kNumChannelsAll; ++c)
+        if (kChannels[c][0] == b[0] && kChannels[c][1] == b[1] && kChannels[c][2] == b[2] && kChannels[c][3] == b[3])
+            return c;
+    return kChannelExtBase + ((b[0] * 8 + b[1]) * 8 + b[2]) * 8 + b[3];
+}
 
 std::string channel_name(int ch) {
-    const int *b = kChannels[ch];
+    const int *b = channel_baryons(ch);
     return std::string(kBaryons[b[0]].name) + " " + kBaryons[b[1]].name + " > " + kBaryons[b[2]].name + " " +
            kBaryons[b[3]].name;
 }
 
 std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *index,
                               std::vector<Intermediate> *inters) {
-    const int *bb = kChannels[ch];
+    const int *bb = channel_baryons(ch);
     const Baryon &B1 = kBaryons[bb[0]], &B2 = kBaryons[bb[1]], &B3 = kBaryons[bb[2]], &B4 = kBaryons[bb[3]];
     int fs[6], fsrc[6], rsrc[6];
     for (int i = 0; i < 3; ++i) {
@@ -340,9 +372,9 @@ Plan build_plan(const std::vector<int> &channels, int spin_offset) {
     P.spin_offset = spin_offset;
     std::map<uint32_t, int> index;
     for (int ch : channels) {
-        if (ch < 0 || ch >= kNumChannelsAll) throw std::invalid_argument("channel index out of range");
+        if (!channel_valid(ch)) throw std::invalid_argument("channel index out of range or flavour not conserved");
         P.ch_begin.push_back((int)P.diags.size());
-        const int *bb = kChannels[ch];
+        const int *bb = channel_baryons(ch);
         for (int t3 = 0; t3 < kBaryons[bb[2]].nterm; ++t3)
             for (int t4 = 0; t4 < kBaryons[bb[3]].nterm; ++t4)
                 for (auto &d : classify(ch, t3, t4, &index, &P.inters)) {

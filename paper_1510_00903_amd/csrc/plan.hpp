@@ -33,10 +33,19 @@ struct Baryon {
 
 constexpr int kNumChannels = 52;
 constexpr int kNumChannelsAll = 56;
+// Other charge states: ids from kChannelExtBase name any quadruple of the 8
+// octet fields, id = kChannelExtBase + ((b1 * 8 + b2) * 8 + b3) * 8 + b4.
+constexpr int kNumBaryons = 8;
+constexpr int kChannelExtBase = kNumChannelsAll;
+constexpr int kNumChannelIds = kChannelExtBase + kNumBaryons * kNumBaryons * kNumBaryons * kNumBaryons;
 
 const Baryon &baryon(int id);
 const int *channel_baryons(int ch);          // 4 baryon ids: sink B1, B2, source B3, B4
 std::string channel_name(int ch);
+// In range, and the sink and source hold the same number of u, d and s quarks.
+bool channel_valid(int ch);
+// Id of a baryon quadruple: its index in the channel list if listed, else the extended id.
+int channel_id(const int b[4]);
 
 // Kinds of what one source baryon leaves at one sink site.
 enum YKind : int { Y_FULL = 0, Y_DD = 1, Y_DDELTA = 2, Y_DIN = 3, Y_DELTAIN = 4 };

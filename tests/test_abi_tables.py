@@ -36,8 +36,11 @@ def test_channel_list_and_content():
     assert bbc.channel_content(1) == (5, 1)
     assert bbc.channel_content(51) == (2, 4)
     assert bbc.source_terms(10) == (3, 3)
-    with pytest.raises(bbc.BBCError):
-        bbc.channel_name(56)
+    # ids from 56 on name other charge states; p p > p n (57) does not conserve flavour
+    assert bbc.channel_name(56) == "p p > p p"
+    for bad in (57, 56 + 8 ** 4, -1):
+        with pytest.raises(bbc.BBCError):
+            bbc.channel_name(bad)
 
 
 def _read_tables():

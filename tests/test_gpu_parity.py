@@ -79,6 +79,41 @@ def test_all_channels_full_field_small(bbc, ctx, lat):
                 assert np.abs(ref).max() < TOL64 * scale
 
 
+OTHER_CHARGE_STATES = [("p", "p", "p", "p"), ("n", "n", "n", "n"), ("p", "n", "n", "p"), ("n", "p", "p", "n"),
+                       ("n", "p", "n", "p"), ("S+", "p", "S+", "p"), ("S-", "n", "S-", "n"),
+                       ("S+", "S+", "S+", "S+"), ("X0", "X0", "X0", "X0"), ("X-", "X0", "X0", "X-"),
+                       ("L", "n", "S0", "n"), ("S-", "p", "L", "n")]
+
+
+@pytest.mark.parametrize("lat", [(3, 3, 3), (4, 2, 3)])
+def test_other_charge_states_full_field(bbc, ctx, lat):
+    """Channels beyond the listed 52 (extended ids), every r, FP64, against the oracle."""
+    Lx, Ly, Lz = lat
+    Sl, Ss = synth.propagators(lat, 1, seed=111)
+    chans = [bbc.channel_id(*q) for q in OTHER_CHARGE_STATES]
+    assert min(chans) >= 56
+    print("case: lattice", lat, "channels", chans, flush=True)
+    out = gpu_correlate(ctx, Sl, Ss, [0], chans)
+    r = wick.all_r(Lx, Ly, Lz)
+    for m, q in enumerate(OTHER_CHARGE_STATES):
+        ref = wick.correlate(Sl[0], Ss[0], q, r)
+        assert normwise(out[0, m].reshape(-1, 16), ref) < TOL64, (lat, q)
+
+
+def test_other_charge_states_isospin_on_gpu_8cubed(bbc, ctx):
+    """At 8^3 the GPU results obey C[pp>pp] = C[nn>nn] = 1/2 sum of the four pn/np
+    channels (I = 1), exactly up to rounding; no oracle involved."""
+    L = 8
+    Sl, Ss = synth.propagators(L, 1, seed=112)
+    qs = [("p", "p", "p", "p"), ("n", "n", "n", "n"), ("p", "n", "p", "n"), ("p", "n", "n", "p"),
+          ("n", "p", "p", "n"), ("n", "p", "n", "p")]
+    out = gpu_correlate(ctx, Sl, Ss, [0], [bbc.channel_id(*q) for q in qs])[0]
+    pp, nn = out[0], out[1]
+    i1 = 0.5 * (out[2] + out[3] + out[4] + out[5])
+    assert normwise(nn, pp) < TOL64
+    assert normwise(i1, pp) < TOL64
+
+
 def test_p_lambda_8cubed_all_t(bbc, ctx):
     """The 8^3 x 8 p-Lambda workload: every r at two slices (O-U), sampled r at every slice (O-W)."""
     L, T = 8, 8
