@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbbcorr.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.cpp", "plan.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "postproc.hip", "api.cpp", "plan.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "plan.hpp")] + [
     os.path.join(ROOT, "include", "bbcorr.h")]
 

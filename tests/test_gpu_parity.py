@@ -165,7 +165,7 @@ def test_errors_are_reported(bbc, ctx):
     dev = torch.device("cuda:0")
     tl, ts = torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
     with pytest.raises(bbc.BBCError):
-        ctx.correlate(tl, ts, [0], [56])
+        ctx.correlate(tl, ts, [0], [57])            # p p > p n: quark content differs
     with pytest.raises(bbc.BBCError):
         ctx.correlate(tl.cpu(), ts, [0], [0])
     bad = torch.zeros((1, 5, 5, 5, 12, 12), dtype=torch.complex128, device=dev)
