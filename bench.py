@@ -92,6 +92,21 @@ def cpu_baseline(Sl, Ss, t_idx, budget_s=20.0):
                       % (t_idx, len(done), [list(p) for p in r_points[:1 + (len(done) - 1) // 13]], el)}
 
 
+def cpu_baseline_unified(Sl, Ss, t_idx):
+    """The FP64 O-U oracle (source weights folded first, X-sum by numpy's FFT) on the
+    full 16^3 field of one channel (p n > p n) at time slice t_idx: a stronger CPU
+    reference than the direct O(V^2) sum (one process, numpy threading as installed)."""
+    from oracle import operators as ops
+    from oracle import unified
+    t0 = time.perf_counter()
+    C = unified.correlate(Sl[t_idx], Ss[t_idx], ops.CHANNELS[0])
+    el = time.perf_counter() - t0
+    n = C.shape[0] * C.shape[1] * C.shape[2]
+    return {"value": n / el, "unit": "site-channels/s", "cores": 1, "kind": "oracle",
+            "sample": "O-U oracle (unified contraction + numpy FFT), full field of channel 0 (p n > p n) "
+                      "on the 16^3 slice t=%d: %d site-channels in %.1f s" % (t_idx, n, el)}
+
+
 def serve_mix(bbc, torch, np, n_jobs=64, n_slots=4, load=0.8):
     """Continuous-batching serving on a Poisson stream of mixed jobs (FP32 form).
 
@@ -329,6 +344,8 @@ def main():
                     choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream", "post-16c32"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each job as a captured HIP graph (stage timings from one extra profiled step)")
     ap.add_argument("--slices", type=int, default=0,
                     help="time only the first N slices of the job (for profiling runs; 0 = all)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -388,18 +405,30 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    if args.graph:
+        ctx.graph_mode(True)
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
     torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read()
+    if not args.graph:
+        ctx.profile(True)
+        ctx.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof_steps = args.steps
+    if args.graph:
+        # stage timings from one more, profiled, eager step (the same kernels)
+        ctx.graph_mode(False)
+        ctx.profile(True)
+        ctx.profile_read()
+        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
+        torch.cuda.synchronize()
+        prof_steps = 1
     prof = ctx.profile_read()
     ctx.profile(False)
     print("bench: timed %d steps in %.3f s" % (args.steps, el), file=sys.stderr, flush=True)
@@ -413,7 +442,7 @@ def main():
     csize = 8 if fp32 else 16
     peak_alu = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     stages = {}
-    n_slices = T * args.steps
+    n_slices = T * prof_steps
     for name, (ms, launches) in prof.items():
         if launches == 0:
             continue                                 # stage without kernels on this path (fused)
@@ -461,10 +490,12 @@ def main():
                    "block_components_per_site": st["components"], "iterations": st["iterations"]},
         "roofline": roof,
         "stages": stages,
+        "hip_graph": bool(args.graph),
     }
     if not args.no_cpu_baseline and L == 16:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(Sl, Ss, 7)
+        res["cpu_baseline_unified"] = cpu_baseline_unified(Sl, Ss, 7)
     ctx.close()
     print(json.dumps(res), flush=True)
 

@@ -210,6 +210,19 @@ bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job);
  * slice; it does not change results.
  */
 #define BBC_NUM_STAGES 7
+
+/*
+ * Graph mode.  With it on, a bbc_correlate call whose propagators, output and
+ * scale are device memory is captured once (all its time slices, on an
+ * internal stream) into a HIP graph, cached under the call's arguments
+ * (buffers, lattice, channels, slices, t0, precision), and replayed on the
+ * caller's stream; later calls with the same arguments replay it and read the
+ * buffers' current contents.  Host-memory calls and profiled calls run as
+ * ordinary stream-ordered launches.  At most 16 graphs are kept; turning the
+ * mode off (or a workspace reallocation) waits for the device and frees them.
+ * The captured sequence holds kernel launches only.
+ */
+bbc_status bbc_graph_mode(bbc_context *ctx, int enable);
 bbc_status bbc_profile_enable(bbc_context *ctx, int enable);
 bbc_status bbc_profile_read(bbc_context *ctx, int n_stages, double *ms, int64_t *launches);
 

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
     "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
     "bbc_spin_project", "bbc_cubic_project", "bbc_central_potential",
-    "bbc_num_baryons", "bbc_baryon_name", "bbc_channel_id",
+    "bbc_num_baryons", "bbc_baryon_name", "bbc_channel_id", "bbc_graph_mode",
 ]
 CUBIC_A1, CUBIC_A1_COMPLEMENT = 0, 1
 JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
@@ -83,6 +83,8 @@ def load():
     lib.bbc_correlate.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
     lib.bbc_profile_enable.argtypes = [P, I]
     lib.bbc_profile_read.argtypes = [P, I, P, P]
+    lib.bbc_graph_mode.argtypes = [P, I]
+    lib.bbc_graph_mode.restype = I
     lib.bbc_server_start.argtypes = [P, I]
     lib.bbc_server_stop.argtypes = [P]
     lib.bbc_prop_upload.argtypes = [P, P, I, P, P, I, P]
@@ -207,6 +209,10 @@ class Context:
     def profile(self, enable: bool = True):
         """Record HIP events around every kernel stage of later correlate calls."""
         _check(self._lib.bbc_profile_enable(self._ptr, 1 if enable else 0))
+
+    def graph_mode(self, enable: bool = True):
+        """Capture device-resident correlate calls into cached HIP graphs and replay them."""
+        _check(self._lib.bbc_graph_mode(self._ptr, 1 if enable else 0))
 
     def profile_read(self):
         """{stage: (milliseconds, launches)} accumulated since the last read."""

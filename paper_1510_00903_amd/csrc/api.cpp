@@ -257,6 +257,15 @@ struct bbc_context {
     std::mutex qmu;                                   // guards groups and plans for the server thread
     hipStream_t cin = nullptr, cout = nullptr;        // copy streams of the host-streamed direct path
     hipEvent_t sev[8] = {};
+    // graph mode: the kernel sequence of a device-resident job captured once per
+    // argument tuple on gs, then replayed on the caller's stream
+    bool graph_mode = false;
+    hipStream_t gs = nullptr;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    void clear_graphs() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
     // profiling: event pairs recorded around kernel stages
     bool prof = false;
     struct Rec { int stage, nk; hipEvent_t a, b; };
@@ -274,6 +283,8 @@ struct bbc_context {
         for (auto &kv : groups) (void)hipFree(kv.second);
         if (cin) (void)hipStreamDestroy(cin);
         if (cout) (void)hipStreamDestroy(cout);
+        clear_graphs();
+        if (gs) (void)hipStreamDestroy(gs);
         for (auto e : sev) if (e) (void)hipEventDestroy(e);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
@@ -512,6 +523,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
     if (ctx->ws_bytes < need) {
         HIP_TRY(hipDeviceSynchronize());
+        ctx->clear_graphs();
         if (ctx->ws) { HIP_TRY(hipFree(ctx->ws)); ctx->ws = nullptr; ctx->ws_bytes = 0; }
         hipError_t e = hipMalloc(&ctx->ws, need);
         if (e != hipSuccess) { ctx->ws = nullptr; return fail(BBC_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e)); }
@@ -519,6 +531,8 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     }
     if (energy) {
         if (ctx->energy_cap < n_ch) {
+            HIP_TRY(hipDeviceSynchronize());
+            ctx->clear_graphs();
             if (ctx->d_energy) HIP_TRY(hipFree(ctx->d_energy));
             ctx->d_energy = nullptr;
             HIP_TRY(hipMalloc((void **)&ctx->d_energy, sizeof(double) * n_ch));
@@ -529,6 +543,38 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     bbc_status s;
     const MomGroups mg = get_groups<T>(ctx, L, &s);
     if (!mg.pos) return s;
+    if (ctx->graph_mode && !host_in && !host_out && !ctx->prof && n_t > 0) {
+        // every value the captured kernels depend on
+        std::vector<int64_t> key = {(int64_t)(intptr_t)dp, L[0], L[1], L[2], (int64_t)sizeof(T),
+                                    (int64_t)(intptr_t)S_light, (int64_t)(intptr_t)S_strange, n_t, t0, n_ch,
+                                    (int64_t)(intptr_t)(energy ? ctx->d_energy : nullptr), (int64_t)(intptr_t)C_out,
+                                    (int64_t)(intptr_t)C_scale, (int64_t)(intptr_t)ctx->ws};
+        for (int n = 0; n < n_t; ++n) key.push_back(t_list[n]);
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            if (!ctx->gs) HIP_TRY(hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking));
+            if (ctx->graphs.size() >= 16) ctx->clear_graphs();
+            HIP_TRY(hipStreamBeginCapture(ctx->gs, hipStreamCaptureModeRelaxed));
+            const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
+            bbc_status es = BBC_OK;
+            for (int n = 0; n < n_t && es == BBC_OK; ++n)
+                es = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, mg, Sl + (size_t)n * V * 144, Ss + (size_t)n * V * 144,
+                                      n_ch, energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0),
+                                      (char *)C_out + (size_t)n * out_slice,
+                                      C_scale ? C_scale + (size_t)n * n_ch : nullptr, ctx->gs, false);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->gs, &g);
+            if (es != BBC_OK) { if (g) (void)hipGraphDestroy(g); return es; }
+            if (e != hipSuccess) return fail(BBC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(BBC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+            it = ctx->graphs.emplace(key, ex).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second, st));
+        return BBC_OK;
+    }
     char *stage_in = (char *)ctx->ws + core, *stage_out = stage_in + in_stage;
     if ((host_in || host_out) && !ctx->cin) {
         HIP_TRY(hipStreamCreateWithFlags(&ctx->cin, hipStreamNonBlocking));
@@ -1125,6 +1171,18 @@ bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job) {
     if (it == S.jobs.end()) return fail(BBC_EINVAL, "unknown job");
     if (it->second->state < JOB_DONE) return fail(BBC_ESTATE, "job not finished");
     S.jobs.erase(it);
+    return BBC_OK;
+}
+
+bbc_status bbc_graph_mode(bbc_context *ctx, int enable) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    ctx->graph_mode = enable != 0;
+    if (!ctx->graph_mode) {
+        HIP_TRY(hipDeviceSynchronize());
+        ctx->clear_graphs();
+    }
     return BBC_OK;
 }
 

@@ -279,6 +279,64 @@ __global__ __launch_bounds__(256) void k_fft(typename cplx_t<T>::type *__restric
     for (int j = 0; j < N; ++j) p[j * stride] = a[j];
 }
 
+// x and y transforms of whole (component, z) planes in LDS (Lx = Ly = N): P
+// planes per workgroup, read and written with coalesced loads, one N-point
+// line per thread and axis, rows padded to N + 1 against bank conflicts.
+// Replaces two of the three axis passes.
+template <typename T, int N, int P>
+__global__ __launch_bounds__(256) void k_fft_xy(typename cplx_t<T>::type *__restrict__ data, long nplanes,
+                                                int sgn) {
+    using T2 = typename cplx_t<T>::type;
+    static_assert(P * N <= 256, "one line per thread");
+    __shared__ T2 buf[P][N][N + 1];
+    __shared__ T2 tw[N];
+    const int t = threadIdx.x;
+    for (int i = t; i < N; i += 256) {
+        double s, c;
+        sincospi(2.0 * i / N, &s, &c);
+        tw[i] = T2{T(c), T(sgn * s)};
+    }
+    const long plane0 = (long)blockIdx.x * P;
+    T2 *base = data + plane0 * N * N;
+    for (int e = t; e < P * N * N; e += 256) {
+        const int p = e / (N * N), rem = e - p * N * N;
+        if (plane0 + p < nplanes) buf[p][rem / N][rem % N] = base[e];
+    }
+    __syncthreads();
+    T2 a[N], b[N];
+    const int p = t / N, l = t % N;
+    const bool line = t < P * N;
+    if (line) {                                    // x line: plane p, row y = l
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = buf[p][l][j];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+        for (int j = 0; j < N; ++j) buf[p][l][j] = a[j];
+    }
+    __syncthreads();
+    if (line) {                                    // y line: plane p, column x = l
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = buf[p][j][l];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+        for (int j = 0; j < N; ++j) buf[p][j][l] = a[j];
+    }
+    __syncthreads();
+    for (int e = t; e < P * N * N; e += 256) {
+        const int pp = e / (N * N), rem = e - pp * N * N;
+        if (plane0 + pp < nplanes) base[e] = buf[pp][rem / N][rem % N];
+    }
+}
+
+template <typename T, int N>
+static void fft_xy(typename cplx_t<T>::type *data, long nplanes, int sgn, hipStream_t st) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int PL = 81920 / (N * (N + 1) * (int)sizeof(T2));     // planes within 80 KB of LDS
+    constexpr int P = PL < 256 / N ? PL : 256 / N;
+    hipLaunchKernelGGL((k_fft_xy<T, N, P>), dim3((unsigned)((nplanes + P - 1) / P)), dim3(256), 0, st, data, nplanes,
+                       sgn);
+}
+
 bool fft_size_supported(int n) {
     switch (n) {
     case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
@@ -299,6 +357,31 @@ static void fft_axis(typename cplx_t<T>::type *data, long ncomp, const int L[3],
 
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sgn, hipStream_t st) {
+    if (L[0] == L[1] && (L[0] == 24 || L[0] == 32)) {   // x and y in one plane pass, then z
+        if (L[0] == 24) fft_xy<T, 24>(data, ncomp * L[2], sgn, st);
+        else fft_xy<T, 32>(data, ncomp * L[2], sgn, st);
+        int n = 1;
+        const int Lz = L[2];
+        if (Lz > 1) {
+            switch (Lz) {
+            case 2: fft_axis<T, 2>(data, ncomp, L, 2, sgn, st); break;
+            case 3: fft_axis<T, 3>(data, ncomp, L, 2, sgn, st); break;
+            case 4: fft_axis<T, 4>(data, ncomp, L, 2, sgn, st); break;
+            case 6: fft_axis<T, 6>(data, ncomp, L, 2, sgn, st); break;
+            case 8: fft_axis<T, 8>(data, ncomp, L, 2, sgn, st); break;
+            case 12: fft_axis<T, 12>(data, ncomp, L, 2, sgn, st); break;
+            case 16: fft_axis<T, 16>(data, ncomp, L, 2, sgn, st); break;
+            case 24: fft_axis<T, 24>(data, ncomp, L, 2, sgn, st); break;
+            case 32: fft_axis<T, 32>(data, ncomp, L, 2, sgn, st); break;
+            case 48: fft_axis<T, 48>(data, ncomp, L, 2, sgn, st); break;
+            case 64: fft_axis<T, 64>(data, ncomp, L, 2, sgn, st); break;
+            case 96: fft_axis<T, 96>(data, ncomp, L, 2, sgn, st); break;
+            default: return -1;
+            }
+            ++n;
+        }
+        return n;
+    }
     int n = 0;
     for (int axis = 0; axis < 3; ++axis) {
         if (L[axis] > 1) ++n;

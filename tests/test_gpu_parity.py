@@ -114,6 +114,29 @@ def test_other_charge_states_isospin_on_gpu_8cubed(bbc, ctx):
     assert normwise(i1, pp) < TOL64
 
 
+@pytest.mark.parametrize("lat", [(32, 32, 2), (24, 24, 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_plane_fft_extents(bbc, ctx, lat, prec):
+    """Lattices whose x and y extents (24, 32) take the plane FFT pass, forward and
+    inverse: sampled r points of two channels against the oracle."""
+    Lx, Ly, Lz = lat
+    dtype = np.complex128 if prec == "f64" else np.complex64
+    Sl, Ss = synth.propagators(lat, 1, seed=113, dtype=dtype)
+    chans = [0, 5]
+    print("case: lattice", lat, prec, flush=True)
+    res = gpu_correlate(ctx, Sl, Ss, [0], chans)
+    out = res[0] * res[1][:, :, None, None, None, None] if prec == "f32" else res
+    rng = np.random.default_rng(114)
+    r = np.concatenate([np.array([[0, 0, 0], [Lx - 1, Ly - 1, Lz - 1], [Lx // 2, 1, 0]]),
+                        np.stack([rng.integers(0, Lx, 13), rng.integers(0, Ly, 13), rng.integers(0, Lz, 13)], 1)])
+    r = r.astype(np.int32)
+    Sl64, Ss64 = Sl.astype(np.complex128), Ss.astype(np.complex128)
+    for m, c in enumerate(chans):
+        ref = wick.correlate(Sl64[0], Ss64[0], ops.CHANNELS[c], r)
+        got = np.stack([out[0, m, rz, ry, rx] for rx, ry, rz in r])
+        assert normwise(got, ref) < (TOL64 if prec == "f64" else 1e-5), (lat, prec, c)
+
+
 def test_p_lambda_8cubed_all_t(bbc, ctx):
     """The 8^3 x 8 p-Lambda workload: every r at two slices (O-U), sampled r at every slice (O-W)."""
     L, T = 8, 8
