@@ -298,9 +298,28 @@ __global__ __launch_bounds__(256) void k_fft_xy(typename cplx_t<T>::type *__rest
     }
     const long plane0 = (long)blockIdx.x * P;
     T2 *base = data + plane0 * N * N;
-    for (int e = t; e < P * N * N; e += 256) {
-        const int p = e / (N * N), rem = e - p * N * N;
-        if (plane0 + p < nplanes) buf[p][rem / N][rem % N] = base[e];
+    const int nvalid = (int)((nplanes - plane0 < P ? nplanes - plane0 : P) * N * N);
+    constexpr int NL = (P * N * N + 255) / 256;    // elements per thread
+    if constexpr (sizeof(T) == 4) {
+        T2 v[NL];                                  // FP32: every load in flight before the LDS stores
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = t + 256 * i;
+            if (e < nvalid) v[i] = base[e];
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = t + 256 * i;
+            if (e < nvalid) {
+                const int p = e / (N * N), rem = e - p * N * N;
+                buf[p][rem / N][rem % N] = v[i];
+            }
+        }
+    } else {                                       // FP64: the register budget goes to the lines
+        for (int e = t; e < nvalid; e += 256) {
+            const int p = e / (N * N), rem = e - p * N * N;
+            buf[p][rem / N][rem % N] = base[e];
+        }
     }
     __syncthreads();
     T2 a[N], b[N];
@@ -322,9 +341,9 @@ __global__ __launch_bounds__(256) void k_fft_xy(typename cplx_t<T>::type *__rest
         for (int j = 0; j < N; ++j) buf[p][j][l] = a[j];
     }
     __syncthreads();
-    for (int e = t; e < P * N * N; e += 256) {
+    for (int e = t; e < nvalid; e += 256) {
         const int pp = e / (N * N), rem = e - pp * N * N;
-        if (plane0 + pp < nplanes) base[e] = buf[pp][rem / N][rem % N];
+        base[e] = buf[pp][rem / N][rem % N];
     }
 }
 
@@ -335,6 +354,108 @@ static void fft_xy(typename cplx_t<T>::type *data, long nplanes, int sgn, hipStr
     constexpr int P = PL < 256 / N ? PL : 256 / N;
     hipLaunchKernelGGL((k_fft_xy<T, N, P>), dim3((unsigned)((nplanes + P - 1) / P)), dim3(256), 0, st, data, nplanes,
                        sgn);
+}
+
+// Long lines (N = N1 * N2) along one axis, without holding a whole line per
+// thread: a tile of W lines adjacent in memory is staged in
+// LDS ([point][line], coalesced loads and stores), then the two-factor form
+//   X[k1 + N1 k2] = sum_j2 w_N2^(j2 k2) w_N^(j2 k1) sum_j1 x[j2 + N2 j1] w_N1^(j1 k1)
+// runs as W*N2 inner N1-point transforms (with the twiddle w_N^(j2 k1)) and
+// W*N1 outer N2-point transforms, each thread holding at most N1 values.
+template <typename T, int N1, int N2, int W>
+__global__ __launch_bounds__(256) void k_fft_lds(typename cplx_t<T>::type *__restrict__ data, long nlines, int Lx,
+                                                 int Ly, int Lz, int axis, int sgn) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int N = N1 * N2;
+    __shared__ T2 buf[N][W + 1];
+    __shared__ T2 tw1[N1], tw2[N2], twN[N];
+    const int t = threadIdx.x;
+    for (int i = t; i < N; i += 256) {
+        double s, c;
+        sincospi(2.0 * i / N, &s, &c);
+        twN[i] = T2{T(c), T(sgn * s)};
+        if (i < N1) { sincospi(2.0 * i / N1, &s, &c); tw1[i] = T2{T(c), T(sgn * s)}; }
+        if (i < N2) { sincospi(2.0 * i / N2, &s, &c); tw2[i] = T2{T(c), T(sgn * s)}; }
+    }
+    __shared__ long lbase[W];                      // first element of each line of the tile, -1 past the end
+    const long V = (long)Lx * Ly * Lz;
+    const long lpc = V / N;                        // lines per component
+    const long l0 = (long)blockIdx.x * W;
+    const long stride = axis == 0 ? 1 : axis == 1 ? Lx : (long)Lx * Ly;
+    if (t < W) {
+        const long l = l0 + t;
+        long b = -1;
+        if (l < nlines) {
+            const long comp = l / lpc, m = l - comp * lpc;
+            long base;
+            if (axis == 0) base = m * Lx;
+            else if (axis == 1) base = (m / Lx) * Lx * Ly + m % Lx;
+            else base = m;
+            b = comp * V + base;
+        }
+        lbase[t] = b;
+    }
+    __syncthreads();
+    for (int e = t; e < N * W; e += 256) {
+        int j, w;
+        if (axis == 0) { w = e / N; j = e - w * N; } else { j = e / W; w = e - j * W; }
+        const long b = lbase[w];
+        if (b >= 0) buf[j][w] = data[b + j * stride];
+    }
+    __syncthreads();
+    for (int u = t; u < W * N2; u += 256) {        // inner transforms over j1, then the twiddle
+        const int w = u % W, j2 = u / W;
+        T2 a[N1], b[N1];
+#pragma unroll
+        for (int j1 = 0; j1 < N1; ++j1) a[j1] = buf[j2 + N2 * j1][w];
+        Stages<T2, N1, 1>::run(a, b, tw1, sgn);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) buf[j2 + N2 * k1][w] = k1 == 0 ? a[0] : cmul(a[k1], twN[(j2 * k1) % N]);
+    }
+    __syncthreads();
+    constexpr int NU = (W * N1 + 255) / 256;       // outer transforms per thread
+    T2 r[NU][N2];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int u = t + 256 * i;
+        if (u < W * N1) {
+            const int w = u % W, k1 = u / W;
+            T2 b[N2];
+#pragma unroll
+            for (int j2 = 0; j2 < N2; ++j2) r[i][j2] = buf[j2 + N2 * k1][w];
+            Stages<T2, N2, 1>::run(r[i], b, tw2, sgn);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int u = t + 256 * i;
+        if (u < W * N1) {
+            const int w = u % W, k1 = u / W;
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) buf[k1 + N1 * k2][w] = r[i][k2];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < N * W; e += 256) {
+        int j, w;
+        if (axis == 0) { w = e / N; j = e - w * N; } else { j = e / W; w = e - j * W; }
+        const long b = lbase[w];
+        if (b >= 0) data[b + j * stride] = buf[j][w];
+    }
+}
+
+template <typename T, int N1, int N2>
+static void fft_axis_lds(typename cplx_t<T>::type *data, long ncomp, const int L[3], int axis, int sgn,
+                         hipStream_t st) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int N = N1 * N2;
+    // tile width: a power of two <= 64 with the tile within 72 KB of LDS
+    constexpr int W = (N * 65 * (int)sizeof(T2) <= 73728) ? 64 : (N * 33 * (int)sizeof(T2) <= 73728) ? 32 : 16;
+    const long V = (long)L[0] * L[1] * L[2];
+    const long nlines = ncomp * (V / N);
+    hipLaunchKernelGGL((k_fft_lds<T, N1, N2, W>), dim3((unsigned)((nlines + W - 1) / W)), dim3(256), 0, st, data,
+                       nlines, L[0], L[1], L[2], axis, sgn);
 }
 
 bool fft_size_supported(int n) {
@@ -353,6 +474,16 @@ static void fft_axis(typename cplx_t<T>::type *data, long ncomp, const int L[3],
     const long nblk = (nlines + 255) / 256;
     hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)nblk), dim3(256), 0, st, data, nlines, L[0], L[1], L[2],
                        axis, sgn);
+}
+
+// 96-point lines: one line per thread in FP32 (fits the registers, most loads in
+// flight); the two-factor LDS form (12 x 8) in FP64, where a 96-point line per
+// thread would spill to scratch.
+template <typename T>
+static void fft_axis96(typename cplx_t<T>::type *data, long ncomp, const int L[3], int axis, int sgn,
+                       hipStream_t st) {
+    if constexpr (sizeof(T) == 8) fft_axis_lds<T, 12, 8>(data, ncomp, L, axis, sgn, st);
+    else fft_axis<T, 96>(data, ncomp, L, axis, sgn, st);
 }
 
 template <typename T>
@@ -375,7 +506,7 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
             case 32: fft_axis<T, 32>(data, ncomp, L, 2, sgn, st); break;
             case 48: fft_axis<T, 48>(data, ncomp, L, 2, sgn, st); break;
             case 64: fft_axis<T, 64>(data, ncomp, L, 2, sgn, st); break;
-            case 96: fft_axis<T, 96>(data, ncomp, L, 2, sgn, st); break;
+            case 96: fft_axis96<T>(data, ncomp, L, 2, sgn, st); break;
             default: return -1;
             }
             ++n;
@@ -398,7 +529,7 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
         case 32: fft_axis<T, 32>(data, ncomp, L, axis, sgn, st); break;
         case 48: fft_axis<T, 48>(data, ncomp, L, axis, sgn, st); break;
         case 64: fft_axis<T, 64>(data, ncomp, L, axis, sgn, st); break;
-        case 96: fft_axis<T, 96>(data, ncomp, L, axis, sgn, st); break;
+        case 96: fft_axis96<T>(data, ncomp, L, axis, sgn, st); break;
         default: return -1;
         }
     }

@@ -137,6 +137,25 @@ def test_plane_fft_extents(bbc, ctx, lat, prec):
         assert normwise(got, ref) < (TOL64 if prec == "f64" else 1e-5), (lat, prec, c)
 
 
+@pytest.mark.parametrize("lat", [(48, 2, 2), (2, 48, 2), (2, 2, 48), (96, 1, 2), (1, 64, 1)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_long_line_fft_extents(bbc, ctx, lat, prec):
+    """Extents 48, 64 and 96 take the two-factor LDS FFT on each axis (forward and
+    inverse): full field of two channels against the oracle."""
+    Lx, Ly, Lz = lat
+    dtype = np.complex128 if prec == "f64" else np.complex64
+    Sl, Ss = synth.propagators(lat, 1, seed=115, dtype=dtype)
+    chans = [0, 5]
+    print("case: lattice", lat, prec, flush=True)
+    res = gpu_correlate(ctx, Sl, Ss, [0], chans)
+    out = res[0] * res[1][:, :, None, None, None, None] if prec == "f32" else res
+    r = wick.all_r(Lx, Ly, Lz)
+    Sl64, Ss64 = Sl.astype(np.complex128), Ss.astype(np.complex128)
+    for m, c in enumerate(chans):
+        ref = wick.correlate(Sl64[0], Ss64[0], ops.CHANNELS[c], r)
+        assert normwise(out[0, m].reshape(-1, 16), ref) < (TOL64 if prec == "f64" else 1e-5), (lat, prec, c)
+
+
 def test_p_lambda_8cubed_all_t(bbc, ctx):
     """The 8^3 x 8 p-Lambda workload: every r at two slices (O-U), sampled r at every slice (O-W)."""
     L, T = 8, 8
