@@ -260,23 +260,24 @@ __global__ __launch_bounds__(256) void k_fft(typename cplx_t<T>::type *__restric
         tw[i] = T2{T(c), T(sgn * s)};
     }
     __syncthreads();
-    const long line = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (line >= nlines) return;
     const long V = (long)Lx * Ly * Lz;
     const long lpc = V / N;                    // lines per component
-    const long comp = line / lpc;
-    const long l = line - comp * lpc;
-    long base, stride;
-    if (axis == 0) { base = l * Lx; stride = 1; }
-    else if (axis == 1) { long x = l % Lx, z = l / Lx; base = z * Lx * Ly + x; stride = Lx; }
-    else { base = l; stride = (long)Lx * Ly; }
-    T2 *p = data + comp * V + base;
-    T2 a[N], b[N];
+    for (long line = (long)blockIdx.x * blockDim.x + threadIdx.x; line < nlines;
+         line += (long)gridDim.x * blockDim.x) {
+        const long comp = line / lpc;
+        const long l = line - comp * lpc;
+        long base, stride;
+        if (axis == 0) { base = l * Lx; stride = 1; }
+        else if (axis == 1) { long x = l % Lx, z = l / Lx; base = z * Lx * Ly + x; stride = Lx; }
+        else { base = l; stride = (long)Lx * Ly; }
+        T2 *p = data + comp * V + base;
+        T2 a[N], b[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) a[j] = p[j * stride];
-    Stages<T2, N, 1>::run(a, b, tw, sgn);
+        for (int j = 0; j < N; ++j) a[j] = p[j * stride];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
 #pragma unroll
-    for (int j = 0; j < N; ++j) p[j * stride] = a[j];
+        for (int j = 0; j < N; ++j) p[j * stride] = a[j];
+    }
 }
 
 // x and y transforms of whole (component, z) planes in LDS (Lx = Ly = N): P
@@ -471,8 +472,7 @@ template <typename T, int N>
 static void fft_axis(typename cplx_t<T>::type *data, long ncomp, const int L[3], int axis, int sgn, hipStream_t st) {
     const long V = (long)L[0] * L[1] * L[2];
     const long nlines = ncomp * (V / N);
-    const long nblk = (nlines + 255) / 256;
-    hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)nblk), dim3(256), 0, st, data, nlines, L[0], L[1], L[2],
+    hipLaunchKernelGGL((k_fft<T, N>), dim3(grid1d(nlines)), dim3(256), 0, st, data, nlines, L[0], L[1], L[2],
                        axis, sgn);
 }
 
@@ -856,7 +856,7 @@ __device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__re
 template <typename T>
 __global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type *__restrict__ Iq,
                                                   typename cplx_t<T>::type *__restrict__ slots, int nc, long V,
-                                                  int ngroup, const int2 *__restrict__ gpos, int ntask,
+                                                  int gbase, int gcount, const int2 *__restrict__ gpos, int ntask,
                                                   const int4 *__restrict__ segs, const DDiag *__restrict__ diags,
                                                   const DRef *__restrict__ refs) {
     using T2 = typename cplx_t<T>::type;
@@ -864,13 +864,14 @@ __global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type
     constexpr int G = Ly::G;             // momentum lanes per open index
     constexpr int NI = 64 / G;           // open-index lanes per wave
     // XCD-aware placement: consecutive workgroup ids cycle over the 8 XCDs;
-    // XCD x owns the contiguous range of groups [x*P8, (x+1)*P8).
+    // XCD x owns the contiguous range of groups [x*P8, (x+1)*P8) of this launch.
     const int xcd = blockIdx.x & 7;
     const int j = blockIdx.x >> 3;
-    const int P8 = (ngroup + 7) >> 3;
-    const int grp = xcd * P8 + j / ntask;
+    const int P8 = (gcount + 7) >> 3;
+    const int gl8 = xcd * P8 + j / ntask;
     const int task = j - (j / ntask) * ntask;
-    if (grp >= ngroup) return;
+    if (gl8 >= gcount) return;
+    const int grp = gbase + gl8;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gl = lane & (G - 1), il = lane / G;
@@ -928,33 +929,40 @@ __global__ __launch_bounds__(256) void k_combine(const typename cplx_t<T>::type 
                                                  typename cplx_t<T>::type *__restrict__ Ct, int n_ch, int V,
                                                  const int32_t *__restrict__ ch_slot_begin) {
     using T2 = typename cplx_t<T>::type;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)n_ch * 16 * V) return;
-    const int m = (int)(i / (16L * V));
-    const long rest = i - (long)m * 16 * V;
-    const int b = ch_slot_begin[m], e = ch_slot_begin[m + 1];
-    T2 v = slots[(size_t)b * 16 * V + rest];
-    for (int s = b + 1; s < e; ++s) {
-        const T2 w = slots[(size_t)s * 16 * V + rest];
-        v.x += w.x;
-        v.y += w.y;
+    const long n = (long)n_ch * 16 * V;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int m = (int)(i / (16L * V));
+        const long rest = i - (long)m * 16 * V;
+        const int b = ch_slot_begin[m], e = ch_slot_begin[m + 1];
+        T2 v = slots[(size_t)b * 16 * V + rest];
+        for (int s = b + 1; s < e; ++s) {
+            const T2 w = slots[(size_t)s * 16 * V + rest];
+            v.x += w.x;
+            v.y += w.y;
+        }
+        Ct[i] = v;
     }
-    Ct[i] = v;
 }
 
 template <typename T>
 void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots, int nc, long V,
                      const ContractTables &tb, hipStream_t st) {
-    const long nwg = 8L * ((tb.ngroup + 7) / 8) * tb.ntask;
-    hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, V, tb.ngroup,
-                       tb.gpos, tb.ntask, tb.segs, tb.diags, tb.refs);
+    // groups per launch: below 2^32 work-items per dispatch (the packet's grid size is 32-bit)
+    const long max_wg = (1L << 32) / 256 - 64;
+    const int chunk = (int)std::max<long>(8, std::min<long>(tb.ngroup, (max_wg / tb.ntask) / 8 * 8));
+    for (int g0 = 0; g0 < tb.ngroup; g0 += chunk) {
+        const int gc = std::min(chunk, tb.ngroup - g0);
+        const long nwg = 8L * ((gc + 7) / 8) * tb.ntask;
+        hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, V, g0, gc, tb.gpos,
+                           tb.ntask, tb.segs, tb.diags, tb.refs);
+    }
 }
 
 template <typename T>
 void launch_combine(const typename cplx_t<T>::type *slots, typename cplx_t<T>::type *Ct, int n_ch, long V,
                     const int32_t *ch_slot_begin, hipStream_t st) {
     const long n = (long)n_ch * 16 * V;
-    hipLaunchKernelGGL((k_combine<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slots, Ct, n_ch, (int)V,
+    hipLaunchKernelGGL((k_combine<T>), dim3(grid1d(n)), dim3(256), 0, st, slots, Ct, n_ch, (int)V,
                        ch_slot_begin);
 }
 
@@ -971,8 +979,8 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
                                                   double *__restrict__ scale_out, const uint32_t *__restrict__ kmax,
                                                   const int2 *__restrict__ content) {
     using T2 = typename cplx_t<T>::type;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)n_ch * V) return;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n_ch * V;
+         i += (long)gridDim.x * blockDim.x) {
     const int m = (int)(i / V), x = (int)(i - (long)m * V);
     const double e = energy ? exp(energy[m] * dt) : 1.0;
     T f;
@@ -995,6 +1003,7 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
         T2 v = Ct[((size_t)m * 16 + s) * V + x];
         o[s] = T2{v.x * f, v.y * f};
     }
+    }
 }
 
 template <typename T>
@@ -1002,7 +1011,7 @@ void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::typ
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
                      const int2 *content, hipStream_t st) {
     const long n = (long)n_ch * V;
-    hipLaunchKernelGGL((k_finalize<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Ct, out, n_ch, V,
+    hipLaunchKernelGGL((k_finalize<T>), dim3(grid1d(n)), dim3(256), 0, st, Ct, out, n_ch, V,
                        energy, dt, inv_v, scale_out, kmax, content);
 }
 

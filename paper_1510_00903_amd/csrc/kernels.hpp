@@ -35,6 +35,14 @@ struct ContractTables {
     int nslot;
 };
 
+// Blocks of 256 threads for a one-dimensional launch over n items, capped so
+// that a dispatch stays below 2^32 work-items (the packet's grid size is 32-bit);
+// such kernels loop over their items with the grid stride.
+inline unsigned grid1d(long n) {
+    const long b = (n + 255) / 256;
+    return (unsigned)(b < (1L << 22) ? (b > 0 ? b : 1) : (1L << 22));
+}
+
 template <typename T> struct cplx_t;
 template <> struct cplx_t<double> { using type = double2; };
 template <> struct cplx_t<float> { using type = float2; };

@@ -19,8 +19,7 @@ __global__ __launch_bounds__(256) void k_spin_project(const typename cplx_t<T>::
                                                       typename cplx_t<T>::type *__restrict__ out, long nsite,
                                                       int n_out, int m0, SpinWeights4 W) {
     using T2 = typename cplx_t<T>::type;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsite) return;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nsite; i += (long)gridDim.x * blockDim.x) {
     const T2 *p = in + i * 16;
     double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
 #pragma unroll
@@ -36,6 +35,7 @@ __global__ __launch_bounds__(256) void k_spin_project(const typename cplx_t<T>::
     }
     T2 *q = out + i * n_out + m0;
     for (int m = 0; m < W.n; ++m) q[m] = T2{T(acc[m].x), T(acc[m].y)};
+    }
 }
 
 // The 24 proper rotations of the cube as signed permutations of (x, y, z):
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(256) void k_cubic_project(const typename cplx_t<T>:
                                                        int L, int n_comp, int complement) {
     using T2 = typename cplx_t<T>::type;
     const long V = (long)L * L * L;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_fields * V * n_comp) return;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_fields * V * n_comp;
+         i += (long)gridDim.x * blockDim.x) {
     const int c = (int)(i % n_comp);
     const long site = (i / n_comp) % V;
     const long f = i / (n_comp * V);
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void k_cubic_project(const typename cplx_t<T>:
         a.y = v.y - a.y;
     }
     out[i] = T2{T(a.x), T(a.y)};
+    }
 }
 
 // The same projection with one component of one field staged whole in LDS
@@ -158,8 +159,8 @@ __global__ __launch_bounds__(256) void k_central_potential(const double2 *__rest
                                                            int Lx, int Ly, int Lz, long n_fields, int n_t,
                                                            double inv_2mu) {
     const long V = (long)Lx * Ly * Lz;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_fields * (n_t - 2) * V) return;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_fields * (n_t - 2) * V;
+         i += (long)gridDim.x * blockDim.x) {
     const long site = i % V;
     const long ft = i / V;                         // f * (n_t - 2) + (t - 1)
     const long f = ft / (n_t - 2);
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(256) void k_central_potential(const double2 *__rest
     const double ny = ly * inv_2mu - 0.5 * (up.y - dn.y);
     const double den = c.x * c.x + c.y * c.y;     // (nx + i ny) / (c.x + i c.y)
     Vout[i] = double2{(nx * c.x + ny * c.y) / den, (ny * c.x - nx * c.y) / den};
+    }
 }
 
 template <typename T>
@@ -189,7 +191,7 @@ void launch_spin_project(const typename cplx_t<T>::type *in, typename cplx_t<T>:
         w.n = n_out - m0 < 4 ? n_out - m0 : 4;
         for (int m = 0; m < w.n; ++m)
             for (int s = 0; s < 16; ++s) w.w[m][s] = double2{W[((m0 + m) * 16 + s) * 2], W[((m0 + m) * 16 + s) * 2 + 1]};
-        hipLaunchKernelGGL((k_spin_project<T>), dim3((unsigned)((nsite + 255) / 256)), dim3(256), 0, st, in, out,
+        hipLaunchKernelGGL((k_spin_project<T>), dim3(grid1d(nsite)), dim3(256), 0, st, in, out,
                            nsite, n_out, m0, w);
     }
 }
@@ -199,21 +201,21 @@ void launch_cubic_project(const typename cplx_t<T>::type *in, typename cplx_t<T>
                           int n_comp, int complement, hipStream_t st) {
     using T2 = typename cplx_t<T>::type;
     const long V = (long)L * L * L;
-    if (V * (long)sizeof(T2) <= 65536) {
+    if (V * (long)sizeof(T2) <= 65536 && n_fields * n_comp < (1L << 24) - 8) {
         const long nwg = n_fields * n_comp;
         hipLaunchKernelGGL((k_cubic_project_lds<T>), dim3((unsigned)(8 * ((nwg + 7) / 8))), dim3(256),
                            V * sizeof(T2), st, in, out, n_fields, L, n_comp, complement);
         return;
     }
     const long n = n_fields * V * n_comp;
-    hipLaunchKernelGGL((k_cubic_project<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n_fields,
+    hipLaunchKernelGGL((k_cubic_project<T>), dim3(grid1d(n)), dim3(256), 0, st, in, out, n_fields,
                        L, n_comp, complement);
 }
 
 void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], long n_fields, int n_t,
                               double inv_2mu, hipStream_t st) {
     const long n = n_fields * (n_t - 2) * L[0] * L[1] * L[2];
-    hipLaunchKernelGGL(k_central_potential, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, Vout, L[0], L[1],
+    hipLaunchKernelGGL(k_central_potential, dim3(grid1d(n)), dim3(256), 0, st, R, Vout, L[0], L[1],
                        L[2], n_fields, n_t, inv_2mu);
 }
 

@@ -363,3 +363,33 @@ def test_host_streamed_path_equals_device_path(bbc, ctx, dtype):
     a = got2[0] if isinstance(got2, tuple) else got2
     b = got[0] if isinstance(got, tuple) else got
     assert torch.equal(a, b)
+
+
+def test_96cubed_fp32_relations_full_field(bbc, ctx):
+    """The largest lattice (96^3, FP32 form, one slice, device-resident): exact
+    relations over every r, which fail if any momentum is missing from a launch:
+    the isospin-zero channel vanishes, C[LL>pX-] = -C[LL>nX0], and identical sink
+    baryons give C(r)_{ab..} = -C(-r)_{ba..} for LL>LL."""
+    L = 96
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(131)
+    shape = (1, L, L, L, 12, 12)
+    Sl = torch.randn(shape, dtype=torch.complex64, device=dev, generator=g)
+    Ss = torch.randn(shape, dtype=torch.complex64, device=dev, generator=g) * 0.5
+    chans = [10, 11, 12, 52]
+    out, scale = ctx.correlate(Sl, Ss, [0], chans)
+    torch.cuda.synchronize()
+    C = out[0].to(torch.complex128) * scale[0].view(-1, 1, 1, 1, 1)
+    del out, Sl, Ss
+    ref = C[0].abs().max().item()
+    assert ref > 0
+    assert C[3].abs().max().item() <= 1e-5 * ref                               # zero channel
+    assert (C[1] + C[2]).abs().max().item() <= 1e-5 * C[1].abs().max().item()  # isospin pair
+    # C(r)_{a b a' b'} = -C(-r)_{b a a' b'}: -r = (L - r) mod L per axis, swap a <-> b
+    LL = C[0]
+    neg = torch.roll(torch.flip(LL, dims=(0, 1, 2)), shifts=(1, 1, 1), dims=(0, 1, 2))
+    idx = torch.tensor([((s >> 1) & 1) + 2 * (s & 1) + 4 * (s >> 2) for s in range(16)], device=dev)
+    swapped = neg[..., idx]
+    assert (LL + swapped).abs().max().item() <= 1e-5 * ref
+
