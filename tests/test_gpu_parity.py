@@ -321,6 +321,32 @@ def test_fp32_vs_fp64_16cubed_all_channels(bbc, ctx):
     assert errs.max() < TOL32, errs.max()
 
 
+def test_fp32_vs_fp64_32cubed_all_channels(bbc, ctx):
+    """The 32^3 x 64 configuration's inputs (t-independent field + 1e-3 noise per
+    slice, exp(-m t) decay) at t = 0, 31, 63 (the deepest slice): FP32 form against
+    the FP64 form over every r, all 52 channels; per-channel errors are written to
+    gpurun_out/ when that folder exists."""
+    L = 32
+    t_list = [0, 31, 63]
+    Sl, Ss = synth.propagators(L, 64, seed=synth.BASE_SEED + 2, kind="correlated", t_list=t_list,
+                               dtype=np.complex64)
+    chans = list(range(52))
+    errs = np.zeros((len(t_list), 52))
+    for n, t in enumerate(t_list):                      # one slice at a time (device memory)
+        out32, scale = gpu_correlate(ctx, Sl[n:n + 1], Ss[n:n + 1], [t], chans)
+        out64 = gpu_correlate(ctx, Sl[n:n + 1].astype(np.complex128), Ss[n:n + 1].astype(np.complex128), [t], chans)
+        for c in chans:
+            errs[n, c] = normwise(out32[0, c].astype(np.complex128) * scale[0, c], out64[0, c])
+        del out32, out64
+    out_dir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out_dir):
+        with open(os.path.join(out_dir, "fp32_errors_32c64.txt"), "w") as f:
+            f.write("# channel  normwise error of the FP32 form vs the FP64 form, 32^3, t=%s\n" % t_list)
+            for c in chans:
+                f.write("%2d %-16s %s\n" % (c, bbc.channel_name(c), " ".join("%.3e" % e for e in errs[:, c])))
+    assert errs.max() < TOL32, errs.max()
+
+
 def test_16cubed_su3_limit_relations(bbc, ctx):
     """SU(3)-limit run (S_s := S_l) at 16^3: u <-> s maps Sigma+ n onto Sigma- Xi0 and
     p Xi- onto itself, with r -> -r and both baryon pairs swapped."""
