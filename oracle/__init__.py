@@ -20,4 +20,6 @@ Contents
                 of the unified-contraction cross-check of Sec. 6).
   postproc.py   post-processing of C(r, t) (Sec. 2): spin projection to (J, M),
                 A1+ projection over the cubic group, HAL QCD central potential.
+  cpt.py        forward/backward (CPT) average of upper and lower components
+                (Sec. 6).
 """

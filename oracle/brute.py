@@ -38,10 +38,12 @@ def tensor_entries(g):
     return np.array(idx), np.array(val)
 
 
-def correlate(S_l, S_s, ch, r_list, spins=None):
+def correlate(S_l, S_s, ch, r_list, spins=None, lower=False):
     """C_ch(r) by brute force for one time slice.
 
     spins: iterable of spin indices a + 2*(b + 2*(a' + 2*b')) (default: all 16).
+    lower: take the lower two Dirac components of every spinor index (component
+           2 + a for a, Sec. 6) instead of the upper two.
     Returns complex128 [n_r][16] (entries not requested are left 0).
     """
     Lz, Ly, Lx = S_l.shape[:3]
@@ -51,7 +53,7 @@ def correlate(S_l, S_s, ch, r_list, spins=None):
     props = [Sl, Sl, Ss]          # u, d, s (u = d numerically, distinct as fields)
     if spins is None:
         spins = range(16)
-    ent = [tensor_entries(g) for g in range(2)]
+    ent = [tensor_entries(g + (2 if lower else 0)) for g in range(2)]
     terms = ops.channel_terms(ch)
     out = np.zeros((len(r_list), 16), dtype=np.complex128)
     for ir, (rx, ry, rz) in enumerate(r_list):
