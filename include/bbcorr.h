@@ -152,6 +152,41 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
                          const double *energy, void *C_out, double *C_scale, void *stream);
 
 /*
+ * Forward/backward (CPT) average of Sec. 6.  The baryon pair propagating
+ * forward in time (upper spinor components) and the antibaryon pair
+ * propagating backward (lower components) are related by charge conjugation,
+ * parity and time reversal; the paper averages the two to double its samples.
+ * For each tau in tau_list:
+ *
+ *   R(r, tau) = 1/2 exp(E tau) [ C_upper(r; slice (t0 + tau) mod Lt)
+ *                                + sign * C_lower(r; slice (t0 - tau) mod Lt) ]
+ *
+ * with the lower component 2 + s re-indexed to s (no spin flip), as the paper
+ * describes.  Readings: the slice map mod Lt, the common factor exp(E tau), and
+ * sign (+1 or -1; +1 when each baryon's backward part carries the same factor,
+ * which enters the pair squared).
+ *
+ *   lattice[3], prec, ch_list, energy   as for bbc_correlate.
+ *   Lt            number of time slices held in S_light / S_strange (>= 1).
+ *   S_light, S_strange  device pointers, [Lt][Lz][Ly][Lx][12][12]: every slice.
+ *   t0            source slice, 0 <= t0 < Lt.
+ *   tau_list[n_tau]  distances from t0, 0 <= tau < Lt (tau >= Lt/2 is accepted
+ *                 and simply reads the slices the map gives).
+ *   R_out         device pointer, n_tau * n_ch * V * 16 complex, the
+ *                 bbc_correlate layout with tau in place of t.
+ *   R_scale       BBC_F32 only: device pointer to n_tau * n_ch doubles; R is
+ *                 R_scale times the FP32 field (the larger of the two parts'
+ *                 factors; the parts are combined in FP64 and rounded once).
+ * Device memory only (BBC_EINVAL otherwise).  Uses the context workspace of one
+ * slice plus one output slice; stream-ordered like bbc_correlate; graph mode
+ * does not apply (the calls run as ordinary launches).
+ */
+bbc_status bbc_correlate_cpt(bbc_context *ctx, const int32_t lattice[3], int Lt, bbc_precision prec,
+                             const void *S_light, const void *S_strange, int t0, int n_tau,
+                             const int32_t *tau_list, int n_ch, const int32_t *ch_list, int sign,
+                             const double *energy, void *R_out, double *R_scale, void *stream);
+
+/*
  * Serving: continuous batching of correlator jobs on one device.
  *
  * A job is (resident propagator set, list of its time slices, channel list).

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
     "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
     "bbc_spin_project", "bbc_cubic_project", "bbc_central_potential",
-    "bbc_num_baryons", "bbc_baryon_name", "bbc_channel_id", "bbc_graph_mode",
+    "bbc_num_baryons", "bbc_baryon_name", "bbc_channel_id", "bbc_graph_mode", "bbc_correlate_cpt",
 ]
 CUBIC_A1, CUBIC_A1_COMPLEMENT = 0, 1
 JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
@@ -81,6 +81,7 @@ def load():
     lib.bbc_last_error.restype = ctypes.c_char_p
     lib.bbc_footprint.argtypes = [P, I, I, P, P]
     lib.bbc_correlate.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
+    lib.bbc_correlate_cpt.argtypes = [P, P, I, I, P, P, I, I, P, I, P, I, P, P, P, P]
     lib.bbc_profile_enable.argtypes = [P, I]
     lib.bbc_profile_read.argtypes = [P, I, P, P]
     lib.bbc_graph_mode.argtypes = [P, I]
@@ -340,6 +341,57 @@ class Context:
             self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()), ctypes.c_void_p(S_strange.data_ptr()),
             n_t, t_arr, int(t0), n_ch, ch_arr, int(spin), e_arr, ctypes.c_void_p(out.data_ptr()),
             ctypes.c_void_p(scale.data_ptr()) if (prec == F32) else None,
+            ctypes.c_void_p(stream.cuda_stream)))
+        return (out, scale) if prec == F32 else out
+
+    def correlate_cpt(self, S_light, S_strange, t0, taus, channels, sign=1, energy=None, out=None, scale=None,
+                      stream=None):
+        """Forward/backward (CPT) average R_ch(r, tau) (Sec. 6): half the sum of the upper
+        components on slice (t0 + tau) mod Lt and sign times the lower components on slice
+        (t0 - tau) mod Lt, both normalised by exp(E tau).
+
+        S_*:   device tensors [Lt, Lz, Ly, Lx, 12, 12] holding every time slice,
+               complex128 (FP64 form) or complex64 (FP32 form).
+        Returns ``out`` [n_tau, n_ch, Lz, Ly, Lx, 16]; in the FP32 form also ``scale``
+        [n_tau, n_ch] float64.  Stream-ordered on ``stream`` (default: torch's current stream).
+        """
+        import torch
+
+        if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
+            raise BBCError("S_light and S_strange must have the same shape and dtype")
+        if S_light.dim() != 6 or tuple(S_light.shape[-2:]) != (12, 12):
+            raise BBCError("propagators must be [Lt, Lz, Ly, Lx, 12, 12]")
+        if not (S_light.is_cuda and S_strange.is_cuda):
+            raise BBCError("correlate_cpt takes device tensors")
+        if S_light.dtype == torch.complex128:
+            prec = F64
+        elif S_light.dtype == torch.complex64:
+            prec = F32
+        else:
+            raise BBCError("propagators must be complex128 or complex64")
+        S_light = S_light.contiguous()
+        S_strange = S_strange.contiguous()
+        Lt, Lz, Ly, Lx = S_light.shape[:4]
+        tau_arr, n_tau = _i32(taus)
+        ch_arr, n_ch = _i32(channels)
+        lat, _ = _i32([Lx, Ly, Lz])
+        dev = S_light.device
+        if out is None:
+            out = torch.empty((n_tau, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, device=dev)
+        if prec == F32 and scale is None:
+            scale = torch.empty((n_tau, n_ch), dtype=torch.float64, device=dev)
+        e_arr = None
+        if energy is not None:
+            e_vals = [float(e) for e in energy]
+            if len(e_vals) != n_ch:
+                raise BBCError("energy must have one entry per channel")
+            e_arr = (ctypes.c_double * n_ch)(*e_vals)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(self._lib.bbc_correlate_cpt(
+            self._ptr, lat, int(Lt), prec, ctypes.c_void_p(S_light.data_ptr()),
+            ctypes.c_void_p(S_strange.data_ptr()), int(t0), n_tau, tau_arr, n_ch, ch_arr, int(sign), e_arr,
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(scale.data_ptr()) if prec == F32 else None,
             ctypes.c_void_p(stream.cuda_stream)))
         return (out, scale) if prec == F32 else out
 

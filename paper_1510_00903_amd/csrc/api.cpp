@@ -504,6 +504,33 @@ bool is_host_pointer(const void *p) {
     return !(attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
 }
 
+// Grows the context workspace to at least `need` bytes (waits for the device
+// and drops the cached graphs, which hold its old address).
+bbc_status ensure_workspace(bbc_context *ctx, size_t need) {
+    if (ctx->ws_bytes >= need) return BBC_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->clear_graphs();
+    if (ctx->ws) { HIP_TRY(hipFree(ctx->ws)); ctx->ws = nullptr; ctx->ws_bytes = 0; }
+    hipError_t e = hipMalloc(&ctx->ws, need);
+    if (e != hipSuccess) { ctx->ws = nullptr; return fail(BBC_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e)); }
+    ctx->ws_bytes = need;
+    return BBC_OK;
+}
+
+// Copies the per-channel energies to the context's device array (stream-ordered).
+bbc_status upload_energy(bbc_context *ctx, const double *energy, int n_ch, hipStream_t st) {
+    if (ctx->energy_cap < n_ch) {
+        HIP_TRY(hipDeviceSynchronize());
+        ctx->clear_graphs();
+        if (ctx->d_energy) HIP_TRY(hipFree(ctx->d_energy));
+        ctx->d_energy = nullptr;
+        HIP_TRY(hipMalloc((void **)&ctx->d_energy, sizeof(double) * n_ch));
+        ctx->energy_cap = n_ch;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->d_energy, energy, sizeof(double) * n_ch, hipMemcpyHostToDevice, st));
+    return BBC_OK;
+}
+
 // Direct path.  Propagators and output may be device or host memory; host
 // buffers (pinned memory recommended) are streamed per slice through two
 // device staging buffers each, on separate copy streams, so that the transfer
@@ -521,26 +548,9 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     const size_t need = core + in_stage + out_stage;
     if (ctx->budget && need + dp->table_bytes > ctx->budget)
         return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
-    if (ctx->ws_bytes < need) {
-        HIP_TRY(hipDeviceSynchronize());
-        ctx->clear_graphs();
-        if (ctx->ws) { HIP_TRY(hipFree(ctx->ws)); ctx->ws = nullptr; ctx->ws_bytes = 0; }
-        hipError_t e = hipMalloc(&ctx->ws, need);
-        if (e != hipSuccess) { ctx->ws = nullptr; return fail(BBC_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e)); }
-        ctx->ws_bytes = need;
-    }
-    if (energy) {
-        if (ctx->energy_cap < n_ch) {
-            HIP_TRY(hipDeviceSynchronize());
-            ctx->clear_graphs();
-            if (ctx->d_energy) HIP_TRY(hipFree(ctx->d_energy));
-            ctx->d_energy = nullptr;
-            HIP_TRY(hipMalloc((void **)&ctx->d_energy, sizeof(double) * n_ch));
-            ctx->energy_cap = n_ch;
-        }
-        HIP_TRY(hipMemcpyAsync(ctx->d_energy, energy, sizeof(double) * n_ch, hipMemcpyHostToDevice, st));
-    }
-    bbc_status s;
+    bbc_status s = ensure_workspace(ctx, need);
+    if (s) return s;
+    if (energy && (s = upload_energy(ctx, energy, n_ch, st))) return s;
     const MomGroups mg = get_groups<T>(ctx, L, &s);
     if (!mg.pos) return s;
     if (ctx->graph_mode && !host_in && !host_out && !ctx->prof && n_t > 0) {
@@ -633,6 +643,53 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         if (n_t > 1) HIP_TRY(hipStreamWaitEvent(st, ev[6 + ((n_t - 2) & 1)], 0));
     }
     if (host_in && n_t > 0) HIP_TRY(hipStreamWaitEvent(st, ev[(n_t - 1) & 1], 0));
+    return BBC_OK;
+}
+
+// Forward/backward (CPT) average (Sec. 6), device memory only.  Per tau the
+// upper components of slice t0 + tau are written to R_out, the lower components
+// of slice t0 - tau (both mod Lt) to a workspace buffer after the slice
+// workspace, and the averaging kernel combines them in place.  Both parts are
+// normalised by exp(E tau).
+template <typename T>
+bbc_status run_cpt(bbc_context *ctx, DevPlan *up, DevPlan *lo, const int L[3], long V, int Lt,
+                   const void *S_light, const void *S_strange, int t0, int n_tau, const int32_t *tau_list,
+                   int n_ch, const double *energy, int sign, void *R_out, double *R_scale, hipStream_t st) {
+    using T2 = typename bbc::cplx_t<T>::type;
+    constexpr bool fp32 = sizeof(T) == 4;
+    const size_t cs = sizeof(T2);
+    const size_t core = std::max(workspace_bytes(V, up->plan.ncomp, n_ch, up->nslot, cs),
+                                 workspace_bytes(V, lo->plan.ncomp, n_ch, lo->nslot, cs));
+    const size_t out_slice = (size_t)n_ch * V * 16 * cs;
+    const size_t bwd_off = (core + 255) & ~(size_t)255;
+    const size_t sc_off = (bwd_off + out_slice + 255) & ~(size_t)255;
+    const size_t need = sc_off + 2 * sizeof(double) * n_ch;
+    if (ctx->budget && need + up->table_bytes + lo->table_bytes > ctx->budget)
+        return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
+    bbc_status s = ensure_workspace(ctx, need);
+    if (s) return s;
+    if (energy && (s = upload_energy(ctx, energy, n_ch, st))) return s;
+    const MomGroups mg = get_groups<T>(ctx, L, &s);
+    if (!mg.pos) return s;
+    T2 *bwd = (T2 *)((char *)ctx->ws + bwd_off);
+    double *sf = fp32 ? (double *)((char *)ctx->ws + sc_off) : nullptr;
+    double *sb = fp32 ? sf + n_ch : nullptr;
+    const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
+    const double *de = energy ? ctx->d_energy : nullptr;
+    for (int n = 0; n < n_tau; ++n) {
+        const int tau = tau_list[n];
+        const size_t tf = (size_t)(((t0 + tau) % Lt + Lt) % Lt), tb = (size_t)(((t0 - tau) % Lt + Lt) % Lt);
+        T2 *out = (T2 *)((char *)R_out + (size_t)n * out_slice);
+        s = enqueue_slice<T>(ctx, up, L, V, ctx->ws, mg, Sl + tf * V * 144, Ss + tf * V * 144, n_ch, de, (double)tau,
+                             out, sf, st, true);
+        if (s) return s;
+        s = enqueue_slice<T>(ctx, lo, L, V, ctx->ws, mg, Sl + tb * V * 144, Ss + tb * V * 144, n_ch, de, (double)tau,
+                             bwd, sb, st, true);
+        if (s) return s;
+        bbc::launch_cpt_average<T>(out, bwd, V * 16, n_ch, (double)sign, sf, sb,
+                                   fp32 ? R_scale + (size_t)n * n_ch : nullptr, st);
+        HIP_TRY(hipGetLastError());
+    }
     return BBC_OK;
 }
 
@@ -968,6 +1025,45 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
                                 st, host_in, host_out);
 }
 
+
+bbc_status bbc_correlate_cpt(bbc_context *ctx, const int32_t lattice[3], int Lt, bbc_precision prec,
+                             const void *S_light, const void *S_strange, int t0, int n_tau, const int32_t *tau_list,
+                             int n_ch, const int32_t *ch_list, int sign, const double *energy, void *R_out,
+                             double *R_scale, void *stream) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_lattice(lattice, &V);
+    if (s) return s;
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    if (Lt < 1) return fail(BBC_EINVAL, "Lt must be positive");
+    if (sign != 1 && sign != -1) return fail(BBC_EINVAL, "sign must be +1 or -1");
+    if (n_tau < 0 || n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list or negative n_tau");
+    for (int i = 0; i < n_ch; ++i)
+        if (!bbc::channel_valid(ch_list[i]))
+            return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
+    if (n_tau == 0) return BBC_OK;
+    if (!S_light || !S_strange || !tau_list || !R_out) return fail(BBC_EINVAL, "NULL buffer");
+    if (prec == BBC_F32 && !R_scale) return fail(BBC_EINVAL, "R_scale is required in FP32 mode");
+    if (t0 < 0 || t0 >= Lt) return fail(BBC_EINVAL, "t0 outside [0, Lt)");
+    for (int n = 0; n < n_tau; ++n)
+        if (tau_list[n] < 0 || tau_list[n] >= Lt) return fail(BBC_EINVAL, "tau outside [0, Lt)");
+    if (is_host_pointer(S_light) || is_host_pointer(S_strange) || is_host_pointer(R_out) ||
+        (R_scale && is_host_pointer(R_scale)))
+        return fail(BBC_EINVAL, "bbc_correlate_cpt takes device memory only");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    DevPlan *up = nullptr, *lo = nullptr;
+    if ((s = get_plan(ctx, chans, 0, &up))) return s;
+    if ((s = get_plan(ctx, chans, 2, &lo))) return s;
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == BBC_F64)
+        return run_cpt<double>(ctx, up, lo, L, V, Lt, S_light, S_strange, t0, n_tau, tau_list, n_ch, energy, sign,
+                               R_out, nullptr, st);
+    return run_cpt<float>(ctx, up, lo, L, V, Lt, S_light, S_strange, t0, n_tau, tau_list, n_ch, energy, sign, R_out,
+                          R_scale, st);
+}
 
 bbc_status bbc_server_start(bbc_context *ctx, int n_slots) {
     if (!ctx || n_slots < 1 || n_slots > 16) return fail(BBC_EINVAL, "n_slots must be 1..16");

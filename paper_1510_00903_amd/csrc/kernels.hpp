@@ -100,5 +100,9 @@ void launch_cubic_project(const typename cplx_t<T>::type *in, typename cplx_t<T>
                           int n_comp, int complement, hipStream_t st);
 void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], long n_fields, int n_t,
                               double inv_2mu, hipStream_t st);
+// Forward/backward (CPT) average of Sec. 6, in place on R.
+template <typename T>
+void launch_cpt_average(typename cplx_t<T>::type *R, const typename cplx_t<T>::type *B, long per_ch, int n_ch,
+                        double sign, const double *sf, const double *sb, double *scale_out, hipStream_t st);
 
 }  // namespace bbc

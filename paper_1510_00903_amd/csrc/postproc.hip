@@ -183,6 +183,35 @@ __global__ __launch_bounds__(256) void k_central_potential(const double2 *__rest
     }
 }
 
+// ----------------------------------------------------------------------------
+// Forward/backward (CPT) average (Sec. 6): R = a C_fwd + b C_bwd elementwise
+// over n_ch fields of per_ch values, R overwriting C_fwd.  FP64: a = 1/2,
+// b = sign/2.  FP32: each part carries its own per-channel scale (sf, sb); the
+// result is stored against m = max(sf, sb) with a = sf / (2 m), b = sign sb / (2 m),
+// computed in FP64 and rounded once, and m is written to scale_out (a buffer
+// distinct from sf and sb).
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_cpt_average(typename cplx_t<T>::type *__restrict__ R,
+                                                     const typename cplx_t<T>::type *__restrict__ B, long per_ch,
+                                                     int n_ch, double sign, const double *__restrict__ sf,
+                                                     const double *__restrict__ sb, double *__restrict__ scale_out) {
+    using T2 = typename cplx_t<T>::type;
+    const long n = per_ch * n_ch;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double a = 0.5, b = 0.5 * sign;
+        if (sf) {
+            const int ch = (int)(i / per_ch);
+            const double f = sf[ch], g = sb[ch], m = fmax(f, g);
+            a *= f / m;
+            b *= g / m;
+            if (i - (long)ch * per_ch == 0) scale_out[ch] = m;
+        }
+        const T2 x = R[i], y = B[i];
+        R[i] = T2{T(a * (double)x.x + b * (double)y.x), T(a * (double)x.y + b * (double)y.y)};
+    }
+}
+
 template <typename T>
 void launch_spin_project(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, long nsite, int n_out,
                          const double *W, hipStream_t st) {
@@ -219,10 +248,22 @@ void launch_central_potential(const double2 *R, double2 *Vout, const int L[3], l
                        L[2], n_fields, n_t, inv_2mu);
 }
 
+template <typename T>
+void launch_cpt_average(typename cplx_t<T>::type *R, const typename cplx_t<T>::type *B, long per_ch, int n_ch,
+                        double sign, const double *sf, const double *sb, double *scale_out, hipStream_t st) {
+    const long n = per_ch * n_ch;
+    hipLaunchKernelGGL((k_cpt_average<T>), dim3(grid1d(n)), dim3(256), 0, st, R, B, per_ch, n_ch, sign, sf, sb,
+                       scale_out);
+}
+
 // explicit instantiations
 template void launch_spin_project<double>(const double2 *, double2 *, long, int, const double *, hipStream_t);
 template void launch_spin_project<float>(const float2 *, float2 *, long, int, const double *, hipStream_t);
 template void launch_cubic_project<double>(const double2 *, double2 *, long, int, int, int, hipStream_t);
 template void launch_cubic_project<float>(const float2 *, float2 *, long, int, int, int, hipStream_t);
+template void launch_cpt_average<double>(double2 *, const double2 *, long, int, double, const double *,
+                                         const double *, double *, hipStream_t);
+template void launch_cpt_average<float>(float2 *, const float2 *, long, int, double, const double *, const double *,
+                                        double *, hipStream_t);
 
 }  // namespace bbc
