@@ -22,19 +22,20 @@ from . import operators as ops
 _FL = {"u": 0, "d": 1, "s": 2}
 
 
-def tensor_entries(g):
-    """Nonzero entries of eps(c_a c_b c_c) (C gamma_5)(mu_a, mu_b) delta(g, mu_c)."""
+def tensor_entries(g, name="p"):
+    """Nonzero entries of eps(c_a c_b c_c) Gamma_1(mu_a, mu_b) Gamma_2(g, mu_c) of field `name`
+    (octet fields: Gamma_1 = C gamma_5, Gamma_2 = 1)."""
     eps = ops.levi_civita()
-    M = ops.cg5()
+    M1, M2 = ops.spin_structure(name)
     idx, val = [], []
     for ca, cb, cc in itertools.product(range(3), repeat=3):
         if eps[ca, cb, cc] == 0:
             continue
-        for ma, mb in itertools.product(range(4), repeat=2):
-            if M[ma, mb] == 0:
+        for ma, mb, mc in itertools.product(range(4), repeat=3):
+            if M1[ma, mb] == 0 or M2[g, mc] == 0:
                 continue
-            idx.append((3 * ma + ca, 3 * mb + cb, 3 * g + cc))
-            val.append(eps[ca, cb, cc] * M[ma, mb])
+            idx.append((3 * ma + ca, 3 * mb + cb, 3 * mc + cc))
+            val.append(eps[ca, cb, cc] * M1[ma, mb] * M2[g, mc])
     return np.array(idx), np.array(val)
 
 
@@ -53,7 +54,8 @@ def correlate(S_l, S_s, ch, r_list, spins=None, lower=False):
     props = [Sl, Sl, Ss]          # u, d, s (u = d numerically, distinct as fields)
     if spins is None:
         spins = range(16)
-    ent = [tensor_entries(g + (2 if lower else 0)) for g in range(2)]
+    g0 = 2 if lower else 0
+    ent = [[tensor_entries(g + g0, b) for g in range(2)] for b in ch]
     terms = ops.channel_terms(ch)
     out = np.zeros((len(r_list), 16), dtype=np.complex128)
     for ir, (rx, ry, rz) in enumerate(r_list):
@@ -67,11 +69,10 @@ def correlate(S_l, S_s, ch, r_list, spins=None, lower=False):
                 for (w1, f1), (w2, f2), (w3, f3), (w4, f4) in itertools.product(*terms):
                     fsnk = [_FL[q] for q in f1 + f2]
                     fsrc = [_FL[q] for q in f3 + f4]
-                    (i1, v1), (i2, v2), (i3, v3), (i4, v4) = ent[a], ent[b], ent[a3], ent[b4]
-                    n = len(v1)
+                    (i1, v1), (i2, v2), (i3, v3), (i4, v4) = ent[0][a], ent[1][b], ent[2][a3], ent[3][b4]
                     # all index combinations: grid over the four entry lists
-                    g1, g2, g3, g4 = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), np.arange(n),
-                                                 indexing="ij")
+                    g1, g2, g3, g4 = np.meshgrid(np.arange(len(v1)), np.arange(len(v2)), np.arange(len(v3)),
+                                                 np.arange(len(v4)), indexing="ij")
                     g1, g2, g3, g4 = g1.ravel(), g2.ravel(), g3.ravel(), g4.ravel()
                     xi = np.concatenate([i1[g1], i2[g2]], axis=1)      # [N, 6] sink indices
                     xp = np.concatenate([i3[g3], i4[g4]], axis=1)      # [N, 6] source indices

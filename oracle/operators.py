@@ -45,6 +45,12 @@ def cg5():
     return (g4 @ g2) @ g5
 
 
+def charge_conjugation():
+    """C = gamma_4 gamma_2 (Sec. 2)."""
+    g1, g2, g3, g4, g5 = dirac_gammas()
+    return g4 @ g2
+
+
 def levi_civita():
     e = np.zeros((3, 3, 3))
     for (a, b, c), s in (((0, 1, 2), 1), ((1, 2, 0), 1), ((2, 0, 1), 1),
@@ -70,6 +76,32 @@ BARYONS = {
     "S0":  [(+_R2, _X["Xu"]), (-_R2, _X["Xd"])],
     "L":   [(+_R6, _X["Xu"]), (+_R6, _X["Xd"]), (-2.0 * _R6, _X["Xs"])],
 }
+
+# General fields of Sec. 2, Eq. (FieldOperator_B): B = eps ((q1 Gamma_1 q2) Gamma_2 q3).
+#  * "p2", "n2": the nucleon with {Gamma_1, Gamma_2} = {C, gamma_5} (same flavour terms as p, n);
+#  * decuplet fields with {C gamma_l, 1} (Sec. 4 footnote), l = 1, 2, 3 in the name:
+#    Delta++ (uuu), Delta- (ddd), Omega- (sss), one term each.
+DECUPLET = {"D++": ("u", "u", "u"), "D-": ("d", "d", "d"), "O-": ("s", "s", "s")}
+BARYONS["p2"] = BARYONS["p"]
+BARYONS["n2"] = BARYONS["n"]
+for _name, _f in DECUPLET.items():
+    for _l in (1, 2, 3):
+        BARYONS["%s(%d)" % (_name, _l)] = [(1.0, _f)]
+
+
+def spin_structure(name):
+    """(Gamma_1, Gamma_2) of a field, 4x4 complex (Dirac representation)."""
+    g = dirac_gammas()
+    if name in ("p2", "n2"):
+        return charge_conjugation(), g[4]
+    for d in DECUPLET:
+        if name.startswith(d + "("):
+            ell = int(name[len(d) + 1])
+            return charge_conjugation() @ g[ell - 1], np.eye(4, dtype=complex)
+    if name not in BARYONS:
+        raise KeyError(name)
+    return cg5(), np.eye(4, dtype=complex)
+
 
 # The 52 channels in the order printed in Sec. 4, Eqs. (GeneralBB_NN)-(GeneralBB_XX):
 # (B1, B2, B3, B4) = sink pair B1(X+r) B2(X), source pair with B3 <-> alpha', B4 <-> beta'.

@@ -19,9 +19,11 @@
  * (Sec. 3, Eq. (Qexchdiag)), i.e. a signed sum over flavour-preserving
  * bijections sigma of sink fields onto source fields.
  *
- * T(xi_a xi_b xi_c; g) = eps(c_a c_b c_c) M(mu_a, mu_b) delta(g, mu_c), M = C gamma_5,
- * from the interpolating fields of Sec. 2; xi = 3*mu + c.  The source tensor is
- * the sink tensor with primed indices, exactly as printed in Sec. 3.
+ * T(xi_a xi_b xi_c; g) = eps(c_a c_b c_c) Gamma_1(mu_a, mu_b) Gamma_2(g, mu_c), per
+ * baryon, from the general interpolating field of Sec. 2, Eq. (FieldOperator_B)
+ * (the octet fields of Sec. 2 have Gamma_1 = C gamma_5 and Gamma_2 = 1); xi = 3*mu + c.
+ * The source tensor is the sink tensor with primed indices, exactly as printed
+ * in Sec. 3.
  *
  * Evaluation order (plain, no FFT): the sum over the sink indices xi of one
  * baryon is done first at each site, giving
@@ -53,21 +55,20 @@ static double eps3(int a, int b, int c) {
 }
 
 /* Nonzero entries of one baryon tensor T(e_a e_b e_c; g). */
-typedef struct { int e[3]; double v; } nzent;
+typedef struct { int e[3]; cplx v; } nzent;
 
-static int tensor_nz(const cplx *M, int g, nzent *out) {
+#define MAXNZ 384 /* 6 colour orders x 16 Gamma_1 entries x 4 Gamma_2 entries */
+
+static int tensor_nz(const cplx *M1, const cplx *M2, int g, nzent *out) {
     int n = 0;
     for (int ca = 0; ca < 3; ++ca) for (int cb = 0; cb < 3; ++cb) for (int cc = 0; cc < 3; ++cc) {
         double e = eps3(ca, cb, cc);
         if (e == 0.0) continue;
-        for (int ma = 0; ma < 4; ++ma) for (int mb = 0; mb < 4; ++mb) {
-            cplx m = M[4 * ma + mb];
+        for (int ma = 0; ma < 4; ++ma) for (int mb = 0; mb < 4; ++mb) for (int mc = 0; mc < 4; ++mc) {
+            cplx m = M1[4 * ma + mb] * M2[4 * g + mc];
             if (m == 0) continue;
-            /* C gamma_5 is real in the Dirac representation; keep the real part
-               and refuse anything else so that a wrong matrix cannot pass silently. */
-            if (cimag(m) != 0.0) return -1;
-            out[n].e[0] = 3 * ma + ca; out[n].e[1] = 3 * mb + cb; out[n].e[2] = 3 * g + cc;
-            out[n].v = e * creal(m);
+            out[n].e[0] = 3 * ma + ca; out[n].e[1] = 3 * mb + cb; out[n].e[2] = 3 * mc + cc;
+            out[n].v = e * m;
             ++n;
         }
     }
@@ -80,7 +81,7 @@ static const cplx *prop(const cplx *Sl, const cplx *Ss, int f, long x) {
 
 /* G(x; g; .) for one sink term, for g in {g_lo, g_lo+1}, all sites. */
 static void build_G(long V, const cplx *Sl, const cplx *Ss, const nzent *nz, const int *nnz,
-                    const int *f, cplx *G) {
+                    const int *f, cplx *G) {   /* nz: [2][MAXNZ], the entries for g_lo and g_lo+1 */
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < V; ++x) {
         const cplx *Sa = prop(Sl, Ss, f[0], x), *Sb = prop(Sl, Ss, f[1], x), *Sc = prop(Sl, Ss, f[2], x);
@@ -88,7 +89,7 @@ static void build_G(long V, const cplx *Sl, const cplx *Ss, const nzent *nz, con
             cplx *Gx = G + (x * 2 + g) * NE;
             memset(Gx, 0, sizeof(cplx) * NE);
             for (int k = 0; k < nnz[g]; ++k) {
-                const nzent *t = &nz[g * 24 + k];
+                const nzent *t = &nz[g * MAXNZ + k];
                 const cplx *ra = Sa + 12 * t->e[0], *rb = Sb + 12 * t->e[1], *rc = Sc + 12 * t->e[2];
                 for (int ea = 0; ea < 12; ++ea) {
                     cplx va = t->v * ra[ea];
@@ -105,13 +106,14 @@ static void build_G(long V, const cplx *Sl, const cplx *Ss, const nzent *nz, con
 
 /* One entry of the flattened work list: a (sigma, source-tensor entry pair) with
    its sign and weight, the G-index of each sink baryon, and the source spins. */
-typedef struct { int t1, t2; int A, B; int sp; double coef; } work;
+typedef struct { int t1, t2; int A, B; int sp; cplx coef; } work;
 
 /*
  * Arguments
  *   Lx,Ly,Lz     lattice extent; sites ordered x fastest, then y, then z.
  *   Sl, Ss       light / strange propagator of one time slice, [V][12][12] complex (re,im).
- *   M            4x4 complex spin matrix of the diquark (C gamma_5), row-major.
+ *   M1, M2       per baryon B1..B4, the 4x4 complex matrices Gamma_1 and Gamma_2,
+ *                [4][4][4] row-major (octet fields: C gamma_5 and the identity).
  *   nterm[4]     number of terms of B1, B2, B3, B4 (at most 3 each).
  *   w[4][3]      term weights.
  *   flav[4][3][3] flavour of each field of each term (0 = u, 1 = d, 2 = s), field order a,b,c.
@@ -120,34 +122,37 @@ typedef struct { int t1, t2; int A, B; int sp; double coef; } work;
  *   out[nr][16]  complex result, spin index a + 2*(b + 2*(a' + 2*b')), spins relative to glo.
  * Returns 0, or a negative value on bad input or allocation failure.
  */
-int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, const double *M_,
-                const int *nterm, const double *w, const int *flav, int glo,
+int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, const double *M1_,
+                const double *M2_, const int *nterm, const double *w, const int *flav, int glo,
                 int nr, const int *r, double *out_) {
-    const cplx *Sl = (const cplx *)Sl_, *Ss = (const cplx *)Ss_, *M = (const cplx *)M_;
+    const cplx *Sl = (const cplx *)Sl_, *Ss = (const cplx *)Ss_;
+    const cplx *M1 = (const cplx *)M1_, *M2 = (const cplx *)M2_;
     cplx *out = (cplx *)out_;
     long V = (long)Lx * Ly * Lz;
     for (int b = 0; b < 4; ++b) if (nterm[b] < 1 || nterm[b] > 3) return -1;
 
-    /* tensor nonzeros for the two spin components g = glo, glo+1 */
-    nzent nz[2 * 24];
-    int nnz[2];
-    for (int g = 0; g < 2; ++g) {
-        nnz[g] = tensor_nz(M, glo + g, nz + 24 * g);
-        if (nnz[g] < 0 || nnz[g] > 24) return -2;
-    }
+    /* tensor nonzeros of every baryon for the two spin components g = glo, glo+1 */
+    nzent *nz = malloc(sizeof(nzent) * 4 * 2 * MAXNZ);
+    int nnz[4][2];
+    if (!nz) return -3;
+    for (int b = 0; b < 4; ++b)
+        for (int g = 0; g < 2; ++g) nnz[b][g] = tensor_nz(M1 + 16 * b, M2 + 16 * b, glo + g, nz + (2 * b + g) * MAXNZ);
 
     /* G tensors of every sink term of B1 and B2 */
     int n1 = nterm[0], n2 = nterm[1];
     cplx *G1 = malloc(sizeof(cplx) * (size_t)n1 * V * 2 * NE);
     cplx *G2 = malloc(sizeof(cplx) * (size_t)n2 * V * 2 * NE);
-    if (!G1 || !G2) { free(G1); free(G2); return -3; }
-    for (int t = 0; t < n1; ++t) build_G(V, Sl, Ss, nz, nnz, flav + (0 * 3 + t) * 3, G1 + (size_t)t * V * 2 * NE);
-    for (int t = 0; t < n2; ++t) build_G(V, Sl, Ss, nz, nnz, flav + (1 * 3 + t) * 3, G2 + (size_t)t * V * 2 * NE);
+    if (!G1 || !G2) { free(G1); free(G2); free(nz); return -3; }
+    for (int t = 0; t < n1; ++t)
+        build_G(V, Sl, Ss, nz, nnz[0], flav + (0 * 3 + t) * 3, G1 + (size_t)t * V * 2 * NE);
+    for (int t = 0; t < n2; ++t)
+        build_G(V, Sl, Ss, nz + 2 * MAXNZ, nnz[1], flav + (1 * 3 + t) * 3, G2 + (size_t)t * V * 2 * NE);
+    const nzent *nz3 = nz + 4 * MAXNZ, *nz4 = nz + 6 * MAXNZ;
 
     /* flattened work list over term tuples, sigma and source nonzeros */
     size_t cap = 1024, nw = 0;
     work *wl = malloc(sizeof(work) * cap);
-    if (!wl) { free(G1); free(G2); return -3; }
+    if (!wl) { free(G1); free(G2); free(nz); return -3; }
     for (int t1 = 0; t1 < nterm[0]; ++t1) for (int t2 = 0; t2 < nterm[1]; ++t2)
     for (int t3 = 0; t3 < nterm[2]; ++t3) for (int t4 = 0; t4 < nterm[3]; ++t4) {
         int fs[6], fsrc[6];
@@ -164,13 +169,14 @@ int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, co
             if (ok) {
                 int sg = perm_sign(p, 6);
                 for (int a3 = 0; a3 < 2; ++a3) for (int a4 = 0; a4 < 2; ++a4)
-                for (int k3 = 0; k3 < nnz[a3]; ++k3) for (int k4 = 0; k4 < nnz[a4]; ++k4) {
+                for (int k3 = 0; k3 < nnz[2][a3]; ++k3) for (int k4 = 0; k4 < nnz[3][a4]; ++k4) {
+                    const nzent *n3 = &nz3[MAXNZ * a3 + k3], *n4 = &nz4[MAXNZ * a4 + k4];
                     int e[6];
-                    for (int i = 0; i < 3; ++i) { e[i] = nz[24 * a3 + k3].e[i]; e[3 + i] = nz[24 * a4 + k4].e[i]; }
+                    for (int i = 0; i < 3; ++i) { e[i] = n3->e[i]; e[3 + i] = n4->e[i]; }
                     if (nw == cap) {
                         cap *= 2;
                         work *nwl = realloc(wl, sizeof(work) * cap);
-                        if (!nwl) { free(wl); free(G1); free(G2); return -3; }
+                        if (!nwl) { free(wl); free(G1); free(G2); free(nz); return -3; }
                         wl = nwl;
                     }
                     work *q = &wl[nw++];
@@ -178,7 +184,7 @@ int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, co
                     q->A = 144 * e[p[0]] + 12 * e[p[1]] + e[p[2]];
                     q->B = 144 * e[p[3]] + 12 * e[p[4]] + e[p[5]];
                     q->sp = a3 + 2 * a4;
-                    q->coef = wt * sg * nz[24 * a3 + k3].v * nz[24 * a4 + k4].v;
+                    q->coef = wt * sg * n3->v * n4->v;
                 }
             }
             /* next permutation */
@@ -200,7 +206,7 @@ int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, co
     const long XB = 64;
     const long nxb = (V + XB - 1) / XB;
     long double _Complex *tot = calloc((size_t)nr * 16, sizeof(long double _Complex));
-    if (!tot) { free(wl); free(G1); free(G2); return -3; }
+    if (!tot) { free(wl); free(G1); free(G2); free(nz); return -3; }
 #pragma omp parallel
     {
         long double _Complex *acc = calloc((size_t)nr * 16, sizeof(long double _Complex));
@@ -240,6 +246,6 @@ int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, co
     }
     for (size_t i = 0; i < (size_t)nr * 16; ++i) out[i] = (cplx)tot[i];
     free(tot);
-    free(wl); free(G1); free(G2);
+    free(wl); free(G1); free(G2); free(nz);
     return 0;
 }

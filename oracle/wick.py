@@ -38,7 +38,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         f = lib.oracle_wick
         P = ctypes.c_void_p
-        f.argtypes = [ctypes.c_int] * 3 + [P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
+        f.argtypes = [ctypes.c_int] * 3 + [P, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
         f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -70,10 +70,11 @@ def correlate(S_l, S_s, ch, r_list, lower=False):
     Lz, Ly, Lx = S_l.shape[:3]
     assert S_l.shape == (Lz, Ly, Lx, 12, 12) and S_s.shape == S_l.shape
     r = np.ascontiguousarray(np.asarray(r_list, dtype=np.int32).reshape(-1, 3))
-    M = np.ascontiguousarray(ops.cg5(), dtype=np.complex128)
+    M1 = np.ascontiguousarray([ops.spin_structure(b)[0] for b in ch], dtype=np.complex128)
+    M2 = np.ascontiguousarray([ops.spin_structure(b)[1] for b in ch], dtype=np.complex128)
     nterm, w, fl = _term_arrays(ch)
     out = np.zeros((r.shape[0], 16), dtype=np.complex128)
-    rc = lib.oracle_wick(Lx, Ly, Lz, S_l.ctypes.data, S_s.ctypes.data, M.ctypes.data,
+    rc = lib.oracle_wick(Lx, Ly, Lz, S_l.ctypes.data, S_s.ctypes.data, M1.ctypes.data, M2.ctypes.data,
                          nterm.ctypes.data, w.ctypes.data, fl.ctypes.data, 2 if lower else 0,
                          r.shape[0], r.ctypes.data, out.ctypes.data)
     if rc != 0:
