@@ -42,7 +42,7 @@ bbc_status fail(bbc_status s, const std::string &msg) {
 
 struct DevPlan {
     bbc::Plan plan;
-    int pat_begin[5];
+    bbc::BlockPatterns pats;
     uint32_t *d_terms = nullptr;
     int32_t *d_term_begin = nullptr;
     bbc::DDiag *d_diags = nullptr;
@@ -323,11 +323,36 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         return fail(BBC_EINVAL, std::string("planner: ") + e.what());
     }
     const bbc::Plan &P = dp->plan;
-    // pattern ranges of the component layout
-    for (int p = 0; p <= 4; ++p) dp->pat_begin[p] = P.ncomp;
-    for (int c = P.ncomp - 1; c >= 0; --c) dp->pat_begin[P.comp_pat[c]] = c;
-    for (int p = 3; p >= 0; --p)
-        if (dp->pat_begin[p] > dp->pat_begin[p + 1]) dp->pat_begin[p] = dp->pat_begin[p + 1];
+    // pattern runs of the component layout (components are sorted by pattern id)
+    dp->pats.n = 0;
+    dp->pats.any_imag = 0;
+    for (uint32_t code : P.terms) dp->pats.any_imag |= (int)((code >> 13) & 1);
+    for (int c = 0; c < P.ncomp;) {
+        const int id = P.comp_pat[c];
+        int e = c;
+        while (e < P.ncomp && P.comp_pat[e] == id) ++e;
+        if (dp->pats.n == bbc::kMaxBlockPatterns) return fail(BBC_EUNSUPPORTED, "too many component patterns");
+        bbc::BlockPattern &bp = dp->pats.p[dp->pats.n++];
+        const int sp = id / 8;
+        const bbc::SpinStruct &S = bbc::spin_struct(sp);
+        bp.begin = c;
+        bp.end = e;
+        bp.qa = (uint8_t)((id >> 2) & 1);
+        bp.qb = (uint8_t)((id >> 1) & 1);
+        bp.qc = (uint8_t)(id & 1);
+        for (int m = 0; m < 4; ++m) {
+            bp.p1[m] = (uint8_t)S.p1[m]; bp.k1[m] = (uint8_t)S.k1[m];
+            bp.p2[m] = (uint8_t)S.p2[m]; bp.k2[m] = (uint8_t)S.k2[m];
+        }
+        bp.new_diquark = 1;
+        if (dp->pats.n > 1) {
+            const bbc::BlockPattern &pv = dp->pats.p[dp->pats.n - 2];
+            bool same = pv.qa == bp.qa && pv.qb == bp.qb;
+            for (int m = 0; m < 4; ++m) same = same && pv.p1[m] == bp.p1[m] && pv.k1[m] == bp.k1[m];
+            bp.new_diquark = same ? 0 : 1;
+        }
+        c = e;
+    }
     std::vector<bbc::DDiag> diags;
     std::vector<bbc::DRef> refs;
     std::vector<int4> segs;
@@ -349,7 +374,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
     {
         std::vector<int2> content;
         for (int ch : P.channels) {
-            const int *b = bbc::channel_baryons(ch);
+            const auto b = bbc::channel_baryons(ch);
             int ns = 0;
             for (int s2 = 0; s2 < 2; ++s2)
                 for (int i = 0; i < 3; ++i) ns += bbc::baryon(b[s2]).flav[i] == bbc::FS;
@@ -454,7 +479,7 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     {
         StageTimer tm(pc, st, 0);
         if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
-        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin, dp->pat_begin,
+        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin, dp->pats,
                               fp32 ? kmax : nullptr, st);
     }
     // small cubic lattices: one fused pass (FFT in LDS, written straight into the groups)
@@ -860,13 +885,14 @@ int bbc_num_channels(void) { return bbc::kNumChannels; }
 int bbc_num_channels_all(void) { return bbc::kNumChannelsAll; }
 
 const char *bbc_channel_name(int channel) {
-    static std::vector<std::string> names = [] {
-        std::vector<std::string> v;
-        for (int c = 0; c < bbc::kNumChannelIds; ++c) v.push_back(bbc::channel_name(c));
-        return v;
-    }();
+    // names are made on first request and kept (map nodes do not move)
+    static std::mutex mu;
+    static std::map<int, std::string> names;
     if (!bbc::channel_valid(channel)) return nullptr;
-    return names[channel].c_str();
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = names.find(channel);
+    if (it == names.end()) it = names.emplace(channel, bbc::channel_name(channel)).first;
+    return it->second.c_str();
 }
 
 int bbc_num_baryons(void) { return bbc::kNumBaryons; }
@@ -888,7 +914,7 @@ int bbc_channel_id(int b1, int b2, int b3, int b4) {
 bbc_status bbc_channel_content(int channel, int *n_light, int *n_strange) {
     if (!bbc::channel_valid(channel)) return fail(BBC_EINVAL, "channel index out of range or flavour not conserved");
     if (!n_light || !n_strange) return fail(BBC_EINVAL, "NULL output");
-    const int *b = bbc::channel_baryons(channel);
+    const auto b = bbc::channel_baryons(channel);
     int ns = 0;
     for (int s = 0; s < 2; ++s)
         for (int i = 0; i < 3; ++i) ns += bbc::baryon(b[s]).flav[i] == bbc::FS;
@@ -900,7 +926,7 @@ bbc_status bbc_channel_content(int channel, int *n_light, int *n_strange) {
 bbc_status bbc_source_terms(int channel, int *n3, int *n4) {
     if (!bbc::channel_valid(channel)) return fail(BBC_EINVAL, "channel index out of range or flavour not conserved");
     if (!n3 || !n4) return fail(BBC_EINVAL, "NULL output");
-    const int *b = bbc::channel_baryons(channel);
+    const auto b = bbc::channel_baryons(channel);
     *n3 = bbc::baryon(b[2]).nterm;
     *n4 = bbc::baryon(b[3]).nterm;
     return BBC_OK;
@@ -909,7 +935,7 @@ bbc_status bbc_source_terms(int channel, int *n3, int *n4) {
 bbc_status bbc_diagram_table(int channel, int term3, int term4, int max_diagrams, int *n_diagrams, int32_t *K,
                              int32_t *sign) {
     if (!bbc::channel_valid(channel)) return fail(BBC_EINVAL, "channel index out of range or flavour not conserved");
-    const int *b = bbc::channel_baryons(channel);
+    const auto b = bbc::channel_baryons(channel);
     if (term3 < 0 || term3 >= bbc::baryon(b[2]).nterm || term4 < 0 || term4 >= bbc::baryon(b[3]).nterm)
         return fail(BBC_EINVAL, "source term index out of range");
     if (!n_diagrams) return fail(BBC_EINVAL, "NULL output");

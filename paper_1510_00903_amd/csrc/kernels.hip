@@ -37,16 +37,19 @@ template <typename T2> __device__ __forceinline__ void cfma(T2 &acc, T2 a, T2 b)
 // ----------------------------------------------------------------------------
 // Step 1a: block intermediates.
 //
-// For a sink baryon term with tensor eps(c_a c_b c_c) (C g5)(mu_a mu_b) delta(g, mu_c)
-// (Sec. 2) and propagators S_a, S_b, S_c, the diquark tensor
-//   Q(c_c; e_a, e_b) = sum_{c_a c_b} eps(c_a c_b c_c) sum_mu (C g5)(mu, mu^1)
-//                      S_a[3mu + c_a][e_a] S_b[3(mu^1) + c_b][e_b]
-// gives G(g; e_a, e_b, e_c) = sum_{c_c} Q(c_c; e_a, e_b) S_c[3g + c_c][e_c].
-// Every intermediate component is a signed sum of G values over the source
-// indices closed at this site; the host planner lists those terms (packed
-// e_a | e_b << 4 | e_c << 8 | negative << 12) per component.
-// Components are grouped by pattern: 0 = (light diquark, light third quark),
-// 1 = (light, strange), 2 = (light-strange diquark, light), 3 = (ls, strange).
+// For a sink baryon term with tensor eps(c_a c_b c_c) Gamma_1(mu_a mu_b) Gamma_2(g, mu_c)
+// (Sec. 2, Eq. (FieldOperator_B); the octet fields have Gamma_1 = C g5, Gamma_2 = 1)
+// and propagators S_a, S_b, S_c, with Gamma_1(mu, p1[mu]) = i^k1[mu] and
+// Gamma_2(g, p2[g]) = i^k2[g] (monomial in the Dirac representation), the diquark tensor
+//   Q(c_c; e_a, e_b) = sum_{c_a c_b} eps(c_a c_b c_c) sum_mu i^k1[mu]
+//                      S_a[3mu + c_a][e_a] S_b[3 p1[mu] + c_b][e_b]
+// gives G(g; e_a, e_b, e_c) = i^k2[g] sum_{c_c} Q(c_c; e_a, e_b) S_c[3 p2[g] + c_c][e_c].
+// Every intermediate component is a sum of G values times powers of i over the
+// source indices closed at this site; the host planner lists those terms (packed
+// e_a | e_b << 4 | e_c << 8 | (factor -1) << 12 | (factor i) << 13) per component.
+// Components come in patterns (BlockPatterns): runs sharing the spin structure
+// and the flavours of the three roles; adjacent patterns with the same diquark
+// (flavours of roles a, b and Gamma_1) reuse its tensor.
 // One workgroup handles TS consecutive sites and one of NSPLIT interleaved
 // shares of the components (the diquark tensor is rebuilt per share, which is
 // cheap next to the components); both sink spins are produced.  LDS rows are
@@ -55,13 +58,20 @@ template <typename T2> __device__ __forceinline__ void cfma(T2 &acc, T2 a, T2 b)
 // partial output lines of neighbouring blocks meet in the same L2.
 // Output layout: I[(g * nc + comp) * V + x].
 // ----------------------------------------------------------------------------
-template <typename T, int TS, int NSPLIT>
+// v * i^k for a wave-uniform k
+template <typename T2> __device__ __forceinline__ T2 rot_i(T2 v, int k) {
+    if (k & 1) v = T2{-v.y, v.x};
+    if (k & 2) v = T2{-v.x, -v.y};
+    return v;
+}
+
+template <typename T, int TS, int NSPLIT, bool IMAG>
 __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *__restrict__ Sl,
                                                 const typename cplx_t<T>::type *__restrict__ Ss,
                                                 typename cplx_t<T>::type *__restrict__ I, int V, int nc, int g0,
                                                 const uint32_t *__restrict__ terms,
-                                                const int32_t *__restrict__ term_begin, int p0, int p1, int p2,
-                                                int p3, int p4, const uint32_t *__restrict__ kmax) {
+                                                const int32_t *__restrict__ term_begin, const BlockPatterns pt,
+                                                const uint32_t *__restrict__ kmax) {
     using T2 = typename cplx_t<T>::type;
     __shared__ T2 sS[2][TS][145];
     __shared__ T2 sQ[TS][433];
@@ -84,56 +94,65 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
         sS[0][s][e] = T2{zl.x * kl, zl.y * kl};
         sS[1][s][e] = T2{zs.x * ks, zs.y * ks};
     }
-    const int pb[5] = {p0, p1, p2, p3, p4};
     const int site = tid % TS;
     const int slot = tid / TS;
     constexpr int NSLOT = 256 / TS;
-    for (int qsel = 0; qsel < 2; ++qsel) {
-        __syncthreads();
-        // diquark tensor: a-quark light, b-quark light (qsel 0) or strange (qsel 1)
-        for (int i = tid; i < TS * 432; i += 256) {
-            int s = i / 432, r = i - s * 432;
-            int cc = r / 144, ea = (r / 12) % 12, eb = r % 12;
-            int c1 = (cc + 1) % 3, c2 = (cc + 2) % 3;
-            T2 acc = T2{0, 0};
+    for (int ip = 0; ip < pt.n; ++ip) {
+        const BlockPattern &P = pt.p[ip];
+        if (P.new_diquark) {
+            __syncthreads();
+            // diquark tensor of roles a (flavour qa) and b (flavour qb)
+            const int qa = P.qa, qb = P.qb;
+            for (int i = tid; i < TS * 432; i += 256) {
+                int s = i / 432, r = i - s * 432;
+                int cc = r / 144, ea = (r / 12) % 12, eb = r % 12;
+                int c1 = (cc + 1) % 3, c2 = (cc + 2) % 3;
+                T2 acc = T2{0, 0};
 #pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-                const T m = (mu & 1) ? T(-1) : T(1);           // (C g5)(mu, mu^1)
-                const int nu = mu ^ 1;
-                T2 a1 = sS[0][s][(3 * mu + c1) * 12 + ea], b2 = sS[qsel][s][(3 * nu + c2) * 12 + eb];
-                T2 a2 = sS[0][s][(3 * mu + c2) * 12 + ea], b1 = sS[qsel][s][(3 * nu + c1) * 12 + eb];
-                T2 d = cmul(a1, b2);
-                T2 e = cmul(a2, b1);
-                acc.x += m * (d.x - e.x);
-                acc.y += m * (d.y - e.y);
+                for (int mu = 0; mu < 4; ++mu) {
+                    const int nu = P.p1[mu];
+                    T2 a1 = sS[qa][s][(3 * mu + c1) * 12 + ea], b2 = sS[qb][s][(3 * nu + c2) * 12 + eb];
+                    T2 a2 = sS[qa][s][(3 * mu + c2) * 12 + ea], b1 = sS[qb][s][(3 * nu + c1) * 12 + eb];
+                    T2 d = cmul(a1, b2);
+                    T2 e = cmul(a2, b1);
+                    T2 t = rot_i(T2{d.x - e.x, d.y - e.y}, P.k1[mu]);
+                    acc.x += t.x;
+                    acc.y += t.y;
+                }
+                sQ[s][r] = acc;
             }
-            sQ[s][r] = acc;
+            __syncthreads();
         }
-        __syncthreads();
-        for (int pc = 0; pc < 2; ++pc) {
-            const int p = qsel * 2 + pc;
-            for (int comp = pb[p] + share * NSLOT + slot; comp < pb[p + 1]; comp += NSLOT * NSPLIT) {
-                T2 acc0 = T2{0, 0}, acc1 = T2{0, 0};
-                const int tb = term_begin[comp], te = term_begin[comp + 1];
-                for (int t = tb; t < te; ++t) {
-                    const uint32_t code = terms[t];
-                    const int ea = code & 15, eb = (code >> 4) & 15, ec = (code >> 8) & 15;
-                    const T sg = (code >> 12) & 1 ? T(-1) : T(1);
-                    T2 g0v = T2{0, 0}, g1v = T2{0, 0};
+        const int pc = P.qc;
+        const int r0 = 3 * P.p2[g0], r1 = 3 * P.p2[g0 + 1];
+        for (int comp = P.begin + share * NSLOT + slot; comp < P.end; comp += NSLOT * NSPLIT) {
+            T2 acc0 = T2{0, 0}, acc1 = T2{0, 0};
+            const int tb = term_begin[comp], te = term_begin[comp + 1];
+            for (int t = tb; t < te; ++t) {
+                const uint32_t code = terms[t];
+                const int ea = code & 15, eb = (code >> 4) & 15, ec = (code >> 8) & 15;
+                const T sg = (code >> 12) & 1 ? T(-1) : T(1);
+                const bool im = IMAG && ((code >> 13) & 1);
+                T2 g0v = T2{0, 0}, g1v = T2{0, 0};
 #pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) {
-                        const T2 q = sQ[site][cc * 144 + ea * 12 + eb];
-                        cfma(g0v, q, sS[pc][site][(3 * (g0 + 0) + cc) * 12 + ec]);
-                        cfma(g1v, q, sS[pc][site][(3 * (g0 + 1) + cc) * 12 + ec]);
-                    }
-                    acc0.x += sg * g0v.x; acc0.y += sg * g0v.y;
-                    acc1.x += sg * g1v.x; acc1.y += sg * g1v.y;
+                for (int cc = 0; cc < 3; ++cc) {
+                    const T2 q = sQ[site][cc * 144 + ea * 12 + eb];
+                    cfma(g0v, q, sS[pc][site][(r0 + cc) * 12 + ec]);
+                    cfma(g1v, q, sS[pc][site][(r1 + cc) * 12 + ec]);
                 }
-                const int x = x0 + site;
-                if (x < V) {
-                    I[((size_t)comp) * V + x] = acc0;
-                    I[((size_t)nc + comp) * V + x] = acc1;
+                if (im) {
+                    g0v = T2{-g0v.y, g0v.x};
+                    g1v = T2{-g1v.y, g1v.x};
                 }
+                acc0.x += sg * g0v.x; acc0.y += sg * g0v.y;
+                acc1.x += sg * g1v.x; acc1.y += sg * g1v.y;
+            }
+            acc0 = rot_i(acc0, P.k2[g0]);
+            acc1 = rot_i(acc1, P.k2[g0 + 1]);
+            const int x = x0 + site;
+            if (x < V) {
+                I[((size_t)comp) * V + x] = acc0;
+                I[((size_t)nc + comp) * V + x] = acc1;
             }
         }
     }
@@ -142,12 +161,16 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const int pb[5], const uint32_t *kmax, hipStream_t st) {
+                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st) {
     constexpr int TS = 4, NSPLIT = 2;
     const long nsb = (V + TS - 1) / TS;
     const dim3 grid((unsigned)(8 * ((nsb + 7) / 8)), NSPLIT);
-    hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms, term_begin,
-                       pb[0], pb[1], pb[2], pb[3], pb[4], kmax);
+    if (pt.any_imag)      // some term carries a factor i (spin structures with imaginary entries)
+        hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, true>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
+                           term_begin, pt, kmax);
+    else
+        hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, false>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
+                           term_begin, pt, kmax);
 }
 
 // ----------------------------------------------------------------------------
@@ -1017,9 +1040,9 @@ void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::typ
 
 // explicit instantiations
 template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
-                                    const int32_t *, const int[5], const uint32_t *, hipStream_t);
+                                    const int32_t *, const BlockPatterns &, const uint32_t *, hipStream_t);
 template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
-                                   const int32_t *, const int[5], const uint32_t *, hipStream_t);
+                                   const int32_t *, const BlockPatterns &, const uint32_t *, hipStream_t);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
 template void launch_transpose_grouped<double>(const double2 *, double2 *, int, long, int, const int2 *,

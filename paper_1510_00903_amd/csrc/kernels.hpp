@@ -47,10 +47,26 @@ template <typename T> struct cplx_t;
 template <> struct cplx_t<double> { using type = double2; };
 template <> struct cplx_t<float> { using type = float2; };
 
+// Component patterns of the block kernel: components [begin, end) share the
+// flavours of roles a, b, c (0 light, 1 strange) and the spin structure, given
+// as monomial matrices Gamma_1(mu, p1[mu]) = i^k1[mu], Gamma_2(g, p2[g]) = i^k2[g].
+// new_diquark: the diquark tensor (qa, qb, Gamma_1) differs from the previous pattern's.
+struct BlockPattern {
+    int begin, end;
+    uint8_t qa, qb, qc, new_diquark;
+    uint8_t p1[4], k1[4], p2[4], k2[4];
+};
+constexpr int kMaxBlockPatterns = 40;
+struct BlockPatterns {
+    int n;
+    int any_imag;         // some term has the factor-i bit
+    BlockPattern p[kMaxBlockPatterns];
+};
+
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const int pat_begin[5], const uint32_t *kmax, hipStream_t st);
+                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st);
 
 // FP32 form: per-flavour max |Re|,|Im| of a slice into kmax[0] (light), kmax[1] (strange).
 void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st);

@@ -17,18 +17,108 @@ const double kR6 = 1.0 / std::sqrt(6.0), kR2 = 1.0 / std::sqrt(2.0);
 // (d, s, u) used in Sec. 3, Eq. (LN.pLLp.ududsu): X_d = eps (s C g5 u) d and
 // X_s = eps (u C g5 d) s are cyclic rotations of that order (an even
 // permutation of three Grassmann fields), so only their tensor roles move.
-enum { B_P, B_N, B_SP, B_SM, B_X0, B_XM, B_L, B_S0, B_COUNT };
+// Further fields of the general form of Sec. 2, Eq. (FieldOperator_B): the
+// nucleon with {C, gamma_5} (same flavour terms as p, n) and the decuplet fields
+// of maximal flavour with {C gamma_l, 1} (Sec. 4 footnote), l = 1, 2, 3.
+enum { B_P, B_N, B_SP, B_SM, B_X0, B_XM, B_L, B_S0, B_P2, B_N2, B_DPP1, B_DM1 = B_DPP1 + 3, B_OM1 = B_DM1 + 3,
+       B_COUNT = B_OM1 + 3 };
+static_assert(B_COUNT == kNumBaryons && B_P2 == kNumOctet, "baryon table");
 
 const Baryon kBaryons[B_COUNT] = {
-    {"p",  {FU, FD, FU}, 1, {{+1.0, {0, 1, 2}, "-"}}},
-    {"n",  {FU, FD, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}},
-    {"S+", {FU, FS, FU}, 1, {{-1.0, {0, 1, 2}, "-"}}},
-    {"S-", {FD, FS, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}},
-    {"X0", {FU, FS, FS}, 1, {{+1.0, {0, 1, 2}, "-"}}},
-    {"X-", {FD, FS, FS}, 1, {{-1.0, {0, 1, 2}, "-"}}},
-    {"L",  {FD, FS, FU}, 3, {{kR6, {0, 1, 2}, "Xu"}, {kR6, {1, 2, 0}, "Xd"}, {-2.0 * kR6, {2, 0, 1}, "Xs"}}},
-    {"S0", {FD, FS, FU}, 2, {{kR2, {0, 1, 2}, "Xu"}, {-kR2, {1, 2, 0}, "Xd"}}},
+    {"p",  {FU, FD, FU}, 1, {{+1.0, {0, 1, 2}, "-"}}, SP_OCTET},
+    {"n",  {FU, FD, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}, SP_OCTET},
+    {"S+", {FU, FS, FU}, 1, {{-1.0, {0, 1, 2}, "-"}}, SP_OCTET},
+    {"S-", {FD, FS, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}, SP_OCTET},
+    {"X0", {FU, FS, FS}, 1, {{+1.0, {0, 1, 2}, "-"}}, SP_OCTET},
+    {"X-", {FD, FS, FS}, 1, {{-1.0, {0, 1, 2}, "-"}}, SP_OCTET},
+    {"L",  {FD, FS, FU}, 3, {{kR6, {0, 1, 2}, "Xu"}, {kR6, {1, 2, 0}, "Xd"}, {-2.0 * kR6, {2, 0, 1}, "Xs"}}, SP_OCTET},
+    {"S0", {FD, FS, FU}, 2, {{kR2, {0, 1, 2}, "Xu"}, {-kR2, {1, 2, 0}, "Xd"}}, SP_OCTET},
+    {"p2", {FU, FD, FU}, 1, {{+1.0, {0, 1, 2}, "-"}}, SP_CHI2},
+    {"n2", {FU, FD, FD}, 1, {{-1.0, {0, 1, 2}, "-"}}, SP_CHI2},
+    {"D++(1)", {FU, FU, FU}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1},
+    {"D++(2)", {FU, FU, FU}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 1},
+    {"D++(3)", {FU, FU, FU}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 2},
+    {"D-(1)", {FD, FD, FD}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1},
+    {"D-(2)", {FD, FD, FD}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 1},
+    {"D-(3)", {FD, FD, FD}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 2},
+    {"O-(1)", {FS, FS, FS}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1},
+    {"O-(2)", {FS, FS, FS}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 1},
+    {"O-(3)", {FS, FS, FS}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 2},
 };
+
+// Complex 4x4 matrices with Gaussian-integer entries, enough for products of
+// Dirac matrices in the Dirac representation.
+struct GI { int re, im; };
+using M4 = std::array<std::array<GI, 4>, 4>;
+M4 mmul(const M4 &A, const M4 &B) {
+    M4 C{};
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) {
+        int re = 0, im = 0;
+        for (int k = 0; k < 4; ++k) {
+            re += A[i][k].re * B[k][j].re - A[i][k].im * B[k][j].im;
+            im += A[i][k].re * B[k][j].im + A[i][k].im * B[k][j].re;
+        }
+        C[i][j] = GI{re, im};
+    }
+    return C;
+}
+// Dirac representation: gamma_4 = diag(1, 1, -1, -1); gamma_k has -i sigma_k in the
+// upper right and i sigma_k in the lower left 2x2 block; gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4.
+M4 dirac_gamma(int mu) {
+    M4 G{};
+    if (mu == 4) {
+        for (int i = 0; i < 4; ++i) G[i][i] = GI{i < 2 ? 1 : -1, 0};
+        return G;
+    }
+    if (mu == 5) return mmul(mmul(dirac_gamma(1), dirac_gamma(2)), mmul(dirac_gamma(3), dirac_gamma(4)));
+    // Pauli matrix sigma_mu
+    GI sg[2][2];
+    if (mu == 1) { sg[0][0] = {0, 0}; sg[0][1] = {1, 0}; sg[1][0] = {1, 0}; sg[1][1] = {0, 0}; }
+    else if (mu == 2) { sg[0][0] = {0, 0}; sg[0][1] = {0, -1}; sg[1][0] = {0, 1}; sg[1][1] = {0, 0}; }
+    else { sg[0][0] = {1, 0}; sg[0][1] = {0, 0}; sg[1][0] = {0, 0}; sg[1][1] = {-1, 0}; }
+    for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
+        G[i][2 + j] = GI{sg[i][j].im, -sg[i][j].re};       // -i sigma
+        G[2 + i][j] = GI{-sg[i][j].im, sg[i][j].re};       //  i sigma
+    }
+    return G;
+}
+M4 identity4() {
+    M4 I{};
+    for (int i = 0; i < 4; ++i) I[i][i] = GI{1, 0};
+    return I;
+}
+// Monomial form of M: per row the column and the power of i of its single nonzero entry.
+void monomial(const M4 &M, int p[4], int k[4]) {
+    for (int i = 0; i < 4; ++i) {
+        int n = 0;
+        for (int j = 0; j < 4; ++j) {
+            const GI v = M[i][j];
+            if (v.re == 0 && v.im == 0) continue;
+            ++n;
+            p[i] = j;
+            if (v.re == 1 && v.im == 0) k[i] = 0;
+            else if (v.re == 0 && v.im == 1) k[i] = 1;
+            else if (v.re == -1 && v.im == 0) k[i] = 2;
+            else if (v.re == 0 && v.im == -1) k[i] = 3;
+            else throw std::logic_error("spin matrix entry is not a power of i");
+        }
+        if (n != 1) throw std::logic_error("spin matrix is not monomial");
+    }
+}
+SpinStruct make_spin(const M4 &G1, const M4 &G2) {
+    SpinStruct S{};
+    monomial(G1, S.p1, S.k1);
+    monomial(G2, S.p2, S.k2);
+    bool sym = true, anti = true;
+    for (int m = 0; m < 4; ++m) {
+        const int n = S.p1[m];
+        sym = sym && S.p1[n] == m && S.k1[n] == S.k1[m];
+        anti = anti && S.p1[n] == m && S.k1[n] == (S.k1[m] + 2) % 4;
+    }
+    if (sym == anti) throw std::logic_error("Gamma_1 neither symmetric nor antisymmetric");
+    S.x = sym ? -1 : +1;
+    return S;
+}
 
 // Channel list of Sec. 4 (printed order), then the four omitted isospin-zero ones.
 const int kChannels[kNumChannelsAll][4] = {
@@ -65,43 +155,58 @@ int perm_sign(const int *p, int n) {
 }
 
 // Canonical key of an intermediate from per-role (light/strange, source baryon
-// X, type).  The sink tensor is symmetric under exchanging roles a and b
-// together with their propagators (eps and C gamma_5 are both antisymmetric),
+// X, source role a'/b'/c') and the spin structures involved.  Exchanging sink
+// roles a and b together with their propagators multiplies the sink tensor by
+// its exchange sign x (+1 for C gamma_5 and C, -1 for the symmetric C gamma_l),
 // and which source baryon is "first" is a label; the canonical form relabels
 // source baryons by first appearance and takes the smaller of the two role
-// orders.  ymap receives X -> canonical Y for the chosen form.
-uint32_t canonical(const int pf[3], const int X[3], const int T[3], int ymap[2], int cpf[3], int cy[3],
-                   int ct[3]) {
+// orders (*swapped = 1 if that is b, a, c).  Where a source tensor is symmetric
+// under a' <-> b' the two read alike (0).  ymap receives X -> canonical Y and
+// csrc the spin structure of each canonical Y (-1 if absent).
+uint32_t canonical(const int pf[3], const int X[3], const int T[3], int sink_spin, const int src_spin[2],
+                   int ymap[2], int cpf[3], int cy[3], int ct[3], int csrc[2], int *swapped) {
     uint32_t best = 0xffffffffu;
     const int orders[2][3] = {{0, 1, 2}, {1, 0, 2}};
-    for (const auto &ord : orders) {
+    for (int o = 0; o < 2; ++o) {
+        const int *ord = orders[o];
         int m[2] = {-1, -1}, nx = 0;
         int lpf[3], ly[3], lt[3];
         for (int i = 0; i < 3; ++i) {
             int r = ord[i];
             if (m[X[r]] < 0) m[X[r]] = nx++;
-            lpf[i] = pf[r]; ly[i] = m[X[r]]; lt[i] = T[r];
+            lpf[i] = pf[r]; ly[i] = m[X[r]];
+            lt[i] = (T[r] != 2 && spin_struct(src_spin[X[r]]).x == 1) ? 0 : T[r];
         }
+        int ls[2] = {-1, -1};
+        for (int x = 0; x < 2; ++x)
+            if (m[x] >= 0) ls[m[x]] = src_spin[x];
         uint32_t key = 0;
-        for (int i = 0; i < 3; ++i) key = key * 8 + (uint32_t)(lpf[i] * 4 + ly[i] * 2 + lt[i]);
+        for (int i = 0; i < 3; ++i) key = key * 16 + (uint32_t)((lpf[i] * 2 + ly[i]) * 4 + lt[i]);
+        key = (key << 9) | ((uint32_t)sink_spin << 6) | ((uint32_t)(ls[0] < 0 ? 7 : ls[0]) << 3) |
+              (uint32_t)(ls[1] < 0 ? 7 : ls[1]);
         if (key < best) {
             best = key;
+            *swapped = o;
             ymap[0] = m[0]; ymap[1] = m[1];
+            csrc[0] = ls[0]; csrc[1] = ls[1];
             for (int i = 0; i < 3; ++i) { cpf[i] = lpf[i]; cy[i] = ly[i]; ct[i] = lt[i]; }
         }
     }
     return best;
 }
 
-Intermediate make_intermediate(uint32_t key, const int pf[3], const int y[3], const int t[3]) {
+Intermediate make_intermediate(uint32_t key, const int pf[3], const int y[3], const int t[3], int sink_spin,
+                               const int src_spin[2]) {
     Intermediate I{};
     I.key = key;
     for (int i = 0; i < 3; ++i) { I.pflav[i] = pf[i]; I.role_y[i] = y[i]; I.role_t[i] = t[i]; }
+    I.sink_spin = sink_spin;
+    I.src_spin[0] = src_spin[0]; I.src_spin[1] = src_spin[1];
     I.ny = (y[0] == 1 || y[1] == 1 || y[2] == 1) ? 2 : 1;
     for (int Y = 0; Y < 2; ++Y) {
         int nD = 0, nd = 0;
         for (int i = 0; i < 3; ++i)
-            if (y[i] == Y) (t[i] ? nd : nD)++;
+            if (y[i] == Y) (t[i] == 2 ? nd : nD)++;
         int kind = -1;
         if (nD == 2 && nd == 1) kind = Y_FULL;
         else if (nD == 2 && nd == 0) kind = Y_DD;
@@ -124,25 +229,37 @@ Intermediate make_intermediate(uint32_t key, const int pf[3], const int y[3], co
 
 }  // namespace
 
-// Baryon quadruples of every channel id: the listed channels, then all quadruples.
-static const std::vector<std::array<int, 4>> &channel_table() {
-    static const std::vector<std::array<int, 4>> t = [] {
-        std::vector<std::array<int, 4>> v;
-        for (int c = 0; c < kNumChannelsAll; ++c)
-            v.push_back({kChannels[c][0], kChannels[c][1], kChannels[c][2], kChannels[c][3]});
-        for (int e = 0; e < kNumChannelIds - kChannelExtBase; ++e)
-            v.push_back({e / 512, (e / 64) % 8, (e / 8) % 8, e % 8});
+const SpinStruct &spin_struct(int s) {
+    static const std::array<SpinStruct, kNumSpinStructs> t = [] {
+        std::array<SpinStruct, kNumSpinStructs> v{};
+        const M4 C = mmul(dirac_gamma(4), dirac_gamma(2));
+        v[SP_OCTET] = make_spin(mmul(C, dirac_gamma(5)), identity4());
+        v[SP_CHI2] = make_spin(C, dirac_gamma(5));
+        for (int l = 1; l <= 3; ++l) v[SP_DEC1 + l - 1] = make_spin(mmul(C, dirac_gamma(l)), identity4());
         return v;
     }();
-    return t;
+    return t[s];
 }
 
 const Baryon &baryon(int id) { return kBaryons[id]; }
-const int *channel_baryons(int ch) { return channel_table()[ch].data(); }
+
+// Baryon quadruple of a channel id: the listed channels, the octet quadruples,
+// then the quadruples of all fields.
+std::array<int, 4> channel_baryons(int ch) {
+    if (ch < kChannelExtBase) return {kChannels[ch][0], kChannels[ch][1], kChannels[ch][2], kChannels[ch][3]};
+    if (ch < kChannelGenBase) {
+        const int e = ch - kChannelExtBase;
+        return {e / 512, (e / 64) % 8, (e / 8) % 8, e % 8};
+    }
+    const int e = ch - kChannelGenBase, n = kNumBaryons;
+    return {e / (n * n * n), (e / (n * n)) % n, (e / n) % n, e % n};
+}
 
 bool channel_valid(int ch) {
     if (ch < 0 || ch >= kNumChannelIds) return false;
-    const int *b = channel_baryons(ch);
+    const auto b = channel_baryons(ch);
+    if (ch >= kChannelGenBase && b[0] < kNumOctet && b[1] < kNumOctet && b[2] < kNumOctet && b[3] < kNumOctet)
+        return false;                               // octet quadruples have their id below kChannelGenBase
     int n[3] = {0, 0, 0};
     for (int i = 0; i < 3; ++i) {
         n[kBaryons[b[0]].flav[i]]++; n[kBaryons[b[1]].flav[i]]++;
@@ -155,18 +272,21 @@ int channel_id(const int b[4]) {
     for (int c = 0; c < kNumChannelsAll; ++c)
         if (kChannels[c][0] == b[0] && kChannels[c][1] == b[1] && kChannels[c][2] == b[2] && kChannels[c][3] == b[3])
             return c;
-    return kChannelExtBase + ((b[0] * 8 + b[1]) * 8 + b[2]) * 8 + b[3];
+    if (b[0] < kNumOctet && b[1] < kNumOctet && b[2] < kNumOctet && b[3] < kNumOctet)
+        return kChannelExtBase + ((b[0] * 8 + b[1]) * 8 + b[2]) * 8 + b[3];
+    const int n = kNumBaryons;
+    return kChannelGenBase + ((b[0] * n + b[1]) * n + b[2]) * n + b[3];
 }
 
 std::string channel_name(int ch) {
-    const int *b = channel_baryons(ch);
+    const auto b = channel_baryons(ch);
     return std::string(kBaryons[b[0]].name) + " " + kBaryons[b[1]].name + " > " + kBaryons[b[2]].name + " " +
            kBaryons[b[3]].name;
 }
 
 std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *index,
                               std::vector<Intermediate> *inters) {
-    const int *bb = channel_baryons(ch);
+    const auto bb = channel_baryons(ch);
     const Baryon &B1 = kBaryons[bb[0]], &B2 = kBaryons[bb[1]], &B3 = kBaryons[bb[2]], &B4 = kBaryons[bb[3]];
     int fs[6], fsrc[6], rsrc[6];
     for (int i = 0; i < 3; ++i) {
@@ -179,6 +299,7 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
         rsrc[3 + B4.term[t4].role[r]] = r;
     }
     const double w34 = B3.term[t3].w * B4.term[t4].w;
+    const int srcspin[2] = {B3.spin, B4.spin};
     std::vector<Diagram> out;
     // A diagram is the set of source fields contracted with the quarks of B1
     // (site X+r); Wick maps differing only by exchanges of identical quarks
@@ -239,19 +360,20 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
                                     int q = sig[3 * s + pi[p]];
                                     pf[r] = Bs.flav[p] == FS ? 1 : 0;
                                     X[r] = q / 3;
-                                    T[r] = rsrc[q] == 2 ? 1 : 0;
+                                    T[r] = rsrc[q];
                                 }
                                 BlockRef br;
-                                int cpf[3], cy[3], ct[3];
-                                uint32_t key = canonical(pf, X, T, br.ymap, cpf, cy, ct);
+                                int cpf[3], cy[3], ct[3], csrc[2], swapped = 0;
+                                uint32_t key = canonical(pf, X, T, Bs.spin, srcspin, br.ymap, cpf, cy, ct, csrc,
+                                                         &swapped);
                                 auto it = index->find(key);
                                 if (it == index->end()) {
                                     int id = (int)inters->size();
-                                    inters->push_back(make_intermediate(key, cpf, cy, ct));
+                                    inters->push_back(make_intermediate(key, cpf, cy, ct, Bs.spin, csrc));
                                     it = index->emplace(key, id).first;
                                 }
                                 br.inter = it->second;
-                                br.coef = Bs.term[t].w * perm_sign(pi, 3);
+                                br.coef = Bs.term[t].w * perm_sign(pi, 3) * (swapped ? spin_struct(Bs.spin).x : 1);
                                 d.blk[s].push_back(br);
                             }
                     }
@@ -282,38 +404,39 @@ int eps3(int a, int b, int c) {
     return ((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) ? 1 : -1;
 }
 
-// C gamma_5 in the Dirac representation: nonzero (mu, nu) -> +-1.
-int cg5(int mu, int nu) {
-    if (mu == 0 && nu == 1) return 1;
-    if (mu == 1 && nu == 0) return -1;
-    if (mu == 2 && nu == 3) return 1;
-    if (mu == 3 && nu == 2) return -1;
-    return 0;
-}
-int cg5_partner(int mu) { return mu ^ 1; }
-
-struct Part { int e[3]; int set[3]; int sign; };   // partial assignment of source indices to roles
+struct Part { int e[3]; int set[3]; int ph; };     // partial assignment of source indices; ph: power of i
 
 // Source-tensor pieces of one canonical source baryon Y at the site, for fixed (o, k).
-// Source tensor (Sec. 3): eps(c'_a c'_b c'_c) (C g5)(mu'_a, mu'_b) delta(o, mu'_c).
+// Source tensor (Sec. 3, with the general field of Sec. 2): eps(c'_a c'_b c'_c)
+// Gamma_1(mu'_a, mu'_b) Gamma_2(so + o, mu'_c); the outer spin o selects the row of Gamma_2.
 std::vector<Part> y_parts(const Intermediate &I, int Y, int o, int k, int so) {
-    int rD[3], nD = 0, rd = -1;
-    for (int r = 0; r < 3; ++r)
-        if (I.role_y[r] == Y) { if (I.role_t[r]) rd = r; else rD[nD++] = r; }
+    int ra = -1, rb = -1, rd = -1;
+    for (int r = 0; r < 3; ++r) {
+        if (I.role_y[r] != Y) continue;
+        if (I.role_t[r] == 2) rd = r;
+        else if (I.role_t[r] == 1) rb = r;
+        else if (ra < 0) ra = r;
+        else rb = r;                 // a' and b' read alike: role order decides
+    }
     std::vector<Part> out;
-    auto base = []() { Part p{}; p.sign = 1; for (int i = 0; i < 3; ++i) { p.e[i] = 0; p.set[i] = 0; } return p; };
+    auto base = []() { Part p{}; p.ph = 0; for (int i = 0; i < 3; ++i) { p.e[i] = 0; p.set[i] = 0; } return p; };
+    auto put = [](Part &p, int r, int e) { p.e[r] = e; p.set[r] = 1; };
+    if (I.kind[Y] < 0) { out.push_back(base()); return out; }
+    const SpinStruct &S = spin_struct(I.src_spin[Y]);
+    int inv1[4];
+    for (int m = 0; m < 4; ++m) inv1[S.p1[m]] = m;
+    const int g = so + o, mc = S.p2[g], kc = S.k2[g];     // Gamma_2(g, mc) = i^kc
     switch (I.kind[Y]) {
     case Y_FULL:
         for (int c1 = 0; c1 < 3; ++c1) for (int c2 = 0; c2 < 3; ++c2) for (int c3 = 0; c3 < 3; ++c3) {
             int e = eps3(c1, c2, c3);
             if (!e) continue;
             for (int m1 = 0; m1 < 4; ++m1) {
-                int m2 = cg5_partner(m1);
                 Part p = base();
-                p.sign = e * cg5(m1, m2);
-                p.e[rD[0]] = 3 * m1 + c1; p.set[rD[0]] = 1;
-                p.e[rD[1]] = 3 * m2 + c2; p.set[rD[1]] = 1;
-                p.e[rd] = 3 * (so + o) + c3; p.set[rd] = 1;
+                p.ph = (e < 0 ? 2 : 0) + S.k1[m1] + kc;
+                put(p, ra, 3 * m1 + c1);
+                put(p, rb, 3 * S.p1[m1] + c2);
+                put(p, rd, 3 * mc + c3);
                 out.push_back(p);
             }
         }
@@ -323,38 +446,47 @@ std::vector<Part> y_parts(const Intermediate &I, int Y, int o, int k, int so) {
             int e = eps3(c1, c2, k);
             if (!e) continue;
             for (int m1 = 0; m1 < 4; ++m1) {
-                int m2 = cg5_partner(m1);
                 Part p = base();
-                p.sign = e * cg5(m1, m2);
-                p.e[rD[0]] = 3 * m1 + c1; p.set[rD[0]] = 1;
-                p.e[rD[1]] = 3 * m2 + c2; p.set[rD[1]] = 1;
+                p.ph = (e < 0 ? 2 : 0) + S.k1[m1];
+                put(p, ra, 3 * m1 + c1);
+                put(p, rb, 3 * S.p1[m1] + c2);
                 out.push_back(p);
             }
         }
         break;
     case Y_DDELTA: {  // k = (mu_L, c_L) of the diquark partner at the other site
-        int muL = k / 3, cL = k % 3;
-        int mD = cg5_partner(muL);
+        const int muL = k / 3, cL = k % 3;
         for (int cD = 0; cD < 3; ++cD) for (int cd = 0; cd < 3; ++cd) {
-            int e = eps3(cD, cL, cd);
-            if (!e) continue;
             Part p = base();
-            p.sign = e * cg5(mD, muL);
-            p.e[rD[0]] = 3 * mD + cD; p.set[rD[0]] = 1;
-            p.e[rd] = 3 * (so + o) + cd; p.set[rd] = 1;
+            int e;
+            if (ra >= 0) {           // local quark is a': Gamma_1(mD, mu_L)
+                const int mD = inv1[muL];
+                e = eps3(cD, cL, cd);
+                p.ph = S.k1[mD];
+                put(p, ra, 3 * mD + cD);
+            } else {                 // local quark is b': Gamma_1(mu_L, mD)
+                const int mD = S.p1[muL];
+                e = eps3(cL, cD, cd);
+                p.ph = S.k1[muL];
+                put(p, rb, 3 * mD + cD);
+            }
+            if (!e) continue;
+            p.ph += (e < 0 ? 2 : 0) + kc;
+            put(p, rd, 3 * mc + cd);
             out.push_back(p);
         }
         break;
     }
     case Y_DIN: {
         Part p = base();
-        p.e[rD[0]] = k; p.set[rD[0]] = 1;
+        put(p, ra >= 0 ? ra : rb, k);
         out.push_back(p);
         break;
     }
     case Y_DELTAIN: {
         Part p = base();
-        p.e[rd] = 3 * (so + o) + k; p.set[rd] = 1;
+        p.ph = kc;
+        put(p, rd, 3 * mc + k);
         out.push_back(p);
         break;
     }
@@ -374,7 +506,7 @@ Plan build_plan(const std::vector<int> &channels, int spin_offset) {
     for (int ch : channels) {
         if (!channel_valid(ch)) throw std::invalid_argument("channel index out of range or flavour not conserved");
         P.ch_begin.push_back((int)P.diags.size());
-        const int *bb = channel_baryons(ch);
+        const auto bb = channel_baryons(ch);
         for (int t3 = 0; t3 < kBaryons[bb[2]].nterm; ++t3)
             for (int t4 = 0; t4 < kBaryons[bb[3]].nterm; ++t4)
                 for (auto &d : classify(ch, t3, t4, &index, &P.inters)) {
@@ -401,7 +533,6 @@ Plan build_plan(const std::vector<int> &channels, int spin_offset) {
     P.comp_pat.assign(P.ncomp, 0);
     std::vector<std::vector<uint32_t>> per(P.ncomp);
     for (const auto &I : P.inters) {
-        if (I.pflav[0] != 0) throw std::logic_error("canonical pattern with strange first role");
         for (int o0 = 0; o0 < I.no[0]; ++o0) for (int k0 = 0; k0 < I.nk[0]; ++k0)
         for (int o1 = 0; o1 < I.no[1]; ++o1) for (int k1 = 0; k1 < I.nk[1]; ++k1) {
             int c = I.offset + o0 * I.stride_o[0] + k0 * I.stride_k[0] + o1 * I.stride_o[1] + k1 * I.stride_k[1];
@@ -414,10 +545,9 @@ Plan build_plan(const std::vector<int> &channels, int spin_offset) {
                     if (a.set[r] + b.set[r] != 1) throw std::logic_error("role not covered exactly once");
                     e[r] = a.set[r] ? a.e[r] : b.e[r];
                 }
-                int sg = a.sign * b.sign;
-                if (sg == 0) continue;
+                const int ph = (a.ph + b.ph) & 3;       // coefficient i^ph: bit 13 = factor i, bit 12 = factor -1
                 per[c].push_back((uint32_t)e[0] | ((uint32_t)e[1] << 4) | ((uint32_t)e[2] << 8) |
-                                 ((sg < 0 ? 1u : 0u) << 12));
+                                 ((uint32_t)(ph >> 1) << 12) | ((uint32_t)(ph & 1) << 13));
             }
         }
     }

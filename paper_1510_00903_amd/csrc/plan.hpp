@@ -6,6 +6,7 @@
 // channels, Tables 1-4), Appendix A (reusable blocks).
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -15,8 +16,25 @@ namespace bbc {
 
 enum : int { FU = 0, FD = 1, FS = 2 };
 
+// Spin structure {Gamma_1, Gamma_2} of a field B = eps((q1 Gamma_1 q2) Gamma_2 q3)
+// (Sec. 2, Eq. (FieldOperator_B)).  Every structure used is monomial in the Dirac
+// representation: Gamma_1(mu, p1[mu]) = i^k1[mu] and Gamma_2(g, p2[g]) = i^k2[g], all
+// other entries zero.  x is the sign of the tensor eps Gamma_1 under exchanging its
+// first two legs (-1 times the transpose symmetry of Gamma_1).
+struct SpinStruct {
+    int p1[4], k1[4], p2[4], k2[4];
+    int x;
+};
+enum : int {
+    SP_OCTET = 0,    // {C gamma_5, 1}: the octet fields of Sec. 2
+    SP_CHI2 = 1,     // {C, gamma_5}: the other nucleon field
+    SP_DEC1 = 2,     // {C gamma_l, 1}, l = 1, 2, 3: decuplet fields (Sec. 4 footnote)
+    kNumSpinStructs = 5
+};
+const SpinStruct &spin_struct(int s);
+
 // One term of a baryon field: weight and, for each tensor role r in {a, b, c}
-// (eps(c_a c_b c_c) (C gamma_5)(mu_a, mu_b) delta(gamma, mu_c)), the position of
+// (eps(c_a c_b c_c) Gamma_1(mu_a, mu_b) Gamma_2(gamma, mu_c)), the position of
 // the quark field that plays it in the baryon's fixed field order.
 struct BaryonTerm {
     double w;
@@ -29,18 +47,25 @@ struct Baryon {
     int flav[3];      // flavour of the quark fields in Grassmann order
     int nterm;
     BaryonTerm term[3];
+    int spin;         // spin structure (SP_*)
 };
 
 constexpr int kNumChannels = 52;
 constexpr int kNumChannelsAll = 56;
 // Other charge states: ids from kChannelExtBase name any quadruple of the 8
 // octet fields, id = kChannelExtBase + ((b1 * 8 + b2) * 8 + b3) * 8 + b4.
-constexpr int kNumBaryons = 8;
+// Fields with other spin structures (ids 8..18: p2, n2 with {C, gamma_5}; the
+// decuplet Delta++, Delta-, Omega- with {C gamma_l, 1}, l = 1..3) enter through
+// ids from kChannelGenBase: id = kChannelGenBase + ((b1 * 19 + b2) * 19 + b3) * 19 + b4
+// for quadruples holding at least one of them.
+constexpr int kNumOctet = 8;
+constexpr int kNumBaryons = 19;
 constexpr int kChannelExtBase = kNumChannelsAll;
-constexpr int kNumChannelIds = kChannelExtBase + kNumBaryons * kNumBaryons * kNumBaryons * kNumBaryons;
+constexpr int kChannelGenBase = kChannelExtBase + kNumOctet * kNumOctet * kNumOctet * kNumOctet;
+constexpr int kNumChannelIds = kChannelGenBase + kNumBaryons * kNumBaryons * kNumBaryons * kNumBaryons;
 
 const Baryon &baryon(int id);
-const int *channel_baryons(int ch);          // 4 baryon ids: sink B1, B2, source B3, B4
+std::array<int, 4> channel_baryons(int ch);  // 4 baryon ids: sink B1, B2, source B3, B4
 std::string channel_name(int ch);
 // In range, and the sink and source hold the same number of u, d and s quarks.
 bool channel_valid(int ch);
@@ -58,7 +83,10 @@ struct Intermediate {
     uint32_t key;
     int pflav[3];     // per role a, b, c: 0 light, 1 strange
     int role_y[3];    // per role: canonical source baryon 0/1
-    int role_t[3];    // per role: 0 = diquark quark (a' or b'), 1 = delta quark (c')
+    int role_t[3];    // per role: source role 0 = a', 1 = b', 2 = c' (delta quark); a' and b'
+                      // both read 0 when the source tensor is symmetric under a' <-> b' (x = +1)
+    int sink_spin;    // spin structure of the sink field
+    int src_spin[2];  // spin structure of canonical source baryon Y (-1 if absent)
     int ny;
     int kind[2], no[2], nk[2];
     int ncomp;        // components per sink spin
@@ -91,7 +119,7 @@ struct Plan {
     // block-kernel tables
     std::vector<uint32_t> terms;             // packed (e_a, e_b, e_c, sign)
     std::vector<int32_t> term_begin;         // per component (size ncomp+1)
-    std::vector<int32_t> comp_pat;           // per component: pattern id 0..3
+    std::vector<int32_t> comp_pat;           // per component: pattern id (pattern_id)
     int64_t iterations = 0;                  // sum of K over diagrams
 };
 
@@ -102,7 +130,12 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
 
 Plan build_plan(const std::vector<int> &channels, int spin_offset);
 
-// Pattern id of an intermediate: diquark flavour pair (ll = 0, ls = 1) * 2 + delta flavour.
-inline int pattern_id(const Intermediate &I) { return (I.pflav[1] ? 2 : 0) + (I.pflav[2] ? 1 : 0); }
+// Pattern of an intermediate: what the block kernel builds once for all its
+// components -- the sink spin structure, the flavours of the two diquark roles
+// (the diquark tensor) and of the third role.
+constexpr int kNumPatterns = kNumSpinStructs * 8;
+inline int pattern_id(const Intermediate &I) {
+    return ((I.sink_spin * 2 + I.pflav[0]) * 2 + I.pflav[1]) * 2 + I.pflav[2];
+}
 
 }  // namespace bbc

@@ -62,7 +62,7 @@ def test_u_d_exchange(field, a, b):
 def test_channel_ids_and_names():
     import paper_1510_00903_amd as bbc
     names = bbc.baryon_names()
-    assert names == ["p", "n", "S+", "S-", "X0", "X-", "L", "S0"]
+    assert names[:8] == ["p", "n", "S+", "S-", "X0", "X-", "L", "S0"]
     # listed channels keep their index
     assert bbc.channel_id("p", "n", "p", "n") == 0
     assert bbc.channel_id("X-", "X0", "X-", "X0") == 51
@@ -78,4 +78,25 @@ def test_channel_ids_and_names():
     with pytest.raises(bbc.BBCError):
         bbc.plan_stats([56 + 1])                      # p p > p n: not a channel
     st = bbc.plan_stats([bbc.channel_id("p", "p", "p", "p")])
+    assert st["iterations"] > 0
+
+
+def test_general_field_ids():
+    import paper_1510_00903_amd as bbc
+    names = bbc.baryon_names()
+    assert names[8:] == ["p2", "n2"] + ["%s(%d)" % (f, l) for f in ("D++", "D-", "O-") for l in (1, 2, 3)]
+    # quadruples with a general field: 4152 + ((b1 * 19 + b2) * 19 + b3) * 19 + b4
+    c = bbc.channel_id("O-(3)", "O-(3)", "O-(3)", "O-(3)")
+    assert c == 4152 + ((18 * 19 + 18) * 19 + 18) * 19 + 18
+    assert bbc.channel_name(c) == "O-(3) O-(3) > O-(3) O-(3)"
+    assert bbc.channel_content(c) == (0, 6)
+    c = bbc.channel_id("p2", "n", "p", "n2")
+    assert c == 4152 + ((8 * 19 + 1) * 19 + 0) * 19 + 9
+    assert bbc.channel_content(c) == (6, 0)
+    assert bbc.channel_id("p", "n", "p", "n") == 0             # octet ids unchanged
+    with pytest.raises(bbc.BBCError):
+        bbc.channel_id("O-(1)", "p", "O-(1)", "n")            # quark content differs
+    with pytest.raises(bbc.BBCError):
+        bbc.channel_name(4152)                                 # octet quadruple in the general range
+    st = bbc.plan_stats([bbc.channel_id("O-(1)", "O-(2)", "O-(1)", "O-(2)")])
     assert st["iterations"] > 0
