@@ -334,6 +334,76 @@ def postproc(bbc, torch, np, steps):
             "kernels": res}
 
 
+def next_rows(bbc, torch, np, synth, steps):
+    """The paths beyond the 52-channel correlator, on the 16^3 x 32 FP64 propagators
+    of the default job:
+      * CPT average (Sec. 6): bbc_correlate_cpt over tau = 0..15 with t0 = 0 (two
+        correlator slices per tau: upper at t0 + tau, lower at t0 - tau mod 32), 52 channels;
+      * general fields (Sec. 2, Eq. (FieldOperator_B)): 25 channels -- Omega- Omega- and
+        Delta++ Delta++ for every (l1, l2) pair (source = sink), four {C, gamma_5} nucleon
+        channels, Omega- p for l = 1, 2, 3 -- over all 32 slices.
+    Wall time over `steps` calls after one warm-up call, per-stage HIP-event times
+    from one more profiled call."""
+    L, T = 16, 32
+    V = L ** 3
+    dev = torch.device("cuda:0")
+    Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 1)
+    d_l, d_s = torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
+    ctx = bbc.Context(0)
+    out = {}
+
+    def timed(fn, n_units):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / steps
+        ctx.profile(True)
+        ctx.profile_read()
+        fn()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        stages = {k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}
+        return {"ms_per_step": round(ms, 3), "value": round(n_units / (ms * 1e-3), 1), "stages_ms": stages}
+
+    taus = list(range(16))
+    chans = list(range(52))
+    R = torch.empty((len(taus), len(chans), L, L, L, 16), dtype=torch.complex128, device=dev)
+    r = timed(lambda: ctx.correlate_cpt(d_l, d_s, 0, taus, chans, out=R), len(taus) * len(chans) * V)
+    r.update({"unit": "averaged site-channels/s", "correlator_slices_per_step": 2 * len(taus),
+              "outputs_finite": bool(torch.isfinite(R).all().item())})
+    out["cpt_average"] = r
+    del R
+
+    quads = []
+    for f in ("O-", "D++"):
+        for l1 in (1, 2, 3):
+            for l2 in (1, 2, 3):
+                a, b = "%s(%d)" % (f, l1), "%s(%d)" % (f, l2)
+                quads.append((a, b, a, b))
+    quads += [("p2", "n2", "p2", "n2"), ("p2", "n", "p", "n2"), ("p", "n2", "p2", "n"), ("p2", "n2", "p", "n")]
+    quads += [("O-(%d)" % l, "p", "O-(%d)" % l, "p") for l in (1, 2, 3)]
+    gch = [bbc.channel_id(*q) for q in quads]
+    C = torch.empty((T, len(gch), L, L, L, 16), dtype=torch.complex128, device=dev)
+    r = timed(lambda: ctx.correlate(d_l, d_s, list(range(T)), gch, out=C), T * len(gch) * V)
+    st = bbc.plan_stats(gch)
+    r.update({"unit": "site-channels/s", "channels": len(gch), "block_components_per_site": st["components"],
+              "iterations": st["iterations"], "outputs_finite": bool(torch.isfinite(C).all().item())})
+    out["general_fields"] = r
+    ctx.close()
+    return {"metric": "CPT average and general-field correlators: site-channels/sec",
+            "value": out["general_fields"]["value"], "unit": "site-channels/s", "n_gpus": 1, "steps": steps,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic (seeded Gaussian propagators, "
+            "exp(-m t) decay; the default job's inputs)",
+            "config": {"workload": "16^3x32 FP64: CPT average (16 tau, 52 channels) and 25 general-field "
+                                   "channels (decuplet Omega-/Delta++, {C, gamma_5} nucleon, Omega- p)",
+                       "lattice": [L, L, L], "T": T},
+            "paths": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,7 +411,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="16c32-f64",
-                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream", "post-16c32"],
+                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream", "post-16c32",
+                             "next-16c32"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
     ap.add_argument("--graph", action="store_true",
@@ -371,6 +442,9 @@ def main():
         return
     if args.workload == "post-16c32":
         print(json.dumps(postproc(bbc, torch, np, args.steps)), flush=True)
+        return
+    if args.workload == "next-16c32":
+        print(json.dumps(next_rows(bbc, torch, np, synth, args.steps)), flush=True)
         return
 
     fp32 = args.workload.endswith("f32")

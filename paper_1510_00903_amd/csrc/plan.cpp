@@ -154,39 +154,70 @@ int perm_sign(const int *p, int n) {
     return s;
 }
 
+// The spin structure an intermediate needs to know of a source baryon with n
+// diquark legs and ncp delta legs at its site: a lone diquark leg carries no
+// tensor factor, a lone delta leg only a row of Gamma_2, two diquark legs only
+// Gamma_1; structures that agree on what is used share the smallest id.
+int effective_spin(int s, int n, int ncp) {
+    if (n == 1 && ncp == 0) return 0;
+    const SpinStruct &S = spin_struct(s);
+    for (int t = 0; t < s; ++t) {
+        const SpinStruct &U = spin_struct(t);
+        bool same = true;
+        for (int m = 0; m < 4; ++m) {
+            if (ncp) same = same && U.p2[m] == S.p2[m] && U.k2[m] == S.k2[m];
+            if (n) same = same && U.p1[m] == S.p1[m] && U.k1[m] == S.k1[m];
+        }
+        if (same) return t;
+    }
+    return s;
+}
+
 // Canonical key of an intermediate from per-role (light/strange, source baryon
 // X, source role a'/b'/c') and the spin structures involved.  Exchanging sink
 // roles a and b together with their propagators multiplies the sink tensor by
 // its exchange sign x (+1 for C gamma_5 and C, -1 for the symmetric C gamma_l),
 // and which source baryon is "first" is a label; the canonical form relabels
 // source baryons by first appearance and takes the smaller of the two role
-// orders (*swapped = 1 if that is b, a, c).  Where a source tensor is symmetric
-// under a' <-> b' the two read alike (0).  ymap receives X -> canonical Y and
-// csrc the spin structure of each canonical Y (-1 if absent).
+// orders.  The source legs a' and b' are relabelled too: in the canonical form
+// the diquark leg at the lower role (or the only local one, next to a local c')
+// is a' and both read 0; where that exchanges a' and b' the intermediate picks
+// up the source field's exchange sign x.  A lone diquark leg without c' carries
+// no tensor factor, so its label is free.  *sign receives the product of these
+// factors for the chosen form, ymap X -> canonical Y, csrc the spin structure
+// of each canonical Y (-1 if absent).
 uint32_t canonical(const int pf[3], const int X[3], const int T[3], int sink_spin, const int src_spin[2],
-                   int ymap[2], int cpf[3], int cy[3], int ct[3], int csrc[2], int *swapped) {
+                   int ymap[2], int cpf[3], int cy[3], int ct[3], int csrc[2], int *sign) {
     uint32_t best = 0xffffffffu;
     const int orders[2][3] = {{0, 1, 2}, {1, 0, 2}};
     for (int o = 0; o < 2; ++o) {
         const int *ord = orders[o];
         int m[2] = {-1, -1}, nx = 0;
         int lpf[3], ly[3], lt[3];
+        int sg = o ? spin_struct(sink_spin).x : 1;
         for (int i = 0; i < 3; ++i) {
             int r = ord[i];
             if (m[X[r]] < 0) m[X[r]] = nx++;
             lpf[i] = pf[r]; ly[i] = m[X[r]];
-            lt[i] = (T[r] != 2 && spin_struct(src_spin[X[r]]).x == 1) ? 0 : T[r];
+            lt[i] = T[r] == 2 ? 2 : 0;
         }
         int ls[2] = {-1, -1};
-        for (int x = 0; x < 2; ++x)
-            if (m[x] >= 0) ls[m[x]] = src_spin[x];
+        for (int x = 0; x < 2; ++x) {
+            if (m[x] < 0) continue;
+            int tp[3], n = 0, ncp = 0;
+            for (int i = 0; i < 3; ++i)
+                if (X[ord[i]] == x) { if (T[ord[i]] == 2) ++ncp; else tp[n++] = T[ord[i]]; }
+            const bool relabel = (n == 2 || (n == 1 && ncp == 1)) && tp[0] == 1;
+            if (relabel) sg *= spin_struct(src_spin[x]).x;
+            ls[m[x]] = effective_spin(src_spin[x], n, ncp);
+        }
         uint32_t key = 0;
         for (int i = 0; i < 3; ++i) key = key * 16 + (uint32_t)((lpf[i] * 2 + ly[i]) * 4 + lt[i]);
         key = (key << 9) | ((uint32_t)sink_spin << 6) | ((uint32_t)(ls[0] < 0 ? 7 : ls[0]) << 3) |
               (uint32_t)(ls[1] < 0 ? 7 : ls[1]);
         if (key < best) {
             best = key;
-            *swapped = o;
+            *sign = sg;
             ymap[0] = m[0]; ymap[1] = m[1];
             csrc[0] = ls[0]; csrc[1] = ls[1];
             for (int i = 0; i < 3; ++i) { cpf[i] = lpf[i]; cy[i] = ly[i]; ct[i] = lt[i]; }
@@ -363,9 +394,9 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
                                     T[r] = rsrc[q];
                                 }
                                 BlockRef br;
-                                int cpf[3], cy[3], ct[3], csrc[2], swapped = 0;
+                                int cpf[3], cy[3], ct[3], csrc[2], csign = 1;
                                 uint32_t key = canonical(pf, X, T, Bs.spin, srcspin, br.ymap, cpf, cy, ct, csrc,
-                                                         &swapped);
+                                                         &csign);
                                 auto it = index->find(key);
                                 if (it == index->end()) {
                                     int id = (int)inters->size();
@@ -373,7 +404,7 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
                                     it = index->emplace(key, id).first;
                                 }
                                 br.inter = it->second;
-                                br.coef = Bs.term[t].w * perm_sign(pi, 3) * (swapped ? spin_struct(Bs.spin).x : 1);
+                                br.coef = Bs.term[t].w * perm_sign(pi, 3) * csign;
                                 d.blk[s].push_back(br);
                             }
                     }
@@ -410,13 +441,13 @@ struct Part { int e[3]; int set[3]; int ph; };     // partial assignment of sour
 // Source tensor (Sec. 3, with the general field of Sec. 2): eps(c'_a c'_b c'_c)
 // Gamma_1(mu'_a, mu'_b) Gamma_2(so + o, mu'_c); the outer spin o selects the row of Gamma_2.
 std::vector<Part> y_parts(const Intermediate &I, int Y, int o, int k, int so) {
+    // canonical labelling: a' is the diquark leg at the lower role, or the only one
     int ra = -1, rb = -1, rd = -1;
     for (int r = 0; r < 3; ++r) {
         if (I.role_y[r] != Y) continue;
         if (I.role_t[r] == 2) rd = r;
-        else if (I.role_t[r] == 1) rb = r;
         else if (ra < 0) ra = r;
-        else rb = r;                 // a' and b' read alike: role order decides
+        else rb = r;
     }
     std::vector<Part> out;
     auto base = []() { Part p{}; p.ph = 0; for (int i = 0; i < 3; ++i) { p.e[i] = 0; p.set[i] = 0; } return p; };

@@ -83,8 +83,8 @@ struct Intermediate {
     uint32_t key;
     int pflav[3];     // per role a, b, c: 0 light, 1 strange
     int role_y[3];    // per role: canonical source baryon 0/1
-    int role_t[3];    // per role: source role 0 = a', 1 = b', 2 = c' (delta quark); a' and b'
-                      // both read 0 when the source tensor is symmetric under a' <-> b' (x = +1)
+    int role_t[3];    // per role: 0 = source diquark leg, 2 = delta quark c'; of two diquark legs
+                      // the one at the lower role is a' (canonical labelling, see canonical())
     int sink_spin;    // spin structure of the sink field
     int src_spin[2];  // spin structure of canonical source baryon Y (-1 if absent)
     int ny;
