@@ -59,15 +59,18 @@ struct DevPlan {
 };
 
 // Contraction tables of a plan.  Per requested channel: its diagrams, cut into
-// segments of whole diagrams holding about kSegItems (diagram, k3, k4) items
-// each.  Every segment owns one partial-result slot; the slots of a channel are
+// segments of whole diagrams holding about seg_items (diagram, k3, k4) items
+// each (seg_items_for: 256 in FP64, 512 in FP32 -- in FP64 the smaller
+// segments give more tasks per momentum group, so fewer groups are in flight
+// per XCD and their 2 MB of data stay in L2).  Every segment owns one partial-result slot; the slots of a channel are
 // contiguous.  Segments, largest first, are dealt four to a task (one per wave
 // of a workgroup).  A diagram records its carry pattern, K = kdim3 * kdim4 and
 // kdim4 with a 16-bit reciprocal, from which a lane rebuilds (k3, k4) = divmod(kk, kdim4).
-constexpr int kSegItems = 512;
+int seg_items_for(bbc_precision prec) { return prec == BBC_F64 ? 256 : 512; }
 
-void contraction_tables(const bbc::Plan &P, std::vector<bbc::DDiag> &diags, std::vector<bbc::DRef> &refs,
-                        std::vector<int4> &segs, std::vector<int32_t> &ch_slot_begin, int *ntask) {
+void contraction_tables(const bbc::Plan &P, int seg_items, std::vector<bbc::DDiag> &diags,
+                        std::vector<bbc::DRef> &refs, std::vector<int4> &segs, std::vector<int32_t> &ch_slot_begin,
+                        int *ntask) {
     const int n = (int)P.channels.size();
     ch_slot_begin.assign(n + 1, 0);
     std::vector<int4> all;   // (first diagram, end diagram, slot, items)
@@ -110,7 +113,7 @@ void contraction_tables(const bbc::Plan &P, std::vector<bbc::DDiag> &diags, std:
             total += D.K;
         }
         const int de = (int)diags.size();
-        const int nseg = (int)std::max<long>(1, (total + kSegItems - 1) / kSegItems);
+        const int nseg = (int)std::max<long>(1, (total + seg_items - 1) / seg_items);
         ch_slot_begin[m] = slot;
         long acc = 0;
         int sb = db;
@@ -248,7 +251,7 @@ struct bbc_context {
     Server srv;
     uint64_t budget = 0;
     std::mutex mu;
-    std::map<std::pair<std::vector<int>, int>, std::unique_ptr<DevPlan>> plans;
+    std::map<std::pair<std::vector<int>, int>, std::unique_ptr<DevPlan>> plans;   // key: (channels, 2 spin_offset + FP32)
     void *ws = nullptr;
     size_t ws_bytes = 0;
     double *d_energy = nullptr;
@@ -311,9 +314,10 @@ struct StageTimer {
 
 namespace {
 
-bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, DevPlan **out) {
+bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, bbc_precision prec,
+                    DevPlan **out) {
     std::lock_guard<std::mutex> lock(ctx->qmu);
-    auto key = std::make_pair(chans, spin_offset);
+    auto key = std::make_pair(chans, spin_offset * 2 + (prec == BBC_F32 ? 1 : 0));
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) { *out = it->second.get(); return BBC_OK; }
     std::unique_ptr<DevPlan> dp(new DevPlan);
@@ -358,7 +362,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
     std::vector<int4> segs;
     std::vector<int32_t> ch_slot_begin;
     try {
-        contraction_tables(P, diags, refs, segs, ch_slot_begin, &dp->ntask);
+        contraction_tables(P, seg_items_for(prec), diags, refs, segs, ch_slot_begin, &dp->ntask);
     } catch (const std::exception &e) {
         return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
     }
@@ -435,7 +439,7 @@ struct MomGroups {
 };
 template <typename T>
 MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
-    constexpr int G = sizeof(T) == 8 ? 4 : 8;   // momenta per group (a component's 2 G values: 128 bytes)
+    constexpr int G = 8;                         // momenta per group
     std::lock_guard<std::mutex> lock(ctx->qmu);
     auto key = std::vector<int>{L[0], L[1], L[2], G};
     auto it = ctx->groups.find(key);
@@ -1007,7 +1011,7 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
         std::vector<int4> segs;
         std::vector<int32_t> csb;
         int ntask = 0;
-        contraction_tables(P, diags, refs, segs, csb, &ntask);
+        contraction_tables(P, seg_items_for(prec), diags, refs, segs, csb, &ntask);
         *bytes = workspace_bytes(V, P.ncomp, n_ch, csb.back(), prec == BBC_F64 ? 16 : 8);
     } catch (const std::exception &e) {
         return fail(BBC_EINVAL, e.what());
@@ -1040,7 +1044,7 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     HIP_TRY(hipSetDevice(ctx->device));
     std::vector<int> chans(ch_list, ch_list + n_ch);
     DevPlan *dp = nullptr;
-    s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, &dp);
+    s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, prec, &dp);
     if (s) return s;
     const int L[3] = {lattice[0], lattice[1], lattice[2]};
     hipStream_t st = (hipStream_t)stream;
@@ -1080,8 +1084,8 @@ bbc_status bbc_correlate_cpt(bbc_context *ctx, const int32_t lattice[3], int Lt,
     HIP_TRY(hipSetDevice(ctx->device));
     std::vector<int> chans(ch_list, ch_list + n_ch);
     DevPlan *up = nullptr, *lo = nullptr;
-    if ((s = get_plan(ctx, chans, 0, &up))) return s;
-    if ((s = get_plan(ctx, chans, 2, &lo))) return s;
+    if ((s = get_plan(ctx, chans, 0, prec, &up))) return s;
+    if ((s = get_plan(ctx, chans, 2, prec, &lo))) return s;
     const int L[3] = {lattice[0], lattice[1], lattice[2]};
     hipStream_t st = (hipStream_t)stream;
     if (prec == BBC_F64)
@@ -1208,7 +1212,7 @@ bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *s
     if (energy) j->energy.assign(energy, energy + n_ch);
     j->out = C_out;
     j->scale = j->ps->prec == BBC_F32 ? C_scale : nullptr;
-    bbc_status s = get_plan(ctx, j->chans, spin == BBC_SPIN_LOWER ? 2 : 0, &j->dp);
+    bbc_status s = get_plan(ctx, j->chans, spin == BBC_SPIN_LOWER ? 2 : 0, (bbc_precision)j->ps->prec, &j->dp);
     if (s) return s;
     j->foot = job_footprint(*j);
     if (ctx->budget && j->foot > ctx->budget) return fail(BBC_ENOMEM, "job workspace exceeds the HBM budget");

@@ -564,13 +564,14 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
 // ----------------------------------------------------------------------------
 // ----------------------------------------------------------------------------
 // Momentum groups.  The contraction pairs every momentum q with -q.  Momenta are
-// packed into groups of G (4 in FP64, 8 in FP32) that are closed under
-// q -> -q, and the momentum-space intermediates are stored group by group:
-// per group and component c, the two sink spins g and the G momenta,
+// packed into groups of G = 8 that are closed under q -> -q, and the
+// momentum-space intermediates are stored group by group: per group and
+// component c, the two sink spins g and the G momenta,
 //   FP64: [group][c][g][G]      FP32: [group][c][G][g],
-// so that one component of a group fills one 128-byte line (2 x G complex
-// numbers), both sites of a pair (q and -q) read inside the same group, and in
-// FP32 one 16-byte load fetches both sink spins of a momentum.
+// so that every load of eight lanes fills whole 128-byte lines (FP64: one line
+// per sink spin; FP32: one line holds both, and one 16-byte load fetches both
+// sink spins of a momentum), and both sites of a pair (q and -q) read inside
+// the same group.
 // gpos[p] = (momentum held by position p, or -1 for a padding slot; lane of -q
 // within the group).
 // ----------------------------------------------------------------------------
@@ -578,9 +579,9 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
 // c * 2G + j * S + g * SG.
 template <typename T2> struct GroupLayout;
 template <> struct GroupLayout<double2> {
-    static constexpr int G = 4;
+    static constexpr int G = 8;
     static constexpr int S = 1;      // stride of the momentum lane
-    static constexpr int SG = 4;     // stride of the sink spin
+    static constexpr int SG = 8;     // stride of the sink spin
 };
 template <> struct GroupLayout<float2> {
     static constexpr int G = 8;
@@ -670,7 +671,12 @@ __global__ __launch_bounds__(256) void k_fft3d_grouped(const typename cplx_t<T>:
     __shared__ T2 buf[N * N * NP];
     __shared__ T2 tw[N];
     const int t = threadIdx.x;
-    const int g = blockIdx.x / nc, c = blockIdx.x - g * nc;
+    // the two sink spins of a component run back to back on one XCD (consecutive
+    // workgroup ids cycle over the 8 XCDs), so the halves of each output line they
+    // write meet in that XCD's L2
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int g = j & 1, c = xcd * (int)(gridDim.x >> 4) + (j >> 1);
+    if (c >= nc) return;
     const bool line = t < N * N;
     // issue every global load first: this thread's z line (x, y) = (t % N, t / N)
     // and the momenta of its output positions
@@ -744,7 +750,7 @@ int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>:
     using T2 = typename cplx_t<T>::type;
     if (!fft3d_grouped_fits<T>(L)) return -1;
     const long npos = (long)ngroup * GroupLayout<T2>::G;
-    const dim3 grid((unsigned)(2 * nc));
+    const dim3 grid((unsigned)(16 * ((nc + 7) / 8)));     // 8 XCDs x 2 spins x ceil(nc / 8)
     switch (L[0]) {
     case 4: hipLaunchKernelGGL((k_fft3d_grouped<T, 4>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
     case 6: hipLaunchKernelGGL((k_fft3d_grouped<T, 6>), grid, dim3(256), 0, st, in, out, nc, npos, gpos, -1); break;
@@ -769,13 +775,13 @@ int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>:
 // diagram and block tables are wave-uniform (scalar loads); its 64 lanes are
 // 64/G open-index lanes x G momentum lanes, each open-index lane taking one
 // (k3, k4) of the diagram per step.  The G momentum lanes of an open index read
-// one 64-byte sector per load.  Workgroup ids are mapped so that all tasks of
+// one 128-byte line per load.  Workgroup ids are mapped so that all tasks of
 // a group run back to back on the same XCD: the group's intermediates (the
-// only data the tasks read, about 1 MB) then stay in that XCD's L2.  Each wave
+// only data the tasks read, about 2 MB) then stay in that XCD's L2.  Each wave
 // reduces its segment and writes one partial result slot per momentum;
 // k_combine adds the slots of a channel in a fixed order (no atomics: results
 // are bit-reproducible).
-// Iq layout: [group][g][nc][G]; slot layout: [slot][16][V].
+// Iq layout: GroupLayout (per group, component-major); slot layout: [slot][16][V].
 // ----------------------------------------------------------------------------
 // One diagram for this lane's momentum: sum over the (k3, k4) taken by this
 // open-index lane of E1(q) (x) E2(-q), each block value E a weighted sum of
@@ -794,6 +800,7 @@ __device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__re
     constexpr int NI = 64 / G;
     constexpr int N1 = 1 << ((C3 == 0) + (C4 == 0));   // outer-spin combinations held by site 0
     constexpr int N2 = 4 / N1;
+    constexpr int kRefUnroll = sizeof(T) == 4 ? 2 : 1;
     const int K = (D.pad[0] >> 2) & 255, kd4 = (D.pad[0] >> 10) & 15, inv = D.pad[1];
     const double dc = D.coef;
     for (int c = 0; c < K; c += NI * IPL) {
@@ -817,6 +824,9 @@ __device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__re
 #pragma unroll
             for (int i = 0; i < 2 * N2; ++i) e2[u][i] = T2{0, 0};
         }
+        // FP32: two block refs per iteration keep more loads in flight (in FP64 the
+        // extra registers cost more than they gain)
+#pragma unroll kRefUnroll
         for (int r = D.ref0; r < D.ref0_end; ++r) {
             const DRef R = refs[r];
             const T c0 = T(R.coef);
@@ -839,6 +849,7 @@ __device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__re
                 }
             }
         }
+#pragma unroll kRefUnroll
         for (int r = D.ref1; r < D.ref1_end; ++r) {
             const DRef R = refs[r];
             const T c0 = T(R.coef);
