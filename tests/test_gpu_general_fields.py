@@ -84,3 +84,39 @@ def test_decuplet_flavour_relations_8cubed(bbc, ctx, dtype, tol):
     assert np.abs(a[0, 1] - a[0, 0]).max() <= tol * scale
     assert np.abs(b[0, 2] - b[0, 0]).max() <= tol * np.abs(b[0, 0]).max()
     assert np.abs(a[0, 2] - a[0, 0]).max() > 1e-3 * scale
+
+
+def test_rotation_covariance_on_gpu(bbc, ctx):
+    """The GPU's correlators of 90-degree-rotated propagators are the rotated GPU
+    correlators (maps from the Clifford algebra, see test_rotation_pins), at 6^3 x 4."""
+    import itertools
+    import test_rotation_pins as rp
+    lam = rp.spinor_rotation()
+    fams, members = ("O", "p", "O", "p"), (0, 0, 1, 0)
+    maps = [rp.family_maps(rp.FAMILIES[f], lam) for f in fams]
+    lat = (6, 6, 4)
+    Sl, Ss = synth.propagators(lat, 1, seed=157)
+    Slr, Ssr = rp.rotate_props(Sl[0], lam)[None], rp.rotate_props(Ss[0], lam)[None]
+    keys = list(itertools.product(*[range(len(rp.FAMILIES[f])) for f in fams]))
+    names = {k: tuple(rp.FAMILIES[f][m] for f, m in zip(fams, k)) for k in keys}
+    chans = [bbc.channel_id(*names[k]) for k in keys]
+    base = run(ctx, Sl, Ss, chans)[0]
+    target = bbc.channel_id(*names[members])
+    got = run(ctx, Slr, Ssr, [target])[0, 0].reshape(-1, 16)
+    Lx, Ly, Lz = lat
+    r = wick.all_r(*lat)
+    rinv = [((ry % Lx) + Lx * (((-rx) % Ly) + Ly * rz)) for rx, ry, rz in r]
+    rows = [maps[i][0] if i < 2 else maps[i][1] for i in range(4)]
+    want = np.zeros_like(got)
+    for a, b, ap, bp in itertools.product(range(2), repeat=4):
+        s_out = a + 2 * (b + 2 * (ap + 2 * bp))
+        k = [members[0] * 4 + a, members[1] * 4 + b, members[2] * 4 + ap, members[3] * 4 + bp]
+        for j, key in enumerate(keys):
+            field = base[j].reshape(-1, 16)
+            for d1, d2, d3, d4 in itertools.product(range(2), repeat=4):
+                c = (rows[0][k[0], key[0] * 4 + d1] * rows[1][k[1], key[1] * 4 + d2] *
+                     rows[2][k[2], key[2] * 4 + d3] * rows[3][k[3], key[3] * 4 + d4])
+                if abs(c) > 1e-14:
+                    want[:, s_out] += c * field[rinv, d1 + 2 * (d2 + 2 * (d3 + 2 * d4))]
+    assert np.abs(got).max() > 0
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
