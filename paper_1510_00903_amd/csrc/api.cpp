@@ -435,6 +435,7 @@ bbc_status check_lattice(const int32_t *lattice, long *V) {
 // Device table of the momentum groups for precision T.
 struct MomGroups {
     const int2 *pos = nullptr;
+    const int *posof = nullptr;   // momentum -> position (V entries)
     int ngroup = 0;
 };
 template <typename T>
@@ -444,10 +445,17 @@ MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
     auto key = std::vector<int>{L[0], L[1], L[2], G};
     auto it = ctx->groups.find(key);
     const long V = (long)L[0] * L[1] * L[2];
+    const long npos = grouped_positions(V, L, G);
     if (it == ctx->groups.end()) {
+        // one allocation: the npos position entries, then the V momentum -> position entries
         std::vector<int2> g = momentum_groups(L, G);
+        std::vector<int2> all(g);
+        all.resize(npos + (V + 1) / 2);
+        int *posof = reinterpret_cast<int *>(all.data() + npos);
+        for (long p = 0; p < npos; ++p)
+            if (g[p].x >= 0) posof[g[p].x] = (int)p;
         int2 *d = nullptr;
-        hipError_t e = upload_vec(&d, g);
+        hipError_t e = upload_vec(&d, all);
         if (e != hipSuccess) {
             *st = fail(BBC_EDEVICE, std::string("momentum group upload: ") + hipGetErrorString(e));
             return MomGroups{};
@@ -455,7 +463,7 @@ MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
         it = ctx->groups.emplace(key, d).first;
     }
     *st = BBC_OK;
-    return MomGroups{it->second, (int)(grouped_positions(V, L, G) / G)};
+    return MomGroups{it->second, reinterpret_cast<const int *>(it->second + npos), (int)(npos / G)};
 }
 
 // Launches the kernel sequence of one time slice on stream st, using the
@@ -486,18 +494,24 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin, dp->pats,
                               fp32 ? kmax : nullptr, st);
     }
-    // small cubic lattices: one fused pass (FFT in LDS, written straight into the groups)
+    // small cubic lattices: one fused pass (FFT in LDS, written straight into the
+    // groups); 24- and 32-point planes: plane passes, then the z pass writes into
+    // the groups; otherwise axis passes and a separate copy into the groups
     const bool fused = bbc::fft3d_grouped_fits<T>(L);
+    const bool zgrouped = !fused && bbc::fft3d_zgrouped_fits<T>(L);
     {
         StageTimer tm(pc, st, 1);
         if (fused) {
             if (bbc::launch_fft3d_grouped<T>(I, Iq, nc, L, mg.ngroup, mg.pos, st))
                 return fail(BBC_EUNSUPPORTED, "FFT size");
+        } else if (zgrouped) {
+            if ((tm.nk = bbc::launch_fft3d_zgrouped<T>(I, Iq, nc, L, mg.posof, st)) < 0)
+                return fail(BBC_EUNSUPPORTED, "FFT size");
         } else if ((tm.nk = bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) < 0) {
             return fail(BBC_EUNSUPPORTED, "FFT size");
         }
     }
-    if (!fused) {
+    if (!fused && !zgrouped) {
         StageTimer tm(pc, st, 2);
         bbc::launch_transpose_grouped<T>(I, Iq, nc, V, mg.ngroup, mg.pos, st);
     }

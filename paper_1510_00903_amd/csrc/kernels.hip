@@ -6,7 +6,10 @@
 //   k_blocks     step 1a: every block intermediate at every site        (site-local)
 //   k_fft (x3)   step 1b: forward 3-D FFT of every component            (one pass per axis)
 //   k_fft3d_grouped  step 1b fused with the grouped copy, one pass (small cubic lattices)
-//   k_transpose_grouped  component-major [g][comp][q] -> momentum groups (GroupLayout)
+//   k_fft_xy + k_fft_z_grouped  step 1b for 24- and 32-point planes: plane pass, then
+//                the z pass writing into the momentum groups
+//   k_transpose_grouped  component-major [g][comp][q] -> momentum groups (GroupLayout;
+//                lattices without a fused form)
 //   k_contract   step 2a: open-index sums per momentum, all channels    (workgroups per group)
 //   k_fft (x3)   step 2b: inverse 3-D FFT of the 16 spin components per channel
 //   k_finalize   normalisation and transpose to the output layout [r][spin]
@@ -733,6 +736,102 @@ __global__ __launch_bounds__(256) void k_fft3d_grouped(const typename cplx_t<T>:
     }
 }
 
+// ----------------------------------------------------------------------------
+// Last (z) pass of the forward FFT fused with the copy into the momentum groups,
+// for lattices whose x and y transforms ran as plane passes: each thread
+// transforms one z line of one (sink spin g, component c) in registers and
+// writes its N momenta to their group positions (posof: momentum -> position).
+// A workgroup takes 256 lines of one (g, c); all chunks of (c, 0) and then of
+// (c, 1) run back to back on one XCD (consecutive workgroup ids cycle over the
+// 8 XCDs), so the lanes of each output line -- q and -q, and in FP32 both sink
+// spins -- are written close together in time and meet in that XCD's L2.
+// Replaces the z axis pass and k_transpose_grouped.
+// ----------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>::type *__restrict__ in,
+                                                       typename cplx_t<T>::type *__restrict__ out, int nc,
+                                                       int nxy, int nchunk, const int *__restrict__ posof,
+                                                       int sgn) {
+    using T2 = typename cplx_t<T>::type;
+    using Ly = GroupLayout<T2>;
+    constexpr int G = Ly::G;
+    __shared__ T2 tw[N];
+    const int t = threadIdx.x;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int per_c = 2 * nchunk;                    // workgroups of one component on its XCD
+    const int c = xcd * (int)(gridDim.x / (8 * per_c)) + j / per_c;
+    const int r = j - (j / per_c) * per_c;
+    const int g = r / nchunk, chunk = r - g * nchunk;
+    for (int i = t; i < N; i += 256) {
+        double sn, cs;
+        sincospi(2.0 * i / N, &sn, &cs);
+        tw[i] = T2{T(cs), T(sgn * sn)};
+    }
+    __syncthreads();
+    if (c >= nc) return;
+    const int line = chunk * 256 + t;                // (x, y) = (line % Lx, line / Lx)
+    if (line >= nxy) return;
+    const T2 *src = in + ((long)g * nc + c) * (long)nxy * N + line;
+    T2 a[N], b[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] = src[(long)k * nxy];
+    int pk[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) pk[k] = posof[line + k * nxy];
+    Stages<T2, N, 1>::run(a, b, tw, sgn);
+    T2 *dst = out + (long)c * 2 * G + g * Ly::SG;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int p = pk[k];
+        dst[(long)(p / G) * nc * 2 * G + (p % G) * Ly::S] = a[k];
+    }
+}
+
+// Whether the plane pass + fused z pass applies: Lx = Ly in {24, 32}, Lz with a
+// register transform.
+template <typename T> bool fft3d_zgrouped_fits(const int L[3]) {
+    if (L[0] != L[1] || (L[0] != 24 && L[0] != 32)) return false;
+    switch (L[2]) {
+    case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: return true;
+    default: return false;
+    }
+}
+
+template <typename T, int N>
+static void fft_z_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, int nxy,
+                          const int *posof, hipStream_t st) {
+    const int nchunk = (nxy + 255) / 256;
+    const long per_xcd = (long)((nc + 7) / 8) * 2 * nchunk;
+    hipLaunchKernelGGL((k_fft_z_grouped<T, N>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, in, out, nc, nxy,
+                       nchunk, posof, -1);
+}
+
+// Forward 3-D FFT of the intermediates into the momentum groups: x and y as
+// plane passes in place on `in`, then the fused z pass.  Returns the number of
+// kernels launched, or -1 if the lattice does not fit this form.
+template <typename T>
+int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
+                          const int *posof, hipStream_t st) {
+    if (!fft3d_zgrouped_fits<T>(L)) return -1;
+    const long ncomp = 2L * nc;
+    if (L[0] == 24) fft_xy<T, 24>(in, ncomp * L[2], -1, st);
+    else fft_xy<T, 32>(in, ncomp * L[2], -1, st);
+    const int nxy = L[0] * L[1];
+    switch (L[2]) {
+    case 2: fft_z_grouped<T, 2>(in, out, nc, nxy, posof, st); break;
+    case 3: fft_z_grouped<T, 3>(in, out, nc, nxy, posof, st); break;
+    case 4: fft_z_grouped<T, 4>(in, out, nc, nxy, posof, st); break;
+    case 6: fft_z_grouped<T, 6>(in, out, nc, nxy, posof, st); break;
+    case 8: fft_z_grouped<T, 8>(in, out, nc, nxy, posof, st); break;
+    case 12: fft_z_grouped<T, 12>(in, out, nc, nxy, posof, st); break;
+    case 16: fft_z_grouped<T, 16>(in, out, nc, nxy, posof, st); break;
+    case 24: fft_z_grouped<T, 24>(in, out, nc, nxy, posof, st); break;
+    case 32: fft_z_grouped<T, 32>(in, out, nc, nxy, posof, st); break;
+    default: return -1;
+    }
+    return 2;
+}
+
 // Whether the fused single-pass form applies: cubic lattice, N^3 complex <= 64 KB.
 template <typename T> bool fft3d_grouped_fits(const int L[3]) {
     using T2 = typename cplx_t<T>::type;
@@ -1055,6 +1154,10 @@ template void launch_blocks<double>(const double2 *, const double2 *, double2 *,
 template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
                                    const int32_t *, const BlockPatterns &, const uint32_t *, hipStream_t);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
+template int launch_fft3d_zgrouped<double>(double2 *, double2 *, int, const int[3], const int *, hipStream_t);
+template int launch_fft3d_zgrouped<float>(float2 *, float2 *, int, const int[3], const int *, hipStream_t);
+template bool fft3d_zgrouped_fits<double>(const int[3]);
+template bool fft3d_zgrouped_fits<float>(const int[3]);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
 template void launch_transpose_grouped<double>(const double2 *, double2 *, int, long, int, const int2 *,
                                                hipStream_t);

@@ -73,6 +73,13 @@ void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, h
 
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sign, hipStream_t st);
+// Forward FFT of the 2 nc intermediates (in place in `in` for x and y) with the z
+// pass writing straight into the momentum groups of `out`; posof[q] = position
+// of momentum q.  Returns kernels launched, -1 if the lattice does not fit.
+template <typename T> bool fft3d_zgrouped_fits(const int L[3]);
+template <typename T>
+int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
+                          const int *posof, hipStream_t st);
 
 // Momentum-grouped copy: in [g][nc][V] (component-major) -> out, per group of G
 // momenta (4 in FP64, 8 in FP32) and component, both sink spins and the G
