@@ -383,6 +383,18 @@ static void fft_xy(typename cplx_t<T>::type *data, long nplanes, int sgn, hipStr
                        sgn);
 }
 
+// Square planes with a plane pass: 24 and 32 points; 96 points in FP32 (one
+// 96 x 97 plane, 74.5 KB of LDS, per workgroup).
+template <typename T> constexpr bool plane_pass_fits(int n) {
+    return n == 24 || n == 32 || (n == 96 && sizeof(T) == 4);
+}
+template <typename T>
+static void plane_pass(typename cplx_t<T>::type *data, long nplanes, int n, int sgn, hipStream_t st) {
+    if (n == 24) fft_xy<T, 24>(data, nplanes, sgn, st);
+    else if (n == 32) fft_xy<T, 32>(data, nplanes, sgn, st);
+    else if constexpr (sizeof(T) == 4) fft_xy<T, 96>(data, nplanes, sgn, st);
+}
+
 // Long lines (N = N1 * N2) along one axis, without holding a whole line per
 // thread: a tile of W lines adjacent in memory is staged in
 // LDS ([point][line], coalesced loads and stores), then the two-factor form
@@ -514,9 +526,8 @@ static void fft_axis96(typename cplx_t<T>::type *data, long ncomp, const int L[3
 
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sgn, hipStream_t st) {
-    if (L[0] == L[1] && (L[0] == 24 || L[0] == 32)) {   // x and y in one plane pass, then z
-        if (L[0] == 24) fft_xy<T, 24>(data, ncomp * L[2], sgn, st);
-        else fft_xy<T, 32>(data, ncomp * L[2], sgn, st);
+    if (L[0] == L[1] && plane_pass_fits<T>(L[0])) {   // x and y in one plane pass, then z
+        plane_pass<T>(data, ncomp * L[2], L[0], sgn, st);
         int n = 1;
         const int Lz = L[2];
         if (Lz > 1) {
@@ -790,9 +801,10 @@ __global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>:
 // Whether the plane pass + fused z pass applies: Lx = Ly in {24, 32}, Lz with a
 // register transform.
 template <typename T> bool fft3d_zgrouped_fits(const int L[3]) {
-    if (L[0] != L[1] || (L[0] != 24 && L[0] != 32)) return false;
+    if (L[0] != L[1] || !plane_pass_fits<T>(L[0])) return false;
     switch (L[2]) {
     case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: return true;
+    case 96: return sizeof(T) == 4;
     default: return false;
     }
 }
@@ -814,8 +826,7 @@ int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type
                           const int *posof, hipStream_t st) {
     if (!fft3d_zgrouped_fits<T>(L)) return -1;
     const long ncomp = 2L * nc;
-    if (L[0] == 24) fft_xy<T, 24>(in, ncomp * L[2], -1, st);
-    else fft_xy<T, 32>(in, ncomp * L[2], -1, st);
+    plane_pass<T>(in, ncomp * L[2], L[0], -1, st);
     const int nxy = L[0] * L[1];
     switch (L[2]) {
     case 2: fft_z_grouped<T, 2>(in, out, nc, nxy, posof, st); break;
@@ -827,6 +838,9 @@ int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type
     case 16: fft_z_grouped<T, 16>(in, out, nc, nxy, posof, st); break;
     case 24: fft_z_grouped<T, 24>(in, out, nc, nxy, posof, st); break;
     case 32: fft_z_grouped<T, 32>(in, out, nc, nxy, posof, st); break;
+    case 96:
+        if constexpr (sizeof(T) == 4) { fft_z_grouped<T, 96>(in, out, nc, nxy, posof, st); break; }
+        return -1;
     default: return -1;
     }
     return 2;
