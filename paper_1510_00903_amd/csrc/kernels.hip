@@ -1126,30 +1126,46 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
                                                   double *__restrict__ scale_out, const uint32_t *__restrict__ kmax,
                                                   const int2 *__restrict__ content) {
     using T2 = typename cplx_t<T>::type;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n_ch * V;
-         i += (long)gridDim.x * blockDim.x) {
-    const int m = (int)(i / V), x = (int)(i - (long)m * V);
-    const double e = energy ? exp(energy[m] * dt) : 1.0;
-    T f;
-    if (scale_out) {
-        // FP64 factor: exp(E (t - t0)) and the inverse of the propagator rescale,
-        // kappa_l^-n_l kappa_s^-n_s with kappa = 2^-e (exact powers of two)
-        f = T(inv_v);
-        if (x == 0) {
-            const int el = kmax ? pow2_exponent(__uint_as_float(kmax[0])) : 0;
-            const int es = kmax ? pow2_exponent(__uint_as_float(kmax[1])) : 0;
-            const int2 nls = content[m];
-            scale_out[m] = ldexp(e, el * nls.x + es * nls.y);
+    // a tile of 256 sites x 16 spins of one channel: read along the sites (one spin
+    // row at a time), written as one contiguous run of the [site][spin] output
+    __shared__ T2 tile[256][17];
+    const int t = threadIdx.x;
+    const long nchunk = (V + 255) / 256;
+    for (long blk = blockIdx.x; blk < (long)n_ch * nchunk; blk += gridDim.x) {
+        const int m = (int)(blk / nchunk);
+        const int x0 = (int)(blk - (long)m * nchunk) * 256;
+        const double e = energy ? exp(energy[m] * dt) : 1.0;
+        T f;
+        if (scale_out) {
+            // FP64 factor: exp(E (t - t0)) and the inverse of the propagator rescale,
+            // kappa_l^-n_l kappa_s^-n_s with kappa = 2^-e (exact powers of two)
+            f = T(inv_v);
+            if (x0 == 0 && t == 0) {
+                const int el = kmax ? pow2_exponent(__uint_as_float(kmax[0])) : 0;
+                const int es = kmax ? pow2_exponent(__uint_as_float(kmax[1])) : 0;
+                const int2 nls = content[m];
+                scale_out[m] = ldexp(e, el * nls.x + es * nls.y);
+            }
+        } else {
+            f = T(e * inv_v);
         }
-    } else {
-        f = T(e * inv_v);
-    }
-    T2 *o = out + ((size_t)m * V + x) * 16;
+        const int x = x0 + t;
+        if (x < V) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        T2 v = Ct[((size_t)m * 16 + s) * V + x];
-        o[s] = T2{v.x * f, v.y * f};
-    }
+            for (int s = 0; s < 16; ++s) tile[t][s] = Ct[((size_t)m * 16 + s) * V + x];
+        }
+        __syncthreads();
+        const int nsite = min(256, V - x0);
+        T2 *o = out + ((size_t)m * V + x0) * 16;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int idx = k * 256 + t, site = idx >> 4, s = idx & 15;
+            if (site < nsite) {
+                const T2 v = tile[site][s];
+                o[idx] = T2{v.x * f, v.y * f};
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1157,9 +1173,10 @@ template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
                      const int2 *content, hipStream_t st) {
-    const long n = (long)n_ch * V;
-    hipLaunchKernelGGL((k_finalize<T>), dim3(grid1d(n)), dim3(256), 0, st, Ct, out, n_ch, V,
-                       energy, dt, inv_v, scale_out, kmax, content);
+    const long nblk = (long)n_ch * ((V + 255) / 256);
+    const unsigned grid = (unsigned)std::min<long>(nblk, 1L << 22);
+    hipLaunchKernelGGL((k_finalize<T>), dim3(grid), dim3(256), 0, st, Ct, out, n_ch, V, energy, dt, inv_v,
+                       scale_out, kmax, content);
 }
 
 // explicit instantiations
