@@ -114,7 +114,7 @@ def test_other_charge_states_isospin_on_gpu_8cubed(bbc, ctx):
     assert normwise(i1, pp) < TOL64
 
 
-@pytest.mark.parametrize("lat", [(32, 32, 2), (24, 24, 3), (96, 96, 2)])
+@pytest.mark.parametrize("lat", [(32, 32, 2), (24, 24, 3), (96, 96, 2), (24, 24, 32), (32, 32, 24)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_plane_fft_extents(bbc, ctx, lat, prec):
     """Lattices whose x and y extents (24, 32; 96 in FP32) take the plane FFT pass,
