@@ -138,6 +138,27 @@ def test_plane_fft_extents(bbc, ctx, lat, prec):
         assert normwise(got, ref) < (TOL64 if prec == "f64" else 1e-5), (lat, prec, c)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_z96_sampled_points(bbc, ctx, prec):
+    """A 96-point z axis after a plane pass (24 x 24 x 96): in FP32 the z pass writes
+    into the momentum groups, in FP64 it takes the two-factor LDS form and the copy;
+    sampled r points of two channels against the oracle."""
+    lat = (24, 24, 96)
+    Lx, Ly, Lz = lat
+    dtype = np.complex128 if prec == "f64" else np.complex64
+    Sl, Ss = synth.propagators(lat, 1, seed=117, dtype=dtype)
+    chans = [0, 5]
+    print("case: lattice", lat, prec, flush=True)
+    res = gpu_correlate(ctx, Sl, Ss, [0], chans)
+    out = res[0] * res[1][:, :, None, None, None, None] if prec == "f32" else res
+    r = np.array([[0, 0, 0], [3, 20, 95], [12, 12, 48], [7, 1, 33]], dtype=np.int32)
+    Sl64, Ss64 = Sl.astype(np.complex128), Ss.astype(np.complex128)
+    for m, c in enumerate(chans):
+        ref = wick.correlate(Sl64[0], Ss64[0], ops.CHANNELS[c], r)
+        got = np.stack([out[0, m, rz, ry, rx] for rx, ry, rz in r])
+        assert normwise(got, ref) < (TOL64 if prec == "f64" else 1e-5), (prec, c)
+
+
 @pytest.mark.parametrize("lat", [(48, 2, 2), (2, 48, 2), (2, 2, 48), (96, 1, 2), (1, 64, 1)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_long_line_fft_extents(bbc, ctx, lat, prec):
