@@ -80,13 +80,32 @@ BARYONS = {
 # General fields of Sec. 2, Eq. (FieldOperator_B): B = eps ((q1 Gamma_1 q2) Gamma_2 q3).
 #  * "p2", "n2": the nucleon with {Gamma_1, Gamma_2} = {C, gamma_5} (same flavour terms as p, n);
 #  * decuplet fields with {C gamma_l, 1} (Sec. 4 footnote), l = 1, 2, 3 in the name:
-#    Delta++ (uuu), Delta- (ddd), Omega- (sss), one term each.
-DECUPLET = {"D++": ("u", "u", "u"), "D-": ("d", "d", "d"), "O-": ("s", "s", "s")}
+#    Delta++ (uuu), Delta- (ddd), Omega- (sss), one term each; the members of
+#    mixed flavour as the symmetric flavour combinations (a reading: the paper gives
+#    no flavour wavefunctions), each term the literal Grassmann string eps (q1 G q2) q3:
+#      Delta+  = (2 (u G d) u + (u G u) d) / sqrt3      Delta0 = (2 (d G u) d + (d G d) u) / sqrt3
+#      Sigma*+ = (2 (u G s) u + (u G u) s) / sqrt3      Sigma*- = (2 (d G s) d + (d G d) s) / sqrt3
+#      Sigma*0 = sqrt(2/3) ((u G d) s + (d G s) u + (s G u) d)
+#      Xi*0    = (2 (s G u) s + (s G s) u) / sqrt3      Xi*-   = (2 (s G d) s + (s G s) d) / sqrt3
+#    (Delta+ is T_- Delta++ / sqrt3 with T_- replacing one u by d.)
+_R3, _R23 = 1.0 / math.sqrt(3.0), math.sqrt(2.0 / 3.0)
+DECUPLET = {
+    "D++": [(1.0, ("u", "u", "u"))],
+    "D-": [(1.0, ("d", "d", "d"))],
+    "O-": [(1.0, ("s", "s", "s"))],
+    "D+": [(2 * _R3, ("u", "d", "u")), (_R3, ("u", "u", "d"))],
+    "D0": [(2 * _R3, ("d", "u", "d")), (_R3, ("d", "d", "u"))],
+    "S*+": [(2 * _R3, ("u", "s", "u")), (_R3, ("u", "u", "s"))],
+    "S*0": [(_R23, ("u", "d", "s")), (_R23, ("d", "s", "u")), (_R23, ("s", "u", "d"))],
+    "S*-": [(2 * _R3, ("d", "s", "d")), (_R3, ("d", "d", "s"))],
+    "X*0": [(2 * _R3, ("s", "u", "s")), (_R3, ("s", "s", "u"))],
+    "X*-": [(2 * _R3, ("s", "d", "s")), (_R3, ("s", "s", "d"))],
+}
 BARYONS["p2"] = BARYONS["p"]
 BARYONS["n2"] = BARYONS["n"]
-for _name, _f in DECUPLET.items():
+for _name, _terms in DECUPLET.items():
     for _l in (1, 2, 3):
-        BARYONS["%s(%d)" % (_name, _l)] = [(1.0, _f)]
+        BARYONS["%s(%d)" % (_name, _l)] = _terms
 
 
 def spin_structure(name):

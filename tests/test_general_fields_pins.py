@@ -95,3 +95,47 @@ def test_octet_through_general_path():
     assert rel(b, a) > 1e-3
     ob = brute.correlate(Sl[0], Ss[0], ("p", "n", "p", "n"), r, spins=[0, 15])
     assert rel(ob[:, [0, 15]], a[:, [0, 15]]) < 1e-12
+
+
+@pytest.mark.parametrize("ch,spins", [
+    (("D+(1)", "D+(2)", "D+(1)", "D+(2)"), [0, 15]),
+    (("S*0(3)", "p", "S*0(3)", "p"), [5]),
+])
+def test_mixed_decuplet_equals_brute_force(ch, spins):
+    Sl, Ss = synth.propagators((1, 1, 1), 1, seed=41)
+    ob = brute.correlate(Sl[0], Ss[0], ch, [(0, 0, 0)], spins=spins)
+    ow = wick.correlate(Sl[0], Ss[0], ch, [(0, 0, 0)])
+    assert np.abs(ow[:, spins]).max() > 0
+    assert rel(ob[:, spins], ow[:, spins]) < 1e-12
+
+
+def test_decuplet_isospin_three():
+    """S_u = S_d: the I = 3, I3 = 2 state (D++ D+ + D+ D++)/sqrt2 has the correlator of the
+    I3 = 3 state D++ D++, elementwise (D+ = T_- D++ / sqrt3 fixes its normalisation and phase)."""
+    lat = (2, 2, 1)
+    r = wick.all_r(*lat)
+    Sl, Ss = synth.propagators(lat, 1, seed=43)
+    a, b = "D++(1)", "D+(1)"
+    top = wick.correlate(Sl[0], Ss[0], (a, a, a, a), r)
+    pair = 0.5 * sum(wick.correlate(Sl[0], Ss[0], snk + src, r)
+                     for snk in ((a, b), (b, a)) for src in ((a, b), (b, a)))
+    assert np.abs(top).max() > 0
+    assert rel(pair, top) < 1e-12
+    # D+ D+ mixes I = 3, 2, 1, 0: its correlator is a different quantity
+    assert rel(wick.correlate(Sl[0], Ss[0], (b, b, b, b), r), top) > 1e-3
+
+
+@pytest.mark.parametrize("x,y,su3", [("S*+(2)", "S*-(2)", False), ("X*0(1)", "X*-(1)", False),
+                                     ("S*+(2)", "D+(2)", True), ("X*0(3)", "D0(3)", True)])
+def test_mixed_decuplet_flavour_relations(x, y, su3):
+    """u <-> d (S_u = S_d): S*+ <-> S*-, X*0 <-> X*-; with S_s = S_l the s quarks relabel:
+    S*+ (u s u) <-> D+ (u d u), X*0 (s u s) <-> D0 (d u d)."""
+    lat = (2, 2, 1)
+    r = wick.all_r(*lat)
+    Sl, Ss = synth.propagators(lat, 1, seed=47)
+    if su3:
+        Ss = Sl.copy()
+    cx = wick.correlate(Sl[0], Ss[0], (x, x, x, x), r)
+    cy = wick.correlate(Sl[0], Ss[0], (y, y, y, y), r)
+    assert np.abs(cx).max() > 0
+    assert rel(cy, cx) < 1e-12
