@@ -81,19 +81,21 @@ int bbc_num_channels_all(void);      /* 56 */
    accepts these ids.
 
    General fields (Sec. 2, Eq. (FieldOperator_B): B = eps((q1 Gamma_1 q2) Gamma_2 q3)):
-   baryon indices 8..18 name
+   baryon indices 8..39 name
      8, 9    p2, n2: the nucleon with {Gamma_1, Gamma_2} = {C, gamma_5}, flavour
              terms as p and n;
-     10..18  D++(l), D-(l), O-(l) for l = 1, 2, 3 (indices 10 + 3 f + l - 1, f = 0
-             Delta++ uuu, 1 Delta- ddd, 2 Omega- sss): decuplet fields with
-             {C gamma_l, 1} (Sec. 4 footnote), one term each.
+     10..39  decuplet fields with {C gamma_l, 1} (Sec. 4 footnote), l = 1, 2, 3:
+             index 10 + 3 f + l - 1 for f = 0 D++ (uuu), 1 D- (ddd), 2 O- (sss),
+             3 D+, 4 D0, 5 S*+, 6 S*0, 7 S*-, 8 X*0, 9 X*-; names "D++(1)" etc.
+             The members of mixed flavour are the symmetric flavour
+             combinations (a reading), e.g. D+ = (2 eps (u G d) u + eps (u G u) d) / sqrt3,
+             S*0 = sqrt(2/3) (eps (u G d) s + eps (d G s) u + eps (s G u) d).
    A quadruple holding at least one of them has the id
-     4152 + ((b1 * 19 + b2) * 19 + b3) * 19 + b4     (4152 = 56 + 8^4),
+     4152 + ((b1 * 40 + b2) * 40 + b3) * 40 + b4     (4152 = 56 + 8^4),
    valid when the quark content matches.  Sink and source fields may differ in
-   their spin structures (e.g. p2 n > p n2).  Readings: the source tensor is the
-   sink tensor with primed indices for every field (as for the octet); the
-   decuplet fields of mixed flavour are not provided. */
-int bbc_num_baryons(void);           /* 19 */
+   their spin structures (e.g. p2 n > p n2).  Reading: the source tensor is the
+   sink tensor with primed indices for every field (as for the octet). */
+int bbc_num_baryons(void);           /* 40 */
 const char *bbc_baryon_name(int b);  /* NULL for an invalid index */
 int bbc_channel_id(int b1, int b2, int b3, int b4);
 

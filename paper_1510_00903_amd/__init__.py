@@ -156,7 +156,8 @@ def diagram_table(c: int, term3: int, term4: int):
 
 def baryon_names():
     """The fields that name channels, in index order: the octet p n S+ S- X0 X- L S0, then
-    p2 n2 ({C, gamma_5} nucleon) and the decuplet D++(l) D-(l) O-(l), l = 1, 2, 3."""
+    p2 n2 ({C, gamma_5} nucleon) and the decuplet D++ D- O- D+ D0 S*+ S*0 S*- X*0 X*-,
+    each as name(l) for l = 1, 2, 3."""
     lib = load()
     return [lib.bbc_baryon_name(b).decode() for b in range(lib.bbc_num_baryons())]
 

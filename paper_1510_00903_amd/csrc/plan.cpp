@@ -11,6 +11,7 @@ namespace bbc {
 namespace {
 
 const double kR6 = 1.0 / std::sqrt(6.0), kR2 = 1.0 / std::sqrt(2.0);
+const double kR3 = 1.0 / std::sqrt(3.0), kR23 = std::sqrt(2.0 / 3.0);
 
 // Baryon fields of Sec. 2, Eqs. (FieldOperator_N), (FieldOperator_SLXi),
 // (FieldOperator_xxx).  Lambda and Sigma0 keep the fixed field order
@@ -19,9 +20,14 @@ const double kR6 = 1.0 / std::sqrt(6.0), kR2 = 1.0 / std::sqrt(2.0);
 // permutation of three Grassmann fields), so only their tensor roles move.
 // Further fields of the general form of Sec. 2, Eq. (FieldOperator_B): the
 // nucleon with {C, gamma_5} (same flavour terms as p, n) and the decuplet fields
-// of maximal flavour with {C gamma_l, 1} (Sec. 4 footnote), l = 1, 2, 3.
+// with {C gamma_l, 1} (Sec. 4 footnote), l = 1, 2, 3.  The decuplet members of
+// mixed flavour are the symmetric flavour combinations (a reading), e.g.
+// Delta+ = (2 eps (u G d) u + eps (u G u) d) / sqrt3 in the field order (u, d, u):
+// the string u u d is the order's transposition (0 2 1), so that term's weight
+// carries -1; the three terms of Sigma*0 are cyclic rotations of (u, d, s).
 enum { B_P, B_N, B_SP, B_SM, B_X0, B_XM, B_L, B_S0, B_P2, B_N2, B_DPP1, B_DM1 = B_DPP1 + 3, B_OM1 = B_DM1 + 3,
-       B_COUNT = B_OM1 + 3 };
+       B_DP1 = B_OM1 + 3, B_D01 = B_DP1 + 3, B_SSP1 = B_D01 + 3, B_SS01 = B_SSP1 + 3, B_SSM1 = B_SS01 + 3,
+       B_XS01 = B_SSM1 + 3, B_XSM1 = B_XS01 + 3, B_COUNT = B_XSM1 + 3 };
 static_assert(B_COUNT == kNumBaryons && B_P2 == kNumOctet, "baryon table");
 
 const Baryon kBaryons[B_COUNT] = {
@@ -44,6 +50,20 @@ const Baryon kBaryons[B_COUNT] = {
     {"O-(1)", {FS, FS, FS}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1},
     {"O-(2)", {FS, FS, FS}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 1},
     {"O-(3)", {FS, FS, FS}, 1, {{1.0, {0, 1, 2}, "-"}}, SP_DEC1 + 2},
+#define BBC_DEC2(NAME, F0, F1, L)                                                                               \
+    {NAME "(" #L ")", {F0, F1, F0}, 2, {{2.0 * kR3, {0, 1, 2}, "-"}, {-kR3, {0, 2, 1}, "-"}}, SP_DEC1 + L - 1}
+    BBC_DEC2("D+", FU, FD, 1), BBC_DEC2("D+", FU, FD, 2), BBC_DEC2("D+", FU, FD, 3),
+    BBC_DEC2("D0", FD, FU, 1), BBC_DEC2("D0", FD, FU, 2), BBC_DEC2("D0", FD, FU, 3),
+    BBC_DEC2("S*+", FU, FS, 1), BBC_DEC2("S*+", FU, FS, 2), BBC_DEC2("S*+", FU, FS, 3),
+#define BBC_DECS0(L)                                                                                            \
+    {"S*0(" #L ")", {FU, FD, FS}, 3, {{kR23, {0, 1, 2}, "-"}, {kR23, {1, 2, 0}, "-"}, {kR23, {2, 0, 1}, "-"}},  \
+     SP_DEC1 + L - 1}
+    BBC_DECS0(1), BBC_DECS0(2), BBC_DECS0(3),
+    BBC_DEC2("S*-", FD, FS, 1), BBC_DEC2("S*-", FD, FS, 2), BBC_DEC2("S*-", FD, FS, 3),
+    BBC_DEC2("X*0", FS, FU, 1), BBC_DEC2("X*0", FS, FU, 2), BBC_DEC2("X*0", FS, FU, 3),
+    BBC_DEC2("X*-", FS, FD, 1), BBC_DEC2("X*-", FS, FD, 2), BBC_DEC2("X*-", FS, FD, 3),
+#undef BBC_DEC2
+#undef BBC_DECS0
 };
 
 // Complex 4x4 matrices with Gaussian-integer entries, enough for products of

@@ -54,12 +54,13 @@ constexpr int kNumChannels = 52;
 constexpr int kNumChannelsAll = 56;
 // Other charge states: ids from kChannelExtBase name any quadruple of the 8
 // octet fields, id = kChannelExtBase + ((b1 * 8 + b2) * 8 + b3) * 8 + b4.
-// Fields with other spin structures (ids 8..18: p2, n2 with {C, gamma_5}; the
-// decuplet Delta++, Delta-, Omega- with {C gamma_l, 1}, l = 1..3) enter through
-// ids from kChannelGenBase: id = kChannelGenBase + ((b1 * 19 + b2) * 19 + b3) * 19 + b4
-// for quadruples holding at least one of them.
+// Fields with other spin structures (ids 8..39: p2, n2 with {C, gamma_5}; the
+// decuplet Delta++, Delta-, Omega-, Delta+, Delta0, Sigma*+, Sigma*0, Sigma*-,
+// Xi*0, Xi*- with {C gamma_l, 1}, l = 1..3) enter through ids from kChannelGenBase:
+// id = kChannelGenBase + ((b1 * 40 + b2) * 40 + b3) * 40 + b4 for quadruples holding
+// at least one of them.
 constexpr int kNumOctet = 8;
-constexpr int kNumBaryons = 19;
+constexpr int kNumBaryons = 40;
 constexpr int kChannelExtBase = kNumChannelsAll;
 constexpr int kChannelGenBase = kChannelExtBase + kNumOctet * kNumOctet * kNumOctet * kNumOctet;
 constexpr int kNumChannelIds = kChannelGenBase + kNumBaryons * kNumBaryons * kNumBaryons * kNumBaryons;

@@ -84,15 +84,18 @@ def test_channel_ids_and_names():
 def test_general_field_ids():
     import paper_1510_00903_amd as bbc
     names = bbc.baryon_names()
-    assert names[8:] == ["p2", "n2"] + ["%s(%d)" % (f, l) for f in ("D++", "D-", "O-") for l in (1, 2, 3)]
-    # quadruples with a general field: 4152 + ((b1 * 19 + b2) * 19 + b3) * 19 + b4
+    fams = ("D++", "D-", "O-", "D+", "D0", "S*+", "S*0", "S*-", "X*0", "X*-")
+    assert names[8:] == ["p2", "n2"] + ["%s(%d)" % (f, l) for f in fams for l in (1, 2, 3)]
+    # quadruples with a general field: 4152 + ((b1 * 40 + b2) * 40 + b3) * 40 + b4
     c = bbc.channel_id("O-(3)", "O-(3)", "O-(3)", "O-(3)")
-    assert c == 4152 + ((18 * 19 + 18) * 19 + 18) * 19 + 18
+    assert c == 4152 + ((18 * 40 + 18) * 40 + 18) * 40 + 18
     assert bbc.channel_name(c) == "O-(3) O-(3) > O-(3) O-(3)"
     assert bbc.channel_content(c) == (0, 6)
     c = bbc.channel_id("p2", "n", "p", "n2")
-    assert c == 4152 + ((8 * 19 + 1) * 19 + 0) * 19 + 9
+    assert c == 4152 + ((8 * 40 + 1) * 40 + 0) * 40 + 9
     assert bbc.channel_content(c) == (6, 0)
+    c = bbc.channel_id("S*0(2)", "p", "S*0(2)", "p")
+    assert c == 4152 + ((29 * 40 + 0) * 40 + 29) * 40 + 0 and bbc.channel_content(c) == (5, 1)
     assert bbc.channel_id("p", "n", "p", "n") == 0             # octet ids unchanged
     with pytest.raises(bbc.BBCError):
         bbc.channel_id("O-(1)", "p", "O-(1)", "n")            # quark content differs

@@ -23,6 +23,11 @@ QUADS = [
     ("D++(3)", "p2", "D++(3)", "p2"),
     ("O-(1)", "X0", "O-(2)", "X0"),
     ("n2", "D-(1)", "n", "D-(1)"),
+    ("D+(1)", "D+(2)", "D+(1)", "D+(2)"),
+    ("S*0(3)", "p", "S*0(3)", "p"),
+    ("D0(1)", "X*0(2)", "D0(1)", "X*0(2)"),
+    ("X*-(2)", "L", "X*-(2)", "L"),
+    ("D++(1)", "D+(1)", "D+(1)", "D++(1)"),
 ]
 
 
