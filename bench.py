@@ -339,9 +339,9 @@ def next_rows(bbc, torch, np, synth, steps):
     of the default job:
       * CPT average (Sec. 6): bbc_correlate_cpt over tau = 0..15 with t0 = 0 (two
         correlator slices per tau: upper at t0 + tau, lower at t0 - tau mod 32), 52 channels;
-      * general fields (Sec. 2, Eq. (FieldOperator_B)): 25 channels -- Omega- Omega- and
+      * general fields (Sec. 2, Eq. (FieldOperator_B)): 31 channels -- Omega- Omega- and
         Delta++ Delta++ for every (l1, l2) pair (source = sink), four {C, gamma_5} nucleon
-        channels, Omega- p for l = 1, 2, 3 -- over all 32 slices.
+        channels, Omega- p, Delta+ Delta+ and Sigma*0 p for l = 1, 2, 3 -- over all 32 slices.
     Wall time over `steps` calls after one warm-up call, per-stage HIP-event times
     from one more profiled call."""
     L, T = 16, 32
@@ -386,6 +386,8 @@ def next_rows(bbc, torch, np, synth, steps):
                 quads.append((a, b, a, b))
     quads += [("p2", "n2", "p2", "n2"), ("p2", "n", "p", "n2"), ("p", "n2", "p2", "n"), ("p2", "n2", "p", "n")]
     quads += [("O-(%d)" % l, "p", "O-(%d)" % l, "p") for l in (1, 2, 3)]
+    quads += [("D+(%d)" % l,) * 4 for l in (1, 2, 3)]
+    quads += [("S*0(%d)" % l, "p", "S*0(%d)" % l, "p") for l in (1, 2, 3)]
     gch = [bbc.channel_id(*q) for q in quads]
     C = torch.empty((T, len(gch), L, L, L, 16), dtype=torch.complex128, device=dev)
     r = timed(lambda: ctx.correlate(d_l, d_s, list(range(T)), gch, out=C), T * len(gch) * V)
@@ -398,8 +400,9 @@ def next_rows(bbc, torch, np, synth, steps):
             "value": out["general_fields"]["value"], "unit": "site-channels/s", "n_gpus": 1, "steps": steps,
             "higher_is_better": True, "dtype": "f64", "data": "synthetic (seeded Gaussian propagators, "
             "exp(-m t) decay; the default job's inputs)",
-            "config": {"workload": "16^3x32 FP64: CPT average (16 tau, 52 channels) and 25 general-field "
-                                   "channels (decuplet Omega-/Delta++, {C, gamma_5} nucleon, Omega- p)",
+            "config": {"workload": "16^3x32 FP64: CPT average (16 tau, 52 channels) and 31 general-field "
+                                   "channels (decuplet Omega-/Delta++/Delta+/Sigma*0, {C, gamma_5} nucleon, "
+                                   "Omega- p, Sigma*0 p)",
                        "lattice": [L, L, L], "T": T},
             "paths": out}
 
