@@ -750,29 +750,35 @@ __global__ __launch_bounds__(256) void k_fft3d_grouped(const typename cplx_t<T>:
 // ----------------------------------------------------------------------------
 // Last (z) pass of the forward FFT fused with the copy into the momentum groups,
 // for lattices whose x and y transforms ran as plane passes: each thread
-// transforms one z line of one (sink spin g, component c) in registers and
-// writes its N momenta to their group positions (posof: momentum -> position).
-// A workgroup takes 256 lines of one (g, c); all chunks of (c, 0) and then of
-// (c, 1) run back to back on one XCD (consecutive workgroup ids cycle over the
-// 8 XCDs), so the lanes of each output line -- q and -q, and in FP32 both sink
-// spins -- are written close together in time and meet in that XCD's L2.
+// transforms one z line (kx, ky) of one (sink spin g, component c) in registers
+// and writes its N momenta to their group positions (posof: momentum -> position).
+// A group line holds q and -q (and in FP32 both sink spins), so a workgroup
+// takes whole mirror pairs of rows: the rows ky are ordered 0, Ly/2, 1, Ly-1, 2,
+// Ly-2, ... and a workgroup takes R consecutive ones (R even), which puts
+// (kx, ky, kz) and (-kx, -ky, -kz) in the same workgroup.  In FP64 (a spin per
+// line) a workgroup does both sink spins in turn; in FP32 (both spins in a line,
+// and too few registers for the loop) the two spins of a chunk are consecutive
+// workgroups.  All workgroups of a component run back to back on one XCD, so
+// most group lines are completed by one workgroup (or one pair running
+// together) and leave L2 whole.
 // Replaces the z axis pass and k_transpose_grouped.
 // ----------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>::type *__restrict__ in,
-                                                       typename cplx_t<T>::type *__restrict__ out, int nc,
-                                                       int nxy, int nchunk, const int *__restrict__ posof,
+                                                       typename cplx_t<T>::type *__restrict__ out, int nc, int Lx,
+                                                       int Ly, int nchunk, int rows, const int *__restrict__ posof,
                                                        int sgn) {
     using T2 = typename cplx_t<T>::type;
-    using Ly = GroupLayout<T2>;
-    constexpr int G = Ly::G;
+    using Ly_ = GroupLayout<T2>;
+    constexpr int G = Ly_::G;
     __shared__ T2 tw[N];
     const int t = threadIdx.x;
+    constexpr int SPW = sizeof(T) == 8 ? 2 : 1;     // sink spins per workgroup
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int per_c = 2 * nchunk;                    // workgroups of one component on its XCD
+    const int per_c = (2 / SPW) * nchunk;
     const int c = xcd * (int)(gridDim.x / (8 * per_c)) + j / per_c;
     const int r = j - (j / per_c) * per_c;
-    const int g = r / nchunk, chunk = r - g * nchunk;
+    const int chunk = SPW == 2 ? r : r >> 1, g0 = SPW == 2 ? 0 : (r & 1);
     for (int i = t; i < N; i += 256) {
         double sn, cs;
         sincospi(2.0 * i / N, &sn, &cs);
@@ -780,21 +786,27 @@ __global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>:
     }
     __syncthreads();
     if (c >= nc) return;
-    const int line = chunk * 256 + t;                // (x, y) = (line % Lx, line / Lx)
-    if (line >= nxy) return;
-    const T2 *src = in + ((long)g * nc + c) * (long)nxy * N + line;
-    T2 a[N], b[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) a[k] = src[(long)k * nxy];
+    const int slot = t / Lx, kx = t - slot * Lx;
+    const int prow = chunk * rows + slot;
+    if (slot >= rows || prow >= Ly) return;
+    const int ky = prow == 0 ? 0 : prow == 1 ? Ly / 2 : ((prow & 1) ? Ly - (prow >> 1) : (prow >> 1));
+    const int nxy = Lx * Ly, line = kx + Lx * ky;
     int pk[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) pk[k] = posof[line + k * nxy];
-    Stages<T2, N, 1>::run(a, b, tw, sgn);
-    T2 *dst = out + (long)c * 2 * G + g * Ly::SG;
+#pragma unroll 1
+    for (int g = g0; g < g0 + SPW; ++g) {
+        const T2 *src = in + ((long)g * nc + c) * (long)nxy * N + line;
+        T2 a[N], b[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const int p = pk[k];
-        dst[(long)(p / G) * nc * 2 * G + (p % G) * Ly::S] = a[k];
+        for (int k = 0; k < N; ++k) a[k] = src[(long)k * nxy];
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+        T2 *dst = out + (long)c * 2 * G + g * Ly_::SG;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int p = pk[k];
+            dst[(long)(p / G) * nc * 2 * G + (p % G) * Ly_::S] = a[k];
+        }
     }
 }
 
@@ -810,12 +822,13 @@ template <typename T> bool fft3d_zgrouped_fits(const int L[3]) {
 }
 
 template <typename T, int N>
-static void fft_z_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, int nxy,
-                          const int *posof, hipStream_t st) {
-    const int nchunk = (nxy + 255) / 256;
-    const long per_xcd = (long)((nc + 7) / 8) * 2 * nchunk;
-    hipLaunchKernelGGL((k_fft_z_grouped<T, N>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, in, out, nc, nxy,
-                       nchunk, posof, -1);
+static void fft_z_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, int Lx,
+                          int Ly, const int *posof, hipStream_t st) {
+    const int rows = (256 / Lx) / 2 * 2;           // whole mirror pairs of rows per workgroup
+    const int nchunk = (Ly + rows - 1) / rows;
+    const long per_xcd = (long)((nc + 7) / 8) * (sizeof(T) == 8 ? 1 : 2) * nchunk;   // see SPW in the kernel
+    hipLaunchKernelGGL((k_fft_z_grouped<T, N>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, in, out, nc, Lx,
+                       Ly, nchunk, rows, posof, -1);
 }
 
 // Forward 3-D FFT of the intermediates into the momentum groups: x and y as
@@ -827,19 +840,18 @@ int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type
     if (!fft3d_zgrouped_fits<T>(L)) return -1;
     const long ncomp = 2L * nc;
     plane_pass<T>(in, ncomp * L[2], L[0], -1, st);
-    const int nxy = L[0] * L[1];
     switch (L[2]) {
-    case 2: fft_z_grouped<T, 2>(in, out, nc, nxy, posof, st); break;
-    case 3: fft_z_grouped<T, 3>(in, out, nc, nxy, posof, st); break;
-    case 4: fft_z_grouped<T, 4>(in, out, nc, nxy, posof, st); break;
-    case 6: fft_z_grouped<T, 6>(in, out, nc, nxy, posof, st); break;
-    case 8: fft_z_grouped<T, 8>(in, out, nc, nxy, posof, st); break;
-    case 12: fft_z_grouped<T, 12>(in, out, nc, nxy, posof, st); break;
-    case 16: fft_z_grouped<T, 16>(in, out, nc, nxy, posof, st); break;
-    case 24: fft_z_grouped<T, 24>(in, out, nc, nxy, posof, st); break;
-    case 32: fft_z_grouped<T, 32>(in, out, nc, nxy, posof, st); break;
+    case 2: fft_z_grouped<T, 2>(in, out, nc, L[0], L[1], posof, st); break;
+    case 3: fft_z_grouped<T, 3>(in, out, nc, L[0], L[1], posof, st); break;
+    case 4: fft_z_grouped<T, 4>(in, out, nc, L[0], L[1], posof, st); break;
+    case 6: fft_z_grouped<T, 6>(in, out, nc, L[0], L[1], posof, st); break;
+    case 8: fft_z_grouped<T, 8>(in, out, nc, L[0], L[1], posof, st); break;
+    case 12: fft_z_grouped<T, 12>(in, out, nc, L[0], L[1], posof, st); break;
+    case 16: fft_z_grouped<T, 16>(in, out, nc, L[0], L[1], posof, st); break;
+    case 24: fft_z_grouped<T, 24>(in, out, nc, L[0], L[1], posof, st); break;
+    case 32: fft_z_grouped<T, 32>(in, out, nc, L[0], L[1], posof, st); break;
     case 96:
-        if constexpr (sizeof(T) == 4) { fft_z_grouped<T, 96>(in, out, nc, nxy, posof, st); break; }
+        if constexpr (sizeof(T) == 4) { fft_z_grouped<T, 96>(in, out, nc, L[0], L[1], posof, st); break; }
         return -1;
     default: return -1;
     }
