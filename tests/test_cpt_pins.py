@@ -37,6 +37,12 @@ def test_gamma5_premises():
     assert np.abs(M).max() > 0
     v = np.arange(4.0)
     assert np.array_equal(G5 @ v, [2.0, 3.0, 0.0, 1.0])
+    # general fields: C gamma_l picks up a sign per tensor, C and Gamma_2 = gamma_5 do not
+    for name in ("O-(1)", "O-(2)", "O-(3)"):
+        G1, G2 = ops.spin_structure(name)
+        assert np.allclose(G5.T @ G1 @ G5, -G1) and np.allclose(G2, np.eye(4))
+    G1, G2 = ops.spin_structure("p2")
+    assert np.allclose(G5.T @ G1 @ G5, G1) and np.allclose(G5 @ G2 @ G5, G2)
 
 
 @pytest.mark.parametrize("ch", [ops.CHANNELS[0], ops.CHANNELS[51]])
@@ -51,9 +57,12 @@ def test_lower_components_equal_brute_force(ch):
     assert rel(ow, up) > 1e-3                  # the lower components are another quantity
 
 
-@pytest.mark.parametrize("ci", [0, 10, 33, 51])
-def test_gamma5_maps_upper_to_lower(ci):
-    ch = ops.CHANNELS[ci]
+@pytest.mark.parametrize("ch", [ops.CHANNELS[0], ops.CHANNELS[10], ops.CHANNELS[33], ops.CHANNELS[51],
+                                ("O-(1)", "O-(2)", "O-(1)", "O-(2)"), ("p2", "n", "p", "n2"),
+                                ("S*0(3)", "D+(1)", "S*0(3)", "D+(1)")])
+def test_gamma5_maps_upper_to_lower(ch):
+    """Also for the general fields: gamma_5^T (C gamma_l) gamma_5 = -C gamma_l gives one sign per
+    tensor (four in all), C is invariant, and Gamma_2 = gamma_5 commutes with gamma_5."""
     Sl, Ss = synth.propagators((2, 2, 1), 1, seed=17)
     r = wick.all_r(2, 2, 1)
     up = wick.correlate(Sl[0], Ss[0], ch, r)
