@@ -147,7 +147,8 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
  *                 the precision's type: the slices for the times in t_list.
  *   t_list[n_t]   time of each slice (used for exp(E (t - t0)) only).
  *   t0            source time.
- *   ch_list[n_ch] channel indices (0..55), any order, repeats allowed.
+ *   ch_list[n_ch] channel ids (0..55, extended ids and general-field ids as
+ *                 above), any order, repeats allowed.
  *   spin          BBC_SPIN_UPPER or BBC_SPIN_LOWER (components 2,3 mapped to 0,1).
  *   energy[n_ch]  E_ch of the normalisation factor exp(E_ch (t - t0)) of Sec. 2
  *                 Eq. (2); NULL means 0 for every channel (unnormalised).
@@ -159,6 +160,8 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
  *                 rescaling of the propagators and exp(E (t - t0)), so that
  *                 six-propagator products do not leave the FP32 range.
  *   stream        hipStream_t (as void*) on which all work is ordered; NULL = default.
+ * n_t = 0 is a valid empty request: the arguments are checked, nothing is
+ * enqueued, and the slice-sized buffers (S_*, t_list, C_out, C_scale) may be NULL.
  * Stream-ordered: returns after enqueueing; synchronise the stream before reading C_out.
  */
 bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec,

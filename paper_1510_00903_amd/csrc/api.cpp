@@ -1045,7 +1045,7 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
     if (n_t < 0 || n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list or negative n_t");
     if (n_t > 0 && (!S_light || !S_strange || !t_list || !C_out)) return fail(BBC_EINVAL, "NULL buffer");
-    if (prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
+    if (prec == BBC_F32 && n_t > 0 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
     for (int i = 0; i < n_ch; ++i)
         if (!bbc::channel_valid(ch_list[i]))
             return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
