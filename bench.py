@@ -34,7 +34,7 @@ PAPER_SITE_CH_PER_S = 6815744 / 19.0   # best BG/Q layout of Table 5 (32 nodes),
 
 
 def stage_model(stage, L, nc, n_ch, csize):
-    """Algorithmic HBM bytes of one time slice of each stage (see DESIGN.md): every
+    """Algorithmic HBM bytes of one time slice of each stage: every
     array read and written once.  nc = intermediate components per sink spin."""
     V = L ** 3
     field = 2 * nc * V * csize                      # all block intermediates, both sink spins
@@ -426,8 +426,8 @@ def main():
                     help="also run one device copy of 1 GiB (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the correlator of each time slice is "
-              "independent, so more GPUs would shard time slices (see DESIGN.md). Use --gpus 1.",
+        print("bench.py: runs on one GPU; the correlator of each time slice is independent, "
+              "so several GPUs would each take a share of the slices. Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@ typedef enum {
     BBC_EINVAL = -1,       /* bad argument (null pointer, size, channel, lattice) */
     BBC_ENOMEM = -2,       /* workspace would exceed the budget, or allocation failed */
     BBC_EDEVICE = -3,      /* HIP runtime error */
-    BBC_EUNSUPPORTED = -4, /* valid request this build does not handle (e.g. lattice extent) */
+    BBC_EUNSUPPORTED = -4, /* valid request the library does not handle (e.g. lattice extent) */
     BBC_ETIMEOUT = -5,     /* bbc_wait: job not finished within the timeout */
     BBC_ECANCELLED = -6,   /* bbc_wait: job was cancelled */
     BBC_ESTATE = -7        /* call not valid in the current state (server not started, job running) */

@@ -7,7 +7,7 @@ The paper takes the upper two components of every spinor index forward in time
 related to the first by charge conjugation, parity and time reversal), maps both
 to spin indices 0, 1 and averages the two, which doubles the statistics.
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
   * time slices: forward t0 + tau, backward t0 - tau, both taken mod Lt;
   * both parts are normalised by exp(E tau), tau >= 0 being the distance from t0;
   * lower component 2 + s is re-indexed to s, with no spin flip;

@@ -5,7 +5,7 @@ the HAL QCD method.  Plain definitions, FP64, numpy.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-Conventions (readings, listed in DESIGN.md):
+Conventions (readings of the paper taken here):
   * Spinor components: Dirac representation, upper (or lower) two components
     of each baryon index; component 0 is spin up and 1 spin down along z
     (Sigma_z = diag(sigma_z, sigma_z) in this representation).

@@ -2,8 +2,8 @@
 
 Tolerance (FP64 form): normwise per (channel, time slice),
     max_{r,spin} |C_gpu - C_oracle| <= 1e-12 * max_{r,spin} |C_oracle|,
-the reading of the paper's "accuracy of almost the double precision" (Sec. 6)
-adopted for this build; relative errors near zeros are not meaningful.
+the reading taken here of the near-double-precision agreement the paper reports
+(Sec. 6); relative errors near zeros are not meaningful.
 """
 import os
 
@@ -322,7 +322,8 @@ def test_fp32_all_channels_small_with_deep_slice(bbc, ctx):
 
 def test_fp32_vs_fp64_16cubed_all_channels(bbc, ctx):
     """FP32 form against the FP64 form on a 16^3 lattice, every r, all 52 channels;
-    the per-channel normwise error is written to gpurun_out/ when that folder exists."""
+    the per-channel normwise error table is written to the directory named by
+    BBC_REPORT_DIR, if set."""
     lat = (16, 16, 16)
     t_list = [5, 40]
     Sl, Ss = _fp32_inputs(lat, t_list, seed=202)
@@ -334,8 +335,8 @@ def test_fp32_vs_fp64_16cubed_all_channels(bbc, ctx):
         for c in chans:
             got = out32[n, c].astype(np.complex128) * scale[n, c]
             errs[n, c] = normwise(got, out64[n, c])
-    out_dir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out_dir):
+    out_dir = os.environ.get("BBC_REPORT_DIR")
+    if out_dir and os.path.isdir(out_dir):
         with open(os.path.join(out_dir, "fp32_errors_16c.txt"), "w") as f:
             f.write("# channel  normwise error of the FP32 form vs the FP64 form, 16^3, t=%s\n" % t_list)
             for c in chans:
@@ -346,8 +347,8 @@ def test_fp32_vs_fp64_16cubed_all_channels(bbc, ctx):
 def test_fp32_vs_fp64_32cubed_all_channels(bbc, ctx):
     """The 32^3 x 64 configuration's inputs (t-independent field + 1e-3 noise per
     slice, exp(-m t) decay) at t = 0, 31, 63 (the deepest slice): FP32 form against
-    the FP64 form over every r, all 52 channels; per-channel errors are written to
-    gpurun_out/ when that folder exists."""
+    the FP64 form over every r, all 52 channels; the per-channel error table is
+    written to the directory named by BBC_REPORT_DIR, if set."""
     L = 32
     t_list = [0, 31, 63]
     Sl, Ss = synth.propagators(L, 64, seed=synth.BASE_SEED + 2, kind="correlated", t_list=t_list,
@@ -360,8 +361,8 @@ def test_fp32_vs_fp64_32cubed_all_channels(bbc, ctx):
         for c in chans:
             errs[n, c] = normwise(out32[0, c].astype(np.complex128) * scale[0, c], out64[0, c])
         del out32, out64
-    out_dir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out_dir):
+    out_dir = os.environ.get("BBC_REPORT_DIR")
+    if out_dir and os.path.isdir(out_dir):
         with open(os.path.join(out_dir, "fp32_errors_32c64.txt"), "w") as f:
             f.write("# channel  normwise error of the FP32 form vs the FP64 form, 32^3, t=%s\n" % t_list)
             for c in chans:
