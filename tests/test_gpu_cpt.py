@@ -60,6 +60,33 @@ def test_cpt_matches_oracle(ctx, dtype, tol, lat, t0, sign):
             assert err <= tol, (tau, c, err)
 
 
+@pytest.mark.parametrize("dtype,tol", [(np.complex128, 1e-12), (np.complex64, 1e-5)])
+@pytest.mark.parametrize("lat,sign", [((1, 1, 1), 1), ((2, 1, 3), -1)])
+def test_cpt_single_time_slice(ctx, bbc, dtype, tol, lat, sign):
+    """Lt = 1 (degenerate): tau = 0 is the only distance and both halves read slice 0;
+    on lattices with unit extents, octet and general-field channels."""
+    Sl, Ss = synth.propagators(lat, 1, seed=137, dtype=dtype)
+    chans = [0, 10, 51, bbc.channel_id("O-(3)", "O-(3)", "O-(3)", "O-(3)")]
+    print("case: Lt=1 lattice", lat, np.dtype(dtype).name, flush=True)
+    got = run(ctx, Sl, Ss, 0, [0], chans, sign=sign, energy=[0.1, -0.2, 0.3, 0.0])
+    S64l, S64s = Sl.astype(np.complex128), Ss.astype(np.complex128)
+    for m, c in enumerate(chans):
+        ref = cpt.cpt_average(S64l, S64s, ctx_name(c), 0, 0, sign=sign, energy=0.0)
+        err = np.abs(got[0, m].reshape(-1, 16) - ref).max() / np.abs(ref).max()
+        assert err <= tol, (c, err)
+
+
+def test_cpt_empty_tau_list(ctx):
+    """No distances: a valid empty request."""
+    dev = torch.device("cuda:0")
+    S = torch.zeros((3, 2, 2, 2, 12, 12), dtype=torch.complex128, device=dev)
+    out = ctx.correlate_cpt(S, S, 1, [], [0, 51])
+    assert tuple(out.shape) == (0, 2, 2, 2, 2, 16)
+    S32 = S.to(torch.complex64)
+    out, scale = ctx.correlate_cpt(S32, S32, 1, [], [10])
+    assert tuple(out.shape) == (0, 1, 2, 2, 2, 16) and tuple(scale.shape) == (0, 1)
+
+
 def ctx_name(c):
     import paper_1510_00903_amd as mod
     a, b = mod.channel_name(c).split(">")
