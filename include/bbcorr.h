@@ -163,6 +163,10 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
  * n_t = 0 is a valid empty request: the arguments are checked, nothing is
  * enqueued, and the slice-sized buffers (S_*, t_list, C_out, C_scale) may be NULL.
  * Stream-ordered: returns after enqueueing; synchronise the stream before reading C_out.
+ * Calls on one context share its workspace: each bbc_correlate or
+ * bbc_correlate_cpt call's stream first waits for the work of the previous such
+ * call on the context (an event), so calls on different streams run one after
+ * the other on the device and never overwrite each other's intermediates.
  */
 bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec,
                          const void *S_light, const void *S_strange,
@@ -212,7 +216,14 @@ bbc_status bbc_correlate_cpt(bbc_context *ctx, const int32_t lattice[3], int Lt,
  * bbc_server_start starts n_slots slots, each with its own HIP stream and
  * workspace.  Queued jobs are admitted in arrival order as soon as a slot is
  * free and the job's workspace fits the context's HBM budget (together with
- * the resident propagators and the other slots' workspaces); an admitted job
+ * the resident propagators and the other slots' workspaces).  When the job at
+ * the head of the queue does not fit, one of the next 8 queued jobs that fits
+ * may start instead, at most 16 times per head job (so the head job is delayed,
+ * never starved); slot workspaces are kept and reused between jobs, and the
+ * workspaces of idle slots are released when the head job needs the room.  A
+ * job whose workspace cannot fit beside its own propagator set is refused by
+ * bbc_submit (BBC_ENOMEM); one that cannot fit beside the other resident
+ * propagator sets while no job runs fails with BBC_ENOMEM.  An admitted job
  * advances one time slice at a time, so jobs that arrive while others run are
  * started between slices and their work overlaps on the device.  A job's
  * result does not depend on what runs beside it (same kernels, own workspace,

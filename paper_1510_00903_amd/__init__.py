@@ -118,6 +118,35 @@ def _i32(values):
     return (ctypes.c_int32 * max(1, len(vals)))(*vals), len(vals)
 
 
+def _check_tensor(t, shape, dtype, name, device=None, host_ok=False):
+    """Raise unless t is a contiguous tensor of this shape and dtype on `device`
+    (or in host memory where host_ok): the library writes through raw pointers,
+    so a wrong buffer would be written past its end on the GPU."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise BBCError("%s must be a torch tensor" % name)
+    if tuple(t.shape) != tuple(int(v) for v in shape):
+        raise BBCError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if t.dtype != dtype:
+        raise BBCError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    if not t.is_contiguous():
+        raise BBCError("%s must be contiguous" % name)
+    if t.is_cuda:
+        if device is not None and t.device != device:
+            raise BBCError("%s is on %s, expected %s" % (name, t.device, device))
+    elif not host_ok:
+        raise BBCError("%s must be a device tensor" % name)
+
+
+def _prop_dtype(S, name):
+    import torch
+    if S.dtype not in (torch.complex128, torch.complex64):
+        raise BBCError("%s must be complex128 or complex64" % name)
+    if S.dim() != 6 or tuple(S.shape[-2:]) != (12, 12):
+        raise BBCError("%s must be [n_t, Lz, Ly, Lx, 12, 12]" % name)
+    return F64 if S.dtype == torch.complex128 else F32
+
+
 def num_channels() -> int:
     return load().bbc_num_channels()
 
@@ -197,6 +226,11 @@ class Context:
         self._ptr = ctypes.c_void_p()
         _check(self._lib.bbc_create(device, hbm_budget_bytes, ctypes.byref(self._ptr)))
         self.device = device
+        self._props = {}           # handle -> (n_t, Lz, Ly, Lx, dtype) of a resident propagator set
+
+    def _torch_device(self):
+        import torch
+        return torch.device("cuda", self.device)
 
     def close(self):
         if self._ptr:
@@ -236,29 +270,45 @@ class Context:
     def prop_upload(self, S_light, S_strange) -> int:
         """Copy a propagator set ([n_t, Lz, Ly, Lx, 12, 12] complex, host or device tensors)
         into memory owned by the context; returns its handle."""
-        import torch
         if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
             raise BBCError("S_light and S_strange must have the same shape and dtype")
-        prec = F64 if S_light.dtype == torch.complex128 else F32
+        prec = _prop_dtype(S_light, "S_light")
+        for S, nm in ((S_light, "S_light"), (S_strange, "S_strange")):
+            if S.is_cuda and S.device != self._torch_device():
+                raise BBCError("%s is on %s, the context on cuda:%d" % (nm, S.device, self.device))
         S_light, S_strange = S_light.contiguous(), S_strange.contiguous()
         n_t, Lz, Ly, Lx = S_light.shape[:4]
         lat, _ = _i32([Lx, Ly, Lz])
         h = ctypes.c_uint64()
         _check(self._lib.bbc_prop_upload(self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()),
                                          ctypes.c_void_p(S_strange.data_ptr()), n_t, ctypes.byref(h)))
+        self._props[h.value] = (n_t, Lz, Ly, Lx, S_light.dtype)
         return h.value
 
     def prop_release(self, handle: int):
         _check(self._lib.bbc_prop_release(self._ptr, handle))
+        self._props.pop(handle, None)
 
     def submit(self, prop: int, slices, t_list, channels, out, scale=None, t0=0, spin=UPPER, energy=None) -> int:
         """Queue a job over slices of a resident propagator set; out (and scale in FP32)
         are caller-owned device tensors shaped as for correlate()."""
+        import torch
         s_arr, n_t = _i32(slices)
         t_arr, n2 = _i32(t_list)
         ch_arr, n_ch = _i32(channels)
         if n2 != n_t:
             raise BBCError("t_list must have one entry per slice")
+        if prop not in self._props:
+            raise BBCError("unknown propagator handle %d" % prop)
+        _, Lz, Ly, Lx, dt = self._props[prop]
+        dev = self._torch_device()
+        _check_tensor(out, (n_t, n_ch, Lz, Ly, Lx, 16), dt, "out", dev)
+        if dt == torch.complex64:
+            if scale is None:
+                raise BBCError("scale is required in the FP32 form")
+            _check_tensor(scale, (n_t, n_ch), torch.float64, "scale", dev)
+        else:
+            scale = None
         e_arr = None
         if energy is not None:
             e_arr = (ctypes.c_double * n_ch)(*[float(e) for e in energy])
@@ -305,16 +355,11 @@ class Context:
 
         if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
             raise BBCError("S_light and S_strange must have the same shape and dtype")
-        if S_light.dim() != 6 or tuple(S_light.shape[-2:]) != (12, 12):
-            raise BBCError("propagators must be [n_t, Lz, Ly, Lx, 12, 12]")
-        if S_light.dtype == torch.complex128:
-            prec = F64
-        elif S_light.dtype == torch.complex64:
-            prec = F32
-        else:
-            raise BBCError("propagators must be complex128 or complex64")
+        prec = _prop_dtype(S_light, "propagators")
         if S_light.is_cuda != S_strange.is_cuda:
             raise BBCError("S_light and S_strange must both be on the device or both on the host")
+        if S_light.is_cuda and S_light.device != self._torch_device():
+            raise BBCError("propagators are on %s, the context on cuda:%d" % (S_light.device, self.device))
         S_light = S_light.contiguous()
         S_strange = S_strange.contiguous()
         n_t, Lz, Ly, Lx = S_light.shape[:4]
@@ -323,14 +368,18 @@ class Context:
             raise BBCError("t_list must have one entry per slice")
         ch_arr, n_ch = _i32(channels)
         lat, _ = _i32([Lx, Ly, Lz])
-        dev = S_light.device if S_light.is_cuda else torch.device("cuda", self.device)
+        dev = self._torch_device()
+        oshape = (n_t, n_ch, Lz, Ly, Lx, 16)
         if out is None:
             if S_light.is_cuda:
-                out = torch.empty((n_t, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, device=dev)
+                out = torch.empty(oshape, dtype=S_light.dtype, device=dev)
             else:
-                out = torch.empty((n_t, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, pin_memory=True)
-        if prec == F32 and scale is None:
-            scale = torch.empty((n_t, n_ch), dtype=torch.float64, device=dev)
+                out = torch.empty(oshape, dtype=S_light.dtype, pin_memory=True)
+        _check_tensor(out, oshape, S_light.dtype, "out", dev, host_ok=True)
+        if prec == F32:
+            if scale is None:
+                scale = torch.empty((n_t, n_ch), dtype=torch.float64, device=dev)
+            _check_tensor(scale, (n_t, n_ch), torch.float64, "scale", dev)
         e_arr = None
         if energy is not None:
             e_vals = [float(e) for e in energy]
@@ -361,16 +410,9 @@ class Context:
 
         if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
             raise BBCError("S_light and S_strange must have the same shape and dtype")
-        if S_light.dim() != 6 or tuple(S_light.shape[-2:]) != (12, 12):
-            raise BBCError("propagators must be [Lt, Lz, Ly, Lx, 12, 12]")
-        if not (S_light.is_cuda and S_strange.is_cuda):
-            raise BBCError("correlate_cpt takes device tensors")
-        if S_light.dtype == torch.complex128:
-            prec = F64
-        elif S_light.dtype == torch.complex64:
-            prec = F32
-        else:
-            raise BBCError("propagators must be complex128 or complex64")
+        prec = _prop_dtype(S_light, "propagators")
+        if not (S_light.is_cuda and S_strange.is_cuda) or S_light.device != self._torch_device():
+            raise BBCError("correlate_cpt takes device tensors on cuda:%d" % self.device)
         S_light = S_light.contiguous()
         S_strange = S_strange.contiguous()
         Lt, Lz, Ly, Lx = S_light.shape[:4]
@@ -378,10 +420,14 @@ class Context:
         ch_arr, n_ch = _i32(channels)
         lat, _ = _i32([Lx, Ly, Lz])
         dev = S_light.device
+        oshape = (n_tau, n_ch, Lz, Ly, Lx, 16)
         if out is None:
-            out = torch.empty((n_tau, n_ch, Lz, Ly, Lx, 16), dtype=S_light.dtype, device=dev)
-        if prec == F32 and scale is None:
-            scale = torch.empty((n_tau, n_ch), dtype=torch.float64, device=dev)
+            out = torch.empty(oshape, dtype=S_light.dtype, device=dev)
+        _check_tensor(out, oshape, S_light.dtype, "out", dev)
+        if prec == F32:
+            if scale is None:
+                scale = torch.empty((n_tau, n_ch), dtype=torch.float64, device=dev)
+            _check_tensor(scale, (n_tau, n_ch), torch.float64, "scale", dev)
         e_arr = None
         if energy is not None:
             e_vals = [float(e) for e in energy]
@@ -430,6 +476,7 @@ class Context:
         n_out = Wn.shape[0]
         if out is None:
             out = torch.empty(C.shape[:-1] + (n_out,), dtype=C.dtype, device=C.device)
+        _check_tensor(out, C.shape[:-1] + (n_out,), C.dtype, "out", C.device)
         w_arr = Wn.view(np.float64).ctypes.data_as(ctypes.c_void_p)
         if stream is None:
             stream = torch.cuda.current_stream(C.device)
@@ -444,6 +491,7 @@ class Context:
         prec, lat, n_fields, _ = self._field_args(F, F.shape[-1])
         if out is None:
             out = torch.empty_like(F)
+        _check_tensor(out, F.shape, F.dtype, "out", F.device)
         if stream is None:
             stream = torch.cuda.current_stream(F.device)
         _check(self._lib.bbc_cubic_project(self._ptr, lat, prec, n_fields, F.shape[-1],
@@ -462,8 +510,10 @@ class Context:
         n_t, Lz, Ly, Lx = R.shape[-4:]
         n_fields = R.numel() // (n_t * Lz * Ly * Lx) if R.numel() else 0
         lat, _ = _i32([Lx, Ly, Lz])
+        oshape = R.shape[:-4] + (max(n_t - 2, 0), Lz, Ly, Lx)
         if out is None:
-            out = torch.empty(R.shape[:-4] + (max(n_t - 2, 0), Lz, Ly, Lx), dtype=R.dtype, device=R.device)
+            out = torch.empty(oshape, dtype=R.dtype, device=R.device)
+        _check_tensor(out, oshape, R.dtype, "out", R.device)
         if stream is None:
             stream = torch.cuda.current_stream(R.device)
         _check(self._lib.bbc_central_potential(self._ptr, lat, n_fields, n_t, ctypes.c_void_p(R.data_ptr()),

@@ -220,6 +220,7 @@ struct Job {
     std::string err;
     bool cancel = false;
     int next = 0, inflight = 0;
+    int bypassed = 0;        // times a later job was admitted while this one waited at the head
     Clock::time_point t_submit, t_start, t_done;
 };
 
@@ -228,6 +229,7 @@ struct Slot {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     Job *job = nullptr;
+    bool reserved = false;        // held for a job whose workspace is being allocated
     std::deque<hipEvent_t> evs;   // one completion event per enqueued slice
 };
 
@@ -259,6 +261,11 @@ struct bbc_context {
     std::map<std::vector<int>, int2 *> groups;       // per (lattice, G): momentum groups
     std::mutex qmu;                                   // guards groups and plans for the server thread
     hipStream_t cin = nullptr, cout = nullptr;        // copy streams of the host-streamed direct path
+    // direct calls share the workspace and the energy array: each call's stream
+    // waits for the previous call's work (recorded on `last`), whatever streams
+    // the callers use
+    hipEvent_t last = nullptr;
+    bool last_valid = false;
     hipEvent_t sev[8] = {};
     // graph mode: the kernel sequence of a device-resident job captured once per
     // argument tuple on gs, then replayed on the caller's stream
@@ -289,6 +296,7 @@ struct bbc_context {
         clear_graphs();
         if (gs) (void)hipStreamDestroy(gs);
         for (auto e : sev) if (e) (void)hipEventDestroy(e);
+        if (last) (void)hipEventDestroy(last);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
     }
@@ -313,6 +321,17 @@ struct StageTimer {
 }  // namespace
 
 namespace {
+
+// Orders a direct call after the previous one on the context (called with ctx->mu held).
+bbc_status order_after_last(bbc_context *ctx, hipStream_t st) {
+    if (!ctx->last) HIP_TRY(hipEventCreateWithFlags(&ctx->last, hipEventDisableTiming));
+    if (ctx->last_valid) HIP_TRY(hipStreamWaitEvent(st, ctx->last, 0));
+    return BBC_OK;
+}
+bbc_status mark_last(bbc_context *ctx, hipStream_t st, bbc_status s) {
+    if (hipEventRecord(ctx->last, st) == hipSuccess) ctx->last_valid = true;
+    return s;
+}
 
 bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, bbc_precision prec,
                     DevPlan **out) {
@@ -791,6 +810,122 @@ void finish_job(Server &S, Job &j, int state) {
     S.done_cv.notify_all();
 }
 
+// Admission (called by the scheduler thread with S.mu held through lk).
+//
+// A queued job fits a free slot when the slot's workspace is large enough
+// (workspaces are kept between jobs and reused), or when replacing it by one
+// of the job's size keeps the committed bytes -- resident propagator sets plus
+// slot workspaces -- within the context budget.  Jobs are taken in arrival
+// order; when the job at the head does not fit, up to kBypassWindow later jobs
+// that do may start instead, at most kMaxBypass times per head job, so a large
+// job is delayed but never starved.  When nothing fits, the workspaces of idle
+// slots are released; if the head job still does not fit with no job running,
+// it can never run beside the resident propagator sets and is refused.
+// Device allocation and release happen with S.mu unlocked (hipFree waits for
+// the device); the slot is reserved for its job meanwhile.
+constexpr int kBypassWindow = 8;
+constexpr int kMaxBypass = 16;
+
+bool admit_jobs(bbc_context *ctx, std::unique_lock<std::mutex> &lk) {
+    Server &S = ctx->srv;
+    bool progressed = false;
+    auto fits = [&](const Slot &sl, const Job *j) {
+        if (j->foot <= sl.ws_bytes || !ctx->budget) return true;
+        return S.committed - sl.ws_bytes + j->foot <= ctx->budget;
+    };
+    for (;;) {
+        if (S.queue.empty() || S.stop) break;
+        bool any_free = false, any_busy = false;
+        for (auto &sl : S.slots) (sl.job || sl.reserved ? any_busy : any_free) = true;
+        if (!any_free) break;
+        Job *head = S.queue.front();
+        const size_t window = head->bypassed < kMaxBypass ? std::min<size_t>(S.queue.size(), 1 + kBypassWindow) : 1;
+        size_t pick = window;
+        Slot *slot = nullptr;
+        for (size_t q = 0; q < window && !slot; ++q) {
+            const Job *j = S.queue[q];
+            // best fit: the smallest free workspace that holds the job, else the
+            // largest free one that may be replaced within the budget
+            for (auto &sl : S.slots) {
+                if (sl.job || sl.reserved || !fits(sl, j)) continue;
+                const bool holds = sl.ws_bytes >= j->foot;
+                if (!slot) { slot = &sl; continue; }
+                const bool sholds = slot->ws_bytes >= j->foot;
+                if (holds && (!sholds || sl.ws_bytes < slot->ws_bytes)) slot = &sl;
+                else if (!holds && !sholds && sl.ws_bytes > slot->ws_bytes) slot = &sl;
+            }
+            if (slot) pick = q;
+        }
+        if (!slot) {
+            // nothing fits: release the workspaces of idle slots, then look again
+            std::vector<void *> drop;
+            for (auto &sl : S.slots)
+                if (!sl.job && !sl.reserved && sl.ws) {
+                    drop.push_back(sl.ws);
+                    S.committed -= sl.ws_bytes;
+                    sl.ws = nullptr;
+                    sl.ws_bytes = 0;
+                }
+            if (!drop.empty()) {
+                lk.unlock();
+                for (void *p : drop) (void)hipFree(p);
+                lk.lock();
+                progressed = true;
+                continue;
+            }
+            if (!any_busy) {
+                // no job runs and no idle workspace is left: the head job cannot fit
+                S.queue.pop_front();
+                head->status = BBC_ENOMEM;
+                head->err = "job workspace does not fit the HBM budget beside the resident propagator sets";
+                finish_job(S, *head, JOB_FAILED);
+                progressed = true;
+                continue;
+            }
+            break;   // wait for running jobs to free memory
+        }
+        Job *j = S.queue[pick];
+        S.queue.erase(S.queue.begin() + (long)pick);
+        if (pick > 0) head->bypassed++;
+        j->state = JOB_RUNNING;
+        j->t_start = Clock::now();
+        slot->reserved = true;
+        bool ok = true;
+        if (j->foot > slot->ws_bytes) {
+            void *old = slot->ws;
+            S.committed += j->foot - slot->ws_bytes;
+            slot->ws = nullptr;
+            slot->ws_bytes = 0;
+            lk.unlock();
+            if (old) (void)hipFree(old);
+            void *p = nullptr;
+            ok = hipMalloc(&p, j->foot) == hipSuccess;
+            lk.lock();
+            if (ok) { slot->ws = p; slot->ws_bytes = j->foot; }
+            else S.committed -= j->foot;
+        }
+        slot->reserved = false;
+        if (!ok) {
+            j->status = BBC_ENOMEM;
+            j->err = "hipMalloc of a job workspace failed";
+            finish_job(S, *j, JOB_FAILED);
+            progressed = true;
+            continue;
+        }
+        if (!j->energy.empty()) {
+            const PropSet &ps = *j->ps;
+            const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
+            const size_t wsz = workspace_bytes(V, j->dp->plan.ncomp, (int)j->chans.size(), j->dp->nslot,
+                                               ps.prec == BBC_F64 ? 16 : 8);
+            (void)hipMemcpyAsync((char *)slot->ws + ((wsz + 255) & ~(size_t)255), j->energy.data(),
+                                 8 * j->energy.size(), hipMemcpyHostToDevice, slot->st);
+        }
+        slot->job = j;
+        progressed = true;
+    }
+    return progressed;
+}
+
 // Continuous batching: every slot advances its job one time slice at a time
 // (at most two slices in flight per slot); as soon as a slot is free, the
 // next queued job is admitted if its workspace fits the context budget.
@@ -843,51 +978,7 @@ void server_loop(bbc_context *ctx) {
                 progressed = true;
             }
         }
-        for (auto &sl : S.slots) {
-            if (sl.job || S.queue.empty()) continue;
-            Job *j = S.queue.front();
-            if (j->foot > sl.ws_bytes) {
-                const size_t after = S.committed - sl.ws_bytes + j->foot;
-                if (ctx->budget && after > ctx->budget) {
-                    bool any_busy = false;
-                    for (auto &o : S.slots) any_busy = any_busy || o.job;
-                    if (!any_busy && sl.ws_bytes == 0) {
-                        // can never fit: refuse
-                        S.queue.pop_front();
-                        j->status = BBC_ENOMEM;
-                        j->err = "job workspace exceeds the HBM budget";
-                        finish_job(S, *j, JOB_FAILED);
-                        progressed = true;
-                    }
-                    break;   // wait for memory to free up (keeps arrival order)
-                }
-                if (sl.ws) { (void)hipFree(sl.ws); S.committed -= sl.ws_bytes; sl.ws = nullptr; sl.ws_bytes = 0; }
-                if (hipMalloc(&sl.ws, j->foot) != hipSuccess) {
-                    sl.ws = nullptr;
-                    S.queue.pop_front();
-                    j->status = BBC_ENOMEM;
-                    j->err = "hipMalloc of a job workspace failed";
-                    finish_job(S, *j, JOB_FAILED);
-                    progressed = true;
-                    continue;
-                }
-                sl.ws_bytes = j->foot;
-                S.committed += j->foot;
-            }
-            S.queue.pop_front();
-            j->state = JOB_RUNNING;
-            j->t_start = Clock::now();
-            if (!j->energy.empty()) {
-                const PropSet &ps = *j->ps;
-                const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
-                const size_t wsz = workspace_bytes(V, j->dp->plan.ncomp, (int)j->chans.size(), j->dp->nslot,
-                                                   ps.prec == BBC_F64 ? 16 : 8);
-                (void)hipMemcpyAsync((char *)sl.ws + ((wsz + 255) & ~(size_t)255), j->energy.data(),
-                                     8 * j->energy.size(), hipMemcpyHostToDevice, sl.st);
-            }
-            sl.job = j;
-            progressed = true;
-        }
+        if (admit_jobs(ctx, lk)) progressed = true;
         bool idle = S.queue.empty();
         for (auto &sl : S.slots) idle = idle && !sl.job;
         if (S.stop && idle) break;
@@ -1062,11 +1153,14 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     if (s) return s;
     const int L[3] = {lattice[0], lattice[1], lattice[2]};
     hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(ctx, st))) return s;
     if (prec == BBC_F64)
-        return run_correlate<double>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out,
-                                     nullptr, st, host_in, host_out);
-    return run_correlate<float>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, C_scale,
-                                st, host_in, host_out);
+        s = run_correlate<double>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, nullptr,
+                                  st, host_in, host_out);
+    else
+        s = run_correlate<float>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, C_scale,
+                                 st, host_in, host_out);
+    return mark_last(ctx, st, s);
 }
 
 
@@ -1102,11 +1196,14 @@ bbc_status bbc_correlate_cpt(bbc_context *ctx, const int32_t lattice[3], int Lt,
     if ((s = get_plan(ctx, chans, 2, prec, &lo))) return s;
     const int L[3] = {lattice[0], lattice[1], lattice[2]};
     hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(ctx, st))) return s;
     if (prec == BBC_F64)
-        return run_cpt<double>(ctx, up, lo, L, V, Lt, S_light, S_strange, t0, n_tau, tau_list, n_ch, energy, sign,
-                               R_out, nullptr, st);
-    return run_cpt<float>(ctx, up, lo, L, V, Lt, S_light, S_strange, t0, n_tau, tau_list, n_ch, energy, sign, R_out,
-                          R_scale, st);
+        s = run_cpt<double>(ctx, up, lo, L, V, Lt, S_light, S_strange, t0, n_tau, tau_list, n_ch, energy, sign,
+                            R_out, nullptr, st);
+    else
+        s = run_cpt<float>(ctx, up, lo, L, V, Lt, S_light, S_strange, t0, n_tau, tau_list, n_ch, energy, sign,
+                           R_out, R_scale, st);
+    return mark_last(ctx, st, s);
 }
 
 bbc_status bbc_server_start(bbc_context *ctx, int n_slots) {
@@ -1164,22 +1261,29 @@ bbc_status bbc_prop_upload(bbc_context *ctx, const int32_t lattice[3], bbc_preci
     const size_t one = (size_t)n_t * V * 144 * (prec == BBC_F64 ? 16 : 8);
     ps->bytes = 2 * one;
     {
+        // the bytes are reserved before allocating, so concurrent uploads cannot
+        // both pass the budget check
         std::lock_guard<std::mutex> lk(S.mu);
         if (ctx->budget && S.committed + ps->bytes > ctx->budget)
             return fail(BBC_ENOMEM, "propagator set exceeds the HBM budget");
+        S.committed += ps->bytes;
     }
-    HIP_TRY(hipSetDevice(ctx->device));
-    if (hipMalloc(&ps->dl, one) != hipSuccess || hipMalloc(&ps->ds, one) != hipSuccess) {
+    auto unreserve = [&](bbc_status st) {
         (void)hipFree(ps->dl);
         (void)hipFree(ps->ds);
-        return fail(BBC_ENOMEM, "hipMalloc of a propagator set failed");
-    }
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.committed -= ps->bytes;
+        return st;
+    };
+    if (hipSetDevice(ctx->device) != hipSuccess) return unreserve(fail(BBC_EDEVICE, "hipSetDevice"));
+    if (hipMalloc(&ps->dl, one) != hipSuccess || hipMalloc(&ps->ds, one) != hipSuccess)
+        return unreserve(fail(BBC_ENOMEM, "hipMalloc of a propagator set failed"));
     const hipMemcpyKind kl = is_host_pointer(S_light) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind ks = is_host_pointer(S_strange) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    HIP_TRY(hipMemcpy(ps->dl, S_light, one, kl));
-    HIP_TRY(hipMemcpy(ps->ds, S_strange, one, ks));
+    hipError_t e = hipMemcpy(ps->dl, S_light, one, kl);
+    if (e == hipSuccess) e = hipMemcpy(ps->ds, S_strange, one, ks);
+    if (e != hipSuccess) return unreserve(fail(BBC_EDEVICE, std::string("propagator copy: ") + hipGetErrorString(e)));
     std::lock_guard<std::mutex> lk(S.mu);
-    S.committed += ps->bytes;
     *handle = S.next_id++;
     S.props.emplace(*handle, std::move(ps));
     return BBC_OK;
@@ -1207,17 +1311,27 @@ bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *s
     Server &S = ctx->srv;
     std::unique_ptr<Job> j(new Job);
     {
+        // the reference is taken under the lock, so a concurrent bbc_prop_release
+        // cannot free the set between lookup and use
         std::lock_guard<std::mutex> lk(S.mu);
         if (!S.running) return fail(BBC_ESTATE, "server not started");
         auto it = S.props.find(prop);
         if (it == S.props.end() || it->second->released) return fail(BBC_EINVAL, "unknown propagator handle");
         j->ps = it->second.get();
+        j->ps->refs++;
     }
-    if (j->ps->prec == BBC_F32 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
+    // drops the reference on every early return
+    auto drop = [&](bbc_status st) {
+        std::lock_guard<std::mutex> lk(S.mu);
+        j->ps->refs--;
+        release_prop_if_unused(S, j->ps);
+        return st;
+    };
+    if (j->ps->prec == BBC_F32 && !C_scale) return drop(fail(BBC_EINVAL, "C_scale is required in FP32 mode"));
     if (is_host_pointer(C_out) || (C_scale && j->ps->prec == BBC_F32 && is_host_pointer(C_scale)))
-        return fail(BBC_EINVAL, "C_out and C_scale of a served job must be device memory");
+        return drop(fail(BBC_EINVAL, "C_out and C_scale of a served job must be device memory"));
     for (int i = 0; i < n_t; ++i)
-        if (slice_idx[i] < 0 || slice_idx[i] >= j->ps->n_t) return fail(BBC_EINVAL, "slice index out of range");
+        if (slice_idx[i] < 0 || slice_idx[i] >= j->ps->n_t) return drop(fail(BBC_EINVAL, "slice index out of range"));
     j->slice.assign(slice_idx, slice_idx + n_t);
     j->tl.assign(t_list, t_list + n_t);
     j->t0 = t0;
@@ -1227,13 +1341,14 @@ bbc_status bbc_submit(bbc_context *ctx, uint64_t prop, int n_t, const int32_t *s
     j->out = C_out;
     j->scale = j->ps->prec == BBC_F32 ? C_scale : nullptr;
     bbc_status s = get_plan(ctx, j->chans, spin == BBC_SPIN_LOWER ? 2 : 0, (bbc_precision)j->ps->prec, &j->dp);
-    if (s) return s;
+    if (s) return drop(s);
     j->foot = job_footprint(*j);
-    if (ctx->budget && j->foot > ctx->budget) return fail(BBC_ENOMEM, "job workspace exceeds the HBM budget");
+    // a job that cannot fit beside its own propagator set can never run
+    if (ctx->budget && j->foot + j->ps->bytes > ctx->budget)
+        return drop(fail(BBC_ENOMEM, "job workspace and its propagator set exceed the HBM budget"));
     std::lock_guard<std::mutex> lk(S.mu);
     j->id = S.next_id++;
     j->t_submit = Clock::now();
-    j->ps->refs++;
     *job = j->id;
     S.queue.push_back(j.get());
     S.jobs.emplace(j->id, std::move(j));

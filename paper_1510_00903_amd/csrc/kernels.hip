@@ -514,14 +514,15 @@ static void fft_axis(typename cplx_t<T>::type *data, long ncomp, const int L[3],
                        axis, sgn);
 }
 
-// 96-point lines: one line per thread in FP32 (fits the registers, most loads in
-// flight); the two-factor LDS form (12 x 8) in FP64, where a 96-point line per
-// thread would spill to scratch.
-template <typename T>
-static void fft_axis96(typename cplx_t<T>::type *data, long ncomp, const int L[3], int axis, int sgn,
-                       hipStream_t st) {
-    if constexpr (sizeof(T) == 8) fft_axis_lds<T, 12, 8>(data, ncomp, L, axis, sgn, st);
-    else fft_axis<T, 96>(data, ncomp, L, axis, sgn, st);
+// 48-, 64- and 96-point lines: one line per thread in FP32 (fits the registers,
+// most loads in flight); the two-factor LDS form (6 x 8, 8 x 8, 12 x 8) in FP64,
+// where a whole line per thread would spill to scratch.
+template <typename T, int N>
+static void fft_axis_long(typename cplx_t<T>::type *data, long ncomp, const int L[3], int axis, int sgn,
+                          hipStream_t st) {
+    static_assert(N == 48 || N == 64 || N == 96, "long lines");
+    if constexpr (sizeof(T) == 8) fft_axis_lds<T, N / 8, 8>(data, ncomp, L, axis, sgn, st);
+    else fft_axis<T, N>(data, ncomp, L, axis, sgn, st);
 }
 
 template <typename T>
@@ -541,9 +542,9 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
             case 16: fft_axis<T, 16>(data, ncomp, L, 2, sgn, st); break;
             case 24: fft_axis<T, 24>(data, ncomp, L, 2, sgn, st); break;
             case 32: fft_axis<T, 32>(data, ncomp, L, 2, sgn, st); break;
-            case 48: fft_axis<T, 48>(data, ncomp, L, 2, sgn, st); break;
-            case 64: fft_axis<T, 64>(data, ncomp, L, 2, sgn, st); break;
-            case 96: fft_axis96<T>(data, ncomp, L, 2, sgn, st); break;
+            case 48: fft_axis_long<T, 48>(data, ncomp, L, 2, sgn, st); break;
+            case 64: fft_axis_long<T, 64>(data, ncomp, L, 2, sgn, st); break;
+            case 96: fft_axis_long<T, 96>(data, ncomp, L, 2, sgn, st); break;
             default: return -1;
             }
             ++n;
@@ -564,9 +565,9 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
         case 16: fft_axis<T, 16>(data, ncomp, L, axis, sgn, st); break;
         case 24: fft_axis<T, 24>(data, ncomp, L, axis, sgn, st); break;
         case 32: fft_axis<T, 32>(data, ncomp, L, axis, sgn, st); break;
-        case 48: fft_axis<T, 48>(data, ncomp, L, axis, sgn, st); break;
-        case 64: fft_axis<T, 64>(data, ncomp, L, axis, sgn, st); break;
-        case 96: fft_axis96<T>(data, ncomp, L, axis, sgn, st); break;
+        case 48: fft_axis_long<T, 48>(data, ncomp, L, axis, sgn, st); break;
+        case 64: fft_axis_long<T, 64>(data, ncomp, L, axis, sgn, st); break;
+        case 96: fft_axis_long<T, 96>(data, ncomp, L, axis, sgn, st); break;
         default: return -1;
         }
     }

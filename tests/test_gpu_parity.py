@@ -162,8 +162,9 @@ def test_z96_sampled_points(bbc, ctx, prec):
 @pytest.mark.parametrize("lat", [(48, 2, 2), (2, 48, 2), (2, 2, 48), (96, 1, 2), (1, 64, 1)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_long_line_fft_extents(bbc, ctx, lat, prec):
-    """Extents 48, 64 and 96 take the two-factor LDS FFT on each axis (forward and
-    inverse): full field of two channels against the oracle."""
+    """Extents 48, 64 and 96 on each axis (forward and inverse): the two-factor LDS
+    FFT (6 x 8, 8 x 8, 12 x 8) in FP64 and one line per thread in registers in FP32;
+    full field of two channels against the oracle."""
     Lx, Ly, Lz = lat
     dtype = np.complex128 if prec == "f64" else np.complex64
     Sl, Ss = synth.propagators(lat, 1, seed=115, dtype=dtype)
