@@ -264,10 +264,10 @@ bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job);
  *   1 forward FFT (step 1b): one pass per axis, or on small cubic lattices one
  *     fused pass that also writes the momentum groups
  *   2 copy into the momentum groups (no kernel when stage 1 was fused)
- *   3 open-index contraction into partial slots (step 2a)
+ *   3 open-index contraction of every pair of intermediates (step 2a, matrix cores)
  *   4 inverse FFT (step 2b), one pass per axis
  *   5 normalisation / output layout
- *   6 per-channel sum of the partial slots
+ *   6 channels as weighted sums of the pair products (step 2a)
  * bbc_profile_read waits for the recorded events, adds their elapsed times to
  * ms[stage] (milliseconds) and the number of kernels launched inside them to
  * launches[stage] (both arrays of n_stages <= BBC_NUM_STAGES entries,

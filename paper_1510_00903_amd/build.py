@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbbcorr.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "postproc.hip", "api.cpp", "plan.cpp")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "plan.hpp")] + [
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "postproc.hip", "api.cpp", "plan.cpp", "pairs.cpp")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "plan.hpp", "pairs.hpp")] + [
     os.path.join(ROOT, "include", "bbcorr.h")]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] if not src.endswith("plan.cpp") else []
+        lang = ["-x", "hip"] if src.endswith((".hip", "api.cpp")) else []
         cmd = [HIPCC] + FLAGS + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -23,6 +23,7 @@
 
 #include "../../include/bbcorr.h"
 #include "kernels.hpp"
+#include "pairs.hpp"
 #include "plan.hpp"
 
 namespace {
@@ -45,96 +46,19 @@ struct DevPlan {
     bbc::BlockPatterns pats;
     uint32_t *d_terms = nullptr;
     int32_t *d_term_begin = nullptr;
-    bbc::DDiag *d_diags = nullptr;
-    bbc::DRef *d_refs = nullptr;
-    int4 *d_segs = nullptr;
-    int32_t *d_ch_slot_begin = nullptr;
-    int ntask = 0, nslot = 0;
+    // pair form of the contraction (pairs.hpp)
+    bbc::PTask *d_tasks = nullptr;
+    int32_t *d_pterm_begin = nullptr, *d_pterm_pair = nullptr;
+    double *d_pterm_w = nullptr;
+    int ntask = 0, npair = 0;
     int2 *d_content = nullptr;      // per requested channel: (n_light, n_strange)
     size_t table_bytes = 0;
     ~DevPlan() {
-        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_diags);
-        (void)hipFree(d_refs); (void)hipFree(d_segs); (void)hipFree(d_ch_slot_begin); (void)hipFree(d_content);
+        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_tasks);
+        (void)hipFree(d_pterm_begin); (void)hipFree(d_pterm_pair); (void)hipFree(d_pterm_w);
+        (void)hipFree(d_content);
     }
 };
-
-// Contraction tables of a plan.  Per requested channel: its diagrams, cut into
-// segments of whole diagrams holding about seg_items (diagram, k3, k4) items
-// each (seg_items_for: 256 in FP64, 512 in FP32 -- in FP64 the smaller
-// segments give more tasks per momentum group, so fewer groups are in flight
-// per XCD and their 2 MB of data stay in L2).  Every segment owns one partial-result slot; the slots of a channel are
-// contiguous.  Segments, largest first, are dealt four to a task (one per wave
-// of a workgroup).  A diagram records its carry pattern, K = kdim3 * kdim4 and
-// kdim4 with a 16-bit reciprocal, from which a lane rebuilds (k3, k4) = divmod(kk, kdim4).
-int seg_items_for(bbc_precision prec) { return prec == BBC_F64 ? 256 : 512; }
-
-void contraction_tables(const bbc::Plan &P, int seg_items, std::vector<bbc::DDiag> &diags,
-                        std::vector<bbc::DRef> &refs, std::vector<int4> &segs, std::vector<int32_t> &ch_slot_begin,
-                        int *ntask) {
-    const int n = (int)P.channels.size();
-    ch_slot_begin.assign(n + 1, 0);
-    std::vector<int4> all;   // (first diagram, end diagram, slot, items)
-    int slot = 0;
-    for (int m = 0; m < n; ++m) {
-        const int db = (int)diags.size();
-        long total = 0;
-        for (int d = P.ch_begin[m]; d < P.ch_begin[m + 1]; ++d) {
-            const bbc::Diagram &D = P.diags[d];
-            bbc::DDiag dd{};
-            dd.coef = D.coef;
-            const int kd4 = D.kdim[1];
-            const int inv = (65536 + kd4 - 1) / kd4;
-            for (int kk = 0; kk < D.K; ++kk)
-                if (((kk * inv) >> 16) != kk / kd4) throw std::logic_error("open-index reciprocal");
-            if (D.K > 255 || kd4 > 15) throw std::logic_error("open-index range");
-            dd.pad[0] = (D.carry[0] + 2 * D.carry[1]) | (D.K << 2) | (kd4 << 10);
-            dd.pad[1] = inv;
-            for (int s = 0; s < 2; ++s) {
-                int b = (int)refs.size();
-                for (const bbc::BlockRef &br : D.blk[s]) {
-                    const bbc::Intermediate &I = P.inters[br.inter];
-                    bbc::DRef r{};
-                    r.coef = br.coef;
-                    r.base = I.offset;
-                    int so[2] = {0, 0}, sk[2] = {0, 0};
-                    for (int X = 0; X < 2; ++X) {
-                        int y = br.ymap[X];
-                        if (y < 0) continue;
-                        if (I.no[y] == 2) so[X] = I.stride_o[y];
-                        if (I.nk[y] > 1) sk[X] = I.stride_k[y];
-                    }
-                    r.so3 = so[0]; r.so4 = so[1]; r.sk3 = sk[0]; r.sk4 = sk[1];
-                    refs.push_back(r);
-                }
-                if (s == 0) { dd.ref0 = b; dd.ref0_end = (int)refs.size(); }
-                else { dd.ref1 = b; dd.ref1_end = (int)refs.size(); }
-            }
-            diags.push_back(dd);
-            total += D.K;
-        }
-        const int de = (int)diags.size();
-        const int nseg = (int)std::max<long>(1, (total + seg_items - 1) / seg_items);
-        ch_slot_begin[m] = slot;
-        long acc = 0;
-        int sb = db;
-        for (int d = db; d < de; ++d) {
-            acc += P.diags[P.ch_begin[m] + (d - db)].K;
-            // close a segment when the running count reaches the next 1/nseg mark
-            const long mark = total * (long)(slot - ch_slot_begin[m] + 1) / nseg;
-            if (acc >= mark || d + 1 == de) {
-                long items = 0;
-                for (int e = sb; e <= d; ++e) items += P.diags[P.ch_begin[m] + (e - db)].K;
-                all.push_back(make_int4(sb, d + 1, slot++, (int)items));
-                sb = d + 1;
-            }
-        }
-    }
-    ch_slot_begin[n] = slot;
-    std::stable_sort(all.begin(), all.end(), [](const int4 &a, const int4 &b) { return a.w > b.w; });
-    *ntask = (int)((all.size() + 3) / 4);
-    segs.assign((size_t)*ntask * 4, make_int4(0, 0, 0, 0));
-    for (size_t i = 0; i < all.size(); ++i) segs[i] = make_int4(all[i].x, all[i].y, all[i].z, 0);
-}
 
 // Number of self-conjugate momenta (q = -q mod L): 0 and L/2 along each even axis.
 long self_conjugate(const int L[3]) {
@@ -376,24 +300,21 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         }
         c = e;
     }
-    std::vector<bbc::DDiag> diags;
-    std::vector<bbc::DRef> refs;
-    std::vector<int4> segs;
-    std::vector<int32_t> ch_slot_begin;
+    bbc::PairTables pt;
     try {
-        contraction_tables(P, seg_items_for(prec), diags, refs, segs, ch_slot_begin, &dp->ntask);
+        pt = bbc::build_pair_tables(P);
     } catch (const std::exception &e) {
         return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
     }
-    dp->nslot = ch_slot_begin.back();
-    if (diags.size() >= (1u << 24)) return fail(BBC_EUNSUPPORTED, "too many diagrams in one request");
+    dp->ntask = (int)pt.tasks.size();
+    dp->npair = pt.npair;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(upload_vec(&dp->d_terms, P.terms));
     HIP_TRY(upload_vec(&dp->d_term_begin, P.term_begin));
-    HIP_TRY(upload_vec(&dp->d_diags, diags));
-    HIP_TRY(upload_vec(&dp->d_refs, refs));
-    HIP_TRY(upload_vec(&dp->d_segs, segs));
-    HIP_TRY(upload_vec(&dp->d_ch_slot_begin, ch_slot_begin));
+    HIP_TRY(upload_vec(&dp->d_tasks, pt.tasks));
+    HIP_TRY(upload_vec(&dp->d_pterm_begin, pt.term_begin));
+    HIP_TRY(upload_vec(&dp->d_pterm_pair, pt.term_pair));
+    HIP_TRY(upload_vec(&dp->d_pterm_w, pt.term_w));
     {
         std::vector<int2> content;
         for (int ch : P.channels) {
@@ -405,9 +326,8 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         }
         HIP_TRY(upload_vec(&dp->d_content, content));
     }
-    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 +
-                      diags.size() * sizeof(bbc::DDiag) + refs.size() * sizeof(bbc::DRef) +
-                      segs.size() * sizeof(int4) + ch_slot_begin.size() * 4;
+    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + pt.tasks.size() * sizeof(bbc::PTask) +
+                      pt.term_begin.size() * 4 + pt.term_pair.size() * 4 + pt.term_w.size() * 8;
     *out = dp.get();
     ctx->plans.emplace(key, std::move(dp));
     return BBC_OK;
@@ -415,25 +335,28 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
 
 // Workspace of one slice:
 //   region A: the intermediates I in site space (2 spins x nc x V); once they
-//             are transposed it is dead, and the contracted fields Ct (n_ch x 16
-//             x V) and the partial slots (nslot x 16 x V) reuse it;
+//             are in the momentum groups it is dead, and the contracted fields
+//             Ct (n_ch x 16 x V) and, after them, the pair products
+//             P (npair x 16 per grouped position, at most V + 8) reuse it;
 //   region B: the momentum-grouped copy Iq (groups x 2 x nc x G, at most V + 8
 //             positions);
 //   then the rescale maxima of the FP32 form.
 struct WsLayout {
-    size_t a, b, total;   // byte offsets of region B, of the small tail, and total size
+    size_t p, a, b, total;   // byte offsets of P (inside region A), of region B, of the small tail; total
 };
-WsLayout ws_layout(long V, int nc, int n_ch, int nslot, size_t csize) {
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+WsLayout ws_layout(long V, int nc, int n_ch, int npair, size_t csize) {
     WsLayout L;
-    const size_t ra = std::max<size_t>((size_t)2 * nc, (size_t)(n_ch + nslot) * 16) * V * csize;
+    L.p = align256((size_t)n_ch * 16 * V * csize);
+    const size_t ra = std::max<size_t>((size_t)2 * nc * V * csize, L.p + (size_t)npair * 16 * (V + 8) * csize);
     const size_t rb = (size_t)2 * nc * (V + 8) * csize;
-    L.a = (ra + 255) & ~(size_t)255;
-    L.b = L.a + ((rb + 255) & ~(size_t)255);
+    L.a = align256(ra);
+    L.b = L.a + align256(rb);
     L.total = L.b + 256;
     return L;
 }
-size_t workspace_bytes(long V, int nc, int n_ch, int nslot, size_t csize) {
-    return ws_layout(V, nc, n_ch, nslot, csize).total;
+size_t workspace_bytes(long V, int nc, int n_ch, int npair, size_t csize) {
+    return ws_layout(V, nc, n_ch, npair, csize).total;
 }
 
 bbc_status check_lattice(const int32_t *lattice, long *V) {
@@ -495,14 +418,14 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     using T2 = typename bbc::cplx_t<T>::type;
     const bbc::Plan &P = dp->plan;
     const int nc = P.ncomp;
-    const WsLayout lay = ws_layout(V, nc, n_ch, dp->nslot, sizeof(T2));
+    const WsLayout lay = ws_layout(V, nc, n_ch, dp->npair, sizeof(T2));
     T2 *I = (T2 *)ws;
     T2 *Iq = (T2 *)((char *)ws + lay.a);
-    T2 *Ct = I;                                   // reuses region A after the transpose
-    T2 *slots = Ct + (size_t)n_ch * 16 * V;
+    T2 *Ct = I;                                   // reuses region A once Iq is written
+    T2 *Pp = (T2 *)((char *)ws + lay.p);
     uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
-    bbc::ContractTables tb{mg.pos, mg.ngroup, dp->ntask, dp->d_segs, dp->d_diags, dp->d_refs,
-                           dp->d_ch_slot_begin, dp->nslot};
+    bbc::PairDevTables tb{mg.pos, mg.ngroup, dp->d_tasks, dp->ntask, dp->npair,
+                          dp->d_pterm_begin, dp->d_pterm_pair, dp->d_pterm_w};
     const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
     T2 *out = (T2 *)outp;
     const bool fp32 = sizeof(T) == 4;
@@ -536,11 +459,11 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     }
     {
         StageTimer tm(pc, st, 3);
-        bbc::launch_contract<T>(Iq, slots, nc, V, tb, st);
+        bbc::launch_pairs<T>(Iq, Pp, nc, tb, st);
     }
     {
         StageTimer tm(pc, st, 6);
-        bbc::launch_combine<T>(slots, Ct, n_ch, V, dp->d_ch_slot_begin, st);
+        bbc::launch_pair_combine<T>(Pp, Ct, n_ch, V, tb, st);
     }
     {
         StageTimer tm(pc, st, 4);
@@ -604,7 +527,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
                          bool host_out) {
     using T2 = typename bbc::cplx_t<T>::type;
     const size_t cs = sizeof(T2);
-    const size_t core = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->nslot, cs);
+    const size_t core = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, cs);
     const size_t in_slice = (size_t)V * 144 * cs, out_slice = (size_t)n_ch * V * 16 * cs;
     const size_t in_stage = host_in ? 2 * 2 * in_slice : 0, out_stage = host_out ? 2 * out_slice : 0;
     const size_t need = core + in_stage + out_stage;
@@ -720,8 +643,8 @@ bbc_status run_cpt(bbc_context *ctx, DevPlan *up, DevPlan *lo, const int L[3], l
     using T2 = typename bbc::cplx_t<T>::type;
     constexpr bool fp32 = sizeof(T) == 4;
     const size_t cs = sizeof(T2);
-    const size_t core = std::max(workspace_bytes(V, up->plan.ncomp, n_ch, up->nslot, cs),
-                                 workspace_bytes(V, lo->plan.ncomp, n_ch, lo->nslot, cs));
+    const size_t core = std::max(workspace_bytes(V, up->plan.ncomp, n_ch, up->npair, cs),
+                                 workspace_bytes(V, lo->plan.ncomp, n_ch, lo->npair, cs));
     const size_t out_slice = (size_t)n_ch * V * 16 * cs;
     const size_t bwd_off = (core + 255) & ~(size_t)255;
     const size_t sc_off = (bwd_off + out_slice + 255) & ~(size_t)255;
@@ -762,7 +685,7 @@ namespace {
 size_t job_footprint(const Job &j) {
     const long V = (long)j.ps->L[0] * j.ps->L[1] * j.ps->L[2];
     const size_t cs = j.ps->prec == BBC_F64 ? 16 : 8;
-    return workspace_bytes(V, j.dp->plan.ncomp, (int)j.chans.size(), j.dp->nslot, cs) + 8 * j.chans.size() + 256;
+    return workspace_bytes(V, j.dp->plan.ncomp, (int)j.chans.size(), j.dp->npair, cs) + 8 * j.chans.size() + 256;
 }
 
 // Enqueues slice j.next of a running job on its slot.
@@ -771,7 +694,7 @@ bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
     const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
     const int n_ch = (int)j.chans.size();
     bbc_status s;
-    const size_t wsz = workspace_bytes(V, j.dp->plan.ncomp, n_ch, j.dp->nslot, ps.prec == BBC_F64 ? 16 : 8);
+    const size_t wsz = workspace_bytes(V, j.dp->plan.ncomp, n_ch, j.dp->npair, ps.prec == BBC_F64 ? 16 : 8);
     const double *d_energy = j.energy.empty() ? nullptr : (const double *)((char *)sl.ws + ((wsz + 255) & ~(size_t)255));
     const int n = j.next;
     const int si = j.slice[n];
@@ -915,7 +838,7 @@ bool admit_jobs(bbc_context *ctx, std::unique_lock<std::mutex> &lk) {
         if (!j->energy.empty()) {
             const PropSet &ps = *j->ps;
             const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
-            const size_t wsz = workspace_bytes(V, j->dp->plan.ncomp, (int)j->chans.size(), j->dp->nslot,
+            const size_t wsz = workspace_bytes(V, j->dp->plan.ncomp, (int)j->chans.size(), j->dp->npair,
                                                ps.prec == BBC_F64 ? 16 : 8);
             (void)hipMemcpyAsync((char *)slot->ws + ((wsz + 255) & ~(size_t)255), j->energy.data(),
                                  8 * j->energy.size(), hipMemcpyHostToDevice, slot->st);
@@ -1111,13 +1034,8 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
     std::vector<int> chans(ch_list, ch_list + n_ch);
     try {
         bbc::Plan P = bbc::build_plan(chans, 0);
-        std::vector<bbc::DDiag> diags;
-        std::vector<bbc::DRef> refs;
-        std::vector<int4> segs;
-        std::vector<int32_t> csb;
-        int ntask = 0;
-        contraction_tables(P, seg_items_for(prec), diags, refs, segs, csb, &ntask);
-        *bytes = workspace_bytes(V, P.ncomp, n_ch, csb.back(), prec == BBC_F64 ? 16 : 8);
+        const bbc::PairTables pt = bbc::build_pair_tables(P);
+        *bytes = workspace_bytes(V, P.ncomp, n_ch, pt.npair, prec == BBC_F64 ? 16 : 8);
     } catch (const std::exception &e) {
         return fail(BBC_EINVAL, e.what());
     }

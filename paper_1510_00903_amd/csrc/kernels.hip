@@ -10,7 +10,8 @@
 //                the z pass writing into the momentum groups
 //   k_transpose_grouped  component-major [g][comp][q] -> momentum groups (GroupLayout;
 //                lattices without a fused form)
-//   k_contract   step 2a: open-index sums per momentum, all channels    (workgroups per group)
+//   k_pairs      step 2a: open-index sums of every pair of intermediates, per momentum (MFMA)
+//   k_pair_combine  step 2a: channels as weighted sums of the pair products
 //   k_fft (x3)   step 2b: inverse 3-D FFT of the 16 spin components per channel
 //   k_finalize   normalisation and transpose to the output layout [r][spin]
 #include "kernels.hpp"
@@ -595,25 +596,14 @@ int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int
 template <typename T2> struct GroupLayout;
 template <> struct GroupLayout<double2> {
     static constexpr int G = 8;
-    static constexpr int S = 1;      // stride of the momentum lane
-    static constexpr int SG = 8;     // stride of the sink spin
+    static constexpr int S = 2;      // stride of the momentum lane
+    static constexpr int SG = 1;     // stride of the sink spin
 };
 template <> struct GroupLayout<float2> {
     static constexpr int G = 8;
     static constexpr int S = 2;
     static constexpr int SG = 1;
 };
-
-// Loads both sink spins of one component for one momentum lane.
-__device__ __forceinline__ void load_spins(const double2 *__restrict__ p, unsigned i, double2 &v0, double2 &v1) {
-    v0 = p[i];
-    v1 = p[i + GroupLayout<double2>::SG];
-}
-__device__ __forceinline__ void load_spins(const float2 *__restrict__ p, unsigned i, float2 &v0, float2 &v1) {
-    const float4 v = *reinterpret_cast<const float4 *>(p + i);
-    v0 = float2{v.x, v.y};
-    v1 = float2{v.z, v.w};
-}
 
 // Tile: 64 positions x TC components x both sink spins through LDS; read along
 // the (grouped) momenta, written as one contiguous run per group.
@@ -889,241 +879,352 @@ int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>:
 }
 
 // ----------------------------------------------------------------------------
-// Step 2a: contraction in momentum space (Sec. 3, Eq. (LN.pLLp.FFT)):
-//   C~_ch(q)_{a b a' b'} = sum_diagrams coef * sum_{k3,k4} E1(q; a, ., k) E2(-q; b, ., k)
-// with each block value E a weighted sum of intermediate components, and the
-// outer source spins a', b' carried by one of the two blocks each (the site
-// holding that source baryon's delta quark).
+// Step 2a: contraction in momentum space (Sec. 3, Eq. (LN.pLLp.FFT)), pair form.
 //
-// Work decomposition: the diagrams of each channel are cut into segments of
-// whole diagrams; four segments form a task (one per wave).  Workgroup =
-// (momentum group, task).  A wave walks its diagrams one at a time, so the
-// diagram and block tables are wave-uniform (scalar loads); its 64 lanes are
-// 64/G open-index lanes x G momentum lanes, each open-index lane taking one
-// (k3, k4) of the diagram per step.  The G momentum lanes of an open index read
-// one 128-byte line per load.  Workgroup ids are mapped so that all tasks of
-// a group run back to back on the same XCD: the group's intermediates (the
-// only data the tasks read, about 2 MB) then stay in that XCD's L2.  Each wave
-// reduces its segment and writes one partial result slot per momentum;
-// k_combine adds the slots of a channel in a fixed order (no atomics: results
-// are bit-reproducible).
-// Iq layout: GroupLayout (per group, component-major); slot layout: [slot][16][V].
+// Every channel is a weighted sum of pair products (pairs.hpp)
+//   P_p(q)_{a b a' b'} = sum_k X_p(q; a, ., k) Y_p(-q; b, ., k),
+// a complex product of a (sink spin x outer spin) x k matrix at each site with
+// the open source indices k = (k3, k4) contracted.  k_pairs computes every
+// pair product once per momentum with the matrix cores; k_pair_combine forms
+// the channels from them with fixed weights in a fixed order.
+//
+// MFMA operand layouts (measured on gfx950):
+//   FP64 v_mfma_f64_4x4x4_4b (4 blocks, K = 4): A[b][i][k] in lane i + 4b + 16k,
+//        B[b][k][j] in lane j + 4b + 16k, D[b][i][j] in lane j + 4b + 16i;
+//   FP32 v_mfma_f32_4x4x1_16b (16 blocks, K = 1): A[b][i] and B[b][j] in lane
+//        i + 4b (j + 4b), D[b][i][j] in lane j + 4b, register i.
+// Blocks are momenta: FP64 a wave takes one group of 8 momenta as two sets of 4;
+// FP32 a wave takes two groups (16 momenta).  Rows i and columns j are
+// (sink spin g = i & 1, outer spin i >> 1), so with the grouped layout
+// [c][momentum][g] every operand load of a wave reads whole 128-byte lines.
+// A complex product takes two real products per part:
+//   re += Ar Br + (-Ai) Bi,   im += Ar Bi + Ai Br.
+// A task shares its row operand among up to 8 column views (partners), each
+// with its own accumulators; shape 1 (8 x 2) runs as two 4 x 4 halves with two
+// zero columns.  A wave runs one task; workgroup = (momentum unit, 4 tasks),
+// all tasks of a unit back to back on one XCD so the unit's data stays in that
+// XCD's L2.  Output P[group][pair][spin][G], spin = a + 2 (b + 2 (a' + 2 b')).
 // ----------------------------------------------------------------------------
-// One diagram for this lane's momentum: sum over the (k3, k4) taken by this
-// open-index lane of E1(q) (x) E2(-q), each block value E a weighted sum of
-// intermediate components.  `base` points at the group's data; la / lb are the
-// offsets of the lanes of q and -q.  Table data (D, refs) is wave-uniform.
-// Each step a lane takes IPL open indices (kk, kk + NI, ...), sharing the
-// table reads; indices past K are replaced by a valid one with weight 0.
-// Products are formed in T and summed in FP64 (in the FP32 form this keeps the
-// open-index and diagram sums free of FP32 rounding).
-template <typename T, int C3, int C4, int IPL>
-__device__ __forceinline__ void diagram_sum(const typename cplx_t<T>::type *__restrict__ base, unsigned la,
-                                            unsigned lb, const DDiag &D, const DRef *__restrict__ refs, int il,
-                                            double2 (&acc)[16]) {
+typedef double dmfma_acc;
+typedef float fmfma4 __attribute__((ext_vector_type(4)));
+
+// Component offset of a row (or column) value: the task's view, the lane's outer
+// spin(s) and open index.
+struct LaneView {
+    int base;        // view base + outer-spin offsets of this lane's row/column
+    int sk3, sk4;
+};
+
+__device__ __forceinline__ int outer_stride(const PView &v, bool a_prime) { return a_prime ? v.so3 : v.so4; }
+
+// FP64: one task for one group of 8 momenta.
+template <int NP, int SHAPE>
+__device__ __forceinline__ void pair_task64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
+                                            const PTask &T, int lane, const int mir[2]) {
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int G = GroupLayout<double2>::G;
+    constexpr int S = GroupLayout<double2>::S, SG = GroupLayout<double2>::SG;
+    const int ij = lane & 3, blk = (lane >> 2) & 3, kl = lane >> 4;
+    const int g = ij & 1, o = ij >> 1;
+    // momentum slots of the row and column reads of this lane, per set
+    int srow[2], scol[2];
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+        const int m = blk + 4 * st;
+        srow[st] = T.row_site == 0 ? m : mir[st];
+        scol[st] = T.row_site == 0 ? mir[st] : m;
+    }
+    // row: shape 0 -> outer spin o of the view's carried one; shape 1 -> a' = o, b' = half
+    const int rbase = T.row.base + o * (SHAPE == 0 ? outer_stride(T.row, T.row_a) : T.row.so3);
+    const int rso4 = T.row.so4;
+    bool colvalid = true;
+    int cbase[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (SHAPE == 0) cbase[p] = T.col[p].base + o * outer_stride(T.col[p], !T.row_a);
+        else cbase[p] = T.col[p].base;
+    }
+    if (SHAPE == 1) colvalid = ij < 2;
+    double acc[NP][2][H][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int h = 0; h < H; ++h) acc[p][st][h][0] = acc[p][st][h][1] = 0.0;
+    const int K = T.K;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + kl;
+        const bool valid = kk < K;
+        const int k3 = valid ? (kk * T.inv) >> 16 : 0;
+        const int k4 = valid ? kk - k3 * T.kd4 : 0;
+        double2 av[2][H];
+        const int roff = rbase + k3 * T.row.sk3 + k4 * T.row.sk4;
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                av[st][h] = valid ? gb[(unsigned)(roff + h * rso4) * (2 * G) + srow[st] * S + g * SG]
+                                  : double2{0.0, 0.0};
+            }
+        double2 bv[NP][2];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int coff = cbase[p] + k3 * T.col[p].sk3 + k4 * T.col[p].sk4;
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+                bv[p][st] = (valid && colvalid) ? gb[(unsigned)coff * (2 * G) + scol[st] * S + g * SG]
+                                                : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const double2 a = av[st][h], b = bv[p][st];
+                    double re = acc[p][st][h][0], im = acc[p][st][h][1];
+                    re = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.x, re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f64_4x4x4f64(-a.y, b.y, re, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.y, im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, b.x, im, 0, 0, 0);
+                    acc[p][st][h][0] = re;
+                    acc[p][st][h][1] = im;
+                }
+    }
+    // D lane (j = lane & 3, block, i = lane >> 4)
+    const int j = lane & 3, i = lane >> 4;
+    if (SHAPE == 1 && j >= 2) return;
+    const int gR = i & 1, oR = i >> 1, gC = j & 1, oC = j >> 1;
+    const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        int ap, bp;
+        if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+        else { ap = oR; bp = h; }
+        const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            double2 *dst = pb + ((size_t)T.pair[p] * 16 + sp) * G;
+#pragma unroll
+            for (int st = 0; st < 2; ++st) dst[blk + 4 * st] = double2{acc[p][st][h][0], acc[p][st][h][1]};
+        }
+    }
+}
+
+// FP32: one task for two groups (16 momenta).  gb0/gb1 and pb0/pb1 are the
+// groups' data and outputs; lanes of a missing second group load zeros and
+// store nothing.
+template <int NP, int SHAPE>
+__device__ __forceinline__ void pair_task32(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
+                                            float2 *__restrict__ pb0, float2 *__restrict__ pb1, bool has1,
+                                            const PTask &T, int lane, int mir) {
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int G = GroupLayout<float2>::G;
+    constexpr int S = GroupLayout<float2>::S, SG = GroupLayout<float2>::SG;
+    const int ij = lane & 3, blk = lane >> 2;
+    const int g = ij & 1, o = ij >> 1;
+    const bool second = blk >= 8;
+    const bool active = !second || has1;
+    const float2 *gb = second ? gb1 : gb0;
+    const int m = blk & 7;
+    const int srow = T.row_site == 0 ? m : mir, scol = T.row_site == 0 ? mir : m;
+    const int rbase = T.row.base + o * (SHAPE == 0 ? outer_stride(T.row, T.row_a) : T.row.so3);
+    const int rso4 = T.row.so4;
+    int cbase[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (SHAPE == 0) cbase[p] = T.col[p].base + o * outer_stride(T.col[p], !T.row_a);
+        else cbase[p] = T.col[p].base;
+    }
+    const bool colvalid = active && (SHAPE == 0 || ij < 2);
+    fmfma4 acc[NP][H][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int h = 0; h < H; ++h) acc[p][h][0] = acc[p][h][1] = fmfma4{0.f, 0.f, 0.f, 0.f};
+    const int K = T.K;
+    for (int kk = 0; kk < K; ++kk) {
+        const int k3 = (kk * T.inv) >> 16;
+        const int k4 = kk - k3 * T.kd4;
+        float2 av[H];
+        const int roff = rbase + k3 * T.row.sk3 + k4 * T.row.sk4;
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+            av[h] = active ? gb[(unsigned)(roff + h * rso4) * (2 * G) + srow * S + g * SG] : float2{0.f, 0.f};
+        float2 bv[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int coff = cbase[p] + k3 * T.col[p].sk3 + k4 * T.col[p].sk4;
+            bv[p] = colvalid ? gb[(unsigned)coff * (2 * G) + scol * S + g * SG] : float2{0.f, 0.f};
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const float2 a = av[h], b = bv[p];
+                fmfma4 re = acc[p][h][0], im = acc[p][h][1];
+                re = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.x, re, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.y, b.y, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.y, im, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.x, im, 0, 0, 0);
+                acc[p][h][0] = re;
+                acc[p][h][1] = im;
+            }
+    }
+    // D lane (j = lane & 3, block), register i
+    const int j = lane & 3;
+    if (!active || (SHAPE == 1 && j >= 2)) return;
+    float2 *pb = second ? pb1 : pb0;
+    const int gC = j & 1, oC = j >> 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gR = i & 1, oR = i >> 1;
+        const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            int ap, bp;
+            if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+            else { ap = oR; bp = h; }
+            const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                pb[((size_t)T.pair[p] * 16 + sp) * G + m] = float2{acc[p][h][0][i], acc[p][h][1][i]};
+        }
+    }
+}
+
+template <typename T, int SHAPE, int NP>
+__device__ __forceinline__ void pair_dispatch_np(const typename cplx_t<T>::type *g0, const typename cplx_t<T>::type *g1,
+                                                 typename cplx_t<T>::type *p0, typename cplx_t<T>::type *p1,
+                                                 bool has1, const PTask &Tk, int lane, const int mir[2]) {
+    if constexpr (sizeof(T) == 8) pair_task64<NP, SHAPE>(g0, p0, Tk, lane, mir);
+    else pair_task32<NP, SHAPE>(g0, g1, p0, p1, has1, Tk, lane, mir[0]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *__restrict__ Iq,
+                                               typename cplx_t<T>::type *__restrict__ P, int nc, int ubase,
+                                               int ucount, const int2 *__restrict__ gpos, int ngroup,
+                                               const PTask *__restrict__ tasks, int ntask, int npair) {
     using T2 = typename cplx_t<T>::type;
     constexpr int G = GroupLayout<T2>::G;
-    constexpr int NI = 64 / G;
-    constexpr int N1 = 1 << ((C3 == 0) + (C4 == 0));   // outer-spin combinations held by site 0
-    constexpr int N2 = 4 / N1;
-    constexpr int kRefUnroll = sizeof(T) == 4 ? 2 : 1;
-    const int K = (D.pad[0] >> 2) & 255, kd4 = (D.pad[0] >> 10) & 15, inv = D.pad[1];
-    const double dc = D.coef;
-    for (int c = 0; c < K; c += NI * IPL) {
-        if (c + il >= K) break;
-        int k3[IPL], k4[IPL];
-        double wt[IPL];
-#pragma unroll
-        for (int u = 0; u < IPL; ++u) {
-            const int kk = c + il + u * NI;
-            const bool valid = kk < K;
-            const int kc = valid ? kk : c + il;          // an open index in range (weight 0 if padding)
-            k3[u] = (kc * inv) >> 16;
-            k4[u] = kc - k3[u] * kd4;
-            wt[u] = valid ? dc : 0.0;
-        }
-        T2 e1[IPL][2 * N1], e2[IPL][2 * N2];
-#pragma unroll
-        for (int u = 0; u < IPL; ++u) {
-#pragma unroll
-            for (int i = 0; i < 2 * N1; ++i) e1[u][i] = T2{0, 0};
-#pragma unroll
-            for (int i = 0; i < 2 * N2; ++i) e2[u][i] = T2{0, 0};
-        }
-        // FP32: two block refs per iteration keep more loads in flight (in FP64 the
-        // extra registers cost more than they gain)
-#pragma unroll kRefUnroll
-        for (int r = D.ref0; r < D.ref0_end; ++r) {
-            const DRef R = refs[r];
-            const T c0 = T(R.coef);
-            unsigned vl[IPL];
-#pragma unroll
-            for (int u = 0; u < IPL; ++u) vl[u] = la + (unsigned)(2 * G * (k3[u] * R.sk3 + k4[u] * R.sk4));
-#pragma unroll
-            for (int o = 0; o < N1; ++o) {
-                const int a3 = (C3 == 0) ? (o & 1) : 0;
-                const int a4 = (C4 == 0) ? ((C3 == 0) ? (o >> 1) : o) : 0;
-                const T2 *p = base + (size_t)2 * G * (R.base + a3 * R.so3 + a4 * R.so4);
-#pragma unroll
-                for (int u = 0; u < IPL; ++u) {
-                    T2 v0, v1;
-                    load_spins(p, vl[u], v0, v1);
-                    e1[u][2 * o].x += c0 * v0.x;
-                    e1[u][2 * o].y += c0 * v0.y;
-                    e1[u][2 * o + 1].x += c0 * v1.x;
-                    e1[u][2 * o + 1].y += c0 * v1.y;
-                }
-            }
-        }
-#pragma unroll kRefUnroll
-        for (int r = D.ref1; r < D.ref1_end; ++r) {
-            const DRef R = refs[r];
-            const T c0 = T(R.coef);
-            unsigned vl[IPL];
-#pragma unroll
-            for (int u = 0; u < IPL; ++u) vl[u] = lb + (unsigned)(2 * G * (k3[u] * R.sk3 + k4[u] * R.sk4));
-#pragma unroll
-            for (int o = 0; o < N2; ++o) {
-                const int a3 = (C3 == 1) ? (o & 1) : 0;
-                const int a4 = (C4 == 1) ? ((C3 == 1) ? (o >> 1) : o) : 0;
-                const T2 *p = base + (size_t)2 * G * (R.base + a3 * R.so3 + a4 * R.so4);
-#pragma unroll
-                for (int u = 0; u < IPL; ++u) {
-                    T2 v0, v1;
-                    load_spins(p, vl[u], v0, v1);
-                    e2[u][2 * o].x += c0 * v0.x;
-                    e2[u][2 * o].y += c0 * v0.y;
-                    e2[u][2 * o + 1].x += c0 * v1.x;
-                    e2[u][2 * o + 1].y += c0 * v1.y;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < IPL; ++u) {
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int a = s & 1, bb = (s >> 1) & 1, a3 = (s >> 2) & 1, a4 = s >> 3;
-                const int o1 = ((C3 == 0) ? a3 : 0) + ((C3 == 0) ? 2 : 1) * ((C4 == 0) ? a4 : 0);
-                const int o2 = ((C3 == 1) ? a3 : 0) + ((C3 == 1) ? 2 : 1) * ((C4 == 1) ? a4 : 0);
-                const T2 p = cmul(e1[u][a + 2 * o1], e2[u][bb + 2 * o2]);
-                acc[s].x = fma(wt[u], (double)p.x, acc[s].x);
-                acc[s].y = fma(wt[u], (double)p.y, acc[s].y);
-            }
-        }
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_contract(const typename cplx_t<T>::type *__restrict__ Iq,
-                                                  typename cplx_t<T>::type *__restrict__ slots, int nc, long V,
-                                                  int gbase, int gcount, const int2 *__restrict__ gpos, int ntask,
-                                                  const int4 *__restrict__ segs, const DDiag *__restrict__ diags,
-                                                  const DRef *__restrict__ refs) {
-    using T2 = typename cplx_t<T>::type;
-    using Ly = GroupLayout<T2>;
-    constexpr int G = Ly::G;             // momentum lanes per open index
-    constexpr int NI = 64 / G;           // open-index lanes per wave
-    // XCD-aware placement: consecutive workgroup ids cycle over the 8 XCDs;
-    // XCD x owns the contiguous range of groups [x*P8, (x+1)*P8) of this launch.
-    const int xcd = blockIdx.x & 7;
-    const int j = blockIdx.x >> 3;
-    const int P8 = (gcount + 7) >> 3;
-    const int gl8 = xcd * P8 + j / ntask;
-    const int task = j - (j / ntask) * ntask;
-    if (gl8 >= gcount) return;
-    const int grp = gbase + gl8;
-    const int lane = threadIdx.x & 63;
+    constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;        // groups per unit (per wave)
+    const int nchunk = (ntask + 3) >> 2;
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    const int P8 = (ucount + 7) >> 3;
+    const int ul = xcd * P8 + jj / nchunk;
+    const int chunk = jj - (jj / nchunk) * nchunk;
+    if (ul >= ucount) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int gl = lane & (G - 1), il = lane / G;
-    const int2 pq = gpos[(size_t)grp * G + gl];
-    const T2 *base = Iq + (size_t)grp * nc * 2 * G;
-    const int4 sg = segs[task * 4 + wave];
-    const int d0 = __builtin_amdgcn_readfirstlane(sg.x), d1 = __builtin_amdgcn_readfirstlane(sg.y);
-    if (d0 >= d1) return;
-    const unsigned la = gl * Ly::S, lb = pq.y * Ly::S;
-    // diagrams with at least kWide open-index items take two per lane and step
-    // (more loads in flight per table read; register use sets the thresholds)
-    constexpr int kWide = sizeof(T) == 8 ? 128 : 32;
-    double2 acc[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) acc[s] = double2{0, 0};
-    for (int d = d0; d < d1; ++d) {
-        const DDiag D = diags[d];
-        const bool wide = ((D.pad[0] >> 2) & 255) >= kWide;
-        switch ((D.pad[0] & 3) | (wide ? 4 : 0)) {      // carry pattern: site holding a' (bit 0) and b' (bit 1)
-        case 0: diagram_sum<T, 0, 0, 1>(base, la, lb, D, refs, il, acc); break;
-        case 1: diagram_sum<T, 1, 0, 1>(base, la, lb, D, refs, il, acc); break;
-        case 2: diagram_sum<T, 0, 1, 1>(base, la, lb, D, refs, il, acc); break;
-        case 3: diagram_sum<T, 1, 1, 1>(base, la, lb, D, refs, il, acc); break;
-        case 4: diagram_sum<T, 0, 0, 2>(base, la, lb, D, refs, il, acc); break;
-        case 5: diagram_sum<T, 1, 0, 2>(base, la, lb, D, refs, il, acc); break;
-        case 6: diagram_sum<T, 0, 1, 2>(base, la, lb, D, refs, il, acc); break;
-        default: diagram_sum<T, 1, 1, 2>(base, la, lb, D, refs, il, acc); break;
+    const int t = chunk * 4 + wave;
+    if (t >= ntask) return;
+    const int lane = threadIdx.x & 63;
+    const int unit = ubase + ul;
+    const int grp0 = unit * GPU_;
+    const bool has1 = GPU_ == 2 && grp0 + 1 < ngroup;
+    const T2 *g0 = Iq + (size_t)grp0 * nc * 2 * G;
+    const T2 *g1 = has1 ? g0 + (size_t)nc * 2 * G : g0;
+    T2 *p0 = P + (size_t)grp0 * npair * 16 * G;
+    T2 *p1 = has1 ? p0 + (size_t)npair * 16 * G : p0;
+    int mir[2];
+    if constexpr (sizeof(T) == 8) {
+        const int blk = (lane >> 2) & 3;
+        mir[0] = gpos[(size_t)grp0 * G + blk].y;
+        mir[1] = gpos[(size_t)grp0 * G + blk + 4].y;
+    } else {
+        const int blk = lane >> 2;
+        const int gg = (blk >= 8 && has1) ? grp0 + 1 : grp0;
+        mir[0] = gpos[(size_t)gg * G + (blk & 7)].y;
+        mir[1] = 0;
+    }
+    const PTask &Tk = tasks[t];
+    const int np = __builtin_amdgcn_readfirstlane(Tk.np);
+    const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
+#define BBC_PAIR_CASE(SH, N) \
+    case N: pair_dispatch_np<T, SH, N>(g0, g1, p0, p1, has1, Tk, lane, mir); break;
+    if (shape == 0) {
+        switch (np) {
+            BBC_PAIR_CASE(0, 1) BBC_PAIR_CASE(0, 2) BBC_PAIR_CASE(0, 3) BBC_PAIR_CASE(0, 4)
+            BBC_PAIR_CASE(0, 5) BBC_PAIR_CASE(0, 6) BBC_PAIR_CASE(0, 7) BBC_PAIR_CASE(0, 8)
+            default: break;
+        }
+    } else {
+        switch (np) {
+            BBC_PAIR_CASE(1, 1) BBC_PAIR_CASE(1, 2) BBC_PAIR_CASE(1, 3) BBC_PAIR_CASE(1, 4)
+            default: break;
         }
     }
-    // sum over the open-index lanes of each momentum lane
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-#pragma unroll
-        for (int off = 32; off >= G; off >>= 1) {
-            acc[s].x += __shfl_xor(acc[s].x, off, 64);
-            acc[s].y += __shfl_xor(acc[s].y, off, 64);
-        }
-    }
-    if (pq.x < 0) return;             // padding slot
-    const int slot = __builtin_amdgcn_readfirstlane(sg.z);
-#pragma unroll
-    for (int s0 = 0; s0 < 16; s0 += NI) {
-        const int want = s0 + il;
-        double2 v = acc[0];
-#pragma unroll
-        for (int s = 1; s < 16; ++s)
-            if (want == s) v = acc[s];
-        slots[((size_t)slot * 16 + want) * V + pq.x] = T2{T(v.x), T(v.y)};
-    }
+#undef BBC_PAIR_CASE
 }
 
-// Sum of the partial slots of each channel, in slot order.
+// Channel sums: Ct[ch][s][q] = sum_t w_t P[group][pair_t][s][slot], FP64
+// accumulation, terms in table order.  Workgroup = (group, two channels); the
+// lanes of a channel are its 16 spins x G momenta; all channel pairs of a group
+// run back to back on one XCD, so the group's pair products are read from L2.
 template <typename T>
-__global__ __launch_bounds__(256) void k_combine(const typename cplx_t<T>::type *__restrict__ slots,
-                                                 typename cplx_t<T>::type *__restrict__ Ct, int n_ch, int V,
-                                                 const int32_t *__restrict__ ch_slot_begin) {
+__global__ __launch_bounds__(256) void k_pair_combine(const typename cplx_t<T>::type *__restrict__ P,
+                                                      typename cplx_t<T>::type *__restrict__ Ct, int n_ch, long V,
+                                                      const int2 *__restrict__ gpos, int gbase, int gcount,
+                                                      int npair, const int32_t *__restrict__ term_begin,
+                                                      const int32_t *__restrict__ term_pair,
+                                                      const double *__restrict__ term_w) {
     using T2 = typename cplx_t<T>::type;
-    const long n = (long)n_ch * 16 * V;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const int m = (int)(i / (16L * V));
-        const long rest = i - (long)m * 16 * V;
-        const int b = ch_slot_begin[m], e = ch_slot_begin[m + 1];
-        T2 v = slots[(size_t)b * 16 * V + rest];
-        for (int s = b + 1; s < e; ++s) {
-            const T2 w = slots[(size_t)s * 16 * V + rest];
-            v.x += w.x;
-            v.y += w.y;
-        }
-        Ct[i] = v;
+    constexpr int G = GroupLayout<T2>::G;
+    static_assert(16 * G * 2 == 256, "two channels per workgroup");
+    const int nchp = (n_ch + 1) >> 1;
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    const int P8 = (gcount + 7) >> 3;
+    const int gl = xcd * P8 + jj / nchp;
+    const int cp = jj - (jj / nchp) * nchp;
+    if (gl >= gcount) return;
+    const int grp = gbase + gl;
+    const int ch = __builtin_amdgcn_readfirstlane(cp * 2 + (int)(threadIdx.x >> 7));
+    if (ch >= n_ch) return;
+    const int s = (threadIdx.x >> 3) & 15, slot = threadIdx.x & 7;
+    const T2 *pg = P + (size_t)grp * npair * 16 * G + s * G + slot;
+    double2 acc = double2{0.0, 0.0};
+    const int tb = term_begin[ch], te = term_begin[ch + 1];
+    for (int t = tb; t < te; ++t) {
+        const T2 v = pg[(size_t)term_pair[t] * 16 * G];
+        const double w = term_w[t];
+        acc.x = fma(w, (double)v.x, acc.x);
+        acc.y = fma(w, (double)v.y, acc.y);
     }
+    const int q = gpos[(size_t)grp * G + slot].x;
+    if (q >= 0) Ct[((size_t)ch * 16 + s) * V + q] = T2{(T)acc.x, (T)acc.y};
 }
 
 template <typename T>
-void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots, int nc, long V,
-                     const ContractTables &tb, hipStream_t st) {
-    // groups per launch: below 2^32 work-items per dispatch (the packet's grid size is 32-bit)
+void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
+                  hipStream_t st) {
+    constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;
+    const int nunit = (tb.ngroup + GPU_ - 1) / GPU_;
+    const long nchunk = (tb.ntask + 3) / 4;
+    if (nchunk == 0) return;
+    // units per launch: below 2^32 work-items per dispatch
     const long max_wg = (1L << 32) / 256 - 64;
-    const int chunk = (int)std::max<long>(8, std::min<long>(tb.ngroup, (max_wg / tb.ntask) / 8 * 8));
-    for (int g0 = 0; g0 < tb.ngroup; g0 += chunk) {
-        const int gc = std::min(chunk, tb.ngroup - g0);
-        const long nwg = 8L * ((gc + 7) / 8) * tb.ntask;
-        hipLaunchKernelGGL((k_contract<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, slots, nc, V, g0, gc, tb.gpos,
-                           tb.ntask, tb.segs, tb.diags, tb.refs);
+    const int per = (int)std::max<long>(8, std::min<long>(nunit, (max_wg / nchunk) / 8 * 8));
+    for (int u0 = 0; u0 < nunit; u0 += per) {
+        const int uc = std::min(per, nunit - u0);
+        const long nwg = 8L * ((uc + 7) / 8) * nchunk;
+        hipLaunchKernelGGL((k_pairs<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+                           tb.ngroup, tb.tasks, tb.ntask, tb.npair);
     }
 }
 
 template <typename T>
-void launch_combine(const typename cplx_t<T>::type *slots, typename cplx_t<T>::type *Ct, int n_ch, long V,
-                    const int32_t *ch_slot_begin, hipStream_t st) {
-    const long n = (long)n_ch * 16 * V;
-    hipLaunchKernelGGL((k_combine<T>), dim3(grid1d(n)), dim3(256), 0, st, slots, Ct, n_ch, (int)V,
-                       ch_slot_begin);
+void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
+                         const PairDevTables &tb, hipStream_t st) {
+    const long nchp = (n_ch + 1) / 2;
+    const long max_wg = (1L << 32) / 256 - 64;
+    const int per = (int)std::max<long>(8, std::min<long>(tb.ngroup, (max_wg / nchp) / 8 * 8));
+    for (int g0 = 0; g0 < tb.ngroup; g0 += per) {
+        const int gc = std::min(per, tb.ngroup - g0);
+        const long nwg = 8L * ((gc + 7) / 8) * nchp;
+        hipLaunchKernelGGL((k_pair_combine<T>), dim3((unsigned)nwg), dim3(256), 0, st, P, Ct, n_ch, V, tb.gpos, g0,
+                           gc, tb.npair, tb.term_begin, tb.term_pair, tb.term_w);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -1211,10 +1312,10 @@ template bool fft3d_grouped_fits<float>(const int[3]);
 template int launch_fft3d_grouped<double>(const double2 *, double2 *, int, const int[3], int, const int2 *,
                                           hipStream_t);
 template int launch_fft3d_grouped<float>(const float2 *, float2 *, int, const int[3], int, const int2 *, hipStream_t);
-template void launch_contract<double>(const double2 *, double2 *, int, long, const ContractTables &, hipStream_t);
-template void launch_contract<float>(const float2 *, float2 *, int, long, const ContractTables &, hipStream_t);
-template void launch_combine<double>(const double2 *, double2 *, int, long, const int32_t *, hipStream_t);
-template void launch_combine<float>(const float2 *, float2 *, int, long, const int32_t *, hipStream_t);
+template void launch_pairs<double>(const double2 *, double2 *, int, const PairDevTables &, hipStream_t);
+template void launch_pairs<float>(const float2 *, float2 *, int, const PairDevTables &, hipStream_t);
+template void launch_pair_combine<double>(const double2 *, double2 *, int, long, const PairDevTables &, hipStream_t);
+template void launch_pair_combine<float>(const float2 *, float2 *, int, long, const PairDevTables &, hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
                                       double *, const uint32_t *, const int2 *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,

@@ -5,34 +5,20 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "pairs.hpp"
+
 namespace bbc {
 
-// Contraction tables (device layout).
-struct DDiag {           // one diagram of one requested channel
-    double coef;         // parity of the representative permutation times source weights
-    int ref0, ref0_end;  // block refs of site 0 (B1 at X+r)
-    int ref1, ref1_end;  // block refs of site 1 (B2 at X)
-    int pad[2];          // pad[0]: carry pattern (bit 0 = site of a', bit 1 = site of b') | K << 2 | kdim4 << 10;
-                         // pad[1]: ceil(65536 / kdim4), so that k3 = (kk * pad[1]) >> 16 for kk < K
-};
-struct DRef {            // one intermediate entering a block
-    double coef;         // sink-term weight times exchange sign
-    int base;            // component offset (per sink spin)
-    int so3, so4;        // stride of alpha' / beta' (0 if not carried by this intermediate)
-    int sk3, sk4;        // stride of the open index of B3 / B4 (0 if absent)
-    int pad;
-};
-
-// Device pointers of the contraction tables of one plan.
-struct ContractTables {
+// Device pointers of the pair tables of one plan (pairs.hpp).
+struct PairDevTables {
     const int2 *gpos;             // per grouped position: (momentum or -1, lane of -q in the group)
     int ngroup;                   // momentum groups (G positions each)
-    int ntask;                    // tasks per group
-    const int4 *segs;             // 4 per task: first diagram, end diagram, slot, unused
-    const DDiag *diags;
-    const DRef *refs;
-    const int32_t *ch_slot_begin; // n_ch + 1
-    int nslot;
+    const PTask *tasks;
+    int ntask;
+    int npair;
+    const int32_t *term_begin;    // n_ch + 1
+    const int32_t *term_pair;
+    const double *term_w;
 };
 
 // Blocks of 256 threads for a one-dimensional launch over n items, capped so
@@ -82,8 +68,8 @@ int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type
                           const int *posof, hipStream_t st);
 
 // Momentum-grouped copy: in [g][nc][V] (component-major) -> out, per group of G
-// momenta (4 in FP64, 8 in FP32) and component, both sink spins and the G
-// momenta; gpos is the position table of the groups.
+// = 8 momenta and component, the G momenta and both sink spins ([c][G][g]);
+// gpos is the position table of the groups.
 template <typename T>
 void launch_transpose_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, long V,
                               int ngroup, const int2 *gpos, hipStream_t st);
@@ -95,13 +81,14 @@ template <typename T>
 int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
                          int ngroup, const int2 *gpos, hipStream_t st);
 
-// Open-index contraction into the partial slots, then their per-channel sum.
+// Pair products P[group][pair][spin][G] of every task (MFMA), then the channel
+// sums Ct[ch][spin][q] = sum_t w_t P[pair_t] (fixed order, FP64 accumulation).
 template <typename T>
-void launch_contract(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *slots, int nc, long V,
-                     const ContractTables &tb, hipStream_t st);
+void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
+                  const PairDevTables &tb, hipStream_t st);
 template <typename T>
-void launch_combine(const typename cplx_t<T>::type *slots, typename cplx_t<T>::type *Ct, int n_ch, long V,
-                    const int32_t *ch_slot_begin, hipStream_t st);
+void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
+                         const PairDevTables &tb, hipStream_t st);
 
 template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
