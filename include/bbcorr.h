@@ -175,6 +175,31 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
                          const double *energy, void *C_out, double *C_scale, void *stream);
 
 /*
+ * bbc_correlate without any device allocation, for callers that cannot call
+ * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, results and layouts as
+ * bbc_correlate (the same kernels run, so the results are bit-identical), with
+ * S_light, S_strange, C_out and C_scale in device memory only (BBC_EINVAL
+ * otherwise).  The plan tables, the momentum-group table, the energies and the
+ * slice workspace live in a fixed scratch array of 192 MiB (201326592 bytes)
+ * that the library holds on every GPU it runs on until the process ends; a
+ * request that needs more (bbc_footprint plus a few hundred KB of tables)
+ * fails with BBC_ENOMEM before anything is enqueued.  192 MiB holds, e.g.,
+ * 8^3 with channel 1 (p Lambda) in FP64, 6^3 with all 52 channels in FP64, or
+ * 8^3 with all 52 channels in FP32.  Host-side planning may allocate host
+ * memory; the tables are copied to the scratch with hipMemcpyAsync on `stream`.
+ * Every call on one GPU -- from any context or stream -- shares that GPU's
+ * scratch, which keeps the last call's contents: calls that overlap on one
+ * GPU race, so the caller must order them (e.g. one stream).  Profiling and
+ * graph mode do not apply (ordinary stream-ordered launches).
+ */
+bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec,
+                                 const void *S_light, const void *S_strange,
+                                 int n_t, const int32_t *t_list, int t0,
+                                 int n_ch, const int32_t *ch_list, bbc_spin spin,
+                                 const double *energy, void *C_out, double *C_scale, void *stream);
+
+/*
  * Forward/backward (CPT) average of Sec. 6.  The baryon pair propagating
  * forward in time (upper spinor components) and the antibaryon pair
  * propagating backward (lower components) are related by charge conjugation,

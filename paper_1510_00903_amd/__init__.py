@@ -29,7 +29,8 @@ _lib = None
 EXPORTED_SYMBOLS = [
     "bbc_num_channels", "bbc_num_channels_all", "bbc_channel_name", "bbc_channel_content",
     "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create", "bbc_destroy",
-    "bbc_last_error", "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
+    "bbc_last_error", "bbc_footprint", "bbc_correlate", "bbc_correlate_noalloc", "bbc_profile_enable",
+    "bbc_profile_read",
     "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
     "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
     "bbc_spin_project", "bbc_cubic_project", "bbc_central_potential",
@@ -81,6 +82,7 @@ def load():
     lib.bbc_last_error.restype = ctypes.c_char_p
     lib.bbc_footprint.argtypes = [P, I, I, P, P]
     lib.bbc_correlate.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
+    lib.bbc_correlate_noalloc.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
     lib.bbc_correlate_cpt.argtypes = [P, P, I, I, P, P, I, I, P, I, P, I, P, P, P, P]
     lib.bbc_profile_enable.argtypes = [P, I]
     lib.bbc_profile_read.argtypes = [P, I, P, P]
@@ -100,7 +102,7 @@ def load():
     lib.bbc_cubic_project.argtypes = [P, P, I, I, I, P, I, P, P]
     lib.bbc_central_potential.argtypes = [P, P, I, I, P, ctypes.c_double, P, P]
     for f in ("bbc_spin_project", "bbc_cubic_project", "bbc_central_potential", "bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
-              "bbc_footprint", "bbc_correlate", "bbc_profile_enable", "bbc_profile_read",
+              "bbc_footprint", "bbc_correlate", "bbc_correlate_noalloc", "bbc_profile_enable", "bbc_profile_read",
               "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit",
               "bbc_poll", "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget"):
         getattr(lib, f).restype = I
@@ -393,6 +395,46 @@ class Context:
             n_t, t_arr, int(t0), n_ch, ch_arr, int(spin), e_arr, ctypes.c_void_p(out.data_ptr()),
             ctypes.c_void_p(scale.data_ptr()) if (prec == F32) else None,
             ctypes.c_void_p(stream.cuda_stream)))
+        return (out, scale) if prec == F32 else out
+
+    def correlate_noalloc(self, S_light, S_strange, t_list, channels, out, scale=None, t0=0, spin=UPPER,
+                          energy=None, stream=None):
+        """correlate() through bbc_correlate_noalloc: no device allocation by the library
+        (its tables and workspace live in a fixed 192 MiB scratch array per GPU).
+        Device tensors only; ``out`` (and ``scale`` in the FP32 form) are required.
+        Returns ``out`` (FP64) or ``(out, scale)`` (FP32)."""
+        import torch
+
+        if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
+            raise BBCError("S_light and S_strange must have the same shape and dtype")
+        prec = _prop_dtype(S_light, "propagators")
+        dev = self._torch_device()
+        if not (S_light.is_cuda and S_strange.is_cuda) or S_light.device != dev:
+            raise BBCError("correlate_noalloc takes device tensors on cuda:%d" % self.device)
+        S_light, S_strange = S_light.contiguous(), S_strange.contiguous()
+        n_t, Lz, Ly, Lx = S_light.shape[:4]
+        t_arr, nt2 = _i32(t_list)
+        if nt2 != n_t:
+            raise BBCError("t_list must have one entry per slice")
+        ch_arr, n_ch = _i32(channels)
+        lat, _ = _i32([Lx, Ly, Lz])
+        _check_tensor(out, (n_t, n_ch, Lz, Ly, Lx, 16), S_light.dtype, "out", dev)
+        if prec == F32:
+            if scale is None:
+                raise BBCError("scale is required in the FP32 form")
+            _check_tensor(scale, (n_t, n_ch), torch.float64, "scale", dev)
+        e_arr = None
+        if energy is not None:
+            e_vals = [float(e) for e in energy]
+            if len(e_vals) != n_ch:
+                raise BBCError("energy must have one entry per channel")
+            e_arr = (ctypes.c_double * n_ch)(*e_vals)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        _check(self._lib.bbc_correlate_noalloc(
+            self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()), ctypes.c_void_p(S_strange.data_ptr()),
+            n_t, t_arr, int(t0), n_ch, ch_arr, int(spin), e_arr, ctypes.c_void_p(out.data_ptr()),
+            ctypes.c_void_p(scale.data_ptr()) if prec == F32 else None, ctypes.c_void_p(stream.cuda_stream)))
         return (out, scale) if prec == F32 else out
 
     def correlate_cpt(self, S_light, S_strange, t0, taus, channels, sign=1, energy=None, out=None, scale=None,

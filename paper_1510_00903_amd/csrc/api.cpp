@@ -44,21 +44,34 @@ bbc_status fail(bbc_status s, const std::string &msg) {
 struct DevPlan {
     bbc::Plan plan;
     bbc::BlockPatterns pats;
-    uint32_t *d_terms = nullptr;
-    int32_t *d_term_begin = nullptr;
-    // pair form of the contraction (pairs.hpp)
-    bbc::PTask *d_tasks = nullptr;
-    int32_t *d_pterm_begin = nullptr, *d_pterm_pair = nullptr;
-    double *d_pterm_w = nullptr;
     int ntask = 0, npair = 0;
-    int2 *d_content = nullptr;      // per requested channel: (n_light, n_strange)
+    // every table the kernels read, as one image (byte offsets below): block-kernel
+    // terms, pair tasks and channel terms (pairs.hpp), per-channel quark content
+    std::vector<unsigned char> image;
+    size_t off_terms = 0, off_term_begin = 0, off_tasks = 0, off_pbegin = 0, off_ppair = 0, off_pw = 0,
+           off_content = 0;
+    void *d_image = nullptr;        // device copy, made by the entry points that allocate
     size_t table_bytes = 0;
-    ~DevPlan() {
-        (void)hipFree(d_terms); (void)hipFree(d_term_begin); (void)hipFree(d_tasks);
-        (void)hipFree(d_pterm_begin); (void)hipFree(d_pterm_pair); (void)hipFree(d_pterm_w);
-        (void)hipFree(d_content);
-    }
+    ~DevPlan() { (void)hipFree(d_image); }
 };
+
+// Device pointers of one plan's tables, for an image copied to `base`.
+struct PlanDev {
+    const DevPlan *dp;
+    const uint32_t *terms;
+    const int32_t *term_begin;
+    const bbc::PTask *tasks;
+    const int32_t *pbegin, *ppair;
+    const double *pw;
+    const int2 *content;
+};
+PlanDev plan_dev(const DevPlan *dp, const void *base) {
+    const char *b = (const char *)base;
+    return PlanDev{dp, (const uint32_t *)(b + dp->off_terms), (const int32_t *)(b + dp->off_term_begin),
+                   (const bbc::PTask *)(b + dp->off_tasks), (const int32_t *)(b + dp->off_pbegin),
+                   (const int32_t *)(b + dp->off_ppair), (const double *)(b + dp->off_pw),
+                   (const int2 *)(b + dp->off_content)};
+}
 
 // Number of self-conjugate momenta (q = -q mod L): 0 and L/2 along each even axis.
 long self_conjugate(const int L[3]) {
@@ -183,6 +196,11 @@ struct bbc_context {
     double *d_energy = nullptr;
     int energy_cap = 0;
     std::map<std::vector<int>, int2 *> groups;       // per (lattice, G): momentum groups
+    // allocation-free entry point: this device's copy of the scratch array, and
+    // host images of the momentum groups per lattice
+    void *scratch = nullptr;
+    std::map<std::vector<int>, std::pair<std::vector<int2>, long>> group_images;
+    std::vector<double> noalloc_energy;
     std::mutex qmu;                                   // guards groups and plans for the server thread
     hipStream_t cin = nullptr, cout = nullptr;        // copy streams of the host-streamed direct path
     // direct calls share the workspace and the energy array: each call's stream
@@ -257,79 +275,97 @@ bbc_status mark_last(bbc_context *ctx, hipStream_t st, bbc_status s) {
     return s;
 }
 
+// Appends `n` elements at a 256-byte boundary of the image; returns their offset.
+template <typename E>
+size_t image_put(std::vector<unsigned char> &img, const E *data, size_t n) {
+    const size_t off = (img.size() + 255) & ~(size_t)255;
+    img.resize(off + std::max<size_t>(1, n) * sizeof(E), 0);
+    if (n) std::memcpy(img.data() + off, data, n * sizeof(E));
+    return off;
+}
+
+// Plan of a channel list and spin selection (cached per context).  With
+// `upload`, the table image is also copied to a device allocation of its own;
+// the allocation-free entry point copies it into its scratch instead.
 bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, bbc_precision prec,
-                    DevPlan **out) {
+                    DevPlan **out, bool upload = true) {
     std::lock_guard<std::mutex> lock(ctx->qmu);
     auto key = std::make_pair(chans, spin_offset * 2 + (prec == BBC_F32 ? 1 : 0));
     auto it = ctx->plans.find(key);
-    if (it != ctx->plans.end()) { *out = it->second.get(); return BBC_OK; }
-    std::unique_ptr<DevPlan> dp(new DevPlan);
-    try {
-        dp->plan = bbc::build_plan(chans, spin_offset);
-    } catch (const std::exception &e) {
-        return fail(BBC_EINVAL, std::string("planner: ") + e.what());
-    }
-    const bbc::Plan &P = dp->plan;
-    // pattern runs of the component layout (components are sorted by pattern id)
-    dp->pats.n = 0;
-    dp->pats.any_imag = 0;
-    for (uint32_t code : P.terms) dp->pats.any_imag |= (int)((code >> 13) & 1);
-    for (int c = 0; c < P.ncomp;) {
-        const int id = P.comp_pat[c];
-        int e = c;
-        while (e < P.ncomp && P.comp_pat[e] == id) ++e;
-        if (dp->pats.n == bbc::kMaxBlockPatterns) return fail(BBC_EUNSUPPORTED, "too many component patterns");
-        bbc::BlockPattern &bp = dp->pats.p[dp->pats.n++];
-        const int sp = id / 8;
-        const bbc::SpinStruct &S = bbc::spin_struct(sp);
-        bp.begin = c;
-        bp.end = e;
-        bp.qa = (uint8_t)((id >> 2) & 1);
-        bp.qb = (uint8_t)((id >> 1) & 1);
-        bp.qc = (uint8_t)(id & 1);
-        for (int m = 0; m < 4; ++m) {
-            bp.p1[m] = (uint8_t)S.p1[m]; bp.k1[m] = (uint8_t)S.k1[m];
-            bp.p2[m] = (uint8_t)S.p2[m]; bp.k2[m] = (uint8_t)S.k2[m];
+    if (it == ctx->plans.end()) {
+        std::unique_ptr<DevPlan> dp(new DevPlan);
+        try {
+            dp->plan = bbc::build_plan(chans, spin_offset);
+        } catch (const std::exception &e) {
+            return fail(BBC_EINVAL, std::string("planner: ") + e.what());
         }
-        bp.new_diquark = 1;
-        if (dp->pats.n > 1) {
-            const bbc::BlockPattern &pv = dp->pats.p[dp->pats.n - 2];
-            bool same = pv.qa == bp.qa && pv.qb == bp.qb;
-            for (int m = 0; m < 4; ++m) same = same && pv.p1[m] == bp.p1[m] && pv.k1[m] == bp.k1[m];
-            bp.new_diquark = same ? 0 : 1;
+        const bbc::Plan &P = dp->plan;
+        // pattern runs of the component layout (components are sorted by pattern id)
+        dp->pats.n = 0;
+        dp->pats.any_imag = 0;
+        for (uint32_t code : P.terms) dp->pats.any_imag |= (int)((code >> 13) & 1);
+        for (int c = 0; c < P.ncomp;) {
+            const int id = P.comp_pat[c];
+            int e = c;
+            while (e < P.ncomp && P.comp_pat[e] == id) ++e;
+            if (dp->pats.n == bbc::kMaxBlockPatterns) return fail(BBC_EUNSUPPORTED, "too many component patterns");
+            bbc::BlockPattern &bp = dp->pats.p[dp->pats.n++];
+            const int sp = id / 8;
+            const bbc::SpinStruct &S = bbc::spin_struct(sp);
+            bp.begin = c;
+            bp.end = e;
+            bp.qa = (uint8_t)((id >> 2) & 1);
+            bp.qb = (uint8_t)((id >> 1) & 1);
+            bp.qc = (uint8_t)(id & 1);
+            for (int m = 0; m < 4; ++m) {
+                bp.p1[m] = (uint8_t)S.p1[m]; bp.k1[m] = (uint8_t)S.k1[m];
+                bp.p2[m] = (uint8_t)S.p2[m]; bp.k2[m] = (uint8_t)S.k2[m];
+            }
+            bp.new_diquark = 1;
+            if (dp->pats.n > 1) {
+                const bbc::BlockPattern &pv = dp->pats.p[dp->pats.n - 2];
+                bool same = pv.qa == bp.qa && pv.qb == bp.qb;
+                for (int m = 0; m < 4; ++m) same = same && pv.p1[m] == bp.p1[m] && pv.k1[m] == bp.k1[m];
+                bp.new_diquark = same ? 0 : 1;
+            }
+            c = e;
         }
-        c = e;
-    }
-    bbc::PairTables pt;
-    try {
-        pt = bbc::build_pair_tables(P);
-    } catch (const std::exception &e) {
-        return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
-    }
-    dp->ntask = (int)pt.tasks.size();
-    dp->npair = pt.npair;
-    HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(upload_vec(&dp->d_terms, P.terms));
-    HIP_TRY(upload_vec(&dp->d_term_begin, P.term_begin));
-    HIP_TRY(upload_vec(&dp->d_tasks, pt.tasks));
-    HIP_TRY(upload_vec(&dp->d_pterm_begin, pt.term_begin));
-    HIP_TRY(upload_vec(&dp->d_pterm_pair, pt.term_pair));
-    HIP_TRY(upload_vec(&dp->d_pterm_w, pt.term_w));
-    {
+        bbc::PairTables pt;
+        try {
+            pt = bbc::build_pair_tables(P);
+        } catch (const std::exception &e) {
+            return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
+        }
+        dp->ntask = (int)pt.tasks.size();
+        dp->npair = pt.npair;
         std::vector<int2> content;
         for (int ch : P.channels) {
-            const auto b = bbc::channel_baryons(ch);
+            const auto bq = bbc::channel_baryons(ch);
             int ns = 0;
             for (int s2 = 0; s2 < 2; ++s2)
-                for (int i = 0; i < 3; ++i) ns += bbc::baryon(b[s2]).flav[i] == bbc::FS;
+                for (int i = 0; i < 3; ++i) ns += bbc::baryon(bq[s2]).flav[i] == bbc::FS;
             content.push_back(make_int2(6 - ns, ns));
         }
-        HIP_TRY(upload_vec(&dp->d_content, content));
+        std::vector<unsigned char> &img = dp->image;
+        dp->off_terms = image_put(img, P.terms.data(), P.terms.size());
+        dp->off_term_begin = image_put(img, P.term_begin.data(), P.term_begin.size());
+        dp->off_tasks = image_put(img, pt.tasks.data(), pt.tasks.size());
+        dp->off_pbegin = image_put(img, pt.term_begin.data(), pt.term_begin.size());
+        dp->off_ppair = image_put(img, pt.term_pair.data(), pt.term_pair.size());
+        dp->off_pw = image_put(img, pt.term_w.data(), pt.term_w.size());
+        dp->off_content = image_put(img, content.data(), content.size());
+        img.resize((img.size() + 255) & ~(size_t)255, 0);
+        dp->table_bytes = img.size();
+        it = ctx->plans.emplace(key, std::move(dp)).first;
     }
-    dp->table_bytes = P.terms.size() * 4 + P.term_begin.size() * 4 + pt.tasks.size() * sizeof(bbc::PTask) +
-                      pt.term_begin.size() * 4 + pt.term_pair.size() * 4 + pt.term_w.size() * 8;
-    *out = dp.get();
-    ctx->plans.emplace(key, std::move(dp));
+    DevPlan *dp = it->second.get();
+    if (upload && !dp->d_image) {
+        HIP_TRY(hipSetDevice(ctx->device));
+        hipError_t e = hipMalloc(&dp->d_image, dp->image.size());
+        if (e != hipSuccess) { dp->d_image = nullptr; return fail(BBC_ENOMEM, "hipMalloc of the plan tables"); }
+        HIP_TRY(hipMemcpy(dp->d_image, dp->image.data(), dp->image.size(), hipMemcpyHostToDevice));
+    }
+    *out = dp;
     return BBC_OK;
 }
 
@@ -380,22 +416,35 @@ struct MomGroups {
     const int *posof = nullptr;   // momentum -> position (V entries)
     int ngroup = 0;
 };
+constexpr int kGroupSize = 8;                    // momenta per group
+
+// Host image of the momentum groups of a lattice: the npos position entries,
+// then the V momentum -> position entries (as ints, two per int2).
+std::vector<int2> group_image(const int L[3], long *npos_out) {
+    const long V = (long)L[0] * L[1] * L[2];
+    const long npos = grouped_positions(V, L, kGroupSize);
+    std::vector<int2> g = momentum_groups(L, kGroupSize);
+    std::vector<int2> all(g);
+    all.resize(npos + (V + 1) / 2);
+    int *posof = reinterpret_cast<int *>(all.data() + npos);
+    for (long p = 0; p < npos; ++p)
+        if (g[p].x >= 0) posof[g[p].x] = (int)p;
+    *npos_out = npos;
+    return all;
+}
+
+MomGroups groups_at(const int2 *base, long npos) {
+    return MomGroups{base, reinterpret_cast<const int *>(base + npos), (int)(npos / kGroupSize)};
+}
+
 template <typename T>
 MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
-    constexpr int G = 8;                         // momenta per group
     std::lock_guard<std::mutex> lock(ctx->qmu);
-    auto key = std::vector<int>{L[0], L[1], L[2], G};
+    auto key = std::vector<int>{L[0], L[1], L[2], kGroupSize};
     auto it = ctx->groups.find(key);
-    const long V = (long)L[0] * L[1] * L[2];
-    const long npos = grouped_positions(V, L, G);
+    long npos = 0;
     if (it == ctx->groups.end()) {
-        // one allocation: the npos position entries, then the V momentum -> position entries
-        std::vector<int2> g = momentum_groups(L, G);
-        std::vector<int2> all(g);
-        all.resize(npos + (V + 1) / 2);
-        int *posof = reinterpret_cast<int *>(all.data() + npos);
-        for (long p = 0; p < npos; ++p)
-            if (g[p].x >= 0) posof[g[p].x] = (int)p;
+        std::vector<int2> all = group_image(L, &npos);
         int2 *d = nullptr;
         hipError_t e = upload_vec(&d, all);
         if (e != hipSuccess) {
@@ -403,19 +452,22 @@ MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
             return MomGroups{};
         }
         it = ctx->groups.emplace(key, d).first;
+    } else {
+        npos = grouped_positions((long)L[0] * L[1] * L[2], L, kGroupSize);
     }
     *st = BBC_OK;
-    return MomGroups{it->second, reinterpret_cast<const int *>(it->second + npos), (int)(npos / G)};
+    return groups_at(it->second, npos);
 }
 
 // Launches the kernel sequence of one time slice on stream st, using the
 // workspace ws (layout of workspace_bytes).  Stage events are recorded only
 // for the direct (profiled) path.
 template <typename T>
-bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, void *ws, const MomGroups &mg,
+bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], long V, void *ws, const MomGroups &mg,
                          const void *slp, const void *ssp, int n_ch, const double *d_energy, double dt, void *outp,
                          double *scale, hipStream_t st, bool timed) {
     using T2 = typename bbc::cplx_t<T>::type;
+    const DevPlan *dp = pd.dp;
     const bbc::Plan &P = dp->plan;
     const int nc = P.ncomp;
     const WsLayout lay = ws_layout(V, nc, n_ch, dp->npair, sizeof(T2));
@@ -424,8 +476,7 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     T2 *Ct = I;                                   // reuses region A once Iq is written
     T2 *Pp = (T2 *)((char *)ws + lay.p);
     uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
-    bbc::PairDevTables tb{mg.pos, mg.ngroup, dp->d_tasks, dp->ntask, dp->npair,
-                          dp->d_pterm_begin, dp->d_pterm_pair, dp->d_pterm_w};
+    bbc::PairDevTables tb{mg.pos, mg.ngroup, pd.tasks, dp->ntask, dp->npair, pd.pbegin, pd.ppair, pd.pw};
     const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
     T2 *out = (T2 *)outp;
     const bool fp32 = sizeof(T) == 4;
@@ -433,7 +484,7 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     {
         StageTimer tm(pc, st, 0);
         if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
-        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, dp->d_terms, dp->d_term_begin, dp->pats,
+        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, pd.terms, pd.term_begin, dp->pats,
                               fp32 ? kmax : nullptr, st);
     }
     // small cubic lattices: one fused pass (FFT in LDS, written straight into the
@@ -472,7 +523,7 @@ bbc_status enqueue_slice(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     {
         StageTimer tm(pc, st, 5);
         bbc::launch_finalize<T>(Ct, out, n_ch, (int)V, d_energy, dt, 1.0 / (double)V, scale, fp32 ? kmax : nullptr,
-                                dp->d_content, st);
+                                pd.content, st);
     }
     HIP_TRY(hipGetLastError());
     return BBC_OK;
@@ -553,7 +604,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
             const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
             bbc_status es = BBC_OK;
             for (int n = 0; n < n_t && es == BBC_OK; ++n)
-                es = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, mg, Sl + (size_t)n * V * 144, Ss + (size_t)n * V * 144,
+                es = enqueue_slice<T>(ctx, plan_dev(dp, dp->d_image), L, V, ctx->ws, mg, Sl + (size_t)n * V * 144, Ss + (size_t)n * V * 144,
                                       n_ch, energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0),
                                       (char *)C_out + (size_t)n * out_slice,
                                       C_scale ? C_scale + (size_t)n * n_ch : nullptr, ctx->gs, false);
@@ -609,7 +660,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
             if (n >= 2) HIP_TRY(hipStreamWaitEvent(st, ev[6 + b], 0));
             out = stage_out + (size_t)b * out_slice;
         }
-        s = enqueue_slice<T>(ctx, dp, L, V, ctx->ws, mg, sl, ss, n_ch, energy ? ctx->d_energy : nullptr,
+        s = enqueue_slice<T>(ctx, plan_dev(dp, dp->d_image), L, V, ctx->ws, mg, sl, ss, n_ch, energy ? ctx->d_energy : nullptr,
                              (double)(t_list[n] - t0), out, C_scale ? C_scale + (size_t)n * n_ch : nullptr, st,
                              true);
         if (s) return s;
@@ -665,10 +716,10 @@ bbc_status run_cpt(bbc_context *ctx, DevPlan *up, DevPlan *lo, const int L[3], l
         const int tau = tau_list[n];
         const size_t tf = (size_t)(((t0 + tau) % Lt + Lt) % Lt), tb = (size_t)(((t0 - tau) % Lt + Lt) % Lt);
         T2 *out = (T2 *)((char *)R_out + (size_t)n * out_slice);
-        s = enqueue_slice<T>(ctx, up, L, V, ctx->ws, mg, Sl + tf * V * 144, Ss + tf * V * 144, n_ch, de, (double)tau,
+        s = enqueue_slice<T>(ctx, plan_dev(up, up->d_image), L, V, ctx->ws, mg, Sl + tf * V * 144, Ss + tf * V * 144, n_ch, de, (double)tau,
                              out, sf, st, true);
         if (s) return s;
-        s = enqueue_slice<T>(ctx, lo, L, V, ctx->ws, mg, Sl + tb * V * 144, Ss + tb * V * 144, n_ch, de, (double)tau,
+        s = enqueue_slice<T>(ctx, plan_dev(lo, lo->d_image), L, V, ctx->ws, mg, Sl + tb * V * 144, Ss + tb * V * 144, n_ch, de, (double)tau,
                              bwd, sb, st, true);
         if (s) return s;
         bbc::launch_cpt_average<T>(out, bwd, V * 16, n_ch, (double)sign, sf, sb,
@@ -704,13 +755,13 @@ bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
         const MomGroups mg = get_groups<double>(ctx, ps.L, &s);
         if (!mg.pos) return s;
         const double2 *dl = (const double2 *)ps.dl + si * slice_elems, *ds = (const double2 *)ps.ds + si * slice_elems;
-        return enqueue_slice<double>(ctx, j.dp, ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
+        return enqueue_slice<double>(ctx, plan_dev(j.dp, j.dp->d_image), ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
                                      (double2 *)j.out + (size_t)n * n_ch * V * 16, nullptr, sl.st, false);
     }
     const MomGroups mg = get_groups<float>(ctx, ps.L, &s);
     if (!mg.pos) return s;
     const float2 *dl = (const float2 *)ps.dl + si * slice_elems, *ds = (const float2 *)ps.ds + si * slice_elems;
-    return enqueue_slice<float>(ctx, j.dp, ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
+    return enqueue_slice<float>(ctx, plan_dev(j.dp, j.dp->d_image), ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
                                 (float2 *)j.out + (size_t)n * n_ch * V * 16, j.scale + (size_t)n * n_ch, sl.st,
                                 false);
 }
@@ -911,6 +962,32 @@ void server_loop(bbc_context *ctx) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free entry point
+namespace {
+// Scratch of bbc_correlate_noalloc: a file-scope device array, one copy on every
+// GPU the library runs on, held until the process ends.  In host code the
+// array's name is not a device address: a GPU's copy is reached only through
+// the address hipGetSymbolAddress returns with that GPU current, taken once per
+// device (bbc_create) and kept here.
+constexpr size_t kScratchBytes = (size_t)192 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;           // device -> address of its copy
+
+bbc_status scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) { *out = it->second; return BBC_OK; }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(BBC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr.emplace(device, p);
+    *out = p;
+    return BBC_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int bbc_num_channels(void) { return bbc::kNumChannels; }
@@ -1006,10 +1083,14 @@ bbc_status bbc_create(int device, uint64_t budget, bbc_context **out) {
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(BBC_EINVAL, "no HIP device " + std::to_string(device));
     HIP_TRY(hipSetDevice(device));
+    void *scr = nullptr;
+    bbc_status s = scratch_address(device, &scr);   // with the device current
+    if (s) return s;
     bbc_context *c = new (std::nothrow) bbc_context;
     if (!c) return fail(BBC_ENOMEM, "context allocation");
     c->device = device;
     c->budget = budget;
+    c->scratch = scr;
     *out = c;
     return BBC_OK;
 }
@@ -1081,6 +1162,80 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     return mark_last(ctx, st, s);
 }
 
+
+bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, const void *S_light,
+                                 const void *S_strange, int n_t, const int32_t *t_list, int t0, int n_ch,
+                                 const int32_t *ch_list, bbc_spin spin, const double *energy, void *C_out,
+                                 double *C_scale, void *stream) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_lattice(lattice, &V);
+    if (s) return s;
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
+    if (n_t < 0 || n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list or negative n_t");
+    if (n_t > 0 && (!S_light || !S_strange || !t_list || !C_out)) return fail(BBC_EINVAL, "NULL buffer");
+    if (prec == BBC_F32 && n_t > 0 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
+    for (int i = 0; i < n_ch; ++i)
+        if (!bbc::channel_valid(ch_list[i]))
+            return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
+    if (n_t == 0) return BBC_OK;
+    if (is_host_pointer(S_light) || is_host_pointer(S_strange) || is_host_pointer(C_out) ||
+        (C_scale && is_host_pointer(C_scale)))
+        return fail(BBC_EINVAL, "bbc_correlate_noalloc takes device memory only");
+    if (!ctx->scratch) return fail(BBC_ESTATE, "no scratch address for the context's device");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    DevPlan *dp = nullptr;
+    if ((s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, prec, &dp, false))) return s;
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    auto gk = std::vector<int>{L[0], L[1], L[2]};
+    auto git = ctx->group_images.find(gk);
+    if (git == ctx->group_images.end()) {
+        long npos = 0;
+        std::vector<int2> img = group_image(L, &npos);
+        git = ctx->group_images.emplace(gk, std::make_pair(std::move(img), npos)).first;
+    }
+    const std::vector<int2> &gimg = git->second.first;
+    const long npos = git->second.second;
+    // scratch layout: plan tables, momentum groups, energies, slice workspace
+    const size_t cs = prec == BBC_F64 ? 16 : 8;
+    const size_t off_grp = align256(dp->image.size());
+    const size_t off_en = align256(off_grp + gimg.size() * sizeof(int2));
+    const size_t off_ws = align256(off_en + sizeof(double) * n_ch);
+    const size_t need = off_ws + workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, cs);
+    if (need > kScratchBytes)
+        return fail(BBC_ENOMEM, "request needs " + std::to_string(need) + " bytes of scratch; the allocation-free "
+                                "entry point holds at most " + std::to_string(kScratchBytes) + " bytes (192 MiB)");
+    char *sc = (char *)ctx->scratch;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(sc, dp->image.data(), dp->image.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sc + off_grp, gimg.data(), gimg.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    if (energy) {
+        ctx->noalloc_energy.assign(energy, energy + n_ch);
+        HIP_TRY(hipMemcpyAsync(sc + off_en, ctx->noalloc_energy.data(), sizeof(double) * n_ch, hipMemcpyHostToDevice,
+                               st));
+    }
+    const PlanDev pd = plan_dev(dp, sc);
+    const MomGroups mg = groups_at((const int2 *)(sc + off_grp), npos);
+    const double *d_en = energy ? (const double *)(sc + off_en) : nullptr;
+    const size_t in_slice = (size_t)V * 144, out_slice = (size_t)n_ch * V * 16;
+    for (int n = 0; n < n_t; ++n) {
+        const double dt = (double)(t_list[n] - t0);
+        if (prec == BBC_F64) {
+            const double2 *sl = (const double2 *)S_light + n * in_slice, *ss = (const double2 *)S_strange + n * in_slice;
+            s = enqueue_slice<double>(ctx, pd, L, V, sc + off_ws, mg, sl, ss, n_ch, d_en, dt,
+                                      (double2 *)C_out + n * out_slice, nullptr, st, false);
+        } else {
+            const float2 *sl = (const float2 *)S_light + n * in_slice, *ss = (const float2 *)S_strange + n * in_slice;
+            s = enqueue_slice<float>(ctx, pd, L, V, sc + off_ws, mg, sl, ss, n_ch, d_en, dt,
+                                     (float2 *)C_out + n * out_slice, C_scale + (size_t)n * n_ch, st, false);
+        }
+        if (s) return s;
+    }
+    return BBC_OK;
+}
 
 bbc_status bbc_correlate_cpt(bbc_context *ctx, const int32_t lattice[3], int Lt, bbc_precision prec,
                              const void *S_light, const void *S_strange, int t0, int n_tau, const int32_t *tau_list,
