@@ -48,8 +48,7 @@ struct DevPlan {
     // every table the kernels read, as one image (byte offsets below): block-kernel
     // terms, pair tasks and channel terms (pairs.hpp), per-channel quark content
     std::vector<unsigned char> image;
-    size_t off_terms = 0, off_term_begin = 0, off_tasks = 0, off_pbegin = 0, off_ppair = 0, off_pw = 0,
-           off_content = 0;
+    size_t off_terms = 0, off_term_begin = 0, off_tasks = 0, off_comb = 0, off_comb_begin = 0, off_content = 0;
     void *d_image = nullptr;        // device copy, made by the entry points that allocate
     size_t table_bytes = 0;
     ~DevPlan() { (void)hipFree(d_image); }
@@ -61,16 +60,15 @@ struct PlanDev {
     const uint32_t *terms;
     const int32_t *term_begin;
     const bbc::PTask *tasks;
-    const int32_t *pbegin, *ppair;
-    const double *pw;
+    const bbc::CombEntry *comb;
+    const int32_t *comb_begin;
     const int2 *content;
 };
 PlanDev plan_dev(const DevPlan *dp, const void *base) {
     const char *b = (const char *)base;
     return PlanDev{dp, (const uint32_t *)(b + dp->off_terms), (const int32_t *)(b + dp->off_term_begin),
-                   (const bbc::PTask *)(b + dp->off_tasks), (const int32_t *)(b + dp->off_pbegin),
-                   (const int32_t *)(b + dp->off_ppair), (const double *)(b + dp->off_pw),
-                   (const int2 *)(b + dp->off_content)};
+                   (const bbc::PTask *)(b + dp->off_tasks), (const bbc::CombEntry *)(b + dp->off_comb),
+                   (const int32_t *)(b + dp->off_comb_begin), (const int2 *)(b + dp->off_content)};
 }
 
 // Number of self-conjugate momenta (q = -q mod L): 0 and L/2 along each even axis.
@@ -350,9 +348,8 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         dp->off_terms = image_put(img, P.terms.data(), P.terms.size());
         dp->off_term_begin = image_put(img, P.term_begin.data(), P.term_begin.size());
         dp->off_tasks = image_put(img, pt.tasks.data(), pt.tasks.size());
-        dp->off_pbegin = image_put(img, pt.term_begin.data(), pt.term_begin.size());
-        dp->off_ppair = image_put(img, pt.term_pair.data(), pt.term_pair.size());
-        dp->off_pw = image_put(img, pt.term_w.data(), pt.term_w.size());
+        dp->off_comb = image_put(img, pt.comb.data(), pt.comb.size());
+        dp->off_comb_begin = image_put(img, pt.comb_begin.data(), pt.comb_begin.size());
         dp->off_content = image_put(img, content.data(), content.size());
         img.resize((img.size() + 255) & ~(size_t)255, 0);
         dp->table_bytes = img.size();
@@ -476,7 +473,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     T2 *Ct = I;                                   // reuses region A once Iq is written
     T2 *Pp = (T2 *)((char *)ws + lay.p);
     uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
-    bbc::PairDevTables tb{mg.pos, mg.ngroup, pd.tasks, dp->ntask, dp->npair, pd.pbegin, pd.ppair, pd.pw};
+    bbc::PairDevTables tb{mg.pos, mg.ngroup, pd.tasks, dp->ntask, dp->npair, pd.comb, pd.comb_begin};
     const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
     T2 *out = (T2 *)outp;
     const bool fp32 = sizeof(T) == 4;

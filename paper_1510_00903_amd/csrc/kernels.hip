@@ -746,12 +746,11 @@ __global__ __launch_bounds__(256) void k_fft3d_grouped(const typename cplx_t<T>:
 // A group line holds q and -q (and in FP32 both sink spins), so a workgroup
 // takes whole mirror pairs of rows: the rows ky are ordered 0, Ly/2, 1, Ly-1, 2,
 // Ly-2, ... and a workgroup takes R consecutive ones (R even), which puts
-// (kx, ky, kz) and (-kx, -ky, -kz) in the same workgroup.  In FP64 (a spin per
-// line) a workgroup does both sink spins in turn; in FP32 (both spins in a line,
-// and too few registers for the loop) the two spins of a chunk are consecutive
-// workgroups.  All workgroups of a component run back to back on one XCD, so
-// most group lines are completed by one workgroup (or one pair running
-// together) and leave L2 whole.
+// (kx, ky, kz) and (-kx, -ky, -kz) in the same workgroup.  A group line holds
+// both sink spins of its momenta, so the two spins of a chunk are consecutive
+// workgroups (they run together and complete the lines in L2).  All workgroups
+// of a component run back to back on one XCD, so most group lines are
+// completed by one pair of workgroups running together and leave L2 whole.
 // Replaces the z axis pass and k_transpose_grouped.
 // ----------------------------------------------------------------------------
 template <typename T, int N>
@@ -764,12 +763,11 @@ __global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>:
     constexpr int G = Ly_::G;
     __shared__ T2 tw[N];
     const int t = threadIdx.x;
-    constexpr int SPW = sizeof(T) == 8 ? 2 : 1;     // sink spins per workgroup
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int per_c = (2 / SPW) * nchunk;
+    const int per_c = 2 * nchunk;                   // (chunk, sink spin) per component
     const int c = xcd * (int)(gridDim.x / (8 * per_c)) + j / per_c;
     const int r = j - (j / per_c) * per_c;
-    const int chunk = SPW == 2 ? r : r >> 1, g0 = SPW == 2 ? 0 : (r & 1);
+    const int chunk = r >> 1, g = r & 1;
     for (int i = t; i < N; i += 256) {
         double sn, cs;
         sincospi(2.0 * i / N, &sn, &cs);
@@ -785,19 +783,16 @@ __global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>:
     int pk[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) pk[k] = posof[line + k * nxy];
-#pragma unroll 1
-    for (int g = g0; g < g0 + SPW; ++g) {
-        const T2 *src = in + ((long)g * nc + c) * (long)nxy * N + line;
-        T2 a[N], b[N];
+    const T2 *src = in + ((long)g * nc + c) * (long)nxy * N + line;
+    T2 a[N], b[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) a[k] = src[(long)k * nxy];
-        Stages<T2, N, 1>::run(a, b, tw, sgn);
-        T2 *dst = out + (long)c * 2 * G + g * Ly_::SG;
+    for (int k = 0; k < N; ++k) a[k] = src[(long)k * nxy];
+    Stages<T2, N, 1>::run(a, b, tw, sgn);
+    T2 *dst = out + (long)c * 2 * G + g * Ly_::SG;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const int p = pk[k];
-            dst[(long)(p / G) * nc * 2 * G + (p % G) * Ly_::S] = a[k];
-        }
+    for (int k = 0; k < N; ++k) {
+        const int p = pk[k];
+        dst[(long)(p / G) * nc * 2 * G + (p % G) * Ly_::S] = a[k];
     }
 }
 
@@ -817,7 +812,7 @@ static void fft_z_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>
                           int Ly, const int *posof, hipStream_t st) {
     const int rows = (256 / Lx) / 2 * 2;           // whole mirror pairs of rows per workgroup
     const int nchunk = (Ly + rows - 1) / rows;
-    const long per_xcd = (long)((nc + 7) / 8) * (sizeof(T) == 8 ? 1 : 2) * nchunk;   // see SPW in the kernel
+    const long per_xcd = (long)((nc + 7) / 8) * 2 * nchunk;   // both sink spins of each chunk
     hipLaunchKernelGGL((k_fft_z_grouped<T, N>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, in, out, nc, Lx,
                        Ly, nchunk, rows, posof, -1);
 }
@@ -1159,40 +1154,59 @@ __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *_
 }
 
 // Channel sums: Ct[ch][s][q] = sum_t w_t P[group][pair_t][s][slot], FP64
-// accumulation, terms in table order.  Workgroup = (group, two channels); the
-// lanes of a channel are its 16 spins x G momenta; all channel pairs of a group
-// run back to back on one XCD, so the group's pair products are read from L2.
+// accumulation in ascending pair order.  One workgroup per momentum group reads
+// the group's pair products pair by pair (pair-major entry lists) for up to
+// kCombChunk channels; its 1024 lanes are 8 channel classes (ch mod 8) x 16
+// spins x G momenta, and a lane keeps the sums of its class's (at most 8)
+// channels in registers, the channel of each entry selected by a wave-uniform
+// branch.  Every sum belongs to one lane and is formed in a fixed order
+// (no atomics).  Entries are taken in batches whose loads are all issued first.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_combine(const typename cplx_t<T>::type *__restrict__ P,
-                                                      typename cplx_t<T>::type *__restrict__ Ct, int n_ch, long V,
-                                                      const int2 *__restrict__ gpos, int gbase, int gcount,
-                                                      int npair, const int32_t *__restrict__ term_begin,
-                                                      const int32_t *__restrict__ term_pair,
-                                                      const double *__restrict__ term_w) {
+__global__ __launch_bounds__(1024) void k_pair_combine(const typename cplx_t<T>::type *__restrict__ P,
+                                                       typename cplx_t<T>::type *__restrict__ Ct, int ch0, int nch,
+                                                       long V, const int2 *__restrict__ gpos, int gbase, int npair,
+                                                       const CombEntry *__restrict__ comb,
+                                                       const int32_t *__restrict__ comb_begin) {
     using T2 = typename cplx_t<T>::type;
     constexpr int G = GroupLayout<T2>::G;
-    static_assert(16 * G * 2 == 256, "two channels per workgroup");
-    const int nchp = (n_ch + 1) >> 1;
-    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
-    const int P8 = (gcount + 7) >> 3;
-    const int gl = xcd * P8 + jj / nchp;
-    const int cp = jj - (jj / nchp) * nchp;
-    if (gl >= gcount) return;
-    const int grp = gbase + gl;
-    const int ch = __builtin_amdgcn_readfirstlane(cp * 2 + (int)(threadIdx.x >> 7));
-    if (ch >= n_ch) return;
-    const int s = (threadIdx.x >> 3) & 15, slot = threadIdx.x & 7;
+    constexpr int NJ = kCombChunk / kCombSubs;      // channels per class
+    static_assert(kCombSubs * 16 * G == 1024, "one lane per (class, spin, momentum)");
+    const int grp = gbase + blockIdx.x;
+    const int t = threadIdx.x;
+    const int sub = __builtin_amdgcn_readfirstlane(t >> 7);
+    const int s = (t >> 3) & 15, slot = t & 7;
     const T2 *pg = P + (size_t)grp * npair * 16 * G + s * G + slot;
-    double2 acc = double2{0.0, 0.0};
-    const int tb = term_begin[ch], te = term_begin[ch + 1];
-    for (int t = tb; t < te; ++t) {
-        const T2 v = pg[(size_t)term_pair[t] * 16 * G];
-        const double w = term_w[t];
-        acc.x = fma(w, (double)v.x, acc.x);
-        acc.y = fma(w, (double)v.y, acc.y);
+    double2 acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = double2{0.0, 0.0};
+    const int eb = comb_begin[sub], ee = comb_begin[sub + 1];
+    constexpr int B = 8;
+    for (int i0 = eb; i0 < ee; i0 += B) {
+        T2 v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = i0 + u < ee ? pg[(size_t)comb[i0 + u].pair * 16 * G] : T2{0, 0};
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (i0 + u >= ee) break;
+            const int j = comb[i0 + u].ch >> 3;       // ch = sub + 8 j
+            const double w = comb[i0 + u].w;
+            switch (j) {
+#define BBC_COMB_CASE(J) \
+    case J: acc[J].x = fma(w, (double)v[u].x, acc[J].x); acc[J].y = fma(w, (double)v[u].y, acc[J].y); break;
+                BBC_COMB_CASE(0) BBC_COMB_CASE(1) BBC_COMB_CASE(2) BBC_COMB_CASE(3)
+                BBC_COMB_CASE(4) BBC_COMB_CASE(5) BBC_COMB_CASE(6) BBC_COMB_CASE(7)
+#undef BBC_COMB_CASE
+                default: break;
+            }
+        }
     }
     const int q = gpos[(size_t)grp * G + slot].x;
-    if (q >= 0) Ct[((size_t)ch * 16 + s) * V + q] = T2{(T)acc.x, (T)acc.y};
+    if (q < 0) return;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int ch = sub + 8 * j;
+        if (ch < nch) Ct[((size_t)(ch0 + ch) * 16 + s) * V + q] = T2{(T)acc[j].x, (T)acc[j].y};
+    }
 }
 
 template <typename T>
@@ -1216,14 +1230,15 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
 template <typename T>
 void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
                          const PairDevTables &tb, hipStream_t st) {
-    const long nchp = (n_ch + 1) / 2;
-    const long max_wg = (1L << 32) / 256 - 64;
-    const int per = (int)std::max<long>(8, std::min<long>(tb.ngroup, (max_wg / nchp) / 8 * 8));
-    for (int g0 = 0; g0 < tb.ngroup; g0 += per) {
-        const int gc = std::min(per, tb.ngroup - g0);
-        const long nwg = 8L * ((gc + 7) / 8) * nchp;
-        hipLaunchKernelGGL((k_pair_combine<T>), dim3((unsigned)nwg), dim3(256), 0, st, P, Ct, n_ch, V, tb.gpos, g0,
-                           gc, tb.npair, tb.term_begin, tb.term_pair, tb.term_w);
+    const long max_wg = (1L << 32) / 1024 - 64;
+    for (int c0 = 0; c0 < n_ch; c0 += kCombChunk) {
+        const int nch = std::min(kCombChunk, n_ch - c0);
+        const int32_t *cb = tb.comb_begin + (size_t)(c0 / kCombChunk) * kCombSubs;
+        for (long g0 = 0; g0 < tb.ngroup; g0 += max_wg) {
+            const long gc = std::min<long>(max_wg, tb.ngroup - g0);
+            hipLaunchKernelGGL((k_pair_combine<T>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch, V, tb.gpos,
+                               (int)g0, tb.npair, tb.comb, cb);
+        }
     }
 }
 

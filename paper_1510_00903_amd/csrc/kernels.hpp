@@ -16,9 +16,8 @@ struct PairDevTables {
     const PTask *tasks;
     int ntask;
     int npair;
-    const int32_t *term_begin;    // n_ch + 1
-    const int32_t *term_pair;
-    const double *term_w;
+    const CombEntry *comb;        // channel terms, pair-major (pairs.hpp)
+    const int32_t *comb_begin;    // per chunk of kCombChunk channels and class: entry ranges
 };
 
 // Blocks of 256 threads for a one-dimensional launch over n items, capped so
@@ -82,7 +81,7 @@ int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>:
                          int ngroup, const int2 *gpos, hipStream_t st);
 
 // Pair products P[group][pair][spin][G] of every task (MFMA), then the channel
-// sums Ct[ch][spin][q] = sum_t w_t P[pair_t] (fixed order, FP64 accumulation).
+// sums Ct[ch][spin][q] = sum_t w_t P[pair_t] (ascending pair order, FP64 accumulation).
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
                   const PairDevTables &tb, hipStream_t st);

@@ -91,6 +91,21 @@ PairTables build_pair_tables(const Plan &P) {
         }
     }
     T.term_begin[n] = (int)T.term_pair.size();
+    // pair-major form: per chunk of channels and class ch mod kCombSubs, by pair
+    // (within a channel the terms keep their ascending pair order)
+    const int nchunk = (n + kCombChunk - 1) / kCombChunk;
+    T.comb_begin.assign((size_t)nchunk * kCombSubs + 1, 0);
+    for (int c = 0; c < nchunk; ++c)
+        for (int k = 0; k < kCombSubs; ++k) {
+            std::vector<CombEntry> e;
+            for (int m = c * kCombChunk + k; m < std::min(n, (c + 1) * kCombChunk); m += kCombSubs)
+                for (int t = T.term_begin[m]; t < T.term_begin[m + 1]; ++t)
+                    e.push_back(CombEntry{T.term_pair[t], m - c * kCombChunk, T.term_w[t]});
+            std::stable_sort(e.begin(), e.end(), [](const CombEntry &a, const CombEntry &b) { return a.pair < b.pair; });
+            T.comb_begin[(size_t)c * kCombSubs + k] = (int)T.comb.size();
+            T.comb.insert(T.comb.end(), e.begin(), e.end());
+        }
+    T.comb_begin[(size_t)nchunk * kCombSubs] = (int)T.comb.size();
 
     // Tasks.  The row view is the one holding both outer spins (shape 1), else
     // (shape 0) the side whose views are fewer within the pair's class, so that

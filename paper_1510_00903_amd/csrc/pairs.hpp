@@ -55,12 +55,26 @@ struct PTask {
     int32_t pair[kMaxPartners];
 };
 
+// One channel term in pair-major order: channel ch (within its chunk) gains
+// w times pair product `pair`.
+struct CombEntry {
+    int32_t pair;
+    int32_t ch;
+    double w;
+};
+constexpr int kCombChunk = 64;        // channels per pass of the channel sums
+constexpr int kCombSubs = 8;          // channel classes (ch mod 8) per pass
+
 struct PairTables {
     std::vector<PTask> tasks;         // most expensive first
     int npair = 0;
     std::vector<int32_t> term_begin;  // per requested channel, n_ch + 1 entries
     std::vector<int32_t> term_pair;
     std::vector<double> term_w;
+    // the same terms per chunk of kCombChunk channels and per class ch mod kCombSubs,
+    // each class sorted by pair: entries [comb_begin[c * kCombSubs + k], comb_begin[... + 1])
+    std::vector<CombEntry> comb;
+    std::vector<int32_t> comb_begin;
     int64_t pair_items = 0;           // sum over pairs of K
 };
 
