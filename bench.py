@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -105,37 +106,26 @@ def cpu_baseline(Sl, Ss, t_idx, budget_s=20.0):
                       % (t_idx, len(done), [list(p) for p in r_points[:1 + (len(done) - 1) // 13]], el)}
 
 
-def cpu_baseline_unified(Sl, Ss, t_idx):
-    """The FP64 O-U oracle (source weights folded first, X-sum by numpy's FFT) on the
-    full 16^3 field of one channel (p n > p n) at time slice t_idx: a stronger CPU
-    reference than the direct O(V^2) sum (one process, numpy threading as installed)."""
-    from oracle import operators as ops
-    from oracle import unified
-    t0 = time.perf_counter()
-    C = unified.correlate(Sl[t_idx], Ss[t_idx], ops.CHANNELS[0])
-    el = time.perf_counter() - t0
-    n = C.shape[0] * C.shape[1] * C.shape[2]
-    return {"value": n / el, "unit": "site-channels/s", "cores": 1, "kind": "oracle",
-            "sample": "O-U oracle (unified contraction + numpy FFT), full field of channel 0 (p n > p n) "
-                      "on the 16^3 slice t=%d: %d site-channels in %.1f s" % (t_idx, n, el)}
-
-
-def serve_mix(bbc, torch, np, n_jobs=64, n_slots=4, load=0.8):
-    """Continuous-batching serving on a Poisson stream of mixed jobs (FP32 form).
+def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96,
+                runs=((0.5, 4), (0.8, 4), (1.2, 4), (1.2, 1))):
+    """Continuous-batching serving on a Poisson stream of mixed jobs (FP32 form),
+    under a finite HBM budget (resident propagator sets plus slot workspaces).
 
     Jobs: lattice uniform over {16^3x32, 24^3x48, 32^3x64}, channel subset of
     size U[4,52] drawn without replacement, n_t U[4,16] distinct slices, one of
     4 resident propagator sets per lattice (seeded PCG64, seed 1510009034).
-    The service rate is measured by running all jobs one after another on a
-    single slot (which also gives every job's result alone); the stream then
-    arrives at load x that rate on n_slots slots.  Reports p50/p99 latency
-    (submit to completion) and throughput, and checks that every job's result
-    in the mix is bit-identical to its result alone.
+    The service rate mu is measured by running all jobs one after another on a
+    single slot, which also gives every job's result alone (kept on the device).
+    Each run then replays the stream with Poisson arrivals at load x mu on the
+    given number of slots and reports p50/p99 latency (submit to completion) and
+    throughput; every job's result in the mix is compared bit for bit with its
+    result alone.
     """
     dev = torch.device("cuda:0")
     lattices = [(16, 32), (24, 48), (32, 64)]
     rng = np.random.Generator(np.random.PCG64(1510009034))
-    ctx = bbc.Context(0)
+    budget = int(budget_gb) << 30
+    ctx = bbc.Context(0, hbm_budget_bytes=budget)
     ctx.server_start(1)
     # propagator sets: seeded Gaussian entries x exp(-m t), generated on the device (FP32)
     props = {}
@@ -169,60 +159,61 @@ def serve_mix(bbc, torch, np, n_jobs=64, n_slots=4, load=0.8):
         jid = ctx.submit(j["prop"], j["sl"], j["sl"], j["ch"], out, scale)
         return jid, out, scale
 
-    def fingerprint(out, scale):
-        return (int(out.view(torch.int32).to(torch.int64).sum().item()),
-                int(scale.view(torch.int64).sum().item()))
-
     # single stream: service rate and results alone
+    jid, _, _ = run_job(jobs[0])     # warm-up: plans and workspaces
+    ctx.wait(jid)
     alone, service = [], []
-    run_job(jobs[0])   # warm-up: plans and workspaces
-    torch.cuda.synchronize()
-    ctx.server_stop()
-    ctx.server_start(1)
     t0 = time.perf_counter()
     for j in jobs:
         jid, out, scale = run_job(j)
         ctx.wait(jid)
         service.append(ctx.job_times(jid)[1])
-        alone.append(fingerprint(out, scale))
+        alone.append((out, scale))
         ctx.job_forget(jid)
-        del out, scale
     single_s = time.perf_counter() - t0
+    ctx.server_stop()
     mu = n_jobs / single_s
-    lam = load * mu
-    gaps = rng.exponential(1.0 / lam, size=n_jobs)
-    arrivals = np.cumsum(gaps) - gaps[0]
-    ctx.server_stop()
-    ctx.server_start(n_slots)
-    print("serve: single stream %.2f s (%.1f jobs/s); mix at %.1f jobs/s on %d slots"
-          % (single_s, mu, lam, n_slots), file=sys.stderr, flush=True)
-    inflight = []
-    start = time.perf_counter()
-    for j, at in zip(jobs, arrivals):
-        now = time.perf_counter() - start
-        if at > now:
-            time.sleep(at - now)
-        inflight.append(run_job(j))
-    lat, same = [], 0
-    for (jid, out, scale), a in zip(inflight, alone):
-        ctx.wait(jid)
-        lat.append(ctx.job_times(jid)[2])
-        same += fingerprint(out, scale) == a
-    makespan = time.perf_counter() - start
-    ctx.server_stop()
-    ctx.close()
     sites = sum(j["sites"] for j in jobs)
-    lat = np.array(lat)
+    results = []
+    for load, n_slots in runs:
+        lam = load * mu
+        gaps = rng.exponential(1.0 / lam, size=n_jobs)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        ctx.server_start(n_slots)
+        print("serve: load %.1f on %d slots (%.1f jobs/s)" % (load, n_slots, lam), file=sys.stderr, flush=True)
+        inflight = []
+        start = time.perf_counter()
+        for j, at in zip(jobs, arrivals):
+            now = time.perf_counter() - start
+            if at > now:
+                time.sleep(at - now)
+            inflight.append(run_job(j))
+        lat, same = [], 0
+        for (jid, out, scale), (aout, ascale) in zip(inflight, alone):
+            ctx.wait(jid)
+            lat.append(ctx.job_times(jid)[2])
+            ctx.job_forget(jid)
+            same += bool(torch.equal(out, aout)) and bool(torch.equal(scale, ascale))
+        makespan = time.perf_counter() - start
+        ctx.server_stop()
+        del inflight
+        lat = np.array(lat)
+        results.append({"load": load, "slots": n_slots, "arrival_rate_jobs_per_s": round(lam, 3),
+                        "site_channels_per_s": round(sites / makespan, 1), "makespan_s": round(makespan, 3),
+                        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                                       "p99": round(float(np.percentile(lat, 99)), 2),
+                                       "mean": round(float(lat.mean()), 2), "max": round(float(lat.max()), 2)},
+                        "results_identical_alone_vs_mix": "%d/%d" % (same, n_jobs)})
+    del alone
+    ctx.close()
+    torch.cuda.empty_cache()
     return {
         "metric": "serving: job latency p50/p99 and throughput (site-channels/s)",
-        "value": round(sites / makespan, 1), "unit": "site-channels/s", "n_gpus": 1,
-        "higher_is_better": True, "dtype": "f32", "data": "synthetic (seeded on the device)",
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
-                       "mean": round(float(lat.mean()), 2), "max": round(float(lat.max()), 2)},
+        "unit": "site-channels/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic (seeded on the device)", "hbm_budget_bytes": budget,
         "single_stream": {"jobs_per_s": round(mu, 3), "site_channels_per_s": round(sites / single_s, 1),
                           "mean_service_ms": round(float(np.mean(service)), 2)},
-        "arrival_rate_jobs_per_s": round(lam, 3), "load": load, "slots": n_slots, "jobs": n_jobs,
-        "makespan_s": round(makespan, 3), "results_identical_alone_vs_mix": "%d/%d" % (same, n_jobs),
+        "runs": results, "jobs": n_jobs,
         "config": {"workload": "64-job Poisson mix: lattices 16^3x32/24^3x48/32^3x64, 4-52 channels, "
                                "4-16 slices, 4 resident propagator sets per lattice, FP32 form"},
     }
@@ -263,15 +254,29 @@ def stream96(bbc, torch, np, n_slices):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = ctx.profile_read()
-    ok = bool(torch.isfinite(out[-1, :, :2]).all().item()) and bool(torch.isfinite(scale).all().item())
     ctx.close()
+    # exact relations on the last slice (host copy of the output): the isospin pair
+    # C[L L > p X-] = -C[L L > n X0] on two z planes, and for identical sink baryons
+    # C(r)_{a b a' b'} = -C(-r)_{b a a' b'} (L L > L L) over every r
+    sc = scale[-1].cpu()
+    a = out[-1, 11, [0, 48]].to(torch.complex128) * float(sc[11])
+    b = out[-1, 12, [0, 48]].to(torch.complex128) * float(sc[12])
+    iso = float((a + b).abs().max() / a.abs().max())
+    C = out[-1, 10].to(torch.complex128)
+    neg = torch.roll(torch.flip(C, dims=(0, 1, 2)), shifts=(1, 1, 1), dims=(0, 1, 2))
+    idx = torch.tensor([((s >> 1) & 1) + 2 * (s & 1) + 4 * (s >> 2) for s in range(16)])
+    anti = float((C + neg[..., idx]).abs().max() / C.abs().max())
+    del a, b, C, neg
+    ok = iso <= 1e-5 and anti <= 1e-5
     site_ch = V * T * n_ch
     stages = {k: {"ms_total": round(v[0], 2), "ms_per_slice": round(v[0] / max(1, T), 2)} for k, v in prof.items()}
     return {"metric": "correlator site-channels/sec (C_ch(r,t))", "value": round(site_ch / el, 1),
             "unit": "site-channels/s", "n_gpus": 1, "steps": T, "warmup": 1,
             "ms_per_slice": round(1000 * el / T, 2), "higher_is_better": True, "dtype": "f32",
             "data": "synthetic (seeded on the host, streamed from pinned memory)",
-            "outputs_finite": ok,
+            "relations_hold": ok,
+            "relations": {"isospin_LL_pXm_plus_LL_nX0": iso, "identical_sink_antisymmetry_LL": anti,
+                          "tolerance": 1e-5, "slice": T - 1},
             "config": {"workload": "96^3 lattice, all 52 channels, FP32 form, slices streamed host->device, "
                                    "outputs streamed back", "lattice": [L, L, L], "slices": T,
                        "input_GB_per_slice": round(2 * V * 144 * 8 / 1e9, 3),
@@ -420,15 +425,156 @@ def next_rows(bbc, torch, np, synth, steps):
             "paths": out}
 
 
+def device_correlated(torch, L, T, seed, dtype):
+    """The 32^3 x 64 configuration's inputs, drawn on the device (seeded torch generator):
+    S_f(x, t) = exp(-m_f t) (Z_f(x) + 1e-3 eta_f(x, t)), Z and eta complex Gaussian (re, im
+    independent N(0, 1)), m = 0.5 (light), 0.7 (strange).  Drawn in FP32; the FP64 form
+    takes the same values."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    out = []
+    for m in (0.5, 0.7):
+        Z = torch.randn((L, L, L, 12, 12), dtype=torch.complex64, device=dev, generator=g) * (2 ** 0.5)
+        S = torch.empty((T, L, L, L, 12, 12), dtype=torch.complex64, device=dev)
+        for t in range(T):
+            eta = torch.randn((L, L, L, 12, 12), dtype=torch.complex64, device=dev, generator=g) * (2 ** 0.5)
+            S[t] = (Z + 1e-3 * eta) * math.exp(-m * t)
+        out.append(S if dtype == torch.complex64 else S.to(dtype))
+    return out
+
+
+def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, channels=None):
+    """Time `steps` whole jobs (every slice of d_l/d_s, all channels) after `warmup`
+    untimed ones; per-stage device times from HIP events of the profiled steps."""
+    T = d_l.shape[0]
+    channels = list(range(52)) if channels is None else channels
+    n_ch = len(channels)
+    dev = torch.device("cuda:0")
+    out = torch.empty((T, n_ch, L, L, L, 16), dtype=torch.complex64 if fp32 else torch.complex128, device=dev)
+    scale = torch.empty((T, n_ch), dtype=torch.float64, device=dev) if fp32 else None
+    ctx = bbc.Context(0)
+    t_list = list(range(T))
+    if graph:
+        ctx.graph_mode(True)
+    for _ in range(warmup):
+        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
+    torch.cuda.synchronize()
+    if not graph:
+        ctx.profile(True)
+        ctx.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof_steps = steps
+    if graph:
+        ctx.graph_mode(False)
+        ctx.profile(True)
+        ctx.profile_read()
+        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
+        torch.cuda.synchronize()
+        prof_steps = 1
+    prof = ctx.profile_read()
+    ctx.close()
+    ms_per_step = 1000.0 * el / steps
+    site_ch = L ** 3 * T * n_ch
+    st = bbc.plan_stats(channels)
+    nc = st["components"] // 2
+    csize = 8 if fp32 else 16
+    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    stages = {}
+    n_slices = T * prof_steps
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue                                 # stage without kernels on this path (fused)
+        ms_slice = ms / n_slices
+        stages[name] = {"ms_total": round(ms, 4), "kernels": int(launches), "ms_per_slice": round(ms_slice, 4)}
+        nb = stage_model(name, L, nc, n_ch, csize)
+        if nb is not None:
+            stages[name]["alg_GBs"] = round(nb / (ms_slice * 1e-3) / 1e9, 1)
+    dom = max(stages, key=lambda k: stages[k]["ms_total"])
+    avg_s = stages[dom]["ms_total"] / 1000.0 / stages[dom]["kernels"]
+    if dom == "contract":
+        # the method's work: 16 complex MACs (8 flops each) per open-index item, all
+        # channels; the pair products run on the matrix cores (peak of the dtype)
+        flops = 8.0 * 16 * st["iterations"] * L ** 3
+        achieved = flops / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4)}
+    else:
+        nbytes = stage_model(dom, L, nc, n_ch, csize) * n_slices / stages[dom]["kernels"]
+        achieved = nbytes / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = round(avg_s * 1e6, 2)
+    roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64", L)
+    return {"value": round(site_ch / (ms_per_step / 1000.0), 1), "ms_per_step": round(ms_per_step, 3),
+            "site_channels_per_step": site_ch, "roofline": roof, "stages": stages,
+            "block_components_per_site": st["components"], "iterations": st["iterations"]}, out, scale
+
+
+def c1_job(bbc, torch, np, synth, steps):
+    """8^3 x 8, channel 1 (p Lambda > p Lambda), FP64: eager launches and HIP-graph replay."""
+    L, T = 8, 8
+    dev = torch.device("cuda:0")
+    Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED)
+    d_l, d_s = torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
+    res = {}
+    for mode in ("eager", "graph"):
+        r, _, _ = correlator_job(bbc, torch, d_l, d_s, L, False, steps, 3, graph=mode == "graph", channels=[1])
+        res[mode] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                     "stages_ms_per_slice": {k: v["ms_per_slice"] for k, v in r["stages"].items()}}
+    return {"workload": "8^3x8 lattice, channel 1 (p Lambda > p Lambda), FP64, all r, all t",
+            "unit": "site-channels/s", "site_channels_per_step": L ** 3 * T, **res}
+
+
+def c3_jobs(bbc, torch, np, steps):
+    """32^3 x 64, 52 channels: the FP64 form and the FP32 form on the same (FP32-drawn)
+    inputs, generated on the device; per-channel normwise error of the FP32 form against
+    the FP64 form over every r at t = 0, 31, 63."""
+    L, T = 32, 64
+    res = {}
+    d_l, d_s = device_correlated(torch, L, T, synth_seed_c3(), torch.complex64)
+    r32, out32, scale32 = correlator_job(bbc, torch, d_l, d_s, L, True, steps, 1)
+    res["f32"] = r32
+    keep = [0, 31, 63]
+    c32 = (out32[keep].to(torch.complex128) * scale32[keep].view(3, 52, 1, 1, 1, 1)).contiguous()
+    del out32, scale32
+    torch.cuda.empty_cache()
+    d_l64, d_s64 = d_l.to(torch.complex128), d_s.to(torch.complex128)
+    del d_l, d_s
+    r64, out64, _ = correlator_job(bbc, torch, d_l64, d_s64, L, False, steps, 1)
+    res["f64"] = r64
+    c64 = out64[keep]
+    err = ((c32 - c64).abs().amax(dim=(2, 3, 4, 5)) / c64.abs().amax(dim=(2, 3, 4, 5))).amax(dim=0)
+    del out64, d_l64, d_s64, c32, c64
+    torch.cuda.empty_cache()
+    e = [float(x) for x in err.cpu()]
+    return {"workload": "32^3x64 lattice, all 52 channels, inputs exp(-m t)(Z + 1e-3 eta_t) drawn on the device",
+            "unit": "site-channels/s", "f32": res["f32"], "f64": res["f64"],
+            "fp32_speedup": round(res["f32"]["value"] / res["f64"]["value"], 3),
+            "fp32_vs_fp64_normwise_error": {"max": max(e), "per_channel": [float("%.3g" % x) for x in e],
+                                            "slices": keep, "tolerance": 1e-5}}
+
+
+def synth_seed_c3():
+    return 1510009030 + 2
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the c1, c3 and serving measurements")
     ap.add_argument("--workload", default="16c32-f64",
                     choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream", "post-16c32",
-                             "next-16c32"],
+                             "next-16c32", "8c8-plambda"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
     ap.add_argument("--graph", action="store_true",
@@ -451,7 +597,7 @@ def main():
     import synth
 
     if args.workload == "serve-mix":
-        print(json.dumps(serve_mix(bbc, torch, np)), flush=True)
+        print(json.dumps(serve_sweep(bbc, torch, np)), flush=True)
         return
     if args.workload == "96c-f32-stream":
         print(json.dumps(stream96(bbc, torch, np, args.steps)), flush=True)
@@ -462,30 +608,25 @@ def main():
     if args.workload == "next-16c32":
         print(json.dumps(next_rows(bbc, torch, np, synth, args.steps)), flush=True)
         return
+    if args.workload == "8c8-plambda":
+        print(json.dumps(c1_job(bbc, torch, np, synth, args.steps)), flush=True)
+        return
 
     fp32 = args.workload.endswith("f32")
     L, T = (16, 32) if args.workload.startswith("16") else (32, 64)
-    channels = list(range(52))
-    n_ch = len(channels)
     dev = torch.device("cuda:0")
-    cdt = np.complex64 if fp32 else np.complex128
     print("bench: generating %d^3 x %d propagators" % (L, T), file=sys.stderr, flush=True)
     if L == 16:
         Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 1)
+        d_l = torch.from_numpy(Sl).to(dev)
+        d_s = torch.from_numpy(Ss).to(dev)
     else:
-        Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED + 2, kind="correlated", dtype=cdt)
-    d_l = torch.from_numpy(Sl).to(dev)
-    d_s = torch.from_numpy(Ss).to(dev)
-    out = torch.empty((T, n_ch, L, L, L, 16), dtype=torch.complex64 if fp32 else torch.complex128, device=dev)
-    scale = torch.empty((T, n_ch), dtype=torch.float64, device=dev) if fp32 else None
-    ctx = bbc.Context(0)
+        Sl = Ss = None
+        d_l, d_s = device_correlated(torch, L, T, synth_seed_c3(),
+                                     torch.complex64 if fp32 else torch.complex128)
     if args.slices:
         T = min(T, args.slices)
-        Sl, Ss = Sl[:T], Ss[:T]
-        d_l, d_s, out = d_l[:T], d_s[:T], out[:T]
-        scale = scale[:T] if scale is not None else None
-    t_list = list(range(T))
-
+        d_l, d_s = d_l[:T], d_s[:T]
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         b = torch.empty_like(a)
@@ -494,101 +635,49 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-
-    if args.graph:
-        ctx.graph_mode(True)
-    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
-    torch.cuda.synchronize()
-    if not args.graph:
-        ctx.profile(True)
-        ctx.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof_steps = args.steps
-    if args.graph:
-        # stage timings from one more, profiled, eager step (the same kernels)
-        ctx.graph_mode(False)
-        ctx.profile(True)
-        ctx.profile_read()
-        ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
-        torch.cuda.synchronize()
-        prof_steps = 1
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    print("bench: timed %d steps in %.3f s" % (args.steps, el), file=sys.stderr, flush=True)
-
-    ms_per_step = 1000.0 * el / args.steps
-    site_ch = L ** 3 * T * n_ch
-    value = site_ch / (ms_per_step / 1000.0)
-
-    st = bbc.plan_stats(channels)
-    nc = st["components"] // 2
-    csize = 8 if fp32 else 16
-    peak_alu = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
-    stages = {}
-    n_slices = T * prof_steps
-    for name, (ms, launches) in prof.items():
-        if launches == 0:
-            continue                                 # stage without kernels on this path (fused)
-        ms_slice = ms / n_slices
-        stages[name] = {"ms_total": round(ms, 4), "kernels": int(launches), "ms_per_slice": round(ms_slice, 4)}
-        nb = stage_model(name, L, nc, n_ch, csize)
-        if nb is not None:
-            stages[name]["alg_GBs"] = round(nb / (ms_slice * 1e-3) / 1e9, 1)
-    # dominant kernel: the contraction (one kernel per slice)
-    dom = max(stages, key=lambda k: stages[k]["ms_total"])
-    avg_s = stages[dom]["ms_total"] / 1000.0 / stages[dom]["kernels"]
-    if dom == "contract":
-        # the method's work: 16 complex MACs (8 flops each) per open-index item, all
-        # channels; the pair products run on the matrix cores (peak of the dtype)
-        flops = 8.0 * 16 * st["iterations"] * L ** 3
-        achieved = flops / avg_s / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak_alu,
-                "unit": "TFLOP/s", "frac": round(achieved / peak_alu, 4)}
-    else:
-        nbytes = stage_model(dom, L, nc, n_ch, csize) * n_slices / stages[dom]["kernels"]
-        achieved = nbytes / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4)}
-    roof["kernel"] = dom
-    roof["avg_launch_us"] = round(avg_s * 1e6, 2)
-    roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64", L)
-
+    print("bench: warmup %d, steps %d" % (args.warmup, args.steps), file=sys.stderr, flush=True)
+    r, out, scale = correlator_job(bbc, torch, d_l, d_s, L, fp32, args.steps, args.warmup, graph=args.graph)
+    del out, scale
+    print("bench: timed %d steps, %.3f ms per step" % (args.steps, r["ms_per_step"]), file=sys.stderr, flush=True)
+    n_ch = 52
     res = {
         "metric": "correlator site-channels/sec (C_ch(r,t))",
-        "value": round(value, 1),
+        "value": r["value"],
         "unit": "site-channels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(value / PAPER_SITE_CH_PER_S, 2) if L == 16 else None,
+        "vs_baseline": round(r["value"] / PAPER_SITE_CH_PER_S, 2) if L == 16 and not fp32 else None,
         "baseline_context": "paper Table 5, 16^3x32, 52 channels, 32 BlueGene/Q nodes, best layout 19 s"
                             if L == 16 else None,
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic (seeded Gaussian propagators, exp(-m t) decay)" if L == 16 else
-                "synthetic (seeded t-independent Gaussian field + 1e-3 noise per slice, exp(-m t) decay)",
+                "synthetic (seeded t-independent Gaussian field + 1e-3 noise per slice, exp(-m t) decay, "
+                "drawn on the device)",
         "config": {"workload": "%d^3x%d lattice, all 52 BB channels, %s, upper spins"
-                               % (L, T, "FP32 form (power-of-two rescaled, FP32 matrix-core products, FP64 channel sums)" if fp32 else "FP64 plain form"),
-                   "lattice": [L, L, L], "T": T, "channels": n_ch, "site_channels_per_step": site_ch,
-                   "block_components_per_site": st["components"], "iterations": st["iterations"]},
-        "roofline": roof,
-        "stages": stages,
+                               % (L, T, "FP32 form (power-of-two rescaled, FP32 matrix-core products, "
+                                        "FP64 channel sums)" if fp32 else "FP64 plain form"),
+                   "lattice": [L, L, L], "T": T, "channels": n_ch, "site_channels_per_step": r["site_channels_per_step"],
+                   "block_components_per_site": r["block_components_per_site"], "iterations": r["iterations"]},
+        "roofline": r["roofline"],
+        "stages": r["stages"],
         "hip_graph": bool(args.graph),
     }
-    if not args.no_cpu_baseline and L == 16:
+    if L == 16 and not fp32 and not args.no_extras and not args.slices:
+        del d_l, d_s
+        torch.cuda.empty_cache()
+        print("bench: c1 (8^3 x 8 p Lambda)", file=sys.stderr, flush=True)
+        res["c1_8c8_plambda_f64"] = c1_job(bbc, torch, np, synth, 20)
+        print("bench: c3 (32^3 x 64, FP32 and FP64)", file=sys.stderr, flush=True)
+        res["c3_32c64"] = c3_jobs(bbc, torch, np, 2)
+        print("bench: c4 (serving sweep)", file=sys.stderr, flush=True)
+        res["c4_serving"] = serve_sweep(bbc, torch, np)
+    if not args.no_cpu_baseline and L == 16 and Sl is not None:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(Sl, Ss, 7)
-        res["cpu_baseline_unified"] = cpu_baseline_unified(Sl, Ss, 7)
-    ctx.close()
     print(json.dumps(res), flush=True)
 
 

@@ -125,6 +125,15 @@ bbc_status bbc_diagram_table(int channel, int term3, int term4, int max_diagrams
 bbc_status bbc_plan_stats(int n_ch, const int32_t *ch_list, int64_t *n_intermediates,
                           int64_t *n_components, int64_t *n_terms, int64_t *n_iterations);
 
+/* Pair form of the contraction for a channel set (Sec. 3 Eq. (LN.pLLp.FFT)):
+   each channel is a weighted sum of products of two intermediate views with the
+   open source indices summed.  Outputs: the number of distinct pair products,
+   of contraction tasks (one wave each: a row view and its partners), the sum
+   over pairs of the open-index extent K, and the number of (channel, pair)
+   weights.  Host only; any output may be NULL. */
+bbc_status bbc_pair_stats(int n_ch, const int32_t *ch_list, int64_t *n_pairs, int64_t *n_tasks,
+                          int64_t *pair_items, int64_t *n_weights);
+
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
    workspace (0: no bound beyond free memory). */
 bbc_status bbc_create(int device, uint64_t hbm_budget_bytes, bbc_context **out);

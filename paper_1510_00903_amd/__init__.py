@@ -28,7 +28,7 @@ _lib = None
 
 EXPORTED_SYMBOLS = [
     "bbc_num_channels", "bbc_num_channels_all", "bbc_channel_name", "bbc_channel_content",
-    "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create", "bbc_destroy",
+    "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_pair_stats", "bbc_create", "bbc_destroy",
     "bbc_last_error", "bbc_footprint", "bbc_correlate", "bbc_correlate_noalloc", "bbc_profile_enable",
     "bbc_profile_read",
     "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit", "bbc_poll",
@@ -76,6 +76,7 @@ def load():
     lib.bbc_source_terms.argtypes = [I, P, P]
     lib.bbc_diagram_table.argtypes = [I, I, I, I, P, P, P]
     lib.bbc_plan_stats.argtypes = [I, P, P, P, P, P]
+    lib.bbc_pair_stats.argtypes = [I, P, P, P, P, P]
     lib.bbc_create.argtypes = [I, U64, P]
     lib.bbc_destroy.argtypes = [P]
     lib.bbc_destroy.restype = None
@@ -101,7 +102,7 @@ def load():
     lib.bbc_spin_project.argtypes = [P, P, I, I, P, I, P, P, P]
     lib.bbc_cubic_project.argtypes = [P, P, I, I, I, P, I, P, P]
     lib.bbc_central_potential.argtypes = [P, P, I, I, P, ctypes.c_double, P, P]
-    for f in ("bbc_spin_project", "bbc_cubic_project", "bbc_central_potential", "bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_create",
+    for f in ("bbc_spin_project", "bbc_cubic_project", "bbc_central_potential", "bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_pair_stats", "bbc_create",
               "bbc_footprint", "bbc_correlate", "bbc_correlate_noalloc", "bbc_profile_enable", "bbc_profile_read",
               "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit",
               "bbc_poll", "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget"):
@@ -209,6 +210,16 @@ def plan_stats(channels):
     vals = [ctypes.c_int64() for _ in range(4)]
     _check(load().bbc_plan_stats(n, arr, *[ctypes.byref(v) for v in vals]))
     keys = ("intermediates", "components", "diagrams", "iterations")
+    return dict(zip(keys, (v.value for v in vals)))
+
+
+def pair_stats(channels):
+    """Pair form of the contraction: distinct pair products, tasks, sum of K over
+    pairs, (channel, pair) weights."""
+    arr, n = _i32(channels)
+    vals = [ctypes.c_int64() for _ in range(4)]
+    _check(load().bbc_pair_stats(n, arr, *[ctypes.byref(v) for v in vals]))
+    keys = ("pairs", "tasks", "pair_items", "weights")
     return dict(zip(keys, (v.value for v in vals)))
 
 

@@ -1072,6 +1072,23 @@ bbc_status bbc_plan_stats(int n_ch, const int32_t *ch_list, int64_t *n_inter, in
     return BBC_OK;
 }
 
+bbc_status bbc_pair_stats(int n_ch, const int32_t *ch_list, int64_t *n_pairs, int64_t *n_tasks, int64_t *items,
+                          int64_t *n_weights) {
+    if (n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list");
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    try {
+        const bbc::Plan P = bbc::build_plan(chans, 0);
+        const bbc::PairTables T = bbc::build_pair_tables(P);
+        if (n_pairs) *n_pairs = T.npair;
+        if (n_tasks) *n_tasks = (int64_t)T.tasks.size();
+        if (items) *items = T.pair_items;
+        if (n_weights) *n_weights = (int64_t)T.term_pair.size();
+    } catch (const std::exception &e) {
+        return fail(BBC_EINVAL, e.what());
+    }
+    return BBC_OK;
+}
+
 const char *bbc_last_error(void) { return g_err.c_str(); }
 
 bbc_status bbc_create(int device, uint64_t budget, bbc_context **out) {
