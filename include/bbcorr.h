@@ -209,6 +209,70 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
                                  const double *energy, void *C_out, double *C_scale, void *stream);
 
 /*
+ * Kernel variants (tile and launch shapes) of one request shape: the lattice,
+ * the precision, the spin selection and the channel list (in its order).  The
+ * steps of Sec. 3 and Sec. 5 (blocks, forward FFT, open-index contraction) each
+ * have variants that form the same values in the same order, so every choice
+ * gives bit-identical results and only the speed differs:
+ *   pairs   open-index contraction on the matrix cores: FP64 0 = a whole
+ *           momentum group per wave, 1 = the same with the loads of the next
+ *           open-index step issued ahead, 2 = half a group per wave, 3 = half a
+ *           group, loads ahead; FP32 0 = plain, 1 = loads ahead;
+ *   blocks  block construction, sites per workgroup x component shares:
+ *           0 = 4 x 2, 1 = 4 x 4, 2 = 8 x 2;
+ *   planes  x-y plane pass of the forward FFT (square 24- and 32-point planes):
+ *           0 = as many planes per workgroup as 80 KB of LDS hold, 1 = half.
+ * A context keeps one choice per request shape; shapes without one take the
+ * library's built-in choice.  Graphs captured in graph mode keep the variants
+ * of their capture (same results).
+ */
+typedef struct {
+    int32_t pairs;
+    int32_t blocks;
+    int32_t planes;
+} bbc_tuning;
+
+/* The variants a request shape runs with; *tuned (may be NULL) = 1 if the
+   context holds a choice for it (set, tuned or loaded), 0 if built-in. */
+bbc_status bbc_tuning_get(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_ch,
+                          const int32_t *ch_list, bbc_spin spin, bbc_tuning *out, int *tuned);
+
+/* Sets the variants of a request shape (t = NULL: back to the built-in choice).
+   BBC_EINVAL for a variant out of range. */
+bbc_status bbc_tuning_set(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_ch,
+                          const int32_t *ch_list, bbc_spin spin, const bbc_tuning *t);
+
+/*
+ * Autotuner: times whole time slices (blocks through finalisation) of the
+ * request shape on one device-resident slice S_light, S_strange
+ * ([Lz][Ly][Lx][12][12] of the precision's type) and keeps the fastest
+ * variants: a coordinate search from the current choice over the contraction
+ * kernel, then the plane pass (lattices that take one), then the block
+ * kernel, each candidate timed over `reps` slices (1..1000) after one untimed
+ * slice, with HIP events on `stream`.  The choice is stored in the context
+ * (and written to the tuning file, see below); out and ms_per_slice (the best
+ * time per slice, milliseconds) may be NULL.  Allocates a scratch output
+ * buffer and grows the context workspace as bbc_correlate does; synchronises
+ * `stream` before returning.
+ */
+bbc_status bbc_autotune(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec,
+                        const void *S_light, const void *S_strange, int n_ch, const int32_t *ch_list,
+                        bbc_spin spin, int reps, void *stream, bbc_tuning *out, double *ms_per_slice);
+
+/*
+ * Tuning file (JSON): {"bbc_tuning": 1, "entries": [{"lattice": [Lx, Ly, Lz],
+ * "precision": 0|1, "spin_offset": 0|2, "channel_hash": "<FNV-1a of the
+ * channel list, 16 hex digits>", "pairs": p, "blocks": b, "planes": l}, ...]}.
+ * bbc_tuning_save writes every choice the context holds (replacing the file
+ * atomically); bbc_tuning_load merges a file's entries into the context
+ * (BBC_EINVAL on a malformed file or a value out of range).  If the environment
+ * variable BBC_TUNING_CACHE names a file, bbc_create loads it when it exists
+ * and bbc_autotune rewrites it after each tuning.
+ */
+bbc_status bbc_tuning_save(bbc_context *ctx, const char *path);
+bbc_status bbc_tuning_load(bbc_context *ctx, const char *path);
+
+/*
  * Forward/backward (CPT) average of Sec. 6.  The baryon pair propagating
  * forward in time (upper spinor components) and the antibaryon pair
  * propagating backward (lower components) are related by charge conjugation,

@@ -35,6 +35,7 @@ EXPORTED_SYMBOLS = [
     "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget",
     "bbc_spin_project", "bbc_cubic_project", "bbc_central_potential",
     "bbc_num_baryons", "bbc_baryon_name", "bbc_channel_id", "bbc_graph_mode", "bbc_correlate_cpt",
+    "bbc_tuning_get", "bbc_tuning_set", "bbc_autotune", "bbc_tuning_save", "bbc_tuning_load",
 ]
 CUBIC_A1, CUBIC_A1_COMPLEMENT = 0, 1
 JOB_STATES = ["queued", "running", "done", "cancelled", "failed"]
@@ -84,6 +85,11 @@ def load():
     lib.bbc_footprint.argtypes = [P, I, I, P, P]
     lib.bbc_correlate.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
     lib.bbc_correlate_noalloc.argtypes = [P, P, I, P, P, I, P, I, I, P, I, P, P, P, P]
+    lib.bbc_tuning_get.argtypes = [P, P, I, I, P, I, P, P]
+    lib.bbc_tuning_set.argtypes = [P, P, I, I, P, I, P]
+    lib.bbc_autotune.argtypes = [P, P, I, P, P, I, P, I, I, P, P, P]
+    lib.bbc_tuning_save.argtypes = [P, ctypes.c_char_p]
+    lib.bbc_tuning_load.argtypes = [P, ctypes.c_char_p]
     lib.bbc_correlate_cpt.argtypes = [P, P, I, I, P, P, I, I, P, I, P, I, P, P, P, P]
     lib.bbc_profile_enable.argtypes = [P, I]
     lib.bbc_profile_read.argtypes = [P, I, P, P]
@@ -105,7 +111,8 @@ def load():
     for f in ("bbc_spin_project", "bbc_cubic_project", "bbc_central_potential", "bbc_channel_content", "bbc_source_terms", "bbc_diagram_table", "bbc_plan_stats", "bbc_pair_stats", "bbc_create",
               "bbc_footprint", "bbc_correlate", "bbc_correlate_noalloc", "bbc_profile_enable", "bbc_profile_read",
               "bbc_server_start", "bbc_server_stop", "bbc_prop_upload", "bbc_prop_release", "bbc_submit",
-              "bbc_poll", "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget"):
+              "bbc_poll", "bbc_wait", "bbc_cancel", "bbc_job_times", "bbc_job_forget", "bbc_tuning_get",
+              "bbc_tuning_set", "bbc_autotune", "bbc_tuning_save", "bbc_tuning_load"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -229,6 +236,10 @@ def footprint(lattice, channels, precision=F64) -> int:
     b = ctypes.c_uint64()
     _check(load().bbc_footprint(lat, precision, n, arr, ctypes.byref(b)))
     return b.value
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int32), ("blocks", ctypes.c_int32), ("planes", ctypes.c_int32)]
 
 
 class Context:
@@ -407,6 +418,56 @@ class Context:
             ctypes.c_void_p(scale.data_ptr()) if (prec == F32) else None,
             ctypes.c_void_p(stream.cuda_stream)))
         return (out, scale) if prec == F32 else out
+
+    # -- kernel variants of a request shape (bbc_tuning_*, bbc_autotune) ----------
+    def tuning(self, lattice, channels, precision=F64, spin=UPPER):
+        """Kernel variants of a request shape: (dict pairs/blocks/planes, tuned?)."""
+        lat, _ = _i32(lattice)
+        arr, n = _i32(channels)
+        t = _Tuning()
+        tuned = ctypes.c_int()
+        _check(self._lib.bbc_tuning_get(self._ptr, lat, int(precision), n, arr, int(spin), ctypes.byref(t),
+                                        ctypes.byref(tuned)))
+        return {"pairs": t.pairs, "blocks": t.blocks, "planes": t.planes}, bool(tuned.value)
+
+    def set_tuning(self, lattice, channels, tuning, precision=F64, spin=UPPER):
+        """Set the variants of a request shape (dict pairs/blocks/planes; None: built-in)."""
+        lat, _ = _i32(lattice)
+        arr, n = _i32(channels)
+        t = None
+        if tuning is not None:
+            t = ctypes.byref(_Tuning(int(tuning["pairs"]), int(tuning["blocks"]), int(tuning["planes"])))
+        _check(self._lib.bbc_tuning_set(self._ptr, lat, int(precision), n, arr, int(spin), t))
+
+    def autotune(self, S_light, S_strange, channels, spin=UPPER, reps=3, stream=None):
+        """Time the kernel variants on one device-resident slice ([Lz, Ly, Lx, 12, 12]) and keep
+        the fastest; returns (dict pairs/blocks/planes, ms per slice)."""
+        import torch
+
+        if S_light.shape != S_strange.shape or S_light.dtype != S_strange.dtype:
+            raise BBCError("S_light and S_strange must have the same shape and dtype")
+        prec = _prop_dtype(S_light.unsqueeze(0), "propagators")
+        dev = self._torch_device()
+        for name, s in (("S_light", S_light), ("S_strange", S_strange)):
+            if not s.is_cuda or s.device != dev or not s.is_contiguous():
+                raise BBCError("%s must be a contiguous tensor on cuda:%d" % (name, self.device))
+        Lz, Ly, Lx = S_light.shape[:3]
+        lat, _ = _i32([Lx, Ly, Lz])
+        arr, n = _i32(channels)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        t = _Tuning()
+        ms = ctypes.c_double()
+        _check(self._lib.bbc_autotune(self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()),
+                                      ctypes.c_void_p(S_strange.data_ptr()), n, arr, int(spin), int(reps),
+                                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(t), ctypes.byref(ms)))
+        return {"pairs": t.pairs, "blocks": t.blocks, "planes": t.planes}, ms.value
+
+    def save_tuning(self, path):
+        _check(self._lib.bbc_tuning_save(self._ptr, os.fsencode(path)))
+
+    def load_tuning(self, path):
+        _check(self._lib.bbc_tuning_load(self._ptr, os.fsencode(path)))
 
     def correlate_noalloc(self, S_light, S_strange, t_list, channels, out, scale=None, t0=0, spin=UPPER,
                           energy=None, stream=None):

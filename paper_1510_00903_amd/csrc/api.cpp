@@ -7,6 +7,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -51,8 +55,23 @@ struct DevPlan {
     size_t off_terms = 0, off_term_begin = 0, off_tasks = 0, off_comb = 0, off_comb_begin = 0, off_content = 0;
     void *d_image = nullptr;        // device copy, made by the entry points that allocate
     size_t table_bytes = 0;
+    // request key: channel list, spin offset, precision, and a hash of the list
+    std::vector<int> chans;
+    int spin_offset = 0, prec = 0;
+    uint64_t chash = 0;
     ~DevPlan() { (void)hipFree(d_image); }
 };
+
+// FNV-1a over the channel list (identifies a channel set in the tuning table).
+uint64_t channel_hash(const std::vector<int> &chans) {
+    uint64_t h = 1469598103934665603ull;
+    for (int c : chans)
+        for (int b = 0; b < 4; ++b) {
+            h ^= (uint64_t)((c >> (8 * b)) & 255);
+            h *= 1099511628211ull;
+        }
+    return h;
+}
 
 // Device pointers of one plan's tables, for an image copied to `base`.
 struct PlanDev {
@@ -85,12 +104,24 @@ long grouped_positions(long V, const int L[3], int G) {
     return (n + G - 1) / G * G;
 }
 
-// Momentum groups of G positions, each closed under q -> -q: the self-conjugate
-// momenta first, one padding slot if their number is odd, then the pairs
-// (q, -q) in increasing q (a pair starts at an even position, so never straddles
-// two groups), the last group padded.  Entry p: (momentum at position p, or -1
-// for padding; the lane within the group that holds -q).
-std::vector<int2> momentum_groups(const int L[3], int G) {
+// Lattices whose momentum groups come in x-row runs (square 24-, 32- and
+// 96-point planes: the forward FFT's last pass writes whole runs).
+bool run_ordered(const int L[3]) { return L[0] == L[1] && (L[0] == 24 || L[0] == 32 || L[0] == 96); }
+
+// Momentum groups of G positions, each closed under q -> -q.  Entry p: (momentum
+// at position p, or -1 for padding; the lane within the group that holds -q).
+//
+// Default order: the self-conjugate momenta first, one padding slot if their
+// number is odd, then the pairs (q, -q) in increasing q (a pair starts at an
+// even position, so never straddles two groups), the last group padded.
+//
+// Run order (run_ordered lattices; Lx a multiple of 8, Ly even): for each x-row
+// r = (ky, kz) whose mirror row m = (-ky, -kz) is not smaller, one run of whole
+// groups: r != m: the pairs ((kx, r), (-kx, m)) for kx = 0 .. Lx-1 (2 Lx
+// positions); r == m: (0, r) and (Lx/2, r) (self-conjugate), then the pairs
+// ((kx, r), (-kx, r)) for kx = 1 .. Lx/2-1 (Lx positions).  xrun (optional)
+// receives, for every x-row, the first group of the run that holds it.
+std::vector<int2> momentum_groups(const int L[3], int G, std::vector<int> *xrun = nullptr) {
     const int V = L[0] * L[1] * L[2];
     auto neg = [&](int q) {
         const int qx = q % L[0], qy = (q / L[0]) % L[1], qz = q / (L[0] * L[1]);
@@ -98,6 +129,35 @@ std::vector<int2> momentum_groups(const int L[3], int G) {
     };
     std::vector<int2> pos;
     auto lane = [&]() { return (int)(pos.size() % G); };
+    if (run_ordered(L)) {
+        const int Lx = L[0], Ly = L[1], Lz = L[2], nrow = Ly * Lz;
+        auto mrow = [&](int r) { return (Ly - r % Ly) % Ly + Ly * ((Lz - r / Ly) % Lz); };
+        if (xrun) xrun->assign(nrow, -1);
+        for (int r = 0; r < nrow; ++r) {
+            const int m = mrow(r);
+            if (m < r) continue;
+            if (pos.size() % G) throw std::logic_error("x-row run not aligned to a group");
+            if (xrun) (*xrun)[r] = (*xrun)[m] = (int)(pos.size() / G);
+            const int b = Lx * r, mb = Lx * m;
+            if (m == r) {
+                pos.push_back(make_int2(b, lane()));
+                pos.push_back(make_int2(b + Lx / 2, lane()));
+                for (int kx = 1; kx < Lx / 2; ++kx) {
+                    const int l = lane();
+                    pos.push_back(make_int2(b + kx, l + 1));
+                    pos.push_back(make_int2(b + Lx - kx, l));
+                }
+            } else {
+                for (int kx = 0; kx < Lx; ++kx) {
+                    const int l = lane();
+                    pos.push_back(make_int2(b + kx, l + 1));
+                    pos.push_back(make_int2(mb + (Lx - kx) % Lx, l));
+                }
+            }
+        }
+        if ((long)pos.size() != V) throw std::logic_error("x-row runs do not cover the lattice");
+        return pos;
+    }
     for (int q = 0; q < V; ++q)
         if (neg(q) == q) pos.push_back(make_int2(q, lane()));
     if (pos.size() & 1) pos.push_back(make_int2(-1, lane()));
@@ -212,6 +272,12 @@ struct bbc_context {
     bool graph_mode = false;
     hipStream_t gs = nullptr;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    // kernel variants per request shape (lattice, precision, spin offset, channel
+    // hash), set by bbc_tuning_set / bbc_autotune / a tuning file; tune_path: the
+    // file bbc_autotune rewrites (from BBC_TUNING_CACHE)
+    std::mutex tmu;
+    std::map<std::array<uint64_t, 6>, bbc::Tuning> tuning;
+    std::string tune_path;
     void clear_graphs() {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
@@ -297,6 +363,10 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         } catch (const std::exception &e) {
             return fail(BBC_EINVAL, std::string("planner: ") + e.what());
         }
+        dp->chans = chans;
+        dp->spin_offset = spin_offset;
+        dp->prec = (int)prec;
+        dp->chash = channel_hash(chans);
         const bbc::Plan &P = dp->plan;
         // pattern runs of the component layout (components are sorted by pattern id)
         dp->pats.n = 0;
@@ -411,27 +481,33 @@ bbc_status check_lattice(const int32_t *lattice, long *V) {
 struct MomGroups {
     const int2 *pos = nullptr;
     const int *posof = nullptr;   // momentum -> position (V entries)
+    const int *xrun = nullptr;    // run-ordered lattices: x-row -> first group of its run (Ly Lz entries)
     int ngroup = 0;
 };
 constexpr int kGroupSize = 8;                    // momenta per group
 
 // Host image of the momentum groups of a lattice: the npos position entries,
-// then the V momentum -> position entries (as ints, two per int2).
+// then the V momentum -> position entries and, for run-ordered lattices, the
+// Ly Lz x-row -> run entries (as ints, two per int2).
 std::vector<int2> group_image(const int L[3], long *npos_out) {
     const long V = (long)L[0] * L[1] * L[2];
     const long npos = grouped_positions(V, L, kGroupSize);
-    std::vector<int2> g = momentum_groups(L, kGroupSize);
+    std::vector<int> xrun;
+    std::vector<int2> g = momentum_groups(L, kGroupSize, &xrun);
     std::vector<int2> all(g);
-    all.resize(npos + (V + 1) / 2);
+    all.resize(npos + (V + (long)xrun.size() + 1) / 2);
     int *posof = reinterpret_cast<int *>(all.data() + npos);
     for (long p = 0; p < npos; ++p)
         if (g[p].x >= 0) posof[g[p].x] = (int)p;
+    std::copy(xrun.begin(), xrun.end(), posof + V);
     *npos_out = npos;
     return all;
 }
 
-MomGroups groups_at(const int2 *base, long npos) {
-    return MomGroups{base, reinterpret_cast<const int *>(base + npos), (int)(npos / kGroupSize)};
+MomGroups groups_at(const int2 *base, long npos, const int L[3]) {
+    const int *posof = reinterpret_cast<const int *>(base + npos);
+    const long V = (long)L[0] * L[1] * L[2];
+    return MomGroups{base, posof, run_ordered(L) ? posof + V : nullptr, (int)(npos / kGroupSize)};
 }
 
 template <typename T>
@@ -453,18 +529,41 @@ MomGroups get_groups(bbc_context *ctx, const int L[3], bbc_status *st) {
         npos = grouped_positions((long)L[0] * L[1] * L[2], L, kGroupSize);
     }
     *st = BBC_OK;
-    return groups_at(it->second, npos);
+    return groups_at(it->second, npos, L);
+}
+
+using TuneKey = std::array<uint64_t, 6>;
+TuneKey tune_key(const int L[3], int prec, int spin_offset, uint64_t chash) {
+    return TuneKey{(uint64_t)L[0], (uint64_t)L[1], (uint64_t)L[2], (uint64_t)prec, (uint64_t)spin_offset, chash};
+}
+
+// Built-in choice for shapes without a tuning entry (the fastest variants
+// measured at 16^3 and 32^3 with 52 channels): FP32 takes the pipelined
+// contraction, 4 x 4 block workgroups and half-size plane-pass workgroups.
+bbc::Tuning default_tuning(const int L[3], int prec) {
+    (void)L;
+    if (prec == BBC_F32) return bbc::Tuning{1, 1, 1};
+    return bbc::Tuning{0, 0, 0};
+}
+
+// Tuning of a request: the context's entry for its shape, else the built-in choice.
+bbc::Tuning tuning_for(bbc_context *ctx, const int L[3], const DevPlan *dp) {
+    std::lock_guard<std::mutex> lock(ctx->tmu);
+    auto it = ctx->tuning.find(tune_key(L, dp->prec, dp->spin_offset, dp->chash));
+    return it != ctx->tuning.end() ? it->second : default_tuning(L, dp->prec);
 }
 
 // Launches the kernel sequence of one time slice on stream st, using the
 // workspace ws (layout of workspace_bytes).  Stage events are recorded only
-// for the direct (profiled) path.
+// for the direct (profiled) path.  force: kernel variants to use instead of
+// the request's tuning (the autotuner's candidates).
 template <typename T>
 bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], long V, void *ws, const MomGroups &mg,
                          const void *slp, const void *ssp, int n_ch, const double *d_energy, double dt, void *outp,
-                         double *scale, hipStream_t st, bool timed) {
+                         double *scale, hipStream_t st, bool timed, const bbc::Tuning *force = nullptr) {
     using T2 = typename bbc::cplx_t<T>::type;
     const DevPlan *dp = pd.dp;
+    const bbc::Tuning tu = force ? *force : tuning_for(ctx, L, dp);
     const bbc::Plan &P = dp->plan;
     const int nc = P.ncomp;
     const WsLayout lay = ws_layout(V, nc, n_ch, dp->npair, sizeof(T2));
@@ -482,7 +581,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
         StageTimer tm(pc, st, 0);
         if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
         bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, pd.terms, pd.term_begin, dp->pats,
-                              fp32 ? kmax : nullptr, st);
+                              fp32 ? kmax : nullptr, tu.blocks, st);
     }
     // small cubic lattices: one fused pass (FFT in LDS, written straight into the
     // groups); 24- and 32-point planes: plane passes, then the z pass writes into
@@ -495,7 +594,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
             if (bbc::launch_fft3d_grouped<T>(I, Iq, nc, L, mg.ngroup, mg.pos, st))
                 return fail(BBC_EUNSUPPORTED, "FFT size");
         } else if (zgrouped) {
-            if ((tm.nk = bbc::launch_fft3d_zgrouped<T>(I, Iq, nc, L, mg.posof, st)) < 0)
+            if ((tm.nk = bbc::launch_fft3d_zgrouped<T>(I, Iq, nc, L, mg.posof, mg.xrun, tu.planes, st)) < 0)
                 return fail(BBC_EUNSUPPORTED, "FFT size");
         } else if ((tm.nk = bbc::launch_fft3d<T>(I, 2L * nc, L, -1, st)) < 0) {
             return fail(BBC_EUNSUPPORTED, "FFT size");
@@ -507,7 +606,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     }
     {
         StageTimer tm(pc, st, 3);
-        bbc::launch_pairs<T>(Iq, Pp, nc, tb, st);
+        bbc::launch_pairs<T>(Iq, Pp, nc, tb, tu.pairs, st);
     }
     {
         StageTimer tm(pc, st, 6);
@@ -985,6 +1084,10 @@ bbc_status scratch_address(int device, void **out) {
 }
 }  // namespace
 
+namespace {
+bbc_status load_tuning(bbc_context *ctx, const std::string &path);
+}
+
 extern "C" {
 
 int bbc_num_channels(void) { return bbc::kNumChannels; }
@@ -1105,6 +1208,16 @@ bbc_status bbc_create(int device, uint64_t budget, bbc_context **out) {
     c->device = device;
     c->budget = budget;
     c->scratch = scr;
+    // tuning file: loaded if present, rewritten by bbc_autotune
+    if (const char *tp = std::getenv("BBC_TUNING_CACHE")) {
+        if (*tp) {
+            c->tune_path = tp;
+            if (std::ifstream(tp).good()) {
+                bbc_status ts = load_tuning(c, tp);
+                if (ts) { delete c; return ts; }
+            }
+        }
+    }
     *out = c;
     return BBC_OK;
 }
@@ -1232,7 +1345,7 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
                                st));
     }
     const PlanDev pd = plan_dev(dp, sc);
-    const MomGroups mg = groups_at((const int2 *)(sc + off_grp), npos);
+    const MomGroups mg = groups_at((const int2 *)(sc + off_grp), npos, L);
     const double *d_en = energy ? (const double *)(sc + off_en) : nullptr;
     const size_t in_slice = (size_t)V * 144, out_slice = (size_t)n_ch * V * 16;
     for (int n = 0; n < n_t; ++n) {
@@ -1657,6 +1770,275 @@ bbc_status bbc_central_potential(bbc_context *ctx, const int32_t lattice[3], int
                                   (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return BBC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Kernel variants per request shape, and the autotuner.
+// ---------------------------------------------------------------------------
+namespace {
+
+bool tuning_valid(const bbc_tuning &t, bbc_precision prec) {
+    const int np = prec == BBC_F64 ? bbc::kPairVariants64 : bbc::kPairVariants32;
+    return t.pairs >= 0 && t.pairs < np && t.blocks >= 0 && t.blocks < bbc::kBlockVariants && t.planes >= 0 &&
+           t.planes < bbc::kPlaneVariants;
+}
+
+bbc_status check_request(const int32_t lattice[3], bbc_precision prec, int n_ch, const int32_t *ch_list,
+                         bbc_spin spin, long *V) {
+    bbc_status s = check_lattice(lattice, V);
+    if (s) return s;
+    if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
+    if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
+    if (n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list");
+    for (int i = 0; i < n_ch; ++i)
+        if (!bbc::channel_valid(ch_list[i]))
+            return fail(BBC_EINVAL, "channel index " + std::to_string(ch_list[i]) + " out of range");
+    return BBC_OK;
+}
+
+TuneKey request_key(const int32_t lattice[3], bbc_precision prec, int n_ch, const int32_t *ch_list, bbc_spin spin) {
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    return tune_key(L, (int)prec, spin == BBC_SPIN_LOWER ? 2 : 0,
+                    channel_hash(std::vector<int>(ch_list, ch_list + n_ch)));
+}
+
+// Tuning file: one JSON object, {"bbc_tuning": 1, "entries": [...]}, each entry
+// {"lattice": [Lx, Ly, Lz], "precision": 0|1, "spin_offset": 0|2,
+//  "channel_hash": "<16 hex digits>", "pairs": p, "blocks": b, "planes": l}.
+std::string tuning_json(const std::map<TuneKey, bbc::Tuning> &m) {
+    std::ostringstream o;
+    o << "{\"bbc_tuning\": 1, \"entries\": [";
+    bool first = true;
+    for (const auto &kv : m) {
+        char hx[17];
+        std::snprintf(hx, sizeof hx, "%016llx", (unsigned long long)kv.first[5]);
+        o << (first ? "\n " : ",\n ") << "{\"lattice\": [" << kv.first[0] << ", " << kv.first[1] << ", "
+          << kv.first[2] << "], \"precision\": " << kv.first[3] << ", \"spin_offset\": " << kv.first[4]
+          << ", \"channel_hash\": \"" << hx << "\", \"pairs\": " << kv.second.pairs << ", \"blocks\": "
+          << kv.second.blocks << ", \"planes\": " << kv.second.planes << "}";
+        first = false;
+    }
+    o << "\n]}\n";
+    return o.str();
+}
+
+// Integer value of "key": in text[from, to), or false.
+bool json_int(const std::string &text, size_t from, size_t to, const char *key, long long *v) {
+    const std::string k = std::string("\"") + key + "\":";
+    size_t p = text.find(k, from);
+    if (p == std::string::npos || p >= to) return false;
+    p += k.size();
+    while (p < to && text[p] == ' ') ++p;
+    char *end = nullptr;
+    *v = std::strtoll(text.c_str() + p, &end, 10);
+    return end != text.c_str() + p;
+}
+
+bbc_status parse_tuning(const std::string &text, std::map<TuneKey, bbc::Tuning> *out) {
+    if (text.find("\"bbc_tuning\": 1") == std::string::npos) return fail(BBC_EINVAL, "not a tuning file");
+    size_t p = 0;
+    while ((p = text.find("{\"lattice\": [", p)) != std::string::npos) {
+        const size_t e = text.find('}', p);
+        if (e == std::string::npos) return fail(BBC_EINVAL, "tuning file: unterminated entry");
+        int L[3];
+        if (std::sscanf(text.c_str() + p, "{\"lattice\": [%d, %d, %d]", &L[0], &L[1], &L[2]) != 3)
+            return fail(BBC_EINVAL, "tuning file: lattice");
+        long long prec, spin, pr, bl, pl;
+        if (!json_int(text, p, e, "precision", &prec) || !json_int(text, p, e, "spin_offset", &spin) ||
+            !json_int(text, p, e, "pairs", &pr) || !json_int(text, p, e, "blocks", &bl) ||
+            !json_int(text, p, e, "planes", &pl))
+            return fail(BBC_EINVAL, "tuning file: missing field");
+        const size_t h = text.find("\"channel_hash\": \"", p);
+        if (h == std::string::npos || h > e) return fail(BBC_EINVAL, "tuning file: channel_hash");
+        const uint64_t hash = std::strtoull(text.c_str() + h + 17, nullptr, 16);
+        bbc_tuning t{(int32_t)pr, (int32_t)bl, (int32_t)pl};
+        if ((prec != 0 && prec != 1) || (spin != 0 && spin != 2) || !tuning_valid(t, (bbc_precision)prec))
+            return fail(BBC_EINVAL, "tuning file: value out of range");
+        (*out)[tune_key(L, (int)prec, (int)spin, hash)] = bbc::Tuning{t.pairs, t.blocks, t.planes};
+        p = e + 1;
+    }
+    return BBC_OK;
+}
+
+bbc_status save_tuning(bbc_context *ctx, const std::string &path) {
+    std::string text;
+    {
+        std::lock_guard<std::mutex> lock(ctx->tmu);
+        text = tuning_json(ctx->tuning);
+    }
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return fail(BBC_EINVAL, "cannot write " + tmp);
+        f << text;
+        if (!f) return fail(BBC_EINVAL, "write failed: " + tmp);
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) return fail(BBC_EINVAL, "cannot replace " + path);
+    return BBC_OK;
+}
+
+bbc_status load_tuning(bbc_context *ctx, const std::string &path) {
+    std::ifstream f(path);
+    if (!f) return fail(BBC_EINVAL, "cannot read " + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    std::map<TuneKey, bbc::Tuning> m;
+    bbc_status s = parse_tuning(ss.str(), &m);
+    if (s) return s;
+    std::lock_guard<std::mutex> lock(ctx->tmu);
+    for (const auto &kv : m) ctx->tuning[kv.first] = kv.second;
+    return BBC_OK;
+}
+
+// Device time of `reps` slices with the variants `tu` (one untimed slice first).
+template <typename T>
+bbc_status time_variant(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const MomGroups &mg,
+                        const void *sl, const void *ss, int n_ch, void *out, double *scale, int reps,
+                        const bbc::Tuning &tu, hipStream_t st, hipEvent_t a, hipEvent_t b, float *ms) {
+    const PlanDev pd = plan_dev(dp, dp->d_image);
+    bbc_status s = enqueue_slice<T>(ctx, pd, L, V, ctx->ws, mg, sl, ss, n_ch, nullptr, 0.0, out, scale, st, false, &tu);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(a, st));
+    for (int r = 0; r < reps && s == BBC_OK; ++r)
+        s = enqueue_slice<T>(ctx, pd, L, V, ctx->ws, mg, sl, ss, n_ch, nullptr, 0.0, out, scale, st, false, &tu);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(b, st));
+    HIP_TRY(hipEventSynchronize(b));
+    float e = 0.f;
+    HIP_TRY(hipEventElapsedTime(&e, a, b));
+    *ms = e / (float)reps;
+    return BBC_OK;
+}
+
+template <typename T>
+bbc_status autotune(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const void *sl, const void *ss, int n_ch,
+                    int reps, hipStream_t st, bbc::Tuning *best, float *best_ms) {
+    using T2 = typename bbc::cplx_t<T>::type;
+    bbc_status s = ensure_workspace(ctx, workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, sizeof(T2)));
+    if (s) return s;
+    const MomGroups mg = get_groups<T>(ctx, L, &s);
+    if (!mg.pos) return s;
+    void *out = nullptr;
+    double *scale = nullptr;
+    const size_t ob = (size_t)n_ch * 16 * V * sizeof(T2);
+    if (hipMalloc(&out, ob) != hipSuccess) return fail(BBC_ENOMEM, "autotune output buffer");
+    if (hipMalloc((void **)&scale, sizeof(double) * n_ch) != hipSuccess) {
+        (void)hipFree(out);
+        return fail(BBC_ENOMEM, "autotune scale buffer");
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    // coordinate search from the current choice: the pair-product kernel, then the
+    // plane pass (only where the lattice takes one), then the block kernel
+    bbc::Tuning cur = tuning_for(ctx, L, dp);
+    float cur_ms = 0.f;
+    s = time_variant<T>(ctx, dp, L, V, mg, sl, ss, n_ch, out, scale, reps, cur, st, a, b, &cur_ms);
+    const bool planes = bbc::fft3d_zgrouped_fits<T>(L) && !bbc::fft3d_grouped_fits<T>(L);
+    const int npv = sizeof(T) == 8 ? bbc::kPairVariants64 : bbc::kPairVariants32;
+    for (int dim = 0; dim < 3 && s == BBC_OK; ++dim) {
+        const int n = dim == 0 ? npv : dim == 1 ? (planes ? bbc::kPlaneVariants : 1) : bbc::kBlockVariants;
+        for (int v = 0; v < n && s == BBC_OK; ++v) {
+            bbc::Tuning c = cur;
+            int &field = dim == 0 ? c.pairs : dim == 1 ? c.planes : c.blocks;
+            if (field == v) continue;
+            field = v;
+            float ms = 0.f;
+            s = time_variant<T>(ctx, dp, L, V, mg, sl, ss, n_ch, out, scale, reps, c, st, a, b, &ms);
+            if (s == BBC_OK && ms < cur_ms) { cur = c; cur_ms = ms; }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(out);
+    (void)hipFree(scale);
+    *best = cur;
+    *best_ms = cur_ms;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+bbc_status bbc_tuning_get(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_ch,
+                          const int32_t *ch_list, bbc_spin spin, bbc_tuning *out, int *tuned) {
+    if (!ctx || !out) return fail(BBC_EINVAL, "NULL argument");
+    long V;
+    bbc_status s = check_request(lattice, prec, n_ch, ch_list, spin, &V);
+    if (s) return s;
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    std::lock_guard<std::mutex> lock(ctx->tmu);
+    auto it = ctx->tuning.find(request_key(lattice, prec, n_ch, ch_list, spin));
+    const bbc::Tuning t = it != ctx->tuning.end() ? it->second : default_tuning(L, (int)prec);
+    *out = bbc_tuning{t.pairs, t.blocks, t.planes};
+    if (tuned) *tuned = it != ctx->tuning.end();
+    return BBC_OK;
+}
+
+bbc_status bbc_tuning_set(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, int n_ch,
+                          const int32_t *ch_list, bbc_spin spin, const bbc_tuning *t) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_request(lattice, prec, n_ch, ch_list, spin, &V);
+    if (s) return s;
+    const TuneKey key = request_key(lattice, prec, n_ch, ch_list, spin);
+    std::lock_guard<std::mutex> lock(ctx->tmu);
+    if (!t) {
+        ctx->tuning.erase(key);
+        return BBC_OK;
+    }
+    if (!tuning_valid(*t, prec)) return fail(BBC_EINVAL, "kernel variant out of range");
+    ctx->tuning[key] = bbc::Tuning{t->pairs, t->blocks, t->planes};
+    return BBC_OK;
+}
+
+bbc_status bbc_autotune(bbc_context *ctx, const int32_t lattice[3], bbc_precision prec, const void *S_light,
+                        const void *S_strange, int n_ch, const int32_t *ch_list, bbc_spin spin, int reps,
+                        void *stream, bbc_tuning *out, double *ms_per_slice) {
+    if (!ctx) return fail(BBC_EINVAL, "NULL context");
+    long V;
+    bbc_status s = check_request(lattice, prec, n_ch, ch_list, spin, &V);
+    if (s) return s;
+    if (reps < 1 || reps > 1000) return fail(BBC_EINVAL, "reps in [1, 1000]");
+    if (!S_light || !S_strange) return fail(BBC_EINVAL, "NULL buffer");
+    if (is_host_pointer(S_light) || is_host_pointer(S_strange))
+        return fail(BBC_EINVAL, "bbc_autotune takes one device-resident slice");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<int> chans(ch_list, ch_list + n_ch);
+    DevPlan *dp = nullptr;
+    if ((s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, prec, &dp))) return s;
+    const int L[3] = {lattice[0], lattice[1], lattice[2]};
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = order_after_last(ctx, st))) return s;
+    bbc::Tuning best;
+    float ms = 0.f;
+    if (prec == BBC_F64) s = autotune<double>(ctx, dp, L, V, S_light, S_strange, n_ch, reps, st, &best, &ms);
+    else s = autotune<float>(ctx, dp, L, V, S_light, S_strange, n_ch, reps, st, &best, &ms);
+    s = mark_last(ctx, st, s);
+    if (s) return s;
+    {
+        std::lock_guard<std::mutex> tl(ctx->tmu);
+        ctx->tuning[tune_key(L, (int)prec, dp->spin_offset, dp->chash)] = best;
+    }
+    if (out) *out = bbc_tuning{best.pairs, best.blocks, best.planes};
+    if (ms_per_slice) *ms_per_slice = ms;
+    if (!ctx->tune_path.empty()) return save_tuning(ctx, ctx->tune_path);
+    return BBC_OK;
+}
+
+bbc_status bbc_tuning_save(bbc_context *ctx, const char *path) {
+    if (!ctx || !path || !*path) return fail(BBC_EINVAL, "NULL argument");
+    return save_tuning(ctx, path);
+}
+
+bbc_status bbc_tuning_load(bbc_context *ctx, const char *path) {
+    if (!ctx || !path || !*path) return fail(BBC_EINVAL, "NULL argument");
+    return load_tuning(ctx, path);
 }
 
 }  // extern "C"

@@ -162,11 +162,10 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
     }
 }
 
-template <typename T>
-void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
-                   typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st) {
-    constexpr int TS = 4, NSPLIT = 2;
+template <typename T, int TS, int NSPLIT>
+static void launch_blocks_v(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
+                            typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
+                            const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st) {
     const long nsb = (V + TS - 1) / TS;
     const dim3 grid((unsigned)(8 * ((nsb + 7) / 8)), NSPLIT);
     if (pt.any_imag)      // some term carries a factor i (spin structures with imaginary entries)
@@ -175,6 +174,21 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
     else
         hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, false>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
                            term_begin, pt, kmax);
+}
+
+// Variants (each component of each site is formed by one thread in the same
+// order, so every variant gives the same bits): sites per workgroup x component
+// shares 0 = 4 x 2, 1 = 4 x 4, 2 = 8 x 2.
+template <typename T>
+void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
+                   typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
+                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, int variant,
+                   hipStream_t st) {
+    switch (variant) {
+    case 1: launch_blocks_v<T, 4, 4>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st); break;
+    case 2: launch_blocks_v<T, 8, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st); break;
+    default: launch_blocks_v<T, 4, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st); break;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -375,13 +389,22 @@ __global__ __launch_bounds__(256) void k_fft_xy(typename cplx_t<T>::type *__rest
     }
 }
 
-template <typename T, int N>
-static void fft_xy(typename cplx_t<T>::type *data, long nplanes, int sgn, hipStream_t st) {
+// Planes per workgroup: variant 0 fills up to 80 KB of LDS (one line per
+// thread at most), variant 1 takes half as many (smaller workgroups, more of
+// them per CU).  The transforms are the same either way.
+template <typename T, int N, int PV>
+static void fft_xy_v(typename cplx_t<T>::type *data, long nplanes, int sgn, hipStream_t st) {
     using T2 = typename cplx_t<T>::type;
     constexpr int PL = 81920 / (N * (N + 1) * (int)sizeof(T2));     // planes within 80 KB of LDS
-    constexpr int P = PL < 256 / N ? PL : 256 / N;
+    constexpr int P0 = PL < 256 / N ? PL : 256 / N;
+    constexpr int P = PV == 0 || P0 < 2 ? P0 : P0 / 2;
     hipLaunchKernelGGL((k_fft_xy<T, N, P>), dim3((unsigned)((nplanes + P - 1) / P)), dim3(256), 0, st, data, nplanes,
                        sgn);
+}
+template <typename T, int N>
+static void fft_xy(typename cplx_t<T>::type *data, long nplanes, int sgn, int variant, hipStream_t st) {
+    if (variant == 1) fft_xy_v<T, N, 1>(data, nplanes, sgn, st);
+    else fft_xy_v<T, N, 0>(data, nplanes, sgn, st);
 }
 
 // Square planes with a plane pass: 24 and 32 points; 96 points in FP32 (one
@@ -390,10 +413,11 @@ template <typename T> constexpr bool plane_pass_fits(int n) {
     return n == 24 || n == 32 || (n == 96 && sizeof(T) == 4);
 }
 template <typename T>
-static void plane_pass(typename cplx_t<T>::type *data, long nplanes, int n, int sgn, hipStream_t st) {
-    if (n == 24) fft_xy<T, 24>(data, nplanes, sgn, st);
-    else if (n == 32) fft_xy<T, 32>(data, nplanes, sgn, st);
-    else if constexpr (sizeof(T) == 4) fft_xy<T, 96>(data, nplanes, sgn, st);
+static void plane_pass(typename cplx_t<T>::type *data, long nplanes, int n, int sgn, hipStream_t st,
+                       int variant = 0) {
+    if (n == 24) fft_xy<T, 24>(data, nplanes, sgn, variant, st);
+    else if (n == 32) fft_xy<T, 32>(data, nplanes, sgn, variant, st);
+    else if constexpr (sizeof(T) == 4) fft_xy<T, 96>(data, nplanes, sgn, 0, st);
 }
 
 // Long lines (N = N1 * N2) along one axis, without holding a whole line per
@@ -796,6 +820,98 @@ __global__ __launch_bounds__(256) void k_fft_z_grouped(const typename cplx_t<T>:
     }
 }
 
+// Last (z) pass for square 24- and 32-point planes, writing whole x-row runs.
+// The momentum groups of these lattices come in runs (one per mirror pair of
+// x-rows {(ky, kz), (-ky, -kz)}, whole groups; xrun[ky + Ly kz] = first group of
+// the run), so the z lines of the y-row pair {w, Ly - w} (w = 0: {0, Ly/2}), all
+// kx and both sink spins hold every momentum of their runs: one workgroup per
+// (component, y-row pair) transforms those 4 Lx z lines (one per thread), keeps
+// them in LDS, then writes each run as whole group lines (the 2G values of a
+// (group, component) are contiguous), reading the LDS at the momentum each
+// output position holds:
+//   r != m: position 2 j -> (kx = j, row r), 2 j + 1 -> (kx = -j, row m);
+//   r == m: 0 -> kx = 0, 1 -> kx = Lx/2, 2 j -> kx = j, 2 j + 1 -> kx = -j (j >= 1).
+template <typename T, int LX, int N>
+__global__ __launch_bounds__(4 * LX) void k_fft_z_runs(const typename cplx_t<T>::type *__restrict__ in,
+                                                      typename cplx_t<T>::type *__restrict__ out, int nc,
+                                                      const int *__restrict__ xrun, int sgn) {
+    using T2 = typename cplx_t<T>::type;
+    using Ly_ = GroupLayout<T2>;
+    constexpr int G = Ly_::G, LY = LX, NXY = LX * LY, NT = 4 * LX;
+    __shared__ T2 buf[2][2][N][LX];               // [sink spin][row][kz][kx]
+    __shared__ T2 tw[N];
+    const int t = threadIdx.x;
+    constexpr int NW = LY / 2;                     // y-row pairs
+    const int c = blockIdx.x / NW, w = blockIdx.x - c * NW;
+    for (int i = t; i < N; i += NT) {
+        double sn, cs;
+        sincospi(2.0 * i / N, &sn, &cs);
+        tw[i] = T2{T(cs), T(sgn * sn)};
+    }
+    const int ky0 = w, ky1 = w == 0 ? LY / 2 : LY - w;
+    {
+        const int kx = t % LX, row = (t / LX) & 1, g = t / (2 * LX);
+        const T2 *src = in + ((long)g * nc + c) * (long)NXY * N + (row ? ky1 : ky0) * LX + kx;
+        T2 a[N], b[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] = src[(long)k * NXY];
+        __syncthreads();                           // twiddles
+        Stages<T2, N, 1>::run(a, b, tw, sgn);
+#pragma unroll
+        for (int k = 0; k < N; ++k) buf[g][row][k][kx] = a[k];
+    }
+    __syncthreads();
+    T2 *dst = out + (long)c * 2 * G;
+    for (int ri = 0; ri < 2; ++ri) {
+        const int ky = ri ? ky1 : ky0, kym = (LY - ky) % LY;
+        const int rim = kym == ky0 ? 0 : 1;        // row index of the mirror y-row
+        for (int kz = 0; kz < N; ++kz) {
+            const int kzm = (N - kz) % N;
+            const int r = ky + LY * kz, m = kym + LY * kzm;
+            if (m < r) continue;                   // written from the mirror row
+            const int g0 = xrun[r];
+            const bool self = m == r;
+            const int nval = (self ? LX : 2 * LX) * 2;
+            for (int v = t; v < nval; v += NT) {
+                const int s = v >> 1, gs = v & 1, j = s >> 1;
+                int x, rw = ri, z = kz;
+                if (self) {
+                    x = s == 0 ? 0 : s == 1 ? LX / 2 : ((s & 1) ? LX - j : j);
+                } else if (s & 1) {
+                    x = (LX - j) % LX; rw = rim; z = kzm;
+                } else {
+                    x = j;
+                }
+                dst[(long)(g0 + s / G) * nc * 2 * G + (s % G) * Ly_::S + gs * Ly_::SG] = buf[gs][rw][z][x];
+            }
+        }
+    }
+}
+
+template <typename T, int LX, int N>
+static void fft_z_runs(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int *xrun,
+                       hipStream_t st) {
+    const long nwg = (long)nc * (LX / 2);
+    hipLaunchKernelGGL((k_fft_z_runs<T, LX, N>), dim3((unsigned)nwg), dim3(4 * LX), 0, st, in, out, nc, xrun, -1);
+}
+
+template <typename T, int LX>
+static bool fft_z_runs_lz(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, int Lz,
+                          const int *xrun, hipStream_t st) {
+    switch (Lz) {
+    case 2: fft_z_runs<T, LX, 2>(in, out, nc, xrun, st); return true;
+    case 3: fft_z_runs<T, LX, 3>(in, out, nc, xrun, st); return true;
+    case 4: fft_z_runs<T, LX, 4>(in, out, nc, xrun, st); return true;
+    case 6: fft_z_runs<T, LX, 6>(in, out, nc, xrun, st); return true;
+    case 8: fft_z_runs<T, LX, 8>(in, out, nc, xrun, st); return true;
+    case 12: fft_z_runs<T, LX, 12>(in, out, nc, xrun, st); return true;
+    case 16: fft_z_runs<T, LX, 16>(in, out, nc, xrun, st); return true;
+    case 24: fft_z_runs<T, LX, 24>(in, out, nc, xrun, st); return true;
+    case 32: fft_z_runs<T, LX, 32>(in, out, nc, xrun, st); return true;
+    default: return false;
+    }
+}
+
 // Whether the plane pass + fused z pass applies: Lx = Ly in {24, 32}, Lz with a
 // register transform.
 template <typename T> bool fft3d_zgrouped_fits(const int L[3]) {
@@ -822,10 +938,14 @@ static void fft_z_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>
 // kernels launched, or -1 if the lattice does not fit this form.
 template <typename T>
 int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
-                          const int *posof, hipStream_t st) {
+                          const int *posof, const int *xrun, int plane_variant, hipStream_t st) {
     if (!fft3d_zgrouped_fits<T>(L)) return -1;
     const long ncomp = 2L * nc;
-    plane_pass<T>(in, ncomp * L[2], L[0], -1, st);
+    plane_pass<T>(in, ncomp * L[2], L[0], -1, st, plane_variant);
+    if (xrun && L[2] <= 32) {                      // run-ordered groups: whole runs per workgroup
+        if (L[0] == 24 && fft_z_runs_lz<T, 24>(in, out, nc, L[2], xrun, st)) return 2;
+        if (L[0] == 32 && fft_z_runs_lz<T, 32>(in, out, nc, L[2], xrun, st)) return 2;
+    }
     switch (L[2]) {
     case 2: fft_z_grouped<T, 2>(in, out, nc, L[0], L[1], posof, st); break;
     case 3: fft_z_grouped<T, 3>(in, out, nc, L[0], L[1], posof, st); break;
@@ -912,20 +1032,21 @@ struct LaneView {
 
 __device__ __forceinline__ int outer_stride(const PView &v, bool a_prime) { return a_prime ? v.so3 : v.so4; }
 
-// FP64: one task for one group of 8 momenta.
-template <int NP, int SHAPE>
+// FP64: one task for NS sets of 4 momenta of a group of 8 (sets set0 ..
+// set0 + NS - 1); PIPE: software-pipelined loads.
+template <int NP, int SHAPE, int NS, bool PIPE>
 __device__ __forceinline__ void pair_task64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
-                                            const PTask &T, int lane, const int mir[2]) {
+                                            const PTask &T, int lane, const int mir[2], int set0) {
     constexpr int H = SHAPE == 1 ? 2 : 1;
     constexpr int G = GroupLayout<double2>::G;
     constexpr int S = GroupLayout<double2>::S, SG = GroupLayout<double2>::SG;
     const int ij = lane & 3, blk = (lane >> 2) & 3, kl = lane >> 4;
     const int g = ij & 1, o = ij >> 1;
     // momentum slots of the row and column reads of this lane, per set
-    int srow[2], scol[2];
+    int srow[NS], scol[NS];
 #pragma unroll
-    for (int st = 0; st < 2; ++st) {
-        const int m = blk + 4 * st;
+    for (int st = 0; st < NS; ++st) {
+        const int m = blk + 4 * (set0 + st);
         srow[st] = T.row_site == 0 ? m : mir[st];
         scol[st] = T.row_site == 0 ? mir[st] : m;
     }
@@ -940,41 +1061,48 @@ __device__ __forceinline__ void pair_task64(const double2 *__restrict__ gb, doub
         else cbase[p] = T.col[p].base;
     }
     if (SHAPE == 1) colvalid = ij < 2;
-    double acc[NP][2][H][2];
+    double acc[NP][NS][H][2];
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int st = 0; st < 2; ++st)
+        for (int st = 0; st < NS; ++st)
 #pragma unroll
             for (int h = 0; h < H; ++h) acc[p][st][h][0] = acc[p][st][h][1] = 0.0;
     const int K = T.K;
-    for (int k0 = 0; k0 < K; k0 += 4) {
+    // Operands of one step of four k (lane kl takes k = k0 + kl): every lane loads
+    // (lanes past K read the in-range k = 0 entry and then take zeros, so no branch
+    // surrounds the loads).  Software-pipelined: the loads of step k0 + 4 are issued
+    // before the products of step k0, so each wave keeps a step of loads in flight.
+    auto load_step = [&](int k0, double2 (&av)[NS][H], double2 (&bv)[NP][NS]) {
         const int kk = k0 + kl;
         const bool valid = kk < K;
         const int k3 = valid ? (kk * T.inv) >> 16 : 0;
         const int k4 = valid ? kk - k3 * T.kd4 : 0;
-        double2 av[2][H];
         const int roff = rbase + k3 * T.row.sk3 + k4 * T.row.sk4;
 #pragma unroll
-        for (int st = 0; st < 2; ++st)
+        for (int st = 0; st < NS; ++st)
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-                av[st][h] = valid ? gb[(unsigned)(roff + h * rso4) * (2 * G) + srow[st] * S + g * SG]
-                                  : double2{0.0, 0.0};
-            }
-        double2 bv[NP][2];
+            for (int h = 0; h < H; ++h) av[st][h] = gb[(unsigned)(roff + h * rso4) * (2 * G) + srow[st] * S + g * SG];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int coff = cbase[p] + k3 * T.col[p].sk3 + k4 * T.col[p].sk4;
 #pragma unroll
-            for (int st = 0; st < 2; ++st)
-                bv[p][st] = (valid && colvalid) ? gb[(unsigned)coff * (2 * G) + scol[st] * S + g * SG]
-                                                : double2{0.0, 0.0};
+            for (int st = 0; st < NS; ++st) bv[p][st] = gb[(unsigned)coff * (2 * G) + scol[st] * S + g * SG];
         }
+        const bool zr = valid, zc = valid && colvalid;
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) av[st][h] = zr ? av[st][h] : double2{0.0, 0.0};
+#pragma unroll
+            for (int p = 0; p < NP; ++p) bv[p][st] = zc ? bv[p][st] : double2{0.0, 0.0};
+        }
+    };
+    auto mma_step = [&](const double2 (&av)[NS][H], const double2 (&bv)[NP][NS]) {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int st = 0; st < 2; ++st)
+            for (int st = 0; st < NS; ++st)
 #pragma unroll
                 for (int h = 0; h < H; ++h) {
                     const double2 a = av[st][h], b = bv[p][st];
@@ -986,6 +1114,24 @@ __device__ __forceinline__ void pair_task64(const double2 *__restrict__ gb, doub
                     acc[p][st][h][0] = re;
                     acc[p][st][h][1] = im;
                 }
+    };
+    if constexpr (PIPE) {
+        double2 av0[NS][H], bv0[NP][NS], av1[NS][H], bv1[NP][NS];
+        load_step(0, av0, bv0);
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            // a step past K reloads k = 0 (in range) and is never used
+            load_step(k0 + 4 < K ? k0 + 4 : 0, av1, bv1);
+            mma_step(av0, bv0);
+            if (k0 + 4 >= K) break;
+            load_step(k0 + 8 < K ? k0 + 8 : 0, av0, bv0);
+            mma_step(av1, bv1);
+        }
+    } else {
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            double2 av[NS][H], bv[NP][NS];
+            load_step(k0, av, bv);
+            mma_step(av, bv);
+        }
     }
     // D lane (j = lane & 3, block, i = lane >> 4)
     const int j = lane & 3, i = lane >> 4;
@@ -1002,7 +1148,7 @@ __device__ __forceinline__ void pair_task64(const double2 *__restrict__ gb, doub
         for (int p = 0; p < NP; ++p) {
             double2 *dst = pb + ((size_t)T.pair[p] * 16 + sp) * G;
 #pragma unroll
-            for (int st = 0; st < 2; ++st) dst[blk + 4 * st] = double2{acc[p][st][h][0], acc[p][st][h][1]};
+            for (int st = 0; st < NS; ++st) dst[blk + 4 * (set0 + st)] = double2{acc[p][st][h][0], acc[p][st][h][1]};
         }
     }
 }
@@ -1010,7 +1156,7 @@ __device__ __forceinline__ void pair_task64(const double2 *__restrict__ gb, doub
 // FP32: one task for two groups (16 momenta).  gb0/gb1 and pb0/pb1 are the
 // groups' data and outputs; lanes of a missing second group load zeros and
 // store nothing.
-template <int NP, int SHAPE>
+template <int NP, int SHAPE, bool PIPE>
 __device__ __forceinline__ void pair_task32(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
                                             float2 *__restrict__ pb0, float2 *__restrict__ pb1, bool has1,
                                             const PTask &T, int lane, int mir) {
@@ -1039,20 +1185,26 @@ __device__ __forceinline__ void pair_task32(const float2 *__restrict__ gb0, cons
 #pragma unroll
         for (int h = 0; h < H; ++h) acc[p][h][0] = acc[p][h][1] = fmfma4{0.f, 0.f, 0.f, 0.f};
     const int K = T.K;
-    for (int kk = 0; kk < K; ++kk) {
+    // Operands of one k: every lane loads (lanes of a missing second group read
+    // the first), then inactive lanes take zeros.  Software-pipelined as in the
+    // FP64 form: the loads of k + 1 are issued before the products of k.
+    auto load_step = [&](int kk, float2 (&av)[H], float2 (&bv)[NP]) {
         const int k3 = (kk * T.inv) >> 16;
         const int k4 = kk - k3 * T.kd4;
-        float2 av[H];
         const int roff = rbase + k3 * T.row.sk3 + k4 * T.row.sk4;
 #pragma unroll
-        for (int h = 0; h < H; ++h)
-            av[h] = active ? gb[(unsigned)(roff + h * rso4) * (2 * G) + srow * S + g * SG] : float2{0.f, 0.f};
-        float2 bv[NP];
+        for (int h = 0; h < H; ++h) av[h] = gb[(unsigned)(roff + h * rso4) * (2 * G) + srow * S + g * SG];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const int coff = cbase[p] + k3 * T.col[p].sk3 + k4 * T.col[p].sk4;
-            bv[p] = colvalid ? gb[(unsigned)coff * (2 * G) + scol * S + g * SG] : float2{0.f, 0.f};
+            bv[p] = gb[(unsigned)coff * (2 * G) + scol * S + g * SG];
         }
+#pragma unroll
+        for (int h = 0; h < H; ++h) av[h] = active ? av[h] : float2{0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bv[p] = colvalid ? bv[p] : float2{0.f, 0.f};
+    };
+    auto mma_step = [&](const float2 (&av)[H], const float2 (&bv)[NP]) {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1066,6 +1218,24 @@ __device__ __forceinline__ void pair_task32(const float2 *__restrict__ gb0, cons
                 acc[p][h][0] = re;
                 acc[p][h][1] = im;
             }
+    };
+    if constexpr (PIPE) {
+        float2 av0[H], bv0[NP], av1[H], bv1[NP];
+        load_step(0, av0, bv0);
+        for (int kk = 0; kk < K; kk += 2) {
+            // a step past K reloads k = 0 (in range) and is never used
+            load_step(kk + 1 < K ? kk + 1 : 0, av1, bv1);
+            mma_step(av0, bv0);
+            if (kk + 1 >= K) break;
+            load_step(kk + 2 < K ? kk + 2 : 0, av0, bv0);
+            mma_step(av1, bv1);
+        }
+    } else {
+        for (int kk = 0; kk < K; ++kk) {
+            float2 av[H], bv[NP];
+            load_step(kk, av, bv);
+            mma_step(av, bv);
+        }
     }
     // D lane (j = lane & 3, block), register i
     const int j = lane & 3;
@@ -1089,31 +1259,39 @@ __device__ __forceinline__ void pair_task32(const float2 *__restrict__ gb0, cons
     }
 }
 
-template <typename T, int SHAPE, int NP>
+template <typename T, int SHAPE, int NP, int NS, bool PIPE>
 __device__ __forceinline__ void pair_dispatch_np(const typename cplx_t<T>::type *g0, const typename cplx_t<T>::type *g1,
                                                  typename cplx_t<T>::type *p0, typename cplx_t<T>::type *p1,
-                                                 bool has1, const PTask &Tk, int lane, const int mir[2]) {
-    if constexpr (sizeof(T) == 8) pair_task64<NP, SHAPE>(g0, p0, Tk, lane, mir);
-    else pair_task32<NP, SHAPE>(g0, g1, p0, p1, has1, Tk, lane, mir[0]);
+                                                 bool has1, const PTask &Tk, int lane, const int mir[2], int set0) {
+    if constexpr (sizeof(T) == 8) pair_task64<NP, SHAPE, NS, PIPE>(g0, p0, Tk, lane, mir, set0);
+    else pair_task32<NP, SHAPE, PIPE>(g0, g1, p0, p1, has1, Tk, lane, mir[0]);
 }
 
-template <typename T>
+// One wave per (task, momentum part) of a momentum unit: FP64 units are one
+// group, a wave takes NS of its two sets of 4 momenta (NS = 2: the whole group);
+// FP32 units are two groups, a wave takes both.  Workgroups of 4 waves; the
+// workgroups of a unit are consecutive on one XCD.
+template <typename T, int NS, bool PIPE>
 __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *__restrict__ Iq,
                                                typename cplx_t<T>::type *__restrict__ P, int nc, int ubase,
                                                int ucount, const int2 *__restrict__ gpos, int ngroup,
                                                const PTask *__restrict__ tasks, int ntask, int npair) {
     using T2 = typename cplx_t<T>::type;
     constexpr int G = GroupLayout<T2>::G;
-    constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;        // groups per unit (per wave)
-    const int nchunk = (ntask + 3) >> 2;
+    constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;        // groups per unit
+    constexpr int PARTS = sizeof(T) == 8 ? 2 / NS : 1;  // waves per task
+    const int nitem = ntask * PARTS;
+    const int nchunk = (nitem + 3) >> 2;
     const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
     const int P8 = (ucount + 7) >> 3;
     const int ul = xcd * P8 + jj / nchunk;
     const int chunk = jj - (jj / nchunk) * nchunk;
     if (ul >= ucount) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = chunk * 4 + wave;
-    if (t >= ntask) return;
+    const int item = chunk * 4 + wave;
+    if (item >= nitem) return;
+    const int t = PARTS == 1 ? item : item / PARTS;
+    const int set0 = PARTS == 1 ? 0 : item - t * PARTS;
     const int lane = threadIdx.x & 63;
     const int unit = ubase + ul;
     const int grp0 = unit * GPU_;
@@ -1125,8 +1303,8 @@ __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *_
     int mir[2];
     if constexpr (sizeof(T) == 8) {
         const int blk = (lane >> 2) & 3;
-        mir[0] = gpos[(size_t)grp0 * G + blk].y;
-        mir[1] = gpos[(size_t)grp0 * G + blk + 4].y;
+        mir[0] = gpos[(size_t)grp0 * G + blk + 4 * set0].y;
+        mir[1] = NS == 2 ? gpos[(size_t)grp0 * G + blk + 4].y : 0;
     } else {
         const int blk = lane >> 2;
         const int gg = (blk >= 8 && has1) ? grp0 + 1 : grp0;
@@ -1137,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *_
     const int np = __builtin_amdgcn_readfirstlane(Tk.np);
     const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
 #define BBC_PAIR_CASE(SH, N) \
-    case N: pair_dispatch_np<T, SH, N>(g0, g1, p0, p1, has1, Tk, lane, mir); break;
+    case N: pair_dispatch_np<T, SH, N, NS, PIPE>(g0, g1, p0, p1, has1, Tk, lane, mir, set0); break;
     if (shape == 0) {
         switch (np) {
             BBC_PAIR_CASE(0, 1) BBC_PAIR_CASE(0, 2) BBC_PAIR_CASE(0, 3) BBC_PAIR_CASE(0, 4)
@@ -1209,12 +1387,13 @@ __global__ __launch_bounds__(1024) void k_pair_combine(const typename cplx_t<T>:
     }
 }
 
-template <typename T>
-void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
-                  hipStream_t st) {
+template <typename T, int NS, bool PIPE>
+static void launch_pairs_v(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
+                           const PairDevTables &tb, hipStream_t st) {
     constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;
+    constexpr int PARTS = sizeof(T) == 8 ? 2 / NS : 1;
     const int nunit = (tb.ngroup + GPU_ - 1) / GPU_;
-    const long nchunk = (tb.ntask + 3) / 4;
+    const long nchunk = ((long)tb.ntask * PARTS + 3) / 4;
     if (nchunk == 0) return;
     // units per launch: below 2^32 work-items per dispatch
     const long max_wg = (1L << 32) / 256 - 64;
@@ -1222,8 +1401,27 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
     for (int u0 = 0; u0 < nunit; u0 += per) {
         const int uc = std::min(per, nunit - u0);
         const long nwg = 8L * ((uc + 7) / 8) * nchunk;
-        hipLaunchKernelGGL((k_pairs<T>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+        hipLaunchKernelGGL((k_pairs<T, NS, PIPE>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
                            tb.ngroup, tb.tasks, tb.ntask, tb.npair);
+    }
+}
+
+// Variants (same products in the same order, so the same bits): FP64 0 = whole
+// group per wave, 1 = whole group, pipelined, 2 = half group, 3 = half group,
+// pipelined; FP32 0 = plain, 1 = pipelined.
+template <typename T>
+void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
+                  int variant, hipStream_t st) {
+    if constexpr (sizeof(T) == 8) {
+        switch (variant) {
+        case 1: launch_pairs_v<T, 2, true>(Iq, P, nc, tb, st); break;
+        case 2: launch_pairs_v<T, 1, false>(Iq, P, nc, tb, st); break;
+        case 3: launch_pairs_v<T, 1, true>(Iq, P, nc, tb, st); break;
+        default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
+        }
+    } else {
+        if (variant == 1) launch_pairs_v<T, 2, true>(Iq, P, nc, tb, st);
+        else launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st);
     }
 }
 
@@ -1310,12 +1508,14 @@ void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::typ
 
 // explicit instantiations
 template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
-                                    const int32_t *, const BlockPatterns &, const uint32_t *, hipStream_t);
+                                    const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t);
 template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
-                                   const int32_t *, const BlockPatterns &, const uint32_t *, hipStream_t);
+                                   const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
-template int launch_fft3d_zgrouped<double>(double2 *, double2 *, int, const int[3], const int *, hipStream_t);
-template int launch_fft3d_zgrouped<float>(float2 *, float2 *, int, const int[3], const int *, hipStream_t);
+template int launch_fft3d_zgrouped<double>(double2 *, double2 *, int, const int[3], const int *, const int *, int,
+                                            hipStream_t);
+template int launch_fft3d_zgrouped<float>(float2 *, float2 *, int, const int[3], const int *, const int *, int,
+                                           hipStream_t);
 template bool fft3d_zgrouped_fits<double>(const int[3]);
 template bool fft3d_zgrouped_fits<float>(const int[3]);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
@@ -1327,8 +1527,8 @@ template bool fft3d_grouped_fits<float>(const int[3]);
 template int launch_fft3d_grouped<double>(const double2 *, double2 *, int, const int[3], int, const int2 *,
                                           hipStream_t);
 template int launch_fft3d_grouped<float>(const float2 *, float2 *, int, const int[3], int, const int2 *, hipStream_t);
-template void launch_pairs<double>(const double2 *, double2 *, int, const PairDevTables &, hipStream_t);
-template void launch_pairs<float>(const float2 *, float2 *, int, const PairDevTables &, hipStream_t);
+template void launch_pairs<double>(const double2 *, double2 *, int, const PairDevTables &, int, hipStream_t);
+template void launch_pairs<float>(const float2 *, float2 *, int, const PairDevTables &, int, hipStream_t);
 template void launch_pair_combine<double>(const double2 *, double2 *, int, long, const PairDevTables &, hipStream_t);
 template void launch_pair_combine<float>(const float2 *, float2 *, int, long, const PairDevTables &, hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,

@@ -51,7 +51,19 @@ struct BlockPatterns {
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st);
+                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, int variant,
+                   hipStream_t st);
+
+// Kernel variants of one request shape (every variant forms the same values in
+// the same order, so the results are the same bits; only speed differs):
+//   pairs  - pair-product kernel: FP64 0 = whole group per wave, 1 = pipelined,
+//            2 = half group per wave, 3 = half group, pipelined; FP32 0, 1 = pipelined;
+//   blocks - block kernel sites per workgroup x component shares: 0 = 4x2, 1 = 4x4, 2 = 8x2;
+//   planes - plane-pass FFT planes per workgroup: 0 = as many as 80 KB of LDS hold, 1 = half.
+struct Tuning {
+    int pairs = 0, blocks = 0, planes = 0;
+};
+constexpr int kPairVariants64 = 4, kPairVariants32 = 2, kBlockVariants = 3, kPlaneVariants = 2;
 
 // FP32 form: per-flavour max |Re|,|Im| of a slice into kmax[0] (light), kmax[1] (strange).
 void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st);
@@ -60,11 +72,12 @@ template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sign, hipStream_t st);
 // Forward FFT of the 2 nc intermediates (in place in `in` for x and y) with the z
 // pass writing straight into the momentum groups of `out`; posof[q] = position
-// of momentum q.  Returns kernels launched, -1 if the lattice does not fit.
+// of momentum q; xrun (run-ordered groups, else NULL) = first group of each
+// x-row's run.  Returns kernels launched, -1 if the lattice does not fit.
 template <typename T> bool fft3d_zgrouped_fits(const int L[3]);
 template <typename T>
 int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
-                          const int *posof, hipStream_t st);
+                          const int *posof, const int *xrun, int plane_variant, hipStream_t st);
 
 // Momentum-grouped copy: in [g][nc][V] (component-major) -> out, per group of G
 // = 8 momenta and component, the G momenta and both sink spins ([c][G][g]);
@@ -84,7 +97,7 @@ int launch_fft3d_grouped(const typename cplx_t<T>::type *in, typename cplx_t<T>:
 // sums Ct[ch][spin][q] = sum_t w_t P[pair_t] (ascending pair order, FP64 accumulation).
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
-                  const PairDevTables &tb, hipStream_t st);
+                  const PairDevTables &tb, int variant, hipStream_t st);
 template <typename T>
 void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
                          const PairDevTables &tb, hipStream_t st);
