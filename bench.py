@@ -455,12 +455,17 @@ def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, ch
     scale = torch.empty((T, n_ch), dtype=torch.float64, device=dev) if fp32 else None
     ctx = bbc.Context(0)
     t_list = list(range(T))
+    tune = ctx.tuning((L, L, L), channels, precision=bbc.F32 if fp32 else bbc.F64)[0]
+    # profiled calls run one slice at a time; when the job's tuning runs several
+    # at once (or in graph mode) the timed steps are unprofiled and the stage
+    # times come from one more, profiled, step
+    separate = graph or (tune["slices"] > 0 and T > 1)
     if graph:
         ctx.graph_mode(True)
     for _ in range(warmup):
         ctx.correlate(d_l, d_s, t_list, channels, out=out, scale=scale)
     torch.cuda.synchronize()
-    if not graph:
+    if not separate:
         ctx.profile(True)
         ctx.profile_read()
     t0 = time.perf_counter()
@@ -469,7 +474,7 @@ def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, ch
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof_steps = steps
-    if graph:
+    if separate:
         ctx.graph_mode(False)
         ctx.profile(True)
         ctx.profile_read()
@@ -511,8 +516,10 @@ def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, ch
     roof["kernel"] = dom
     roof["avg_launch_us"] = round(avg_s * 1e6, 2)
     roof["traffic"] = traffic_for(dom, "f32" if fp32 else "f64", L)
+    roof["timed_in"] = ("a profiled step after the timed region (one slice at a time)" if separate
+                        else "the timed region")
     return {"value": round(site_ch / (ms_per_step / 1000.0), 1), "ms_per_step": round(ms_per_step, 3),
-            "site_channels_per_step": site_ch, "roofline": roof, "stages": stages,
+            "site_channels_per_step": site_ch, "roofline": roof, "stages": stages, "tuning": tune,
             "block_components_per_site": st["components"], "iterations": st["iterations"]}, out, scale
 
 

@@ -221,7 +221,15 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
  *   blocks  block construction, sites per workgroup x component shares:
  *           0 = 4 x 2, 1 = 4 x 4, 2 = 8 x 2;
  *   planes  x-y plane pass of the forward FFT (square 24- and 32-point planes):
- *           0 = as many planes per workgroup as 80 KB of LDS hold, 1 = half.
+ *           0 = as many planes per workgroup as 80 KB of LDS hold, 1 = half;
+ *   slices  time slices of one device-resident request run at once, 2^slices
+ *           (0..3): slice i runs on library stream i mod 2^slices with its own
+ *           workspace, the streams forked from and joined back into the
+ *           caller's stream (in graph mode: parallel branches of one graph);
+ *           the workspace grows accordingly, and fewer run at once where the
+ *           context budget would be exceeded.  Profiled calls run one at a time;
+ *   combine channel sums from the pair products: 0 = batches of 8 entries whose
+ *           loads are issued together, 1 = batches of 16.
  * A context keeps one choice per request shape; shapes without one take the
  * library's built-in choice.  Graphs captured in graph mode keep the variants
  * of their capture (same results).
@@ -230,6 +238,8 @@ typedef struct {
     int32_t pairs;
     int32_t blocks;
     int32_t planes;
+    int32_t slices;
+    int32_t combine;
 } bbc_tuning;
 
 /* The variants a request shape runs with; *tuned (may be NULL) = 1 if the
@@ -247,9 +257,10 @@ bbc_status bbc_tuning_set(bbc_context *ctx, const int32_t lattice[3], bbc_precis
  * request shape on one device-resident slice S_light, S_strange
  * ([Lz][Ly][Lx][12][12] of the precision's type) and keeps the fastest
  * variants: a coordinate search from the current choice over the contraction
- * kernel, then the plane pass (lattices that take one), then the block
- * kernel, each candidate timed over `reps` slices (1..1000) after one untimed
- * slice, with HIP events on `stream`.  The choice is stored in the context
+ * kernel, the plane pass (lattices that take one), the block kernel, the
+ * channel sums and the number of concurrent slices (those whose workspaces fit in 16 GB and the
+ * context budget), each candidate timed over `reps` rounds (1..1000) of up to
+ * 8 slices after one untimed round, with HIP events on `stream`.  The choice is stored in the context
  * (and written to the tuning file, see below); out and ms_per_slice (the best
  * time per slice, milliseconds) may be NULL.  Allocates a scratch output
  * buffer and grows the context workspace as bbc_correlate does; synchronises
@@ -262,7 +273,8 @@ bbc_status bbc_autotune(bbc_context *ctx, const int32_t lattice[3], bbc_precisio
 /*
  * Tuning file (JSON): {"bbc_tuning": 1, "entries": [{"lattice": [Lx, Ly, Lz],
  * "precision": 0|1, "spin_offset": 0|2, "channel_hash": "<FNV-1a of the
- * channel list, 16 hex digits>", "pairs": p, "blocks": b, "planes": l}, ...]}.
+ * channel list, 16 hex digits>", "pairs": p, "blocks": b, "planes": l,
+ * "slices": s, "combine": c}, ...]}.
  * bbc_tuning_save writes every choice the context holds (replacing the file
  * atomically); bbc_tuning_load merges a file's entries into the context
  * (BBC_EINVAL on a malformed file or a value out of range).  If the environment

@@ -239,7 +239,8 @@ def footprint(lattice, channels, precision=F64) -> int:
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("pairs", ctypes.c_int32), ("blocks", ctypes.c_int32), ("planes", ctypes.c_int32)]
+    _fields_ = [("pairs", ctypes.c_int32), ("blocks", ctypes.c_int32), ("planes", ctypes.c_int32),
+                ("slices", ctypes.c_int32), ("combine", ctypes.c_int32)]
 
 
 class Context:
@@ -428,15 +429,17 @@ class Context:
         tuned = ctypes.c_int()
         _check(self._lib.bbc_tuning_get(self._ptr, lat, int(precision), n, arr, int(spin), ctypes.byref(t),
                                         ctypes.byref(tuned)))
-        return {"pairs": t.pairs, "blocks": t.blocks, "planes": t.planes}, bool(tuned.value)
+        return {"pairs": t.pairs, "blocks": t.blocks, "planes": t.planes, "slices": t.slices,
+                "combine": t.combine}, bool(tuned.value)
 
     def set_tuning(self, lattice, channels, tuning, precision=F64, spin=UPPER):
-        """Set the variants of a request shape (dict pairs/blocks/planes; None: built-in)."""
+        """Set the variants of a request shape (dict pairs/blocks/planes/slices/combine; None: built-in)."""
         lat, _ = _i32(lattice)
         arr, n = _i32(channels)
         t = None
         if tuning is not None:
-            t = ctypes.byref(_Tuning(int(tuning["pairs"]), int(tuning["blocks"]), int(tuning["planes"])))
+            t = ctypes.byref(_Tuning(int(tuning["pairs"]), int(tuning["blocks"]), int(tuning["planes"]),
+                                     int(tuning.get("slices", 0)), int(tuning.get("combine", 0))))
         _check(self._lib.bbc_tuning_set(self._ptr, lat, int(precision), n, arr, int(spin), t))
 
     def autotune(self, S_light, S_strange, channels, spin=UPPER, reps=3, stream=None):
@@ -461,7 +464,8 @@ class Context:
         _check(self._lib.bbc_autotune(self._ptr, lat, prec, ctypes.c_void_p(S_light.data_ptr()),
                                       ctypes.c_void_p(S_strange.data_ptr()), n, arr, int(spin), int(reps),
                                       ctypes.c_void_p(stream.cuda_stream), ctypes.byref(t), ctypes.byref(ms)))
-        return {"pairs": t.pairs, "blocks": t.blocks, "planes": t.planes}, ms.value
+        return {"pairs": t.pairs, "blocks": t.blocks, "planes": t.planes, "slices": t.slices,
+                "combine": t.combine}, ms.value
 
     def save_tuning(self, path):
         _check(self._lib.bbc_tuning_save(self._ptr, os.fsencode(path)))

@@ -278,6 +278,10 @@ struct bbc_context {
     std::mutex tmu;
     std::map<std::array<uint64_t, 6>, bbc::Tuning> tuning;
     std::string tune_path;
+    // concurrent time slices of one direct call: streams forked from and joined
+    // back into the caller's stream (bev[0] fork, bev[1 + b] join of stream b)
+    hipStream_t bstreams[bbc::kMaxSliceStreams] = {};
+    hipEvent_t bev[bbc::kMaxSliceStreams + 1] = {};
     void clear_graphs() {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
@@ -301,6 +305,8 @@ struct bbc_context {
         if (cout) (void)hipStreamDestroy(cout);
         clear_graphs();
         if (gs) (void)hipStreamDestroy(gs);
+        for (auto s : bstreams) if (s) (void)hipStreamDestroy(s);
+        for (auto e : bev) if (e) (void)hipEventDestroy(e);
         for (auto e : sev) if (e) (void)hipEventDestroy(e);
         if (last) (void)hipEventDestroy(last);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -538,12 +544,14 @@ TuneKey tune_key(const int L[3], int prec, int spin_offset, uint64_t chash) {
 }
 
 // Built-in choice for shapes without a tuning entry (the fastest variants
-// measured at 16^3 and 32^3 with 52 channels): FP32 takes the pipelined
+// measured at 16^3 and 32^3 with 52 channels): FP32 takes the LDS-staged
 // contraction, 4 x 4 block workgroups and half-size plane-pass workgroups.
+// Small lattices run several slices at once (a slice alone does not fill the GPU).
 bbc::Tuning default_tuning(const int L[3], int prec) {
-    (void)L;
-    if (prec == BBC_F32) return bbc::Tuning{1, 1, 1};
-    return bbc::Tuning{0, 0, 0};
+    const long V = (long)L[0] * L[1] * L[2];
+    const int sl = V <= 1024 ? 3 : V <= 4096 ? 1 : 0;
+    if (prec == BBC_F32) return bbc::Tuning{2, 1, 1, sl, 0};
+    return bbc::Tuning{0, 0, 0, sl, 0};
 }
 
 // Tuning of a request: the context's entry for its shape, else the built-in choice.
@@ -610,7 +618,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     }
     {
         StageTimer tm(pc, st, 6);
-        bbc::launch_pair_combine<T>(Pp, Ct, n_ch, V, tb, st);
+        bbc::launch_pair_combine<T>(Pp, Ct, n_ch, V, tb, tu.combine, st);
     }
     {
         StageTimer tm(pc, st, 4);
@@ -623,6 +631,60 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     }
     HIP_TRY(hipGetLastError());
     return BBC_OK;
+}
+
+// Streams and events of the concurrent-slice path (created once per context).
+bbc_status slice_streams(bbc_context *ctx, int B) {
+    for (int b = 0; b < B; ++b)
+        if (!ctx->bstreams[b]) HIP_TRY(hipStreamCreateWithFlags(&ctx->bstreams[b], hipStreamNonBlocking));
+    for (int b = 0; b <= B; ++b)
+        if (!ctx->bev[b]) HIP_TRY(hipEventCreateWithFlags(&ctx->bev[b], hipEventDisableTiming));
+    return BBC_OK;
+}
+
+// n device-resident slices, B of them at a time: slice i runs on stream i mod B
+// (the caller's stream when B = 1) with its own workspace ws + (i mod B) stride.
+// The B streams wait for the caller's earlier work and the caller's stream waits
+// for all of them, so the call stays ordered on `st`; under graph capture on `st`
+// the streams become parallel branches of the graph.  Each slice runs the same
+// kernels on its own buffers, so the results do not depend on B.
+template <typename T>
+bbc_status enqueue_slices(bbc_context *ctx, const PlanDev &pd, const int L[3], long V, char *ws, size_t stride,
+                          int B, const MomGroups &mg, int n, const void *const *sl, const void *const *ss, int n_ch,
+                          const double *d_energy, const double *dt, void *const *out, double *const *scale,
+                          hipStream_t st, bool timed, const bbc::Tuning *force = nullptr) {
+    if (B <= 1) {
+        for (int i = 0; i < n; ++i) {
+            bbc_status s = enqueue_slice<T>(ctx, pd, L, V, ws, mg, sl[i], ss[i], n_ch, d_energy, dt[i], out[i],
+                                            scale[i], st, timed, force);
+            if (s) return s;
+        }
+        return BBC_OK;
+    }
+    bbc_status s = slice_streams(ctx, B);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(ctx->bev[0], st));
+    for (int b = 0; b < B; ++b) HIP_TRY(hipStreamWaitEvent(ctx->bstreams[b], ctx->bev[0], 0));
+    for (int i = 0; i < n; ++i) {
+        const int b = i % B;
+        s = enqueue_slice<T>(ctx, pd, L, V, ws + (size_t)b * stride, mg, sl[i], ss[i], n_ch, d_energy, dt[i], out[i],
+                             scale[i], ctx->bstreams[b], false, force);
+        if (s) return s;
+    }
+    for (int b = 0; b < B; ++b) {
+        HIP_TRY(hipEventRecord(ctx->bev[1 + b], ctx->bstreams[b]));
+        HIP_TRY(hipStreamWaitEvent(st, ctx->bev[1 + b], 0));
+    }
+    return BBC_OK;
+}
+
+// Concurrent slices of a direct call: the tuning's choice, at most n_t, one when
+// profiling (stage events are per stream), and as many as the budget allows.
+int concurrent_slices(bbc_context *ctx, const bbc::Tuning &tu, int n_t, size_t per_slice, size_t extra) {
+    int B = std::min(n_t, 1 << tu.slices);
+    if (ctx->prof) B = 1;
+    while (B > 1 && ctx->budget && (size_t)B * per_slice + extra > ctx->budget) B >>= 1;
+    return std::max(B, 1);
 }
 
 // True unless the pointer is memory kernels may dereference directly: HIP device
@@ -677,7 +739,11 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     const size_t core = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, cs);
     const size_t in_slice = (size_t)V * 144 * cs, out_slice = (size_t)n_ch * V * 16 * cs;
     const size_t in_stage = host_in ? 2 * 2 * in_slice : 0, out_stage = host_out ? 2 * out_slice : 0;
-    const size_t need = core + in_stage + out_stage;
+    // device-resident requests may run several slices at once (own workspace each)
+    const bool device_path = !host_in && !host_out;
+    const size_t stride = (core + 255) & ~(size_t)255;
+    const int B = device_path ? concurrent_slices(ctx, tuning_for(ctx, L, dp), n_t, stride, dp->table_bytes) : 1;
+    const size_t need = B > 1 ? (size_t)B * stride : core + in_stage + out_stage;
     if (ctx->budget && need + dp->table_bytes > ctx->budget)
         return fail(BBC_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the context budget");
     bbc_status s = ensure_workspace(ctx, need);
@@ -685,25 +751,35 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     if (energy && (s = upload_energy(ctx, energy, n_ch, st))) return s;
     const MomGroups mg = get_groups<T>(ctx, L, &s);
     if (!mg.pos) return s;
-    if (ctx->graph_mode && !host_in && !host_out && !ctx->prof && n_t > 0) {
+    std::vector<const void *> vsl, vss;
+    std::vector<void *> vout;
+    std::vector<double *> vsc;
+    std::vector<double> vdt;
+    if (device_path) {
+        for (int n = 0; n < n_t; ++n) {
+            vsl.push_back((const T2 *)S_light + (size_t)n * V * 144);
+            vss.push_back((const T2 *)S_strange + (size_t)n * V * 144);
+            vout.push_back((char *)C_out + (size_t)n * out_slice);
+            vsc.push_back(C_scale ? C_scale + (size_t)n * n_ch : nullptr);
+            vdt.push_back((double)(t_list[n] - t0));
+        }
+    }
+    if (ctx->graph_mode && device_path && !ctx->prof && n_t > 0) {
         // every value the captured kernels depend on
         std::vector<int64_t> key = {(int64_t)(intptr_t)dp, L[0], L[1], L[2], (int64_t)sizeof(T),
                                     (int64_t)(intptr_t)S_light, (int64_t)(intptr_t)S_strange, n_t, t0, n_ch,
                                     (int64_t)(intptr_t)(energy ? ctx->d_energy : nullptr), (int64_t)(intptr_t)C_out,
-                                    (int64_t)(intptr_t)C_scale, (int64_t)(intptr_t)ctx->ws};
+                                    (int64_t)(intptr_t)C_scale, (int64_t)(intptr_t)ctx->ws, B};
         for (int n = 0; n < n_t; ++n) key.push_back(t_list[n]);
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             if (!ctx->gs) HIP_TRY(hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking));
             if (ctx->graphs.size() >= 16) ctx->clear_graphs();
             HIP_TRY(hipStreamBeginCapture(ctx->gs, hipStreamCaptureModeRelaxed));
-            const T2 *Sl = (const T2 *)S_light, *Ss = (const T2 *)S_strange;
-            bbc_status es = BBC_OK;
-            for (int n = 0; n < n_t && es == BBC_OK; ++n)
-                es = enqueue_slice<T>(ctx, plan_dev(dp, dp->d_image), L, V, ctx->ws, mg, Sl + (size_t)n * V * 144, Ss + (size_t)n * V * 144,
-                                      n_ch, energy ? ctx->d_energy : nullptr, (double)(t_list[n] - t0),
-                                      (char *)C_out + (size_t)n * out_slice,
-                                      C_scale ? C_scale + (size_t)n * n_ch : nullptr, ctx->gs, false);
+            bbc_status es = enqueue_slices<T>(ctx, plan_dev(dp, dp->d_image), L, V, (char *)ctx->ws, stride, B, mg,
+                                              n_t, vsl.data(), vss.data(), n_ch,
+                                              energy ? ctx->d_energy : nullptr, vdt.data(), vout.data(), vsc.data(),
+                                              ctx->gs, false);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(ctx->gs, &g);
             if (es != BBC_OK) { if (g) (void)hipGraphDestroy(g); return es; }
@@ -717,6 +793,10 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
         HIP_TRY(hipGraphLaunch(it->second, st));
         return BBC_OK;
     }
+    if (device_path)
+        return enqueue_slices<T>(ctx, plan_dev(dp, dp->d_image), L, V, (char *)ctx->ws, stride, B, mg, n_t,
+                                 vsl.data(), vss.data(), n_ch, energy ? ctx->d_energy : nullptr, vdt.data(),
+                                 vout.data(), vsc.data(), st, true);
     char *stage_in = (char *)ctx->ws + core, *stage_out = stage_in + in_stage;
     if ((host_in || host_out) && !ctx->cin) {
         HIP_TRY(hipStreamCreateWithFlags(&ctx->cin, hipStreamNonBlocking));
@@ -1782,7 +1862,8 @@ namespace {
 bool tuning_valid(const bbc_tuning &t, bbc_precision prec) {
     const int np = prec == BBC_F64 ? bbc::kPairVariants64 : bbc::kPairVariants32;
     return t.pairs >= 0 && t.pairs < np && t.blocks >= 0 && t.blocks < bbc::kBlockVariants && t.planes >= 0 &&
-           t.planes < bbc::kPlaneVariants;
+           t.planes < bbc::kPlaneVariants && t.slices >= 0 && t.slices < bbc::kSliceVariants && t.combine >= 0 &&
+           t.combine < bbc::kCombineVariants;
 }
 
 bbc_status check_request(const int32_t lattice[3], bbc_precision prec, int n_ch, const int32_t *ch_list,
@@ -1817,7 +1898,8 @@ std::string tuning_json(const std::map<TuneKey, bbc::Tuning> &m) {
         o << (first ? "\n " : ",\n ") << "{\"lattice\": [" << kv.first[0] << ", " << kv.first[1] << ", "
           << kv.first[2] << "], \"precision\": " << kv.first[3] << ", \"spin_offset\": " << kv.first[4]
           << ", \"channel_hash\": \"" << hx << "\", \"pairs\": " << kv.second.pairs << ", \"blocks\": "
-          << kv.second.blocks << ", \"planes\": " << kv.second.planes << "}";
+          << kv.second.blocks << ", \"planes\": " << kv.second.planes << ", \"slices\": " << kv.second.slices
+          << ", \"combine\": " << kv.second.combine << "}";
         first = false;
     }
     o << "\n]}\n";
@@ -1845,18 +1927,19 @@ bbc_status parse_tuning(const std::string &text, std::map<TuneKey, bbc::Tuning> 
         int L[3];
         if (std::sscanf(text.c_str() + p, "{\"lattice\": [%d, %d, %d]", &L[0], &L[1], &L[2]) != 3)
             return fail(BBC_EINVAL, "tuning file: lattice");
-        long long prec, spin, pr, bl, pl;
+        long long prec, spin, pr, bl, pl, sl, cm;
         if (!json_int(text, p, e, "precision", &prec) || !json_int(text, p, e, "spin_offset", &spin) ||
             !json_int(text, p, e, "pairs", &pr) || !json_int(text, p, e, "blocks", &bl) ||
-            !json_int(text, p, e, "planes", &pl))
+            !json_int(text, p, e, "planes", &pl) || !json_int(text, p, e, "slices", &sl) ||
+            !json_int(text, p, e, "combine", &cm))
             return fail(BBC_EINVAL, "tuning file: missing field");
         const size_t h = text.find("\"channel_hash\": \"", p);
         if (h == std::string::npos || h > e) return fail(BBC_EINVAL, "tuning file: channel_hash");
         const uint64_t hash = std::strtoull(text.c_str() + h + 17, nullptr, 16);
-        bbc_tuning t{(int32_t)pr, (int32_t)bl, (int32_t)pl};
+        bbc_tuning t{(int32_t)pr, (int32_t)bl, (int32_t)pl, (int32_t)sl, (int32_t)cm};
         if ((prec != 0 && prec != 1) || (spin != 0 && spin != 2) || !tuning_valid(t, (bbc_precision)prec))
             return fail(BBC_EINVAL, "tuning file: value out of range");
-        (*out)[tune_key(L, (int)prec, (int)spin, hash)] = bbc::Tuning{t.pairs, t.blocks, t.planes};
+        (*out)[tune_key(L, (int)prec, (int)spin, hash)] = bbc::Tuning{t.pairs, t.blocks, t.planes, t.slices, t.combine};
         p = e + 1;
     }
     return BBC_OK;
@@ -1892,23 +1975,31 @@ bbc_status load_tuning(bbc_context *ctx, const std::string &path) {
     return BBC_OK;
 }
 
-// Device time of `reps` slices with the variants `tu` (one untimed slice first).
+// Device time per slice of `reps` rounds of nb slices (one untimed round first)
+// with the variants `tu`; every slice reads the same input, slice i writes
+// outs[i].
 template <typename T>
-bbc_status time_variant(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const MomGroups &mg,
-                        const void *sl, const void *ss, int n_ch, void *out, double *scale, int reps,
-                        const bbc::Tuning &tu, hipStream_t st, hipEvent_t a, hipEvent_t b, float *ms) {
+bbc_status time_variant(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const MomGroups &mg, size_t stride,
+                        const void *sl, const void *ss, int n_ch, int nb, void *const *outs, double *const *scales,
+                        int reps, const bbc::Tuning &tu, hipStream_t st, hipEvent_t a, hipEvent_t b, float *ms) {
     const PlanDev pd = plan_dev(dp, dp->d_image);
-    bbc_status s = enqueue_slice<T>(ctx, pd, L, V, ctx->ws, mg, sl, ss, n_ch, nullptr, 0.0, out, scale, st, false, &tu);
+    std::vector<const void *> vsl(nb, sl), vss(nb, ss);
+    std::vector<double> dt(nb, 0.0);
+    const int B = std::min(nb, 1 << tu.slices);
+    auto round = [&]() {
+        return enqueue_slices<T>(ctx, pd, L, V, (char *)ctx->ws, stride, B, mg, nb, vsl.data(), vss.data(), n_ch,
+                                 nullptr, dt.data(), outs, scales, st, false, &tu);
+    };
+    bbc_status s = round();
     if (s) return s;
     HIP_TRY(hipEventRecord(a, st));
-    for (int r = 0; r < reps && s == BBC_OK; ++r)
-        s = enqueue_slice<T>(ctx, pd, L, V, ctx->ws, mg, sl, ss, n_ch, nullptr, 0.0, out, scale, st, false, &tu);
+    for (int r = 0; r < reps && s == BBC_OK; ++r) s = round();
     if (s) return s;
     HIP_TRY(hipEventRecord(b, st));
     HIP_TRY(hipEventSynchronize(b));
     float e = 0.f;
     HIP_TRY(hipEventElapsedTime(&e, a, b));
-    *ms = e / (float)reps;
+    *ms = e / (float)(reps * nb);
     return BBC_OK;
 }
 
@@ -1916,37 +2007,55 @@ template <typename T>
 bbc_status autotune(bbc_context *ctx, DevPlan *dp, const int L[3], long V, const void *sl, const void *ss, int n_ch,
                     int reps, hipStream_t st, bbc::Tuning *best, float *best_ms) {
     using T2 = typename bbc::cplx_t<T>::type;
-    bbc_status s = ensure_workspace(ctx, workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, sizeof(T2)));
+    const size_t stride = (workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, sizeof(T2)) + 255) & ~(size_t)255;
+    // concurrent-slice candidates: workspaces within 16 GB and the budget
+    int max_sv = 0;
+    while (max_sv + 1 < bbc::kSliceVariants) {
+        const size_t w = (size_t)(2 << max_sv) * stride;
+        if (w > (16ull << 30) || (ctx->budget && w + dp->table_bytes > ctx->budget)) break;
+        ++max_sv;
+    }
+    const int nb = 1 << max_sv;                 // slices per timed round
+    bbc_status s = ensure_workspace(ctx, (size_t)nb * stride);
     if (s) return s;
     const MomGroups mg = get_groups<T>(ctx, L, &s);
     if (!mg.pos) return s;
-    void *out = nullptr;
-    double *scale = nullptr;
     const size_t ob = (size_t)n_ch * 16 * V * sizeof(T2);
-    if (hipMalloc(&out, ob) != hipSuccess) return fail(BBC_ENOMEM, "autotune output buffer");
-    if (hipMalloc((void **)&scale, sizeof(double) * n_ch) != hipSuccess) {
+    char *out = nullptr;
+    double *scale = nullptr;
+    if (hipMalloc((void **)&out, ob * nb) != hipSuccess) return fail(BBC_ENOMEM, "autotune output buffer");
+    if (hipMalloc((void **)&scale, sizeof(double) * n_ch * nb) != hipSuccess) {
         (void)hipFree(out);
         return fail(BBC_ENOMEM, "autotune scale buffer");
     }
+    std::vector<void *> outs(nb);
+    std::vector<double *> scales(nb);
+    for (int i = 0; i < nb; ++i) { outs[i] = out + (size_t)i * ob; scales[i] = scale + (size_t)i * n_ch; }
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    // coordinate search from the current choice: the pair-product kernel, then the
-    // plane pass (only where the lattice takes one), then the block kernel
+    // coordinate search from the current choice: the pair-product kernel, the plane
+    // pass (only where the lattice takes one), the block kernel, the channel sums,
+    // concurrent slices
     bbc::Tuning cur = tuning_for(ctx, L, dp);
+    cur.slices = std::min(cur.slices, max_sv);
     float cur_ms = 0.f;
-    s = time_variant<T>(ctx, dp, L, V, mg, sl, ss, n_ch, out, scale, reps, cur, st, a, b, &cur_ms);
+    s = time_variant<T>(ctx, dp, L, V, mg, stride, sl, ss, n_ch, nb, outs.data(), scales.data(), reps, cur, st, a, b,
+                        &cur_ms);
     const bool planes = bbc::fft3d_zgrouped_fits<T>(L) && !bbc::fft3d_grouped_fits<T>(L);
     const int npv = sizeof(T) == 8 ? bbc::kPairVariants64 : bbc::kPairVariants32;
-    for (int dim = 0; dim < 3 && s == BBC_OK; ++dim) {
-        const int n = dim == 0 ? npv : dim == 1 ? (planes ? bbc::kPlaneVariants : 1) : bbc::kBlockVariants;
+    for (int dim = 0; dim < 5 && s == BBC_OK; ++dim) {
+        const int n = dim == 0 ? npv : dim == 1 ? (planes ? bbc::kPlaneVariants : 1)
+                                     : dim == 2 ? bbc::kBlockVariants : dim == 3 ? bbc::kCombineVariants : max_sv + 1;
         for (int v = 0; v < n && s == BBC_OK; ++v) {
             bbc::Tuning c = cur;
-            int &field = dim == 0 ? c.pairs : dim == 1 ? c.planes : c.blocks;
+            int &field = dim == 0 ? c.pairs : dim == 1 ? c.planes : dim == 2 ? c.blocks : dim == 3 ? c.combine
+                                                                                                 : c.slices;
             if (field == v) continue;
             field = v;
             float ms = 0.f;
-            s = time_variant<T>(ctx, dp, L, V, mg, sl, ss, n_ch, out, scale, reps, c, st, a, b, &ms);
+            s = time_variant<T>(ctx, dp, L, V, mg, stride, sl, ss, n_ch, nb, outs.data(), scales.data(), reps, c, st,
+                                a, b, &ms);
             if (s == BBC_OK && ms < cur_ms) { cur = c; cur_ms = ms; }
         }
     }
@@ -1974,7 +2083,7 @@ bbc_status bbc_tuning_get(bbc_context *ctx, const int32_t lattice[3], bbc_precis
     std::lock_guard<std::mutex> lock(ctx->tmu);
     auto it = ctx->tuning.find(request_key(lattice, prec, n_ch, ch_list, spin));
     const bbc::Tuning t = it != ctx->tuning.end() ? it->second : default_tuning(L, (int)prec);
-    *out = bbc_tuning{t.pairs, t.blocks, t.planes};
+    *out = bbc_tuning{t.pairs, t.blocks, t.planes, t.slices, t.combine};
     if (tuned) *tuned = it != ctx->tuning.end();
     return BBC_OK;
 }
@@ -1992,7 +2101,7 @@ bbc_status bbc_tuning_set(bbc_context *ctx, const int32_t lattice[3], bbc_precis
         return BBC_OK;
     }
     if (!tuning_valid(*t, prec)) return fail(BBC_EINVAL, "kernel variant out of range");
-    ctx->tuning[key] = bbc::Tuning{t->pairs, t->blocks, t->planes};
+    ctx->tuning[key] = bbc::Tuning{t->pairs, t->blocks, t->planes, t->slices, t->combine};
     return BBC_OK;
 }
 
@@ -2025,7 +2134,7 @@ bbc_status bbc_autotune(bbc_context *ctx, const int32_t lattice[3], bbc_precisio
         std::lock_guard<std::mutex> tl(ctx->tmu);
         ctx->tuning[tune_key(L, (int)prec, dp->spin_offset, dp->chash)] = best;
     }
-    if (out) *out = bbc_tuning{best.pairs, best.blocks, best.planes};
+    if (out) *out = bbc_tuning{best.pairs, best.blocks, best.planes, best.slices, best.combine};
     if (ms_per_slice) *ms_per_slice = ms;
     if (!ctx->tune_path.empty()) return save_tuning(ctx, ctx->tune_path);
     return BBC_OK;

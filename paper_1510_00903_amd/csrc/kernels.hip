@@ -1259,6 +1259,337 @@ __device__ __forceinline__ void pair_task32(const float2 *__restrict__ gb0, cons
     }
 }
 
+// ----------------------------------------------------------------------------
+// LDS-staged forms.  Direct operand loads give each 4-lane block (one momentum,
+// rows (sink spin, outer spin)) two 16- or 8-byte pieces of two different
+// components, so the L1 takes two accesses per quad of lanes and limits the
+// kernel (counters: texture data unit about 98 % busy in FP32).  Here a wave
+// first copies the whole group lines its operands need for one round of open
+// indices into its own LDS area (global_load_lds_dwordx4: 16 contiguous bytes
+// per lane, whole 64-byte quads), then reads the MFMA operands from LDS.  The
+// products and their order are those of the direct forms, so the bits are too.
+// PIPE: two LDS buffers, the copies of the next round in flight while the
+// current one is multiplied.
+// ----------------------------------------------------------------------------
+constexpr int kStageMaxViews = 9;           // H + NP <= 9 operand views per open index
+
+// s_waitcnt immediate that waits until at most n vector-memory operations are
+// outstanding (expcnt and lgkmcnt left at their maxima).
+__host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// FP32: one task for two groups (16 momenta), KS = 2 open indices per round.
+// Lines (128 B: one component, both sink spins of the group's 8 momenta):
+// li = ((v 2 + group) 2 + kr) 2 + outer spin for the V = H + NP views (row
+// halves, then partners); wave load v fills the 8 lines of view v, so the view's
+// offsets are wave-uniform; the two outer spins of a line pair sit 128 B apart
+// (all 64 banks for one LDS read).
+template <int NP, int SHAPE, bool PIPE>
+__device__ __forceinline__ void pair_task32_lds(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
+                                                float2 *__restrict__ pb0, float2 *__restrict__ pb1, bool has1,
+                                                const PTask &T, int lane, int mir, float4 *wlds) {
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int V = H + NP, KS = 2, NL = 8 * V;
+    constexpr int G = GroupLayout<float2>::G;
+    const int ij = lane & 3, blk = lane >> 2;
+    const int g = ij & 1, o = ij >> 1;
+    const bool second = blk >= 8;
+    const bool active = !second || has1;
+    const int m = blk & 7;
+    const int srow = T.row_site == 0 ? m : mir, scol = T.row_site == 0 ? mir : m;
+    const bool colvalid = active && (SHAPE == 0 || ij < 2);
+    // this lane's line within each wave load: q = lane / 8 = (group, kr, outer spin)
+    const int q = lane >> 3, ld_o = q & 1, ld_kr = (q >> 1) & 1, ld_g1 = q >> 2;
+    const float4 *gsrc = (const float4 *)(ld_g1 ? gb1 : gb0) + (lane & 7);
+    const int K = T.K, nround = (K + KS - 1) / KS;
+    auto issue = [&](int r, int buf) {
+        const int kk0 = r * KS + ld_kr;
+        const int kk = kk0 < K ? kk0 : 0;                  // past K: an in-range line, never read
+        const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const PView &vw = v < H ? T.row : T.col[v - H];
+            int ostr, base = vw.base;
+            if (SHAPE == 0) ostr = v < H ? outer_stride(T.row, T.row_a) : outer_stride(vw, !T.row_a);
+            else { ostr = v < H ? T.row.so3 : 0; if (v < H) base += v * T.row.so4; }
+            const int comp = base + ld_o * ostr + k3 * vw.sk3 + k4 * vw.sk4;
+            __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * G),
+                                             (lds_void *)(wlds + (buf * NL + v * 8) * 8), 16, 0, 0);
+        }
+    };
+    fmfma4 acc[NP][H][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int h = 0; h < H; ++h) acc[p][h][0] = acc[p][h][1] = fmfma4{0.f, 0.f, 0.f, 0.f};
+    const int gl = second ? 1 : 0;
+    auto compute = [&](int r, int buf) {
+        const float2 *L2 = (const float2 *)(wlds + buf * NL * 8);
+#pragma unroll
+        for (int kr = 0; kr < KS; ++kr) {
+            if (r * KS + kr >= K) break;
+            float2 av[H], bv[NP];
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int li = ((h * 2 + gl) * 2 + kr) * 2 + o;
+                av[h] = L2[li * 16 + srow * 2 + g];
+                av[h] = active ? av[h] : float2{0.f, 0.f};
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int li = (((H + p) * 2 + gl) * 2 + kr) * 2 + o;
+                bv[p] = L2[li * 16 + scol * 2 + g];
+                bv[p] = colvalid ? bv[p] : float2{0.f, 0.f};
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const float2 a = av[h], b = bv[p];
+                    fmfma4 re = acc[p][h][0], im = acc[p][h][1];
+                    re = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.x, re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.y, b.y, re, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.y, im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.x, im, 0, 0, 0);
+                    acc[p][h][0] = re;
+                    acc[p][h][1] = im;
+                }
+        }
+    };
+    issue(0, 0);
+    for (int r = 0; r < nround; ++r) {
+        if constexpr (PIPE) {
+            if (r + 1 < nround) {
+                issue(r + 1, (r + 1) & 1);
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(V));
+            } else {
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            }
+            compute(r, r & 1);
+        } else {
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            compute(r, 0);
+            if (r + 1 < nround) issue(r + 1, 0);
+        }
+    }
+    // D lane (j = lane & 3, block), register i
+    const int j = lane & 3;
+    if (!active || (SHAPE == 1 && j >= 2)) return;
+    float2 *pb = second ? pb1 : pb0;
+    const int gC = j & 1, oC = j >> 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gR = i & 1, oR = i >> 1;
+        const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            int ap, bp;
+            if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+            else { ap = oR; bp = h; }
+            const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                pb[((size_t)T.pair[p] * 16 + sp) * G + m] = float2{acc[p][h][0][i], acc[p][h][1][i]};
+        }
+    }
+}
+
+// FP64: one task for one group (both sets of 4 momenta), one round = 4 open
+// indices (the MFMA's K).  Lines (256 B: one component, both sink spins of the
+// group's 8 momenta): li = (v 4 + kl) 2 + outer spin; wave load w fills lines
+// 4w .. 4w + 3, all of view v = w / 2, so the view's offsets are wave-uniform.
+// Lines of outer spin 1 hold their two 128-byte halves swapped, so the 16 lanes
+// of one LDS read phase (both outer spins, one set) hit all 64 banks.
+template <int NP, int SHAPE, bool PIPE>
+__device__ __forceinline__ void pair_task64_lds(const double2 *__restrict__ gb, double2 *__restrict__ pb,
+                                                const PTask &T, int lane, const int mir[2], double2 *wlds) {
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int V = H + NP, NL = 8 * V;
+    constexpr int G = GroupLayout<double2>::G;
+    const int ij = lane & 3, blk = (lane >> 2) & 3, kl = lane >> 4;
+    const int g = ij & 1, o = ij >> 1;
+    int srow[2], scol[2];
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+        const int mm = blk + 4 * st;
+        srow[st] = T.row_site == 0 ? mm : mir[st];
+        scol[st] = T.row_site == 0 ? mir[st] : mm;
+    }
+    const bool colvalid = SHAPE == 0 || ij < 2;
+    // this lane's line within a wave load: q = lane / 16 = (kl & 1, outer spin); the
+    // wave load's parity gives kl >> 1
+    const int ld_o = (lane >> 4) & 1, ld_kl = lane >> 5;
+    const double2 *gsrc = gb + ((lane & 15) ^ (ld_o << 3));
+    const int K = T.K, nround = (K + 3) / 4;
+    auto issue = [&](int r, int buf) {
+        int k3[2], k4[2];
+#pragma unroll
+        for (int hk = 0; hk < 2; ++hk) {
+            const int kk0 = r * 4 + 2 * hk + ld_kl;
+            const int kk = kk0 < K ? kk0 : 0;
+            k3[hk] = (kk * T.inv) >> 16;
+            k4[hk] = kk - k3[hk] * T.kd4;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const PView &vw = v < H ? T.row : T.col[v - H];
+            int ostr, base = vw.base;
+            if (SHAPE == 0) ostr = v < H ? outer_stride(T.row, T.row_a) : outer_stride(vw, !T.row_a);
+            else { ostr = v < H ? T.row.so3 : 0; if (v < H) base += v * T.row.so4; }
+#pragma unroll
+            for (int hk = 0; hk < 2; ++hk) {
+                const int comp = base + ld_o * ostr + k3[hk] * vw.sk3 + k4[hk] * vw.sk4;
+                __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * (2 * G)),
+                                                 (lds_void *)(wlds + (buf * NL + (v * 2 + hk) * 4) * 16), 16, 0, 0);
+            }
+        }
+    };
+    double acc[NP][2][H][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int h = 0; h < H; ++h) acc[p][st][h][0] = acc[p][st][h][1] = 0.0;
+    auto compute = [&](int r, int buf) {
+        const double2 *L = wlds + buf * NL * 16;
+        const bool valid = r * 4 + kl < K;
+        double2 av[2][H], bv[NP][2];
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int li = (h * 4 + kl) * 2 + o;
+                av[st][h] = L[li * 16 + ((srow[st] * 2 + g) ^ (o << 3))];
+                av[st][h] = valid ? av[st][h] : double2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int li = ((H + p) * 4 + kl) * 2 + o;
+                bv[p][st] = L[li * 16 + ((scol[st] * 2 + g) ^ (o << 3))];
+                bv[p][st] = (valid && colvalid) ? bv[p][st] : double2{0.0, 0.0};
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const double2 a = av[st][h], b = bv[p][st];
+                    double re = acc[p][st][h][0], im = acc[p][st][h][1];
+                    re = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.x, re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f64_4x4x4f64(-a.y, b.y, re, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.y, im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, b.x, im, 0, 0, 0);
+                    acc[p][st][h][0] = re;
+                    acc[p][st][h][1] = im;
+                }
+    };
+    issue(0, 0);
+    for (int r = 0; r < nround; ++r) {
+        if constexpr (PIPE) {
+            if (r + 1 < nround) {
+                issue(r + 1, (r + 1) & 1);
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * V));
+            } else {
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            }
+            compute(r, r & 1);
+        } else {
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            compute(r, 0);
+            if (r + 1 < nround) issue(r + 1, 0);
+        }
+    }
+    // D lane (j = lane & 3, block, i = lane >> 4)
+    const int j = lane & 3, i = lane >> 4;
+    if (SHAPE == 1 && j >= 2) return;
+    const int gR = i & 1, oR = i >> 1, gC = j & 1, oC = j >> 1;
+    const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        int ap, bp;
+        if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+        else { ap = oR; bp = h; }
+        const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            double2 *dst = pb + ((size_t)T.pair[p] * 16 + sp) * G;
+#pragma unroll
+            for (int st = 0; st < 2; ++st) dst[blk + 4 * st] = double2{acc[p][st][h][0], acc[p][st][h][1]};
+        }
+    }
+}
+
+// One wave per task of a momentum unit (FP64: one group; FP32: two groups),
+// operands staged through each wave's LDS area; workgroups of 4 waves, the
+// workgroups of a unit consecutive on one XCD.
+template <typename T, bool PIPE>
+__global__ __launch_bounds__(256) void k_pairs_lds(const typename cplx_t<T>::type *__restrict__ Iq,
+                                                   typename cplx_t<T>::type *__restrict__ P, int nc, int ubase,
+                                                   int ucount, const int2 *__restrict__ gpos, int ngroup,
+                                                   const PTask *__restrict__ tasks, int ntask, int npair) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int G = GroupLayout<T2>::G;
+    constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;
+    // per wave and buffer: FP32 8 V lines of 128 B (2 open indices), FP64 8 V lines of 256 B (4)
+    constexpr int BUF16 = sizeof(T) == 8 ? 8 * kStageMaxViews * 16 : 8 * kStageMaxViews * 8;   // 16-byte units
+    constexpr int NBUF = PIPE ? 2 : 1;
+    __shared__ float4 lds[4 * NBUF * BUF16];
+    const int nchunk = (ntask + 3) >> 2;
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    const int P8 = (ucount + 7) >> 3;
+    const int ul = xcd * P8 + jj / nchunk;
+    const int chunk = jj - (jj / nchunk) * nchunk;
+    if (ul >= ucount) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = chunk * 4 + wave;
+    if (t >= ntask) return;
+    const int lane = threadIdx.x & 63;
+    const int unit = ubase + ul;
+    const int grp0 = unit * GPU_;
+    const bool has1 = GPU_ == 2 && grp0 + 1 < ngroup;
+    const T2 *g0 = Iq + (size_t)grp0 * nc * 2 * G;
+    const T2 *g1 = has1 ? g0 + (size_t)nc * 2 * G : g0;
+    T2 *p0 = P + (size_t)grp0 * npair * 16 * G;
+    T2 *p1 = has1 ? p0 + (size_t)npair * 16 * G : p0;
+    float4 *wlds = lds + wave * NBUF * BUF16;
+    int mir[2];
+    if constexpr (sizeof(T) == 8) {
+        const int blk = (lane >> 2) & 3;
+        mir[0] = gpos[(size_t)grp0 * G + blk].y;
+        mir[1] = gpos[(size_t)grp0 * G + blk + 4].y;
+    } else {
+        const int blk = lane >> 2;
+        const int gg = (blk >= 8 && has1) ? grp0 + 1 : grp0;
+        mir[0] = gpos[(size_t)gg * G + (blk & 7)].y;
+        mir[1] = 0;
+    }
+    const PTask &Tk = tasks[t];
+    const int np = __builtin_amdgcn_readfirstlane(Tk.np);
+    const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
+#define BBC_PAIRL_CASE(SH, N)                                                                                  \
+    case N:                                                                                                    \
+        if constexpr (sizeof(T) == 8) pair_task64_lds<N, SH, PIPE>(g0, p0, Tk, lane, mir, (double2 *)wlds);   \
+        else pair_task32_lds<N, SH, PIPE>(g0, g1, p0, p1, has1, Tk, lane, mir[0], wlds);                     \
+        break;
+    if (shape == 0) {
+        switch (np) {
+            BBC_PAIRL_CASE(0, 1) BBC_PAIRL_CASE(0, 2) BBC_PAIRL_CASE(0, 3) BBC_PAIRL_CASE(0, 4)
+            BBC_PAIRL_CASE(0, 5) BBC_PAIRL_CASE(0, 6) BBC_PAIRL_CASE(0, 7) BBC_PAIRL_CASE(0, 8)
+            default: break;
+        }
+    } else {
+        switch (np) {
+            BBC_PAIRL_CASE(1, 1) BBC_PAIRL_CASE(1, 2) BBC_PAIRL_CASE(1, 3) BBC_PAIRL_CASE(1, 4)
+            default: break;
+        }
+    }
+#undef BBC_PAIRL_CASE
+}
+
 template <typename T, int SHAPE, int NP, int NS, bool PIPE>
 __device__ __forceinline__ void pair_dispatch_np(const typename cplx_t<T>::type *g0, const typename cplx_t<T>::type *g1,
                                                  typename cplx_t<T>::type *p0, typename cplx_t<T>::type *p1,
@@ -1337,9 +1668,10 @@ __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *_
 // kCombChunk channels; its 1024 lanes are 8 channel classes (ch mod 8) x 16
 // spins x G momenta, and a lane keeps the sums of its class's (at most 8)
 // channels in registers, the channel of each entry selected by a wave-uniform
-// branch.  Every sum belongs to one lane and is formed in a fixed order
-// (no atomics).  Entries are taken in batches whose loads are all issued first.
-template <typename T>
+// branch.  Every sum belongs to one lane and is formed in a fixed order (no
+// atomics).  Entries are taken in batches of B whose loads are all issued
+// first (the kernel is bound by the latency of these loads).
+template <typename T, int B>
 __global__ __launch_bounds__(1024) void k_pair_combine(const typename cplx_t<T>::type *__restrict__ P,
                                                        typename cplx_t<T>::type *__restrict__ Ct, int ch0, int nch,
                                                        long V, const int2 *__restrict__ gpos, int gbase, int npair,
@@ -1358,7 +1690,6 @@ __global__ __launch_bounds__(1024) void k_pair_combine(const typename cplx_t<T>:
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[j] = double2{0.0, 0.0};
     const int eb = comb_begin[sub], ee = comb_begin[sub + 1];
-    constexpr int B = 8;
     for (int i0 = eb; i0 < ee; i0 += B) {
         T2 v[B];
 #pragma unroll
@@ -1406,9 +1737,28 @@ static void launch_pairs_v(const typename cplx_t<T>::type *Iq, typename cplx_t<T
     }
 }
 
+template <typename T, bool PIPE>
+static void launch_pairs_lds(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
+                             const PairDevTables &tb, hipStream_t st) {
+    constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;
+    const int nunit = (tb.ngroup + GPU_ - 1) / GPU_;
+    const long nchunk = ((long)tb.ntask + 3) / 4;
+    if (nchunk == 0) return;
+    const long max_wg = (1L << 32) / 256 - 64;
+    const int per = (int)std::max<long>(8, std::min<long>(nunit, (max_wg / nchunk) / 8 * 8));
+    for (int u0 = 0; u0 < nunit; u0 += per) {
+        const int uc = std::min(per, nunit - u0);
+        const long nwg = 8L * ((uc + 7) / 8) * nchunk;
+        hipLaunchKernelGGL((k_pairs_lds<T, PIPE>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+                           tb.ngroup, tb.tasks, tb.ntask, tb.npair);
+    }
+}
+
 // Variants (same products in the same order, so the same bits): FP64 0 = whole
 // group per wave, 1 = whole group, pipelined, 2 = half group, 3 = half group,
-// pipelined; FP32 0 = plain, 1 = pipelined.
+// pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered;
+// FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
+// double-buffered.
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
                   int variant, hipStream_t st) {
@@ -1417,25 +1767,36 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
         case 1: launch_pairs_v<T, 2, true>(Iq, P, nc, tb, st); break;
         case 2: launch_pairs_v<T, 1, false>(Iq, P, nc, tb, st); break;
         case 3: launch_pairs_v<T, 1, true>(Iq, P, nc, tb, st); break;
+        case 4: launch_pairs_lds<T, false>(Iq, P, nc, tb, st); break;
+        case 5: launch_pairs_lds<T, true>(Iq, P, nc, tb, st); break;
         default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
         }
     } else {
-        if (variant == 1) launch_pairs_v<T, 2, true>(Iq, P, nc, tb, st);
-        else launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st);
+        switch (variant) {
+        case 1: launch_pairs_v<T, 2, true>(Iq, P, nc, tb, st); break;
+        case 2: launch_pairs_lds<T, false>(Iq, P, nc, tb, st); break;
+        case 3: launch_pairs_lds<T, true>(Iq, P, nc, tb, st); break;
+        default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
+        }
     }
 }
 
+// Variants: entries per load batch, 0 = 8, 1 = 16 (same sums in the same order).
 template <typename T>
 void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
-                         const PairDevTables &tb, hipStream_t st) {
+                         const PairDevTables &tb, int variant, hipStream_t st) {
     const long max_wg = (1L << 32) / 1024 - 64;
     for (int c0 = 0; c0 < n_ch; c0 += kCombChunk) {
         const int nch = std::min(kCombChunk, n_ch - c0);
         const int32_t *cb = tb.comb_begin + (size_t)(c0 / kCombChunk) * kCombSubs;
         for (long g0 = 0; g0 < tb.ngroup; g0 += max_wg) {
             const long gc = std::min<long>(max_wg, tb.ngroup - g0);
-            hipLaunchKernelGGL((k_pair_combine<T>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch, V, tb.gpos,
-                               (int)g0, tb.npair, tb.comb, cb);
+            if (variant == 1)
+                hipLaunchKernelGGL((k_pair_combine<T, 16>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch, V,
+                                   tb.gpos, (int)g0, tb.npair, tb.comb, cb);
+            else
+                hipLaunchKernelGGL((k_pair_combine<T, 8>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch, V,
+                                   tb.gpos, (int)g0, tb.npair, tb.comb, cb);
         }
     }
 }
@@ -1529,8 +1890,10 @@ template int launch_fft3d_grouped<double>(const double2 *, double2 *, int, const
 template int launch_fft3d_grouped<float>(const float2 *, float2 *, int, const int[3], int, const int2 *, hipStream_t);
 template void launch_pairs<double>(const double2 *, double2 *, int, const PairDevTables &, int, hipStream_t);
 template void launch_pairs<float>(const float2 *, float2 *, int, const PairDevTables &, int, hipStream_t);
-template void launch_pair_combine<double>(const double2 *, double2 *, int, long, const PairDevTables &, hipStream_t);
-template void launch_pair_combine<float>(const float2 *, float2 *, int, long, const PairDevTables &, hipStream_t);
+template void launch_pair_combine<double>(const double2 *, double2 *, int, long, const PairDevTables &, int,
+                                          hipStream_t);
+template void launch_pair_combine<float>(const float2 *, float2 *, int, long, const PairDevTables &, int,
+                                         hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
                                       double *, const uint32_t *, const int2 *, hipStream_t);
 template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,

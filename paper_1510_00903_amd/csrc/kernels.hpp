@@ -57,13 +57,20 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 // Kernel variants of one request shape (every variant forms the same values in
 // the same order, so the results are the same bits; only speed differs):
 //   pairs  - pair-product kernel: FP64 0 = whole group per wave, 1 = pipelined,
-//            2 = half group per wave, 3 = half group, pipelined; FP32 0, 1 = pipelined;
+//            2 = half group per wave, 3 = half group, pipelined, 4 = operands staged
+//            through LDS, 5 = staged, double-buffered; FP32 0, 1 = pipelined,
+//            2 = staged through LDS, 3 = staged, double-buffered;
 //   blocks - block kernel sites per workgroup x component shares: 0 = 4x2, 1 = 4x4, 2 = 8x2;
-//   planes - plane-pass FFT planes per workgroup: 0 = as many as 80 KB of LDS hold, 1 = half.
+//   planes - plane-pass FFT planes per workgroup: 0 = as many as 80 KB of LDS hold, 1 = half;
+//   slices - time slices of one request run at once (1 << slices), each on its own
+//            stream and workspace;
+//   combine - channel sums: entries per load batch, 0 = 8, 1 = 16.
 struct Tuning {
-    int pairs = 0, blocks = 0, planes = 0;
+    int pairs = 0, blocks = 0, planes = 0, slices = 0, combine = 0;
 };
-constexpr int kPairVariants64 = 4, kPairVariants32 = 2, kBlockVariants = 3, kPlaneVariants = 2;
+constexpr int kPairVariants64 = 6, kPairVariants32 = 4, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
+              kCombineVariants = 2;
+constexpr int kMaxSliceStreams = 1 << (kSliceVariants - 1);
 
 // FP32 form: per-flavour max |Re|,|Im| of a slice into kmax[0] (light), kmax[1] (strange).
 void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st);
@@ -100,7 +107,7 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
                   const PairDevTables &tb, int variant, hipStream_t st);
 template <typename T>
 void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
-                         const PairDevTables &tb, hipStream_t st);
+                         const PairDevTables &tb, int variant, hipStream_t st);
 
 template <typename T>
 void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,

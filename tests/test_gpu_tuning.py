@@ -7,7 +7,8 @@ the same bits for every choice; the autotuner must return a valid choice, keep
 it for the request shape, and write and read it back through the tuning file.
 Lattices: 8^3 (fused one-pass FFT) and 24 x 24 x 4 (plane pass, then the z
 pass that writes whole x-row runs of momentum groups), both precisions, the
-52 channels.  The 24 x 24 x 4 results are also checked against the oracle at
+52 channels, five time slices (so that 2, 4 or 8 slices run at once on the
+library's streams, round robin, give the bits of one at a time).  The 24 x 24 x 4 results are also checked against the oracle at
 sampled points, since its momentum groups come in x-row runs.
 """
 import json
@@ -24,7 +25,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 CHANNELS = list(range(52))
-N_PAIRS = {"f64": 4, "f32": 2}
+N_PAIRS = {"f64": 6, "f32": 4}
 
 
 @pytest.fixture(scope="module")
@@ -53,11 +54,14 @@ def _run(ctx, dl, ds):
 
 
 def _variants(prec, lat):
-    """Each dimension on its own from the built-in choice."""
+    """Each dimension on its own from the plain choice."""
     planes = 2 if lat[0] in (24, 32) and lat[0] == lat[1] else 1
-    out = [{"pairs": p, "blocks": 0, "planes": 0} for p in range(N_PAIRS[prec])]
-    out += [{"pairs": 0, "blocks": b, "planes": 0} for b in range(1, 3)]
-    out += [{"pairs": 0, "blocks": 0, "planes": pl} for pl in range(1, planes)]
+    base = {"pairs": 0, "blocks": 0, "planes": 0, "slices": 0, "combine": 0}
+    out = [dict(base, pairs=p) for p in range(N_PAIRS[prec])]
+    out += [dict(base, blocks=b) for b in range(1, 3)]
+    out += [dict(base, planes=pl) for pl in range(1, planes)]
+    out += [dict(base, slices=s) for s in range(1, 4)]
+    out += [dict(base, combine=1)]
     return out
 
 
@@ -67,8 +71,9 @@ def test_every_variant_gives_the_same_bits(bbc, prec, lat):
     print("case: variants", prec, lat, flush=True)
     ctx = bbc.Context(0)
     P = bbc.F64 if prec == "f64" else bbc.F32
-    dl, ds = _inputs(lat, prec, seed=1510009050, n_t=2)
-    ctx.set_tuning(lat, CHANNELS, {"pairs": 0, "blocks": 0, "planes": 0}, precision=P)
+    # five slices: with 2, 4 or 8 run at once the streams take them round robin
+    dl, ds = _inputs(lat, prec, seed=1510009050, n_t=5)
+    ctx.set_tuning(lat, CHANNELS, {"pairs": 0, "blocks": 0, "planes": 0, "slices": 0}, precision=P)
     ref, ref_s = _run(ctx, dl, ds)
     for v in _variants(prec, lat):
         ctx.set_tuning(lat, CHANNELS, v, precision=P)
@@ -122,7 +127,8 @@ def test_autotune_stores_and_round_trips(bbc, tmp_path):
         t0, tuned0 = ctx.tuning(lat, CHANNELS)
         assert not tuned0
         best, ms = ctx.autotune(dl[0].contiguous(), ds[0].contiguous(), CHANNELS, reps=2)
-        assert 0 <= best["pairs"] < 4 and 0 <= best["blocks"] < 3 and best["planes"] == 0
+        assert 0 <= best["pairs"] < 6 and 0 <= best["blocks"] < 3 and best["planes"] == 0
+        assert 0 <= best["slices"] < 4 and 0 <= best["combine"] < 2
         assert ms > 0
         t1, tuned1 = ctx.tuning(lat, CHANNELS)
         assert tuned1 and t1 == best
@@ -153,9 +159,11 @@ def test_autotune_stores_and_round_trips(bbc, tmp_path):
 def test_tuning_errors(bbc, tmp_path):
     ctx = bbc.Context(0)
     with pytest.raises(bbc.BBCError):
-        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 4, "blocks": 0, "planes": 0})
+        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 6, "blocks": 0, "planes": 0})
     with pytest.raises(bbc.BBCError):
-        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 2, "blocks": 0, "planes": 0}, precision=bbc.F32)
+        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 4, "blocks": 0, "planes": 0}, precision=bbc.F32)
+    with pytest.raises(bbc.BBCError):
+        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 0, "blocks": 0, "planes": 0, "slices": 4})
     bad = tmp_path / "bad.json"
     bad.write_text('{"something": 2}')
     with pytest.raises(bbc.BBCError):
