@@ -665,12 +665,14 @@ def main():
                 "synthetic (seeded t-independent Gaussian field + 1e-3 noise per slice, exp(-m t) decay, "
                 "drawn on the device)",
         "config": {"workload": "%d^3x%d lattice, all 52 BB channels, %s, upper spins"
-                               % (L, T, "FP32 form (power-of-two rescaled, FP32 matrix-core products, "
-                                        "FP64 channel sums)" if fp32 else "FP64 plain form"),
+                               % (L, T, "FP32 form (power-of-two rescaled, FP32 blocks, forward FFT and "
+                                        "matrix-core products, FP64 channel sums, compensated float-float "
+                                        "inverse FFT)" if fp32 else "FP64 plain form"),
                    "lattice": [L, L, L], "T": T, "channels": n_ch, "site_channels_per_step": r["site_channels_per_step"],
                    "block_components_per_site": r["block_components_per_site"], "iterations": r["iterations"]},
         "roofline": r["roofline"],
         "stages": r["stages"],
+        "tuning": r["tuning"],
         "hip_graph": bool(args.graph),
     }
     if L == 16 and not fp32 and not args.no_extras and not args.slices:

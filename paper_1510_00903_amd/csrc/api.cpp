@@ -445,7 +445,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
 // Workspace of one slice:
 //   region A: the intermediates I in site space (2 spins x nc x V); once they
 //             are in the momentum groups it is dead, and the contracted fields
-//             Ct (n_ch x 16 x V) and, after them, the pair products
+//             Ct (n_ch x 16 x V, 16 bytes each) and, after them, the pair products
 //             P (npair x 16 per grouped position, at most V + 8) reuse it;
 //   region B: the momentum-grouped copy Iq (groups x 2 x nc x G, at most V + 8
 //             positions);
@@ -456,7 +456,7 @@ struct WsLayout {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 WsLayout ws_layout(long V, int nc, int n_ch, int npair, size_t csize) {
     WsLayout L;
-    L.p = align256((size_t)n_ch * 16 * V * csize);
+    L.p = align256((size_t)n_ch * 16 * V * 16);   // Ct: 16 bytes per value (double2, or float-float pairs)
     const size_t ra = std::max<size_t>((size_t)2 * nc * V * csize, L.p + (size_t)npair * 16 * (V + 8) * csize);
     const size_t rb = (size_t)2 * nc * (V + 8) * csize;
     L.a = align256(ra);
@@ -577,7 +577,8 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     const WsLayout lay = ws_layout(V, nc, n_ch, dp->npair, sizeof(T2));
     T2 *I = (T2 *)ws;
     T2 *Iq = (T2 *)((char *)ws + lay.a);
-    T2 *Ct = I;                                   // reuses region A once Iq is written
+    using TC = typename bbc::ct_t<T>::type;
+    TC *Ct = (TC *)ws;                            // reuses region A once Iq is written
     T2 *Pp = (T2 *)((char *)ws + lay.p);
     uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
     bbc::PairDevTables tb{mg.pos, mg.ngroup, pd.tasks, dp->ntask, dp->npair, pd.comb, pd.comb_begin};
@@ -622,7 +623,9 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     }
     {
         StageTimer tm(pc, st, 4);
-        if ((tm.nk = bbc::launch_fft3d<T>(Ct, 16L * n_ch, L, +1, st)) < 0) return fail(BBC_EUNSUPPORTED, "FFT size");
+        // FP32 form: compensated float-float arithmetic for this last spatial sum
+        if ((tm.nk = bbc::launch_fft3d<typename bbc::ct_real<T>::type>(Ct, 16L * n_ch, L, +1, st)) < 0)
+            return fail(BBC_EUNSUPPORTED, "FFT size");
     }
     {
         StageTimer tm(pc, st, 5);

@@ -28,6 +28,33 @@ __device__ __forceinline__ int pow2_exponent(float m) {
     return e - 1;
 }
 
+// Float-float arithmetic (the FP32 form's compensated inverse transform):
+// addition by Knuth's TwoSum of the high parts with the low parts added into
+// the error term, multiplication by the FMA TwoProd of the high parts plus the
+// cross terms, both renormalised (Fast2Sum) so that |lo| <= ulp(hi) / 2.
+// Multiplication by an integer is used only with +1 and -1 (exact).
+// The steps use explicitly rounded operations (__fadd_rn, __fsub_rn, __fmul_rn)
+// so that no multiply-add is contracted into them.
+__device__ __forceinline__ ff operator+(ff a, ff b) {
+    const float s = __fadd_rn(a.hi, b.hi);
+    const float v = __fsub_rn(s, a.hi);
+    float e = __fadd_rn(__fsub_rn(a.hi, __fsub_rn(s, v)), __fsub_rn(b.hi, v));
+    e = __fadd_rn(e, __fadd_rn(a.lo, b.lo));
+    const float h = __fadd_rn(s, e);
+    return ff(h, __fsub_rn(e, __fsub_rn(h, s)));
+}
+__device__ __forceinline__ ff operator-(ff a) { return ff(-a.hi, -a.lo); }
+__device__ __forceinline__ ff operator-(ff a, ff b) { return a + (-b); }
+__device__ __forceinline__ ff operator*(ff a, ff b) {
+    const float p = __fmul_rn(a.hi, b.hi);
+    float e = fmaf(a.hi, b.hi, -p);
+    e = fmaf(a.hi, b.lo, e);
+    e = fmaf(a.lo, b.hi, e);
+    const float h = __fadd_rn(p, e);
+    return ff(h, __fsub_rn(e, __fsub_rn(h, p)));
+}
+__device__ __forceinline__ ff operator*(int k, ff a) { return ff((float)k * a.hi, (float)k * a.lo); }
+
 template <typename T2> __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
     return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
@@ -1663,7 +1690,8 @@ __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *_
 }
 
 // Channel sums: Ct[ch][s][q] = sum_t w_t P[group][pair_t][s][slot], FP64
-// accumulation in ascending pair order.  One workgroup per momentum group reads
+// accumulation in ascending pair order (stored as FP64, or in the FP32 form as
+// float-float pairs for the compensated inverse transform).  One workgroup per momentum group reads
 // the group's pair products pair by pair (pair-major entry lists) for up to
 // kCombChunk channels; its 1024 lanes are 8 channel classes (ch mod 8) x 16
 // spins x G momenta, and a lane keeps the sums of its class's (at most 8)
@@ -1673,7 +1701,7 @@ __global__ __launch_bounds__(256) void k_pairs(const typename cplx_t<T>::type *_
 // first (the kernel is bound by the latency of these loads).
 template <typename T, int B>
 __global__ __launch_bounds__(1024) void k_pair_combine(const typename cplx_t<T>::type *__restrict__ P,
-                                                       typename cplx_t<T>::type *__restrict__ Ct, int ch0, int nch,
+                                                       typename ct_t<T>::type *__restrict__ Ct, int ch0, int nch,
                                                        long V, const int2 *__restrict__ gpos, int gbase, int npair,
                                                        const CombEntry *__restrict__ comb,
                                                        const int32_t *__restrict__ comb_begin) {
@@ -1714,7 +1742,11 @@ __global__ __launch_bounds__(1024) void k_pair_combine(const typename cplx_t<T>:
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int ch = sub + 8 * j;
-        if (ch < nch) Ct[((size_t)(ch0 + ch) * 16 + s) * V + q] = T2{(T)acc[j].x, (T)acc[j].y};
+        if (ch >= nch) continue;
+        if constexpr (sizeof(T) == 4)        // FP32 form: the FP64 sums as float-float pairs
+            Ct[((size_t)(ch0 + ch) * 16 + s) * V + q] = ffc{ff(acc[j].x), ff(acc[j].y)};
+        else
+            Ct[((size_t)(ch0 + ch) * 16 + s) * V + q] = T2{(T)acc[j].x, (T)acc[j].y};
     }
 }
 
@@ -1783,7 +1815,7 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
 
 // Variants: entries per load batch, 0 = 8, 1 = 16 (same sums in the same order).
 template <typename T>
-void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
+void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::type *Ct, int n_ch, long V,
                          const PairDevTables &tb, int variant, hipStream_t st) {
     const long max_wg = (1L << 32) / 1024 - 64;
     for (int c0 = 0; c0 < n_ch; c0 += kCombChunk) {
@@ -1808,15 +1840,16 @@ void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::
 // field keeps only 1/V.
 // ----------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type *__restrict__ Ct,
+__global__ __launch_bounds__(256) void k_finalize(const typename ct_t<T>::type *__restrict__ Ct,
                                                   typename cplx_t<T>::type *__restrict__ out, int n_ch, int V,
                                                   const double *__restrict__ energy, double dt, double inv_v,
                                                   double *__restrict__ scale_out, const uint32_t *__restrict__ kmax,
                                                   const int2 *__restrict__ content) {
     using T2 = typename cplx_t<T>::type;
+    using TC = typename ct_t<T>::type;
     // a tile of 256 sites x 16 spins of one channel: read along the sites (one spin
     // row at a time), written as one contiguous run of the [site][spin] output
-    __shared__ T2 tile[256][17];
+    __shared__ TC tile[256][17];
     const int t = threadIdx.x;
     const long nchunk = (V + 255) / 256;
     for (long blk = blockIdx.x; blk < (long)n_ch * nchunk; blk += gridDim.x) {
@@ -1849,8 +1882,12 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
         for (int k = 0; k < 16; ++k) {
             const int idx = k * 256 + t, site = idx >> 4, s = idx & 15;
             if (site < nsite) {
-                const T2 v = tile[site][s];
-                o[idx] = T2{v.x * f, v.y * f};
+                const TC v = tile[site][s];
+                if constexpr (sizeof(T) == 4)    // float-float: one rounding of hi + lo, times 1/V
+                    o[idx] = T2{(T)(((double)v.x.hi + (double)v.x.lo) * (double)f),
+                                (T)(((double)v.y.hi + (double)v.y.lo) * (double)f)};
+                else
+                    o[idx] = T2{v.x * f, v.y * f};
             }
         }
         __syncthreads();
@@ -1858,7 +1895,7 @@ __global__ __launch_bounds__(256) void k_finalize(const typename cplx_t<T>::type
 }
 
 template <typename T>
-void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
+void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
                      const int2 *content, hipStream_t st) {
     const long nblk = (long)n_ch * ((V + 255) / 256);
@@ -1880,6 +1917,7 @@ template int launch_fft3d_zgrouped<float>(float2 *, float2 *, int, const int[3],
 template bool fft3d_zgrouped_fits<double>(const int[3]);
 template bool fft3d_zgrouped_fits<float>(const int[3]);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
+template int launch_fft3d<ff>(ffc *, long, const int[3], int, hipStream_t);
 template void launch_transpose_grouped<double>(const double2 *, double2 *, int, long, int, const int2 *,
                                                hipStream_t);
 template void launch_transpose_grouped<float>(const float2 *, float2 *, int, long, int, const int2 *, hipStream_t);
@@ -1892,11 +1930,11 @@ template void launch_pairs<double>(const double2 *, double2 *, int, const PairDe
 template void launch_pairs<float>(const float2 *, float2 *, int, const PairDevTables &, int, hipStream_t);
 template void launch_pair_combine<double>(const double2 *, double2 *, int, long, const PairDevTables &, int,
                                           hipStream_t);
-template void launch_pair_combine<float>(const float2 *, float2 *, int, long, const PairDevTables &, int,
+template void launch_pair_combine<float>(const float2 *, ffc *, int, long, const PairDevTables &, int,
                                          hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
                                       double *, const uint32_t *, const int2 *, hipStream_t);
-template void launch_finalize<float>(const float2 *, float2 *, int, int, const double *, double, double, double *,
+template void launch_finalize<float>(const ffc *, float2 *, int, int, const double *, double, double, double *,
                                      const uint32_t *, const int2 *, hipStream_t);
 
 }  // namespace bbc

@@ -32,6 +32,29 @@ template <typename T> struct cplx_t;
 template <> struct cplx_t<double> { using type = double2; };
 template <> struct cplx_t<float> { using type = float2; };
 
+// Float-float real: the value hi + lo with |lo| <= ulp(hi) / 2 (about 48
+// significant bits from FP32 arithmetic).  The FP32 form sums the channels in
+// FP64 and keeps them as float-float pairs, and the inverse transform (the sum
+// over momenta that gives C(r)) runs in compensated float-float arithmetic
+// (error-free TwoSum / FMA TwoProd steps, kernels.hip); the field is rounded
+// to FP32 once, when it is written out.
+struct ff {
+    float hi, lo;
+    ff() = default;
+    __host__ __device__ constexpr ff(float h, float l) : hi(h), lo(l) {}
+    __host__ __device__ explicit ff(double d) : hi((float)d), lo((float)(d - (double)(float)d)) {}
+};
+struct ffc {
+    ff x, y;
+};
+template <> struct cplx_t<ff> { using type = ffc; };
+// Type of the contracted field Ct (channel sums, then the inverse transform):
+// FP64 form double2, FP32 form float-float pairs.
+template <typename T> struct ct_t { using type = typename cplx_t<T>::type; };
+template <> struct ct_t<float> { using type = ffc; };
+template <typename T> struct ct_real { using type = T; };
+template <> struct ct_real<float> { using type = ff; };
+
 // Component patterns of the block kernel: components [begin, end) share the
 // flavours of roles a, b, c (0 light, 1 strange) and the spin structure, given
 // as monomial matrices Gamma_1(mu, p1[mu]) = i^k1[mu], Gamma_2(g, p2[g]) = i^k2[g].
@@ -106,11 +129,11 @@ template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
                   const PairDevTables &tb, int variant, hipStream_t st);
 template <typename T>
-void launch_pair_combine(const typename cplx_t<T>::type *P, typename cplx_t<T>::type *Ct, int n_ch, long V,
+void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::type *Ct, int n_ch, long V,
                          const PairDevTables &tb, int variant, hipStream_t st);
 
 template <typename T>
-void launch_finalize(const typename cplx_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
+void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
                      const int2 *content, hipStream_t st);
 
