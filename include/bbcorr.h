@@ -217,7 +217,10 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
  *   pairs   open-index contraction on the matrix cores: FP64 0 = a whole
  *           momentum group per wave, 1 = the same with the loads of the next
  *           open-index step issued ahead, 2 = half a group per wave, 3 = half a
- *           group, loads ahead; FP32 0 = plain, 1 = loads ahead;
+ *           group, loads ahead, 4 = operands staged through LDS (whole group
+ *           lines), 5 = staged, double-buffered, 6 = staged per set of 4
+ *           momenta (half lines), 7 = the same, double-buffered; FP32 0 = plain,
+ *           1 = loads ahead, 2 = staged through LDS, 3 = staged, double-buffered;
  *   blocks  block construction, sites per workgroup x component shares:
  *           0 = 4 x 2, 1 = 4 x 4, 2 = 8 x 2;
  *   planes  x-y plane pass of the forward FFT (square 24- and 32-point planes):
@@ -229,7 +232,9 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
  *           the workspace grows accordingly, and fewer run at once where the
  *           context budget would be exceeded.  Profiled calls run one at a time;
  *   combine channel sums from the pair products: 0 = batches of 8 entries whose
- *           loads are issued together, 1 = batches of 16.
+ *           loads are issued together, 1 = batches of 16, 2 = the pair products
+ *           staged through LDS a chunk at a time (each read once per momentum
+ *           group).
  * A context keeps one choice per request shape; shapes without one take the
  * library's built-in choice.  Graphs captured in graph mode keep the variants
  * of their capture (same results).

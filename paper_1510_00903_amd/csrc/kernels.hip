@@ -1550,6 +1550,157 @@ __device__ __forceinline__ void pair_task64_lds(const double2 *__restrict__ gb, 
     }
 }
 
+// FP64, one set of 4 momenta per wave (set0).  A set is closed under q -> -q
+// (the mirror of group position p is p or p ^ 1), so the wave needs only the
+// set's 128-byte half of each group line: li = (v 4 + kl) 2 + outer spin, wave
+// load v fills the 8 lines of view v (lane / 8 = (kl, outer spin)); the two
+// outer spins of a line pair sit 128 B apart, so a 16-lane LDS read phase hits
+// all 64 banks.
+template <int NP, int SHAPE, bool PIPE>
+__device__ __forceinline__ void pair_task64_lds1(const double2 *__restrict__ gb, double2 *__restrict__ pb,
+                                                 const PTask &T, int lane, int mir, int set0, double2 *wlds) {
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int V = H + NP, NL = 8 * V;
+    constexpr int G = GroupLayout<double2>::G;
+    const int ij = lane & 3, blk = (lane >> 2) & 3, kl = lane >> 4;
+    const int g = ij & 1, o = ij >> 1;
+    const int mm = blk + 4 * set0;
+    const int srow = (T.row_site == 0 ? mm : mir) - 4 * set0, scol = (T.row_site == 0 ? mir : mm) - 4 * set0;
+    const bool colvalid = SHAPE == 0 || ij < 2;
+    const int q = lane >> 3, ld_o = q & 1, ld_kl = q >> 1;
+    const double2 *gsrc = gb + 8 * set0 + (lane & 7);
+    const int K = T.K, nround = (K + 3) / 4;
+    auto issue = [&](int r, int buf) {
+        const int kk0 = r * 4 + ld_kl;
+        const int kk = kk0 < K ? kk0 : 0;                  // past K: an in-range line, never read
+        const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const PView &vw = v < H ? T.row : T.col[v - H];
+            int ostr, base = vw.base;
+            if (SHAPE == 0) ostr = v < H ? outer_stride(T.row, T.row_a) : outer_stride(vw, !T.row_a);
+            else { ostr = v < H ? T.row.so3 : 0; if (v < H) base += v * T.row.so4; }
+            const int comp = base + ld_o * ostr + k3 * vw.sk3 + k4 * vw.sk4;
+            __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * (2 * G)),
+                                             (lds_void *)(wlds + (buf * NL + v * 8) * 8), 16, 0, 0);
+        }
+    };
+    double acc[NP][H][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int h = 0; h < H; ++h) acc[p][h][0] = acc[p][h][1] = 0.0;
+    auto compute = [&](int r, int buf) {
+        const double2 *L = wlds + buf * NL * 8;
+        const bool valid = r * 4 + kl < K;
+        double2 av[H], bv[NP];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            const int li = (h * 4 + kl) * 2 + o;
+            av[h] = L[li * 8 + srow * 2 + g];
+            av[h] = valid ? av[h] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int li = ((H + p) * 4 + kl) * 2 + o;
+            bv[p] = L[li * 8 + scol * 2 + g];
+            bv[p] = (valid && colvalid) ? bv[p] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const double2 a = av[h], b = bv[p];
+                double re = acc[p][h][0], im = acc[p][h][1];
+                re = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.x, re, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f64_4x4x4f64(-a.y, b.y, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.y, im, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, b.x, im, 0, 0, 0);
+                acc[p][h][0] = re;
+                acc[p][h][1] = im;
+            }
+    };
+    issue(0, 0);
+    for (int r = 0; r < nround; ++r) {
+        if constexpr (PIPE) {
+            if (r + 1 < nround) {
+                issue(r + 1, (r + 1) & 1);
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(V));
+            } else {
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            }
+            compute(r, r & 1);
+        } else {
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            compute(r, 0);
+            if (r + 1 < nround) issue(r + 1, 0);
+        }
+    }
+    // D lane (j = lane & 3, block, i = lane >> 4)
+    const int j = lane & 3, i = lane >> 4;
+    if (SHAPE == 1 && j >= 2) return;
+    const int gR = i & 1, oR = i >> 1, gC = j & 1, oC = j >> 1;
+    const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        int ap, bp;
+        if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+        else { ap = oR; bp = h; }
+        const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            pb[((size_t)T.pair[p] * 16 + sp) * G + mm] = double2{acc[p][h][0], acc[p][h][1]};
+    }
+}
+
+// FP64 staged per set: one wave per (task, set of 4 momenta), workgroups of 4
+// waves, the workgroups of a group consecutive on one XCD.
+template <bool PIPE>
+__global__ __launch_bounds__(256) void k_pairs_lds64s(const double2 *__restrict__ Iq, double2 *__restrict__ P, int nc,
+                                                      int ubase, int ucount, const int2 *__restrict__ gpos,
+                                                      int ngroup, const PTask *__restrict__ tasks, int ntask,
+                                                      int npair) {
+    constexpr int G = GroupLayout<double2>::G;
+    constexpr int BUF16 = 8 * kStageMaxViews * 8;          // 16-byte units per wave and buffer (9 KB)
+    constexpr int NBUF = PIPE ? 2 : 1;
+    __shared__ double2 lds[4 * NBUF * BUF16];
+    const int nitem = ntask * 2;
+    const int nchunk = (nitem + 3) >> 2;
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    const int P8 = (ucount + 7) >> 3;
+    const int ul = xcd * P8 + jj / nchunk;
+    const int chunk = jj - (jj / nchunk) * nchunk;
+    if (ul >= ucount) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int item = chunk * 4 + wave;
+    if (item >= nitem) return;
+    const int t = item >> 1, set0 = item & 1;
+    const int lane = threadIdx.x & 63;
+    const int grp = ubase + ul;
+    const double2 *g0 = Iq + (size_t)grp * nc * 2 * G;
+    double2 *p0 = P + (size_t)grp * npair * 16 * G;
+    double2 *wlds = lds + wave * NBUF * BUF16;
+    const int mir = gpos[(size_t)grp * G + ((lane >> 2) & 3) + 4 * set0].y;
+    const PTask &Tk = tasks[t];
+    const int np = __builtin_amdgcn_readfirstlane(Tk.np);
+    const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
+#define BBC_PAIRS_CASE(SH, N) \
+    case N: pair_task64_lds1<N, SH, PIPE>(g0, p0, Tk, lane, mir, set0, wlds); break;
+    if (shape == 0) {
+        switch (np) {
+            BBC_PAIRS_CASE(0, 1) BBC_PAIRS_CASE(0, 2) BBC_PAIRS_CASE(0, 3) BBC_PAIRS_CASE(0, 4)
+            BBC_PAIRS_CASE(0, 5) BBC_PAIRS_CASE(0, 6) BBC_PAIRS_CASE(0, 7) BBC_PAIRS_CASE(0, 8)
+            default: break;
+        }
+    } else {
+        switch (np) {
+            BBC_PAIRS_CASE(1, 1) BBC_PAIRS_CASE(1, 2) BBC_PAIRS_CASE(1, 3) BBC_PAIRS_CASE(1, 4)
+            default: break;
+        }
+    }
+#undef BBC_PAIRS_CASE
+}
+
 // One wave per task of a momentum unit (FP64: one group; FP32: two groups),
 // operands staged through each wave's LDS area; workgroups of 4 waves, the
 // workgroups of a unit consecutive on one XCD.
@@ -1786,9 +1937,25 @@ static void launch_pairs_lds(const typename cplx_t<T>::type *Iq, typename cplx_t
     }
 }
 
+template <bool PIPE>
+static void launch_pairs_lds64s(const double2 *Iq, double2 *P, int nc, const PairDevTables &tb, hipStream_t st) {
+    const int nunit = tb.ngroup;
+    const long nchunk = ((long)tb.ntask * 2 + 3) / 4;
+    if (nchunk == 0) return;
+    const long max_wg = (1L << 32) / 256 - 64;
+    const int per = (int)std::max<long>(8, std::min<long>(nunit, (max_wg / nchunk) / 8 * 8));
+    for (int u0 = 0; u0 < nunit; u0 += per) {
+        const int uc = std::min(per, nunit - u0);
+        const long nwg = 8L * ((uc + 7) / 8) * nchunk;
+        hipLaunchKernelGGL((k_pairs_lds64s<PIPE>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+                           tb.ngroup, tb.tasks, tb.ntask, tb.npair);
+    }
+}
+
 // Variants (same products in the same order, so the same bits): FP64 0 = whole
 // group per wave, 1 = whole group, pipelined, 2 = half group, 3 = half group,
-// pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered;
+// pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered,
+// 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered;
 // FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
 // double-buffered.
 template <typename T>
@@ -1801,6 +1968,8 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
         case 3: launch_pairs_v<T, 1, true>(Iq, P, nc, tb, st); break;
         case 4: launch_pairs_lds<T, false>(Iq, P, nc, tb, st); break;
         case 5: launch_pairs_lds<T, true>(Iq, P, nc, tb, st); break;
+        case 6: launch_pairs_lds64s<false>(Iq, P, nc, tb, st); break;
+        case 7: launch_pairs_lds64s<true>(Iq, P, nc, tb, st); break;
         default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
         }
     } else {
@@ -1813,7 +1982,73 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
     }
 }
 
-// Variants: entries per load batch, 0 = 8, 1 = 16 (same sums in the same order).
+// Channel sums with the pair products staged through LDS: the workgroup of a
+// momentum group copies PC consecutive pairs at a time (contiguous in P) into
+// LDS with 16-byte lanes, then every lane applies its class's entries for those
+// pairs from LDS, so each pair product is read from memory once per group (the
+// classes of the direct form read a pair at different times, after it has left
+// L2).  Lanes, sums and their order are those of k_pair_combine.  (Tried and
+// slower: a second LDS buffer filled by direct loads while the first is used,
+// and batches of LDS reads; both need registers that cost a workgroup per CU.)
+template <typename T, int PC>
+__global__ __launch_bounds__(1024) void k_pair_combine_lds(const typename cplx_t<T>::type *__restrict__ P,
+                                                           typename ct_t<T>::type *__restrict__ Ct, int ch0,
+                                                           int nch, long V, const int2 *__restrict__ gpos, int gbase,
+                                                           int npair, const CombEntry *__restrict__ comb,
+                                                           const int32_t *__restrict__ comb_begin) {
+    using T2 = typename cplx_t<T>::type;
+    constexpr int G = GroupLayout<T2>::G;
+    constexpr int NJ = kCombChunk / kCombSubs;
+    constexpr int PAIR16 = 16 * G * (int)sizeof(T2) / 16;      // 16-byte units per pair
+    __shared__ float4 stage[PC * PAIR16];
+    const int grp = gbase + blockIdx.x;
+    const int t = threadIdx.x;
+    const int sub = __builtin_amdgcn_readfirstlane(t >> 7);
+    const int s = (t >> 3) & 15, slot = t & 7;
+    const float4 *pg4 = (const float4 *)(P + (size_t)grp * npair * 16 * G);
+    const T2 *st2 = (const T2 *)stage + s * G + slot;
+    double2 acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = double2{0.0, 0.0};
+    int e = comb_begin[sub];
+    const int ee = comb_begin[sub + 1];
+    for (int p0 = 0; p0 < npair; p0 += PC) {
+        const int np = min(PC, npair - p0);
+        __syncthreads();                                           // previous chunk consumed
+        for (int i = t; i < np * PAIR16; i += 1024) stage[i] = pg4[(size_t)p0 * PAIR16 + i];
+        __syncthreads();
+        // this class's entries with pairs in [p0, p0 + np), in ascending pair order
+        while (e < ee) {
+            const CombEntry ce = comb[e];
+            if (ce.pair >= p0 + np) break;
+            const T2 v = st2[(size_t)(ce.pair - p0) * 16 * G];
+            const int j = ce.ch >> 3;
+            switch (j) {
+#define BBC_COMB_CASE(J) \
+    case J: acc[J].x = fma(ce.w, (double)v.x, acc[J].x); acc[J].y = fma(ce.w, (double)v.y, acc[J].y); break;
+                BBC_COMB_CASE(0) BBC_COMB_CASE(1) BBC_COMB_CASE(2) BBC_COMB_CASE(3)
+                BBC_COMB_CASE(4) BBC_COMB_CASE(5) BBC_COMB_CASE(6) BBC_COMB_CASE(7)
+#undef BBC_COMB_CASE
+                default: break;
+            }
+            ++e;
+        }
+    }
+    const int q = gpos[(size_t)grp * G + slot].x;
+    if (q < 0) return;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int ch = sub + 8 * j;
+        if (ch >= nch) continue;
+        if constexpr (sizeof(T) == 4)
+            Ct[((size_t)(ch0 + ch) * 16 + s) * V + q] = ffc{ff(acc[j].x), ff(acc[j].y)};
+        else
+            Ct[((size_t)(ch0 + ch) * 16 + s) * V + q] = T2{(T)acc[j].x, (T)acc[j].y};
+    }
+}
+
+// Variants (same sums in the same order): entries per load batch, 0 = 8, 1 = 16;
+// 2 = pair products staged through LDS, 32 pairs at a time (FP64 64 KB, FP32 32 KB).
 template <typename T>
 void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::type *Ct, int n_ch, long V,
                          const PairDevTables &tb, int variant, hipStream_t st) {
@@ -1823,7 +2058,10 @@ void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::ty
         const int32_t *cb = tb.comb_begin + (size_t)(c0 / kCombChunk) * kCombSubs;
         for (long g0 = 0; g0 < tb.ngroup; g0 += max_wg) {
             const long gc = std::min<long>(max_wg, tb.ngroup - g0);
-            if (variant == 1)
+            if (variant == 2)
+                hipLaunchKernelGGL((k_pair_combine_lds<T, 32>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch,
+                                   V, tb.gpos, (int)g0, tb.npair, tb.comb, cb);
+            else if (variant == 1)
                 hipLaunchKernelGGL((k_pair_combine<T, 16>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch, V,
                                    tb.gpos, (int)g0, tb.npair, tb.comb, cb);
             else

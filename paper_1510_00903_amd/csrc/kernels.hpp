@@ -81,18 +81,20 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 // the same order, so the results are the same bits; only speed differs):
 //   pairs  - pair-product kernel: FP64 0 = whole group per wave, 1 = pipelined,
 //            2 = half group per wave, 3 = half group, pipelined, 4 = operands staged
-//            through LDS, 5 = staged, double-buffered; FP32 0, 1 = pipelined,
+//            through LDS, 5 = staged, double-buffered, 6 = staged per set of 4 momenta,
+//            7 = the same, double-buffered; FP32 0, 1 = pipelined,
 //            2 = staged through LDS, 3 = staged, double-buffered;
 //   blocks - block kernel sites per workgroup x component shares: 0 = 4x2, 1 = 4x4, 2 = 8x2;
 //   planes - plane-pass FFT planes per workgroup: 0 = as many as 80 KB of LDS hold, 1 = half;
 //   slices - time slices of one request run at once (1 << slices), each on its own
 //            stream and workspace;
-//   combine - channel sums: entries per load batch, 0 = 8, 1 = 16.
+//   combine - channel sums: entries per load batch, 0 = 8, 1 = 16; 2 = pair products staged
+//            through LDS (read once per group).
 struct Tuning {
     int pairs = 0, blocks = 0, planes = 0, slices = 0, combine = 0;
 };
-constexpr int kPairVariants64 = 6, kPairVariants32 = 4, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
-              kCombineVariants = 2;
+constexpr int kPairVariants64 = 8, kPairVariants32 = 4, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
+              kCombineVariants = 3;
 constexpr int kMaxSliceStreams = 1 << (kSliceVariants - 1);
 
 // FP32 form: per-flavour max |Re|,|Im| of a slice into kmax[0] (light), kmax[1] (strange).
