@@ -596,11 +596,16 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     // small cubic lattices: one fused pass (FFT in LDS, written straight into the
     // groups); 24- and 32-point planes: plane passes, then the z pass writes into
     // the groups; otherwise axis passes and a separate copy into the groups
-    const bool fused = bbc::fft3d_grouped_fits<T>(L);
+    // FP32 cubic 32-point lattices: one pass too (z in registers, x and y in LDS,
+    // written into the run-ordered groups)
+    const bool onepass = mg.xrun && bbc::fft3d_onepass_fits<T>(L);
+    const bool fused = onepass || bbc::fft3d_grouped_fits<T>(L);
     const bool zgrouped = !fused && bbc::fft3d_zgrouped_fits<T>(L);
     {
         StageTimer tm(pc, st, 1);
-        if (fused) {
+        if (onepass) {
+            if (bbc::launch_fft3d_onepass<T>(I, Iq, nc, L, mg.xrun, st)) return fail(BBC_EUNSUPPORTED, "FFT size");
+        } else if (fused) {
             if (bbc::launch_fft3d_grouped<T>(I, Iq, nc, L, mg.ngroup, mg.pos, st))
                 return fail(BBC_EUNSUPPORTED, "FFT size");
         } else if (zgrouped) {

@@ -650,10 +650,13 @@ template <> struct GroupLayout<double2> {
     static constexpr int S = 2;      // stride of the momentum lane
     static constexpr int SG = 1;     // stride of the sink spin
 };
+// FP32: spin-major inside a group line ([c][g][G]): the 8 momenta of one sink
+// spin are 64 contiguous bytes, so a writer that holds one spin (the one-pass
+// FFT) stores whole 64-byte sectors.
 template <> struct GroupLayout<float2> {
     static constexpr int G = 8;
-    static constexpr int S = 2;
-    static constexpr int SG = 1;
+    static constexpr int S = 1;
+    static constexpr int SG = 8;
 };
 
 // Tile: 64 positions x TC components x both sink spins through LDS; read along
@@ -936,6 +939,148 @@ static bool fft_z_runs_lz(const typename cplx_t<T>::type *in, typename cplx_t<T>
     case 24: fft_z_runs<T, LX, 24>(in, out, nc, xrun, st); return true;
     case 32: fft_z_runs<T, LX, 32>(in, out, nc, xrun, st); return true;
     default: return false;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// One-pass forward 3-D FFT of cubic 32-point (or 24-point) lattices in FP32, written
+// into the run-ordered momentum groups: one workgroup per (component, sink
+// spin) reads the component once, with its L^2 z lines in registers (two per
+// thread) and transformed there; the kz planes are then taken in two batches,
+// each closed under kz -> -kz (A: kz <= L/4 or kz >= L - L/4; B: the rest), so
+// that every x-row run lies in one batch: a batch's planes go to LDS, their x
+// and y lines are transformed there, and the batch's runs are written as whole
+// 64-byte spin sectors (GroupLayout<float2> is spin-major).  The z transform
+// comes first here and last in the two-pass form, so the two differ by
+// rounding only.  Replaces the plane pass and the z pass (two HBM round trips)
+// for these lattices.
+// ----------------------------------------------------------------------------
+template <int L>
+__host__ __device__ constexpr int onepass_na() { return L / 4; }
+// plane slot of kz in batch b (-1 if not in it), and the kz of slot p
+template <int L>
+__device__ __forceinline__ int onepass_slot(int b, int kz) {
+    constexpr int NA = onepass_na<L>(), PA = 2 * NA + 1;
+    if (b == 0) return kz <= NA ? kz : (kz >= L - NA ? PA - (L - kz) : -1);
+    return (kz > NA && kz < L - NA) ? kz - NA - 1 : -1;
+}
+template <int L>
+__device__ __forceinline__ int onepass_kz(int b, int p) {
+    constexpr int NA = onepass_na<L>(), PA = 2 * NA + 1;
+    if (b == 0) return p <= NA ? p : L - (PA - p);
+    return NA + 1 + p;
+}
+
+template <int L>
+__global__ __launch_bounds__(L * L / 2) void k_fft3d_onepass(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                             int nc, const int *__restrict__ xrun, int sgn) {
+    using Ly = GroupLayout<float2>;
+    constexpr int G = Ly::G;
+    constexpr int NT = L * L / 2;                  // threads; thread t holds z lines t and t + NT
+    constexpr int NA = onepass_na<L>(), PA = 2 * NA + 1, PB = L - PA;
+    constexpr int LP = L + 1;                      // padded row
+    __shared__ float2 buf[PA][L][LP];
+    __shared__ float2 tw[L];
+    const int t = threadIdx.x;
+    // the two sink spins of a component run back to back on one XCD
+    const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
+    const int g = jb & 1, c = xcd * (int)(gridDim.x >> 4) + (jb >> 1);
+    if (c >= nc) return;                           // whole workgroup
+    for (int i = t; i < L; i += NT) {
+        double sn, cs;
+        sincospi(2.0 * i / L, &sn, &cs);
+        tw[i] = float2{(float)cs, (float)(sgn * sn)};
+    }
+    const float2 *src = in + ((long)g * nc + c) * (long)(L * L * L);
+    float2 a0[L], a1[L], bt[L];
+#pragma unroll
+    for (int kz = 0; kz < L; ++kz) {
+        a0[kz] = src[kz * L * L + t];
+        a1[kz] = src[kz * L * L + t + NT];
+    }
+    __syncthreads();                               // twiddles
+    Stages<float2, L, 1>::run(a0, bt, tw, sgn);
+    Stages<float2, L, 1>::run(a1, bt, tw, sgn);
+    const int x0 = t % L, y0 = t / L, x1 = (t + NT) % L, y1 = (t + NT) / L;
+    float2 *dst = out + (long)c * 2 * G + g * Ly::SG;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int np = b == 0 ? PA : PB;
+        if (b == 1) __syncthreads();               // batch A's runs written
+#pragma unroll
+        for (int kz = 0; kz < L; ++kz) {
+            const int p = onepass_slot<L>(b, kz);
+            if (p >= 0) {
+                buf[p][y0][x0] = a0[kz];
+                buf[p][y1][x1] = a1[kz];
+            }
+        }
+        __syncthreads();
+        for (int l = t; l < np * L; l += NT) {     // x lines (plane p, row y)
+            const int p = l / L, y = l - p * L;
+            float2 v[L], w[L];
+#pragma unroll
+            for (int x = 0; x < L; ++x) v[x] = buf[p][y][x];
+            Stages<float2, L, 1>::run(v, w, tw, sgn);
+#pragma unroll
+            for (int x = 0; x < L; ++x) buf[p][y][x] = v[x];
+        }
+        __syncthreads();
+        for (int l = t; l < np * L; l += NT) {     // y lines (plane p, column x)
+            const int p = l / L, x = l - p * L;
+            float2 v[L], w[L];
+#pragma unroll
+            for (int y = 0; y < L; ++y) v[y] = buf[p][y][x];
+            Stages<float2, L, 1>::run(v, w, tw, sgn);
+#pragma unroll
+            for (int y = 0; y < L; ++y) buf[p][y][x] = v[y];
+        }
+        __syncthreads();
+        // the runs of this batch's x-rows r = (ky, kz) with mirror m = (-ky, -kz) >= r:
+        // position s of a run -> (kx, row) as in k_fft_z_runs
+        for (int it = t; it < np * L * 2 * L; it += NT) {
+            const int s = it % (2 * L), row = it / (2 * L);
+            const int p = row / L, ky = row - p * L;
+            const int kz = onepass_kz<L>(b, p);
+            const int kym = (L - ky) % L, kzm = (L - kz) % L;
+            const int r = ky + L * kz, m = kym + L * kzm;
+            if (m < r) continue;                   // written from the mirror row
+            const bool self = m == r;
+            if (self && s >= L) continue;
+            const int j = s >> 1;
+            int x, yy = ky, pz = p;
+            if (self) {
+                x = s == 0 ? 0 : s == 1 ? L / 2 : ((s & 1) ? L - j : j);
+            } else if (s & 1) {
+                x = (L - j) % L; yy = kym; pz = onepass_slot<L>(b, kzm);
+            } else {
+                x = j;
+            }
+            dst[(long)(xrun[r] + s / G) * nc * 2 * G + (s % G) * Ly::S] = buf[pz][yy][x];
+        }
+    }
+}
+
+// Whether the one-pass form is used: FP32, cubic 32, run-ordered groups.  (At
+// 24^3 it is correct but slower than the two passes: with 288 threads and one
+// workgroup per CU its serial phases are not hidden; 2.26 ms per 52-channel slice.)
+template <typename T> bool fft3d_onepass_fits(const int L[3]) {
+    return sizeof(T) == 4 && L[0] == L[1] && L[1] == L[2] && L[0] == 32;
+}
+
+template <typename T>
+int launch_fft3d_onepass(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
+                         const int *xrun, hipStream_t st) {
+    if constexpr (sizeof(T) != 4) {
+        return -1;
+    } else {
+        if (!fft3d_onepass_fits<T>(L) || !xrun) return -1;
+        const dim3 grid((unsigned)(16 * ((nc + 7) / 8)));   // 8 XCDs x 2 spins x ceil(nc / 8)
+        if (L[0] == 24)
+            hipLaunchKernelGGL((k_fft3d_onepass<24>), grid, dim3(24 * 24 / 2), 0, st, in, out, nc, xrun, -1);
+        else
+            hipLaunchKernelGGL((k_fft3d_onepass<32>), grid, dim3(32 * 32 / 2), 0, st, in, out, nc, xrun, -1);
+        return 0;
     }
 }
 
@@ -1360,13 +1505,13 @@ __device__ __forceinline__ void pair_task32_lds(const float2 *__restrict__ gb0, 
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int li = ((h * 2 + gl) * 2 + kr) * 2 + o;
-                av[h] = L2[li * 16 + srow * 2 + g];
+                av[h] = L2[li * 16 + srow * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
                 av[h] = active ? av[h] : float2{0.f, 0.f};
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int li = (((H + p) * 2 + gl) * 2 + kr) * 2 + o;
-                bv[p] = L2[li * 16 + scol * 2 + g];
+                bv[p] = L2[li * 16 + scol * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
                 bv[p] = colvalid ? bv[p] : float2{0.f, 0.f};
             }
 #pragma unroll
@@ -2153,6 +2298,10 @@ template int launch_fft3d_zgrouped<double>(double2 *, double2 *, int, const int[
 template int launch_fft3d_zgrouped<float>(float2 *, float2 *, int, const int[3], const int *, const int *, int,
                                            hipStream_t);
 template bool fft3d_zgrouped_fits<double>(const int[3]);
+template bool fft3d_onepass_fits<double>(const int[3]);
+template bool fft3d_onepass_fits<float>(const int[3]);
+template int launch_fft3d_onepass<double>(const double2 *, double2 *, int, const int[3], const int *, hipStream_t);
+template int launch_fft3d_onepass<float>(const float2 *, float2 *, int, const int[3], const int *, hipStream_t);
 template bool fft3d_zgrouped_fits<float>(const int[3]);
 template int launch_fft3d<float>(float2 *, long, const int[3], int, hipStream_t);
 template int launch_fft3d<ff>(ffc *, long, const int[3], int, hipStream_t);

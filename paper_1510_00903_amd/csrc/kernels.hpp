@@ -111,6 +111,13 @@ template <typename T>
 int launch_fft3d_zgrouped(typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
                           const int *posof, const int *xrun, int plane_variant, hipStream_t st);
 
+// One-pass forward FFT into the run-ordered groups (FP32, cubic 24 or 32):
+// -1 where it does not apply.
+template <typename T> bool fft3d_onepass_fits(const int L[3]);
+template <typename T>
+int launch_fft3d_onepass(const typename cplx_t<T>::type *in, typename cplx_t<T>::type *out, int nc, const int L[3],
+                         const int *xrun, hipStream_t st);
+
 // Momentum-grouped copy: in [g][nc][V] (component-major) -> out, per group of G
 // = 8 momenta and component, the G momenta and both sink spins ([c][G][g]);
 // gpos is the position table of the groups.

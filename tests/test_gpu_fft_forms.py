@@ -4,7 +4,8 @@ The 3-D transforms of Sec. 3 Eq. (LN.pLLp.FFT) take different kernels by
 lattice shape and precision: the fused one-pass form for cubic lattices with
 L in {4, 6, 8, 12, 16} (both precisions), the plane pass with the z pass
 written into the momentum groups (24- and 32-point planes, z in
-{2, 3, 4, 6, 8, 12, 16, 24, 32}; 96-point planes in FP32), and per-axis line
+{2, 3, 4, 6, 8, 12, 16, 24, 32}; 96-point planes in FP32), the one-pass form of
+cubic 32^3 lattices in FP32, and per-axis line
 transforms otherwise (inverse transforms always).  This file reaches the forms
 the other parity tests do not: the fused form in FP32 for every L and in FP64
 for L = 6 and 12, 6- and 12-point lines, and the z pass for z in
@@ -168,3 +169,19 @@ def test_plane_pass_z_grouped_lengths(bbc, ctx, lat):
         for prec in ("f64", "f32"):
             e = normwise(_at(res[prec][0, m], r), ref)
             assert e < TOL[prec], (lat, prec, c, e)
+
+
+@pytest.mark.parametrize("L,chans", [(24, [0, 5, 30, 51]), (32, [1, 30])])
+def test_onepass_cubic_fp32_sampled_points(bbc, ctx, L, chans):
+    """Cubic 24^3 and 32^3 lattices in both forms against the oracle at r in {0, L/2}^3
+    and two more points: at 32^3 the FP32 form takes the one-pass forward FFT (z lines
+    in registers, x and y planes in LDS in two mirror-closed batches, written into the
+    run-ordered groups), the others the plane pass and then the z pass."""
+    lat = (L, L, L)
+    res, s64l, s64s = _both(ctx, lat, [5], chans, seed=330 + L)
+    r = _special_and_random(lat, 2, seed=L + 1)
+    for m, c in enumerate(chans):
+        ref = wick.correlate(s64l[0], s64s[0], ops.CHANNELS[c], r)
+        for prec in ("f64", "f32"):
+            e = normwise(_at(res[prec][0, m], r), ref)
+            assert e < TOL[prec], (L, prec, c, e)
