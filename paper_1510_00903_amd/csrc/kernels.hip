@@ -1451,18 +1451,19 @@ __host__ __device__ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4)
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// FP32: one task for two groups (16 momenta), KS = 2 open indices per round.
-// Lines (128 B: one component, both sink spins of the group's 8 momenta):
-// li = ((v 2 + group) 2 + kr) 2 + outer spin for the V = H + NP views (row
-// halves, then partners); wave load v fills the 8 lines of view v, so the view's
-// offsets are wave-uniform; the two outer spins of a line pair sit 128 B apart
-// (all 64 banks for one LDS read).
-template <int NP, int SHAPE, bool PIPE>
+// FP32: one task for two groups (16 momenta), KS (2 or 4) open indices per
+// round.  Lines (128 B: one component, both sink spins of the group's 8 momenta):
+// li = ((v KS + kr) 2 + group) 2 + outer spin for the V = H + NP views (row
+// halves, then partners); wave load w fills lines 8w .. 8w + 7, i.e. two open
+// indices of one view, so the view's offsets are wave-uniform; the two outer
+// spins of a line pair sit 128 B apart (all 64 banks for one LDS read).  More
+// open indices per round give each wave more products per copy round trip.
+template <int NP, int SHAPE, bool PIPE, int KS>
 __device__ __forceinline__ void pair_task32_lds(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
                                                 float2 *__restrict__ pb0, float2 *__restrict__ pb1, bool has1,
                                                 const PTask &T, int lane, int mir, float4 *wlds) {
     constexpr int H = SHAPE == 1 ? 2 : 1;
-    constexpr int V = H + NP, KS = 2, NL = 8 * V;
+    constexpr int V = H + NP, NL = 4 * KS * V, WL = NL / 8;
     constexpr int G = GroupLayout<float2>::G;
     const int ij = lane & 3, blk = lane >> 2;
     const int g = ij & 1, o = ij >> 1;
@@ -1471,23 +1472,27 @@ __device__ __forceinline__ void pair_task32_lds(const float2 *__restrict__ gb0, 
     const int m = blk & 7;
     const int srow = T.row_site == 0 ? m : mir, scol = T.row_site == 0 ? mir : m;
     const bool colvalid = active && (SHAPE == 0 || ij < 2);
-    // this lane's line within each wave load: q = lane / 8 = (group, kr, outer spin)
-    const int q = lane >> 3, ld_o = q & 1, ld_kr = (q >> 1) & 1, ld_g1 = q >> 2;
+    // this lane's line within a wave load: q = lane / 8 = (kr & 1, group, outer spin)
+    const int q = lane >> 3, ld_o = q & 1, ld_g1 = (q >> 1) & 1, ld_kr = q >> 2;
     const float4 *gsrc = (const float4 *)(ld_g1 ? gb1 : gb0) + (lane & 7);
     const int K = T.K, nround = (K + KS - 1) / KS;
     auto issue = [&](int r, int buf) {
-        const int kk0 = r * KS + ld_kr;
-        const int kk = kk0 < K ? kk0 : 0;                  // past K: an in-range line, never read
-        const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const PView &vw = v < H ? T.row : T.col[v - H];
-            int ostr, base = vw.base;
-            if (SHAPE == 0) ostr = v < H ? outer_stride(T.row, T.row_a) : outer_stride(vw, !T.row_a);
-            else { ostr = v < H ? T.row.so3 : 0; if (v < H) base += v * T.row.so4; }
-            const int comp = base + ld_o * ostr + k3 * vw.sk3 + k4 * vw.sk4;
-            __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * G),
-                                             (lds_void *)(wlds + (buf * NL + v * 8) * 8), 16, 0, 0);
+        for (int hk = 0; hk < KS / 2; ++hk) {
+            const int kk0 = r * KS + 2 * hk + ld_kr;
+            const int kk = kk0 < K ? kk0 : 0;              // past K: an in-range line, never read
+            const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const PView &vw = v < H ? T.row : T.col[v - H];
+                int ostr, base = vw.base;
+                if (SHAPE == 0) ostr = v < H ? outer_stride(T.row, T.row_a) : outer_stride(vw, !T.row_a);
+                else { ostr = v < H ? T.row.so3 : 0; if (v < H) base += v * T.row.so4; }
+                const int comp = base + ld_o * ostr + k3 * vw.sk3 + k4 * vw.sk4;
+                __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * G),
+                                                 (lds_void *)(wlds + (buf * NL + (v * (KS / 2) + hk) * 8) * 8), 16,
+                                                 0, 0);
+            }
         }
     };
     fmfma4 acc[NP][H][2];
@@ -1504,13 +1509,13 @@ __device__ __forceinline__ void pair_task32_lds(const float2 *__restrict__ gb0, 
             float2 av[H], bv[NP];
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                const int li = ((h * 2 + gl) * 2 + kr) * 2 + o;
+                const int li = ((h * KS + kr) * 2 + gl) * 2 + o;
                 av[h] = L2[li * 16 + srow * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
                 av[h] = active ? av[h] : float2{0.f, 0.f};
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const int li = (((H + p) * 2 + gl) * 2 + kr) * 2 + o;
+                const int li = (((H + p) * KS + kr) * 2 + gl) * 2 + o;
                 bv[p] = L2[li * 16 + scol * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
                 bv[p] = colvalid ? bv[p] : float2{0.f, 0.f};
             }
@@ -1534,7 +1539,7 @@ __device__ __forceinline__ void pair_task32_lds(const float2 *__restrict__ gb0, 
         if constexpr (PIPE) {
             if (r + 1 < nround) {
                 issue(r + 1, (r + 1) & 1);
-                __builtin_amdgcn_s_waitcnt(vmcnt_imm(V));
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(WL));
             } else {
                 __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
             }
@@ -1849,7 +1854,7 @@ __global__ __launch_bounds__(256) void k_pairs_lds64s(const double2 *__restrict_
 // One wave per task of a momentum unit (FP64: one group; FP32: two groups),
 // operands staged through each wave's LDS area; workgroups of 4 waves, the
 // workgroups of a unit consecutive on one XCD.
-template <typename T, bool PIPE>
+template <typename T, bool PIPE, int KS = 2>
 __global__ __launch_bounds__(256) void k_pairs_lds(const typename cplx_t<T>::type *__restrict__ Iq,
                                                    typename cplx_t<T>::type *__restrict__ P, int nc, int ubase,
                                                    int ucount, const int2 *__restrict__ gpos, int ngroup,
@@ -1857,8 +1862,8 @@ __global__ __launch_bounds__(256) void k_pairs_lds(const typename cplx_t<T>::typ
     using T2 = typename cplx_t<T>::type;
     constexpr int G = GroupLayout<T2>::G;
     constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;
-    // per wave and buffer: FP32 8 V lines of 128 B (2 open indices), FP64 8 V lines of 256 B (4)
-    constexpr int BUF16 = sizeof(T) == 8 ? 8 * kStageMaxViews * 16 : 8 * kStageMaxViews * 8;   // 16-byte units
+    // per wave and buffer: FP32 4 KS V lines of 128 B (KS open indices), FP64 8 V lines of 256 B (4)
+    constexpr int BUF16 = sizeof(T) == 8 ? 8 * kStageMaxViews * 16 : 4 * KS * kStageMaxViews * 8;   // 16-byte units
     constexpr int NBUF = PIPE ? 2 : 1;
     __shared__ float4 lds[4 * NBUF * BUF16];
     const int nchunk = (ntask + 3) >> 2;
@@ -1896,7 +1901,7 @@ __global__ __launch_bounds__(256) void k_pairs_lds(const typename cplx_t<T>::typ
 #define BBC_PAIRL_CASE(SH, N)                                                                                  \
     case N:                                                                                                    \
         if constexpr (sizeof(T) == 8) pair_task64_lds<N, SH, PIPE>(g0, p0, Tk, lane, mir, (double2 *)wlds);   \
-        else pair_task32_lds<N, SH, PIPE>(g0, g1, p0, p1, has1, Tk, lane, mir[0], wlds);                     \
+        else pair_task32_lds<N, SH, PIPE, KS>(g0, g1, p0, p1, has1, Tk, lane, mir[0], wlds);                 \
         break;
     if (shape == 0) {
         switch (np) {
@@ -2065,7 +2070,7 @@ static void launch_pairs_v(const typename cplx_t<T>::type *Iq, typename cplx_t<T
     }
 }
 
-template <typename T, bool PIPE>
+template <typename T, bool PIPE, int KS = 2>
 static void launch_pairs_lds(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc,
                              const PairDevTables &tb, hipStream_t st) {
     constexpr int GPU_ = sizeof(T) == 8 ? 1 : 2;
@@ -2077,7 +2082,7 @@ static void launch_pairs_lds(const typename cplx_t<T>::type *Iq, typename cplx_t
     for (int u0 = 0; u0 < nunit; u0 += per) {
         const int uc = std::min(per, nunit - u0);
         const long nwg = 8L * ((uc + 7) / 8) * nchunk;
-        hipLaunchKernelGGL((k_pairs_lds<T, PIPE>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+        hipLaunchKernelGGL((k_pairs_lds<T, PIPE, KS>), dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
                            tb.ngroup, tb.tasks, tb.ntask, tb.npair);
     }
 }
@@ -2102,7 +2107,7 @@ static void launch_pairs_lds64s(const double2 *Iq, double2 *P, int nc, const Pai
 // pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered,
 // 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered;
 // FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
-// double-buffered.
+// double-buffered, 4 = staged, 4 open indices per round.
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
                   int variant, hipStream_t st) {
@@ -2122,6 +2127,7 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
         case 1: launch_pairs_v<T, 2, true>(Iq, P, nc, tb, st); break;
         case 2: launch_pairs_lds<T, false>(Iq, P, nc, tb, st); break;
         case 3: launch_pairs_lds<T, true>(Iq, P, nc, tb, st); break;
+        case 4: launch_pairs_lds<T, false, 4>(Iq, P, nc, tb, st); break;
         default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
         }
     }

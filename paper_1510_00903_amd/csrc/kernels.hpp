@@ -83,7 +83,8 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 //            2 = half group per wave, 3 = half group, pipelined, 4 = operands staged
 //            through LDS, 5 = staged, double-buffered, 6 = staged per set of 4 momenta,
 //            7 = the same, double-buffered; FP32 0, 1 = pipelined,
-//            2 = staged through LDS, 3 = staged, double-buffered;
+//            2 = staged through LDS, 3 = staged, double-buffered, 4 = staged, 4 open
+//            indices per round;
 //   blocks - block kernel sites per workgroup x component shares: 0 = 4x2, 1 = 4x4, 2 = 8x2;
 //   planes - plane-pass FFT planes per workgroup: 0 = as many as 80 KB of LDS hold, 1 = half;
 //   slices - time slices of one request run at once (1 << slices), each on its own
@@ -93,7 +94,7 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 struct Tuning {
     int pairs = 0, blocks = 0, planes = 0, slices = 0, combine = 0;
 };
-constexpr int kPairVariants64 = 8, kPairVariants32 = 4, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
+constexpr int kPairVariants64 = 8, kPairVariants32 = 5, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
               kCombineVariants = 3;
 constexpr int kMaxSliceStreams = 1 << (kSliceVariants - 1);
 
