@@ -106,23 +106,31 @@ def cpu_baseline(Sl, Ss, t_idx, budget_s=20.0):
                       % (t_idx, len(done), [list(p) for p in r_points[:1 + (len(done) - 1) // 13]], el)}
 
 
-def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96,
-                runs=((0.5, 4), (0.8, 4), (1.2, 4), (1.2, 1))):
+SERVE_LARGE = ((16, 32), (24, 48), (32, 64))
+SERVE_SMALL = ((8, 8), (12, 12), (16, 16))
+
+
+def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96, lattices=SERVE_LARGE, max_t=16, presets=0,
+                runs=((0.5, 4, False), (0.8, 4, False), (0.8, 4, True), (1.2, 4, False), (1.2, 4, True),
+                      (1.2, 1, False))):
     """Continuous-batching serving on a Poisson stream of mixed jobs (FP32 form),
     under a finite HBM budget (resident propagator sets plus slot workspaces).
 
-    Jobs: lattice uniform over {16^3x32, 24^3x48, 32^3x64}, channel subset of
-    size U[4,52] drawn without replacement, n_t U[4,16] distinct slices, one of
-    4 resident propagator sets per lattice (seeded PCG64, seed 1510009034).
+    Jobs: lattice (L, T) uniform over `lattices` (default 16^3x32, 24^3x48,
+    32^3x64), channel subset of size U[4,52] drawn without replacement (or, with
+    presets > 0, one of that many such subsets drawn first: recurring analysis
+    requests), n_t U[4,max_t] distinct slices (at most T), one of 4 resident
+    propagator sets per lattice (seeded PCG64, seed 1510009034).
     The service rate mu is measured by running all jobs one after another on a
     single slot, which also gives every job's result alone (kept on the device).
-    Each run then replays the stream with Poisson arrivals at load x mu on the
-    given number of slots and reports p50/p99 latency (submit to completion) and
-    throughput; every job's result in the mix is compared bit for bit with its
-    result alone.
+    Each run (load, slots, graphs) then replays the stream with Poisson arrivals
+    at load x mu on the given number of slots, with the slots replaying captured
+    slices (graph mode) or launching every kernel, and reports p50/p99 latency
+    (submit to completion) and throughput; every job's result in the mix is
+    compared bit for bit with its result alone.
     """
     dev = torch.device("cuda:0")
-    lattices = [(16, 32), (24, 48), (32, 64)]
+    lattices = list(lattices)
     rng = np.random.Generator(np.random.PCG64(1510009034))
     budget = int(budget_gb) << 30
     ctx = bbc.Context(0, hbm_budget_bytes=budget)
@@ -142,15 +150,19 @@ def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96,
             del Sl, Ss
     torch.cuda.empty_cache()
     jobs = []
+    preset = [sorted(rng.choice(52, size=int(rng.integers(4, 53)), replace=False).tolist()) for _ in range(presets)]
     for _ in range(n_jobs):
         li = int(rng.integers(0, 3))
         L, T = lattices[li]
-        n_ch = int(rng.integers(4, 53))
-        ch = sorted(rng.choice(52, size=n_ch, replace=False).tolist())
-        n_t = int(rng.integers(4, 17))
+        if presets:
+            ch = preset[int(rng.integers(0, presets))]
+        else:
+            n_ch = int(rng.integers(4, 53))
+            ch = sorted(rng.choice(52, size=n_ch, replace=False).tolist())
+        n_t = int(rng.integers(4, min(max_t, T) + 1))
         sl = sorted(rng.choice(T, size=n_t, replace=False).tolist())
         jobs.append({"li": li, "L": L, "prop": props[(li, int(rng.integers(0, 4)))], "ch": ch, "sl": sl,
-                     "sites": L ** 3 * n_t * n_ch})
+                     "sites": L ** 3 * n_t * len(ch)})
 
     def run_job(j):
         L = j["L"]
@@ -172,15 +184,33 @@ def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96,
         ctx.job_forget(jid)
     single_s = time.perf_counter() - t0
     ctx.server_stop()
+    # the same single stream with the slot replaying captured slices (each job's
+    # first slice captures its shape's graph; later slices replay it)
+    ctx.graph_mode(True)
+    ctx.server_start(1)
+    service_g, same_g = [], 0
+    t0 = time.perf_counter()
+    for j, (aout, ascale) in zip(jobs, alone):
+        jid, out, scale = run_job(j)
+        ctx.wait(jid)
+        service_g.append(ctx.job_times(jid)[1])
+        same_g += bool(torch.equal(out, aout)) and bool(torch.equal(scale, ascale))
+        ctx.job_forget(jid)
+        del out, scale
+    single_g = time.perf_counter() - t0
+    ctx.server_stop()
+    ctx.graph_mode(False)
     mu = n_jobs / single_s
     sites = sum(j["sites"] for j in jobs)
     results = []
-    for load, n_slots in runs:
+    for load, n_slots, graphs in runs:
         lam = load * mu
         gaps = rng.exponential(1.0 / lam, size=n_jobs)
         arrivals = np.cumsum(gaps) - gaps[0]
+        ctx.graph_mode(graphs)
         ctx.server_start(n_slots)
-        print("serve: load %.1f on %d slots (%.1f jobs/s)" % (load, n_slots, lam), file=sys.stderr, flush=True)
+        print("serve: load %.1f on %d slots (%.1f jobs/s)%s" % (load, n_slots, lam, ", graphs" if graphs else ""),
+              file=sys.stderr, flush=True)
         inflight = []
         start = time.perf_counter()
         for j, at in zip(jobs, arrivals):
@@ -198,7 +228,9 @@ def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96,
         ctx.server_stop()
         del inflight
         lat = np.array(lat)
-        results.append({"load": load, "slots": n_slots, "arrival_rate_jobs_per_s": round(lam, 3),
+        ctx.graph_mode(False)
+        results.append({"load": load, "slots": n_slots, "slot_graphs": graphs,
+                        "arrival_rate_jobs_per_s": round(lam, 3),
                         "site_channels_per_s": round(sites / makespan, 1), "makespan_s": round(makespan, 3),
                         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                                        "p99": round(float(np.percentile(lat, 99)), 2),
@@ -213,9 +245,16 @@ def serve_sweep(bbc, torch, np, n_jobs=64, budget_gb=96,
         "data": "synthetic (seeded on the device)", "hbm_budget_bytes": budget,
         "single_stream": {"jobs_per_s": round(mu, 3), "site_channels_per_s": round(sites / single_s, 1),
                           "mean_service_ms": round(float(np.mean(service)), 2)},
+        "single_stream_slot_graphs": {"jobs_per_s": round(n_jobs / single_g, 3),
+                                      "site_channels_per_s": round(sites / single_g, 1),
+                                      "mean_service_ms": round(float(np.mean(service_g)), 2),
+                                      "results_identical_to_eager": "%d/%d" % (same_g, n_jobs)},
         "runs": results, "jobs": n_jobs,
-        "config": {"workload": "64-job Poisson mix: lattices 16^3x32/24^3x48/32^3x64, 4-52 channels, "
-                               "4-16 slices, 4 resident propagator sets per lattice, FP32 form"},
+        "config": {"workload": "%d-job Poisson mix: lattices %s, %s, 4-%d slices, 4 resident "
+                               "propagator sets per lattice, FP32 form"
+                               % (n_jobs, "/".join("%d^3x%d" % lt for lt in lattices),
+                                  "one of %d channel subsets of 4-52 channels" % presets if presets
+                                  else "4-52 channels", max_t)},
     }
 
 
@@ -580,8 +619,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the c1, c3 and serving measurements")
     ap.add_argument("--workload", default="16c32-f64",
-                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "96c-f32-stream", "post-16c32",
-                             "next-16c32", "8c8-plambda"],
+                    choices=["16c32-f64", "32c64-f64", "32c64-f32", "serve-mix", "serve-small", "96c-f32-stream",
+                             "post-16c32", "next-16c32", "8c8-plambda"],
                     help="16c32-f64: 16^3x32, 52 channels, FP64 (default, the paper's Table 5 job); "
                          "32c64-*: 32^3x64, 52 channels, correlated inputs, FP64 or FP32 form")
     ap.add_argument("--graph", action="store_true",
@@ -605,6 +644,9 @@ def main():
 
     if args.workload == "serve-mix":
         print(json.dumps(serve_sweep(bbc, torch, np)), flush=True)
+        return
+    if args.workload == "serve-small":
+        print(json.dumps(serve_sweep(bbc, torch, np, n_jobs=256, lattices=SERVE_SMALL, max_t=8, presets=4)), flush=True)
         return
     if args.workload == "96c-f32-stream":
         print(json.dumps(stream96(bbc, torch, np, args.steps)), flush=True)
@@ -684,6 +726,8 @@ def main():
         res["c3_32c64"] = c3_jobs(bbc, torch, np, 2)
         print("bench: c4 (serving sweep)", file=sys.stderr, flush=True)
         res["c4_serving"] = serve_sweep(bbc, torch, np)
+        print("bench: c4 small lattices (serving sweep)", file=sys.stderr, flush=True)
+        res["c4_serving_small"] = serve_sweep(bbc, torch, np, n_jobs=256, lattices=SERVE_SMALL, max_t=8, presets=4)
     if not args.no_cpu_baseline and L == 16 and Sl is not None:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(Sl, Ss, 7)

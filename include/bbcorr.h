@@ -402,6 +402,17 @@ bbc_status bbc_job_forget(bbc_context *ctx, uint64_t job);
  * ordinary stream-ordered launches.  At most 16 graphs are kept; turning the
  * mode off (or a workspace reallocation) waits for the device and frees them.
  * The captured sequence holds kernel launches only.
+ *
+ * The serving loop follows the same switch: with it on, each slot captures one
+ * time slice per request shape (plan, lattice, precision, with or without
+ * energies, the slot's workspace, kernel variants) and replays it for every
+ * slice of every job of that shape on the slot, after a one-thread kernel has
+ * written the slice's propagator, output and scale addresses and t - t0 to the
+ * slot's argument record in device memory (the captured block, rescale and
+ * output kernels read them there).  Per slice the host then issues two
+ * launches instead of one per kernel.  A slot keeps at most 16 graphs; they
+ * are freed when its workspace changes and when the server stops.  Results
+ * are the same bits with the mode on or off.
  */
 bbc_status bbc_graph_mode(bbc_context *ctx, int enable);
 bbc_status bbc_profile_enable(bbc_context *ctx, int enable);

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdlib>
 #include <fstream>
 #include <sstream>
@@ -226,6 +227,14 @@ struct Slot {
     Job *job = nullptr;
     bool reserved = false;        // held for a job whose workspace is being allocated
     std::deque<hipEvent_t> evs;   // one completion event per enqueued slice
+    // graph replay: the slot's device copy of the current slice's arguments, and
+    // one captured slice per request shape on this slot's workspace
+    bbc::SliceArgs *d_args = nullptr;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    void clear_graphs() {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
 };
 
 struct Server {
@@ -238,6 +247,7 @@ struct Server {
     std::map<uint64_t, std::unique_ptr<PropSet>> props;
     std::vector<Slot> slots;
     std::vector<hipEvent_t> evpool;
+    hipStream_t cap = nullptr;    // capture stream of the slot graphs
     uint64_t next_id = 1;
     size_t committed = 0;         // resident propagators + slot workspaces
 };
@@ -269,7 +279,7 @@ struct bbc_context {
     hipEvent_t sev[8] = {};
     // graph mode: the kernel sequence of a device-resident job captured once per
     // argument tuple on gs, then replayed on the caller's stream
-    bool graph_mode = false;
+    std::atomic<bool> graph_mode{false};     // read by the serving thread too
     hipStream_t gs = nullptr;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     // kernel variants per request shape (lattice, precision, spin offset, channel
@@ -569,7 +579,8 @@ bbc::Tuning tuning_for(bbc_context *ctx, const int L[3], const DevPlan *dp) {
 template <typename T>
 bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], long V, void *ws, const MomGroups &mg,
                          const void *slp, const void *ssp, int n_ch, const double *d_energy, double dt, void *outp,
-                         double *scale, hipStream_t st, bool timed, const bbc::Tuning *force = nullptr) {
+                         double *scale, hipStream_t st, bool timed, const bbc::Tuning *force = nullptr,
+                         const bbc::SliceArgs *ia = nullptr) {
     using T2 = typename bbc::cplx_t<T>::type;
     const DevPlan *dp = pd.dp;
     const bbc::Tuning tu = force ? *force : tuning_for(ctx, L, dp);
@@ -589,9 +600,9 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     bbc_context *pc = timed ? ctx : nullptr;
     {
         StageTimer tm(pc, st, 0);
-        if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st);
+        if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st, ia);
         bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, pd.terms, pd.term_begin, dp->pats,
-                              fp32 ? kmax : nullptr, tu.blocks, st);
+                              fp32 ? kmax : nullptr, tu.blocks, st, ia);
     }
     // small cubic lattices: one fused pass (FFT in LDS, written straight into the
     // groups); 24- and 32-point planes: plane passes, then the z pass writes into
@@ -636,7 +647,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     {
         StageTimer tm(pc, st, 5);
         bbc::launch_finalize<T>(Ct, out, n_ch, (int)V, d_energy, dt, 1.0 / (double)V, scale, fp32 ? kmax : nullptr,
-                                pd.content, st);
+                                pd.content, st, ia);
     }
     HIP_TRY(hipGetLastError());
     return BBC_OK;
@@ -924,31 +935,63 @@ size_t job_footprint(const Job &j) {
     return workspace_bytes(V, j.dp->plan.ncomp, (int)j.chans.size(), j.dp->npair, cs) + 8 * j.chans.size() + 256;
 }
 
-// Enqueues slice j.next of a running job on its slot.
-bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
+// Enqueues slice j.next of a running job on its slot.  In graph mode the slot
+// replays one captured slice per request shape (plan, lattice, precision,
+// energies, workspace, kernel variants): a one-thread kernel first writes this
+// slice's propagator, output and scale pointers and t - t0 to the slot's
+// argument record, which the captured block, rescale and output kernels read.
+// The same kernels run in the same order either way, so the results are the
+// same bits.
+template <typename T>
+bbc_status server_enqueue_t(bbc_context *ctx, Slot &sl, Job &j) {
+    using T2 = typename bbc::cplx_t<T>::type;
+    Server &S = ctx->srv;
     const PropSet &ps = *j.ps;
     const long V = (long)ps.L[0] * ps.L[1] * ps.L[2];
     const int n_ch = (int)j.chans.size();
     bbc_status s;
-    const size_t wsz = workspace_bytes(V, j.dp->plan.ncomp, n_ch, j.dp->npair, ps.prec == BBC_F64 ? 16 : 8);
+    const size_t wsz = workspace_bytes(V, j.dp->plan.ncomp, n_ch, j.dp->npair, sizeof(T2));
     const double *d_energy = j.energy.empty() ? nullptr : (const double *)((char *)sl.ws + ((wsz + 255) & ~(size_t)255));
     const int n = j.next;
     const int si = j.slice[n];
     const size_t slice_elems = (size_t)V * 144;
     const double dt = (double)(j.tl[n] - j.t0);
-    if (ps.prec == BBC_F64) {
-        const MomGroups mg = get_groups<double>(ctx, ps.L, &s);
-        if (!mg.pos) return s;
-        const double2 *dl = (const double2 *)ps.dl + si * slice_elems, *ds = (const double2 *)ps.ds + si * slice_elems;
-        return enqueue_slice<double>(ctx, plan_dev(j.dp, j.dp->d_image), ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
-                                     (double2 *)j.out + (size_t)n * n_ch * V * 16, nullptr, sl.st, false);
-    }
-    const MomGroups mg = get_groups<float>(ctx, ps.L, &s);
+    const MomGroups mg = get_groups<T>(ctx, ps.L, &s);
     if (!mg.pos) return s;
-    const float2 *dl = (const float2 *)ps.dl + si * slice_elems, *ds = (const float2 *)ps.ds + si * slice_elems;
-    return enqueue_slice<float>(ctx, plan_dev(j.dp, j.dp->d_image), ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt,
-                                (float2 *)j.out + (size_t)n * n_ch * V * 16, j.scale + (size_t)n * n_ch, sl.st,
-                                false);
+    const T2 *dl = (const T2 *)ps.dl + si * slice_elems, *ds = (const T2 *)ps.ds + si * slice_elems;
+    T2 *out = (T2 *)j.out + (size_t)n * n_ch * V * 16;
+    double *scale = sizeof(T) == 4 ? j.scale + (size_t)n * n_ch : nullptr;
+    const PlanDev pd = plan_dev(j.dp, j.dp->d_image);
+    if (!ctx->graph_mode || !sl.d_args)
+        return enqueue_slice<T>(ctx, pd, ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt, out, scale, sl.st, false);
+    const bbc::Tuning tu = tuning_for(ctx, ps.L, j.dp);
+    const std::vector<int64_t> key = {(int64_t)(intptr_t)j.dp, ps.L[0], ps.L[1], ps.L[2], (int64_t)sizeof(T), n_ch,
+                                      d_energy ? 1 : 0, (int64_t)(intptr_t)sl.ws, tu.pairs, tu.blocks, tu.planes,
+                                      tu.combine};
+    auto it = sl.graphs.find(key);
+    if (it == sl.graphs.end()) {
+        if (!S.cap) HIP_TRY(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(S.cap, hipStreamCaptureModeRelaxed));
+        const bbc_status es = enqueue_slice<T>(ctx, pd, ps.L, V, sl.ws, mg, dl, ds, n_ch, d_energy, dt, out, scale,
+                                               S.cap, false, &tu, sl.d_args);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(S.cap, &g);
+        if (es != BBC_OK) { if (g) (void)hipGraphDestroy(g); return es; }
+        if (e != hipSuccess) return fail(BBC_EDEVICE, std::string("slot graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(BBC_EDEVICE, std::string("slot graph instantiate: ") + hipGetErrorString(e));
+        it = sl.graphs.emplace(key, ex).first;
+    }
+    bbc::launch_slice_args(sl.d_args, bbc::SliceArgs{dl, ds, out, scale, dt}, sl.st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipGraphLaunch(it->second, sl.st));
+    return BBC_OK;
+}
+
+bbc_status server_enqueue(bbc_context *ctx, Slot &sl, Job &j) {
+    return j.ps->prec == BBC_F64 ? server_enqueue_t<double>(ctx, sl, j) : server_enqueue_t<float>(ctx, sl, j);
 }
 
 void release_prop_if_unused(Server &S, PropSet *ps) {
@@ -1020,6 +1063,7 @@ bool admit_jobs(bbc_context *ctx, std::unique_lock<std::mutex> &lk) {
             std::vector<void *> drop;
             for (auto &sl : S.slots)
                 if (!sl.job && !sl.reserved && sl.ws) {
+                    sl.clear_graphs();
                     drop.push_back(sl.ws);
                     S.committed -= sl.ws_bytes;
                     sl.ws = nullptr;
@@ -1050,6 +1094,8 @@ bool admit_jobs(bbc_context *ctx, std::unique_lock<std::mutex> &lk) {
         j->t_start = Clock::now();
         slot->reserved = true;
         bool ok = true;
+        // the slot is idle: its graphs may go (a new workspace, or a full cache)
+        if (j->foot > slot->ws_bytes || slot->graphs.size() >= 16) slot->clear_graphs();
         if (j->foot > slot->ws_bytes) {
             void *old = slot->ws;
             S.committed += j->foot - slot->ws_bytes;
@@ -1502,7 +1548,10 @@ bbc_status bbc_server_start(bbc_context *ctx, int n_slots) {
     if (S.running) return fail(BBC_ESTATE, "server already running");
     HIP_TRY(hipSetDevice(ctx->device));
     S.slots.assign(n_slots, Slot());
-    for (auto &sl : S.slots) HIP_TRY(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+    for (auto &sl : S.slots) {
+        HIP_TRY(hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking));
+        HIP_TRY(hipMalloc((void **)&sl.d_args, sizeof(bbc::SliceArgs)));
+    }
     S.stop = false;
     S.running = true;
     S.th = std::thread(server_loop, ctx);
@@ -1525,12 +1574,15 @@ bbc_status bbc_server_stop(bbc_context *ctx) {
     for (auto &sl : S.slots) {
         (void)hipStreamSynchronize(sl.st);
         for (auto e : sl.evs) (void)hipEventDestroy(e);
+        sl.clear_graphs();
         (void)hipStreamDestroy(sl.st);
+        if (sl.d_args) (void)hipFree(sl.d_args);
         if (sl.ws) { (void)hipFree(sl.ws); S.committed -= sl.ws_bytes; }
     }
     S.slots.clear();
     for (auto e : S.evpool) (void)hipEventDestroy(e);
     S.evpool.clear();
+    if (S.cap) { (void)hipStreamDestroy(S.cap); S.cap = nullptr; }
     S.running = false;
     return BBC_OK;
 }

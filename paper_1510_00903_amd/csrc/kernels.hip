@@ -102,8 +102,12 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
                                                 typename cplx_t<T>::type *__restrict__ I, int V, int nc, int g0,
                                                 const uint32_t *__restrict__ terms,
                                                 const int32_t *__restrict__ term_begin, const BlockPatterns pt,
-                                                const uint32_t *__restrict__ kmax) {
+                                                const uint32_t *__restrict__ kmax, const SliceArgs *__restrict__ ia) {
     using T2 = typename cplx_t<T>::type;
+    if (ia) {
+        Sl = (const T2 *)ia->sl;
+        Ss = (const T2 *)ia->ss;
+    }
     __shared__ T2 sS[2][TS][145];
     __shared__ T2 sQ[TS][433];
     const int tid = threadIdx.x;
@@ -192,15 +196,16 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
 template <typename T, int TS, int NSPLIT>
 static void launch_blocks_v(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                             typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                            const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st) {
+                            const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st,
+                            const SliceArgs *ia) {
     const long nsb = (V + TS - 1) / TS;
     const dim3 grid((unsigned)(8 * ((nsb + 7) / 8)), NSPLIT);
     if (pt.any_imag)      // some term carries a factor i (spin structures with imaginary entries)
         hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, true>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
-                           term_begin, pt, kmax);
+                           term_begin, pt, kmax, ia);
     else
         hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, false>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
-                           term_begin, pt, kmax);
+                           term_begin, pt, kmax, ia);
 }
 
 // Variants (each component of each site is formed by one thread in the same
@@ -210,11 +215,11 @@ template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
                    const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, int variant,
-                   hipStream_t st) {
+                   hipStream_t st, const SliceArgs *ia) {
     switch (variant) {
-    case 1: launch_blocks_v<T, 4, 4>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st); break;
-    case 2: launch_blocks_v<T, 8, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st); break;
-    default: launch_blocks_v<T, 4, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st); break;
+    case 1: launch_blocks_v<T, 4, 4>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st, ia); break;
+    case 2: launch_blocks_v<T, 8, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st, ia); break;
+    default: launch_blocks_v<T, 4, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st, ia); break;
     }
 }
 
@@ -223,7 +228,9 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 // bit pattern of a non-negative float (integer max is order independent, so
 // the result does not depend on scheduling).
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_absmax(const float2 *__restrict__ S, long n, uint32_t *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_absmax(const float2 *__restrict__ S, long n, uint32_t *__restrict__ out,
+                                                const SliceArgs *__restrict__ ia, int strange) {
+    if (ia) S = (const float2 *)(strange ? ia->ss : ia->sl);
     float m = 0.0f;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const float2 v = S[i];
@@ -238,11 +245,20 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st) {
+void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st,
+                   const SliceArgs *ia) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, kmax, 2);
     const int nblk = (int)std::min<long>(2048, (n + 255) / 256);
-    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Sl, n, kmax);
-    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Ss, n, kmax + 1);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Sl, n, kmax, ia, 0);
+    hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Ss, n, kmax + 1, ia, 1);
+}
+
+__global__ void k_slice_args(SliceArgs *dst, SliceArgs v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+
+void launch_slice_args(SliceArgs *dst, const SliceArgs &v, hipStream_t st) {
+    hipLaunchKernelGGL(k_slice_args, dim3(1), dim3(64), 0, st, dst, v);
 }
 
 // ----------------------------------------------------------------------------
@@ -2233,9 +2249,14 @@ __global__ __launch_bounds__(256) void k_finalize(const typename ct_t<T>::type *
                                                   typename cplx_t<T>::type *__restrict__ out, int n_ch, int V,
                                                   const double *__restrict__ energy, double dt, double inv_v,
                                                   double *__restrict__ scale_out, const uint32_t *__restrict__ kmax,
-                                                  const int2 *__restrict__ content) {
+                                                  const int2 *__restrict__ content, const SliceArgs *__restrict__ ia) {
     using T2 = typename cplx_t<T>::type;
     using TC = typename ct_t<T>::type;
+    if (ia) {
+        out = (T2 *)ia->out;
+        scale_out = ia->scale;
+        dt = ia->dt;
+    }
     // a tile of 256 sites x 16 spins of one channel: read along the sites (one spin
     // row at a time), written as one contiguous run of the [site][spin] output
     __shared__ TC tile[256][17];
@@ -2286,18 +2307,20 @@ __global__ __launch_bounds__(256) void k_finalize(const typename ct_t<T>::type *
 template <typename T>
 void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
-                     const int2 *content, hipStream_t st) {
+                     const int2 *content, hipStream_t st, const SliceArgs *ia) {
     const long nblk = (long)n_ch * ((V + 255) / 256);
     const unsigned grid = (unsigned)std::min<long>(nblk, 1L << 22);
     hipLaunchKernelGGL((k_finalize<T>), dim3(grid), dim3(256), 0, st, Ct, out, n_ch, V, energy, dt, inv_v,
-                       scale_out, kmax, content);
+                       scale_out, kmax, content, ia);
 }
 
 // explicit instantiations
 template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
-                                    const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t);
+                                    const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t,
+                                    const SliceArgs *);
 template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
-                                   const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t);
+                                   const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t,
+                                   const SliceArgs *);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
 template int launch_fft3d_zgrouped<double>(double2 *, double2 *, int, const int[3], const int *, const int *, int,
                                             hipStream_t);
@@ -2326,8 +2349,8 @@ template void launch_pair_combine<double>(const double2 *, double2 *, int, long,
 template void launch_pair_combine<float>(const float2 *, ffc *, int, long, const PairDevTables &, int,
                                          hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
-                                      double *, const uint32_t *, const int2 *, hipStream_t);
+                                      double *, const uint32_t *, const int2 *, hipStream_t, const SliceArgs *);
 template void launch_finalize<float>(const ffc *, float2 *, int, int, const double *, double, double, double *,
-                                     const uint32_t *, const int2 *, hipStream_t);
+                                     const uint32_t *, const int2 *, hipStream_t, const SliceArgs *);
 
 }  // namespace bbc

@@ -71,11 +71,25 @@ struct BlockPatterns {
     BlockPattern p[kMaxBlockPatterns];
 };
 
+// Arguments of one time slice that change from slice to slice: the two
+// propagator slices, the output slab, the FP32 scale row (else NULL) and t - t0.
+// Where a launcher takes `ia` (a device copy of this record), a non-NULL `ia`
+// replaces the pointers and dt it is given, so that one captured kernel
+// sequence serves every slice of a request shape (graph replay in the serving
+// loop): launch_slice_args writes the next slice's record, stream-ordered.
+struct SliceArgs {
+    const void *sl, *ss;
+    void *out;
+    double *scale;
+    double dt;
+};
+void launch_slice_args(SliceArgs *dst, const SliceArgs &v, hipStream_t st);
+
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
                    typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
                    const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, int variant,
-                   hipStream_t st);
+                   hipStream_t st, const SliceArgs *ia = nullptr);
 
 // Kernel variants of one request shape (every variant forms the same values in
 // the same order, so the results are the same bits; only speed differs):
@@ -99,7 +113,8 @@ constexpr int kPairVariants64 = 8, kPairVariants32 = 5, kBlockVariants = 3, kPla
 constexpr int kMaxSliceStreams = 1 << (kSliceVariants - 1);
 
 // FP32 form: per-flavour max |Re|,|Im| of a slice into kmax[0] (light), kmax[1] (strange).
-void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st);
+void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st,
+                   const SliceArgs *ia = nullptr);
 
 template <typename T>
 int launch_fft3d(typename cplx_t<T>::type *data, long ncomp, const int L[3], int sign, hipStream_t st);
@@ -145,7 +160,7 @@ void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::ty
 template <typename T>
 void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
-                     const int2 *content, hipStream_t st);
+                     const int2 *content, hipStream_t st, const SliceArgs *ia = nullptr);
 
 bool fft_size_supported(int n);
 

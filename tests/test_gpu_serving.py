@@ -24,10 +24,14 @@ def _props(lat, T, seed, dtype):
     return torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
 
 
+@pytest.mark.parametrize("graphs", [False, True])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_mix_equals_alone(bbc, prec):
+def test_mix_equals_alone(bbc, prec, graphs):
     """Jobs of different lattices, channel subsets and slices, submitted together to a
-    3-slot server, give bit-identical results to the same jobs run alone."""
+    3-slot server, give bit-identical results to the same jobs run alone.  With graph
+    mode on, the slots replay one captured slice per request shape (the slice's
+    pointers written to the slot's argument record first); the jobs then run twice,
+    so the second round replays graphs captured in the first."""
     dtype = np.complex128 if prec == "f64" else np.complex64
     tdt = torch.complex128 if prec == "f64" else torch.complex64
     ctx = bbc.Context(0)
@@ -51,10 +55,12 @@ def test_mix_equals_alone(bbc, prec):
         torch.cuda.synchronize()
         alone.append(tuple(x.cpu() for x in r) if isinstance(r, tuple) else r.cpu())
     # mix: server
+    if graphs:
+        ctx.graph_mode(True)
     ctx.server_start(3)
     handles = {lat: ctx.prop_upload(*sets[lat]) for lat in sets}
     outs, ids = [], []
-    for lat, sl, ch in jobs:
+    for lat, sl, ch in jobs * (2 if graphs else 1):
         Lx, Ly, Lz = lat
         out = torch.zeros((len(sl), len(ch), Lz, Ly, Lx, 16), dtype=tdt, device="cuda:0")
         scale = torch.zeros((len(sl), len(ch)), dtype=torch.float64, device="cuda:0") if prec == "f32" else None
@@ -67,7 +73,7 @@ def test_mix_equals_alone(bbc, prec):
         q, r, tot = ctx.job_times(j)
         assert 0 <= q <= tot and 0 <= r <= tot
     torch.cuda.synchronize()
-    for (out, scale), ref in zip(outs, alone):
+    for (out, scale), ref in zip(outs, alone * (2 if graphs else 1)):
         if prec == "f64":
             assert torch.equal(out.cpu(), ref)
         else:
