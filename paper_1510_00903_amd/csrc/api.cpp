@@ -51,9 +51,10 @@ struct DevPlan {
     bbc::BlockPatterns pats;
     int ntask = 0, npair = 0;
     // every table the kernels read, as one image (byte offsets below): block-kernel
-    // terms, pair tasks and channel terms (pairs.hpp), per-channel quark content
+    // component records and terms (kernels.hpp, BlockComp), pair tasks and channel
+    // terms (pairs.hpp), per-channel quark content
     std::vector<unsigned char> image;
-    size_t off_terms = 0, off_term_begin = 0, off_tasks = 0, off_comb = 0, off_comb_begin = 0, off_content = 0;
+    size_t off_terms = 0, off_comps = 0, off_tasks = 0, off_comb = 0, off_comb_begin = 0, off_content = 0;
     void *d_image = nullptr;        // device copy, made by the entry points that allocate
     size_t table_bytes = 0;
     // request key: channel list, spin offset, precision, and a hash of the list
@@ -78,7 +79,7 @@ uint64_t channel_hash(const std::vector<int> &chans) {
 struct PlanDev {
     const DevPlan *dp;
     const uint32_t *terms;
-    const int32_t *term_begin;
+    const bbc::BlockComp *comps;
     const bbc::PTask *tasks;
     const bbc::CombEntry *comb;
     const int32_t *comb_begin;
@@ -86,7 +87,7 @@ struct PlanDev {
 };
 PlanDev plan_dev(const DevPlan *dp, const void *base) {
     const char *b = (const char *)base;
-    return PlanDev{dp, (const uint32_t *)(b + dp->off_terms), (const int32_t *)(b + dp->off_term_begin),
+    return PlanDev{dp, (const uint32_t *)(b + dp->off_terms), (const bbc::BlockComp *)(b + dp->off_comps),
                    (const bbc::PTask *)(b + dp->off_tasks), (const bbc::CombEntry *)(b + dp->off_comb),
                    (const int32_t *)(b + dp->off_comb_begin), (const int2 *)(b + dp->off_content)};
 }
@@ -431,8 +432,21 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
             content.push_back(make_int2(6 - ns, ns));
         }
         std::vector<unsigned char> &img = dp->image;
-        dp->off_terms = image_put(img, P.terms.data(), P.terms.size());
-        dp->off_term_begin = image_put(img, P.term_begin.data(), P.term_begin.size());
+        // block kernel: terms with the diquark index ea * 12 + eb precomputed, and one
+        // record per component holding its first two terms
+        std::vector<uint32_t> kterms(P.terms.size());
+        for (size_t t = 0; t < P.terms.size(); ++t) {
+            const uint32_t code = P.terms[t];
+            kterms[t] = ((code & 15) * 12 + ((code >> 4) & 15)) | (code & 0x3f00u);
+        }
+        std::vector<bbc::BlockComp> comps(P.ncomp);
+        for (int c = 0; c < P.ncomp; ++c) {
+            const int tb = P.term_begin[c], n = P.term_begin[c + 1] - tb;
+            comps[c] = bbc::BlockComp{n > 0 ? kterms[tb] : 0u, n > 1 ? kterms[tb + 1] : 0u, (uint32_t)(tb + 2),
+                                      (uint32_t)n};
+        }
+        dp->off_terms = image_put(img, kterms.data(), kterms.size());
+        dp->off_comps = image_put(img, comps.data(), comps.size());
         dp->off_tasks = image_put(img, pt.tasks.data(), pt.tasks.size());
         dp->off_comb = image_put(img, pt.comb.data(), pt.comb.size());
         dp->off_comb_begin = image_put(img, pt.comb_begin.data(), pt.comb_begin.size());
@@ -555,13 +569,13 @@ TuneKey tune_key(const int L[3], int prec, int spin_offset, uint64_t chash) {
 
 // Built-in choice for shapes without a tuning entry (the fastest variants
 // measured at 16^3 and 32^3 with 52 channels): the LDS-staged contraction
-// (FP64 per set of 4 momenta), and in FP32 the LDS-staged channel sums, 4 x 4
+// (FP64 per set of 4 momenta), and in FP32 the LDS-staged channel sums, 8 x 2
 // block workgroups and half-size plane-pass workgroups.
 // Small lattices run several slices at once (a slice alone does not fill the GPU).
 bbc::Tuning default_tuning(const int L[3], int prec) {
     const long V = (long)L[0] * L[1] * L[2];
     const int sl = V <= 1024 ? 3 : V <= 4096 ? 1 : 0;
-    if (prec == BBC_F32) return bbc::Tuning{2, 1, 1, sl, 2};
+    if (prec == BBC_F32) return bbc::Tuning{2, 2, 1, sl, 2};
     return bbc::Tuning{6, 0, 0, sl, 0};
 }
 
@@ -601,7 +615,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     {
         StageTimer tm(pc, st, 0);
         if (fp32) bbc::launch_absmax((const float2 *)sl, (const float2 *)ss, V * 144, kmax, st, ia);
-        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, pd.terms, pd.term_begin, dp->pats,
+        bbc::launch_blocks<T>(sl, ss, I, (int)V, nc, P.spin_offset, pd.comps, pd.terms, dp->pats,
                               fp32 ? kmax : nullptr, tu.blocks, st, ia);
     }
     // small cubic lattices: one fused pass (FFT in LDS, written straight into the

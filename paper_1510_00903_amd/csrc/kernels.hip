@@ -100,8 +100,8 @@ template <typename T, int TS, int NSPLIT, bool IMAG>
 __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *__restrict__ Sl,
                                                 const typename cplx_t<T>::type *__restrict__ Ss,
                                                 typename cplx_t<T>::type *__restrict__ I, int V, int nc, int g0,
-                                                const uint32_t *__restrict__ terms,
-                                                const int32_t *__restrict__ term_begin, const BlockPatterns pt,
+                                                const BlockComp *__restrict__ comps,
+                                                const uint32_t *__restrict__ terms, const BlockPatterns pt,
                                                 const uint32_t *__restrict__ kmax, const SliceArgs *__restrict__ ia) {
     using T2 = typename cplx_t<T>::type;
     if (ia) {
@@ -158,54 +158,101 @@ __global__ __launch_bounds__(256) void k_blocks(const typename cplx_t<T>::type *
             }
             __syncthreads();
         }
-        const int pc = P.qc;
-        const int r0 = 3 * P.p2[g0], r1 = 3 * P.p2[g0 + 1];
-        for (int comp = P.begin + share * NSLOT + slot; comp < P.end; comp += NSLOT * NSPLIT) {
-            T2 acc0 = T2{0, 0}, acc1 = T2{0, 0};
-            const int tb = term_begin[comp], te = term_begin[comp + 1];
-            for (int t = tb; t < te; ++t) {
-                const uint32_t code = terms[t];
-                const int ea = code & 15, eb = (code >> 4) & 15, ec = (code >> 8) & 15;
-                const T sg = (code >> 12) & 1 ? T(-1) : T(1);
-                const bool im = IMAG && ((code >> 13) & 1);
-                T2 g0v = T2{0, 0}, g1v = T2{0, 0};
+        // pattern constants, wave-uniform (scalar registers)
+        const int pc = __builtin_amdgcn_readfirstlane((int)P.qc);
+        const int r0 = __builtin_amdgcn_readfirstlane(3 * (int)P.p2[g0]);
+        const int r1 = __builtin_amdgcn_readfirstlane(3 * (int)P.p2[g0 + 1]);
+        const int k20 = __builtin_amdgcn_readfirstlane((int)P.k2[g0]);
+        const int k21 = __builtin_amdgcn_readfirstlane((int)P.k2[g0 + 1]);
+        const int pbeg = __builtin_amdgcn_readfirstlane(P.begin), pend = __builtin_amdgcn_readfirstlane(P.end);
+        const T2 *qs = &sQ[site][0];
+        const T2 *s0 = &sS[pc][site][r0 * 12], *s1 = &sS[pc][site][r1 * 12];
+        // one term for both sink spins: i^bit13 sum_c Q[c][ab] S_c[row + c][ec]
+        auto term = [&](uint32_t code, T2 &g0v, T2 &g1v) {
+            const int ab = code & 255, ec = (code >> 8) & 15;
+            g0v = T2{0, 0};
+            g1v = T2{0, 0};
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    const T2 q = sQ[site][cc * 144 + ea * 12 + eb];
-                    cfma(g0v, q, sS[pc][site][(r0 + cc) * 12 + ec]);
-                    cfma(g1v, q, sS[pc][site][(r1 + cc) * 12 + ec]);
-                }
-                if (im) {
-                    g0v = T2{-g0v.y, g0v.x};
-                    g1v = T2{-g1v.y, g1v.x};
-                }
-                acc0.x += sg * g0v.x; acc0.y += sg * g0v.y;
-                acc1.x += sg * g1v.x; acc1.y += sg * g1v.y;
+            for (int cc = 0; cc < 3; ++cc) {
+                const T2 q = qs[cc * 144 + ab];
+                cfma(g0v, q, s0[cc * 12 + ec]);
+                cfma(g1v, q, s1[cc * 12 + ec]);
             }
-            acc0 = rot_i(acc0, P.k2[g0]);
-            acc1 = rot_i(acc1, P.k2[g0 + 1]);
-            const int x = x0 + site;
-            if (x < V) {
-                I[((size_t)comp) * V + x] = acc0;
-                I[((size_t)nc + comp) * V + x] = acc1;
+            if (IMAG && ((code >> 13) & 1)) {
+                g0v = T2{-g0v.y, g0v.x};
+                g1v = T2{-g1v.y, g1v.x};
             }
+        };
+        auto add = [](T2 &acc, const T2 g, uint32_t code) {
+            const T sg = (code >> 12) & 1 ? T(-1) : T(1);
+            acc.x += sg * g.x;
+            acc.y += sg * g.y;
+        };
+        // a pair of terms (every component has an even number of them): the LDS
+        // reads of both issue together; they are added in their listed order
+        auto pair = [&](uint32_t c0, uint32_t c1, T2 &acc0, T2 &acc1) {
+            T2 ga0, ga1, gb0, gb1;
+            term(c0, ga0, ga1);
+            term(c1, gb0, gb1);
+            add(acc0, ga0, c0);
+            add(acc1, ga1, c0);
+            add(acc0, gb0, c1);
+            add(acc1, gb1, c1);
+        };
+        // each thread takes runs of CB consecutive components; the records of its
+        // next run are in flight while it works on the current one
+        constexpr int CB = 4;
+        constexpr int CSTEP = NSLOT * NSPLIT * CB;
+        auto fetch = [&](int c0, BlockComp *r) {
+#pragma unroll
+            for (int j = 0; j < CB; ++j) r[j] = comps[min(c0 + j, pend - 1)];   // past the end: unused
+        };
+        const int x = x0 + site;
+        auto run = [&](int c0, const BlockComp *r) {
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                const int comp = c0 + j;
+                if (comp >= pend) break;
+                T2 acc0 = T2{0, 0}, acc1 = T2{0, 0};
+                pair(r[j].t0, r[j].t1, acc0, acc1);
+                for (uint32_t t = 2; t < r[j].n; t += 2) {
+                    const uint2 cd = *(const uint2 *)&terms[r[j].rest + t - 2];
+                    pair(cd.x, cd.y, acc0, acc1);
+                }
+                acc0 = rot_i(acc0, k20);
+                acc1 = rot_i(acc1, k21);
+                if (x < V) {
+                    I[((size_t)comp) * V + x] = acc0;
+                    I[((size_t)nc + comp) * V + x] = acc1;
+                }
+            }
+        };
+        BlockComp ra[CB], rb[CB];
+        const int cfirst = pbeg + (share * NSLOT + slot) * CB;
+        fetch(cfirst, ra);
+        for (int c0 = cfirst; c0 < pend; c0 += 2 * CSTEP) {
+            fetch(c0 + CSTEP, rb);
+            run(c0, ra);
+            if (c0 + CSTEP >= pend) break;
+            fetch(c0 + 2 * CSTEP, ra);
+            run(c0 + CSTEP, rb);
         }
     }
 }
 
 template <typename T, int TS, int NSPLIT>
 static void launch_blocks_v(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
-                            typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                            const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st,
+                            typename cplx_t<T>::type *I, int V, int nc, int g0, const BlockComp *comps,
+                            const uint32_t *terms, const BlockPatterns &pt, const uint32_t *kmax, hipStream_t st,
                             const SliceArgs *ia) {
     const long nsb = (V + TS - 1) / TS;
     const dim3 grid((unsigned)(8 * ((nsb + 7) / 8)), NSPLIT);
     if (pt.any_imag)      // some term carries a factor i (spin structures with imaginary entries)
-        hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, true>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
-                           term_begin, pt, kmax, ia);
+        hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, true>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, comps,
+                           terms, pt, kmax, ia);
     else
-        hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, false>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, terms,
-                           term_begin, pt, kmax, ia);
+        hipLaunchKernelGGL((k_blocks<T, TS, NSPLIT, false>), grid, dim3(256), 0, st, Sl, Ss, I, V, nc, g0, comps,
+                           terms, pt, kmax, ia);
 }
 
 // Variants (each component of each site is formed by one thread in the same
@@ -213,13 +260,13 @@ static void launch_blocks_v(const typename cplx_t<T>::type *Sl, const typename c
 // shares 0 = 4 x 2, 1 = 4 x 4, 2 = 8 x 2.
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
-                   typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, int variant,
+                   typename cplx_t<T>::type *I, int V, int nc, int g0, const BlockComp *comps,
+                   const uint32_t *terms, const BlockPatterns &pt, const uint32_t *kmax, int variant,
                    hipStream_t st, const SliceArgs *ia) {
     switch (variant) {
-    case 1: launch_blocks_v<T, 4, 4>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st, ia); break;
-    case 2: launch_blocks_v<T, 8, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st, ia); break;
-    default: launch_blocks_v<T, 4, 2>(Sl, Ss, I, V, nc, g0, terms, term_begin, pt, kmax, st, ia); break;
+    case 1: launch_blocks_v<T, 4, 4>(Sl, Ss, I, V, nc, g0, comps, terms, pt, kmax, st, ia); break;
+    case 2: launch_blocks_v<T, 8, 2>(Sl, Ss, I, V, nc, g0, comps, terms, pt, kmax, st, ia); break;
+    default: launch_blocks_v<T, 4, 2>(Sl, Ss, I, V, nc, g0, comps, terms, pt, kmax, st, ia); break;
     }
 }
 
@@ -2315,11 +2362,11 @@ void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type 
 }
 
 // explicit instantiations
-template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const uint32_t *,
-                                    const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t,
+template void launch_blocks<double>(const double2 *, const double2 *, double2 *, int, int, int, const BlockComp *,
+                                    const uint32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t,
                                     const SliceArgs *);
-template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const uint32_t *,
-                                   const int32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t,
+template void launch_blocks<float>(const float2 *, const float2 *, float2 *, int, int, int, const BlockComp *,
+                                   const uint32_t *, const BlockPatterns &, const uint32_t *, int, hipStream_t,
                                    const SliceArgs *);
 template int launch_fft3d<double>(double2 *, long, const int[3], int, hipStream_t);
 template int launch_fft3d_zgrouped<double>(double2 *, double2 *, int, const int[3], const int *, const int *, int,

@@ -85,10 +85,20 @@ struct SliceArgs {
 };
 void launch_slice_args(SliceArgs *dst, const SliceArgs &v, hipStream_t st);
 
+// One block component: its number of terms n, its first two terms t0, t1 (0 where
+// absent), and the index in the term array of its third term.  A term is
+// ab | ec << 8 | sign << 12 | i << 13, with ab = 12 ea + eb the diquark column and
+// ec the third propagator's column (term value: sign * i^bit13 * sum_c
+// Q[c][ea][eb] S_c[row + c][ec]).  Records let a thread fetch the next
+// component with one load while it works on the current one.
+struct BlockComp {
+    uint32_t t0, t1, rest, n;
+};
+
 template <typename T>
 void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>::type *Ss,
-                   typename cplx_t<T>::type *I, int V, int nc, int g0, const uint32_t *terms,
-                   const int32_t *term_begin, const BlockPatterns &pt, const uint32_t *kmax, int variant,
+                   typename cplx_t<T>::type *I, int V, int nc, int g0, const BlockComp *comps,
+                   const uint32_t *terms, const BlockPatterns &pt, const uint32_t *kmax, int variant,
                    hipStream_t st, const SliceArgs *ia = nullptr);
 
 // Kernel variants of one request shape (every variant forms the same values in
