@@ -39,12 +39,14 @@ def tensor_entries(g, name="p"):
     return np.array(idx), np.array(val)
 
 
-def correlate(S_l, S_s, ch, r_list, spins=None, lower=False):
+def correlate(S_l, S_s, ch, r_list, spins=None, lower=False, offsets=None):
     """C_ch(r) by brute force for one time slice.
 
     spins: iterable of spin indices a + 2*(b + 2*(a' + 2*b')) (default: all 16).
     lower: take the lower two Dirac components of every spinor index (component
            2 + a for a, Sec. 6) instead of the upper two.
+    offsets: per baryon B1..B4 the first Dirac component of its pair (0 or 2),
+           overriding ``lower``.
     Returns complex128 [n_r][16] (entries not requested are left 0).
     """
     Lz, Ly, Lx = S_l.shape[:3]
@@ -54,8 +56,9 @@ def correlate(S_l, S_s, ch, r_list, spins=None, lower=False):
     props = [Sl, Sl, Ss]          # u, d, s (u = d numerically, distinct as fields)
     if spins is None:
         spins = range(16)
-    g0 = 2 if lower else 0
-    ent = [[tensor_entries(g + g0, b) for g in range(2)] for b in ch]
+    if offsets is None:
+        offsets = (2 if lower else 0,) * 4
+    ent = [[tensor_entries(g + offsets[i], b) for g in range(2)] for i, b in enumerate(ch)]
     terms = ops.channel_terms(ch)
     out = np.zeros((len(r_list), 16), dtype=np.complex128)
     for ir, (rx, ry, rz) in enumerate(r_list):

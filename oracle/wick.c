@@ -117,26 +117,30 @@ typedef struct { int t1, t2; int A, B; int sp; cplx coef; } work;
  *   nterm[4]     number of terms of B1, B2, B3, B4 (at most 3 each).
  *   w[4][3]      term weights.
  *   flav[4][3][3] flavour of each field of each term (0 = u, 1 = d, 2 = s), field order a,b,c.
- *   glo          first spin component computed for every baryon (0: upper two, 2: lower two).
+ *   glo[4]       per baryon B1..B4, the first of its two spin components computed
+ *                (0: the upper two, 2: the lower two; Sec. 6 uses the upper two of
+ *                every baryon forward in time and the lower two backward).
  *   nr, r[nr][3] relative coordinates.
- *   out[nr][16]  complex result, spin index a + 2*(b + 2*(a' + 2*b')), spins relative to glo.
+ *   out[nr][16]  complex result, spin index a + 2*(b + 2*(a' + 2*b')), each spin
+ *                relative to its baryon's glo.
  * Returns 0, or a negative value on bad input or allocation failure.
  */
 int oracle_wick(int Lx, int Ly, int Lz, const double *Sl_, const double *Ss_, const double *M1_,
-                const double *M2_, const int *nterm, const double *w, const int *flav, int glo,
+                const double *M2_, const int *nterm, const double *w, const int *flav, const int *glo,
                 int nr, const int *r, double *out_) {
     const cplx *Sl = (const cplx *)Sl_, *Ss = (const cplx *)Ss_;
     const cplx *M1 = (const cplx *)M1_, *M2 = (const cplx *)M2_;
     cplx *out = (cplx *)out_;
     long V = (long)Lx * Ly * Lz;
     for (int b = 0; b < 4; ++b) if (nterm[b] < 1 || nterm[b] > 3) return -1;
+    for (int b = 0; b < 4; ++b) if (glo[b] != 0 && glo[b] != 2) return -1;
 
-    /* tensor nonzeros of every baryon for the two spin components g = glo, glo+1 */
+    /* tensor nonzeros of every baryon for its two spin components g = glo[b], glo[b]+1 */
     nzent *nz = malloc(sizeof(nzent) * 4 * 2 * MAXNZ);
     int nnz[4][2];
     if (!nz) return -3;
     for (int b = 0; b < 4; ++b)
-        for (int g = 0; g < 2; ++g) nnz[b][g] = tensor_nz(M1 + 16 * b, M2 + 16 * b, glo + g, nz + (2 * b + g) * MAXNZ);
+        for (int g = 0; g < 2; ++g) nnz[b][g] = tensor_nz(M1 + 16 * b, M2 + 16 * b, glo[b] + g, nz + (2 * b + g) * MAXNZ);
 
     /* G tensors of every sink term of B1 and B2 */
     int n1 = nterm[0], n2 = nterm[1];
