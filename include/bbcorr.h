@@ -24,7 +24,10 @@
  *    indices and the quark fields in mirrored order (Sec. 3, Eq. (LN.pLLp.ududsu)).
  *  - Spatial boundary periodic; B1 sits at X + r (Sec. 3).
  *  - Spin components: BBC_SPIN_UPPER computes alpha, beta, alpha', beta' in
- *    {0, 1} (Dirac upper components, positive parity forward in time, Sec. 6).
+ *    {0, 1} (Dirac upper components, positive parity forward in time, Sec. 6),
+ *    BBC_SPIN_LOWER the lower pair {2, 3} of every index (backward in time),
+ *    BBC_SPIN_FULL all four components of every index (256 values, bbc_correlate
+ *    only, layout below).
  *  - Output element (t-index n, channel-index m, site r, spin s) with
  *    s = a + 2*(b + 2*(a' + 2*b')) is at
  *        C_out[((n * n_ch + m) * V + r) * 16 + s]
@@ -61,7 +64,7 @@ typedef enum {
 } bbc_status;
 
 typedef enum { BBC_F64 = 0, BBC_F32 = 1 } bbc_precision;
-typedef enum { BBC_SPIN_UPPER = 0, BBC_SPIN_LOWER = 1 } bbc_spin;
+typedef enum { BBC_SPIN_UPPER = 0, BBC_SPIN_LOWER = 1, BBC_SPIN_FULL = 2 } bbc_spin;
 
 typedef struct bbc_context bbc_context;
 
@@ -158,7 +161,18 @@ bbc_status bbc_footprint(const int32_t lattice[3], bbc_precision prec, int n_ch,
  *   t0            source time.
  *   ch_list[n_ch] channel ids (0..55, extended ids and general-field ids as
  *                 above), any order, repeats allowed.
- *   spin          BBC_SPIN_UPPER or BBC_SPIN_LOWER (components 2,3 mapped to 0,1).
+ *   spin          BBC_SPIN_UPPER or BBC_SPIN_LOWER (components 2,3 mapped to 0,1),
+ *                 or BBC_SPIN_FULL: every component of alpha, beta, alpha', beta'
+ *                 over 0..3, 256 values per site, at
+ *                     C_out[((n * n_ch + m) * V + r) * 256 + s],
+ *                     s = alpha + 4 * (beta + 4 * (alpha' + 4 * beta')),
+ *                 computed as 16 upper-pair evaluations, one per choice of upper
+ *                 or lower pair for each of the four baryons (a baryon's lower
+ *                 pair is the upper pair of its field with the rows of Gamma_2
+ *                 moved up by two).  C_out (device memory only in this mode) then
+ *                 holds n_t * n_ch * V * 256 values; C_scale is as below (the same
+ *                 for every component).  The serving calls, the CPT average and
+ *                 bbc_correlate_noalloc take UPPER or LOWER only.
  *   energy[n_ch]  E_ch of the normalisation factor exp(E_ch (t - t0)) of Sec. 2
  *                 Eq. (2); NULL means 0 for every channel (unnormalised).
  *   C_out         device pointer, n_t * n_ch * V * 16 complex of the

@@ -13,14 +13,14 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["BBCError", "F64", "F32", "UPPER", "LOWER", "STAGES", "CUBIC_A1", "CUBIC_A1_COMPLEMENT",
+__all__ = ["BBCError", "F64", "F32", "UPPER", "LOWER", "FULL", "STAGES", "CUBIC_A1", "CUBIC_A1_COMPLEMENT",
            "baryon_names", "channel_id",
            "Context", "library_path", "load",
            "num_channels", "num_channels_all", "channel_name", "channel_content", "source_terms",
            "diagram_table", "plan_stats", "footprint", "EXPORTED_SYMBOLS"]
 
 F64, F32 = 0, 1
-UPPER, LOWER = 0, 1
+UPPER, LOWER, FULL = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libbbcorr.so")
@@ -371,9 +371,12 @@ class Context:
         S_*:   [n_t, Lz, Ly, Lx, 12, 12], complex128 (FP64 form) or complex64 (FP32 form), on the
                context's GPU or in host memory (pinned recommended: slices are then streamed
                through device staging buffers, overlapping the transfers with the kernels).
-        out:   device or host tensor (default: device if the inputs are, else pinned host memory).
-        Returns ``out`` [n_t, n_ch, Lz, Ly, Lx, 16] (same dtype); in the FP32 form also
-        ``scale`` [n_t, n_ch] float64, the FP64 factor of each (t, channel) field.
+        spin:  UPPER, LOWER, or FULL (all 256 components, alpha + 4 (beta + 4 (alpha' + 4 beta')),
+               output on the device only).
+        out:   device or host tensor (default: device if the inputs are or spin is FULL, else
+               pinned host memory).
+        Returns ``out`` [n_t, n_ch, Lz, Ly, Lx, 16] (256 for FULL, same dtype); in the FP32 form
+        also ``scale`` [n_t, n_ch] float64, the FP64 factor of each (t, channel) field.
         Stream-ordered on ``stream`` (default: torch's current stream).
         """
         import torch
@@ -394,13 +397,14 @@ class Context:
         ch_arr, n_ch = _i32(channels)
         lat, _ = _i32([Lx, Ly, Lz])
         dev = self._torch_device()
-        oshape = (n_t, n_ch, Lz, Ly, Lx, 16)
+        full = int(spin) == FULL
+        oshape = (n_t, n_ch, Lz, Ly, Lx, 256 if full else 16)
         if out is None:
-            if S_light.is_cuda:
+            if S_light.is_cuda or full:
                 out = torch.empty(oshape, dtype=S_light.dtype, device=dev)
             else:
                 out = torch.empty(oshape, dtype=S_light.dtype, pin_memory=True)
-        _check_tensor(out, oshape, S_light.dtype, "out", dev, host_ok=True)
+        _check_tensor(out, oshape, S_light.dtype, "out", dev, host_ok=not full)
         if prec == F32:
             if scale is None:
                 scale = torch.empty((n_t, n_ch), dtype=torch.float64, device=dev)

@@ -61,6 +61,9 @@ struct DevPlan {
     std::vector<int> chans;
     int spin_offset = 0, prec = 0;
     uint64_t chash = 0;
+    // all-components request: which of the 16 upper/lower choices (bit i: baryon
+    // B(i+1) takes its lower pair) this plan evaluates, else -1
+    int full_sub = -1;
     ~DevPlan() { (void)hipFree(d_image); }
 };
 
@@ -369,17 +372,20 @@ size_t image_put(std::vector<unsigned char> &img, const E *data, size_t n) {
 // `upload`, the table image is also copied to a device allocation of its own;
 // the allocation-free entry point copies it into its scratch instead.
 bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, bbc_precision prec,
-                    DevPlan **out, bool upload = true) {
+                    DevPlan **out, bool upload = true, int full_sub = -1) {
     std::lock_guard<std::mutex> lock(ctx->qmu);
-    auto key = std::make_pair(chans, spin_offset * 2 + (prec == BBC_F32 ? 1 : 0));
+    auto key = std::make_pair(chans, spin_offset * 2 + (prec == BBC_F32 ? 1 : 0) + 8 * (full_sub + 1));
     auto it = ctx->plans.find(key);
     if (it == ctx->plans.end()) {
         std::unique_ptr<DevPlan> dp(new DevPlan);
         try {
-            dp->plan = bbc::build_plan(chans, spin_offset);
+            int lower[4];
+            for (int i = 0; i < 4; ++i) lower[i] = (full_sub >> i) & 1;
+            dp->plan = full_sub >= 0 ? bbc::build_plan(chans, 0, lower) : bbc::build_plan(chans, spin_offset);
         } catch (const std::exception &e) {
             return fail(BBC_EINVAL, std::string("planner: ") + e.what());
         }
+        dp->full_sub = full_sub;
         dp->chans = chans;
         dp->spin_offset = spin_offset;
         dp->prec = (int)prec;
@@ -661,7 +667,7 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     {
         StageTimer tm(pc, st, 5);
         bbc::launch_finalize<T>(Ct, out, n_ch, (int)V, d_energy, dt, 1.0 / (double)V, scale, fp32 ? kmax : nullptr,
-                                pd.content, st, ia);
+                                pd.content, st, ia, dp->full_sub);
     }
     HIP_TRY(hipGetLastError());
     return BBC_OK;
@@ -771,7 +777,7 @@ bbc_status run_correlate(bbc_context *ctx, DevPlan *dp, const int L[3], long V, 
     using T2 = typename bbc::cplx_t<T>::type;
     const size_t cs = sizeof(T2);
     const size_t core = workspace_bytes(V, dp->plan.ncomp, n_ch, dp->npair, cs);
-    const size_t in_slice = (size_t)V * 144 * cs, out_slice = (size_t)n_ch * V * 16 * cs;
+    const size_t in_slice = (size_t)V * 144 * cs, out_slice = (size_t)n_ch * V * (dp->full_sub >= 0 ? 256 : 16) * cs;
     const size_t in_stage = host_in ? 2 * 2 * in_slice : 0, out_stage = host_out ? 2 * out_slice : 0;
     // device-resident requests may run several slices at once (own workspace each)
     const bool device_path = !host_in && !host_out;
@@ -1408,7 +1414,8 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     bbc_status s = check_lattice(lattice, &V);
     if (s) return s;
     if (prec != BBC_F64 && prec != BBC_F32) return fail(BBC_EINVAL, "precision");
-    if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER) return fail(BBC_EINVAL, "spin selection");
+    if (spin != BBC_SPIN_UPPER && spin != BBC_SPIN_LOWER && spin != BBC_SPIN_FULL)
+        return fail(BBC_EINVAL, "spin selection");
     if (n_t < 0 || n_ch <= 0 || !ch_list) return fail(BBC_EINVAL, "empty channel list or negative n_t");
     if (n_t > 0 && (!S_light || !S_strange || !t_list || !C_out)) return fail(BBC_EINVAL, "NULL buffer");
     if (prec == BBC_F32 && n_t > 0 && !C_scale) return fail(BBC_EINVAL, "C_scale is required in FP32 mode");
@@ -1420,14 +1427,30 @@ bbc_status bbc_correlate(bbc_context *ctx, const int32_t lattice[3], bbc_precisi
     if (is_host_pointer(S_strange) != host_in)
         return fail(BBC_EINVAL, "S_light and S_strange must both be host or both be device memory");
     if (C_scale && is_host_pointer(C_scale)) return fail(BBC_EINVAL, "C_scale must be device memory");
+    if (spin == BBC_SPIN_FULL && host_out) return fail(BBC_EINVAL, "BBC_SPIN_FULL needs C_out in device memory");
     std::lock_guard<std::mutex> lock(ctx->mu);
     HIP_TRY(hipSetDevice(ctx->device));
     std::vector<int> chans(ch_list, ch_list + n_ch);
-    DevPlan *dp = nullptr;
-    s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, prec, &dp);
-    if (s) return s;
     const int L[3] = {lattice[0], lattice[1], lattice[2]};
     hipStream_t st = (hipStream_t)stream;
+    DevPlan *dp = nullptr;
+    if (spin == BBC_SPIN_FULL) {
+        // 16 evaluations, one per choice of upper or lower pair for each baryon,
+        // each writing its 16 components into the 256-value layout
+        if ((s = order_after_last(ctx, st))) return s;
+        for (int sub = 0; sub < 16 && !s; ++sub) {
+            if ((s = get_plan(ctx, chans, 0, prec, &dp, true, sub))) break;
+            if (prec == BBC_F64)
+                s = run_correlate<double>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out,
+                                          nullptr, st, host_in, false);
+            else
+                s = run_correlate<float>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out,
+                                         C_scale, st, host_in, false);
+        }
+        return mark_last(ctx, st, s);
+    }
+    s = get_plan(ctx, chans, spin == BBC_SPIN_LOWER ? 2 : 0, prec, &dp);
+    if (s) return s;
     if ((s = order_after_last(ctx, st))) return s;
     if (prec == BBC_F64)
         s = run_correlate<double>(ctx, dp, L, V, S_light, S_strange, n_t, t_list, t0, n_ch, energy, C_out, nullptr,

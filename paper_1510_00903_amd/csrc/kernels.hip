@@ -2296,7 +2296,8 @@ __global__ __launch_bounds__(256) void k_finalize(const typename ct_t<T>::type *
                                                   typename cplx_t<T>::type *__restrict__ out, int n_ch, int V,
                                                   const double *__restrict__ energy, double dt, double inv_v,
                                                   double *__restrict__ scale_out, const uint32_t *__restrict__ kmax,
-                                                  const int2 *__restrict__ content, const SliceArgs *__restrict__ ia) {
+                                                  const int2 *__restrict__ content, const SliceArgs *__restrict__ ia,
+                                                  int full) {
     using T2 = typename cplx_t<T>::type;
     using TC = typename ct_t<T>::type;
     if (ia) {
@@ -2334,17 +2335,26 @@ __global__ __launch_bounds__(256) void k_finalize(const typename ct_t<T>::type *
         }
         __syncthreads();
         const int nsite = min(256, V - x0);
-        T2 *o = out + ((size_t)m * V + x0) * 16;
+        // all-components request: this evaluation's 16 values go to alpha = 2 h1 + a,
+        // beta = 2 h2 + b, ... of the 256-value site record (h = the lower-pair bits)
+        const int ostride = full >= 0 ? 256 : 16;
+        const int obase = full >= 0 ? 2 * (full & 1) + 8 * ((full >> 1) & 1) + 32 * ((full >> 2) & 1) +
+                                          128 * ((full >> 3) & 1)
+                                    : 0;
+        T2 *o = out + ((size_t)m * V + x0) * ostride;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int idx = k * 256 + t, site = idx >> 4, s = idx & 15;
             if (site < nsite) {
                 const TC v = tile[site][s];
+                const int oi = full >= 0 ? site * 256 + obase + (s & 1) + 4 * ((s >> 1) & 1) + 16 * ((s >> 2) & 1) +
+                                               64 * ((s >> 3) & 1)
+                                         : idx;
                 if constexpr (sizeof(T) == 4)    // float-float: one rounding of hi + lo, times 1/V
-                    o[idx] = T2{(T)(((double)v.x.hi + (double)v.x.lo) * (double)f),
-                                (T)(((double)v.y.hi + (double)v.y.lo) * (double)f)};
+                    o[oi] = T2{(T)(((double)v.x.hi + (double)v.x.lo) * (double)f),
+                               (T)(((double)v.y.hi + (double)v.y.lo) * (double)f)};
                 else
-                    o[idx] = T2{v.x * f, v.y * f};
+                    o[oi] = T2{v.x * f, v.y * f};
             }
         }
         __syncthreads();
@@ -2354,11 +2364,11 @@ __global__ __launch_bounds__(256) void k_finalize(const typename ct_t<T>::type *
 template <typename T>
 void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
-                     const int2 *content, hipStream_t st, const SliceArgs *ia) {
+                     const int2 *content, hipStream_t st, const SliceArgs *ia, int full) {
     const long nblk = (long)n_ch * ((V + 255) / 256);
     const unsigned grid = (unsigned)std::min<long>(nblk, 1L << 22);
     hipLaunchKernelGGL((k_finalize<T>), dim3(grid), dim3(256), 0, st, Ct, out, n_ch, V, energy, dt, inv_v,
-                       scale_out, kmax, content, ia);
+                       scale_out, kmax, content, ia, full);
 }
 
 // explicit instantiations
@@ -2396,8 +2406,8 @@ template void launch_pair_combine<double>(const double2 *, double2 *, int, long,
 template void launch_pair_combine<float>(const float2 *, ffc *, int, long, const PairDevTables &, int,
                                          hipStream_t);
 template void launch_finalize<double>(const double2 *, double2 *, int, int, const double *, double, double,
-                                      double *, const uint32_t *, const int2 *, hipStream_t, const SliceArgs *);
+                                      double *, const uint32_t *, const int2 *, hipStream_t, const SliceArgs *, int);
 template void launch_finalize<float>(const ffc *, float2 *, int, int, const double *, double, double, double *,
-                                     const uint32_t *, const int2 *, hipStream_t, const SliceArgs *);
+                                     const uint32_t *, const int2 *, hipStream_t, const SliceArgs *, int);
 
 }  // namespace bbc

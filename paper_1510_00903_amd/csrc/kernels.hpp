@@ -170,7 +170,7 @@ void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::ty
 template <typename T>
 void launch_finalize(const typename ct_t<T>::type *Ct, typename cplx_t<T>::type *out, int n_ch, int V,
                      const double *energy, double dt, double inv_v, double *scale_out, const uint32_t *kmax,
-                     const int2 *content, hipStream_t st, const SliceArgs *ia = nullptr);
+                     const int2 *content, hipStream_t st, const SliceArgs *ia = nullptr, int full = -1);
 
 bool fft_size_supported(int n);
 

@@ -233,8 +233,8 @@ uint32_t canonical(const int pf[3], const int X[3], const int T[3], int sink_spi
         }
         uint32_t key = 0;
         for (int i = 0; i < 3; ++i) key = key * 16 + (uint32_t)((lpf[i] * 2 + ly[i]) * 4 + lt[i]);
-        key = (key << 9) | ((uint32_t)sink_spin << 6) | ((uint32_t)(ls[0] < 0 ? 7 : ls[0]) << 3) |
-              (uint32_t)(ls[1] < 0 ? 7 : ls[1]);
+        key = (key << 12) | ((uint32_t)sink_spin << 8) | ((uint32_t)(ls[0] < 0 ? 15 : ls[0]) << 4) |
+              (uint32_t)(ls[1] < 0 ? 15 : ls[1]);
         if (key < best) {
             best = key;
             *sign = sg;
@@ -281,12 +281,20 @@ Intermediate make_intermediate(uint32_t key, const int pf[3], const int y[3], co
 }  // namespace
 
 const SpinStruct &spin_struct(int s) {
-    static const std::array<SpinStruct, kNumSpinStructs> t = [] {
-        std::array<SpinStruct, kNumSpinStructs> v{};
+    static const std::array<SpinStruct, kNumSpinStructsAll> t = [] {
+        std::array<SpinStruct, kNumSpinStructsAll> v{};
         const M4 C = mmul(dirac_gamma(4), dirac_gamma(2));
         v[SP_OCTET] = make_spin(mmul(C, dirac_gamma(5)), identity4());
         v[SP_CHI2] = make_spin(C, dirac_gamma(5));
         for (int l = 1; l <= 3; ++l) v[SP_DEC1 + l - 1] = make_spin(mmul(C, dirac_gamma(l)), identity4());
+        for (int s = 0; s < kNumSpinStructs; ++s) {
+            SpinStruct &u = v[kNumSpinStructs + s];
+            u = v[s];
+            for (int g = 0; g < 4; ++g) {
+                u.p2[g] = v[s].p2[(g + 2) & 3];
+                u.k2[g] = v[s].k2[(g + 2) & 3];
+            }
+        }
         return v;
     }();
     return t[s];
@@ -336,9 +344,12 @@ std::string channel_name(int ch) {
 }
 
 std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *index,
-                              std::vector<Intermediate> *inters) {
+                              std::vector<Intermediate> *inters, const int *lower) {
     const auto bb = channel_baryons(ch);
     const Baryon &B1 = kBaryons[bb[0]], &B2 = kBaryons[bb[1]], &B3 = kBaryons[bb[2]], &B4 = kBaryons[bb[3]];
+    // spin structure of each baryon, its shifted form where its lower pair is asked for
+    int spn[4];
+    for (int i = 0; i < 4; ++i) spn[i] = kBaryons[bb[i]].spin + (lower && lower[i] ? kNumSpinStructs : 0);
     int fs[6], fsrc[6], rsrc[6];
     for (int i = 0; i < 3; ++i) {
         fs[i] = B1.flav[i]; fs[3 + i] = B2.flav[i];
@@ -350,7 +361,7 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
         rsrc[3 + B4.term[t4].role[r]] = r;
     }
     const double w34 = B3.term[t3].w * B4.term[t4].w;
-    const int srcspin[2] = {B3.spin, B4.spin};
+    const int srcspin[2] = {spn[2], spn[3]};
     std::vector<Diagram> out;
     // A diagram is the set of source fields contracted with the quarks of B1
     // (site X+r); Wick maps differing only by exchanges of identical quarks
@@ -415,12 +426,12 @@ std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *i
                                 }
                                 BlockRef br;
                                 int cpf[3], cy[3], ct[3], csrc[2], csign = 1;
-                                uint32_t key = canonical(pf, X, T, Bs.spin, srcspin, br.ymap, cpf, cy, ct, csrc,
+                                uint32_t key = canonical(pf, X, T, spn[s], srcspin, br.ymap, cpf, cy, ct, csrc,
                                                          &csign);
                                 auto it = index->find(key);
                                 if (it == index->end()) {
                                     int id = (int)inters->size();
-                                    inters->push_back(make_intermediate(key, cpf, cy, ct, Bs.spin, csrc));
+                                    inters->push_back(make_intermediate(key, cpf, cy, ct, spn[s], csrc));
                                     it = index->emplace(key, id).first;
                                 }
                                 br.inter = it->second;
@@ -549,7 +560,7 @@ std::vector<Part> y_parts(const Intermediate &I, int Y, int o, int k, int so) {
 
 }  // namespace
 
-Plan build_plan(const std::vector<int> &channels, int spin_offset) {
+Plan build_plan(const std::vector<int> &channels, int spin_offset, const int *lower) {
     Plan P;
     P.channels = channels;
     P.spin_offset = spin_offset;
@@ -560,7 +571,7 @@ Plan build_plan(const std::vector<int> &channels, int spin_offset) {
         const auto bb = channel_baryons(ch);
         for (int t3 = 0; t3 < kBaryons[bb[2]].nterm; ++t3)
             for (int t4 = 0; t4 < kBaryons[bb[3]].nterm; ++t4)
-                for (auto &d : classify(ch, t3, t4, &index, &P.inters)) {
+                for (auto &d : classify(ch, t3, t4, &index, &P.inters, lower)) {
                     P.iterations += d.K;
                     P.diags.push_back(std::move(d));
                 }

@@ -29,7 +29,13 @@ enum : int {
     SP_OCTET = 0,    // {C gamma_5, 1}: the octet fields of Sec. 2
     SP_CHI2 = 1,     // {C, gamma_5}: the other nucleon field
     SP_DEC1 = 2,     // {C gamma_l, 1}, l = 1, 2, 3: decuplet fields (Sec. 4 footnote)
-    kNumSpinStructs = 5
+    kNumSpinStructs = 5,
+    // structure s + kNumSpinStructs is s with the rows of Gamma_2 moved up by two
+    // (Gamma_2'(g, .) = Gamma_2(g + 2 mod 4, .)): its spin components 0, 1 are the
+    // components 2, 3 of s, so one baryon of a channel can take its lower pair
+    // while the others take the upper one (all 256 spin components, Sec. 6 uses
+    // the lower pair backward in time)
+    kNumSpinStructsAll = 2 * kNumSpinStructs
 };
 const SpinStruct &spin_struct(int s);
 
@@ -126,15 +132,19 @@ struct Plan {
 
 // Diagrams of one channel and source-term pair; intermediates are registered in
 // `index`/`inters` (pass nullptrs to only classify).
+// `lower` (optional, per baryon B1..B4): 1 takes that baryon's lower spin pair
+// through its shifted structure (see kNumSpinStructsAll).
 std::vector<Diagram> classify(int ch, int t3, int t4, std::map<uint32_t, int> *index,
-                              std::vector<Intermediate> *inters);
+                              std::vector<Intermediate> *inters, const int *lower = nullptr);
 
-Plan build_plan(const std::vector<int> &channels, int spin_offset);
+// spin_offset 0 (upper pair of every baryon) or 2 (lower pair of every baryon);
+// with `lower`, spin_offset is 0 and each baryon's pair is chosen on its own.
+Plan build_plan(const std::vector<int> &channels, int spin_offset, const int *lower = nullptr);
 
 // Pattern of an intermediate: what the block kernel builds once for all its
 // components -- the sink spin structure, the flavours of the two diquark roles
 // (the diquark tensor) and of the third role.
-constexpr int kNumPatterns = kNumSpinStructs * 8;
+constexpr int kNumPatterns = kNumSpinStructsAll * 8;
 inline int pattern_id(const Intermediate &I) {
     return ((I.sink_spin * 2 + I.pflav[0]) * 2 + I.pflav[1]) * 2 + I.pflav[2];
 }

@@ -1,0 +1,90 @@
+"""All 256 spin components (BBC_SPIN_FULL) on the GPU against the oracle's
+256-component assembly (every baryon's upper or lower pair chosen on its own,
+Sec. 2 fields, Sec. 6 components), element by element over every r; the
+all-upper and all-lower blocks against the UPPER and LOWER requests; argument
+errors."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import wick
+from oracle import operators as ops
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    import paper_1510_00903_amd as mod
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mod.load()
+    return mod
+
+
+def _run(ctx, Sl, Ss, chans, spin):
+    dev = torch.device("cuda:0")
+    out = ctx.correlate(torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev), list(range(Sl.shape[0])),
+                        chans, spin=spin)
+    torch.cuda.synchronize()
+    if isinstance(out, tuple):
+        return out[0].cpu().numpy().astype(np.complex128) * out[1].cpu().numpy()[:, :, None, None, None, None]
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype,tol,lat", [(np.complex128, 1e-12, (2, 2, 2)), (np.complex128, 1e-12, (3, 2, 1)),
+                                           (np.complex64, 1e-5, (4, 2, 3))])
+def test_full_spin_matches_oracle(bbc, dtype, tol, lat):
+    print("case: full spin", np.dtype(dtype).name, lat, flush=True)
+    Sl, Ss = synth.propagators(lat, 1, seed=161, dtype=dtype)
+    chans = [1, 2, 10, 51, bbc.channel_id("D++(1)", "O-(2)", "D++(1)", "O-(2)")]
+    ctx = bbc.Context(0)
+    got = _run(ctx, Sl, Ss, chans, bbc.FULL)
+    ctx.close()
+    assert got.shape[-1] == 256
+    S64l, S64s = Sl.astype(np.complex128), Ss.astype(np.complex128)
+    r = wick.all_r(*lat)
+    for m, c in enumerate(chans):
+        a, b = bbc.channel_name(c).split(">")
+        ref = wick.correlate_full(S64l[0], S64s[0], tuple(a.split() + b.split()), r)
+        err = np.abs(got[0, m].reshape(-1, 256) - ref).max() / np.abs(ref).max()
+        assert err <= tol, (bbc.channel_name(c), err)
+
+
+def test_full_spin_blocks_equal_upper_and_lower(bbc):
+    lat = (4, 4, 4)
+    print("case: full spin blocks", lat, flush=True)
+    Sl, Ss = synth.propagators(lat, 2, seed=163)
+    chans = list(range(0, 52, 5))
+    ctx = bbc.Context(0)
+    full = _run(ctx, Sl, Ss, chans, bbc.FULL)
+    up = _run(ctx, Sl, Ss, chans, bbc.UPPER)
+    lo = _run(ctx, Sl, Ss, chans, bbc.LOWER)
+    ctx.close()
+    s = np.arange(16)
+    a, b, ap, bp = s & 1, (s >> 1) & 1, (s >> 2) & 1, (s >> 3) & 1
+    # the all-upper evaluation is the UPPER request (same plan, same kernels)
+    assert np.array_equal(full[..., a + 4 * b + 16 * ap + 64 * bp], up)
+    iu = (a + 2) + 4 * (b + 2) + 16 * (ap + 2) + 64 * (bp + 2)
+    assert np.abs(full[..., iu] - lo).max() <= 1e-12 * np.abs(lo).max()
+
+
+def test_full_spin_argument_errors(bbc):
+    ctx = bbc.Context(0)
+    Sl, Ss = synth.propagators((2, 2, 2), 1, seed=165)
+    dev = torch.device("cuda:0")
+    dl, ds = torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
+    with pytest.raises(bbc.BBCError):            # 16 spin values per site: wrong shape for FULL
+        ctx.correlate(dl, ds, [0], [1], spin=bbc.FULL,
+                      out=torch.empty((1, 1, 2, 2, 2, 16), dtype=torch.complex128, device=dev))
+    with pytest.raises(bbc.BBCError):            # FULL writes device memory only
+        ctx.correlate(dl, ds, [0], [1], spin=bbc.FULL, out=torch.empty((1, 1, 2, 2, 2, 256), dtype=torch.complex128))
+    ctx.server_start(1)
+    h = ctx.prop_upload(dl, ds)
+    with pytest.raises(bbc.BBCError):            # the serving loop takes UPPER or LOWER (library check)
+        ctx.submit(h, [0], [0], [1], torch.empty((1, 1, 2, 2, 2, 16), dtype=torch.complex128, device=dev),
+                   spin=bbc.FULL)
+    ctx.prop_release(h)
+    ctx.server_stop()
+    ctx.close()
