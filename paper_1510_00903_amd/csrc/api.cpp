@@ -49,12 +49,13 @@ bbc_status fail(bbc_status s, const std::string &msg) {
 struct DevPlan {
     bbc::Plan plan;
     bbc::BlockPatterns pats;
-    int ntask = 0, npair = 0;
+    int ntask = 0, npair = 0, ntile = 0;
     // every table the kernels read, as one image (byte offsets below): block-kernel
     // component records and terms (kernels.hpp, BlockComp), pair tasks and channel
     // terms (pairs.hpp), per-channel quark content
     std::vector<unsigned char> image;
-    size_t off_terms = 0, off_comps = 0, off_tasks = 0, off_comb = 0, off_comb_begin = 0, off_content = 0;
+    size_t off_terms = 0, off_comps = 0, off_tasks = 0, off_tiles = 0, off_comb = 0, off_comb_begin = 0,
+           off_content = 0;
     void *d_image = nullptr;        // device copy, made by the entry points that allocate
     size_t table_bytes = 0;
     // request key: channel list, spin offset, precision, and a hash of the list
@@ -84,6 +85,7 @@ struct PlanDev {
     const uint32_t *terms;
     const bbc::BlockComp *comps;
     const bbc::PTask *tasks;
+    const bbc::PTask *tiles;
     const bbc::CombEntry *comb;
     const int32_t *comb_begin;
     const int2 *content;
@@ -91,8 +93,9 @@ struct PlanDev {
 PlanDev plan_dev(const DevPlan *dp, const void *base) {
     const char *b = (const char *)base;
     return PlanDev{dp, (const uint32_t *)(b + dp->off_terms), (const bbc::BlockComp *)(b + dp->off_comps),
-                   (const bbc::PTask *)(b + dp->off_tasks), (const bbc::CombEntry *)(b + dp->off_comb),
-                   (const int32_t *)(b + dp->off_comb_begin), (const int2 *)(b + dp->off_content)};
+                   (const bbc::PTask *)(b + dp->off_tasks), (const bbc::PTask *)(b + dp->off_tiles),
+                   (const bbc::CombEntry *)(b + dp->off_comb), (const int32_t *)(b + dp->off_comb_begin),
+                   (const int2 *)(b + dp->off_content)};
 }
 
 // Number of self-conjugate momenta (q = -q mod L): 0 and L/2 along each even axis.
@@ -428,6 +431,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
             return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
         }
         dp->ntask = (int)pt.tasks.size();
+        dp->ntile = (int)pt.tiles.size();
         dp->npair = pt.npair;
         std::vector<int2> content;
         for (int ch : P.channels) {
@@ -454,6 +458,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         dp->off_terms = image_put(img, kterms.data(), kterms.size());
         dp->off_comps = image_put(img, comps.data(), comps.size());
         dp->off_tasks = image_put(img, pt.tasks.data(), pt.tasks.size());
+        dp->off_tiles = image_put(img, pt.tiles.data(), pt.tiles.size());
         dp->off_comb = image_put(img, pt.comb.data(), pt.comb.size());
         dp->off_comb_begin = image_put(img, pt.comb_begin.data(), pt.comb_begin.size());
         dp->off_content = image_put(img, content.data(), content.size());
@@ -575,14 +580,14 @@ TuneKey tune_key(const int L[3], int prec, int spin_offset, uint64_t chash) {
 
 // Built-in choice for shapes without a tuning entry (the fastest variants
 // measured at 16^3 and 32^3 with 52 channels): the LDS-staged contraction
-// (FP64 per set of 4 momenta), and in FP32 the LDS-staged channel sums, 8 x 2
-// block workgroups and half-size plane-pass workgroups.
+// (FP64 two-row tiles per set of 4 momenta), and in FP32 the LDS-staged channel
+// sums, 8 x 2 block workgroups and half-size plane-pass workgroups.
 // Small lattices run several slices at once (a slice alone does not fill the GPU).
 bbc::Tuning default_tuning(const int L[3], int prec) {
     const long V = (long)L[0] * L[1] * L[2];
     const int sl = V <= 1024 ? 3 : V <= 4096 ? 1 : 0;
     if (prec == BBC_F32) return bbc::Tuning{2, 2, 1, sl, 2};
-    return bbc::Tuning{6, 0, 0, sl, 0};
+    return bbc::Tuning{8, 0, 0, sl, 0};
 }
 
 // Tuning of a request: the context's entry for its shape, else the built-in choice.
@@ -613,7 +618,8 @@ bbc_status enqueue_slice(bbc_context *ctx, const PlanDev &pd, const int L[3], lo
     TC *Ct = (TC *)ws;                            // reuses region A once Iq is written
     T2 *Pp = (T2 *)((char *)ws + lay.p);
     uint32_t *kmax = (uint32_t *)((char *)ws + lay.b);
-    bbc::PairDevTables tb{mg.pos, mg.ngroup, pd.tasks, dp->ntask, dp->npair, pd.comb, pd.comb_begin};
+    bbc::PairDevTables tb{mg.pos, mg.ngroup, pd.tasks, dp->ntask, pd.tiles, dp->ntile, dp->npair, pd.comb,
+                          pd.comb_begin};
     const T2 *sl = (const T2 *)slp, *ss = (const T2 *)ssp;
     T2 *out = (T2 *)outp;
     const bool fp32 = sizeof(T) == 4;

@@ -1914,6 +1914,166 @@ __global__ __launch_bounds__(256) void k_pairs_lds64s(const double2 *__restrict_
 #undef BBC_PAIRS_CASE
 }
 
+// FP64 two-row tile per set of 4 momenta (PairTables::tiles): the H views of
+// each of the two row views and the NP column views are staged through LDS per
+// round of 4 open-index items, as in pair_task64_lds1; row r multiplies column p
+// where its pair id is set (wave-uniform), so each product is formed with the
+// operands, order and MFMA sequence of the one-row tasks (same bits), while a
+// column view is loaded once for both rows.
+constexpr int kTileMaxViews = 10;                  // 2 H + NP
+template <int NP, int SHAPE>
+__device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
+                                            const PTask &T, int lane, int mir, int set0, double2 *wlds) {
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int V = 2 * H + NP, NL = 8 * V;
+    static_assert(V <= kTileMaxViews, "tile views");
+    constexpr int G = GroupLayout<double2>::G;
+    const int ij = lane & 3, blk = (lane >> 2) & 3, kl = lane >> 4;
+    const int g = ij & 1, o = ij >> 1;
+    const int mm = blk + 4 * set0;
+    const int srow = (T.row_site == 0 ? mm : mir) - 4 * set0, scol = (T.row_site == 0 ? mir : mm) - 4 * set0;
+    const bool colvalid = SHAPE == 0 || ij < 2;
+    const int q = lane >> 3, ld_o = q & 1, ld_kl = q >> 1;
+    const double2 *gsrc = gb + 8 * set0 + (lane & 7);
+    const int K = T.K, nround = (K + 3) / 4;
+    const int nrow = __builtin_amdgcn_readfirstlane(T.nrow);
+    int pid[2][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        pid[0][p] = __builtin_amdgcn_readfirstlane(T.pair[p]);
+        pid[1][p] = __builtin_amdgcn_readfirstlane(T.pair2[p]);
+    }
+    auto issue = [&](int r) {
+        const int kk0 = r * 4 + ld_kl;
+        const int kk = kk0 < K ? kk0 : 0;                  // past K: an in-range line, never read
+        const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (v >= H && v < 2 * H && nrow < 2) continue;   // no second row
+            const bool isrow = v < 2 * H;
+            const PView &vw = v < H ? T.row : (isrow ? T.row2 : T.col[v - 2 * H]);
+            int ostr, base = vw.base;
+            if (SHAPE == 0) ostr = isrow ? outer_stride(vw, T.row_a) : outer_stride(vw, !T.row_a);
+            else { ostr = isrow ? vw.so3 : 0; if (isrow) base += (v % H) * vw.so4; }
+            const int comp = base + ld_o * ostr + k3 * vw.sk3 + k4 * vw.sk4;
+            __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * (2 * G)),
+                                             (lds_void *)(wlds + v * 8 * 8), 16, 0, 0);
+        }
+    };
+    double acc[2][NP][H][2];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < H; ++h) acc[rr][p][h][0] = acc[rr][p][h][1] = 0.0;
+    auto compute = [&](int r) {
+        const double2 *L = wlds;
+        const bool valid = r * 4 + kl < K;
+        double2 av[2][H], bv[NP];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int li = ((rr * H + h) * 4 + kl) * 2 + o;
+                av[rr][h] = L[li * 8 + srow * 2 + g];
+                av[rr][h] = valid ? av[rr][h] : double2{0.0, 0.0};
+            }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int li = ((2 * H + p) * 4 + kl) * 2 + o;
+            bv[p] = L[li * 8 + scol * 2 + g];
+            bv[p] = (valid && colvalid) ? bv[p] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                if (pid[rr][p] < 0) continue;
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const double2 a = av[rr][h], b = bv[p];
+                    double re = acc[rr][p][h][0], im = acc[rr][p][h][1];
+                    re = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.x, re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f64_4x4x4f64(-a.y, b.y, re, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, b.y, im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, b.x, im, 0, 0, 0);
+                    acc[rr][p][h][0] = re;
+                    acc[rr][p][h][1] = im;
+                }
+            }
+    };
+    for (int r = 0; r < nround; ++r) {
+        issue(r);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        compute(r);
+    }
+    // D lane (j = lane & 3, block, i = lane >> 4)
+    const int j = lane & 3, i = lane >> 4;
+    if (SHAPE == 1 && j >= 2) return;
+    const int gR = i & 1, oR = i >> 1, gC = j & 1, oC = j >> 1;
+    const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        int ap, bp;
+        if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+        else { ap = oR; bp = h; }
+        const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr)
+                if (pid[rr][p] >= 0)
+                    pb[((size_t)pid[rr][p] * 16 + sp) * G + mm] = double2{acc[rr][p][h][0], acc[rr][p][h][1]};
+    }
+}
+
+// FP64 two-row tiles per set: one wave per (tile, set of 4 momenta), workgroups of
+// 4 waves, the workgroups of a group consecutive on one XCD.
+__global__ __launch_bounds__(256) void k_pairs_tiles64s(const double2 *__restrict__ Iq, double2 *__restrict__ P,
+                                                        int nc, int ubase, int ucount,
+                                                        const int2 *__restrict__ gpos, int ngroup,
+                                                        const PTask *__restrict__ tiles, int ntile, int npair) {
+    constexpr int G = GroupLayout<double2>::G;
+    constexpr int BUF16 = 8 * kTileMaxViews * 8;           // 16-byte units per wave (10 KB)
+    __shared__ double2 lds[4 * BUF16];
+    const int nitem = ntile * 2;
+    const int nchunk = (nitem + 3) >> 2;
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    const int P8 = (ucount + 7) >> 3;
+    const int ul = xcd * P8 + jj / nchunk;
+    const int chunk = jj - (jj / nchunk) * nchunk;
+    if (ul >= ucount) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int item = chunk * 4 + wave;
+    if (item >= nitem) return;
+    const int t = item >> 1, set0 = item & 1;
+    const int lane = threadIdx.x & 63;
+    const int grp = ubase + ul;
+    const double2 *g0 = Iq + (size_t)grp * nc * 2 * G;
+    double2 *p0 = P + (size_t)grp * npair * 16 * G;
+    double2 *wlds = lds + wave * BUF16;
+    const int mir = gpos[(size_t)grp * G + ((lane >> 2) & 3) + 4 * set0].y;
+    const PTask &Tk = tiles[t];
+    const int np = __builtin_amdgcn_readfirstlane(Tk.np);
+    const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
+#define BBC_TILE_CASE(SH, N) \
+    case N: pair_tile64<N, SH>(g0, p0, Tk, lane, mir, set0, wlds); break;
+    if (shape == 0) {
+        switch (np) {
+            BBC_TILE_CASE(0, 1) BBC_TILE_CASE(0, 2) BBC_TILE_CASE(0, 3) BBC_TILE_CASE(0, 4)
+            BBC_TILE_CASE(0, 5) BBC_TILE_CASE(0, 6) BBC_TILE_CASE(0, 7) BBC_TILE_CASE(0, 8)
+            default: break;
+        }
+    } else {
+        switch (np) {
+            BBC_TILE_CASE(1, 1) BBC_TILE_CASE(1, 2) BBC_TILE_CASE(1, 3) BBC_TILE_CASE(1, 4)
+            default: break;
+        }
+    }
+#undef BBC_TILE_CASE
+}
+
 // One wave per task of a momentum unit (FP64: one group; FP32: two groups),
 // operands staged through each wave's LDS area; workgroups of 4 waves, the
 // workgroups of a unit consecutive on one XCD.
@@ -2165,11 +2325,25 @@ static void launch_pairs_lds64s(const double2 *Iq, double2 *P, int nc, const Pai
     }
 }
 
+static void launch_pairs_tiles64s(const double2 *Iq, double2 *P, int nc, const PairDevTables &tb, hipStream_t st) {
+    const int nunit = tb.ngroup;
+    const long nchunk = ((long)tb.ntile * 2 + 3) / 4;
+    if (nchunk == 0) return;
+    const long max_wg = (1L << 32) / 256 - 64;
+    const int per = (int)std::max<long>(8, std::min<long>(nunit, (max_wg / nchunk) / 8 * 8));
+    for (int u0 = 0; u0 < nunit; u0 += per) {
+        const int uc = std::min(per, nunit - u0);
+        const long nwg = 8L * ((uc + 7) / 8) * nchunk;
+        hipLaunchKernelGGL(k_pairs_tiles64s, dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+                           tb.ngroup, tb.tiles, tb.ntile, tb.npair);
+    }
+}
+
 // Variants (same products in the same order, so the same bits): FP64 0 = whole
 // group per wave, 1 = whole group, pipelined, 2 = half group, 3 = half group,
 // pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered,
-// 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered;
-// FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
+// 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered,
+// 8 = two-row tiles staged per set of 4 momenta; FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
 // double-buffered, 4 = staged, 4 open indices per round.
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
@@ -2183,6 +2357,7 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
         case 5: launch_pairs_lds<T, true>(Iq, P, nc, tb, st); break;
         case 6: launch_pairs_lds64s<false>(Iq, P, nc, tb, st); break;
         case 7: launch_pairs_lds64s<true>(Iq, P, nc, tb, st); break;
+        case 8: launch_pairs_tiles64s((const double2 *)Iq, (double2 *)P, nc, tb, st); break;
         default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
         }
     } else {

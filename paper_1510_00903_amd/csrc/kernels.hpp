@@ -15,6 +15,8 @@ struct PairDevTables {
     int ngroup;                   // momentum groups (G positions each)
     const PTask *tasks;
     int ntask;
+    const PTask *tiles;           // the same products as two-row tiles (pairs.hpp)
+    int ntile;
     int npair;
     const CombEntry *comb;        // channel terms, pair-major (pairs.hpp)
     const int32_t *comb_begin;    // per chunk of kCombChunk channels and class: entry ranges
@@ -118,7 +120,7 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 struct Tuning {
     int pairs = 0, blocks = 0, planes = 0, slices = 0, combine = 0;
 };
-constexpr int kPairVariants64 = 8, kPairVariants32 = 5, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
+constexpr int kPairVariants64 = 9, kPairVariants32 = 5, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
               kCombineVariants = 3;
 constexpr int kMaxSliceStreams = 1 << (kSliceVariants - 1);
 

@@ -53,6 +53,12 @@ struct PTask {
     PView row;
     PView col[kMaxPartners];
     int32_t pair[kMaxPartners];
+    // two-row tiles (PairTables::tiles): a second row view of the same class with
+    // its own products against the same columns; pair[i], pair2[i] = -1 where
+    // that row does not pair with column i.  nrow = 1 in PairTables::tasks.
+    int32_t nrow;
+    PView row2;
+    int32_t pair2[kMaxPartners];
 };
 
 // One channel term in pair-major order: channel ch (within its chunk) gains
@@ -67,6 +73,10 @@ constexpr int kCombSubs = 8;          // channel classes (ch mod 8) per pass
 
 struct PairTables {
     std::vector<PTask> tasks;         // most expensive first
+    // the same products as tiles of two row views sharing up to kMaxPartners
+    // (shape 1: kMaxPartners / 2) column views, rows of a class paired greedily by
+    // common partners, so that a column view is loaded once for both rows
+    std::vector<PTask> tiles;
     int npair = 0;
     std::vector<int32_t> term_begin;  // per requested channel, n_ch + 1 entries
     std::vector<int32_t> term_pair;

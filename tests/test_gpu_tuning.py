@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 CHANNELS = list(range(52))
-N_PAIRS = {"f64": 8, "f32": 5}
+N_PAIRS = {"f64": 9, "f32": 5}
 
 
 @pytest.fixture(scope="module")
@@ -127,7 +127,7 @@ def test_autotune_stores_and_round_trips(bbc, tmp_path):
         t0, tuned0 = ctx.tuning(lat, CHANNELS)
         assert not tuned0
         best, ms = ctx.autotune(dl[0].contiguous(), ds[0].contiguous(), CHANNELS, reps=2)
-        assert 0 <= best["pairs"] < 8 and 0 <= best["blocks"] < 3 and best["planes"] == 0
+        assert 0 <= best["pairs"] < 9 and 0 <= best["blocks"] < 3 and best["planes"] == 0
         assert 0 <= best["slices"] < 4 and 0 <= best["combine"] < 3
         assert ms > 0
         t1, tuned1 = ctx.tuning(lat, CHANNELS)
@@ -159,7 +159,7 @@ def test_autotune_stores_and_round_trips(bbc, tmp_path):
 def test_tuning_errors(bbc, tmp_path):
     ctx = bbc.Context(0)
     with pytest.raises(bbc.BBCError):
-        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 8, "blocks": 0, "planes": 0})
+        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 9, "blocks": 0, "planes": 0})
     with pytest.raises(bbc.BBCError):
         ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 5, "blocks": 0, "planes": 0}, precision=bbc.F32)
     with pytest.raises(bbc.BBCError):
