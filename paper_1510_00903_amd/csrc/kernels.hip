@@ -2028,6 +2028,178 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
     }
 }
 
+// FP32 two-row tile over two groups (16 momenta), 2 open indices per round:
+// pair_task32_lds with a second row view (same operands, order and MFMA
+// sequence per product, so the same bits).
+template <int NP, int SHAPE>
+__device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
+                                            float2 *__restrict__ pb0, float2 *__restrict__ pb1, bool has1,
+                                            const PTask &T, int lane, int mir, float4 *wlds) {
+    constexpr int KS = 2;
+    constexpr int H = SHAPE == 1 ? 2 : 1;
+    constexpr int V = 2 * H + NP, NL = 4 * KS * V;
+    static_assert(V <= kTileMaxViews, "tile views");
+    constexpr int G = GroupLayout<float2>::G;
+    const int ij = lane & 3, blk = lane >> 2;
+    const int g = ij & 1, o = ij >> 1;
+    const bool second = blk >= 8;
+    const bool active = !second || has1;
+    const int m = blk & 7;
+    const int srow = T.row_site == 0 ? m : mir, scol = T.row_site == 0 ? mir : m;
+    const bool colvalid = active && (SHAPE == 0 || ij < 2);
+    const int q = lane >> 3, ld_o = q & 1, ld_g1 = (q >> 1) & 1, ld_kr = q >> 2;
+    const float4 *gsrc = (const float4 *)(ld_g1 ? gb1 : gb0) + (lane & 7);
+    const int K = T.K, nround = (K + KS - 1) / KS;
+    const int nrow = __builtin_amdgcn_readfirstlane(T.nrow);
+    int pid[2][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        pid[0][p] = __builtin_amdgcn_readfirstlane(T.pair[p]);
+        pid[1][p] = __builtin_amdgcn_readfirstlane(T.pair2[p]);
+    }
+    auto issue = [&](int r) {
+        const int kk0 = r * KS + ld_kr;
+        const int kk = kk0 < K ? kk0 : 0;                  // past K: an in-range line, never read
+        const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (v >= H && v < 2 * H && nrow < 2) continue;   // no second row
+            const bool isrow = v < 2 * H;
+            const PView &vw = v < H ? T.row : (isrow ? T.row2 : T.col[v - 2 * H]);
+            int ostr, base = vw.base;
+            if (SHAPE == 0) ostr = isrow ? outer_stride(vw, T.row_a) : outer_stride(vw, !T.row_a);
+            else { ostr = isrow ? vw.so3 : 0; if (isrow) base += (v % H) * vw.so4; }
+            const int comp = base + ld_o * ostr + k3 * vw.sk3 + k4 * vw.sk4;
+            __builtin_amdgcn_global_load_lds((const void *)(gsrc + (size_t)(unsigned)comp * G),
+                                             (lds_void *)(wlds + v * 8 * 8), 16, 0, 0);
+        }
+    };
+    fmfma4 acc[2][NP][H][2];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < H; ++h) acc[rr][p][h][0] = acc[rr][p][h][1] = fmfma4{0.f, 0.f, 0.f, 0.f};
+    const int gl = second ? 1 : 0;
+    auto compute = [&](int r) {
+        const float2 *L2 = (const float2 *)wlds;
+#pragma unroll
+        for (int kr = 0; kr < KS; ++kr) {
+            if (r * KS + kr >= K) break;
+            float2 av[2][H], bv[NP];
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const int li = (((rr * H + h) * KS + kr) * 2 + gl) * 2 + o;
+                    av[rr][h] = L2[li * 16 + srow * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
+                    av[rr][h] = active ? av[rr][h] : float2{0.f, 0.f};
+                }
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int li = (((2 * H + p) * KS + kr) * 2 + gl) * 2 + o;
+                bv[p] = L2[li * 16 + scol * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
+                bv[p] = colvalid ? bv[p] : float2{0.f, 0.f};
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    if (pid[rr][p] < 0) continue;
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        const float2 a = av[rr][h], b = bv[p];
+                        fmfma4 re = acc[rr][p][h][0], im = acc[rr][p][h][1];
+                        re = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.x, re, 0, 0, 0);
+                        re = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.y, b.y, re, 0, 0, 0);
+                        im = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.y, im, 0, 0, 0);
+                        im = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.x, im, 0, 0, 0);
+                        acc[rr][p][h][0] = re;
+                        acc[rr][p][h][1] = im;
+                    }
+                }
+        }
+    };
+    for (int r = 0; r < nround; ++r) {
+        issue(r);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        compute(r);
+    }
+    const int j = lane & 3;
+    if (!active || (SHAPE == 1 && j >= 2)) return;
+    float2 *pb = second ? pb1 : pb0;
+    const int gC = j & 1, oC = j >> 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gR = i & 1, oR = i >> 1;
+        const int a = T.row_site == 0 ? gR : gC, b = T.row_site == 0 ? gC : gR;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            int ap, bp;
+            if (SHAPE == 0) { ap = T.row_a ? oR : oC; bp = T.row_a ? oC : oR; }
+            else { ap = oR; bp = h; }
+            const int sp = a + 2 * b + 4 * ap + 8 * bp;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr)
+                    if (pid[rr][p] >= 0)
+                        pb[((size_t)pid[rr][p] * 16 + sp) * G + m] =
+                            float2{acc[rr][p][h][0][i], acc[rr][p][h][1][i]};
+        }
+    }
+}
+
+// FP32 two-row tiles: one wave per (tile, unit of two groups), workgroups of 4
+// waves, the workgroups of a unit consecutive on one XCD.
+__global__ __launch_bounds__(256) void k_pairs_tiles32(const float2 *__restrict__ Iq, float2 *__restrict__ P, int nc,
+                                                       int ubase, int ucount, const int2 *__restrict__ gpos,
+                                                       int ngroup, const PTask *__restrict__ tiles, int ntile,
+                                                       int npair) {
+    constexpr int G = GroupLayout<float2>::G;
+    constexpr int BUF16 = 4 * 2 * kTileMaxViews * 8;       // 16-byte units per wave (10 KB)
+    __shared__ float4 lds[4 * BUF16];
+    const int nchunk = (ntile + 3) >> 2;
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    const int P8 = (ucount + 7) >> 3;
+    const int ul = xcd * P8 + jj / nchunk;
+    const int chunk = jj - (jj / nchunk) * nchunk;
+    if (ul >= ucount) return;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = chunk * 4 + wave;
+    if (t >= ntile) return;
+    const int lane = threadIdx.x & 63;
+    const int grp0 = (ubase + ul) * 2;
+    const bool has1 = grp0 + 1 < ngroup;
+    const float2 *g0 = Iq + (size_t)grp0 * nc * 2 * G;
+    const float2 *g1 = has1 ? g0 + (size_t)nc * 2 * G : g0;
+    float2 *p0 = P + (size_t)grp0 * npair * 16 * G;
+    float2 *p1 = has1 ? p0 + (size_t)npair * 16 * G : p0;
+    float4 *wlds = lds + wave * BUF16;
+    const int blk = lane >> 2;
+    const int gg = (blk >= 8 && has1) ? grp0 + 1 : grp0;
+    const int mir = gpos[(size_t)gg * G + (blk & 7)].y;
+    const PTask &Tk = tiles[t];
+    const int np = __builtin_amdgcn_readfirstlane(Tk.np);
+    const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
+#define BBC_TILE32_CASE(SH, N) \
+    case N: pair_tile32<N, SH>(g0, g1, p0, p1, has1, Tk, lane, mir, wlds); break;
+    if (shape == 0) {
+        switch (np) {
+            BBC_TILE32_CASE(0, 1) BBC_TILE32_CASE(0, 2) BBC_TILE32_CASE(0, 3) BBC_TILE32_CASE(0, 4)
+            BBC_TILE32_CASE(0, 5) BBC_TILE32_CASE(0, 6) BBC_TILE32_CASE(0, 7) BBC_TILE32_CASE(0, 8)
+            default: break;
+        }
+    } else {
+        switch (np) {
+            BBC_TILE32_CASE(1, 1) BBC_TILE32_CASE(1, 2) BBC_TILE32_CASE(1, 3) BBC_TILE32_CASE(1, 4)
+            default: break;
+        }
+    }
+#undef BBC_TILE32_CASE
+}
+
 // FP64 two-row tiles per set: one wave per (tile, set of 4 momenta), workgroups of
 // 4 waves, the workgroups of a group consecutive on one XCD.
 __global__ __launch_bounds__(256) void k_pairs_tiles64s(const double2 *__restrict__ Iq, double2 *__restrict__ P,
@@ -2339,12 +2511,26 @@ static void launch_pairs_tiles64s(const double2 *Iq, double2 *P, int nc, const P
     }
 }
 
+static void launch_pairs_tiles32(const float2 *Iq, float2 *P, int nc, const PairDevTables &tb, hipStream_t st) {
+    const int nunit = (tb.ngroup + 1) / 2;
+    const long nchunk = ((long)tb.ntile + 3) / 4;
+    if (nchunk == 0) return;
+    const long max_wg = (1L << 32) / 256 - 64;
+    const int per = (int)std::max<long>(8, std::min<long>(nunit, (max_wg / nchunk) / 8 * 8));
+    for (int u0 = 0; u0 < nunit; u0 += per) {
+        const int uc = std::min(per, nunit - u0);
+        const long nwg = 8L * ((uc + 7) / 8) * nchunk;
+        hipLaunchKernelGGL(k_pairs_tiles32, dim3((unsigned)nwg), dim3(256), 0, st, Iq, P, nc, u0, uc, tb.gpos,
+                           tb.ngroup, tb.tiles, tb.ntile, tb.npair);
+    }
+}
+
 // Variants (same products in the same order, so the same bits): FP64 0 = whole
 // group per wave, 1 = whole group, pipelined, 2 = half group, 3 = half group,
 // pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered,
 // 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered,
 // 8 = two-row tiles staged per set of 4 momenta; FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
-// double-buffered, 4 = staged, 4 open indices per round.
+// double-buffered, 4 = staged, 4 open indices per round, 5 = two-row tiles.
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
                   int variant, hipStream_t st) {
@@ -2366,6 +2552,7 @@ void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *
         case 2: launch_pairs_lds<T, false>(Iq, P, nc, tb, st); break;
         case 3: launch_pairs_lds<T, true>(Iq, P, nc, tb, st); break;
         case 4: launch_pairs_lds<T, false, 4>(Iq, P, nc, tb, st); break;
+        case 5: launch_pairs_tiles32((const float2 *)Iq, (float2 *)P, nc, tb, st); break;
         default: launch_pairs_v<T, 2, false>(Iq, P, nc, tb, st); break;
         }
     }

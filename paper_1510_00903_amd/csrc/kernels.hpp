@@ -120,7 +120,7 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 struct Tuning {
     int pairs = 0, blocks = 0, planes = 0, slices = 0, combine = 0;
 };
-constexpr int kPairVariants64 = 9, kPairVariants32 = 5, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
+constexpr int kPairVariants64 = 9, kPairVariants32 = 6, kBlockVariants = 3, kPlaneVariants = 2, kSliceVariants = 4,
               kCombineVariants = 3;
 constexpr int kMaxSliceStreams = 1 << (kSliceVariants - 1);
 

@@ -25,7 +25,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 CHANNELS = list(range(52))
-N_PAIRS = {"f64": 9, "f32": 5}
+N_PAIRS = {"f64": 9, "f32": 6}
 
 
 @pytest.fixture(scope="module")
@@ -161,7 +161,7 @@ def test_tuning_errors(bbc, tmp_path):
     with pytest.raises(bbc.BBCError):
         ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 9, "blocks": 0, "planes": 0})
     with pytest.raises(bbc.BBCError):
-        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 5, "blocks": 0, "planes": 0}, precision=bbc.F32)
+        ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 6, "blocks": 0, "planes": 0}, precision=bbc.F32)
     with pytest.raises(bbc.BBCError):
         ctx.set_tuning((8, 8, 8), CHANNELS, {"pairs": 0, "blocks": 0, "planes": 0, "slices": 4})
     bad = tmp_path / "bad.json"
