@@ -1914,18 +1914,19 @@ __global__ __launch_bounds__(256) void k_pairs_lds64s(const double2 *__restrict_
 #undef BBC_PAIRS_CASE
 }
 
-// FP64 two-row tile per set of 4 momenta (PairTables::tiles): the H views of
-// each of the two row views and the NP column views are staged through LDS per
-// round of 4 open-index items, as in pair_task64_lds1; row r multiplies column p
-// where its pair id is set (wave-uniform), so each product is formed with the
-// operands, order and MFMA sequence of the one-row tasks (same bits), while a
-// column view is loaded once for both rows.
-constexpr int kTileMaxViews = 10;                  // 2 H + NP
+// FP64 row tile per set of 4 momenta (PairTables::tiles): the H views of each of
+// the tile's row views (up to 2) and the NP column views are staged
+// through LDS per round of 4 open-index items, as in pair_task64_lds1; row r
+// multiplies column p where its pair id is set (wave-uniform), so each product is
+// formed with the operands, order and MFMA sequence of the one-row tasks (same
+// bits), while a column view is loaded once for all rows of the tile.
+constexpr int kTileMaxViews = 10;                  // R H + NP (R = 2 rows)
 template <int NP, int SHAPE>
 __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
                                             const PTask &T, int lane, int mir, int set0, double2 *wlds) {
     constexpr int H = SHAPE == 1 ? 2 : 1;
-    constexpr int V = 2 * H + NP, NL = 8 * V;
+    constexpr int R = 2;                           // plans hold tiles of at most 2 rows
+    constexpr int V = R * H + NP, NL = 8 * V;
     static_assert(V <= kTileMaxViews, "tile views");
     constexpr int G = GroupLayout<double2>::G;
     const int ij = lane & 3, blk = (lane >> 2) & 3, kl = lane >> 4;
@@ -1937,11 +1938,12 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
     const double2 *gsrc = gb + 8 * set0 + (lane & 7);
     const int K = T.K, nround = (K + 3) / 4;
     const int nrow = __builtin_amdgcn_readfirstlane(T.nrow);
-    int pid[2][NP];
+    int pid[R][NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         pid[0][p] = __builtin_amdgcn_readfirstlane(T.pair[p]);
-        pid[1][p] = __builtin_amdgcn_readfirstlane(T.pair2[p]);
+#pragma unroll
+        for (int rr = 1; rr < R; ++rr) pid[rr][p] = rr < nrow ? __builtin_amdgcn_readfirstlane(T.pairx[rr - 1][p]) : -1;
     }
     auto issue = [&](int r) {
         const int kk0 = r * 4 + ld_kl;
@@ -1949,9 +1951,9 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
         const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            if (v >= H && v < 2 * H && nrow < 2) continue;   // no second row
-            const bool isrow = v < 2 * H;
-            const PView &vw = v < H ? T.row : (isrow ? T.row2 : T.col[v - 2 * H]);
+            const bool isrow = v < R * H;
+            if (isrow && v / H >= nrow) continue;           // no such row in this tile
+            const PView &vw = v < H ? T.row : (isrow ? T.rowx[v / H - 1] : T.col[v - R * H]);
             int ostr, base = vw.base;
             if (SHAPE == 0) ostr = isrow ? outer_stride(vw, T.row_a) : outer_stride(vw, !T.row_a);
             else { ostr = isrow ? vw.so3 : 0; if (isrow) base += (v % H) * vw.so4; }
@@ -1960,9 +1962,9 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
                                              (lds_void *)(wlds + v * 8 * 8), 16, 0, 0);
         }
     };
-    double acc[2][NP][H][2];
+    double acc[R][NP][H][2];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
+    for (int rr = 0; rr < R; ++rr)
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1970,9 +1972,9 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
     auto compute = [&](int r) {
         const double2 *L = wlds;
         const bool valid = r * 4 + kl < K;
-        double2 av[2][H], bv[NP];
+        double2 av[R][H], bv[NP];
 #pragma unroll
-        for (int rr = 0; rr < 2; ++rr)
+        for (int rr = 0; rr < R; ++rr)
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const int li = ((rr * H + h) * 4 + kl) * 2 + o;
@@ -1981,14 +1983,14 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
             }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int li = ((2 * H + p) * 4 + kl) * 2 + o;
+            const int li = ((R * H + p) * 4 + kl) * 2 + o;
             bv[p] = L[li * 8 + scol * 2 + g];
             bv[p] = (valid && colvalid) ? bv[p] : double2{0.0, 0.0};
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int rr = 0; rr < 2; ++rr) {
+            for (int rr = 0; rr < R; ++rr) {
                 if (pid[rr][p] < 0) continue;
 #pragma unroll
                 for (int h = 0; h < H; ++h) {
@@ -2022,14 +2024,14 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int rr = 0; rr < 2; ++rr)
+            for (int rr = 0; rr < R; ++rr)
                 if (pid[rr][p] >= 0)
                     pb[((size_t)pid[rr][p] * 16 + sp) * G + mm] = double2{acc[rr][p][h][0], acc[rr][p][h][1]};
     }
 }
 
-// FP32 two-row tile over two groups (16 momenta), 2 open indices per round:
-// pair_task32_lds with a second row view (same operands, order and MFMA
+// FP32 row tile over two groups (16 momenta), 2 open indices per round:
+// pair_task32_lds with up to 2 row views (same operands, order and MFMA
 // sequence per product, so the same bits).
 template <int NP, int SHAPE>
 __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
@@ -2037,7 +2039,8 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
                                             const PTask &T, int lane, int mir, float4 *wlds) {
     constexpr int KS = 2;
     constexpr int H = SHAPE == 1 ? 2 : 1;
-    constexpr int V = 2 * H + NP, NL = 4 * KS * V;
+    constexpr int R = 2;                           // FP32 plans hold tiles of at most 2 rows
+    constexpr int V = R * H + NP, NL = 4 * KS * V;
     static_assert(V <= kTileMaxViews, "tile views");
     constexpr int G = GroupLayout<float2>::G;
     const int ij = lane & 3, blk = lane >> 2;
@@ -2051,11 +2054,12 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
     const float4 *gsrc = (const float4 *)(ld_g1 ? gb1 : gb0) + (lane & 7);
     const int K = T.K, nround = (K + KS - 1) / KS;
     const int nrow = __builtin_amdgcn_readfirstlane(T.nrow);
-    int pid[2][NP];
+    int pid[R][NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         pid[0][p] = __builtin_amdgcn_readfirstlane(T.pair[p]);
-        pid[1][p] = __builtin_amdgcn_readfirstlane(T.pair2[p]);
+#pragma unroll
+        for (int rr = 1; rr < R; ++rr) pid[rr][p] = rr < nrow ? __builtin_amdgcn_readfirstlane(T.pairx[rr - 1][p]) : -1;
     }
     auto issue = [&](int r) {
         const int kk0 = r * KS + ld_kr;
@@ -2063,9 +2067,9 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
         const int k3 = (kk * T.inv) >> 16, k4 = kk - k3 * T.kd4;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            if (v >= H && v < 2 * H && nrow < 2) continue;   // no second row
-            const bool isrow = v < 2 * H;
-            const PView &vw = v < H ? T.row : (isrow ? T.row2 : T.col[v - 2 * H]);
+            const bool isrow = v < R * H;
+            if (isrow && v / H >= nrow) continue;           // no such row in this tile
+            const PView &vw = v < H ? T.row : (isrow ? T.rowx[v / H - 1] : T.col[v - R * H]);
             int ostr, base = vw.base;
             if (SHAPE == 0) ostr = isrow ? outer_stride(vw, T.row_a) : outer_stride(vw, !T.row_a);
             else { ostr = isrow ? vw.so3 : 0; if (isrow) base += (v % H) * vw.so4; }
@@ -2074,9 +2078,9 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
                                              (lds_void *)(wlds + v * 8 * 8), 16, 0, 0);
         }
     };
-    fmfma4 acc[2][NP][H][2];
+    fmfma4 acc[R][NP][H][2];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
+    for (int rr = 0; rr < R; ++rr)
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -2087,9 +2091,9 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
 #pragma unroll
         for (int kr = 0; kr < KS; ++kr) {
             if (r * KS + kr >= K) break;
-            float2 av[2][H], bv[NP];
+            float2 av[R][H], bv[NP];
 #pragma unroll
-            for (int rr = 0; rr < 2; ++rr)
+            for (int rr = 0; rr < R; ++rr)
 #pragma unroll
                 for (int h = 0; h < H; ++h) {
                     const int li = (((rr * H + h) * KS + kr) * 2 + gl) * 2 + o;
@@ -2098,14 +2102,14 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
                 }
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const int li = (((2 * H + p) * KS + kr) * 2 + gl) * 2 + o;
+                const int li = (((R * H + p) * KS + kr) * 2 + gl) * 2 + o;
                 bv[p] = L2[li * 16 + scol * GroupLayout<float2>::S + g * GroupLayout<float2>::SG];
                 bv[p] = colvalid ? bv[p] : float2{0.f, 0.f};
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
-                for (int rr = 0; rr < 2; ++rr) {
+                for (int rr = 0; rr < R; ++rr) {
                     if (pid[rr][p] < 0) continue;
 #pragma unroll
                     for (int h = 0; h < H; ++h) {
@@ -2143,7 +2147,7 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
-                for (int rr = 0; rr < 2; ++rr)
+                for (int rr = 0; rr < R; ++rr)
                     if (pid[rr][p] >= 0)
                         pb[((size_t)pid[rr][p] * 16 + sp) * G + m] =
                             float2{acc[rr][p][h][0][i], acc[rr][p][h][1][i]};
@@ -2151,7 +2155,7 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
     }
 }
 
-// FP32 two-row tiles: one wave per (tile, unit of two groups), workgroups of 4
+// FP32 row tiles: one wave per (tile, unit of two groups), workgroups of 4
 // waves, the workgroups of a unit consecutive on one XCD.
 __global__ __launch_bounds__(256) void k_pairs_tiles32(const float2 *__restrict__ Iq, float2 *__restrict__ P, int nc,
                                                        int ubase, int ucount, const int2 *__restrict__ gpos,
@@ -2200,7 +2204,7 @@ __global__ __launch_bounds__(256) void k_pairs_tiles32(const float2 *__restrict_
 #undef BBC_TILE32_CASE
 }
 
-// FP64 two-row tiles per set: one wave per (tile, set of 4 momenta), workgroups of
+// FP64 row tiles per set: one wave per (tile, set of 4 momenta), workgroups of
 // 4 waves, the workgroups of a group consecutive on one XCD.
 __global__ __launch_bounds__(256) void k_pairs_tiles64s(const double2 *__restrict__ Iq, double2 *__restrict__ P,
                                                         int nc, int ubase, int ucount,
@@ -2530,7 +2534,7 @@ static void launch_pairs_tiles32(const float2 *Iq, float2 *P, int nc, const Pair
 // pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered,
 // 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered,
 // 8 = two-row tiles staged per set of 4 momenta; FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
-// double-buffered, 4 = staged, 4 open indices per round, 5 = two-row tiles.
+// double-buffered, 4 = staged, 4 open indices per round, 5 = row tiles.
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
                   int variant, hipStream_t st) {

@@ -40,7 +40,8 @@ struct PairInfo {
 
 }  // namespace
 
-PairTables build_pair_tables(const Plan &P) {
+PairTables build_pair_tables(const Plan &P, int tile_rows) {
+    if (tile_rows < 1 || tile_rows > kMaxTileRows) throw std::logic_error("tile rows");
     PairTables T;
     const int n = (int)P.channels.size();
     std::map<PairKey, int> pair_index;
@@ -159,16 +160,18 @@ PairTables build_pair_tables(const Plan &P) {
             const int halves = shape == 1 ? 2 : 1;
             t.cost = steps * (2 * halves + t.np * (2 + 8 * halves));
             t.nrow = 1;
-            for (int i = 0; i < kMaxPartners; ++i) t.pair2[i] = -1;
+            for (int r = 0; r < kMaxTileRows - 1; ++r)
+                for (int i = 0; i < kMaxPartners; ++i) t.pairx[r][i] = -1;
             T.tasks.push_back(t);
         }
     }
     std::stable_sort(T.tasks.begin(), T.tasks.end(), [](const PTask &a, const PTask &b) { return a.cost > b.cost; });
 
-    // Two-row tiles.  Per (row site, class): each row view in turn (in key order)
-    // is paired with the not yet taken row view sharing most column views with
-    // it (at least two); the union of their columns, in key order, is cut into
-    // tiles of maxp columns.
+    // Row tiles.  Per (row site, class): each row view in turn (in key order)
+    // starts a tile, and the not yet taken row view sharing most column views
+    // with the tile's columns so far (at least two) joins it, up to kMaxTileRows
+    // rows; the union of their columns, in key order, is cut into tiles of maxp
+    // columns.
     std::map<std::pair<int, ClassKey>, std::vector<ViewKey>> rows_of_class;
     for (const auto &kv : rows) rows_of_class[{std::get<0>(kv.first), std::get<1>(kv.first)}].push_back(std::get<2>(kv.first));
     for (const auto &rc : rows_of_class) {
@@ -183,28 +186,35 @@ PairTables build_pair_tables(const Plan &P) {
         for (size_t i = 0; i < rv.size(); ++i) {
             if (taken[i]) continue;
             taken[i] = true;
-            int best = -1;
-            size_t bc = 0;
-            for (size_t j = i + 1; j < rv.size(); ++j) {
-                if (taken[j]) continue;
-                size_t c = 0;
-                for (const auto &kv : nb[i]) c += nb[j].count(kv.first);
-                if (c > bc) { best = (int)j; bc = c; }
-            }
-            if (bc < 2) best = -1;
-            if (best >= 0) taken[best] = true;
-            std::map<ViewKey, std::pair<int, int>> cols;            // column -> (pair of row 1, of row 2)
-            for (const auto &kv : nb[i]) cols[kv.first] = {kv.second, -1};
-            if (best >= 0)
+            std::vector<int> members{(int)i};
+            std::map<ViewKey, std::vector<int>> cols;              // column -> pair per member row
+            for (const auto &kv : nb[i]) cols[kv.first] = {kv.second};
+            while ((int)members.size() < tile_rows) {
+                int best = -1;
+                size_t bc = 0;
+                for (size_t j = i + 1; j < rv.size(); ++j) {
+                    if (taken[j]) continue;
+                    size_t c = 0;
+                    for (const auto &kv : nb[j]) c += cols.count(kv.first);
+                    if (c > bc) { best = (int)j; bc = c; }
+                }
+                if (best < 0 || bc < 2) break;
+                taken[best] = true;
+                const int m = (int)members.size();
+                members.push_back(best);
+                for (auto &kv : cols) kv.second.resize(m + 1, -1);
                 for (const auto &kv : nb[best]) {
                     auto it = cols.find(kv.first);
-                    if (it == cols.end()) cols[kv.first] = {-1, kv.second};
-                    else it->second.second = kv.second;
+                    if (it == cols.end()) { cols[kv.first] = std::vector<int>(m + 1, -1); it = cols.find(kv.first); }
+                    it->second[m] = kv.second;
                 }
+            }
+            const int nr = (int)members.size();
+            for (auto &kv : cols) kv.second.resize(nr, -1);
             const PairInfo &p0 = pairs[nb[i].begin()->second];
             const int shape = p0.carry3 == p0.carry4 ? 1 : 0;
             const int maxp = shape == 0 ? kMaxPartners : kMaxPartners / 2;
-            std::vector<std::pair<int, int>> cl;
+            std::vector<std::vector<int>> cl;
             for (const auto &kv : cols) cl.push_back(kv.second);
             for (size_t b = 0; b < cl.size(); b += maxp) {
                 PTask t{};
@@ -215,18 +225,23 @@ PairTables build_pair_tables(const Plan &P) {
                 t.row_site = rs;
                 t.row_a = shape == 0 ? (p0.carry3 == rs ? 1 : 0) : 0;
                 t.row = p0.pv[rs];
-                t.nrow = best >= 0 ? 2 : 1;
-                if (best >= 0) t.row2 = pairs[nb[best].begin()->second].pv[rs];
+                t.nrow = nr;
+                for (int r = 1; r < nr; ++r) t.rowx[r - 1] = pairs[nb[members[r]].begin()->second].pv[rs];
                 t.np = (int)std::min<size_t>(maxp, cl.size() - b);
-                for (int k = 0; k < kMaxPartners; ++k) t.pair[k] = t.pair2[k] = -1;
+                for (int k = 0; k < kMaxPartners; ++k) {
+                    t.pair[k] = -1;
+                    for (int r = 0; r < kMaxTileRows - 1; ++r) t.pairx[r][k] = -1;
+                }
                 int nprod = 0;
                 for (int k = 0; k < t.np; ++k) {
-                    const int pa = cl[b + k].first, pb2 = cl[b + k].second;
-                    const PairInfo &pc = pairs[pa >= 0 ? pa : pb2];
-                    t.col[k] = pc.pv[1 - rs];
-                    t.pair[k] = pa;
-                    t.pair2[k] = pb2;
-                    nprod += (pa >= 0) + (pb2 >= 0);
+                    const std::vector<int> &pc = cl[b + k];
+                    int any = -1;
+                    for (int r = 0; r < nr; ++r) {
+                        if (pc[r] >= 0) { any = pc[r]; ++nprod; }
+                        if (r == 0) t.pair[k] = pc[0];
+                        else t.pairx[r - 1][k] = pc[r];
+                    }
+                    t.col[k] = pairs[any].pv[1 - rs];
                 }
                 const int steps = (t.K + 3) / 4;
                 const int halves = shape == 1 ? 2 : 1;
@@ -241,10 +256,11 @@ PairTables build_pair_tables(const Plan &P) {
     for (const PTask &t : T.tiles)
         for (int k = 0; k < t.np; ++k) {
             if (t.pair[k] >= 0) seen[t.pair[k]]++;
-            if (t.pair2[k] >= 0) seen[t.pair2[k]]++;
+            for (int r = 0; r + 1 < t.nrow; ++r)
+                if (t.pairx[r][k] >= 0) seen[t.pairx[r][k]]++;
         }
     for (int p = 0; p < T.npair; ++p)
-        if (seen[p] != 1) throw std::logic_error("two-row tiles do not cover every pair once");
+        if (seen[p] != 1) throw std::logic_error("row tiles do not cover every pair once");
     return T;
 }
 

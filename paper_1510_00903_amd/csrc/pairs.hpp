@@ -27,6 +27,7 @@
 namespace bbc {
 
 constexpr int kMaxPartners = 8;
+constexpr int kMaxTileRows = 3;
 
 // One intermediate view at one site: component offset and strides of the
 // outer spins and open indices (0 where the view does not hold them).
@@ -53,12 +54,13 @@ struct PTask {
     PView row;
     PView col[kMaxPartners];
     int32_t pair[kMaxPartners];
-    // two-row tiles (PairTables::tiles): a second row view of the same class with
-    // its own products against the same columns; pair[i], pair2[i] = -1 where
-    // that row does not pair with column i.  nrow = 1 in PairTables::tasks.
+    // row tiles (PairTables::tiles): up to kMaxTileRows row views of the same
+    // class, each with its own products against the same columns: row 0 is `row`
+    // with pair[], row r >= 1 is rowx[r - 1] with pairx[r - 1][]; a pair id is -1
+    // where that row does not pair with column i.  nrow = 1 in PairTables::tasks.
     int32_t nrow;
-    PView row2;
-    int32_t pair2[kMaxPartners];
+    PView rowx[kMaxTileRows - 1];
+    int32_t pairx[kMaxTileRows - 1][kMaxPartners];
 };
 
 // One channel term in pair-major order: channel ch (within its chunk) gains
@@ -73,9 +75,10 @@ constexpr int kCombSubs = 8;          // channel classes (ch mod 8) per pass
 
 struct PairTables {
     std::vector<PTask> tasks;         // most expensive first
-    // the same products as tiles of two row views sharing up to kMaxPartners
-    // (shape 1: kMaxPartners / 2) column views, rows of a class paired greedily by
-    // common partners, so that a column view is loaded once for both rows
+    // the same products as tiles of up to kMaxTileRows row views sharing up to
+    // kMaxPartners (shape 1: kMaxPartners / 2) column views, rows of a class
+    // grouped greedily by common partners, so that a column view is loaded once
+    // for all rows of its tile
     std::vector<PTask> tiles;
     int npair = 0;
     std::vector<int32_t> term_begin;  // per requested channel, n_ch + 1 entries
@@ -89,7 +92,7 @@ struct PairTables {
 };
 
 // Pairs, tasks and channel terms of a plan (throws std::logic_error on a
-// shape the kernels do not take).
-PairTables build_pair_tables(const Plan &P);
+// shape the kernels do not take); row tiles of at most tile_rows rows.
+PairTables build_pair_tables(const Plan &P, int tile_rows = kMaxTileRows);
 
 }  // namespace bbc
