@@ -454,6 +454,10 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         std::vector<bbc::BlockComp> comps(P.ncomp);
         for (int c = 0; c < P.ncomp; ++c) {
             const int tb = P.term_begin[c], n = P.term_begin[c + 1] - tb;
+            // the block kernel takes terms in pairs (every component of the
+            // catalogue has 2, 8 or 24: its colour antisymmetry pairs them)
+            if (n < 2 || n % 2)
+                return fail(BBC_EUNSUPPORTED, "block component with " + std::to_string(n) + " terms");
             comps[c] = bbc::BlockComp{n > 0 ? kterms[tb] : 0u, n > 1 ? kterms[tb + 1] : 0u, (uint32_t)(tb + 2),
                                       (uint32_t)n};
         }
