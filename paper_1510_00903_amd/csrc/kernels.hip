@@ -2592,25 +2592,28 @@ __global__ __launch_bounds__(1024) void k_pair_combine_lds(const typename cplx_t
     for (int j = 0; j < NJ; ++j) acc[j] = double2{0.0, 0.0};
     int e = comb_begin[sub];
     const int ee = comb_begin[sub + 1];
+    // the class's current entry (whole 16-byte record: pair, ch, w), carried across chunks
+    int4 cur = e < ee ? *(const int4 *)&comb[e] : int4{npair, 0, 0, 0};
     for (int p0 = 0; p0 < npair; p0 += PC) {
         const int np = min(PC, npair - p0);
         __syncthreads();                                           // previous chunk consumed
         for (int i = t; i < np * PAIR16; i += 1024) stage[i] = pg4[(size_t)p0 * PAIR16 + i];
         __syncthreads();
-        // this class's entries with pairs in [p0, p0 + np), in ascending pair order
-        while (e < ee) {
-            const CombEntry ce = comb[e];
-            if (ce.pair >= p0 + np) break;
-            const T2 v = st2[(size_t)(ce.pair - p0) * 16 * G];
-            const int j = ce.ch >> 3;
-            switch (j) {
+        // this class's entries with pairs in [p0, p0 + np), in ascending pair order; the
+        // next record is requested together with the current entry's operand
+        while (cur.x < p0 + np) {
+            const int4 nxt = e + 1 < ee ? *(const int4 *)&comb[e + 1] : int4{npair, 0, 0, 0};
+            const T2 v = st2[(size_t)(cur.x - p0) * 16 * G];
+            const double w = __hiloint2double(cur.w, cur.z);
+            switch (cur.y >> 3) {
 #define BBC_COMB_CASE(J) \
-    case J: acc[J].x = fma(ce.w, (double)v.x, acc[J].x); acc[J].y = fma(ce.w, (double)v.y, acc[J].y); break;
+    case J: acc[J].x = fma(w, (double)v.x, acc[J].x); acc[J].y = fma(w, (double)v.y, acc[J].y); break;
                 BBC_COMB_CASE(0) BBC_COMB_CASE(1) BBC_COMB_CASE(2) BBC_COMB_CASE(3)
                 BBC_COMB_CASE(4) BBC_COMB_CASE(5) BBC_COMB_CASE(6) BBC_COMB_CASE(7)
 #undef BBC_COMB_CASE
                 default: break;
             }
+            cur = nxt;
             ++e;
         }
     }
