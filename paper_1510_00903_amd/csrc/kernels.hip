@@ -1009,29 +1009,37 @@ static bool fft_z_runs_lz(const typename cplx_t<T>::type *in, typename cplx_t<T>
 // One-pass forward 3-D FFT of cubic 32-point (or 24-point) lattices in FP32, written
 // into the run-ordered momentum groups: one workgroup per (component, sink
 // spin) reads the component once, with its L^2 z lines in registers (two per
-// thread) and transformed there; the kz planes are then taken in two batches,
-// each closed under kz -> -kz (A: kz <= L/4 or kz >= L - L/4; B: the rest), so
-// that every x-row run lies in one batch: a batch's planes go to LDS, their x
+// thread) and transformed there; the kz planes are then taken in two batches
+// of L/2 planes, each closed under kz -> -kz (below), so that every x-row run
+// lies in one batch: a batch's planes go to LDS, their x
 // and y lines are transformed there, and the batch's runs are written as whole
 // 64-byte spin sectors (GroupLayout<float2> is spin-major).  The z transform
 // comes first here and last in the two-pass form, so the two differ by
 // rounding only.  Replaces the plane pass and the z pass (two HBM round trips)
 // for these lattices.
 // ----------------------------------------------------------------------------
+// Batches of L/2 planes each: A = {0, L/2} and kz = 1..h, L-h..L-1 (h = L/4 - 1),
+// B = the rest (h+1..L/2-1 and L/2+1..L-h-1); both closed under kz -> -kz, and
+// each batch's x (or y) lines are L^2 / 2 = one per thread.
 template <int L>
-__host__ __device__ constexpr int onepass_na() { return L / 4; }
+__host__ __device__ constexpr int onepass_na() { return L / 4 - 1; }
 // plane slot of kz in batch b (-1 if not in it), and the kz of slot p
 template <int L>
 __device__ __forceinline__ int onepass_slot(int b, int kz) {
-    constexpr int NA = onepass_na<L>(), PA = 2 * NA + 1;
-    if (b == 0) return kz <= NA ? kz : (kz >= L - NA ? PA - (L - kz) : -1);
-    return (kz > NA && kz < L - NA) ? kz - NA - 1 : -1;
+    constexpr int h = onepass_na<L>();
+    const bool inA = kz == 0 || kz == L / 2 || kz <= h || kz >= L - h;
+    if (b == 0) {
+        if (!inA) return -1;
+        return kz == L / 2 ? 2 * h + 1 : (kz <= h ? kz : kz - L + 2 * h + 1);
+    }
+    if (inA) return -1;
+    return kz < L / 2 ? kz - h - 1 : kz - h - 2;
 }
 template <int L>
 __device__ __forceinline__ int onepass_kz(int b, int p) {
-    constexpr int NA = onepass_na<L>(), PA = 2 * NA + 1;
-    if (b == 0) return p <= NA ? p : L - (PA - p);
-    return NA + 1 + p;
+    constexpr int h = onepass_na<L>();
+    if (b == 0) return p <= h ? p : (p <= 2 * h ? p + L - 2 * h - 1 : L / 2);
+    return p < L / 2 - h - 1 ? p + h + 1 : p + h + 2;
 }
 
 template <int L>
@@ -1040,7 +1048,7 @@ __global__ __launch_bounds__(L * L / 2) void k_fft3d_onepass(const float2 *__res
     using Ly = GroupLayout<float2>;
     constexpr int G = Ly::G;
     constexpr int NT = L * L / 2;                  // threads; thread t holds z lines t and t + NT
-    constexpr int NA = onepass_na<L>(), PA = 2 * NA + 1, PB = L - PA;
+    constexpr int PA = L / 2, PB = L / 2;          // planes per batch
     constexpr int LP = L + 1;                      // padded row
     __shared__ float2 buf[PA][L][LP];
     __shared__ float2 tw[L];
