@@ -426,9 +426,10 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         }
         bbc::PairTables pt;
         try {
-            // row tiles of two rows (three cut the loads further, 0.59x against 0.71x,
-            // but their accumulators cost a wave per SIMD: slower in both forms)
-            pt = bbc::build_pair_tables(P, 2);
+            // row tiles: FP64 three rows of at most 6 columns (3 in shape 1), FP32 two
+            // rows of 8 (4), the largest that keep three (FP64) or two (FP32) waves
+            // per SIMD with their accumulators
+            pt = prec == BBC_F32 ? bbc::build_pair_tables(P, 2, 8) : bbc::build_pair_tables(P, 3, 6);
         } catch (const std::exception &e) {
             return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
         }

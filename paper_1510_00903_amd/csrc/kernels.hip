@@ -1933,7 +1933,7 @@ template <int NP, int SHAPE>
 __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
                                             const PTask &T, int lane, int mir, int set0, double2 *wlds) {
     constexpr int H = SHAPE == 1 ? 2 : 1;
-    constexpr int R = 2;                           // plans hold tiles of at most 2 rows
+    constexpr int R = 3;                           // FP64 plans hold tiles of at most 3 rows
     constexpr int V = R * H + NP, NL = 8 * V;
     static_assert(V <= kTileMaxViews, "tile views");
     constexpr int G = GroupLayout<double2>::G;
@@ -2243,15 +2243,15 @@ __global__ __launch_bounds__(256) void k_pairs_tiles64s(const double2 *__restric
     const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
 #define BBC_TILE_CASE(SH, N) \
     case N: pair_tile64<N, SH>(g0, p0, Tk, lane, mir, set0, wlds); break;
-    if (shape == 0) {
+    if (shape == 0) {            // FP64 tiles: at most 6 columns (3 in shape 1)
         switch (np) {
             BBC_TILE_CASE(0, 1) BBC_TILE_CASE(0, 2) BBC_TILE_CASE(0, 3) BBC_TILE_CASE(0, 4)
-            BBC_TILE_CASE(0, 5) BBC_TILE_CASE(0, 6) BBC_TILE_CASE(0, 7) BBC_TILE_CASE(0, 8)
+            BBC_TILE_CASE(0, 5) BBC_TILE_CASE(0, 6)
             default: break;
         }
     } else {
         switch (np) {
-            BBC_TILE_CASE(1, 1) BBC_TILE_CASE(1, 2) BBC_TILE_CASE(1, 3) BBC_TILE_CASE(1, 4)
+            BBC_TILE_CASE(1, 1) BBC_TILE_CASE(1, 2) BBC_TILE_CASE(1, 3)
             default: break;
         }
     }

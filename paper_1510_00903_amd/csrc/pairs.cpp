@@ -40,8 +40,9 @@ struct PairInfo {
 
 }  // namespace
 
-PairTables build_pair_tables(const Plan &P, int tile_rows) {
+PairTables build_pair_tables(const Plan &P, int tile_rows, int tile_cols) {
     if (tile_rows < 1 || tile_rows > kMaxTileRows) throw std::logic_error("tile rows");
+    if (tile_cols < 2 || tile_cols > kMaxPartners) throw std::logic_error("tile columns");
     PairTables T;
     const int n = (int)P.channels.size();
     std::map<PairKey, int> pair_index;
@@ -213,7 +214,7 @@ PairTables build_pair_tables(const Plan &P, int tile_rows) {
             for (auto &kv : cols) kv.second.resize(nr, -1);
             const PairInfo &p0 = pairs[nb[i].begin()->second];
             const int shape = p0.carry3 == p0.carry4 ? 1 : 0;
-            const int maxp = shape == 0 ? kMaxPartners : kMaxPartners / 2;
+            const int maxp = shape == 0 ? tile_cols : tile_cols / 2;
             std::vector<std::vector<int>> cl;
             for (const auto &kv : cols) cl.push_back(kv.second);
             for (size_t b = 0; b < cl.size(); b += maxp) {

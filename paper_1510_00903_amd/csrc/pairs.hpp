@@ -92,7 +92,8 @@ struct PairTables {
 };
 
 // Pairs, tasks and channel terms of a plan (throws std::logic_error on a
-// shape the kernels do not take); row tiles of at most tile_rows rows.
-PairTables build_pair_tables(const Plan &P, int tile_rows = kMaxTileRows);
+// shape the kernels do not take); row tiles of at most tile_rows rows and
+// tile_cols columns (shape 1: half as many, rounded down).
+PairTables build_pair_tables(const Plan &P, int tile_rows = kMaxTileRows, int tile_cols = kMaxPartners);
 
 }  // namespace bbc
