@@ -233,9 +233,9 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
  *           open-index step issued ahead, 2 = half a group per wave, 3 = half a
  *           group, loads ahead, 4 = operands staged through LDS (whole group
  *           lines), 5 = staged, double-buffered, 6 = staged per set of 4
- *           momenta (half lines), 7 = the same, double-buffered, 8 = two-row
- *           tiles staged per set of 4 momenta (two row views share their column
- *           views' loads); FP32 0 = plain,
+ *           momenta (half lines), 7 = the same, double-buffered, 8 = row
+ *           tiles staged per set of 4 momenta (up to three row views share
+ *           their column views' loads); FP32 0 = plain,
  *           1 = loads ahead, 2 = staged through LDS, 3 = staged, double-buffered,
  *           4 = staged, 4 open indices per round, 5 = two-row tiles;
  *   blocks  block construction, sites per workgroup x component shares:

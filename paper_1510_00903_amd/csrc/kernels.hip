@@ -1923,12 +1923,12 @@ __global__ __launch_bounds__(256) void k_pairs_lds64s(const double2 *__restrict_
 }
 
 // FP64 row tile per set of 4 momenta (PairTables::tiles): the H views of each of
-// the tile's row views (up to 2) and the NP column views are staged
+// the tile's row views (up to 3) and the NP column views are staged
 // through LDS per round of 4 open-index items, as in pair_task64_lds1; row r
 // multiplies column p where its pair id is set (wave-uniform), so each product is
 // formed with the operands, order and MFMA sequence of the one-row tasks (same
 // bits), while a column view is loaded once for all rows of the tile.
-constexpr int kTileMaxViews = 10;                  // R H + NP (R = 2 rows)
+constexpr int kTileMaxViews = 10;                  // R H + NP: FP64 3 rows x 6 (3) cols, FP32 2 x 8 (4)
 template <int NP, int SHAPE>
 __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
                                             const PTask &T, int lane, int mir, int set0, double2 *wlds) {
@@ -2541,7 +2541,7 @@ static void launch_pairs_tiles32(const float2 *Iq, float2 *P, int nc, const Pair
 // group per wave, 1 = whole group, pipelined, 2 = half group, 3 = half group,
 // pipelined, 4 = operands staged through LDS, 5 = staged, double-buffered,
 // 6 = staged per set of 4 momenta (half lines), 7 = the same, double-buffered,
-// 8 = two-row tiles staged per set of 4 momenta; FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
+// 8 = row tiles (three rows) staged per set of 4 momenta; FP32 0 = plain, 1 = pipelined, 2 = staged through LDS, 3 = staged,
 // double-buffered, 4 = staged, 4 open indices per round, 5 = row tiles.
 template <typename T>
 void launch_pairs(const typename cplx_t<T>::type *Iq, typename cplx_t<T>::type *P, int nc, const PairDevTables &tb,
