@@ -426,10 +426,10 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         }
         bbc::PairTables pt;
         try {
-            // row tiles: FP64 three rows of at most 6 columns (3 in shape 1), FP32 two
-            // rows of 8 (4), the largest that keep three (FP64) or two (FP32) waves
-            // per SIMD with their accumulators
-            pt = prec == BBC_F32 ? bbc::build_pair_tables(P, 2, 8) : bbc::build_pair_tables(P, 3, 6);
+            // row tiles: three rows of at most 6 columns (3 in shape 1) in FP64, 4 (2)
+            // in FP32, whose accumulators take twice the registers: both keep three
+            // waves per SIMD
+            pt = prec == BBC_F32 ? bbc::build_pair_tables(P, 3, 4) : bbc::build_pair_tables(P, 3, 6);
         } catch (const std::exception &e) {
             return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
         }

@@ -1928,7 +1928,7 @@ __global__ __launch_bounds__(256) void k_pairs_lds64s(const double2 *__restrict_
 // multiplies column p where its pair id is set (wave-uniform), so each product is
 // formed with the operands, order and MFMA sequence of the one-row tasks (same
 // bits), while a column view is loaded once for all rows of the tile.
-constexpr int kTileMaxViews = 10;                  // R H + NP: FP64 3 rows x 6 (3) cols, FP32 2 x 8 (4)
+constexpr int kTileMaxViews = 10;                  // R H + NP: FP64 3 rows x 6 (3) cols, FP32 3 x 4 (2)
 template <int NP, int SHAPE>
 __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, double2 *__restrict__ pb,
                                             const PTask &T, int lane, int mir, int set0, double2 *wlds) {
@@ -2039,7 +2039,7 @@ __device__ __forceinline__ void pair_tile64(const double2 *__restrict__ gb, doub
 }
 
 // FP32 row tile over two groups (16 momenta), 2 open indices per round:
-// pair_task32_lds with up to 2 row views (same operands, order and MFMA
+// pair_task32_lds with up to 3 row views (same operands, order and MFMA
 // sequence per product, so the same bits).
 template <int NP, int SHAPE>
 __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, const float2 *__restrict__ gb1,
@@ -2047,7 +2047,7 @@ __device__ __forceinline__ void pair_tile32(const float2 *__restrict__ gb0, cons
                                             const PTask &T, int lane, int mir, float4 *wlds) {
     constexpr int KS = 2;
     constexpr int H = SHAPE == 1 ? 2 : 1;
-    constexpr int R = 2;                           // FP32 plans hold tiles of at most 2 rows
+    constexpr int R = 3;                           // FP32 plans hold tiles of at most 3 rows
     constexpr int V = R * H + NP, NL = 4 * KS * V;
     static_assert(V <= kTileMaxViews, "tile views");
     constexpr int G = GroupLayout<float2>::G;
@@ -2197,15 +2197,14 @@ __global__ __launch_bounds__(256) void k_pairs_tiles32(const float2 *__restrict_
     const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
 #define BBC_TILE32_CASE(SH, N) \
     case N: pair_tile32<N, SH>(g0, g1, p0, p1, has1, Tk, lane, mir, wlds); break;
-    if (shape == 0) {
+    if (shape == 0) {            // FP32 tiles: at most 4 columns (2 in shape 1)
         switch (np) {
             BBC_TILE32_CASE(0, 1) BBC_TILE32_CASE(0, 2) BBC_TILE32_CASE(0, 3) BBC_TILE32_CASE(0, 4)
-            BBC_TILE32_CASE(0, 5) BBC_TILE32_CASE(0, 6) BBC_TILE32_CASE(0, 7) BBC_TILE32_CASE(0, 8)
             default: break;
         }
     } else {
         switch (np) {
-            BBC_TILE32_CASE(1, 1) BBC_TILE32_CASE(1, 2) BBC_TILE32_CASE(1, 3) BBC_TILE32_CASE(1, 4)
+            BBC_TILE32_CASE(1, 1) BBC_TILE32_CASE(1, 2)
             default: break;
         }
     }
