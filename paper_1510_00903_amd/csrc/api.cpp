@@ -429,7 +429,7 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
             // row tiles: three rows of at most 6 columns (3 in shape 1) in FP64, 4 (2)
             // in FP32, whose accumulators take twice the registers: both keep three
             // waves per SIMD
-            pt = prec == BBC_F32 ? bbc::build_pair_tables(P, 3, 4) : bbc::build_pair_tables(P, 3, 6);
+            pt = prec == BBC_F32 ? bbc::build_pair_tables(P, 3, 4) : bbc::build_pair_tables(P, 3, 4);
         } catch (const std::exception &e) {
             return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
         }

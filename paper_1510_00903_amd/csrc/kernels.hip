@@ -2242,15 +2242,14 @@ __global__ __launch_bounds__(256) void k_pairs_tiles64s(const double2 *__restric
     const int shape = __builtin_amdgcn_readfirstlane(Tk.shape);
 #define BBC_TILE_CASE(SH, N) \
     case N: pair_tile64<N, SH>(g0, p0, Tk, lane, mir, set0, wlds); break;
-    if (shape == 0) {            // FP64 tiles: at most 6 columns (3 in shape 1)
+    if (shape == 0) {            // FP64 tiles: at most 4 columns (2 in shape 1)
         switch (np) {
             BBC_TILE_CASE(0, 1) BBC_TILE_CASE(0, 2) BBC_TILE_CASE(0, 3) BBC_TILE_CASE(0, 4)
-            BBC_TILE_CASE(0, 5) BBC_TILE_CASE(0, 6)
             default: break;
         }
     } else {
         switch (np) {
-            BBC_TILE_CASE(1, 1) BBC_TILE_CASE(1, 2) BBC_TILE_CASE(1, 3)
+            BBC_TILE_CASE(1, 1) BBC_TILE_CASE(1, 2)
             default: break;
         }
     }
