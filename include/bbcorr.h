@@ -237,7 +237,7 @@ bbc_status bbc_correlate_noalloc(bbc_context *ctx, const int32_t lattice[3], bbc
  *           tiles staged per set of 4 momenta (up to three row views share
  *           their column views' loads); FP32 0 = plain,
  *           1 = loads ahead, 2 = staged through LDS, 3 = staged, double-buffered,
- *           4 = staged, 4 open indices per round, 5 = two-row tiles;
+ *           4 = staged, 4 open indices per round, 5 = row tiles (three rows);
  *   blocks  block construction, sites per workgroup x component shares:
  *           0 = 4 x 2, 1 = 4 x 4, 2 = 8 x 2;
  *   planes  x-y plane pass of the forward FFT (square 24- and 32-point planes):

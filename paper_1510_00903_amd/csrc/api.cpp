@@ -586,7 +586,7 @@ TuneKey tune_key(const int L[3], int prec, int spin_offset, uint64_t chash) {
 }
 
 // Built-in choice for shapes without a tuning entry (the fastest variants
-// measured at 16^3 and 32^3 with 52 channels): the contraction in two-row tiles
+// measured at 16^3 and 32^3 with 52 channels): the contraction in row tiles
 // staged through LDS (FP64 per set of 4 momenta), and in FP32 the LDS-staged
 // channel sums, 8 x 2 block workgroups and half-size plane-pass workgroups.
 // Small lattices run several slices at once (a slice alone does not fill the GPU).

@@ -15,7 +15,7 @@ struct PairDevTables {
     int ngroup;                   // momentum groups (G positions each)
     const PTask *tasks;
     int ntask;
-    const PTask *tiles;           // the same products as two-row tiles (pairs.hpp)
+    const PTask *tiles;           // the same products as row tiles (pairs.hpp)
     int ntile;
     int npair;
     const CombEntry *comb;        // channel terms, pair-major (pairs.hpp)
