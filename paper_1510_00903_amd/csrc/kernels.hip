@@ -278,13 +278,19 @@ void launch_blocks(const typename cplx_t<T>::type *Sl, const typename cplx_t<T>:
 __global__ __launch_bounds__(256) void k_absmax(const float2 *__restrict__ S, long n, uint32_t *__restrict__ out,
                                                 const SliceArgs *__restrict__ ia, int strange) {
     if (ia) S = (const float2 *)(strange ? ia->ss : ia->sl);
+    __shared__ float wm[4];
     float m = 0.0f;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const float2 v = S[i];
         m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+    // one atomic per workgroup (the maximum of its 4 waves): many workgroups
+    // updating one word serialise on it
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(out, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
 }
 
 __global__ void k_zero_u32(uint32_t *p, int n) {
@@ -295,7 +301,7 @@ __global__ void k_zero_u32(uint32_t *p, int n) {
 void launch_absmax(const float2 *Sl, const float2 *Ss, long n, uint32_t *kmax, hipStream_t st,
                    const SliceArgs *ia) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, kmax, 2);
-    const int nblk = (int)std::min<long>(2048, (n + 255) / 256);
+    const int nblk = (int)std::min<long>(1024, (n + 255) / 256);
     hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Sl, n, kmax, ia, 0);
     hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(256), 0, st, Ss, n, kmax + 1, ia, 1);
 }
