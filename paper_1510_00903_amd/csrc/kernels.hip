@@ -2643,7 +2643,7 @@ __global__ __launch_bounds__(1024) void k_pair_combine_lds(const typename cplx_t
 }
 
 // Variants (same sums in the same order): entries per load batch, 0 = 8, 1 = 16;
-// 2 = pair products staged through LDS, 32 pairs at a time (FP64 64 KB, FP32 32 KB).
+// 2 = pair products staged through LDS, 64 KB at a time (FP64 32 pairs, FP32 64).
 template <typename T>
 void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::type *Ct, int n_ch, long V,
                          const PairDevTables &tb, int variant, hipStream_t st) {
@@ -2654,8 +2654,8 @@ void launch_pair_combine(const typename cplx_t<T>::type *P, typename ct_t<T>::ty
         for (long g0 = 0; g0 < tb.ngroup; g0 += max_wg) {
             const long gc = std::min<long>(max_wg, tb.ngroup - g0);
             if (variant == 2)
-                hipLaunchKernelGGL((k_pair_combine_lds<T, 32>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch,
-                                   V, tb.gpos, (int)g0, tb.npair, tb.comb, cb);
+                hipLaunchKernelGGL((k_pair_combine_lds<T, sizeof(T) == 4 ? 64 : 32>), dim3((unsigned)gc), dim3(1024), 0,
+                                   st, P, Ct, c0, nch, V, tb.gpos, (int)g0, tb.npair, tb.comb, cb);
             else if (variant == 1)
                 hipLaunchKernelGGL((k_pair_combine<T, 16>), dim3((unsigned)gc), dim3(1024), 0, st, P, Ct, c0, nch, V,
                                    tb.gpos, (int)g0, tb.npair, tb.comb, cb);
