@@ -374,6 +374,10 @@ size_t image_put(std::vector<unsigned char> &img, const E *data, size_t n) {
 // Plan of a channel list and spin selection (cached per context).  With
 // `upload`, the table image is also copied to a device allocation of its own;
 // the allocation-free entry point copies it into its scratch instead.
+// Row tiles of the contraction: rows and columns (shape 1: half the columns) per
+// tile, the shapes the tile kernels are instantiated for.
+constexpr int kTileRows = 3, kTileCols = 4;
+
 bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_offset, bbc_precision prec,
                     DevPlan **out, bool upload = true, int full_sub = -1) {
     std::lock_guard<std::mutex> lock(ctx->qmu);
@@ -426,13 +430,16 @@ bbc_status get_plan(bbc_context *ctx, const std::vector<int> &chans, int spin_of
         }
         bbc::PairTables pt;
         try {
-            // row tiles: three rows of at most 6 columns (3 in shape 1) in FP64, 4 (2)
-            // in FP32, whose accumulators take twice the registers: both keep three
-            // waves per SIMD
-            pt = prec == BBC_F32 ? bbc::build_pair_tables(P, 3, 4) : bbc::build_pair_tables(P, 3, 4);
+            // row tiles of three rows and at most 4 columns (2 in shape 1): three (FP32)
+            // or four (FP64) waves per SIMD with their accumulators
+            pt = bbc::build_pair_tables(P, kTileRows, kTileCols);
         } catch (const std::exception &e) {
             return fail(BBC_EUNSUPPORTED, std::string("contraction tables: ") + e.what());
         }
+        // the tile kernels take exactly these shapes (a larger one would be skipped)
+        for (const bbc::PTask &t : pt.tiles)
+            if (t.nrow < 1 || t.nrow > kTileRows || t.np < 1 || t.np > (t.shape ? kTileCols / 2 : kTileCols))
+                return fail(BBC_EUNSUPPORTED, "contraction tile outside the kernels' shapes");
         dp->ntask = (int)pt.tasks.size();
         dp->ntile = (int)pt.tiles.size();
         dp->npair = pt.npair;
