@@ -483,9 +483,10 @@ def device_correlated(torch, L, T, seed, dtype):
     return out
 
 
-def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, channels=None):
+def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, channels=None, tuning=None):
     """Time `steps` whole jobs (every slice of d_l/d_s, all channels) after `warmup`
-    untimed ones; per-stage device times from HIP events of the profiled steps."""
+    untimed ones; per-stage device times from HIP events of the profiled steps.
+    tuning: kernel variants for this request shape (default: the library's built-in choice)."""
     T = d_l.shape[0]
     channels = list(range(52)) if channels is None else channels
     n_ch = len(channels)
@@ -494,6 +495,8 @@ def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, ch
     scale = torch.empty((T, n_ch), dtype=torch.float64, device=dev) if fp32 else None
     ctx = bbc.Context(0)
     t_list = list(range(T))
+    if tuning is not None:
+        ctx.set_tuning((L, L, L), channels, tuning, precision=bbc.F32 if fp32 else bbc.F64)
     tune = ctx.tuning((L, L, L), channels, precision=bbc.F32 if fp32 else bbc.F64)[0]
     # profiled calls run one slice at a time; when the job's tuning runs several
     # at once (or in graph mode) the timed steps are unprofiled and the stage
@@ -563,7 +566,9 @@ def correlator_job(bbc, torch, d_l, d_s, L, fp32, steps, warmup, graph=False, ch
 
 
 def c1_job(bbc, torch, np, synth, steps):
-    """8^3 x 8, channel 1 (p Lambda > p Lambda), FP64: eager launches and HIP-graph replay."""
+    """8^3 x 8, channel 1 (p Lambda > p Lambda), FP64: eager launches and HIP-graph replay,
+    with the library's built-in kernel variants and with those its autotuner picks for this
+    request shape (tuned on one slice before the timed region)."""
     L, T = 8, 8
     dev = torch.device("cuda:0")
     Sl, Ss = synth.propagators(L, T, seed=synth.BASE_SEED)
@@ -573,8 +578,16 @@ def c1_job(bbc, torch, np, synth, steps):
         r, _, _ = correlator_job(bbc, torch, d_l, d_s, L, False, steps, 3, graph=mode == "graph", channels=[1])
         res[mode] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                      "stages_ms_per_slice": {k: v["ms_per_slice"] for k, v in r["stages"].items()}}
+    ctx = bbc.Context(0)
+    best, _ = ctx.autotune(d_l[0].contiguous(), d_s[0].contiguous(), [1], reps=5)
+    ctx.close()
+    tuned = {"variants": best}
+    for mode in ("eager", "graph"):
+        r, _, _ = correlator_job(bbc, torch, d_l, d_s, L, False, steps, 3, graph=mode == "graph", channels=[1],
+                                 tuning=best)
+        tuned[mode] = {"value": r["value"], "ms_per_step": r["ms_per_step"]}
     return {"workload": "8^3x8 lattice, channel 1 (p Lambda > p Lambda), FP64, all r, all t",
-            "unit": "site-channels/s", "site_channels_per_step": L ** 3 * T, **res}
+            "unit": "site-channels/s", "site_channels_per_step": L ** 3 * T, **res, "autotuned": tuned}
 
 
 def c3_jobs(bbc, torch, np, steps):
