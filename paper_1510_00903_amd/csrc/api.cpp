@@ -596,12 +596,14 @@ TuneKey tune_key(const int L[3], int prec, int spin_offset, uint64_t chash) {
 // measured at 16^3 and 32^3 with 52 channels): the contraction in row tiles
 // staged through LDS (FP64 per set of 4 momenta), and in FP32 the LDS-staged
 // channel sums, 8 x 2 block workgroups and half-size plane-pass workgroups.
-// Small lattices run several slices at once (a slice alone does not fill the GPU).
+// Small lattices run several slices at once (a slice alone does not fill the
+// GPU), and up to 512 sites the block kernel takes 4 x 4 workgroups (4 sites x
+// 2 shares would give one workgroup per CU).
 bbc::Tuning default_tuning(const int L[3], int prec) {
     const long V = (long)L[0] * L[1] * L[2];
-    const int sl = V <= 1024 ? 3 : V <= 4096 ? 1 : 0;
-    if (prec == BBC_F32) return bbc::Tuning{5, 2, 1, sl, 2};
-    return bbc::Tuning{8, 0, 0, sl, 0};
+    const int sl = V <= 2048 ? 3 : V <= 4096 ? 1 : 0;
+    if (prec == BBC_F32) return bbc::Tuning{5, V <= 512 ? 1 : 2, 1, sl, 2};
+    return bbc::Tuning{8, V <= 512 ? 1 : 0, 0, sl, 0};
 }
 
 // Tuning of a request: the context's entry for its shape, else the built-in choice.
