@@ -70,3 +70,41 @@ def test_graph_replays_equal_eager(bbc, lat, dtype, chans):
     graph.graph_mode(False)
     eager.close()
     graph.close()
+
+
+@pytest.mark.skip(reason="graph-timed autotuning is not built: the first run of a build that captured each "
+                         "candidate's round ended in a host segmentation fault inside bbc_autotune (FP64 case), "
+                         "with no cause found in the code; the autotuner times ordinary launches")
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_autotune_in_graph_mode(bbc, dtype):
+    """In graph mode the autotuner would time each candidate as replays of one captured
+    graph; it returns a valid choice and keeps it for the shape, and graph replays with
+    that choice still give the eager bits (8^3, three slices, channels 1 and 51)."""
+    lat, chans = (8, 8, 8), [1, 51]
+    print("case: autotune in graph mode", np.dtype(dtype).name, lat, flush=True)
+    dev = torch.device("cuda:0")
+    Sl, Ss = synth.propagators(lat, 3, seed=123, dtype=dtype)
+    dl, ds = torch.from_numpy(Sl).to(dev), torch.from_numpy(Ss).to(dev)
+    prec = bbc.F32 if dtype == np.complex64 else bbc.F64
+    eager = bbc.Context(0)
+    ref = eager.correlate(dl, ds, [0, 1, 2], chans)
+    torch.cuda.synchronize()
+    ref = tuple(x.clone() for x in ref) if isinstance(ref, tuple) else (ref.clone(),)
+    eager.close()
+    ctx = bbc.Context(0)
+    ctx.graph_mode(True)
+    best, ms = ctx.autotune(dl[0].contiguous(), ds[0].contiguous(), chans, reps=2)
+    assert ms > 0
+    assert 0 <= best["pairs"] < (9 if prec == bbc.F64 else 6) and 0 <= best["blocks"] < 3
+    assert 0 <= best["slices"] < 4 and 0 <= best["combine"] < 3 and best["planes"] == 0
+    assert ctx.tuning(lat, chans, precision=prec) == (best, True)
+    for rep in range(3):                             # capture, then replays with eager work between
+        got = ctx.correlate(dl, ds, [0, 1, 2], chans)
+        torch.cuda.synchronize()
+        got = got if isinstance(got, tuple) else (got,)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), (rep, best)
+        x = torch.randn(128, 128, device=dev)
+        (x @ x).sum().item()
+    ctx.graph_mode(False)
+    ctx.close()
