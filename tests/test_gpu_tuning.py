@@ -171,3 +171,21 @@ def test_tuning_errors(bbc, tmp_path):
     with pytest.raises(bbc.BBCError):
         ctx.load_tuning(str(tmp_path / "missing.json"))
     ctx.close()
+
+
+def test_builtin_choices(bbc):
+    """The built-in choice per shape (no tuning entry): row tiles for the contraction,
+    4 x 4 block workgroups up to 512 sites, slices at once by lattice size (8 up to
+    2,048 sites, 2 up to 4,096, else 1), and in FP32 the LDS-staged channel sums."""
+    ctx = bbc.Context(0)
+    cases = [((8, 8, 8), bbc.F64, {"pairs": 8, "blocks": 1, "planes": 0, "slices": 3, "combine": 0}),
+             ((12, 12, 12), bbc.F64, {"pairs": 8, "blocks": 0, "planes": 0, "slices": 3, "combine": 0}),
+             ((16, 16, 16), bbc.F64, {"pairs": 8, "blocks": 0, "planes": 0, "slices": 1, "combine": 0}),
+             ((32, 32, 32), bbc.F64, {"pairs": 8, "blocks": 0, "planes": 0, "slices": 0, "combine": 0}),
+             ((8, 8, 8), bbc.F32, {"pairs": 5, "blocks": 1, "planes": 1, "slices": 3, "combine": 2}),
+             ((16, 16, 16), bbc.F32, {"pairs": 5, "blocks": 2, "planes": 1, "slices": 1, "combine": 2}),
+             ((32, 32, 32), bbc.F32, {"pairs": 5, "blocks": 2, "planes": 1, "slices": 0, "combine": 2})]
+    for lat, prec, want in cases:
+        got, tuned = ctx.tuning(lat, CHANNELS, precision=prec)
+        assert not tuned and got == want, (lat, prec, got)
+    ctx.close()
